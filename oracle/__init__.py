@@ -1,0 +1,238 @@
+"""CPU oracle for the dose product d = A x (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the GPU
+library: the arithmetic lives in ``dose_oracle.c`` (plain C, FP64), written
+from the definitions cited there; this module only marshals numpy arrays.
+
+Value formats are named by strings here ("fp16", "bf16", "fp8e4m3_rowscale")
+so that no enumeration is shared with the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dose_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FORMATS = {"fp16": 1, "bf16": 2, "fp8e4m3_rowscale": 3}
+
+
+def build() -> str:
+    """Compile liboracle.so with gcc, keeping every rounding as written."""
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
+                           "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        sigs = {
+            "or_f16_encode": ([ctypes.c_float], ctypes.c_uint16),
+            "or_f16_decode": ([ctypes.c_uint16], ctypes.c_double),
+            "or_bf16_encode": ([ctypes.c_float], ctypes.c_uint16),
+            "or_bf16_decode": ([ctypes.c_uint16], ctypes.c_double),
+            "or_e4m3_encode_sat": ([ctypes.c_float], ctypes.c_uint8),
+            "or_e4m3_decode": ([ctypes.c_uint8], ctypes.c_double),
+            "or_e4m3_row_scale": ([vp, i64], ctypes.c_float),
+            "or_f16_encode_n": ([vp, i64, vp], None),
+            "or_f16_decode_n": ([vp, i64, vp], None),
+            "or_bf16_encode_n": ([vp, i64, vp], None),
+            "or_bf16_decode_n": ([vp, i64, vp], None),
+            "or_e4m3_encode_n": ([vp, i64, vp], None),
+            "or_e4m3_decode_n": ([vp, i64, vp], None),
+            "or_decode_matrix": ([ctypes.c_int, i64, vp, vp, vp, vp], ctypes.c_int),
+            "or_row_dot": ([i64, vp, vp, vp], ctypes.c_double),
+            "or_spmv": ([i64, vp, vp, vp, vp, vp], None),
+            "or_spmv_multi": ([i64, i32, vp, vp, vp, vp, vp], None),
+            "or_spmv_T": ([i64, i64, vp, vp, vp, vp, vp], None),
+            "or_transpose": ([i64, i64, vp, vp, vp, vp, vp, vp], None),
+            "or_objective": ([i64, vp, vp, vp], ctypes.c_double),
+            "or_objective_seed": ([i64, vp, vp, vp, vp], None),
+            "or_norm2": ([i64, vp], ctypes.c_double),
+        }
+        for name, (args, res) in sigs.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+def _c(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+# ----------------------------------------------------------------- formats
+def encode(fmt: str, v) -> np.ndarray:
+    """Codes of FP32 values: uint16 for fp16/bf16, uint8 for E4M3 (no scaling)."""
+    v, pv = _c(v, np.float32)
+    lib = _load()
+    if fmt == "fp16":
+        out = np.empty(v.size, np.uint16)
+        lib.or_f16_encode_n(pv, v.size, out.ctypes.data)
+    elif fmt == "bf16":
+        out = np.empty(v.size, np.uint16)
+        lib.or_bf16_encode_n(pv, v.size, out.ctypes.data)
+    elif fmt in ("e4m3", "fp8e4m3_rowscale"):
+        out = np.empty(v.size, np.uint8)
+        lib.or_e4m3_encode_n(pv, v.size, out.ctypes.data)
+    else:
+        raise ValueError(fmt)
+    return out
+
+
+def decode(fmt: str, codes) -> np.ndarray:
+    """FP64 values of codes."""
+    lib = _load()
+    if fmt in ("fp16", "bf16"):
+        c, pc = _c(codes, np.uint16)
+        out = np.empty(c.size, np.float64)
+        (lib.or_f16_decode_n if fmt == "fp16" else lib.or_bf16_decode_n)(pc, c.size,
+                                                                        out.ctypes.data)
+    elif fmt in ("e4m3", "fp8e4m3_rowscale"):
+        c, pc = _c(codes, np.uint8)
+        out = np.empty(c.size, np.float64)
+        lib.or_e4m3_decode_n(pc, c.size, out.ctypes.data)
+    else:
+        raise ValueError(fmt)
+    return out
+
+
+def row_scale(vals) -> np.float32:
+    v, pv = _c(vals, np.float32)
+    return np.float32(_load().or_e4m3_row_scale(pv, v.size))
+
+
+def decode_matrix(fmt: str, row_ptr, vals):
+    """Decoded entries (FP32, exact) of a CSR matrix stored in format ``fmt``.
+
+    Returns (dec, scales); scales is None except for the E4M3 row-scale format.
+    """
+    rp, prp = _c(row_ptr, np.int64)
+    v, pv = _c(vals, np.float32)
+    n_rows = rp.size - 1
+    dec = np.empty(max(v.size, 1), np.float32)
+    scales = np.empty(max(n_rows, 1), np.float32) if fmt == "fp8e4m3_rowscale" else None
+    rc = _load().or_decode_matrix(FORMATS[fmt], n_rows, prp, pv, dec.ctypes.data,
+                                  scales.ctypes.data if scales is not None else None)
+    if rc != 0:
+        raise ValueError(fmt)
+    return dec[:v.size], (scales[:n_rows] if scales is not None else None)
+
+
+# ----------------------------------------------------------------- products
+def row_dot(cols, dec, x) -> float:
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    xx, px = _c(x, np.float32)
+    return float(_load().or_row_dot(c.size, pc, pd, px))
+
+
+def spmv(row_ptr, cols, dec, x) -> np.ndarray:
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    xx, px = _c(x, np.float32)
+    y = np.empty(max(rp.size - 1, 1), np.float64)
+    _load().or_spmv(rp.size - 1, prp, pc, pd, px, y.ctypes.data)
+    return y[:rp.size - 1]
+
+
+def spmv_multi(row_ptr, cols, dec, x2d) -> np.ndarray:
+    """x2d is [n_cols][n_rhs]; returns [n_rows][n_rhs] in FP64."""
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    xx, px = _c(x2d, np.float32)
+    n_rhs = xx.shape[1]
+    y = np.empty((max(rp.size - 1, 1), n_rhs), np.float64)
+    _load().or_spmv_multi(rp.size - 1, n_rhs, prp, pc, pd, px, y.ctypes.data)
+    return y[:rp.size - 1]
+
+
+def spmv_T(row_ptr, cols, dec, v, n_cols: int) -> np.ndarray:
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    vv, pv = _c(v, np.float32)
+    g = np.empty(max(n_cols, 1), np.float64)
+    _load().or_spmv_T(rp.size - 1, n_cols, prp, pc, pd, pv, g.ctypes.data)
+    return g[:n_cols]
+
+
+def transpose(row_ptr, cols, dec, n_cols: int):
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    t_rp = np.empty(n_cols + 1, np.int64)
+    t_c = np.empty(max(c.size, 1), np.int32)
+    t_d = np.empty(max(c.size, 1), np.float32)
+    _load().or_transpose(rp.size - 1, n_cols, prp, pc, pd, t_rp.ctypes.data, t_c.ctypes.data,
+                         t_d.ctypes.data)
+    return t_rp, t_c[:c.size], t_d[:c.size]
+
+
+def objective(d, p, w) -> float:
+    dd, pdd = _c(d, np.float64)
+    pp, ppp = _c(p, np.float32)
+    ww, pww = _c(w, np.float32)
+    return float(_load().or_objective(dd.size, pdd, ppp, pww))
+
+
+def objective_seed(d, p, w) -> np.ndarray:
+    dd, pdd = _c(d, np.float64)
+    pp, ppp = _c(p, np.float32)
+    ww, pww = _c(w, np.float32)
+    out = np.empty(max(dd.size, 1), np.float64)
+    _load().or_objective_seed(dd.size, pdd, ppp, pww, out.ctypes.data)
+    return out[:dd.size]
+
+
+def norm2(g) -> float:
+    gg, pg = _c(g, np.float64)
+    return float(_load().or_norm2(gg.size, pg))
+
+
+# ----------------------------------------------------------------- error metrics
+def max_rel_err(y, y_ref) -> float:
+    """max_i |y_i - y*_i| / |y*_i| over rows with y*_i != 0; rows with y*_i == 0
+    must hold exactly 0 in y (returns inf otherwise)."""
+    y = np.asarray(y, np.float64)
+    y_ref = np.asarray(y_ref, np.float64)
+    zero = y_ref == 0.0
+    if np.any(y[zero] != 0.0):
+        return float("inf")
+    nz = ~zero
+    if not np.any(nz):
+        return 0.0
+    return float(np.max(np.abs(y[nz] - y_ref[nz]) / np.abs(y_ref[nz])))
+
+
+def max_scaled_err(y, y_ref, scale) -> float:
+    """max_j |y_j - y*_j| / scale_j with scale = |A| |x| (componentwise); entries
+    with scale_j == 0 must be exactly 0."""
+    y = np.asarray(y, np.float64)
+    y_ref = np.asarray(y_ref, np.float64)
+    scale = np.asarray(scale, np.float64)
+    zero = scale == 0.0
+    if np.any(y[zero] != 0.0):
+        return float("inf")
+    nz = ~zero
+    if not np.any(nz):
+        return 0.0
+    return float(np.max(np.abs(y[nz] - y_ref[nz]) / scale[nz]))
