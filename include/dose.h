@@ -1,0 +1,221 @@
+/*
+ * dose.h — C ABI of libdose, the MI355X (gfx950) dose-product library.
+ *
+ * The dose in every voxel is one sparse matrix-vector product d = A x
+ * (paper Sec. II-A): A is the dose-deposition matrix, one row per voxel and
+ * one column per pencil-beam spot, built once per plan and left unchanged
+ * while the optimiser varies the spot weights x (Sec. II-A, Sec. IV).  The
+ * paper stores A in compressed sparse row form with IEEE-754 half-precision
+ * values and 32-bit column indices (Sec. II-C, II-D, Table I); this library
+ * keeps that format and adds bfloat16 and 8-bit E4M3 values with a per-row
+ * FP32 scale.  Every product accumulates in FP32 and is bitwise reproducible
+ * from run to run: no reduction uses atomics (Sec. II-D).
+ *
+ * Conventions for every call:
+ *   - Return value: DOSE_OK (0) or a negative dose_status; nothing throws or
+ *     aborts across this boundary.  dose_last_error() gives a thread-local
+ *     message for the last failure on the calling thread.
+ *   - "device" pointers are HIP device memory of the current device, owned by
+ *     the caller and valid until the work queued on `hip_stream` completes.
+ *     "host" pointers are ordinary CPU memory, read or written before the call
+ *     returns.
+ *   - `hip_stream` is a hipStream_t passed as void* (NULL: the null stream).
+ *     Product calls only enqueue work on it and return; results are ready when
+ *     the stream reaches them.
+ *   - A dose_matrix is read-only after creation: products on several streams
+ *     may use one matrix at the same time.  A dose_batch_plan is not
+ *     thread-safe.
+ */
+#ifndef DOSE_H
+#define DOSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dose_status;
+enum {
+  DOSE_OK = 0,
+  DOSE_ERR_INVALID_ARGUMENT = -1, /* null pointer, size mismatch, aliasing x/y  */
+  DOSE_ERR_BAD_CSR = -2,          /* row_ptr not monotone, column out of range,
+                                     columns not strictly ascending in a row,
+                                     value not finite                             */
+  DOSE_ERR_UNSUPPORTED = -3,      /* value outside the format's range, sizes
+                                     beyond the library's limits                  */
+  DOSE_ERR_NO_TRANSPOSE = -4,     /* adjoint requested on a matrix created
+                                     without DOSE_CREATE_TRANSPOSE                 */
+  DOSE_ERR_OUT_OF_MEMORY = -5,    /* device or pinned host allocation failed     */
+  DOSE_ERR_HIP = -6,              /* a HIP runtime call failed (message has it)  */
+  DOSE_ERR_INTERNAL = -7
+};
+
+/* Stored value formats.  Decoding is exact in FP32 for all three. */
+typedef enum {
+  DOSE_VAL_FP16 = 1,             /* IEEE binary16, the paper's format (Sec. II-D) */
+  DOSE_VAL_BF16 = 2,             /* bfloat16                                     */
+  DOSE_VAL_FP8E4M3_ROWSCALE = 3  /* OCP E4M3 (max 448) times an FP32 row scale   */
+} dose_value_format;
+
+/* Column index formats. */
+typedef enum {
+  DOSE_IDX_I32 = 1 /* 32-bit column indices, as in the paper (Sec. V) */
+} dose_index_format;
+
+/* dose_matrix_create flags */
+enum { DOSE_CREATE_TRANSPOSE = 1u }; /* also store A^T for dose_spmv_adjoint */
+
+/* Which stored operand dose_matrix_decode reads. */
+enum { DOSE_PART_A = 0, DOSE_PART_AT = 1 };
+
+typedef struct dose_matrix_s* dose_matrix;
+typedef struct dose_batch_plan_s* dose_batch_plan;
+
+/* A CSR matrix in host memory with FP32 source values (the form the paper
+ * converts the planning system's own storage into, Sec. II-C, Sec. IV). */
+typedef struct {
+  int64_t n_rows;          /* voxels                                          */
+  int64_t n_cols;          /* spots                                           */
+  int64_t nnz;             /* stored entries                                  */
+  const int64_t* row_ptr;  /* host, n_rows+1; [0]=0, non-decreasing, [n_rows]=nnz */
+  const int32_t* col_idx;  /* host, nnz; in [0,n_cols), strictly ascending per row */
+  const float* values;     /* host, nnz; finite                               */
+} dose_csr_host;
+
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  int32_t value_format, index_format, has_transpose;
+  int32_t block_nnz;            /* row-block size of the partition of A      */
+  int64_t n_blocks;             /* row blocks of A                           */
+  int64_t n_split_rows;         /* rows of A longer than block_nnz           */
+  int32_t block_nnz_t;          /* the same for A^T (0 without transpose)    */
+  int32_t reserved0;
+  int64_t n_blocks_t, n_split_rows_t;
+  uint64_t device_bytes;        /* device memory held by the matrix          */
+  uint64_t spmv_bytes;          /* algorithmic HBM bytes of one dose_spmv:
+                                   nnz*(value+index) + (n_rows+1)*4 row
+                                   offsets + n_rows*scale + 4*n_cols (x) +
+                                   4*n_rows (y)                             */
+  uint64_t adjoint_bytes;       /* the same for dose_spmv_adjoint on A^T     */
+} dose_matrix_info_t;
+
+/* Host-only check of a CSR matrix for a format: structure (row_ptr, column
+ * range and order, finite values) and range (binary16 and bfloat16 values
+ * must not round to infinity).  No GPU is touched.  Returns DOSE_OK,
+ * DOSE_ERR_BAD_CSR, DOSE_ERR_UNSUPPORTED or DOSE_ERR_INVALID_ARGUMENT. */
+dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf,
+                              dose_index_format xf);
+
+/* Encode a host CSR matrix into device streams (Sec. II-C: the conversion to
+ * CSR happens once, before optimisation).  Validates first (as above).  The
+ * value stream is the format's code of every FP32 source value, rounded to
+ * nearest-even; for DOSE_VAL_FP8E4M3_ROWSCALE each row i gets the scale
+ * s_i = fl32(max_j |a_ij| / 448) (1 when that is 0) and codes of
+ * fl32(a_ij / s_i), saturated at 448.  With DOSE_CREATE_TRANSPOSE the
+ * transpose is built on the device, its rows listing entries in ascending
+ * row of A, with the same decoded values.  Uses the device that is current
+ * on the calling thread; blocks until its uploads on `hip_stream` finish, so
+ * the caller may free the host arrays on return.  *out owns all device memory
+ * of the matrix until dose_matrix_destroy. */
+dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf,
+                               dose_index_format xf, uint32_t flags, void* hip_stream,
+                               dose_matrix* out);
+
+/* Re-partition a matrix (A, and A^T if stored) into row blocks of at most
+ * block_nnz entries (a power of two, 256 .. 8192; longer rows are split into
+ * chunks and combined in a fixed order).  The partition fixes the summation
+ * order, so products are bitwise identical between any two calls made under
+ * the same partition.  Synchronous. */
+dose_status dose_matrix_set_partition(dose_matrix m, int32_t block_nnz, int32_t block_nnz_t);
+
+/* Copy rows [row_begin, row_end) of the stored operand `part` (DOSE_PART_A or
+ * DOSE_PART_AT) back to the host, decoded to FP32 on the device.
+ * row_ptr_out: host, row_end-row_begin+1 offsets, the first one 0.
+ * col_out, val_out: host, as many entries as the rows hold (may be NULL to
+ * query the offsets only).  Synchronous. */
+dose_status dose_matrix_decode(dose_matrix m, int32_t part, int64_t row_begin, int64_t row_end,
+                               int64_t* row_ptr_out, int32_t* col_out, float* val_out);
+
+dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info);
+
+/* Frees the matrix's device memory after synchronising its device. */
+dose_status dose_matrix_destroy(dose_matrix m);
+
+/* y = A x (Listing 1 of the paper; the dose in every voxel).
+ * x: device, n_cols FP32.  y: device, n_rows FP32, every entry written (+0 for
+ * empty rows).  x and y must not overlap.  Asynchronous on hip_stream. */
+dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream);
+
+/* g = A^T v, the gradient of an objective of the dose with respect to the
+ * spot weights when v is the objective's derivative with respect to the dose
+ * (plan optimisation needs gradients every iteration, Sec. I).  Runs the same
+ * kernels on the stored transpose: deterministic, no atomics.
+ * v: device, n_rows FP32.  g: device, n_cols FP32, every entry written.
+ * DOSE_ERR_NO_TRANSPOSE without DOSE_CREATE_TRANSPOSE. */
+dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* g, void* hip_stream);
+
+/* One item of a batched product: y = A x for n_rhs spot-weight vectors,
+ * x stored [n_cols][ldx] and y [n_rows][ldy] (vector r at offset r).
+ * n_rhs is 1, 2 or 4; ldx == ldy == n_rhs. */
+typedef struct {
+  dose_matrix A;
+  int32_t n_rhs;
+  int32_t reserved;
+  const float* x; /* device */
+  int64_t ldx;
+  float* y;       /* device */
+  int64_t ldy;
+} dose_batch_item;
+
+/* All items in one persistent launch (robust optimisation needs the dose of
+ * many scenarios and beams every iteration, Sec. I, II-A).  Each y is bitwise
+ * what dose_spmv gives per vector under the same partition.  Items must not
+ * share outputs. */
+dose_status dose_spmv_batched(const dose_batch_item* items, int32_t n_items, void* hip_stream);
+
+/* Plans: the work list of a batch is built once on the device and the launch
+ * is captured into a HIP graph that dose_batch_plan_launch replays.  With
+ * DOSE_PLAN_AUTOTUNE each distinct matrix is first re-partitioned to the
+ * fastest block size found by timing candidates on `hip_stream` (x/y of the
+ * items are used as scratch for the timing runs). */
+enum { DOSE_PLAN_AUTOTUNE = 1u };
+dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items, uint32_t flags,
+                                   void* hip_stream, dose_batch_plan* out);
+dose_status dose_batch_plan_launch(dose_batch_plan p, void* hip_stream);
+dose_status dose_batch_plan_destroy(dose_batch_plan p);
+
+/* Quadratic plan objective f = sum_v w_v (d_v - p_v)^2, accumulated in FP64
+ * with a fixed-order two-pass reduction, and the adjoint seed
+ * seed_v = 2 w_v (d_v - p_v) in FP32 (may be NULL).
+ * d, p, w: device, n FP32.  f_out: device, one double.  Asynchronous. */
+dose_status dose_objective(int64_t n, const float* d, const float* p, const float* w,
+                           float* seed, double* f_out, void* hip_stream);
+
+/* out = sqrt(sum_j g_j^2) in FP64, fixed-order two-pass reduction.
+ * g: device, n FP32.  out: device, one double.  Asynchronous. */
+dose_status dose_norm2(int64_t n, const float* g, double* out, void* hip_stream);
+
+/* Measurement kernels (not part of the dose path): read `bytes` of device
+ * memory with 16-byte loads and write one float per workgroup to `sink`
+ * (device, 65536 floats), or copy `bytes` from src to dst.  Used to find the
+ * achievable HBM read rate and to calibrate hardware byte counters. */
+dose_status dose_probe_stream_read(const void* buf, uint64_t bytes, float* sink, void* hip_stream);
+dose_status dose_probe_copy(const void* src, void* dst, uint64_t bytes, void* hip_stream);
+
+/* Host-only view of the row-block partition that dose_matrix_create would
+ * build for a row_ptr (the summation order follows from it).  Writes up to
+ * `cap` blocks (5 int64 each: nnz_begin, nnz_count, row_begin, row_count,
+ * lanes_per_row; nnz_count of a chunk of a split row is its own length and
+ * row_count is then -1) and returns the count in *n_blocks. */
+dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t block_nnz,
+                                   int64_t* blocks, int64_t cap, int64_t* n_blocks);
+
+const char* dose_status_string(dose_status s);
+const char* dose_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOSE_H */

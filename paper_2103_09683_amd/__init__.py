@@ -1,0 +1,293 @@
+"""Dose product d = A x on MI355X (gfx950): Python binding of libdose.
+
+The dose-deposition matrix A (voxels x spots, Sec. II-A/II-B of the paper)
+is stored on the device in the paper's CSR format (FP16 values, int32
+columns) or in BF16 / E4M3-with-row-scale variants; products accumulate in
+FP32 and are bitwise reproducible (Sec. II-D).  This module only marshals
+arguments to the C ABI in include/dose.h: PyTorch provides device memory and
+streams, every step of the product runs in libdose's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DoseError
+
+__all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", "norm2",
+           "csr_validate", "partition_preview", "byte_model", "DoseSpMV", "DoseObjective",
+           "dose", "VALUE_FORMATS"]
+
+VALUE_FORMATS = {"fp16": _lib.VAL_FP16, "bf16": _lib.VAL_BF16,
+                 "fp8e4m3_rowscale": _lib.VAL_FP8E4M3_ROWSCALE}
+VALUE_BYTES = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1}
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_ptr(t: torch.Tensor, n: int, name: str, device=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the matrix on {device}")
+    return t.data_ptr()
+
+
+def _csr_struct(row_ptr, cols, vals, n_cols):
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    vals = np.ascontiguousarray(vals, dtype=np.float32)
+    n_rows = row_ptr.size - 1
+    c = _lib.CsrHost(n_rows, int(n_cols), int(cols.size), row_ptr.ctypes.data,
+                     cols.ctypes.data if cols.size else None,
+                     vals.ctypes.data if vals.size else None)
+    return c, (row_ptr, cols, vals)
+
+
+def csr_validate(row_ptr, cols, vals, n_cols, value_format: str = "fp16") -> int:
+    """Host-only validation; returns the dose_status (0 = valid)."""
+    c, keep = _csr_struct(row_ptr, cols, vals, n_cols)
+    return int(_lib.load().dose_csr_validate(ctypes.byref(c), VALUE_FORMATS[value_format],
+                                             _lib.IDX_I32))
+
+
+def partition_preview(row_ptr, block_nnz: int) -> np.ndarray:
+    """Row blocks [nnz_begin, nnz_count, row_begin, row_count (-1: split chunk),
+    lanes_per_row] the library builds for ``row_ptr`` (host only)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    lib = _lib.load()
+    n = ctypes.c_int64(0)
+    _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, block_nnz, None, 0,
+                                          ctypes.byref(n)))
+    out = np.zeros((max(n.value, 1), 5), np.int64)
+    _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, block_nnz,
+                                          out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def byte_model(nnz, n_rows, n_cols, value_bytes=2, index_bytes=4, row_ptr_bytes=4,
+               scale_bytes=0, x_bytes=4, y_bytes=4, n_rhs=1) -> float:
+    """Algorithmic HBM bytes of one product with an ideal cache (Sec. V):
+    every stored entry, every row offset (one per row) and every row scale is
+    read once, x is read once and y written once.  With FP16 values, int32
+    indices and FP64 x/y this is the paper's 6 nnz + 12 nr + 8 nc."""
+    return (nnz * (value_bytes + index_bytes) + n_rows * (row_ptr_bytes + scale_bytes)
+            + n_rhs * (n_cols * x_bytes + n_rows * y_bytes))
+
+
+def storage_bytes(nnz, n_rows, value_bytes=2, index_bytes=4, row_ptr_bytes=4) -> float:
+    """Bytes of a CSR matrix: values, column indices and n_rows+1 row offsets."""
+    return nnz * (value_bytes + index_bytes) + (n_rows + 1) * row_ptr_bytes
+
+
+class DoseMatrix:
+    """A dose-deposition matrix on the current HIP device.
+
+    row_ptr (int64, n_rows+1), cols (int32) and vals (float32) are host CSR
+    arrays; they are validated, uploaded and encoded once.  With
+    ``transpose=True`` A^T is stored as well for :meth:`adjoint`.
+    """
+
+    def __init__(self, row_ptr, cols, vals, n_cols: int, value_format: str = "fp16",
+                 transpose: bool = False, stream=None):
+        if value_format not in VALUE_FORMATS:
+            raise ValueError(f"unknown value format {value_format!r}")
+        self._h = None
+        lib = _lib.load()
+        c, keep = _csr_struct(row_ptr, cols, vals, n_cols)
+        h = ctypes.c_void_p()
+        _lib.check(lib.dose_matrix_create(ctypes.byref(c), VALUE_FORMATS[value_format],
+                                          _lib.IDX_I32,
+                                          _lib.CREATE_TRANSPOSE if transpose else 0,
+                                          _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.value_format = value_format
+        self.n_rows = int(c.n_rows)
+        self.n_cols = int(c.n_cols)
+        self.nnz = int(c.nnz)
+        self.has_transpose = bool(transpose)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @property
+    def handle(self) -> int:
+        if self._h is None:
+            raise RuntimeError("matrix is closed")
+        return self._h.value
+
+    def info(self) -> dict:
+        inf = _lib.MatrixInfo()
+        _lib.check(_lib.load().dose_matrix_info(self.handle, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in _lib.MatrixInfo._fields_}
+
+    def set_partition(self, block_nnz: int, block_nnz_t: int | None = None) -> None:
+        bt = block_nnz_t if block_nnz_t is not None else (self.info()["block_nnz_t"] or block_nnz)
+        _lib.check(_lib.load().dose_matrix_set_partition(self.handle, block_nnz, bt))
+
+    def decode(self, row_begin: int = 0, row_end: int | None = None, part: str = "A"):
+        """Host CSR of rows [row_begin, row_end) decoded to FP32 on the device."""
+        p = _lib.PART_A if part == "A" else _lib.PART_AT
+        n_rows = self.n_rows if p == _lib.PART_A else self.n_cols
+        row_end = n_rows if row_end is None else row_end
+        lib = _lib.load()
+        rp = np.zeros(max(row_end - row_begin, 0) + 1, np.int64)
+        _lib.check(lib.dose_matrix_decode(self.handle, p, row_begin, row_end, rp.ctypes.data,
+                                          None, None))
+        n = int(rp[-1])
+        cols = np.empty(max(n, 1), np.int32)
+        vals = np.empty(max(n, 1), np.float32)
+        _lib.check(lib.dose_matrix_decode(self.handle, p, row_begin, row_end, rp.ctypes.data,
+                                          cols.ctypes.data, vals.ctypes.data))
+        return rp, cols[:n], vals[:n]
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """y = A x (FP32), asynchronous on the current (or given) stream."""
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=torch.float32, device=x.device)
+        _lib.check(_lib.load().dose_spmv(self.handle, _dev_ptr(x, self.n_cols, "x", self.device),
+                                         _dev_ptr(y, self.n_rows, "y", self.device),
+                                         _stream_handle(stream)))
+        return y
+
+    def adjoint(self, v: torch.Tensor, g: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """g = A^T v (FP32), asynchronous."""
+        if g is None:
+            g = torch.empty(self.n_cols, dtype=torch.float32, device=v.device)
+        _lib.check(_lib.load().dose_spmv_adjoint(self.handle,
+                                                 _dev_ptr(v, self.n_rows, "v", self.device),
+                                                 _dev_ptr(g, self.n_cols, "g", self.device),
+                                                 _stream_handle(stream)))
+        return g
+
+    def close(self) -> None:
+        if self._h is not None:
+            _lib.check(_lib.load().dose_matrix_destroy(self._h.value))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _items(entries):
+    arr = (_lib.BatchItem * len(entries))()
+    for i, (A, x, y) in enumerate(entries):
+        n_rhs = 1 if x.dim() == 1 else x.shape[1]
+        _dev_ptr(x.reshape(-1), A.n_cols * n_rhs, "x", A.device)
+        _dev_ptr(y.reshape(-1), A.n_rows * n_rhs, "y", A.device)
+        arr[i] = _lib.BatchItem(A.handle, n_rhs, 0, x.data_ptr(), n_rhs, y.data_ptr(), n_rhs)
+    return arr
+
+
+def spmv_batched(entries, stream=None) -> None:
+    """entries: list of (DoseMatrix, x [n_cols] or [n_cols, n_rhs], y [n_rows(, n_rhs)])."""
+    arr = _items(entries)
+    _lib.check(_lib.load().dose_spmv_batched(arr, len(entries), _stream_handle(stream)))
+
+
+class BatchPlan:
+    """A batched product captured once into a HIP graph and replayed."""
+
+    def __init__(self, entries, autotune: bool = False, stream=None):
+        self._h = None
+        self._keep = list(entries)
+        arr = _items(entries)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().dose_batch_plan_create(arr, len(entries),
+                                                      _lib.PLAN_AUTOTUNE if autotune else 0,
+                                                      _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _lib.check(_lib.load().dose_batch_plan_launch(self._h.value, _stream_handle(stream)))
+
+    def close(self) -> None:
+        if self._h is not None:
+            _lib.check(_lib.load().dose_batch_plan_destroy(self._h.value))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def objective(d, p, w, seed: torch.Tensor | None = None, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+    """f = sum w (d - p)^2 in FP64 on the device (one-element float64 tensor);
+    writes the FP32 adjoint seed 2 w (d - p) into ``seed`` if given."""
+    n = d.numel()
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=d.device)
+    _lib.check(_lib.load().dose_objective(
+        n, _dev_ptr(d, n, "d"), _dev_ptr(p, n, "p"), _dev_ptr(w, n, "w"),
+        _dev_ptr(seed, n, "seed") if seed is not None else None, out.data_ptr(),
+        _stream_handle(stream)))
+    return out
+
+
+def norm2(g: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """sqrt(sum g^2) in FP64 on the device."""
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=g.device)
+    _lib.check(_lib.load().dose_norm2(g.numel(), _dev_ptr(g, g.numel(), "g"), out.data_ptr(),
+                                      _stream_handle(stream)))
+    return out
+
+
+def probe_stream_read(buf: torch.Tensor, sink: torch.Tensor, stream=None) -> None:
+    _lib.check(_lib.load().dose_probe_stream_read(buf.data_ptr(), buf.numel() * buf.element_size(),
+                                                  sink.data_ptr(), _stream_handle(stream)))
+
+
+def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
+    _lib.check(_lib.load().dose_probe_copy(src.data_ptr(), dst.data_ptr(),
+                                           src.numel() * src.element_size(),
+                                           _stream_handle(stream)))
+
+
+class DoseSpMV(torch.autograd.Function):
+    """d = A x with dL/dx = A^T dL/dd (the matrix needs transpose=True for backward)."""
+
+    @staticmethod
+    def forward(ctx, x, A):
+        ctx.A = A
+        return A.spmv(x.contiguous())
+
+    @staticmethod
+    def backward(ctx, gd):
+        return ctx.A.adjoint(gd.contiguous().float()), None
+
+
+class DoseObjective(torch.autograd.Function):
+    """f = sum w (d - p)^2 (FP64 reduction) with df/dd = 2 w (d - p)."""
+
+    @staticmethod
+    def forward(ctx, d, p, w):
+        seed = torch.empty_like(d)
+        f = objective(d.contiguous(), p.contiguous(), w.contiguous(), seed=seed)
+        ctx.save_for_backward(seed)
+        return f.reshape(())
+
+    @staticmethod
+    def backward(ctx, gf):
+        (seed,) = ctx.saved_tensors
+        return seed * gf.float(), None, None
+
+
+def dose(x: torch.Tensor, A: DoseMatrix) -> torch.Tensor:
+    """Differentiable d = A x."""
+    return DoseSpMV.apply(x, A)

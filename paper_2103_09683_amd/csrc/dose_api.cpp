@@ -1,0 +1,920 @@
+// Host side of libdose: the C ABI declared in include/dose.h.
+//
+// Responsibilities: argument and CSR validation, the row-block partition that
+// fixes every summation order, device memory of matrices and plans, the
+// one-time encode/transpose pipeline, batched work lists captured into HIP
+// graphs, and a small autotuner whose choices persist in a text cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <sstream>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/dose.h"
+#include "dose_internal.h"
+
+using namespace dose;
+
+// ------------------------------------------------------------------ errors
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DoseError {
+  dose_status code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(dose_status code, const std::string& msg) { throw DoseError{code, msg}; }
+
+#define HIP_CHECK(expr)                                                                       \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess) {                                                                   \
+      if (_e == hipErrorOutOfMemory) fail(DOSE_ERR_OUT_OF_MEMORY, std::string(#expr) + ": " + \
+                                                                      hipGetErrorString(_e)); \
+      fail(DOSE_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));                  \
+    }                                                                                         \
+  } while (0)
+
+template <typename F>
+dose_status guarded(F&& f) {
+  try {
+    f();
+    return DOSE_OK;
+  } catch (const DoseError& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return DOSE_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return DOSE_ERR_INTERNAL;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return DOSE_ERR_INTERNAL;
+  }
+}
+
+// --------------------------------------------------- allocation fault injection
+// DOSE_FAULT_INJECT=alloc:<n> makes the n-th device allocation (1-based,
+// counted from process start) report out-of-memory, to test cleanup paths.
+std::atomic<int64_t> g_alloc_count{0};
+int64_t fault_alloc_index() {
+  static const int64_t idx = [] {
+    const char* e = std::getenv("DOSE_FAULT_INJECT");
+    if (!e || std::strncmp(e, "alloc:", 6) != 0) return int64_t{-1};
+    return static_cast<int64_t>(std::atoll(e + 6));
+  }();
+  return idx;
+}
+
+void* dev_alloc(size_t bytes) {
+  const int64_t n = ++g_alloc_count;
+  if (n == fault_alloc_index()) fail(DOSE_ERR_OUT_OF_MEMORY, "injected allocation failure");
+  void* p = nullptr;
+  HIP_CHECK(hipMalloc(&p, bytes == 0 ? 256 : bytes));
+  return p;
+}
+
+// Device memory owned by one object.
+class DevBuf {
+ public:
+  DevBuf() = default;
+  explicit DevBuf(size_t bytes) : p_(dev_alloc(bytes)), n_(bytes) {}
+  ~DevBuf() { reset(); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p_(o.p_), n_(o.n_) { o.p_ = nullptr, o.n_ = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p_ = o.p_, n_ = o.n_;
+      o.p_ = nullptr, o.n_ = 0;
+    }
+    return *this;
+  }
+  void reset() {
+    if (p_) (void)hipFree(p_);
+    p_ = nullptr, n_ = 0;
+  }
+  template <typename T = void>
+  T* get() const {
+    return static_cast<T*>(p_);
+  }
+  size_t bytes() const { return n_; }
+
+ private:
+  void* p_ = nullptr;
+  size_t n_ = 0;
+};
+
+// Restores the calling thread's current device on scope exit.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    HIP_CHECK(hipGetDevice(&prev_));
+    if (prev_ != dev) HIP_CHECK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() { (void)hipSetDevice(prev_); }
+
+ private:
+  int prev_ = 0;
+};
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+int value_bytes(int vf) { return vf == kFp8 ? 1 : 2; }
+
+// ------------------------------------------------------------- validation
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// FP32 value that rounds to infinity in the target 16-bit format?
+bool overflows(int vf, float v) {
+  const float a = std::fabs(v);
+  if (vf == kFp16) return a >= 65520.0f;
+  if (vf == kBf16) {
+    uint32_t u;
+    std::memcpy(&u, &a, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (u >> 16) >= 0x7F80u;
+  }
+  return false;
+}
+
+void validate_csr(const dose_csr_host* c, int vf, int xf) {
+  if (!c) fail(DOSE_ERR_INVALID_ARGUMENT, "csr is null");
+  if (vf != kFp16 && vf != kBf16 && vf != kFp8) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown value format");
+  if (xf != DOSE_IDX_I32) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown index format");
+  if (c->n_rows < 0 || c->n_cols < 0 || c->nnz < 0) fail(DOSE_ERR_INVALID_ARGUMENT, "negative size");
+  if (c->n_rows >= (int64_t{1} << 32) - 1) fail(DOSE_ERR_UNSUPPORTED, "more than 2^32-2 rows");
+  if (c->n_cols > INT32_MAX) fail(DOSE_ERR_UNSUPPORTED, "more than 2^31-1 columns");
+  if (!c->row_ptr) fail(DOSE_ERR_INVALID_ARGUMENT, "row_ptr is null");
+  if (c->nnz > 0 && (!c->col_idx || !c->values)) fail(DOSE_ERR_INVALID_ARGUMENT, "col_idx or values is null");
+  if (c->row_ptr[0] != 0) fail(DOSE_ERR_BAD_CSR, "row_ptr[0] != 0");
+  if (c->row_ptr[c->n_rows] != c->nnz) fail(DOSE_ERR_BAD_CSR, "row_ptr[n_rows] != nnz");
+  if (c->nnz > 0 && c->n_cols == 0) fail(DOSE_ERR_BAD_CSR, "entries in a matrix without columns");
+
+  const int64_t n = c->n_rows;
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t parts = std::min<int64_t>(hw, std::max<int64_t>(1, c->nnz / (1 << 22)));
+  std::vector<int> code(parts, DOSE_OK);
+  std::vector<std::string> msg(parts);
+  auto work = [&](int64_t part) {
+    const int64_t r0 = n * part / parts, r1 = n * (part + 1) / parts;
+    for (int64_t i = r0; i < r1; ++i) {
+      const int64_t b = c->row_ptr[i], e = c->row_ptr[i + 1];
+      if (e < b || b < 0 || e > c->nnz) {
+        code[part] = DOSE_ERR_BAD_CSR;
+        msg[part] = "row_ptr decreases or leaves [0, nnz] at row " + std::to_string(i);
+        return;
+      }
+      int64_t prev = -1;
+      for (int64_t k = b; k < e; ++k) {
+        const int64_t j = c->col_idx[k];
+        if (j < 0 || j >= c->n_cols) {
+          code[part] = DOSE_ERR_BAD_CSR;
+          msg[part] = "column out of range at entry " + std::to_string(k);
+          return;
+        }
+        if (j <= prev) {
+          code[part] = DOSE_ERR_BAD_CSR;
+          msg[part] = "columns not strictly ascending in row " + std::to_string(i);
+          return;
+        }
+        prev = j;
+        const float v = c->values[k];
+        if (!std::isfinite(v)) {
+          code[part] = DOSE_ERR_BAD_CSR;
+          msg[part] = "non-finite value at entry " + std::to_string(k);
+          return;
+        }
+        if (overflows(vf, v)) {
+          code[part] = DOSE_ERR_UNSUPPORTED;
+          msg[part] = "value at entry " + std::to_string(k) + " overflows the format";
+          return;
+        }
+      }
+    }
+  };
+  if (parts == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int64_t p = 0; p < parts; ++p) th.emplace_back(work, p);
+    for (auto& t : th) t.join();
+  }
+  for (int64_t p = 0; p < parts; ++p)
+    if (code[p] != DOSE_OK) fail(code[p], msg[p]);
+}
+
+// -------------------------------------------------------------- partition
+// Lanes reducing one row of a block: a power of two near a quarter of the
+// block's mean non-empty row length, 4 .. 64.
+int lanes_log2(int64_t nnz, int64_t nonempty) {
+  const int64_t m = nonempty > 0 ? nnz / nonempty : 0;
+  int lg = 2;
+  while (lg < 6 && (int64_t{1} << (lg + 1)) * 4 <= m) ++lg;
+  return lg;
+}
+
+struct Partition {
+  std::vector<BlockDesc> blocks;
+  std::vector<SplitRow> splits;
+  int64_t n_partials = 0;
+};
+
+Partition build_partition(const int64_t* rp, int64_t n_rows, int block_nnz) {
+  Partition P;
+  P.blocks.reserve(static_cast<size_t>(rp[n_rows] / block_nnz + n_rows / kMaxBlockRows + 16));
+  int64_t r = 0;
+  while (r < n_rows) {
+    const int64_t len = rp[r + 1] - rp[r];
+    if (len > block_nnz) {
+      const int64_t nch = (len + block_nnz - 1) / block_nnz;
+      const int64_t step = (len + nch - 1) / nch;
+      const uint32_t first = static_cast<uint32_t>(P.n_partials);
+      for (int64_t c = 0; c < nch; ++c) {
+        BlockDesc b{};
+        b.nnz_begin = static_cast<uint64_t>(rp[r] + c * step);
+        b.nnz_count = static_cast<uint32_t>(std::min(step, len - c * step));
+        b.row_begin = static_cast<uint32_t>(r);
+        b.row_count = 0;
+        b.meta = 6;
+        b.partial = first + static_cast<uint32_t>(c);
+        P.blocks.push_back(b);
+      }
+      P.splits.push_back(SplitRow{static_cast<uint32_t>(r), first, static_cast<uint32_t>(nch), 0});
+      P.n_partials += nch;
+      ++r;
+      continue;
+    }
+    const int64_t start = r;
+    int64_t nnz = 0, nonempty = 0;
+    while (r < n_rows && r - start < kMaxBlockRows) {
+      const int64_t l = rp[r + 1] - rp[r];
+      if (l > block_nnz || nnz + l > block_nnz) break;
+      nnz += l;
+      nonempty += l > 0;
+      ++r;
+    }
+    BlockDesc b{};
+    b.nnz_begin = static_cast<uint64_t>(rp[start]);
+    b.nnz_count = static_cast<uint32_t>(nnz);
+    b.row_begin = static_cast<uint32_t>(start);
+    b.row_count = static_cast<uint32_t>(r - start);
+    b.meta = static_cast<uint32_t>(lanes_log2(nnz, nonempty));
+    P.blocks.push_back(b);
+  }
+  return P;
+}
+
+int default_block_nnz(int64_t n_rows, int64_t nnz) {
+  // Keep at least ~16 blocks per compute unit when the matrix allows it.
+  const int64_t target = nnz / (256 * 16);
+  int bn = 4096;
+  while (bn > 1024 && bn > target) bn >>= 1;
+  (void)n_rows;
+  return bn;
+}
+
+// ------------------------------------------------------------- operands
+struct Operand {
+  int64_t n_rows = 0, n_cols = 0, nnz = 0;
+  std::vector<int64_t> h_row_ptr;
+  DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
+  DevBuf blocks, splits;
+  int32_t block_nnz = 0;
+  int64_t n_blocks = 0, n_splits = 0, n_partials = 0;
+
+  uint64_t bytes() const {
+    return val.bytes() + col.bytes() + row_ptr.bytes() + blocks.bytes() + splits.bytes();
+  }
+};
+
+void upload_partition(Operand& op, int block_nnz) {
+  Partition P = build_partition(op.h_row_ptr.data(), op.n_rows, block_nnz);
+  DevBuf blocks(std::max<size_t>(1, P.blocks.size()) * sizeof(BlockDesc));
+  DevBuf splits(std::max<size_t>(1, P.splits.size()) * sizeof(SplitRow));
+  if (!P.blocks.empty())
+    HIP_CHECK(hipMemcpy(blocks.get(), P.blocks.data(), P.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
+  if (!P.splits.empty())
+    HIP_CHECK(hipMemcpy(splits.get(), P.splits.data(), P.splits.size() * sizeof(SplitRow), hipMemcpyHostToDevice));
+  op.blocks = std::move(blocks);
+  op.splits = std::move(splits);
+  op.block_nnz = block_nnz;
+  op.n_blocks = static_cast<int64_t>(P.blocks.size());
+  op.n_splits = static_cast<int64_t>(P.splits.size());
+  op.n_partials = P.n_partials;
+}
+
+void upload_row_ptr32(Operand& op, hipStream_t s) {
+  std::vector<uint32_t> rp32(op.h_row_ptr.size());
+  for (size_t i = 0; i < rp32.size(); ++i) rp32[i] = static_cast<uint32_t>(op.h_row_ptr[i]);
+  op.row_ptr = DevBuf(rp32.size() * sizeof(uint32_t));
+  HIP_CHECK(hipMemcpyAsync(op.row_ptr.get(), rp32.data(), rp32.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+size_t padded(int64_t nnz) { return static_cast<size_t>(((nnz + kStreamPad + 63) / 64) * 64); }
+
+}  // namespace
+
+struct dose_matrix_s {
+  int device = 0;
+  int vf = 0, xf = 0;
+  bool has_t = false;
+  Operand A, AT;
+  DevBuf row_scale;  // E4M3: s_i per row of A
+};
+
+namespace {
+
+int scale_mode_A(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleRow : kScaleNone; }
+int scale_mode_AT(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleCol : kScaleNone; }
+
+SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, const float* x, float* y, float* partials) {
+  SpmvArgs a{};
+  a.blocks = op.blocks.get<BlockDesc>();
+  a.val = op.val.get();
+  a.col = op.col.get<int32_t>();
+  a.row_ptr = op.row_ptr.get<uint32_t>();
+  a.scale = sm == kScaleNone ? nullptr : m->row_scale.get<float>();
+  a.x = x;
+  a.y = y;
+  a.partials = partials;
+  a.splits = op.splits.get<SplitRow>();
+  a.n_blocks = op.n_blocks;
+  a.n_splits = op.n_splits;
+  return a;
+}
+
+// Encode A's FP32 source values into its code stream, a row range at a time.
+void encode_values(dose_matrix_s* m, const dose_csr_host* c, hipStream_t s) {
+  Operand& A = m->A;
+  if (A.nnz == 0) return;
+  int64_t max_row = 0;
+  for (int64_t i = 0; i < A.n_rows; ++i) max_row = std::max(max_row, A.h_row_ptr[i + 1] - A.h_row_ptr[i]);
+  const int64_t stage_n = std::max<int64_t>(std::min<int64_t>(A.nnz, int64_t{1} << 26), max_row);
+  DevBuf stage(static_cast<size_t>(stage_n) * sizeof(float));
+  const int vb = value_bytes(m->vf);
+  int64_t r0 = 0;
+  while (r0 < A.n_rows) {
+    int64_t r1 = r0 + 1;
+    // widen the chunk while it fits the staging buffer
+    int64_t lo = r0 + 1, hi = A.n_rows;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo + 1) / 2;
+      if (A.h_row_ptr[mid] - A.h_row_ptr[r0] <= stage_n) lo = mid; else hi = mid - 1;
+    }
+    r1 = lo;
+    const int64_t k0 = A.h_row_ptr[r0], k1 = A.h_row_ptr[r1];
+    if (k1 > k0) {
+      HIP_CHECK(hipMemcpyAsync(stage.get(), c->values + k0, static_cast<size_t>(k1 - k0) * sizeof(float),
+                               hipMemcpyHostToDevice, s));
+      HIP_CHECK(launch_encode_rows(m->vf, A.row_ptr.get<uint32_t>() + r0, static_cast<uint32_t>(k0), r1 - r0,
+                                   stage.get<float>(), static_cast<uint8_t*>(A.val.get()) + k0 * vb,
+                                   m->vf == kFp8 ? m->row_scale.get<float>() + r0 : nullptr, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+    } else if (m->vf == kFp8) {
+      HIP_CHECK(launch_encode_rows(m->vf, A.row_ptr.get<uint32_t>() + r0, static_cast<uint32_t>(k0), r1 - r0,
+                                   stage.get<float>(), A.val.get(), m->row_scale.get<float>() + r0, s));
+    }
+    r0 = r1;
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+}
+
+// A^T on the device: stable radix sort of (column, entry) pairs, so every row
+// of A^T lists its entries in ascending row of A.
+void build_transpose(dose_matrix_s* m, int block_nnz_t, hipStream_t s) {
+  const Operand& A = m->A;
+  Operand& T = m->AT;
+  if (A.nnz > INT32_MAX) fail(DOSE_ERR_UNSUPPORTED, "transpose needs nnz < 2^31");
+  T.n_rows = A.n_cols;
+  T.n_cols = A.n_rows;
+  T.nnz = A.nnz;
+  const int vb = value_bytes(m->vf);
+  T.val = DevBuf(padded(T.nnz) * vb);
+  T.col = DevBuf(padded(T.nnz) * sizeof(int32_t));
+  HIP_CHECK(hipMemsetAsync(T.val.get(), 0, T.val.bytes(), s));
+  HIP_CHECK(hipMemsetAsync(T.col.get(), 0, T.col.bytes(), s));
+  DevBuf rp64(static_cast<size_t>(T.n_rows + 1) * sizeof(int64_t));
+  if (A.nnz > 0) {
+    const int64_t n = A.nnz;
+    DevBuf rows(static_cast<size_t>(n) * 4), keys_out(static_cast<size_t>(n) * 4), perm_in(static_cast<size_t>(n) * 4),
+        perm_out(static_cast<size_t>(n) * 4);
+    HIP_CHECK(launch_row_ids(A.row_ptr.get<uint32_t>(), A.n_rows, static_cast<uint64_t>(n), rows.get<uint32_t>(), s));
+    HIP_CHECK(launch_iota(perm_in.get<uint32_t>(), n, s));
+    int end_bit = 1;
+    while (end_bit < 32 && (int64_t{1} << end_bit) < A.n_cols) ++end_bit;
+    size_t tmp_bytes = 0;
+    HIP_CHECK(radix_sort_pairs(nullptr, &tmp_bytes, reinterpret_cast<const uint32_t*>(A.col.get()),
+                               keys_out.get<uint32_t>(), perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
+    DevBuf tmp(tmp_bytes);
+    HIP_CHECK(radix_sort_pairs(tmp.get(), &tmp_bytes, reinterpret_cast<const uint32_t*>(A.col.get()),
+                               keys_out.get<uint32_t>(), perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
+    HIP_CHECK(launch_gather_transpose(m->vf, perm_out.get<uint32_t>(), rows.get<uint32_t>(), A.val.get(), T.val.get(),
+                                      T.col.get<int32_t>(), n, s));
+    HIP_CHECK(launch_row_ptr_from_sorted(keys_out.get<uint32_t>(), n, T.n_rows, rp64.get<int64_t>(), s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  } else {
+    HIP_CHECK(hipMemsetAsync(rp64.get(), 0, rp64.bytes(), s));
+  }
+  T.h_row_ptr.resize(static_cast<size_t>(T.n_rows + 1));
+  HIP_CHECK(hipMemcpyAsync(T.h_row_ptr.data(), rp64.get(), rp64.bytes(), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  upload_row_ptr32(T, s);
+  upload_partition(T, block_nnz_t);
+}
+
+void check_block_nnz(int32_t bn) {
+  if (!is_pow2(bn) || bn < kMinBlockNnz || bn > kMaxBlockNnz)
+    fail(DOSE_ERR_INVALID_ARGUMENT, "block_nnz must be a power of two in [256, 8192]");
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const auto pa = reinterpret_cast<uintptr_t>(a), pb = reinterpret_cast<uintptr_t>(b);
+  return na > 0 && nb > 0 && pa < pb + nb && pb < pa + na;
+}
+
+// Products whose operand has split rows need one partial per chunk; they are
+// allocated per call in stream order so that concurrent calls never share.
+void run_product(const dose_matrix_s* m, const Operand& op, int sm, const float* x, float* y, hipStream_t s) {
+  float* partials = nullptr;
+  if (op.n_splits > 0) HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partials), op.n_partials * sizeof(float), s));
+  SpmvArgs a = make_args(m, op, sm, x, y, partials);
+  hipError_t e = launch_spmv(m->vf, sm, 1, op.block_nnz, a, s);
+  if (e == hipSuccess) e = launch_combine(sm, 1, a, s);
+  if (partials) (void)hipFreeAsync(partials, s);
+  HIP_CHECK(e);
+}
+
+// ------------------------------------------------------------ tuning cache
+std::mutex g_tune_mu;
+
+std::string tune_key(const dose_matrix_s* m, const Operand& op, int n_rhs) {
+  std::ostringstream k;
+  k << "v1:" << op.n_rows << "x" << op.n_cols << ":" << op.nnz << ":f" << m->vf << ":r" << n_rhs;
+  return k.str();
+}
+
+int tune_lookup(const std::string& key) {
+  const char* path = std::getenv("DOSE_TUNE_CACHE");
+  if (!path) return 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::ifstream f(path);
+  std::string k;
+  int v = 0, found = 0;
+  while (f >> k >> v)
+    if (k == key) found = v;
+  return found;
+}
+
+void tune_store(const std::string& key, int v) {
+  const char* path = std::getenv("DOSE_TUNE_CACHE");
+  if (!path) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << v << "\n";
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ batch plans
+struct dose_batch_plan_s {
+  int device = 0;
+  int vf = 0, sm = 0, n_rhs = 0, cap_nnz = 0;
+  int64_t n_work = 0, n_split = 0;
+  int grid = 0;
+  DevBuf args, work, split_items, split_idx, partials;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~dose_batch_plan_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
+namespace {
+
+void check_items(const dose_batch_item* items, int32_t n_items) {
+  if (!items || n_items <= 0) fail(DOSE_ERR_INVALID_ARGUMENT, "no items");
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_batch_item& it = items[i];
+    if (!it.A) fail(DOSE_ERR_INVALID_ARGUMENT, "item without matrix");
+    if (it.n_rhs != 1 && it.n_rhs != 2 && it.n_rhs != 4) fail(DOSE_ERR_UNSUPPORTED, "n_rhs must be 1, 2 or 4");
+    if (it.ldx != it.n_rhs || it.ldy != it.n_rhs) fail(DOSE_ERR_UNSUPPORTED, "ldx and ldy must equal n_rhs");
+    if ((it.A->A.n_cols > 0 && !it.x) || (it.A->A.n_rows > 0 && !it.y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
+    if (it.A->vf != items[0].A->vf) fail(DOSE_ERR_UNSUPPORTED, "items mix value formats");
+    if (it.n_rhs != items[0].n_rhs) fail(DOSE_ERR_UNSUPPORTED, "items mix n_rhs");
+    if (it.A->device != items[0].A->device) fail(DOSE_ERR_INVALID_ARGUMENT, "items on different devices");
+    if (overlaps(it.x, it.A->A.n_cols * it.n_rhs * 4, it.y, it.A->A.n_rows * it.n_rhs * 4))
+      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+    if (it.n_rhs == 4 && it.A->A.block_nnz > 4096)
+      fail(DOSE_ERR_UNSUPPORTED, "n_rhs 4 needs block_nnz <= 4096");
+    if ((reinterpret_cast<uintptr_t>(it.x) | reinterpret_cast<uintptr_t>(it.y)) % (4 * it.n_rhs) != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be aligned to n_rhs floats");
+  }
+}
+
+int batched_grid(int n_work) {
+  int dev = 0, cus = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  return std::max(1, std::min(n_work, cus * 8));
+}
+
+// Time the plain product of one operand under a block size (median of runs).
+double time_partition(dose_matrix_s* m, Operand& op, int sm, int n_rhs, const float* x, float* y, hipStream_t s) {
+  float* partials = nullptr;
+  if (op.n_splits > 0) HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partials), op.n_partials * n_rhs * sizeof(float), s));
+  SpmvArgs a = make_args(m, op, sm, x, y, partials);
+  hipEvent_t e0, e1;
+  HIP_CHECK(hipEventCreate(&e0));
+  HIP_CHECK(hipEventCreate(&e1));
+  std::vector<float> ts;
+  for (int rep = 0; rep < 7; ++rep) {
+    HIP_CHECK(hipEventRecord(e0, s));
+    HIP_CHECK(launch_spmv(m->vf, sm, n_rhs, op.block_nnz, a, s));
+    HIP_CHECK(launch_combine(sm, n_rhs, a, s));
+    HIP_CHECK(hipEventRecord(e1, s));
+    HIP_CHECK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    if (rep > 0) ts.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (partials) HIP_CHECK(hipFreeAsync(partials, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  std::sort(ts.begin(), ts.end());
+  return ts[ts.size() / 2];
+}
+
+void autotune_matrix(dose_matrix_s* m, int n_rhs, const float* x, float* y, hipStream_t s) {
+  Operand& op = m->A;
+  const std::string key = tune_key(m, op, n_rhs);
+  int best = tune_lookup(key);
+  if (best == 0) {
+    double best_t = 1e30;
+    const int hi = n_rhs == 4 ? 4096 : 8192;
+    for (int bn = 1024; bn <= hi; bn *= 2) {
+      upload_partition(op, bn);
+      const double t = time_partition(m, op, scale_mode_A(m), n_rhs, x, y, s);
+      if (t < best_t) best_t = t, best = bn;
+    }
+    tune_store(key, best);
+  }
+  if (op.block_nnz != best) upload_partition(op, best);
+}
+
+dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uint32_t flags, hipStream_t s) {
+  check_items(items, n_items);
+  auto plan = std::make_unique<dose_batch_plan_s>();
+  const dose_matrix_s* m0 = items[0].A;
+  plan->device = m0->device;
+  plan->vf = m0->vf;
+  plan->sm = scale_mode_A(m0);
+  plan->n_rhs = items[0].n_rhs;
+  if (flags & DOSE_PLAN_AUTOTUNE) {
+    std::map<dose_matrix_s*, int> seen;
+    for (int32_t i = 0; i < n_items; ++i)
+      if (seen.emplace(items[i].A, i).second) autotune_matrix(items[i].A, items[i].n_rhs, items[i].x, items[i].y, s);
+  }
+  std::vector<SpmvArgs> args(n_items);
+  std::vector<WorkItem> work;
+  std::vector<uint32_t> sp_item, sp_idx;
+  int64_t partial_total = 0;
+  std::vector<int64_t> partial_off(n_items);
+  for (int32_t i = 0; i < n_items; ++i) {
+    partial_off[i] = partial_total;
+    partial_total += items[i].A->A.n_partials * plan->n_rhs;
+    plan->cap_nnz = std::max(plan->cap_nnz, items[i].A->A.block_nnz);
+  }
+  plan->partials = DevBuf(static_cast<size_t>(std::max<int64_t>(partial_total, 1)) * sizeof(float));
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_matrix_s* m = items[i].A;
+    args[i] = make_args(m, m->A, plan->sm, items[i].x, items[i].y, plan->partials.get<float>() + partial_off[i]);
+    for (int64_t b = 0; b < m->A.n_blocks; ++b) work.push_back(WorkItem{static_cast<uint32_t>(i), static_cast<uint32_t>(b)});
+    for (int64_t k = 0; k < m->A.n_splits; ++k) {
+      sp_item.push_back(static_cast<uint32_t>(i));
+      sp_idx.push_back(static_cast<uint32_t>(k));
+    }
+  }
+  plan->n_work = static_cast<int64_t>(work.size());
+  plan->n_split = static_cast<int64_t>(sp_item.size());
+  plan->args = DevBuf(args.size() * sizeof(SpmvArgs));
+  plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(WorkItem));
+  plan->split_items = DevBuf(std::max<size_t>(1, sp_item.size()) * 4);
+  plan->split_idx = DevBuf(std::max<size_t>(1, sp_idx.size()) * 4);
+  HIP_CHECK(hipMemcpy(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice));
+  if (!work.empty()) HIP_CHECK(hipMemcpy(plan->work.get(), work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+  if (!sp_item.empty()) {
+    HIP_CHECK(hipMemcpy(plan->split_items.get(), sp_item.data(), sp_item.size() * 4, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(plan->split_idx.get(), sp_idx.data(), sp_idx.size() * 4, hipMemcpyHostToDevice));
+  }
+  plan->grid = batched_grid(static_cast<int>(std::min<int64_t>(plan->n_work, INT32_MAX)));
+  return plan.release();
+}
+
+void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
+  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->cap_nnz, p->args.get<SpmvArgs>(), p->work.get<WorkItem>(),
+                                p->n_work, p->grid, s));
+  HIP_CHECK(launch_combine_batched(p->sm, p->n_rhs, p->args.get<SpmvArgs>(), p->split_items.get<uint32_t>(),
+                                   p->split_idx.get<uint32_t>(), p->n_split, s));
+}
+
+int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4095) / 4096))); }
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* dose_status_string(dose_status s) {
+  switch (s) {
+    case DOSE_OK: return "ok";
+    case DOSE_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case DOSE_ERR_BAD_CSR: return "malformed CSR matrix";
+    case DOSE_ERR_UNSUPPORTED: return "unsupported";
+    case DOSE_ERR_NO_TRANSPOSE: return "matrix has no transpose";
+    case DOSE_ERR_OUT_OF_MEMORY: return "out of memory";
+    case DOSE_ERR_HIP: return "HIP runtime error";
+    case DOSE_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+const char* dose_last_error(void) { return g_last_error.c_str(); }
+
+dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf) {
+  return guarded([&] { validate_csr(csr, vf, xf); });
+}
+
+dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t block_nnz, int64_t* blocks,
+                                   int64_t cap, int64_t* n_blocks) {
+  return guarded([&] {
+    if (!row_ptr || !n_blocks || n_rows < 0 || (cap > 0 && !blocks)) fail(DOSE_ERR_INVALID_ARGUMENT, "bad argument");
+    check_block_nnz(block_nnz);
+    Partition P = build_partition(row_ptr, n_rows, block_nnz);
+    *n_blocks = static_cast<int64_t>(P.blocks.size());
+    for (int64_t i = 0; i < std::min<int64_t>(cap, *n_blocks); ++i) {
+      const BlockDesc& b = P.blocks[i];
+      blocks[5 * i + 0] = static_cast<int64_t>(b.nnz_begin);
+      blocks[5 * i + 1] = b.nnz_count;
+      blocks[5 * i + 2] = b.row_begin;
+      blocks[5 * i + 3] = b.row_count == 0 ? -1 : static_cast<int64_t>(b.row_count);
+      blocks[5 * i + 4] = int64_t{1} << (b.meta & 7u);
+    }
+  });
+}
+
+dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf, uint32_t flags,
+                               void* hip_stream, dose_matrix* out) {
+  return guarded([&] {
+    if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    validate_csr(csr, vf, xf);
+    hipStream_t s = as_stream(hip_stream);
+    auto m = std::make_unique<dose_matrix_s>();
+    HIP_CHECK(hipGetDevice(&m->device));
+    m->vf = vf;
+    m->xf = xf;
+    Operand& A = m->A;
+    A.n_rows = csr->n_rows;
+    A.n_cols = csr->n_cols;
+    A.nnz = csr->nnz;
+    A.h_row_ptr.assign(csr->row_ptr, csr->row_ptr + csr->n_rows + 1);
+    const int vb = value_bytes(vf);
+    A.val = DevBuf(padded(A.nnz) * vb);
+    A.col = DevBuf(padded(A.nnz) * sizeof(int32_t));
+    if (vf == kFp8) m->row_scale = DevBuf(static_cast<size_t>(std::max<int64_t>(A.n_rows, 1)) * sizeof(float));
+    HIP_CHECK(hipMemsetAsync(A.val.get(), 0, A.val.bytes(), s));
+    HIP_CHECK(hipMemsetAsync(A.col.get(), 0, A.col.bytes(), s));
+    upload_row_ptr32(A, s);
+    if (A.nnz > 0)
+      HIP_CHECK(hipMemcpyAsync(A.col.get(), csr->col_idx, static_cast<size_t>(A.nnz) * sizeof(int32_t),
+                               hipMemcpyHostToDevice, s));
+    encode_values(m.get(), csr, s);
+    upload_partition(A, default_block_nnz(A.n_rows, A.nnz));
+    if (flags & DOSE_CREATE_TRANSPOSE) {
+      build_transpose(m.get(), default_block_nnz(A.n_cols, A.nnz), s);
+      m->has_t = true;
+    }
+    HIP_CHECK(hipStreamSynchronize(s));
+    *out = m.release();
+  });
+}
+
+dose_status dose_matrix_set_partition(dose_matrix m, int32_t block_nnz, int32_t block_nnz_t) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    check_block_nnz(block_nnz);
+    if (m->has_t) check_block_nnz(block_nnz_t);
+    DeviceGuard g(m->device);
+    HIP_CHECK(hipDeviceSynchronize());
+    upload_partition(m->A, block_nnz);
+    if (m->has_t) upload_partition(m->AT, block_nnz_t);
+  });
+}
+
+dose_status dose_matrix_decode(dose_matrix m, int32_t part, int64_t row_begin, int64_t row_end, int64_t* row_ptr_out,
+                               int32_t* col_out, float* val_out) {
+  return guarded([&] {
+    if (!m || !row_ptr_out) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    if (part != DOSE_PART_A && part != DOSE_PART_AT) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown part");
+    if (part == DOSE_PART_AT && !m->has_t) fail(DOSE_ERR_NO_TRANSPOSE, "matrix has no transpose");
+    const Operand& op = part == DOSE_PART_A ? m->A : m->AT;
+    if (row_begin < 0 || row_end < row_begin || row_end > op.n_rows) fail(DOSE_ERR_INVALID_ARGUMENT, "row range");
+    DeviceGuard g(m->device);
+    const int64_t nb = op.h_row_ptr[row_begin], ne = op.h_row_ptr[row_end], n = ne - nb;
+    for (int64_t i = row_begin; i <= row_end; ++i) row_ptr_out[i - row_begin] = op.h_row_ptr[i] - nb;
+    if (n == 0) return;
+    if (col_out)
+      HIP_CHECK(hipMemcpy(col_out, op.col.get<int32_t>() + nb, static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (val_out) {
+      DevBuf tmp(static_cast<size_t>(n) * sizeof(float));
+      const int sm = part == DOSE_PART_A ? scale_mode_A(m) : scale_mode_AT(m);
+      HIP_CHECK(launch_decode(m->vf, sm, op.val.get(), op.col.get<int32_t>(), m->row_scale.get<float>(),
+                              op.row_ptr.get<uint32_t>(), row_begin, row_end - row_begin, static_cast<uint64_t>(nb), n,
+                              tmp.get<float>(), nullptr));
+      HIP_CHECK(hipDeviceSynchronize());
+      HIP_CHECK(hipMemcpy(val_out, tmp.get(), static_cast<size_t>(n) * sizeof(float), hipMemcpyDeviceToHost));
+    }
+  });
+}
+
+dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
+  return guarded([&] {
+    if (!m || !info) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    const Operand& A = m->A;
+    info->n_rows = A.n_rows;
+    info->n_cols = A.n_cols;
+    info->nnz = A.nnz;
+    info->value_format = m->vf;
+    info->index_format = m->xf;
+    info->has_transpose = m->has_t ? 1 : 0;
+    info->block_nnz = A.block_nnz;
+    info->n_blocks = A.n_blocks;
+    info->n_split_rows = A.n_splits;
+    info->block_nnz_t = m->has_t ? m->AT.block_nnz : 0;
+    info->n_blocks_t = m->has_t ? m->AT.n_blocks : 0;
+    info->n_split_rows_t = m->has_t ? m->AT.n_splits : 0;
+    info->device_bytes = A.bytes() + m->row_scale.bytes() + (m->has_t ? m->AT.bytes() : 0);
+    const uint64_t per_nnz = static_cast<uint64_t>(value_bytes(m->vf)) + 4;
+    const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
+    info->spmv_bytes = A.nnz * per_nnz + (A.n_rows + 1) * 4 + A.n_rows * scale_b + 4 * A.n_cols + 4 * A.n_rows;
+    // A^T reads the scale of A's rows through its columns: 4 B per column of A^T
+    info->adjoint_bytes = m->has_t ? A.nnz * per_nnz + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
+  });
+}
+
+dose_status dose_matrix_destroy(dose_matrix m) {
+  return guarded([&] {
+    if (!m) return;
+    {
+      DeviceGuard g(m->device);
+      (void)hipDeviceSynchronize();
+      delete m;
+    }
+  });
+}
+
+dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    if ((m->A.n_cols > 0 && !x) || (m->A.n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
+    if (overlaps(x, m->A.n_cols * 4, y, m->A.n_rows * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+    DeviceGuard g(m->device);
+    run_product(m, m->A, scale_mode_A(m), x, y, as_stream(hip_stream));
+  });
+}
+
+dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* gout, void* hip_stream) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    if (!m->has_t) fail(DOSE_ERR_NO_TRANSPOSE, "matrix was created without DOSE_CREATE_TRANSPOSE");
+    if ((m->A.n_rows > 0 && !v) || (m->A.n_cols > 0 && !gout)) fail(DOSE_ERR_INVALID_ARGUMENT, "null v or g");
+    if (overlaps(v, m->A.n_rows * 4, gout, m->A.n_cols * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "v and g overlap");
+    DeviceGuard g(m->device);
+    run_product(m, m->AT, scale_mode_AT(m), v, gout, as_stream(hip_stream));
+  });
+}
+
+dose_status dose_spmv_batched(const dose_batch_item* items, int32_t n_items, void* hip_stream) {
+  return guarded([&] {
+    check_items(items, n_items);
+    DeviceGuard g(items[0].A->device);
+    std::unique_ptr<dose_batch_plan_s> p(build_plan(items, n_items, 0, as_stream(hip_stream)));
+    enqueue_plan(p.get(), as_stream(hip_stream));
+    // the plan's device buffers must outlive the launch
+    HIP_CHECK(hipStreamSynchronize(as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items, uint32_t flags, void* hip_stream,
+                                   dose_batch_plan* out) {
+  return guarded([&] {
+    if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    check_items(items, n_items);
+    DeviceGuard g(items[0].A->device);
+    std::unique_ptr<dose_batch_plan_s> p(build_plan(items, n_items, flags, as_stream(hip_stream)));
+    hipStream_t cap;
+    HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      try {
+        enqueue_plan(p.get(), cap);
+      } catch (...) {
+        hipGraph_t tmp = nullptr;
+        (void)hipStreamEndCapture(cap, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        (void)hipStreamDestroy(cap);
+        throw;
+      }
+      e = hipStreamEndCapture(cap, &p->graph);
+    }
+    (void)hipStreamDestroy(cap);
+    HIP_CHECK(e);
+    HIP_CHECK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    *out = p.release();
+  });
+}
+
+dose_status dose_batch_plan_launch(dose_batch_plan p, void* hip_stream) {
+  return guarded([&] {
+    if (!p || !p->exec) fail(DOSE_ERR_INVALID_ARGUMENT, "plan is null");
+    DeviceGuard g(p->device);
+    HIP_CHECK(hipGraphLaunch(p->exec, as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_batch_plan_destroy(dose_batch_plan p) {
+  return guarded([&] {
+    if (!p) return;
+    DeviceGuard g(p->device);
+    (void)hipDeviceSynchronize();
+    delete p;
+  });
+}
+
+dose_status dose_objective(int64_t n, const float* d, const float* p, const float* w, float* seed, double* f_out,
+                           void* hip_stream) {
+  return guarded([&] {
+    if (n < 0 || !f_out || (n > 0 && (!d || !p || !w))) fail(DOSE_ERR_INVALID_ARGUMENT, "bad argument");
+    hipStream_t s = as_stream(hip_stream);
+    const int np = n_partial_for(n);
+    double* partial = nullptr;
+    HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), np * sizeof(double), s));
+    hipError_t e = launch_objective(n, d, p, w, seed, partial, np, f_out, s);
+    (void)hipFreeAsync(partial, s);
+    HIP_CHECK(e);
+  });
+}
+
+dose_status dose_norm2(int64_t n, const float* gv, double* out, void* hip_stream) {
+  return guarded([&] {
+    if (n < 0 || !out || (n > 0 && !gv)) fail(DOSE_ERR_INVALID_ARGUMENT, "bad argument");
+    hipStream_t s = as_stream(hip_stream);
+    const int np = n_partial_for(n);
+    double* partial = nullptr;
+    HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partial), np * sizeof(double), s));
+    hipError_t e = launch_norm2(n, gv, partial, np, out, s);
+    (void)hipFreeAsync(partial, s);
+    HIP_CHECK(e);
+  });
+}
+
+dose_status dose_probe_stream_read(const void* buf, uint64_t bytes, float* sink, void* hip_stream) {
+  return guarded([&] {
+    if (!buf || !sink) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    HIP_CHECK(launch_probe_read(buf, bytes, sink, as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_probe_copy(const void* src, void* dst, uint64_t bytes, void* hip_stream) {
+  return guarded([&] {
+    if (!src || !dst) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    if (overlaps(src, bytes, dst, bytes)) fail(DOSE_ERR_INVALID_ARGUMENT, "src and dst overlap");
+    HIP_CHECK(launch_probe_copy(src, dst, bytes, as_stream(hip_stream)));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+"""Host-only tests of libdose: exported symbols, CSR validation, the row-block
+partition and the byte model.  None of these touch a GPU."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2103_09683_amd as dm
+from paper_2103_09683_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "dose.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:dose_status|const char\*)\s+(dose_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _header_functions()
+    assert len(names) >= 19
+    lib = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    # the binding declares exactly the header's entry points
+    assert sorted(_lib.SIGNATURES) == names
+
+
+def test_status_strings():
+    lib = _lib.load()
+    assert lib.dose_status_string(0) == b"ok"
+    assert lib.dose_status_string(_lib.ERR_BAD_CSR) == b"malformed CSR matrix"
+    assert lib.dose_status_string(-99) == b"unknown status"
+
+
+# ------------------------------------------------------------------ validation
+def _good():
+    rp = np.array([0, 2, 2, 5], np.int64)
+    c = np.array([0, 3, 1, 2, 4], np.int32)
+    v = np.array([0.5, 1.0, 0.25, 2.0, 3.0], np.float32)
+    return rp, c, v
+
+
+def test_validate_accepts_good_and_empty():
+    rp, c, v = _good()
+    assert dm.csr_validate(rp, c, v, 5) == 0
+    assert dm.csr_validate(np.array([0], np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32), 0) == 0
+    assert dm.csr_validate(np.zeros(4, np.int64), np.zeros(0, np.int32), np.zeros(0, np.float32), 7) == 0
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda rp, c, v: rp.__setitem__(0, 1), _lib.ERR_BAD_CSR),              # row_ptr[0] != 0
+    (lambda rp, c, v: rp.__setitem__(1, 6), _lib.ERR_BAD_CSR),              # decreasing / out of range
+    (lambda rp, c, v: c.__setitem__(1, 5), _lib.ERR_BAD_CSR),               # column out of range
+    (lambda rp, c, v: c.__setitem__(1, -1), _lib.ERR_BAD_CSR),              # negative column
+    (lambda rp, c, v: c.__setitem__(3, 1), _lib.ERR_BAD_CSR),               # duplicate column
+    (lambda rp, c, v: c.__setitem__(2, 3), _lib.ERR_BAD_CSR),               # not ascending
+    (lambda rp, c, v: v.__setitem__(0, np.nan), _lib.ERR_BAD_CSR),
+    (lambda rp, c, v: v.__setitem__(4, -np.inf), _lib.ERR_BAD_CSR),
+    (lambda rp, c, v: v.__setitem__(4, 65520.0), _lib.ERR_UNSUPPORTED),     # rounds to inf in FP16
+])
+def test_validate_rejects(mutate, code):
+    rp, c, v = _good()
+    mutate(rp, c, v)
+    assert dm.csr_validate(rp, c, v, 5) == code
+
+
+def test_validate_format_ranges():
+    rp, c, v = _good()
+    v[4] = 65519.0  # rounds to 65504: representable
+    assert dm.csr_validate(rp, c, v, 5, "fp16") == 0
+    v[4] = 3.0e38
+    assert dm.csr_validate(rp, c, v, 5, "fp16") == _lib.ERR_UNSUPPORTED
+    assert dm.csr_validate(rp, c, v, 5, "bf16") == 0
+    v[4] = np.float32(3.4e38)  # rounds past the largest bfloat16
+    assert dm.csr_validate(rp, c, v, 5, "bf16") == _lib.ERR_UNSUPPORTED
+    assert dm.csr_validate(rp, c, v, 5, "fp8e4m3_rowscale") == 0
+
+
+def test_validate_rejects_nnz_mismatch_and_unknown_format():
+    rp, c, v = _good()
+    rp[-1] = 4
+    assert dm.csr_validate(rp, c[:4], v[:4], 5) == 0
+    lib = _lib.load()
+    cs, keep = dm._csr_struct(*_good(), 5)
+    cs.nnz = 4
+    assert lib.dose_csr_validate(ctypes.byref(cs), 1, 1) == _lib.ERR_BAD_CSR
+    cs, keep = dm._csr_struct(*_good(), 5)
+    assert lib.dose_csr_validate(ctypes.byref(cs), 9, 1) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dose_csr_validate(ctypes.byref(cs), 1, 7) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dose_csr_validate(None, 1, 1) == _lib.ERR_INVALID_ARGUMENT
+    assert b"null" in lib.dose_last_error()
+
+
+# ------------------------------------------------------------------ partition
+def _random_row_ptr(rng, n_rows, long_rows=()):
+    lens = rng.integers(0, 300, size=n_rows)
+    lens[rng.random(n_rows) < 0.5] = 0
+    for i, L in long_rows:
+        lens[i] = L
+    rp = np.zeros(n_rows + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    return rp
+
+
+@pytest.mark.parametrize("block_nnz", [256, 1024, 4096, 8192])
+def test_partition_covers_every_entry_and_row_once(block_nnz):
+    rng = np.random.default_rng(block_nnz)
+    rp = _random_row_ptr(rng, 5000, long_rows=[(7, 30000), (4000, 8193), (4001, 8192), (4999, 100000)])
+    B = dm.partition_preview(rp, block_nnz)
+    nnz_pos, row_pos = 0, 0
+    split_row, split_end = None, None
+    for nb, cnt, r0, rc, G in B:
+        assert nb == nnz_pos, "blocks must tile the entries in order"
+        assert 0 < cnt <= block_nnz or (cnt == 0 and rc > 0)
+        assert G in (4, 8, 16, 32, 64)
+        if rc == -1:  # chunk of a split row
+            assert rp[r0 + 1] - rp[r0] > block_nnz
+            if split_row != r0:
+                assert r0 == row_pos and nb == rp[r0]
+                split_row, split_end = r0, rp[r0 + 1]
+            nnz_pos += cnt
+            if nnz_pos == split_end:
+                row_pos = r0 + 1
+        else:
+            assert r0 == row_pos and 1 <= rc <= 1024
+            assert rp[r0] == nb and rp[r0 + rc] - rp[r0] == cnt
+            row_pos += rc
+            nnz_pos += cnt
+    assert nnz_pos == rp[-1] and row_pos == rp.size - 1
+
+
+def test_partition_is_deterministic_and_balanced_chunks():
+    rp = np.array([0, 10000, 10000, 10005], np.int64)
+    a = dm.partition_preview(rp, 4096)
+    b = dm.partition_preview(rp, 4096)
+    np.testing.assert_array_equal(a, b)
+    chunks = a[a[:, 3] == -1]
+    assert chunks[:, 1].tolist() == [3334, 3334, 3332]
+
+
+def test_partition_empty_inputs():
+    assert dm.partition_preview(np.array([0], np.int64), 1024).shape == (0, 5)
+    B = dm.partition_preview(np.zeros(2501, np.int64), 1024)
+    assert B[:, 3].tolist() == [1024, 1024, 452] and B[:, 1].sum() == 0
+
+
+def test_partition_rejects_bad_block_size():
+    with pytest.raises(dm.DoseError):
+        dm.partition_preview(np.array([0, 1], np.int64), 3000)
+    with pytest.raises(dm.DoseError):
+        dm.partition_preview(np.array([0, 1], np.int64), 128)
+
+
+# ------------------------------------------------------------------ byte model
+def _table1():
+    with open(os.path.join(ROOT, "tests", "golden", "paper_table1.json")) as f:
+        return json.load(f)
+
+
+def test_byte_model_reproduces_paper_oi_bound():
+    t = _table1()
+    liver1 = t["table1"][0]
+    b = dm.byte_model(liver1["nnz"], liver1["rows"], liver1["cols"], value_bytes=2, index_bytes=4,
+                      row_ptr_bytes=4, x_bytes=8, y_bytes=8)
+    assert b == 6 * liver1["nnz"] + 12 * liver1["rows"] + 8 * liver1["cols"]
+    assert round(2 * liver1["nnz"] / b, 3) == t["oi_upper_bound_liver1"]
+
+
+def test_storage_model_reproduces_table1_sizes():
+    """Table I's sizes fit FP16 values + int32 columns + int32 row offsets:
+    solving size = 6 nnz + 4 rows for nnz gives the printed non-zeros to
+    three significant figures on all six matrices, while 6 nnz alone (no row
+    offsets) or 8 B/nnz (FP32 values) do not."""
+    def sig3(v):
+        return float(f"{v:.2e}")
+
+    rows = _table1()["table1"]
+    for r in rows:
+        assert abs(dm.storage_bytes(r["nnz"], r["rows"]) / 1e9 - r["size_gb"]) <= 6 * 0.005 * 10 ** np.floor(
+            np.log10(r["nnz"])) / 1e9 + 1e-9
+        nnz_fit = (r["size_gb"] * 1e9 - 4 * r["rows"]) / 6
+        assert sig3(nnz_fit) == r["nnz"], r["beam"]
+        assert round(r["nnz"] / (r["rows"] * r["cols"]) * 100, 2) == r["ratio_pct"], r["beam"]
+    assert any(sig3(r["size_gb"] * 1e9 / 6) != r["nnz"] for r in rows)
+    assert all(sig3((r["size_gb"] * 1e9 - 4 * r["rows"]) / 8) != r["nnz"] for r in rows)
