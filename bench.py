@@ -174,8 +174,8 @@ def main(argv=None):
         "config": {"workload": spec.name, "n_rows": spec.n_rows, "n_cols": spec.n_cols, "nnz": nnz,
                    "empty_row_frac": float(np.mean(np.diff(rp) == 0)),
                    "value_format": args.format, "index_format": "i32", "accumulate": "f32",
-                   "block_nnz": info["block_nnz"], "n_blocks": info["n_blocks"],
-                   "n_split_rows": info["n_split_rows"]},
+                   "group_nnz": info["group_nnz"], "n_groups": info["n_groups"],
+                   "n_groups_x_in_lds": info["n_groups_windowed"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": info["spmv_bytes"],
@@ -193,7 +193,8 @@ def main(argv=None):
         variants["adjoint"] = {"ms": round(ms_a, 5), "GNNZ_per_s": round(nnz / (ms_a * 1e-3) / 1e9, 3),
                                "GBps_algorithmic": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
                                "frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                               "block_nnz_t": info["block_nnz_t"], "n_split_rows_t": info["n_split_rows_t"]}
+                               "group_nnz_t": info["group_nnz_t"], "n_groups_t": info["n_groups_t"],
+                               "n_groups_t_x_in_lds": info["n_groups_windowed_t"]}
         p_h, w_h = dosegen.objective_masks(spec.nx, spec.ny, spec.nz)
         p, w = torch.from_numpy(p_h).cuda(), torch.from_numpy(w_h).cuda()
         seed = torch.empty_like(y)

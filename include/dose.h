@@ -87,12 +87,13 @@ typedef struct {
 typedef struct {
   int64_t n_rows, n_cols, nnz;
   int32_t value_format, index_format, has_transpose;
-  int32_t block_nnz;            /* row-block size of the partition of A      */
-  int64_t n_blocks;             /* row blocks of A                           */
-  int64_t n_split_rows;         /* rows of A longer than block_nnz           */
-  int32_t block_nnz_t;          /* the same for A^T (0 without transpose)    */
+  int32_t group_nnz;            /* row-group size of the partition of A      */
+  int64_t n_groups;             /* row groups of A                           */
+  int64_t n_groups_windowed;    /* groups of A whose x window fits in LDS
+                                   (single-vector products)                 */
+  int32_t group_nnz_t;          /* the same for A^T (0 without transpose)    */
   int32_t reserved0;
-  int64_t n_blocks_t, n_split_rows_t;
+  int64_t n_groups_t, n_groups_windowed_t;
   uint64_t device_bytes;        /* device memory held by the matrix          */
   uint64_t spmv_bytes;          /* algorithmic HBM bytes of one dose_spmv:
                                    nnz*(value+index) + (n_rows+1)*4 row
@@ -123,12 +124,12 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf,
                                dose_index_format xf, uint32_t flags, void* hip_stream,
                                dose_matrix* out);
 
-/* Re-partition a matrix (A, and A^T if stored) into row blocks of at most
- * block_nnz entries (a power of two, 256 .. 8192; longer rows are split into
- * chunks and combined in a fixed order).  The partition fixes the summation
- * order, so products are bitwise identical between any two calls made under
- * the same partition.  Synchronous. */
-dose_status dose_matrix_set_partition(dose_matrix m, int32_t block_nnz, int32_t block_nnz_t);
+/* Re-partition a matrix (A, and A^T if stored) into row groups of about
+ * group_nnz entries (a power of two, 1024 .. 2^20; a longer row is a group of
+ * its own).  A group is the work of one workgroup.  The partition changes
+ * speed only: every row is summed in an order fixed by its own entries, so
+ * products are bitwise identical under any partition.  Synchronous. */
+dose_status dose_matrix_set_partition(dose_matrix m, int32_t group_nnz, int32_t group_nnz_t);
 
 /* Copy rows [row_begin, row_end) of the stored operand `part` (DOSE_PART_A or
  * DOSE_PART_AT) back to the host, decoded to FP32 on the device.
@@ -171,7 +172,7 @@ typedef struct {
 
 /* All items in one persistent launch (robust optimisation needs the dose of
  * many scenarios and beams every iteration, Sec. I, II-A).  Each y is bitwise
- * what dose_spmv gives per vector under the same partition.  Items must not
+ * what dose_spmv gives per vector (rows are summed in the same order).  Items must not
  * share outputs. */
 dose_status dose_spmv_batched(const dose_batch_item* items, int32_t n_items, void* hip_stream);
 
@@ -204,13 +205,12 @@ dose_status dose_norm2(int64_t n, const float* g, double* out, void* hip_stream)
 dose_status dose_probe_stream_read(const void* buf, uint64_t bytes, float* sink, void* hip_stream);
 dose_status dose_probe_copy(const void* src, void* dst, uint64_t bytes, void* hip_stream);
 
-/* Host-only view of the row-block partition that dose_matrix_create would
- * build for a row_ptr (the summation order follows from it).  Writes up to
- * `cap` blocks (5 int64 each: nnz_begin, nnz_count, row_begin, row_count,
- * lanes_per_row; nnz_count of a chunk of a split row is its own length and
- * row_count is then -1) and returns the count in *n_blocks. */
-dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t block_nnz,
-                                   int64_t* blocks, int64_t cap, int64_t* n_blocks);
+/* Host-only view of the row-group partition for a row_ptr and group size.
+ * Writes up to `cap` groups, 5 int64 each, r0 <= r1 <= r2 <= r3 <= r4: the
+ * group holds rows [r0, r4) and its wave w computes rows [r_w, r_(w+1)).
+ * Returns the number of groups in *n_groups. */
+dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t group_nnz,
+                                   int64_t* groups, int64_t cap, int64_t* n_groups);
 
 const char* dose_status_string(dose_status s);
 const char* dose_last_error(void);

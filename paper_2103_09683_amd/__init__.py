@@ -62,16 +62,17 @@ def csr_validate(row_ptr, cols, vals, n_cols, value_format: str = "fp16") -> int
                                              _lib.IDX_I32))
 
 
-def partition_preview(row_ptr, block_nnz: int) -> np.ndarray:
-    """Row blocks [nnz_begin, nnz_count, row_begin, row_count (-1: split chunk),
-    lanes_per_row] the library builds for ``row_ptr`` (host only)."""
+def partition_preview(row_ptr, group_nnz: int) -> np.ndarray:
+    """Row groups the library builds for ``row_ptr`` (host only): one row per
+    group, [r0, r1, r2, r3, r4], the group holding rows [r0, r4) and its wave
+    w computing rows [r_w, r_(w+1))."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     lib = _lib.load()
     n = ctypes.c_int64(0)
-    _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, block_nnz, None, 0,
+    _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, group_nnz, None, 0,
                                           ctypes.byref(n)))
     out = np.zeros((max(n.value, 1), 5), np.int64)
-    _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, block_nnz,
+    _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, group_nnz,
                                           out.ctypes.data, n.value, ctypes.byref(n)))
     return out[:n.value]
 
@@ -130,9 +131,11 @@ class DoseMatrix:
         _lib.check(_lib.load().dose_matrix_info(self.handle, ctypes.byref(inf)))
         return {name: getattr(inf, name) for name, _ in _lib.MatrixInfo._fields_}
 
-    def set_partition(self, block_nnz: int, block_nnz_t: int | None = None) -> None:
-        bt = block_nnz_t if block_nnz_t is not None else (self.info()["block_nnz_t"] or block_nnz)
-        _lib.check(_lib.load().dose_matrix_set_partition(self.handle, block_nnz, bt))
+    def set_partition(self, group_nnz: int, group_nnz_t: int | None = None) -> None:
+        """Row groups of about ``group_nnz`` entries (speed only: results are
+        bitwise the same under any partition)."""
+        gt = group_nnz_t if group_nnz_t is not None else (self.info()["group_nnz_t"] or group_nnz)
+        _lib.check(_lib.load().dose_matrix_set_partition(self.handle, group_nnz, gt))
 
     def decode(self, row_begin: int = 0, row_end: int | None = None, part: str = "A"):
         """Host CSR of rows [row_begin, row_end) decoded to FP32 on the device."""

@@ -37,10 +37,10 @@ class CsrHost(ctypes.Structure):
 class MatrixInfo(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("value_format", ctypes.c_int32), ("index_format", ctypes.c_int32),
-                ("has_transpose", ctypes.c_int32), ("block_nnz", ctypes.c_int32),
-                ("n_blocks", ctypes.c_int64), ("n_split_rows", ctypes.c_int64),
-                ("block_nnz_t", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("n_blocks_t", ctypes.c_int64), ("n_split_rows_t", ctypes.c_int64),
+                ("has_transpose", ctypes.c_int32), ("group_nnz", ctypes.c_int32),
+                ("n_groups", ctypes.c_int64), ("n_groups_windowed", ctypes.c_int64),
+                ("group_nnz_t", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n_groups_t", ctypes.c_int64), ("n_groups_windowed_t", ctypes.c_int64),
                 ("device_bytes", ctypes.c_uint64), ("spmv_bytes", ctypes.c_uint64),
                 ("adjoint_bytes", ctypes.c_uint64)]
 

@@ -223,73 +223,40 @@ void validate_csr(const dose_csr_host* c, int vf, int xf) {
 }
 
 // -------------------------------------------------------------- partition
-// Lanes reducing one row of a block: a power of two near a quarter of the
-// block's mean non-empty row length, 4 .. 64.
-int lanes_log2(int64_t nnz, int64_t nonempty) {
-  const int64_t m = nonempty > 0 ? nnz / nonempty : 0;
-  int lg = 2;
-  while (lg < 6 && (int64_t{1} << (lg + 1)) * 4 <= m) ++lg;
-  return lg;
-}
-
-struct Partition {
-  std::vector<BlockDesc> blocks;
-  std::vector<SplitRow> splits;
-  int64_t n_partials = 0;
-};
-
-Partition build_partition(const int64_t* rp, int64_t n_rows, int block_nnz) {
-  Partition P;
-  P.blocks.reserve(static_cast<size_t>(rp[n_rows] / block_nnz + n_rows / kMaxBlockRows + 16));
+// Row groups: runs of whole rows holding about group_nnz entries (a longer
+// row forms a group of its own), at most kMaxGroupRows rows, each split into
+// kGroupWaves contiguous shares of nearly equal cost (entries plus 16 per
+// row: an empty row still costs an offset load and a store).  The partition
+// only decides which wave computes which row; it never changes the order in
+// which a row is summed.
+std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int group_nnz) {
+  std::vector<GroupDesc> G;
+  G.reserve(static_cast<size_t>(rp[n_rows] / group_nnz + n_rows / kMaxGroupRows + 16));
+  const int64_t kRowCost = 16;
   int64_t r = 0;
   while (r < n_rows) {
-    const int64_t len = rp[r + 1] - rp[r];
-    if (len > block_nnz) {
-      const int64_t nch = (len + block_nnz - 1) / block_nnz;
-      const int64_t step = (len + nch - 1) / nch;
-      const uint32_t first = static_cast<uint32_t>(P.n_partials);
-      for (int64_t c = 0; c < nch; ++c) {
-        BlockDesc b{};
-        b.nnz_begin = static_cast<uint64_t>(rp[r] + c * step);
-        b.nnz_count = static_cast<uint32_t>(std::min(step, len - c * step));
-        b.row_begin = static_cast<uint32_t>(r);
-        b.row_count = 0;
-        b.meta = 6;
-        b.partial = first + static_cast<uint32_t>(c);
-        P.blocks.push_back(b);
-      }
-      P.splits.push_back(SplitRow{static_cast<uint32_t>(r), first, static_cast<uint32_t>(nch), 0});
-      P.n_partials += nch;
-      ++r;
-      continue;
-    }
     const int64_t start = r;
-    int64_t nnz = 0, nonempty = 0;
-    while (r < n_rows && r - start < kMaxBlockRows) {
+    int64_t nnz = 0;
+    while (r < n_rows && r - start < kMaxGroupRows) {
       const int64_t l = rp[r + 1] - rp[r];
-      if (l > block_nnz || nnz + l > block_nnz) break;
+      if (r > start && nnz + l > group_nnz) break;
       nnz += l;
-      nonempty += l > 0;
       ++r;
     }
-    BlockDesc b{};
-    b.nnz_begin = static_cast<uint64_t>(rp[start]);
-    b.nnz_count = static_cast<uint32_t>(nnz);
-    b.row_begin = static_cast<uint32_t>(start);
-    b.row_count = static_cast<uint32_t>(r - start);
-    b.meta = static_cast<uint32_t>(lanes_log2(nnz, nonempty));
-    P.blocks.push_back(b);
+    GroupDesc g{};
+    g.nnz_base = static_cast<uint64_t>(rp[start]);
+    const int64_t total = nnz + kRowCost * (r - start);
+    int64_t q = start;
+    g.row[0] = static_cast<uint32_t>(start);
+    for (int w = 1; w < kGroupWaves; ++w) {
+      const int64_t target = total * w / kGroupWaves;
+      while (q < r && (rp[q] - rp[start]) + kRowCost * (q - start) < target) ++q;
+      g.row[w] = static_cast<uint32_t>(q);
+    }
+    g.row[kGroupWaves] = static_cast<uint32_t>(r);
+    G.push_back(g);
   }
-  return P;
-}
-
-int default_block_nnz(int64_t n_rows, int64_t nnz) {
-  // Keep at least ~16 blocks per compute unit when the matrix allows it.
-  const int64_t target = nnz / (256 * 16);
-  int bn = 4096;
-  while (bn > 1024 && bn > target) bn >>= 1;
-  (void)n_rows;
-  return bn;
+  return G;
 }
 
 // ------------------------------------------------------------- operands
@@ -297,29 +264,43 @@ struct Operand {
   int64_t n_rows = 0, n_cols = 0, nnz = 0;
   std::vector<int64_t> h_row_ptr;
   DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
-  DevBuf blocks, splits;
-  int32_t block_nnz = 0;
-  int64_t n_blocks = 0, n_splits = 0, n_partials = 0;
+  DevBuf groups;
+  int32_t group_nnz = 0;
+  int64_t n_groups = 0, n_windowed = 0;
+  int32_t win_floats[3] = {0, 0, 0};  // LDS window size for 1, 2 and 4 vectors
 
-  uint64_t bytes() const {
-    return val.bytes() + col.bytes() + row_ptr.bytes() + blocks.bytes() + splits.bytes();
-  }
+  uint64_t bytes() const { return val.bytes() + col.bytes() + row_ptr.bytes() + groups.bytes(); }
 };
 
-void upload_partition(Operand& op, int block_nnz) {
-  Partition P = build_partition(op.h_row_ptr.data(), op.n_rows, block_nnz);
-  DevBuf blocks(std::max<size_t>(1, P.blocks.size()) * sizeof(BlockDesc));
-  DevBuf splits(std::max<size_t>(1, P.splits.size()) * sizeof(SplitRow));
-  if (!P.blocks.empty())
-    HIP_CHECK(hipMemcpy(blocks.get(), P.blocks.data(), P.blocks.size() * sizeof(BlockDesc), hipMemcpyHostToDevice));
-  if (!P.splits.empty())
-    HIP_CHECK(hipMemcpy(splits.get(), P.splits.data(), P.splits.size() * sizeof(SplitRow), hipMemcpyHostToDevice));
-  op.blocks = std::move(blocks);
-  op.splits = std::move(splits);
-  op.block_nnz = block_nnz;
-  op.n_blocks = static_cast<int64_t>(P.blocks.size());
-  op.n_splits = static_cast<int64_t>(P.splits.size());
-  op.n_partials = P.n_partials;
+int rhs_slot(int n_rhs) { return n_rhs == 1 ? 0 : n_rhs == 2 ? 1 : 2; }
+
+void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
+  std::vector<GroupDesc> G = build_partition(op.h_row_ptr.data(), op.n_rows, group_nnz);
+  DevBuf groups(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
+  if (!G.empty()) {
+    HIP_CHECK(hipMemcpyAsync(groups.get(), G.data(), G.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_group_windows(groups.get<GroupDesc>(), static_cast<int64_t>(G.size()), op.col.get<int32_t>(),
+                                   op.row_ptr.get<uint32_t>(), s));
+    HIP_CHECK(hipMemcpyAsync(G.data(), groups.get(), G.size() * sizeof(GroupDesc), hipMemcpyDeviceToHost, s));
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  // LDS per workgroup: the largest window that fits kWinFloatsMax; groups
+  // with larger windows read x from global memory
+  int64_t windowed = 0;
+  int64_t wf[3] = {0, 0, 0};
+  const int rhs[3] = {1, 2, 4};
+  for (const GroupDesc& g : G) {
+    windowed += g.clen > 0 && window_floats(g.clen, 1) <= kWinFloatsMax;
+    for (int i = 0; i < 3; ++i) {
+      const int64_t f = window_floats(g.clen, rhs[i]);
+      if (f <= kWinFloatsMax) wf[i] = std::max(wf[i], f);
+    }
+  }
+  op.groups = std::move(groups);
+  op.group_nnz = group_nnz;
+  op.n_groups = static_cast<int64_t>(G.size());
+  op.n_windowed = windowed;
+  for (int i = 0; i < 3; ++i) op.win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);
 }
 
 void upload_row_ptr32(Operand& op, hipStream_t s) {
@@ -347,61 +328,53 @@ namespace {
 int scale_mode_A(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleRow : kScaleNone; }
 int scale_mode_AT(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleCol : kScaleNone; }
 
-SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, const float* x, float* y, float* partials) {
+SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const float* x, float* y) {
   SpmvArgs a{};
-  a.blocks = op.blocks.get<BlockDesc>();
+  a.win_floats = op.win_floats[rhs_slot(n_rhs)];
+  a.groups = op.groups.get<GroupDesc>();
   a.val = op.val.get();
   a.col = op.col.get<int32_t>();
   a.row_ptr = op.row_ptr.get<uint32_t>();
   a.scale = sm == kScaleNone ? nullptr : m->row_scale.get<float>();
   a.x = x;
   a.y = y;
-  a.partials = partials;
-  a.splits = op.splits.get<SplitRow>();
-  a.n_blocks = op.n_blocks;
-  a.n_splits = op.n_splits;
+  a.n_groups = op.n_groups;
   return a;
 }
 
 // Encode A's FP32 source values into its code stream, a row range at a time.
 void encode_values(dose_matrix_s* m, const dose_csr_host* c, hipStream_t s) {
   Operand& A = m->A;
-  if (A.nnz == 0) return;
+  if (A.nnz == 0 && m->vf != kFp8) return;
   int64_t max_row = 0;
   for (int64_t i = 0; i < A.n_rows; ++i) max_row = std::max(max_row, A.h_row_ptr[i + 1] - A.h_row_ptr[i]);
-  const int64_t stage_n = std::max<int64_t>(std::min<int64_t>(A.nnz, int64_t{1} << 26), max_row);
+  const int64_t stage_n = std::max<int64_t>(std::max<int64_t>(std::min<int64_t>(A.nnz, int64_t{1} << 26), max_row), 1);
   DevBuf stage(static_cast<size_t>(stage_n) * sizeof(float));
   const int vb = value_bytes(m->vf);
   int64_t r0 = 0;
   while (r0 < A.n_rows) {
-    int64_t r1 = r0 + 1;
-    // widen the chunk while it fits the staging buffer
+    // the longest run of rows from r0 that fits the staging buffer
     int64_t lo = r0 + 1, hi = A.n_rows;
     while (lo < hi) {
       const int64_t mid = lo + (hi - lo + 1) / 2;
       if (A.h_row_ptr[mid] - A.h_row_ptr[r0] <= stage_n) lo = mid; else hi = mid - 1;
     }
-    r1 = lo;
+    const int64_t r1 = lo;
     const int64_t k0 = A.h_row_ptr[r0], k1 = A.h_row_ptr[r1];
-    if (k1 > k0) {
+    if (k1 > k0)
       HIP_CHECK(hipMemcpyAsync(stage.get(), c->values + k0, static_cast<size_t>(k1 - k0) * sizeof(float),
                                hipMemcpyHostToDevice, s));
-      HIP_CHECK(launch_encode_rows(m->vf, A.row_ptr.get<uint32_t>() + r0, static_cast<uint32_t>(k0), r1 - r0,
-                                   stage.get<float>(), static_cast<uint8_t*>(A.val.get()) + k0 * vb,
-                                   m->vf == kFp8 ? m->row_scale.get<float>() + r0 : nullptr, s));
-      HIP_CHECK(hipStreamSynchronize(s));
-    } else if (m->vf == kFp8) {
-      HIP_CHECK(launch_encode_rows(m->vf, A.row_ptr.get<uint32_t>() + r0, static_cast<uint32_t>(k0), r1 - r0,
-                                   stage.get<float>(), A.val.get(), m->row_scale.get<float>() + r0, s));
-    }
+    HIP_CHECK(launch_encode_rows(m->vf, A.row_ptr.get<uint32_t>() + r0, static_cast<uint32_t>(k0), r1 - r0,
+                                 stage.get<float>(), static_cast<uint8_t*>(A.val.get()) + k0 * vb,
+                                 m->vf == kFp8 ? m->row_scale.get<float>() + r0 : nullptr, s));
+    HIP_CHECK(hipStreamSynchronize(s));  // the staging buffer is reused
     r0 = r1;
   }
-  HIP_CHECK(hipStreamSynchronize(s));
 }
 
 // A^T on the device: stable radix sort of (column, entry) pairs, so every row
 // of A^T lists its entries in ascending row of A.
-void build_transpose(dose_matrix_s* m, int block_nnz_t, hipStream_t s) {
+void build_transpose(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
   const Operand& A = m->A;
   Operand& T = m->AT;
   if (A.nnz > INT32_MAX) fail(DOSE_ERR_UNSUPPORTED, "transpose needs nnz < 2^31");
@@ -439,12 +412,20 @@ void build_transpose(dose_matrix_s* m, int block_nnz_t, hipStream_t s) {
   HIP_CHECK(hipMemcpyAsync(T.h_row_ptr.data(), rp64.get(), rp64.bytes(), hipMemcpyDeviceToHost, s));
   HIP_CHECK(hipStreamSynchronize(s));
   upload_row_ptr32(T, s);
-  upload_partition(T, block_nnz_t);
+  upload_partition(T, group_nnz_t, s);
 }
 
-void check_block_nnz(int32_t bn) {
-  if (!is_pow2(bn) || bn < kMinBlockNnz || bn > kMaxBlockNnz)
-    fail(DOSE_ERR_INVALID_ARGUMENT, "block_nnz must be a power of two in [256, 8192]");
+void check_group_nnz(int32_t g) {
+  if (!is_pow2(g) || g < kMinGroupNnz || g > kMaxGroupNnz)
+    fail(DOSE_ERR_INVALID_ARGUMENT, "group_nnz must be a power of two in [1024, 2^20]");
+}
+
+// Default row-group size: large enough that staging a group's x window is a
+// small fraction of its stream, small enough for many groups per compute unit.
+int default_group_nnz(int64_t nnz) {
+  int g = 32768;
+  while (g > 4096 && nnz / g < 256 * 8) g >>= 1;
+  return g;
 }
 
 bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
@@ -452,16 +433,9 @@ bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
   return na > 0 && nb > 0 && pa < pb + nb && pb < pa + na;
 }
 
-// Products whose operand has split rows need one partial per chunk; they are
-// allocated per call in stream order so that concurrent calls never share.
-void run_product(const dose_matrix_s* m, const Operand& op, int sm, const float* x, float* y, hipStream_t s) {
-  float* partials = nullptr;
-  if (op.n_splits > 0) HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partials), op.n_partials * sizeof(float), s));
-  SpmvArgs a = make_args(m, op, sm, x, y, partials);
-  hipError_t e = launch_spmv(m->vf, sm, 1, op.block_nnz, a, s);
-  if (e == hipSuccess) e = launch_combine(sm, 1, a, s);
-  if (partials) (void)hipFreeAsync(partials, s);
-  HIP_CHECK(e);
+void run_product(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const float* x, float* y,
+                 hipStream_t s) {
+  HIP_CHECK(launch_spmv(m->vf, sm, n_rhs, make_args(m, op, sm, n_rhs, x, y), s));
 }
 
 // ------------------------------------------------------------ tuning cache
@@ -469,7 +443,7 @@ std::mutex g_tune_mu;
 
 std::string tune_key(const dose_matrix_s* m, const Operand& op, int n_rhs) {
   std::ostringstream k;
-  k << "v1:" << op.n_rows << "x" << op.n_cols << ":" << op.nnz << ":f" << m->vf << ":r" << n_rhs;
+  k << "v2:" << op.n_rows << "x" << op.n_cols << ":" << op.nnz << ":f" << m->vf << ":r" << n_rhs;
   return k.str();
 }
 
@@ -498,10 +472,10 @@ void tune_store(const std::string& key, int v) {
 // ------------------------------------------------------------ batch plans
 struct dose_batch_plan_s {
   int device = 0;
-  int vf = 0, sm = 0, n_rhs = 0, cap_nnz = 0;
-  int64_t n_work = 0, n_split = 0;
+  int vf = 0, sm = 0, n_rhs = 0, lds_floats = 0;
+  int64_t n_work = 0;
   int grid = 0;
-  DevBuf args, work, split_items, split_idx, partials;
+  DevBuf args, work;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~dose_batch_plan_s() {
@@ -525,33 +499,31 @@ void check_items(const dose_batch_item* items, int32_t n_items) {
     if (it.A->device != items[0].A->device) fail(DOSE_ERR_INVALID_ARGUMENT, "items on different devices");
     if (overlaps(it.x, it.A->A.n_cols * it.n_rhs * 4, it.y, it.A->A.n_rows * it.n_rhs * 4))
       fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
-    if (it.n_rhs == 4 && it.A->A.block_nnz > 4096)
-      fail(DOSE_ERR_UNSUPPORTED, "n_rhs 4 needs block_nnz <= 4096");
     if ((reinterpret_cast<uintptr_t>(it.x) | reinterpret_cast<uintptr_t>(it.y)) % (4 * it.n_rhs) != 0)
       fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be aligned to n_rhs floats");
+    for (int32_t j = 0; j < i; ++j)
+      if (overlaps(items[j].y, items[j].A->A.n_rows * items[j].n_rhs * 4, it.y, it.A->A.n_rows * it.n_rhs * 4))
+        fail(DOSE_ERR_INVALID_ARGUMENT, "items share outputs");
   }
 }
 
-int batched_grid(int n_work) {
+int batched_grid(int64_t n_work) {
   int dev = 0, cus = 0;
   HIP_CHECK(hipGetDevice(&dev));
   HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  return std::max(1, std::min(n_work, cus * 8));
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_work, int64_t{cus} * 4)));
 }
 
-// Time the plain product of one operand under a block size (median of runs).
+// Median time of the plain product of one operand under its current partition.
 double time_partition(dose_matrix_s* m, Operand& op, int sm, int n_rhs, const float* x, float* y, hipStream_t s) {
-  float* partials = nullptr;
-  if (op.n_splits > 0) HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&partials), op.n_partials * n_rhs * sizeof(float), s));
-  SpmvArgs a = make_args(m, op, sm, x, y, partials);
+  const SpmvArgs a = make_args(m, op, sm, n_rhs, x, y);
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
   std::vector<float> ts;
   for (int rep = 0; rep < 7; ++rep) {
     HIP_CHECK(hipEventRecord(e0, s));
-    HIP_CHECK(launch_spmv(m->vf, sm, n_rhs, op.block_nnz, a, s));
-    HIP_CHECK(launch_combine(sm, n_rhs, a, s));
+    HIP_CHECK(launch_spmv(m->vf, sm, n_rhs, a, s));
     HIP_CHECK(hipEventRecord(e1, s));
     HIP_CHECK(hipEventSynchronize(e1));
     float ms = 0;
@@ -560,27 +532,26 @@ double time_partition(dose_matrix_s* m, Operand& op, int sm, int n_rhs, const fl
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (partials) HIP_CHECK(hipFreeAsync(partials, s));
-  HIP_CHECK(hipStreamSynchronize(s));
   std::sort(ts.begin(), ts.end());
   return ts[ts.size() / 2];
 }
 
+// Pick the row-group size by timing candidates (the result does not depend on
+// it: every row is summed in the same order under any partition).
 void autotune_matrix(dose_matrix_s* m, int n_rhs, const float* x, float* y, hipStream_t s) {
   Operand& op = m->A;
   const std::string key = tune_key(m, op, n_rhs);
   int best = tune_lookup(key);
   if (best == 0) {
     double best_t = 1e30;
-    const int hi = n_rhs == 4 ? 4096 : 8192;
-    for (int bn = 1024; bn <= hi; bn *= 2) {
-      upload_partition(op, bn);
+    for (int g = 8192; g <= 65536; g *= 2) {
+      upload_partition(op, g, s);
       const double t = time_partition(m, op, scale_mode_A(m), n_rhs, x, y, s);
-      if (t < best_t) best_t = t, best = bn;
+      if (t < best_t) best_t = t, best = g;
     }
     tune_store(key, best);
   }
-  if (op.block_nnz != best) upload_partition(op, best);
+  if (op.group_nnz != best) upload_partition(op, best, s);
 }
 
 dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uint32_t flags, hipStream_t s) {
@@ -598,45 +569,25 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
   }
   std::vector<SpmvArgs> args(n_items);
   std::vector<WorkItem> work;
-  std::vector<uint32_t> sp_item, sp_idx;
-  int64_t partial_total = 0;
-  std::vector<int64_t> partial_off(n_items);
-  for (int32_t i = 0; i < n_items; ++i) {
-    partial_off[i] = partial_total;
-    partial_total += items[i].A->A.n_partials * plan->n_rhs;
-    plan->cap_nnz = std::max(plan->cap_nnz, items[i].A->A.block_nnz);
-  }
-  plan->partials = DevBuf(static_cast<size_t>(std::max<int64_t>(partial_total, 1)) * sizeof(float));
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_matrix_s* m = items[i].A;
-    args[i] = make_args(m, m->A, plan->sm, items[i].x, items[i].y, plan->partials.get<float>() + partial_off[i]);
-    for (int64_t b = 0; b < m->A.n_blocks; ++b) work.push_back(WorkItem{static_cast<uint32_t>(i), static_cast<uint32_t>(b)});
-    for (int64_t k = 0; k < m->A.n_splits; ++k) {
-      sp_item.push_back(static_cast<uint32_t>(i));
-      sp_idx.push_back(static_cast<uint32_t>(k));
-    }
+    args[i] = make_args(m, m->A, plan->sm, plan->n_rhs, items[i].x, items[i].y);
+    plan->lds_floats = std::max(plan->lds_floats, args[i].win_floats);
+    for (int64_t g = 0; g < m->A.n_groups; ++g)
+      work.push_back(WorkItem{static_cast<uint32_t>(i), static_cast<uint32_t>(g)});
   }
   plan->n_work = static_cast<int64_t>(work.size());
-  plan->n_split = static_cast<int64_t>(sp_item.size());
   plan->args = DevBuf(args.size() * sizeof(SpmvArgs));
   plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(WorkItem));
-  plan->split_items = DevBuf(std::max<size_t>(1, sp_item.size()) * 4);
-  plan->split_idx = DevBuf(std::max<size_t>(1, sp_idx.size()) * 4);
   HIP_CHECK(hipMemcpy(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice));
   if (!work.empty()) HIP_CHECK(hipMemcpy(plan->work.get(), work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-  if (!sp_item.empty()) {
-    HIP_CHECK(hipMemcpy(plan->split_items.get(), sp_item.data(), sp_item.size() * 4, hipMemcpyHostToDevice));
-    HIP_CHECK(hipMemcpy(plan->split_idx.get(), sp_idx.data(), sp_idx.size() * 4, hipMemcpyHostToDevice));
-  }
-  plan->grid = batched_grid(static_cast<int>(std::min<int64_t>(plan->n_work, INT32_MAX)));
+  plan->grid = batched_grid(plan->n_work);
   return plan.release();
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
-  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->cap_nnz, p->args.get<SpmvArgs>(), p->work.get<WorkItem>(),
-                                p->n_work, p->grid, s));
-  HIP_CHECK(launch_combine_batched(p->sm, p->n_rhs, p->args.get<SpmvArgs>(), p->split_items.get<uint32_t>(),
-                                   p->split_idx.get<uint32_t>(), p->n_split, s));
+  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->args.get<SpmvArgs>(), p->work.get<WorkItem>(), p->n_work,
+                                p->grid, p->lds_floats, s));
 }
 
 int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4095) / 4096))); }
@@ -666,20 +617,17 @@ dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf, do
   return guarded([&] { validate_csr(csr, vf, xf); });
 }
 
-dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t block_nnz, int64_t* blocks,
-                                   int64_t cap, int64_t* n_blocks) {
+dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t group_nnz, int64_t* groups,
+                                   int64_t cap, int64_t* n_groups) {
   return guarded([&] {
-    if (!row_ptr || !n_blocks || n_rows < 0 || (cap > 0 && !blocks)) fail(DOSE_ERR_INVALID_ARGUMENT, "bad argument");
-    check_block_nnz(block_nnz);
-    Partition P = build_partition(row_ptr, n_rows, block_nnz);
-    *n_blocks = static_cast<int64_t>(P.blocks.size());
-    for (int64_t i = 0; i < std::min<int64_t>(cap, *n_blocks); ++i) {
-      const BlockDesc& b = P.blocks[i];
-      blocks[5 * i + 0] = static_cast<int64_t>(b.nnz_begin);
-      blocks[5 * i + 1] = b.nnz_count;
-      blocks[5 * i + 2] = b.row_begin;
-      blocks[5 * i + 3] = b.row_count == 0 ? -1 : static_cast<int64_t>(b.row_count);
-      blocks[5 * i + 4] = int64_t{1} << (b.meta & 7u);
+    if (!row_ptr || !n_groups || n_rows < 0 || (cap > 0 && !groups)) fail(DOSE_ERR_INVALID_ARGUMENT, "bad argument");
+    check_group_nnz(group_nnz);
+    std::vector<GroupDesc> G = build_partition(row_ptr, n_rows, group_nnz);
+    *n_groups = static_cast<int64_t>(G.size());
+    for (int64_t i = 0; i < std::min<int64_t>(cap, *n_groups); ++i) {
+      const GroupDesc& g = G[i];
+      int64_t* o = groups + i * (kGroupWaves + 1);
+      for (int w = 0; w <= kGroupWaves; ++w) o[w] = g.row[w];
     }
   });
 }
@@ -711,9 +659,9 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, d
       HIP_CHECK(hipMemcpyAsync(A.col.get(), csr->col_idx, static_cast<size_t>(A.nnz) * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
     encode_values(m.get(), csr, s);
-    upload_partition(A, default_block_nnz(A.n_rows, A.nnz));
+    upload_partition(A, default_group_nnz(A.nnz), s);
     if (flags & DOSE_CREATE_TRANSPOSE) {
-      build_transpose(m.get(), default_block_nnz(A.n_cols, A.nnz), s);
+      build_transpose(m.get(), default_group_nnz(A.nnz), s);
       m->has_t = true;
     }
     HIP_CHECK(hipStreamSynchronize(s));
@@ -721,15 +669,15 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, d
   });
 }
 
-dose_status dose_matrix_set_partition(dose_matrix m, int32_t block_nnz, int32_t block_nnz_t) {
+dose_status dose_matrix_set_partition(dose_matrix m, int32_t group_nnz, int32_t group_nnz_t) {
   return guarded([&] {
     if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
-    check_block_nnz(block_nnz);
-    if (m->has_t) check_block_nnz(block_nnz_t);
+    check_group_nnz(group_nnz);
+    if (m->has_t) check_group_nnz(group_nnz_t);
     DeviceGuard g(m->device);
     HIP_CHECK(hipDeviceSynchronize());
-    upload_partition(m->A, block_nnz);
-    if (m->has_t) upload_partition(m->AT, block_nnz_t);
+    upload_partition(m->A, group_nnz, nullptr);
+    if (m->has_t) upload_partition(m->AT, group_nnz_t, nullptr);
   });
 }
 
@@ -770,12 +718,12 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     info->value_format = m->vf;
     info->index_format = m->xf;
     info->has_transpose = m->has_t ? 1 : 0;
-    info->block_nnz = A.block_nnz;
-    info->n_blocks = A.n_blocks;
-    info->n_split_rows = A.n_splits;
-    info->block_nnz_t = m->has_t ? m->AT.block_nnz : 0;
-    info->n_blocks_t = m->has_t ? m->AT.n_blocks : 0;
-    info->n_split_rows_t = m->has_t ? m->AT.n_splits : 0;
+    info->group_nnz = A.group_nnz;
+    info->n_groups = A.n_groups;
+    info->n_groups_windowed = A.n_windowed;
+    info->group_nnz_t = m->has_t ? m->AT.group_nnz : 0;
+    info->n_groups_t = m->has_t ? m->AT.n_groups : 0;
+    info->n_groups_windowed_t = m->has_t ? m->AT.n_windowed : 0;
     info->device_bytes = A.bytes() + m->row_scale.bytes() + (m->has_t ? m->AT.bytes() : 0);
     const uint64_t per_nnz = static_cast<uint64_t>(value_bytes(m->vf)) + 4;
     const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
@@ -788,11 +736,9 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
 dose_status dose_matrix_destroy(dose_matrix m) {
   return guarded([&] {
     if (!m) return;
-    {
-      DeviceGuard g(m->device);
-      (void)hipDeviceSynchronize();
-      delete m;
-    }
+    DeviceGuard g(m->device);
+    (void)hipDeviceSynchronize();
+    delete m;
   });
 }
 
@@ -802,7 +748,7 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
     if ((m->A.n_cols > 0 && !x) || (m->A.n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
     if (overlaps(x, m->A.n_cols * 4, y, m->A.n_rows * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
     DeviceGuard g(m->device);
-    run_product(m, m->A, scale_mode_A(m), x, y, as_stream(hip_stream));
+    run_product(m, m->A, scale_mode_A(m), 1, x, y, as_stream(hip_stream));
   });
 }
 
@@ -813,7 +759,7 @@ dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* gout, void* 
     if ((m->A.n_rows > 0 && !v) || (m->A.n_cols > 0 && !gout)) fail(DOSE_ERR_INVALID_ARGUMENT, "null v or g");
     if (overlaps(v, m->A.n_rows * 4, gout, m->A.n_cols * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "v and g overlap");
     DeviceGuard g(m->device);
-    run_product(m, m->AT, scale_mode_AT(m), v, gout, as_stream(hip_stream));
+    run_product(m, m->AT, scale_mode_AT(m), 1, v, gout, as_stream(hip_stream));
   });
 }
 

@@ -7,40 +7,30 @@
 
 namespace dose {
 
-// Threads of one SpMV workgroup (four wave64 wavefronts).
-constexpr int kThreads = 256;
-// Entries one lane loads per step: 8 values and 8 column indices.
+// Entries one lane loads per step of a row: 8 codes and 8 column indices.
 constexpr int kChunk = 8;
-// Most rows one row block may cover (bounds the LDS copy of its row offsets).
-constexpr int kMaxBlockRows = 1024;
-// Block sizes the kernels are instantiated for (entries of A per row block).
-constexpr int kMinBlockNnz = 256;
-constexpr int kMaxBlockNnz = 8192;
-// Padding of the value and index streams: every 8-entry load issued for a
-// block stays inside the allocation.
+// Waves of one SpMV workgroup, and its threads.
+constexpr int kGroupWaves = 4;
+constexpr int kGroupThreads = kGroupWaves * 64;
+// Row-group sizes (entries); a power of two in this range.
+constexpr int kMinGroupNnz = 1024;
+constexpr int kMaxGroupNnz = 1 << 20;
+// Most rows one group may hold (bounds the time a wave spends on empty rows).
+constexpr int64_t kMaxGroupRows = 16384;
+// Padding of the value and index streams: every 8-entry load of a row stays
+// inside the allocation.
 constexpr int64_t kStreamPad = 64;
 
-// One unit of work of the SpMV kernels: a run of whole rows holding at most
-// block_nnz entries, or one chunk of a row longer than block_nnz.
-struct alignas(32) BlockDesc {
-  uint64_t nnz_begin;  // first entry of the block
-  uint32_t nnz_count;  // entries in the block
-  uint32_t row_begin;  // first row
-  uint32_t row_count;  // rows covered; 0 marks a chunk of a split row
-  uint32_t meta;       // bits 0..2: log2 of the lanes that reduce one row
-  uint32_t partial;    // split chunks: slot of the chunk's partial sum
-  uint32_t pad;
+// One workgroup's work: a run of whole rows, split into one contiguous share
+// per wave, and the window of columns its entries touch.
+struct alignas(64) GroupDesc {
+  uint64_t nnz_base;              // first entry of the group
+  uint32_t row[kGroupWaves + 1];  // wave w takes rows [row[w], row[w+1])
+  uint32_t cmin;                  // smallest column of the group's entries
+  uint32_t clen;                  // largest minus smallest column plus 1 (0: no entries)
+  uint32_t pad[7];
 };
-static_assert(sizeof(BlockDesc) == 32, "BlockDesc layout");
-
-// A row longer than block_nnz: its chunks' partial sums sit in slots
-// [first_slot, first_slot + n_slots) and are added in slot order.
-struct alignas(16) SplitRow {
-  uint32_t row;
-  uint32_t first_slot;
-  uint32_t n_slots;
-  uint32_t pad;
-};
+static_assert(sizeof(GroupDesc) == 64, "GroupDesc layout");
 
 // Value formats (numbers as in dose.h).
 enum ValueFormat : int { kFp16 = 1, kBf16 = 2, kFp8 = 3 };
@@ -54,35 +44,40 @@ enum ScaleMode : int {
 
 // Everything one SpMV kernel needs for one operand and one product.
 struct SpmvArgs {
-  const BlockDesc* blocks;
-  const void* val;         // codes, padded by kStreamPad
-  const int32_t* col;      // padded by kStreamPad
-  const uint32_t* row_ptr; // n_rows+1 offsets modulo 2^32
-  const float* scale;      // row or column scale (E4M3), else null
-  const float* x;          // [n_cols][n_rhs]
-  float* y;                // [n_rows][n_rhs]
-  float* partials;         // [n_partials][n_rhs]
-  const SplitRow* splits;
-  int64_t n_blocks;
-  int64_t n_splits;
+  const GroupDesc* groups;
+  const void* val;          // codes, padded by kStreamPad
+  const int32_t* col;       // padded by kStreamPad
+  const uint32_t* row_ptr;  // n_rows+1 offsets modulo 2^32
+  const float* scale;       // row or column scale (E4M3), else null
+  const float* x;           // [n_cols][n_rhs]
+  float* y;                 // [n_rows][n_rhs]
+  int64_t n_groups;
+  int32_t win_floats;       // LDS floats for the x window (dynamic shared memory)
+  int32_t pad;
 };
 
-// Work item of a batched launch: block `block` of item `item`.
+// Largest LDS x window of one workgroup, in floats.
+constexpr int kWinFloatsMax = 8192;
+
+// LDS floats a window of `clen` columns needs for n_rhs vectors: one padding
+// slot every 8 columns keeps a wave's stride-8 reads free of bank conflicts.
+__host__ __device__ constexpr int64_t window_floats(uint32_t clen, int n_rhs) {
+  return clen == 0 ? 0 : (static_cast<int64_t>(clen - 1) + ((clen - 1) >> 3) + 1) * n_rhs;
+}
+
+// Work item of a batched launch: group `group` of item `item`.
 struct alignas(8) WorkItem {
   uint32_t item;
-  uint32_t block;
+  uint32_t group;
 };
 
 // ------------------------------------------------------------ launchers
-hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, int block_nnz, const SpmvArgs& a,
-                       hipStream_t s);
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int block_nnz,
-                               const SpmvArgs* d_args, const WorkItem* d_work, int64_t n_work,
-                               int grid, hipStream_t s);
-hipError_t launch_combine(int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s);
-hipError_t launch_combine_batched(int scale_mode, int n_rhs, const SpmvArgs* d_args,
-                                  const uint32_t* d_split_items, const uint32_t* d_split_idx,
-                                  int64_t n, hipStream_t s);
+hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s);
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args,
+                               const WorkItem* d_work, int64_t n_work, int grid, int lds_floats,
+                               hipStream_t s);
+hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const int32_t* col,
+                                const uint32_t* row_ptr, hipStream_t s);
 
 // Rows [0, n_rows) of row_ptr (offsets modulo 2^32); entry k of a row sits at
 // src[k - base] and its code goes to dst_codes[k - base].

@@ -1,30 +1,51 @@
 // SpMV kernels of libdose for gfx950 (CDNA4, wave64).
 //
 // The product is Listing 1 of the paper: y_i = sum over row i's stored
-// entries of data[k] * x[col[k]].  The paper gives every row one 32-lane warp
-// that strides the row; here a 256-thread workgroup takes a *row block*, a run
-// of whole rows holding at most block_nnz entries (rows longer than that are
-// cut into chunks), and works in two phases:
+// entries of data[k] * x[col[k]], one wavefront reducing each row (the paper
+// uses one 32-lane warp per row, Sec. III).  The gfx950 design:
 //
-//   1. stream: each lane takes 8 consecutive entries of the block, loads their
-//      8 codes with one 16-byte load (8-byte for E4M3) and their 8 column
-//      indices with two 16-byte loads, decodes the codes to FP32, gathers x
-//      and writes the 8 products to LDS.  Loads are contiguous across lanes
-//      whatever the row lengths are, so the block is read once, coalesced.
-//   2. reduce: G lanes (a power of two picked per block from its mean row
-//      length) sum each row's products from LDS, lane j taking every G-th
-//      product from the row's start plus j, then combine in a fixed xor tree.
-//
-// The summation order depends only on the partition (block boundaries and G),
-// never on timing: no atomics anywhere, so equal inputs give equal bits
-// (Sec. II-D).  Split rows leave one partial per chunk; combine() adds them in
-// chunk order.
+//   * A workgroup (four wave64 waves) takes a *row group*: a run of whole rows
+//     holding about group_nnz entries.  Dose rows of neighbouring voxels touch
+//     a narrow range of spots, so the group's columns span a short window of
+//     x; the workgroup copies that window into LDS once and every gather is
+//     an LDS read.  A group whose window does not fit reads x from global
+//     memory instead (8 consecutive columns with two 16-byte loads).
+//   * Each wave owns a contiguous share of the group's rows and walks its
+//     non-empty rows (listed 64 at a time with a ballot; empty rows get +0
+//     with coalesced stores).  For a row, lane l takes the 8-entry chunks
+//     l, l+64, ... counted from the row's first entry rounded down to a
+//     multiple of 8, loading 8 codes with one 16-byte non-temporal load
+//     (8-byte for E4M3) and 8 column indices with two.
+//   * Software pipelining: the loads of the wave's next (row, step) are
+//     issued before the current one is decoded and multiplied, so every wave
+//     keeps a row of loads in flight.
+//   * Summation order: a lane adds its chunk's 8 products pairwise, adds the
+//     chunk sums of its steps in order, and the 64 lane sums meet in a fixed
+//     xor tree.  The order depends only on the row's entries and alignment --
+//     not on the partition, the launch or timing -- and nothing is atomic, so
+//     equal inputs give equal bits (Sec. II-D), and batched products equal
+//     plain ones bit for bit.
 #include "dose_internal.h"
 
 #include <hip/hip_fp16.h>
 
 namespace dose {
 namespace {
+
+constexpr int kWave = 64;
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// Streamed data is read once: non-temporal loads.
+__device__ __forceinline__ uint4 ld_nt4(const void* p) {
+  const u32x4 v = __builtin_nontemporal_load(static_cast<const u32x4*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ uint2 ld_nt2(const void* p) {
+  const u32x2 v = __builtin_nontemporal_load(static_cast<const u32x2*>(p));
+  return make_uint2(v.x, v.y);
+}
 
 // ----------------------------------------------------------------- decoding
 __device__ __forceinline__ float dec_fp16(uint32_t h) {
@@ -42,13 +63,14 @@ __device__ __forceinline__ float dec_e4m3(uint32_t c) {
   return __uint_as_float(__float_as_uint(mag) | sign);
 }
 
+// The 8 codes of one chunk, loaded with one non-temporal load.
 template <int VF>
 struct Codes;
 template <>
 struct Codes<kFp16> {
   uint4 w;
   __device__ __forceinline__ void load(const void* base, uint64_t k0) {
-    w = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + k0);
+    w = ld_nt4(static_cast<const uint16_t*>(base) + k0);
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
@@ -59,7 +81,7 @@ template <>
 struct Codes<kBf16> {
   uint4 w;
   __device__ __forceinline__ void load(const void* base, uint64_t k0) {
-    w = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + k0);
+    w = ld_nt4(static_cast<const uint16_t*>(base) + k0);
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
@@ -70,7 +92,7 @@ template <>
 struct Codes<kFp8> {
   uint2 w;
   __device__ __forceinline__ void load(const void* base, uint64_t k0) {
-    w = *reinterpret_cast<const uint2*>(static_cast<const uint8_t*>(base) + k0);
+    w = ld_nt2(static_cast<const uint8_t*>(base) + k0);
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 4 ? w.x : w.y;
@@ -78,13 +100,24 @@ struct Codes<kFp8> {
   }
 };
 
+// One lane's share of one (row, step): a chunk of 8 codes and 8 columns.
+template <int VF>
+struct Chunk {
+  Codes<VF> codes;
+  uint4 ca, cb;
+};
+
+// LDS slot of window column t: one padding slot every 8 columns keeps the
+// stride-8 reads of a wave (lane l reads near column 8l + e) conflict-free.
+__device__ __forceinline__ int win_slot(int t) { return t + (t >> 3); }
+
 template <int NRHS>
 struct XVec {
   float v[NRHS];
 };
 
 template <int NRHS>
-__device__ __forceinline__ XVec<NRHS> load_x(const float* x, int c) {
+__device__ __forceinline__ XVec<NRHS> load_x_global(const float* x, int c) {
   XVec<NRHS> r;
   if constexpr (NRHS == 1) {
     r.v[0] = x[c];
@@ -102,298 +135,352 @@ __device__ __forceinline__ XVec<NRHS> load_x(const float* x, int c) {
   return r;
 }
 
-// LDS footprint of one block's products, in floats.
-template <int NRHS, int CAP>
-struct Lds {
-  static constexpr int kProd = (CAP + 2 * kChunk) * NRHS;
+template <int NRHS>
+__device__ __forceinline__ XVec<NRHS> load_x_window(const float* xw, int t) {
+  XVec<NRHS> r;
+  const float* p = xw + win_slot(t) * NRHS;
+  if constexpr (NRHS == 1) {
+    r.v[0] = p[0];
+  } else if constexpr (NRHS == 2) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    r.v[0] = v.x;
+    r.v[1] = v.y;
+  } else {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    r.v[0] = v.x;
+    r.v[1] = v.y;
+    r.v[2] = v.z;
+    r.v[3] = v.w;
+  }
+  return r;
+}
+
+// Sum of the 64 lanes in a fixed order, with DPP moves: within each row of 16
+// lanes, shifts by 1, 2, 4 and 8 leave the row's sum in its lane 15; two row
+// broadcasts then add rows 0..2 into lane 63.  Lanes shifted in from outside
+// a row (or from disabled rows) contribute 0.  Returns lane 63's value.
+__device__ __forceinline__ float wave_sum(float v) {
+  constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 1, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 2, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 4, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 8, 0xf, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowBcast15, 0xa, 0xf, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowBcast31, 0xc, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Position of the wave in its rows: the current 64-row window of row offsets
+// (lane l holds row wb+l's [lo, hi) relative to the group's first entry) and
+// the non-empty rows of the window not yet started.
+struct RowCursor {
+  uint32_t wb;
+  uint64_t mask;
+  uint32_t lo, hi;
 };
 
-// One row block: stream its entries into LDS products, then reduce rows.
-template <int VF, int SM, int NRHS, int CAP>
-__device__ __forceinline__ void process_block(const SpmvArgs& a, const BlockDesc& b,
-                                              float* __restrict__ prod,
-                                              uint32_t* __restrict__ rp) {
-  const int tid = threadIdx.x;
-  const uint64_t nb0 = b.nnz_begin;
-  const uint64_t nb1 = nb0 + b.nnz_count;
-  const uint64_t a0 = nb0 & ~static_cast<uint64_t>(kChunk - 1);
-  const int lo = static_cast<int>(nb0 - a0);
-  const int hi = static_cast<int>(nb1 - a0);
-  const int nchunks = (hi + kChunk - 1) / kChunk;
+// The streamed unit of work: one step (up to 64 chunks) of one row.  All
+// fields are wave-uniform.
+struct Unit {
+  bool valid;
+  uint32_t row;     // the row
+  uint64_t ks, ke;  // its entries [ks, ke)
+  uint64_t ka;      // ks rounded down to a multiple of 8
+  int step, nsteps;
+};
 
-  // ---- phase 1: coalesced stream of codes and indices, products to LDS
-  for (int c = tid; c < nchunks; c += kThreads) {
-    const uint64_t k0 = a0 + static_cast<uint64_t>(c) * kChunk;
-    Codes<VF> codes;
-    codes.load(a.val, k0);
-    const int4 c0 = *reinterpret_cast<const int4*>(a.col + k0);
-    const int4 c1 = *reinterpret_cast<const int4*>(a.col + k0 + 4);
-    const int cols[kChunk] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-    float p[kChunk][NRHS];
+template <int NRHS>
+__device__ __forceinline__ void load_window_rows(const SpmvArgs& a, RowCursor& rc, uint32_t wb, uint32_t r_end,
+                                                 uint32_t base32) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t r = wb + lane;
+  const bool in = r < r_end;
+  const uint32_t lo = in ? a.row_ptr[r] - base32 : 0u;
+  const uint32_t hi = in ? a.row_ptr[r + 1] - base32 : 0u;
+  if (in && hi == lo) {
+    float* dst = a.y + static_cast<int64_t>(r) * NRHS;
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) dst[q] = 0.0f;
+  }
+  rc.wb = wb;
+  rc.lo = lo;
+  rc.hi = hi;
+  rc.mask = __ballot(in && hi > lo);
+}
+
+// Next unit after u (or the first one when u is not valid).
+template <int NRHS>
+__device__ __forceinline__ Unit next_unit(const SpmvArgs& a, RowCursor& rc, const Unit& u, uint32_t r_end,
+                                          uint64_t base) {
+  Unit n = u;
+  if (u.valid && u.step + 1 < u.nsteps) {
+    n.step = u.step + 1;
+    return n;
+  }
+  const uint32_t base32 = static_cast<uint32_t>(base);
+  while (rc.mask == 0) {
+    const uint32_t wb = rc.wb + kWave;
+    if (wb >= r_end) {
+      n.valid = false;
+      return n;
+    }
+    load_window_rows<NRHS>(a, rc, wb, r_end, base32);
+  }
+  const int i = __builtin_ctzll(rc.mask);
+  rc.mask &= rc.mask - 1;
+  n.valid = true;
+  n.row = rc.wb + static_cast<uint32_t>(i);
+  n.ks = base + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(rc.lo), i));
+  n.ke = base + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(rc.hi), i));
+  n.ka = n.ks & ~static_cast<uint64_t>(kChunk - 1);
+  n.step = 0;
+  n.nsteps = static_cast<int>((n.ke - n.ka + kChunk * kWave - 1) / (kChunk * kWave));
+  return n;
+}
+
+template <int VF>
+__device__ __forceinline__ void load_unit(const SpmvArgs& a, const Unit& u, Chunk<VF>& ch) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
+  if (k0 < u.ke) {
+    ch.codes.load(a.val, k0);
+    ch.ca = ld_nt4(a.col + k0);
+    ch.cb = ld_nt4(a.col + k0 + 4);
+  }
+}
+
+// Products of one chunk, summed pairwise, added to the lane's accumulators.
+template <int VF, int SM, int NRHS, bool WIN>
+__device__ __forceinline__ void compute_unit(const SpmvArgs& a, const Unit& u, const Chunk<VF>& ch, const float* xw,
+                                             int cmin, float* acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
+  const uint64_t ks = u.ks, ke = u.ke;
+  if (k0 >= ke) return;
+  const int cols[kChunk] = {static_cast<int>(ch.ca.x), static_cast<int>(ch.ca.y), static_cast<int>(ch.ca.z),
+                            static_cast<int>(ch.ca.w), static_cast<int>(ch.cb.x), static_cast<int>(ch.cb.y),
+                            static_cast<int>(ch.cb.z), static_cast<int>(ch.cb.w)};
+  const bool full = k0 >= ks && k0 + kChunk <= ke;
+  XVec<NRHS> xv[kChunk];
+  if (!WIN && NRHS == 1 && full && cols[7] - cols[0] == kChunk - 1) {
+    // a run of 8 consecutive columns: two 16-byte loads of x
+    const float4 x0 = *reinterpret_cast<const float4*>(a.x + cols[0]);
+    const float4 x1 = *reinterpret_cast<const float4*>(a.x + cols[0] + 4);
+    xv[0].v[0] = x0.x, xv[1].v[0] = x0.y, xv[2].v[0] = x0.z, xv[3].v[0] = x0.w;
+    xv[4].v[0] = x1.x, xv[5].v[0] = x1.y, xv[6].v[0] = x1.z, xv[7].v[0] = x1.w;
+  } else {
 #pragma unroll
     for (int e = 0; e < kChunk; ++e) {
-      const int kl = c * kChunk + e;
-      const bool in = kl >= lo && kl < hi;
+      const bool in = full || (k0 + e >= ks && k0 + e < ke);
 #pragma unroll
-      for (int r = 0; r < NRHS; ++r) p[e][r] = 0.0f;
-      if (in) {
-        float d = codes.get(e);
-        if constexpr (SM == kScaleCol) d = d * a.scale[cols[e]];
-        const XVec<NRHS> xv = load_x<NRHS>(a.x, cols[e]);
-#pragma unroll
-        for (int r = 0; r < NRHS; ++r) p[e][r] = d * xv.v[r];
-      }
-    }
-    float* dst = prod + static_cast<int64_t>(c) * kChunk * NRHS;
-#pragma unroll
-    for (int q = 0; q < kChunk * NRHS; q += 4)
-      *reinterpret_cast<float4*>(dst + q) =
-          make_float4(p[q / NRHS][q % NRHS], p[(q + 1) / NRHS][(q + 1) % NRHS],
-                      p[(q + 2) / NRHS][(q + 2) % NRHS], p[(q + 3) / NRHS][(q + 3) % NRHS]);
-  }
-
-  const bool split = b.row_count == 0;
-  if (!split) {
-    const uint32_t base = static_cast<uint32_t>(a0);
-    for (int i = tid; i <= static_cast<int>(b.row_count); i += kThreads)
-      rp[i] = a.row_ptr[b.row_begin + i] - base;
-  }
-  __syncthreads();
-
-  // ---- phase 2: rows reduced by groups of G lanes in a fixed order
-  const int lg = static_cast<int>(b.meta & 7u);
-  const int G = 1 << lg;
-  const int lane = tid & (G - 1);
-  const int group = tid >> lg;
-  const int ngroups = kThreads >> lg;
-  const int nrows = split ? 1 : static_cast<int>(b.row_count);
-  for (int r = group; r < nrows; r += ngroups) {
-    const int s = split ? lo : static_cast<int>(rp[r]);
-    const int e = split ? hi : static_cast<int>(rp[r + 1]);
-    float acc[NRHS];
-#pragma unroll
-    for (int q = 0; q < NRHS; ++q) acc[q] = 0.0f;
-    if (e > s) {
-      for (int k = s + lane; k < e; k += G) {
-        if constexpr (NRHS == 1) {
-          acc[0] += prod[k];
-        } else if constexpr (NRHS == 2) {
-          const float2 t = *reinterpret_cast<const float2*>(prod + 2 * k);
-          acc[0] += t.x;
-          acc[1] += t.y;
-        } else {
-          const float4 t = *reinterpret_cast<const float4*>(prod + 4 * k);
-          acc[0] += t.x;
-          acc[1] += t.y;
-          acc[2] += t.z;
-          acc[3] += t.w;
-        }
-      }
-      for (int off = G >> 1; off > 0; off >>= 1) {
-#pragma unroll
-        for (int q = 0; q < NRHS; ++q) acc[q] += __shfl_xor(acc[q], off, G);
-      }
-    }
-    if (lane == 0) {
-      if (split) {
-        float* dst = a.partials + static_cast<int64_t>(b.partial) * NRHS;
-#pragma unroll
-        for (int q = 0; q < NRHS; ++q) dst[q] = acc[q];
-      } else {
-        const int64_t row = static_cast<int64_t>(b.row_begin) + r;
-        const float sc = SM == kScaleRow ? a.scale[row] : 1.0f;
-        float* dst = a.y + row * NRHS;
-#pragma unroll
-        for (int q = 0; q < NRHS; ++q) dst[q] = SM == kScaleRow ? acc[q] * sc : acc[q];
-      }
+      for (int q = 0; q < NRHS; ++q) xv[e].v[q] = 0.0f;
+      if (in) xv[e] = WIN ? load_x_window<NRHS>(xw, cols[e] - cmin) : load_x_global<NRHS>(a.x, cols[e]);
     }
   }
-  __syncthreads();
+  float p[kChunk][NRHS];
+#pragma unroll
+  for (int e = 0; e < kChunk; ++e) {
+    const bool in = full || (k0 + e >= ks && k0 + e < ke);
+    float d = in ? ch.codes.get(e) : 0.0f;
+    if constexpr (SM == kScaleCol) d = in ? d * a.scale[cols[e]] : 0.0f;
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) p[e][q] = d * xv[e].v[q];
+  }
+#pragma unroll
+  for (int q = 0; q < NRHS; ++q)
+    acc[q] += ((p[0][q] + p[1][q]) + (p[2][q] + p[3][q])) + ((p[4][q] + p[5][q]) + (p[6][q] + p[7][q]));
 }
 
-template <int VF, int SM, int NRHS, int CAP>
-__global__ __launch_bounds__(kThreads) void k_spmv(SpmvArgs a) {
-  __shared__ __align__(16) float prod[Lds<NRHS, CAP>::kProd];
-  __shared__ uint32_t rp[kMaxBlockRows + 1];
-  const BlockDesc b = a.blocks[blockIdx.x];
-  process_block<VF, SM, NRHS, CAP>(a, b, prod, rp);
+template <int SM, int NRHS>
+__device__ __forceinline__ void finish_row(const SpmvArgs& a, const Unit& u, float* acc) {
+  const int lane = threadIdx.x & (kWave - 1);
+  float tot[NRHS];
+#pragma unroll
+  for (int q = 0; q < NRHS; ++q) {
+    tot[q] = wave_sum(acc[q]);
+    acc[q] = 0.0f;
+  }
+  if (lane == 0) {
+    const int64_t row = u.row;
+    float* dst = a.y + row * NRHS;
+    if constexpr (SM == kScaleRow) {
+      const float sc = a.scale[row];
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) dst[q] = tot[q] * sc;
+    } else {
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) dst[q] = tot[q];
+    }
+  }
 }
 
-// Persistent form: workgroups walk a list of (item, block) pairs that may
+// One wave's rows [r_begin, r_end) of a group whose entries start at `base`.
+template <int VF, int SM, int NRHS, bool WIN>
+__device__ __forceinline__ void wave_rows(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
+                                          const float* xw, int cmin) {
+  if (r_begin >= r_end) return;
+  RowCursor rc;
+  load_window_rows<NRHS>(a, rc, r_begin, r_end, static_cast<uint32_t>(base));
+  float acc[NRHS];
+#pragma unroll
+  for (int q = 0; q < NRHS; ++q) acc[q] = 0.0f;
+  Unit u;
+  u.valid = false;
+  u = next_unit<NRHS>(a, rc, u, r_end, base);
+  if (!u.valid) return;
+  // a ring of three units: the loads of the next two are in flight while the
+  // current one is computed
+  Chunk<VF> c0, c1, c2;
+  load_unit<VF>(a, u, c0);
+  Unit u1 = next_unit<NRHS>(a, rc, u, r_end, base);
+  if (u1.valid) load_unit<VF>(a, u1, c1);
+  while (true) {
+    Unit u2;
+    u2.valid = false;
+    if (u1.valid) {
+      u2 = next_unit<NRHS>(a, rc, u1, r_end, base);
+      if (u2.valid) load_unit<VF>(a, u2, c2);
+    }
+    compute_unit<VF, SM, NRHS, WIN>(a, u, c0, xw, cmin, acc);
+    if (u.step + 1 == u.nsteps) finish_row<SM, NRHS>(a, u, acc);
+    if (!u1.valid) break;
+    u = u1;
+    c0 = c1;
+    u1 = u2;
+    c1 = c2;
+  }
+}
+
+template <int VF, int SM, int NRHS>
+__device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw) {
+  // wave-uniform index, so that the row bounds below are scalar loads
+  const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
+  const uint64_t base = gp->nnz_base;
+  const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
+  const uint32_t clen = gp->clen;
+  if (clen > 0 && window_floats(clen, NRHS) <= a.win_floats) {
+    const int cmin = static_cast<int>(gp->cmin);
+    for (int t = threadIdx.x; t < static_cast<int>(clen); t += kGroupThreads) {
+      const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
+    }
+    __syncthreads();
+    wave_rows<VF, SM, NRHS, true>(a, base, r0, r1, xw, cmin);
+  } else {
+    wave_rows<VF, SM, NRHS, false>(a, base, r0, r1, xw, 0);
+  }
+}
+
+template <int VF, int SM, int NRHS>
+__global__ __launch_bounds__(kGroupThreads) void k_spmv(SpmvArgs a) {
+  extern __shared__ __align__(16) float xw[];  // a.win_floats floats
+  run_group<VF, SM, NRHS>(a, a.groups + blockIdx.x, xw);
+}
+
+// Persistent form: workgroups walk a list of (item, group) pairs that may
 // belong to many matrices.
-template <int VF, int SM, int NRHS, int CAP>
-__global__ __launch_bounds__(kThreads) void k_spmv_batched(const SpmvArgs* __restrict__ args,
-                                                           const WorkItem* __restrict__ work,
-                                                           int64_t n_work) {
-  __shared__ __align__(16) float prod[Lds<NRHS, CAP>::kProd];
-  __shared__ uint32_t rp[kMaxBlockRows + 1];
+template <int VF, int SM, int NRHS>
+__global__ __launch_bounds__(kGroupThreads) void k_spmv_batched(const SpmvArgs* __restrict__ args,
+                                                                const WorkItem* __restrict__ work, int64_t n_work) {
+  extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
     const WorkItem wi = work[w];
     const SpmvArgs a = args[wi.item];
-    const BlockDesc b = a.blocks[wi.block];
-    process_block<VF, SM, NRHS, CAP>(a, b, prod, rp);
+    run_group<VF, SM, NRHS>(a, a.groups + wi.group, xw);
+    __syncthreads();  // the window is reused by the next group
   }
 }
 
-// Split rows: y[row] = (scale) * sum of the row's chunk partials, in chunk order.
-template <int SM, int NRHS>
-__device__ __forceinline__ void combine_one(const SpmvArgs& a, const SplitRow sr, int q) {
-  float acc = 0.0f;
-  for (uint32_t c = 0; c < sr.n_slots; ++c)
-    acc += a.partials[static_cast<int64_t>(sr.first_slot + c) * NRHS + q];
-  if constexpr (SM == kScaleRow) acc = acc * a.scale[sr.row];
-  a.y[static_cast<int64_t>(sr.row) * NRHS + q] = acc;
-}
-
-template <int SM, int NRHS>
-__global__ void k_combine(SpmvArgs a) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= a.n_splits * NRHS) return;
-  combine_one<SM, NRHS>(a, a.splits[t / NRHS], static_cast<int>(t % NRHS));
-}
-
-template <int SM, int NRHS>
-__global__ void k_combine_batched(const SpmvArgs* __restrict__ args,
-                                  const uint32_t* __restrict__ items,
-                                  const uint32_t* __restrict__ idx, int64_t n) {
-  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= n * NRHS) return;
-  const int64_t i = t / NRHS;
-  const SpmvArgs& a = args[items[i]];
-  combine_one<SM, NRHS>(a, a.splits[idx[i]], static_cast<int>(t % NRHS));
-}
-
-int cap_for(int block_nnz) {
-  if (block_nnz <= 1024) return 1024;
-  if (block_nnz <= 2048) return 2048;
-  if (block_nnz <= 4096) return 4096;
-  return 8192;
-}
-
-template <int VF, int SM, int NRHS>
-hipError_t launch_cap(int cap, const SpmvArgs& a, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(a.n_blocks)), block(kThreads);
-  switch (cap) {
-    case 1024: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 1024>), grid, block, 0, s, a); break;
-    case 2048: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 2048>), grid, block, 0, s, a); break;
-    case 4096: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 4096>), grid, block, 0, s, a); break;
-    default:
-      if constexpr (NRHS <= 2) {
-        hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 8192>), grid, block, 0, s, a);
-      } else {
-        return hipErrorInvalidValue;
-      }
-  }
-  return hipGetLastError();
-}
-
-template <int VF, int SM, int NRHS>
-hipError_t launch_cap_batched(int cap, const SpmvArgs* args, const WorkItem* work, int64_t n_work,
-                              int grid, hipStream_t s) {
-  const dim3 g(static_cast<unsigned>(grid)), block(kThreads);
-  switch (cap) {
-    case 1024: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 1024>), g, block, 0, s, args, work, n_work); break;
-    case 2048: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 2048>), g, block, 0, s, args, work, n_work); break;
-    case 4096: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 4096>), g, block, 0, s, args, work, n_work); break;
-    default:
-      if constexpr (NRHS <= 2) {
-        hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 8192>), g, block, 0, s, args, work, n_work);
-      } else {
-        return hipErrorInvalidValue;
-      }
+template <int VF, int SM>
+hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
+  const size_t lds = static_cast<size_t>(a.win_floats) * sizeof(float);
+  switch (n_rhs) {
+    case 1: hipLaunchKernelGGL((k_spmv<VF, SM, 1>), grid, block, lds, s, a); break;
+    case 2: hipLaunchKernelGGL((k_spmv<VF, SM, 2>), grid, block, lds, s, a); break;
+    case 4: hipLaunchKernelGGL((k_spmv<VF, SM, 4>), grid, block, lds, s, a); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <int VF, int SM>
-hipError_t launch_rhs(int n_rhs, int cap, const SpmvArgs& a, hipStream_t s) {
+hipError_t launch_rhs_batched(int n_rhs, const SpmvArgs* args, const WorkItem* work, int64_t n_work, int grid,
+                              int lds_floats, hipStream_t s) {
+  const dim3 g(static_cast<unsigned>(grid)), block(kGroupThreads);
+  const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: return launch_cap<VF, SM, 1>(cap, a, s);
-    case 2: return launch_cap<VF, SM, 2>(cap, a, s);
-    case 4: return launch_cap<VF, SM, 4>(cap, a, s);
+    case 1: hipLaunchKernelGGL((k_spmv_batched<VF, SM, 1>), g, block, lds, s, args, work, n_work); break;
+    case 2: hipLaunchKernelGGL((k_spmv_batched<VF, SM, 2>), g, block, lds, s, args, work, n_work); break;
+    case 4: hipLaunchKernelGGL((k_spmv_batched<VF, SM, 4>), g, block, lds, s, args, work, n_work); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
 }
 
-template <int VF, int SM>
-hipError_t launch_rhs_batched(int n_rhs, int cap, const SpmvArgs* args, const WorkItem* work,
-                              int64_t n_work, int grid, hipStream_t s) {
-  switch (n_rhs) {
-    case 1: return launch_cap_batched<VF, SM, 1>(cap, args, work, n_work, grid, s);
-    case 2: return launch_cap_batched<VF, SM, 2>(cap, args, work, n_work, grid, s);
-    case 4: return launch_cap_batched<VF, SM, 4>(cap, args, work, n_work, grid, s);
-    default: return hipErrorInvalidValue;
+// Column window of every group: min and max column over its entries.
+__global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ groups, int64_t n_groups,
+                                                       const int32_t* __restrict__ col,
+                                                       const uint32_t* __restrict__ row_ptr) {
+  __shared__ int smin[256], smax[256];
+  const GroupDesc g = groups[blockIdx.x];
+  const uint32_t base32 = static_cast<uint32_t>(g.nnz_base);
+  const uint64_t n = static_cast<uint64_t>(row_ptr[g.row[kGroupWaves]] - base32);
+  int mn = 0x7fffffff, mx = -1;
+  for (uint64_t k = threadIdx.x; k < n; k += 256) {
+    const int c = col[g.nnz_base + k];
+    mn = min(mn, c);
+    mx = max(mx, c);
   }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      smin[threadIdx.x] = min(smin[threadIdx.x], smin[threadIdx.x + w]);
+      smax[threadIdx.x] = max(smax[threadIdx.x], smax[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    groups[blockIdx.x].cmin = smax[0] >= 0 ? static_cast<uint32_t>(smin[0]) : 0u;
+    groups[blockIdx.x].clen = smax[0] >= 0 ? static_cast<uint32_t>(smax[0] - smin[0] + 1) : 0u;
+  }
+  (void)n_groups;
 }
 
 }  // namespace
 
-hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, int block_nnz, const SpmvArgs& a,
-                       hipStream_t s) {
-  if (a.n_blocks <= 0) return hipSuccess;
-  const int cap = cap_for(block_nnz);
-  if (vf == kFp16 && scale_mode == kScaleNone) return launch_rhs<kFp16, kScaleNone>(n_rhs, cap, a, s);
-  if (vf == kBf16 && scale_mode == kScaleNone) return launch_rhs<kBf16, kScaleNone>(n_rhs, cap, a, s);
-  if (vf == kFp8 && scale_mode == kScaleRow) return launch_rhs<kFp8, kScaleRow>(n_rhs, cap, a, s);
-  if (vf == kFp8 && scale_mode == kScaleCol) return launch_rhs<kFp8, kScaleCol>(n_rhs, cap, a, s);
+hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s) {
+  if (a.n_groups <= 0) return hipSuccess;
+  if (vf == kFp16 && scale_mode == kScaleNone) return launch_rhs<kFp16, kScaleNone>(n_rhs, a, s);
+  if (vf == kBf16 && scale_mode == kScaleNone) return launch_rhs<kBf16, kScaleNone>(n_rhs, a, s);
+  if (vf == kFp8 && scale_mode == kScaleRow) return launch_rhs<kFp8, kScaleRow>(n_rhs, a, s);
+  if (vf == kFp8 && scale_mode == kScaleCol) return launch_rhs<kFp8, kScaleCol>(n_rhs, a, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int block_nnz,
-                               const SpmvArgs* d_args, const WorkItem* d_work, int64_t n_work,
-                               int grid, hipStream_t s) {
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args, const WorkItem* d_work,
+                               int64_t n_work, int grid, int lds_floats, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
-  const int cap = cap_for(block_nnz);
   if (vf == kFp16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, cap, d_args, d_work, n_work, grid, s);
+    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, cap, d_args, d_work, n_work, grid, s);
+    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleRow)
-    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, cap, d_args, d_work, n_work, grid, s);
+    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)
-    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, cap, d_args, d_work, n_work, grid, s);
+    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
   return hipErrorInvalidValue;
 }
 
-template <int SM>
-static hipError_t combine_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
-  const int64_t n = a.n_splits * n_rhs;
-  const dim3 grid(static_cast<unsigned>((n + 255) / 256)), block(256);
-  switch (n_rhs) {
-    case 1: hipLaunchKernelGGL((k_combine<SM, 1>), grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_combine<SM, 2>), grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_combine<SM, 4>), grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const int32_t* col, const uint32_t* row_ptr,
+                                hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_group_windows, dim3(static_cast<unsigned>(n_groups)), dim3(256), 0, s, groups, n_groups, col,
+                     row_ptr);
   return hipGetLastError();
-}
-
-hipError_t launch_combine(int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s) {
-  if (a.n_splits <= 0) return hipSuccess;
-  return scale_mode == kScaleRow ? combine_rhs<kScaleRow>(n_rhs, a, s)
-                                 : combine_rhs<kScaleNone>(n_rhs, a, s);
-}
-
-template <int SM>
-static hipError_t combine_rhs_batched(int n_rhs, const SpmvArgs* args, const uint32_t* items,
-                                      const uint32_t* idx, int64_t n, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>((n * n_rhs + 255) / 256)), block(256);
-  switch (n_rhs) {
-    case 1: hipLaunchKernelGGL((k_combine_batched<SM, 1>), grid, block, 0, s, args, items, idx, n); break;
-    case 2: hipLaunchKernelGGL((k_combine_batched<SM, 2>), grid, block, 0, s, args, items, idx, n); break;
-    case 4: hipLaunchKernelGGL((k_combine_batched<SM, 4>), grid, block, 0, s, args, items, idx, n); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_combine_batched(int scale_mode, int n_rhs, const SpmvArgs* d_args,
-                                  const uint32_t* d_split_items, const uint32_t* d_split_idx,
-                                  int64_t n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  return scale_mode == kScaleRow
-             ? combine_rhs_batched<kScaleRow>(n_rhs, d_args, d_split_items, d_split_idx, n, s)
-             : combine_rhs_batched<kScaleNone>(n_rhs, d_args, d_split_items, d_split_idx, n, s);
 }
 
 }  // namespace dose

@@ -105,7 +105,7 @@ def test_autotuned_plan_stays_within_tolerance(dev, tmp_path, monkeypatch):
     plan.launch()
     torch.cuda.synchronize()
     for (A, X, Y), (s, rp, cols, vals) in zip(entries, host):
-        assert A.info()["block_nnz"] in (1024, 2048, 4096)
+        assert A.info()["group_nnz"] in (8192, 16384, 32768, 65536)
         dec, _ = oracle.decode_matrix("bf16", rp, vals)
         Y_ref = oracle.spmv_multi(rp, cols, dec, X.cpu().numpy())
         for r in range(4):

@@ -91,22 +91,56 @@ def test_small_plain_parity(fmt, dev):
     A.close()
 
 
-@pytest.mark.parametrize("block_nnz", [256, 1024, 2048, 4096, 8192])
 @pytest.mark.parametrize("fmt", FORMATS)
-def test_partitions_with_split_rows_and_ragged_tail(fmt, block_nnz, dev):
-    rng = np.random.default_rng(block_nnz)
+def test_partitions_long_rows_and_ragged_tail(fmt, dev):
+    """Rows from 1 to 20,000 entries (many 512-entry steps), empty runs, a
+    ragged last row; the product is checked under several partitions and must
+    be bitwise the same under all of them (each row's summation order is its
+    own)."""
+    rng = np.random.default_rng(11)
     lens = rng.integers(0, 700, size=3001)
     lens[rng.random(lens.size) < 0.5] = 0
-    lens[[5, 1000, 3000]] = [20000, 8193, 9999]  # long rows: split into chunks
+    lens[[5, 1000, 3000]] = [20000, 4089, 9999]  # long rows
     lens[1001:1010] = 1                           # short rows
+    lens[2000:2300] = 0                           # a run of empty rows
     rp, cols, vals = _csr_from_lens(rng, lens, 20000, signed=True)
     x = rng.uniform(-1, 1, 20000).astype(np.float32)
-    _say("partition", fmt, block_nnz, rp[-1])
     A = dm.DoseMatrix(rp, cols, vals, 20000, fmt)
-    A.set_partition(block_nnz)
-    assert A.info()["block_nnz"] == block_nnz
-    assert A.info()["n_split_rows"] >= 3
-    _check_forward(A, rp, cols, vals, fmt, x)
+    ys = []
+    for group_nnz in (1024, 4096, 32768, 1 << 20):
+        _say("partition", fmt, group_nnz, rp[-1])
+        A.set_partition(group_nnz)
+        assert A.info()["group_nnz"] == group_nnz
+        ys.append(_check_forward(A, rp, cols, vals, fmt, x)[0])
+    for y in ys[1:]:
+        np.testing.assert_array_equal(_bits(y), _bits(ys[0]))
+    A.close()
+
+
+def test_window_and_global_gathers_agree(dev):
+    """Groups whose column window fits LDS gather x there, the others from
+    global memory; both must give the same bits."""
+    rng = np.random.default_rng(12)
+    n_cols = 60000
+    lens = rng.integers(1, 400, size=4000)
+    rp = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    cols = np.empty(rp[-1], np.int32)
+    for i, L in enumerate(lens):
+        # rows 0..1999 use columns below 2000; rows 2000.. spread over all columns
+        span = 2000 if i < 2000 else n_cols
+        cols[rp[i]:rp[i + 1]] = np.sort(rng.choice(span, size=L, replace=False))
+    vals = np.exp(rng.normal(-3, 1, size=rp[-1])).astype(np.float32)
+    x = rng.uniform(0, 1, n_cols).astype(np.float32)
+    A = dm.DoseMatrix(rp, cols, vals, n_cols, "fp16")
+    A.set_partition(8192)
+    info = A.info()
+    assert 0 < info["n_groups_windowed"] < info["n_groups"]
+    y, _ = _check_forward(A, rp, cols, vals, "fp16", x)
+    A.set_partition(1 << 20)  # one group per 2^20 entries: no window fits
+    assert A.info()["n_groups_windowed"] == 0
+    y2, _ = _check_forward(A, rp, cols, vals, "fp16", x)
+    np.testing.assert_array_equal(_bits(y), _bits(y2))
     A.close()
 
 
@@ -192,12 +226,12 @@ def test_determinism_repeat_and_rebuild(dev):
     x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
     _say("determinism")
     A = dm.DoseMatrix(rp, cols, vals, spec.n_cols)
-    A.set_partition(256)  # many split rows and blocks
+    A.set_partition(1024)  # many groups
     y0 = A.spmv(x).clone()
     for _ in range(50):
         assert torch.equal(A.spmv(x), y0)
     B = dm.DoseMatrix(rp, cols, vals, spec.n_cols)
-    B.set_partition(256)
+    B.set_partition(65536)
     assert torch.equal(B.spmv(x), y0)
     A.close()
     B.close()

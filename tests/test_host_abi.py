@@ -106,53 +106,41 @@ def _random_row_ptr(rng, n_rows, long_rows=()):
     return rp
 
 
-@pytest.mark.parametrize("block_nnz", [256, 1024, 4096, 8192])
-def test_partition_covers_every_entry_and_row_once(block_nnz):
-    rng = np.random.default_rng(block_nnz)
-    rp = _random_row_ptr(rng, 5000, long_rows=[(7, 30000), (4000, 8193), (4001, 8192), (4999, 100000)])
-    B = dm.partition_preview(rp, block_nnz)
-    nnz_pos, row_pos = 0, 0
-    split_row, split_end = None, None
-    for nb, cnt, r0, rc, G in B:
-        assert nb == nnz_pos, "blocks must tile the entries in order"
-        assert 0 < cnt <= block_nnz or (cnt == 0 and rc > 0)
-        assert G in (4, 8, 16, 32, 64)
-        if rc == -1:  # chunk of a split row
-            assert rp[r0 + 1] - rp[r0] > block_nnz
-            if split_row != r0:
-                assert r0 == row_pos and nb == rp[r0]
-                split_row, split_end = r0, rp[r0 + 1]
-            nnz_pos += cnt
-            if nnz_pos == split_end:
-                row_pos = r0 + 1
-        else:
-            assert r0 == row_pos and 1 <= rc <= 1024
-            assert rp[r0] == nb and rp[r0 + rc] - rp[r0] == cnt
-            row_pos += rc
-            nnz_pos += cnt
-    assert nnz_pos == rp[-1] and row_pos == rp.size - 1
+@pytest.mark.parametrize("group_nnz", [1024, 4096, 32768, 1 << 20])
+def test_partition_groups_tile_the_rows(group_nnz):
+    rng = np.random.default_rng(group_nnz)
+    rp = _random_row_ptr(rng, 50000, long_rows=[(7, 30000), (4000, 8193), (49999, 100000)])
+    G = dm.partition_preview(rp, group_nnz)
+    assert G[0, 0] == 0 and G[-1, 4] == rp.size - 1
+    assert np.all(G[1:, 0] == G[:-1, 4]), "groups must tile the rows in order"
+    assert np.all(np.diff(G, axis=1) >= 0)
+    for r0, r1, r2, r3, r4 in G:
+        nnz = rp[r4] - rp[r0]
+        assert 1 <= r4 - r0 <= 16384
+        # a group exceeds group_nnz only when it is a single row
+        assert nnz <= group_nnz or r4 - r0 == 1
+        # wave shares balance entries + 16 per row, up to one row's cost
+        cost = [(rp[b] - rp[a]) + 16 * (b - a) for a, b in ((r0, r1), (r1, r2), (r2, r3), (r3, r4))]
+        biggest_row = max((rp[i + 1] - rp[i]) + 16 for i in range(r0, r4))
+        assert max(cost) - min(cost) <= 2 * biggest_row + (nnz + 16 * (r4 - r0)) // 4 + 1
 
 
-def test_partition_is_deterministic_and_balanced_chunks():
-    rp = np.array([0, 10000, 10000, 10005], np.int64)
-    a = dm.partition_preview(rp, 4096)
-    b = dm.partition_preview(rp, 4096)
-    np.testing.assert_array_equal(a, b)
-    chunks = a[a[:, 3] == -1]
-    assert chunks[:, 1].tolist() == [3334, 3334, 3332]
+def test_partition_is_deterministic():
+    rng = np.random.default_rng(3)
+    rp = _random_row_ptr(rng, 20000)
+    np.testing.assert_array_equal(dm.partition_preview(rp, 8192), dm.partition_preview(rp, 8192))
 
 
 def test_partition_empty_inputs():
     assert dm.partition_preview(np.array([0], np.int64), 1024).shape == (0, 5)
-    B = dm.partition_preview(np.zeros(2501, np.int64), 1024)
-    assert B[:, 3].tolist() == [1024, 1024, 452] and B[:, 1].sum() == 0
+    G = dm.partition_preview(np.zeros(40001, np.int64), 1024)
+    assert (G[:, 4] - G[:, 0]).tolist() == [16384, 16384, 7232]
 
 
-def test_partition_rejects_bad_block_size():
-    with pytest.raises(dm.DoseError):
-        dm.partition_preview(np.array([0, 1], np.int64), 3000)
-    with pytest.raises(dm.DoseError):
-        dm.partition_preview(np.array([0, 1], np.int64), 128)
+def test_partition_rejects_bad_group_size():
+    for bad in (3000, 512, 1 << 21):
+        with pytest.raises(dm.DoseError):
+            dm.partition_preview(np.array([0, 1], np.int64), bad)
 
 
 # ------------------------------------------------------------------ byte model
