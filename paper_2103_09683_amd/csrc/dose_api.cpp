@@ -274,6 +274,20 @@ struct Operand {
 
 int rhs_slot(int n_rhs) { return n_rhs == 1 ? 0 : n_rhs == 2 ? 1 : 2; }
 
+// Cap on one workgroup's LDS x window, in floats: DOSE_LDS_WINDOW_FLOATS
+// (256 .. kWinFloatsMax), default 4096 (16 KB: eight workgroups per compute
+// unit, and 99.8% of the clinical beam's groups fit).  A smaller cap lets
+// more workgroups share a compute unit; groups whose window exceeds it
+// gather x from global memory.
+int64_t window_cap_floats() {
+  static const int64_t cap = [] {
+    const char* e = std::getenv("DOSE_LDS_WINDOW_FLOATS");
+    const int64_t v = e ? std::atoll(e) : 4096;
+    return std::max<int64_t>(256, std::min<int64_t>(kWinFloatsMax, v));
+  }();
+  return cap;
+}
+
 void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
   std::vector<GroupDesc> G = build_partition(op.h_row_ptr.data(), op.n_rows, group_nnz);
   DevBuf groups(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
@@ -284,16 +298,17 @@ void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
     HIP_CHECK(hipMemcpyAsync(G.data(), groups.get(), G.size() * sizeof(GroupDesc), hipMemcpyDeviceToHost, s));
   }
   HIP_CHECK(hipStreamSynchronize(s));
-  // LDS per workgroup: the largest window that fits kWinFloatsMax; groups
-  // with larger windows read x from global memory
+  // LDS per workgroup: the largest window within the cap; groups with larger
+  // windows read x from global memory
+  const int64_t cap = window_cap_floats();
   int64_t windowed = 0;
   int64_t wf[3] = {0, 0, 0};
   const int rhs[3] = {1, 2, 4};
   for (const GroupDesc& g : G) {
-    windowed += g.clen > 0 && window_floats(g.clen, 1) <= kWinFloatsMax;
+    windowed += g.clen > 0 && window_floats(g.clen, 1) <= cap;
     for (int i = 0; i < 3; ++i) {
       const int64_t f = window_floats(g.clen, rhs[i]);
-      if (f <= kWinFloatsMax) wf[i] = std::max(wf[i], f);
+      if (f <= cap) wf[i] = std::max(wf[i], f);
     }
   }
   op.groups = std::move(groups);

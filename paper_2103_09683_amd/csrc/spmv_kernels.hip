@@ -29,6 +29,8 @@
 
 #include <hip/hip_fp16.h>
 
+#include <cstdlib>
+
 namespace dose {
 namespace {
 
@@ -252,17 +254,22 @@ __device__ __forceinline__ void load_unit(const SpmvArgs& a, const Unit& u, Chun
 // Products of one chunk, summed pairwise, added to the lane's accumulators.
 template <int VF, int SM, int NRHS, bool WIN>
 __device__ __forceinline__ void compute_unit(const SpmvArgs& a, const Unit& u, const Chunk<VF>& ch, const float* xw,
-                                             int cmin, float* acc) {
+                                             int cmin, int clen, float* acc) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
-  const uint64_t ks = u.ks, ke = u.ke;
-  if (k0 >= ke) return;
+  if (k0 >= u.ke) return;
+  // entries e of the chunk with lo <= e < hi belong to the row
+  const int lo = k0 >= u.ks ? 0 : static_cast<int>(u.ks - k0);
+  const int hi = u.ke - k0 >= kChunk ? kChunk : static_cast<int>(u.ke - k0);
   const int cols[kChunk] = {static_cast<int>(ch.ca.x), static_cast<int>(ch.ca.y), static_cast<int>(ch.ca.z),
                             static_cast<int>(ch.ca.w), static_cast<int>(ch.cb.x), static_cast<int>(ch.cb.y),
                             static_cast<int>(ch.cb.z), static_cast<int>(ch.cb.w)};
-  const bool full = k0 >= ks && k0 + kChunk <= ke;
+  // Every entry of the chunk is decoded and multiplied, also those of the
+  // neighbouring rows (their columns are valid indices; window positions are
+  // clamped into the window), and the products outside the row are replaced
+  // by 0 afterwards: no branches, and no Inf or NaN of x leaks in.
   XVec<NRHS> xv[kChunk];
-  if (!WIN && NRHS == 1 && full && cols[7] - cols[0] == kChunk - 1) {
+  if (!WIN && NRHS == 1 && lo == 0 && hi == kChunk && cols[7] - cols[0] == kChunk - 1) {
     // a run of 8 consecutive columns: two 16-byte loads of x
     const float4 x0 = *reinterpret_cast<const float4*>(a.x + cols[0]);
     const float4 x1 = *reinterpret_cast<const float4*>(a.x + cols[0] + 4);
@@ -271,20 +278,22 @@ __device__ __forceinline__ void compute_unit(const SpmvArgs& a, const Unit& u, c
   } else {
 #pragma unroll
     for (int e = 0; e < kChunk; ++e) {
-      const bool in = full || (k0 + e >= ks && k0 + e < ke);
-#pragma unroll
-      for (int q = 0; q < NRHS; ++q) xv[e].v[q] = 0.0f;
-      if (in) xv[e] = WIN ? load_x_window<NRHS>(xw, cols[e] - cmin) : load_x_global<NRHS>(a.x, cols[e]);
+      if constexpr (WIN) {
+        const int t = min(max(cols[e] - cmin, 0), clen - 1);
+        xv[e] = load_x_window<NRHS>(xw, t);
+      } else {
+        xv[e] = load_x_global<NRHS>(a.x, cols[e]);
+      }
     }
   }
   float p[kChunk][NRHS];
 #pragma unroll
   for (int e = 0; e < kChunk; ++e) {
-    const bool in = full || (k0 + e >= ks && k0 + e < ke);
-    float d = in ? ch.codes.get(e) : 0.0f;
-    if constexpr (SM == kScaleCol) d = in ? d * a.scale[cols[e]] : 0.0f;
+    const bool in = e >= lo && e < hi;
+    float d = ch.codes.get(e);
+    if constexpr (SM == kScaleCol) d = d * a.scale[cols[e]];
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) p[e][q] = d * xv[e].v[q];
+    for (int q = 0; q < NRHS; ++q) p[e][q] = in ? d * xv[e].v[q] : 0.0f;
   }
 #pragma unroll
   for (int q = 0; q < NRHS; ++q)
@@ -314,92 +323,134 @@ __device__ __forceinline__ void finish_row(const SpmvArgs& a, const Unit& u, flo
   }
 }
 
-// One wave's rows [r_begin, r_end) of a group whose entries start at `base`.
-template <int VF, int SM, int NRHS, bool WIN>
+// One wave's rows [r_begin, r_end) of a group whose entries start at `base`,
+// with the loads of the next DEPTH units in flight while a unit is computed.
+// With WIN the workgroup first copies the x window [cmin, cmin + clen) into
+// LDS; every wave issues its first loads before that copy and its barrier,
+// so the copy's latency hides behind the stream.  All waves reach the
+// barrier, also those without rows.
+template <int VF, int SM, int NRHS, bool WIN, int DEPTH>
 __device__ __forceinline__ void wave_rows(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
-                                          const float* xw, int cmin) {
-  if (r_begin >= r_end) return;
+                                          float* xw, int cmin, int clen) {
   RowCursor rc;
-  load_window_rows<NRHS>(a, rc, r_begin, r_end, static_cast<uint32_t>(base));
+  Unit us[DEPTH + 1];
+  Chunk<VF> cs[DEPTH + 1];
+#pragma unroll
+  for (int d = 0; d <= DEPTH; ++d) us[d].valid = false;
+  if (r_begin < r_end) {
+    load_window_rows<NRHS>(a, rc, r_begin, r_end, static_cast<uint32_t>(base));
+    us[0] = next_unit<NRHS>(a, rc, us[0], r_end, base);
+    if (us[0].valid) load_unit<VF>(a, us[0], cs[0]);
+#pragma unroll
+    for (int d = 1; d < DEPTH; ++d)
+      if (us[d - 1].valid) {
+        us[d] = next_unit<NRHS>(a, rc, us[d - 1], r_end, base);
+        if (us[d].valid) load_unit<VF>(a, us[d], cs[d]);
+      }
+  }
+  if constexpr (WIN) {
+    for (int t = threadIdx.x; t < clen; t += kGroupThreads) {
+      const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
+    }
+    __syncthreads();
+  }
+  if (!us[0].valid) return;
   float acc[NRHS];
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) acc[q] = 0.0f;
-  Unit u;
-  u.valid = false;
-  u = next_unit<NRHS>(a, rc, u, r_end, base);
-  if (!u.valid) return;
-  // a ring of three units: the loads of the next two are in flight while the
-  // current one is computed
-  Chunk<VF> c0, c1, c2;
-  load_unit<VF>(a, u, c0);
-  Unit u1 = next_unit<NRHS>(a, rc, u, r_end, base);
-  if (u1.valid) load_unit<VF>(a, u1, c1);
   while (true) {
-    Unit u2;
-    u2.valid = false;
-    if (u1.valid) {
-      u2 = next_unit<NRHS>(a, rc, u1, r_end, base);
-      if (u2.valid) load_unit<VF>(a, u2, c2);
+    if (us[DEPTH - 1].valid) {
+      us[DEPTH] = next_unit<NRHS>(a, rc, us[DEPTH - 1], r_end, base);
+      if (us[DEPTH].valid) load_unit<VF>(a, us[DEPTH], cs[DEPTH]);
+    } else {
+      us[DEPTH].valid = false;
     }
-    compute_unit<VF, SM, NRHS, WIN>(a, u, c0, xw, cmin, acc);
-    if (u.step + 1 == u.nsteps) finish_row<SM, NRHS>(a, u, acc);
-    if (!u1.valid) break;
-    u = u1;
-    c0 = c1;
-    u1 = u2;
-    c1 = c2;
+    compute_unit<VF, SM, NRHS, WIN>(a, us[0], cs[0], xw, cmin, clen, acc);
+    if (us[0].step + 1 == us[0].nsteps) finish_row<SM, NRHS>(a, us[0], acc);
+    if (!us[1].valid) break;
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      us[d] = us[d + 1];
+      cs[d] = cs[d + 1];
+    }
   }
 }
 
-template <int VF, int SM, int NRHS>
+template <int VF, int SM, int NRHS, int DEPTH>
 __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw) {
   // wave-uniform index, so that the row bounds below are scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const uint64_t base = gp->nnz_base;
   const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
   const uint32_t clen = gp->clen;
-  if (clen > 0 && window_floats(clen, NRHS) <= a.win_floats) {
-    const int cmin = static_cast<int>(gp->cmin);
-    for (int t = threadIdx.x; t < static_cast<int>(clen); t += kGroupThreads) {
-      const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
-#pragma unroll
-      for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
-    }
-    __syncthreads();
-    wave_rows<VF, SM, NRHS, true>(a, base, r0, r1, xw, cmin);
-  } else {
-    wave_rows<VF, SM, NRHS, false>(a, base, r0, r1, xw, 0);
-  }
+  if (clen > 0 && window_floats(clen, NRHS) <= a.win_floats)
+    wave_rows<VF, SM, NRHS, true, DEPTH>(a, base, r0, r1, xw, static_cast<int>(gp->cmin), static_cast<int>(clen));
+  else
+    wave_rows<VF, SM, NRHS, false, DEPTH>(a, base, r0, r1, xw, 0, 0);
 }
 
-template <int VF, int SM, int NRHS>
+template <int VF, int SM, int NRHS, int DEPTH>
 __global__ __launch_bounds__(kGroupThreads) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
-  run_group<VF, SM, NRHS>(a, a.groups + blockIdx.x, xw);
+  run_group<VF, SM, NRHS, DEPTH>(a, a.groups + blockIdx.x, xw);
 }
 
 // Persistent form: workgroups walk a list of (item, group) pairs that may
 // belong to many matrices.
-template <int VF, int SM, int NRHS>
+template <int VF, int SM, int NRHS, int DEPTH>
 __global__ __launch_bounds__(kGroupThreads) void k_spmv_batched(const SpmvArgs* __restrict__ args,
                                                                 const WorkItem* __restrict__ work, int64_t n_work) {
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
     const WorkItem wi = work[w];
     const SpmvArgs a = args[wi.item];
-    run_group<VF, SM, NRHS>(a, a.groups + wi.group, xw);
+    run_group<VF, SM, NRHS, DEPTH>(a, a.groups + wi.group, xw);
     __syncthreads();  // the window is reused by the next group
+  }
+}
+
+// Units of a wave's rows kept in flight ahead of the one being computed:
+// DOSE_PREFETCH_DEPTH (1..3), default 1 (measured fastest on the clinical
+// beam: deeper rings cost registers without adding bandwidth).
+int prefetch_depth() {
+  static const int d = [] {
+    const char* e = std::getenv("DOSE_PREFETCH_DEPTH");
+    const int v = e ? std::atoi(e) : 1;
+    return v < 1 ? 1 : v > 3 ? 3 : v;
+  }();
+  return d;
+}
+
+template <int VF, int SM, int NRHS>
+void launch_depth(const SpmvArgs& a, size_t lds, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
+  switch (prefetch_depth()) {
+    case 1: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 1>), grid, block, lds, s, a); break;
+    case 3: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 3>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 2>), grid, block, lds, s, a); break;
+  }
+}
+
+template <int VF, int SM, int NRHS>
+void launch_depth_batched(const SpmvArgs* args, const WorkItem* work, int64_t n_work, int grid, size_t lds,
+                          hipStream_t s) {
+  const dim3 g(static_cast<unsigned>(grid)), block(kGroupThreads);
+  switch (prefetch_depth()) {
+    case 1: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 1>), g, block, lds, s, args, work, n_work); break;
+    case 3: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 3>), g, block, lds, s, args, work, n_work); break;
+    default: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 2>), g, block, lds, s, args, work, n_work); break;
   }
 }
 
 template <int VF, int SM>
 hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
   const size_t lds = static_cast<size_t>(a.win_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: hipLaunchKernelGGL((k_spmv<VF, SM, 1>), grid, block, lds, s, a); break;
-    case 2: hipLaunchKernelGGL((k_spmv<VF, SM, 2>), grid, block, lds, s, a); break;
-    case 4: hipLaunchKernelGGL((k_spmv<VF, SM, 4>), grid, block, lds, s, a); break;
+    case 1: launch_depth<VF, SM, 1>(a, lds, s); break;
+    case 2: launch_depth<VF, SM, 2>(a, lds, s); break;
+    case 4: launch_depth<VF, SM, 4>(a, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -408,12 +459,11 @@ hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
 template <int VF, int SM>
 hipError_t launch_rhs_batched(int n_rhs, const SpmvArgs* args, const WorkItem* work, int64_t n_work, int grid,
                               int lds_floats, hipStream_t s) {
-  const dim3 g(static_cast<unsigned>(grid)), block(kGroupThreads);
   const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: hipLaunchKernelGGL((k_spmv_batched<VF, SM, 1>), g, block, lds, s, args, work, n_work); break;
-    case 2: hipLaunchKernelGGL((k_spmv_batched<VF, SM, 2>), g, block, lds, s, args, work, n_work); break;
-    case 4: hipLaunchKernelGGL((k_spmv_batched<VF, SM, 4>), g, block, lds, s, args, work, n_work); break;
+    case 1: launch_depth_batched<VF, SM, 1>(args, work, n_work, grid, lds, s); break;
+    case 2: launch_depth_batched<VF, SM, 2>(args, work, n_work, grid, lds, s); break;
+    case 4: launch_depth_batched<VF, SM, 4>(args, work, n_work, grid, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
