@@ -438,7 +438,7 @@ void check_group_nnz(int32_t g) {
 // Default row-group size: large enough that staging a group's x window is a
 // small fraction of its stream, small enough for many groups per compute unit.
 int default_group_nnz(int64_t nnz) {
-  int g = 32768;
+  int g = 16384;
   while (g > 4096 && nnz / g < 256 * 8) g >>= 1;
   return g;
 }
