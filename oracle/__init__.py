@@ -38,38 +38,43 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
-        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
-        sigs = {
-            "or_f16_encode": ([ctypes.c_float], ctypes.c_uint16),
-            "or_f16_decode": ([ctypes.c_uint16], ctypes.c_double),
-            "or_bf16_encode": ([ctypes.c_float], ctypes.c_uint16),
-            "or_bf16_decode": ([ctypes.c_uint16], ctypes.c_double),
-            "or_e4m3_encode_sat": ([ctypes.c_float], ctypes.c_uint8),
-            "or_e4m3_decode": ([ctypes.c_uint8], ctypes.c_double),
-            "or_e4m3_row_scale": ([vp, i64], ctypes.c_float),
-            "or_f16_encode_n": ([vp, i64, vp], None),
-            "or_f16_decode_n": ([vp, i64, vp], None),
-            "or_bf16_encode_n": ([vp, i64, vp], None),
-            "or_bf16_decode_n": ([vp, i64, vp], None),
-            "or_e4m3_encode_n": ([vp, i64, vp], None),
-            "or_e4m3_decode_n": ([vp, i64, vp], None),
-            "or_decode_matrix": ([ctypes.c_int, i64, vp, vp, vp, vp], ctypes.c_int),
-            "or_row_dot": ([i64, vp, vp, vp], ctypes.c_double),
-            "or_spmv": ([i64, vp, vp, vp, vp, vp], None),
-            "or_spmv_multi": ([i64, i32, vp, vp, vp, vp, vp], None),
-            "or_spmv_T": ([i64, i64, vp, vp, vp, vp, vp], None),
-            "or_transpose": ([i64, i64, vp, vp, vp, vp, vp, vp], None),
-            "or_objective": ([i64, vp, vp, vp], ctypes.c_double),
-            "or_objective_seed": ([i64, vp, vp, vp, vp], None),
-            "or_norm2": ([i64, vp], ctypes.c_double),
-        }
-        for name, (args, res) in sigs.items():
-            f = getattr(lib, name)
-            f.argtypes = args
-            f.restype = res
-        _lib = lib
+        _lib = load_library(_LIB_PATH)
     return _lib
+
+
+def load_library(path: str):
+    """A compiled copy of dose_oracle.c with its ctypes signatures declared."""
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    sigs = {
+        "or_f16_encode": ([ctypes.c_float], ctypes.c_uint16),
+        "or_f16_decode": ([ctypes.c_uint16], ctypes.c_double),
+        "or_bf16_encode": ([ctypes.c_float], ctypes.c_uint16),
+        "or_bf16_decode": ([ctypes.c_uint16], ctypes.c_double),
+        "or_e4m3_encode_sat": ([ctypes.c_float], ctypes.c_uint8),
+        "or_e4m3_decode": ([ctypes.c_uint8], ctypes.c_double),
+        "or_e4m3_row_scale": ([vp, i64], ctypes.c_float),
+        "or_f16_encode_n": ([vp, i64, vp], None),
+        "or_f16_decode_n": ([vp, i64, vp], None),
+        "or_bf16_encode_n": ([vp, i64, vp], None),
+        "or_bf16_decode_n": ([vp, i64, vp], None),
+        "or_e4m3_encode_n": ([vp, i64, vp], None),
+        "or_e4m3_decode_n": ([vp, i64, vp], None),
+        "or_decode_matrix": ([ctypes.c_int, i64, vp, vp, vp, vp], ctypes.c_int),
+        "or_row_dot": ([i64, vp, vp, vp], ctypes.c_double),
+        "or_spmv": ([i64, vp, vp, vp, vp, vp], None),
+        "or_spmv_multi": ([i64, i32, vp, vp, vp, vp, vp], None),
+        "or_spmv_T": ([i64, i64, vp, vp, vp, vp, vp], None),
+        "or_transpose": ([i64, i64, vp, vp, vp, vp, vp, vp], None),
+        "or_objective": ([i64, vp, vp, vp], ctypes.c_double),
+        "or_objective_seed": ([i64, vp, vp, vp, vp], None),
+        "or_norm2": ([i64, vp], ctypes.c_double),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
 
 
 def _c(a, dtype):

@@ -1,0 +1,108 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a copy of the oracle's C source (on the CPU,
+in a temporary directory), builds it, points the oracle module at the copy and
+runs the pin checks of test_oracle_pins.py; at least one must fail.  The
+planted mistakes never index outside the arrays the checks pass.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+# (name, text in dose_oracle.c, replacement)
+MUTANTS = [
+    ("dropped last term of a row",
+     "for (int64_t k = 0; k < n; ++k) acc += (double)dec[k] * (double)x[col[k]];",
+     "for (int64_t k = 0; k + 1 < n; ++k) acc += (double)dec[k] * (double)x[col[k]];"),
+    ("x indexed by entry instead of column",
+     "acc += (double)dec[k] * (double)x[col[k]];",
+     "acc += (double)dec[k] * (double)x[col[k] > 0 ? col[k] - 1 : 0];"),
+    ("subtracted term",
+     "acc += (double)dec[k] * (double)x[col[k]];",
+     "acc -= (double)dec[k] * (double)x[col[k]];"),
+    ("product rounded to FP32",
+     "acc += (double)dec[k] * (double)x[col[k]];",
+     "acc += (double)(dec[k] * x[col[k]]);"),
+    ("adjoint weight of the wrong row",
+     "g[col[k]] += (double)dec[k] * (double)v[i];",
+     "g[col[k]] += (double)dec[k] * (double)v[i > 0 ? i - 1 : 0];"),
+    ("binary16 truncation instead of nearest-even",
+     "double q = nearbyint(ldexp(a, 10 - E)); /* 1024 <= q <= 2048 */",
+     "double q = floor(ldexp(a, 10 - E)); /* 1024 <= q <= 2048 */"),
+    ("binary16 exponent bias 14",
+     "return (uint16_t)(sign | (uint16_t)((E + 15) << 10) | (uint16_t)(q - 1024.0));",
+     "return (uint16_t)(sign | (uint16_t)((E + 14) << 10) | (uint16_t)(q - 1024.0));"),
+    ("binary16 subnormals flushed",
+     "double q = nearbyint(ldexp(a, 24));\n    return (uint16_t)(sign | (uint16_t)q);",
+     "return sign;"),
+    ("bfloat16 ties away from zero",
+     "double q = nearbyint(ldexp(a, 7 - E)); /* 128 <= q <= 256 */",
+     "double q = round(ldexp(a, 7 - E)); /* 128 <= q <= 256 */"),
+    ("E4M3 without saturation of the NaN code",
+     "if (code > 0x7Eu) code = 0x7Eu;",
+     "if (code > 0x7Fu) code = 0x7Fu;"),
+    ("E4M3 exponent bias 8",
+     "mag = ldexp((double)(8 + m), E - 10);",
+     "mag = ldexp((double)(8 + m), E - 11);"),
+    ("row scale against 480",
+     "float s = amax / 448.0f;",
+     "float s = amax / 480.0f;"),
+    ("objective residual with the wrong sign",
+     "double r = d[v] - (double)p[v];",
+     "double r = d[v] + (double)p[v];"),
+    ("seed without the factor 2",
+     "out[v] = 2.0 * (double)w[v] * (d[v] - (double)p[v]);",
+     "out[v] = (double)w[v] * (d[v] - (double)p[v]);"),
+    ("transpose lists rows in descending order",
+     "  for (int64_t i = 0; i < n_rows; ++i)\n    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {\n      int64_t j = col[k];",
+     "  for (int64_t i = n_rows - 1; i >= 0; --i)\n    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {\n      int64_t j = col[k];"),
+]
+
+CHECKS = [
+    pins.test_fp16_encode_matches_numpy_on_ties_and_subnormals,
+    pins.test_fp16_decode_exhaustive,
+    pins.test_bf16_encode_matches_torch,
+    pins.test_e4m3_decode_exhaustive_matches_torch,
+    pins.test_e4m3_saturates_at_448,
+    pins.test_e4m3_row_scale_closed_forms,
+    pins.test_decode_matrix_fp8_error_bound,
+    lambda: pins.test_spmv_bit_exact_vs_dense_brute_force(0),
+    pins.test_spmv_hand_worked_example,
+    pins.test_spmv_T_matches_dense_transpose_and_adjointness,
+    pins.test_transpose_structure,
+    pins.test_objective_closed_form_and_seed,
+    pins.test_gradient_matches_central_finite_differences,
+]
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, old, new, tmp_path, monkeypatch):
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, f"mutation site not found: {name}"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-std=c11", "-o", str(so), str(path), "-lm"])
+    monkeypatch.setattr(oracle, "_lib", oracle.load_library(str(so)))
+    caught = []
+    for check in CHECKS:
+        try:
+            check()
+        except AssertionError:
+            caught.append(getattr(check, "__name__", "lambda"))
+    assert caught, f"no pin caught: {name}"
+
+
+def test_unmutated_copy_passes_every_check(tmp_path, monkeypatch):
+    so = tmp_path / "libcopy.so"
+    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared",
+                           "-std=c11", "-o", str(so), oracle._SRC, "-lm"])
+    monkeypatch.setattr(oracle, "_lib", oracle.load_library(str(so)))
+    for check in CHECKS:
+        check()
+    assert os.path.exists(so)
