@@ -175,11 +175,11 @@ def main(argv=None):
                    "empty_row_frac": float(np.mean(np.diff(rp) == 0)),
                    "value_format": args.format, "index_format": "i32", "accumulate": "f32",
                    "group_nnz": info["group_nnz"], "n_groups": info["n_groups"],
-                   "n_groups_x_in_lds": info["n_groups_windowed"]},
+                   "n_groups_x_in_lds": info["n_groups_windowed"], "n_groups_split": info["n_groups_split"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": info["spmv_bytes"],
-                     "kernel": "k_spmv (row-block stream + LDS reduce) + k_combine (split rows)"},
+                     "kernel": f"k_spmv<{args.format}> (row groups, x window in LDS)"},
     }
 
     out["hbm_read_ceiling_GBps"] = round(hbm_read_ceiling(torch, dm), 1)
@@ -194,7 +194,8 @@ def main(argv=None):
                                "GBps_algorithmic": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
                                "frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                                "group_nnz_t": info["group_nnz_t"], "n_groups_t": info["n_groups_t"],
-                               "n_groups_t_x_in_lds": info["n_groups_windowed_t"]}
+                               "n_groups_t_x_in_lds": info["n_groups_windowed_t"],
+                               "n_groups_t_split": info["n_groups_split_t"]}
         p_h, w_h = dosegen.objective_masks(spec.nx, spec.ny, spec.nz)
         p, w = torch.from_numpy(p_h).cuda(), torch.from_numpy(w_h).cuda()
         seed = torch.empty_like(y)

@@ -100,6 +100,9 @@ typedef struct {
                                    offsets + n_rows*scale + 4*n_cols (x) +
                                    4*n_rows (y)                             */
   uint64_t adjoint_bytes;       /* the same for dose_spmv_adjoint on A^T     */
+  int64_t n_groups_split;       /* split groups of A: one long row whose
+                                   steps the four waves share               */
+  int64_t n_groups_split_t;     /* the same for A^T                          */
 } dose_matrix_info_t;
 
 /* Host-only check of a CSR matrix for a format: structure (row_ptr, column
@@ -206,9 +209,12 @@ dose_status dose_probe_stream_read(const void* buf, uint64_t bytes, float* sink,
 dose_status dose_probe_copy(const void* src, void* dst, uint64_t bytes, void* hip_stream);
 
 /* Host-only view of the row-group partition for a row_ptr and group size.
- * Writes up to `cap` groups, 5 int64 each, r0 <= r1 <= r2 <= r3 <= r4: the
- * group holds rows [r0, r4) and its wave w computes rows [r_w, r_(w+1)).
- * Returns the number of groups in *n_groups. */
+ * Writes up to `cap` groups, 6 int64 each: r0 <= r1 <= r2 <= r3 <= r4 and a
+ * split flag.  A group holds rows [r0, r4).  Without the flag its wave w
+ * computes rows [r_w, r_(w+1)); with it the group is the single row r0
+ * (r1 = ... = r4 = r0 + 1), longer than max(group_nnz / 4, 2048) entries,
+ * and its four waves share that row's steps.  Returns the number of groups
+ * in *n_groups. */
 dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t group_nnz,
                                    int64_t* groups, int64_t cap, int64_t* n_groups);
 

@@ -64,14 +64,15 @@ def csr_validate(row_ptr, cols, vals, n_cols, value_format: str = "fp16") -> int
 
 def partition_preview(row_ptr, group_nnz: int) -> np.ndarray:
     """Row groups the library builds for ``row_ptr`` (host only): one row per
-    group, [r0, r1, r2, r3, r4], the group holding rows [r0, r4) and its wave
-    w computing rows [r_w, r_(w+1))."""
+    group, [r0, r1, r2, r3, r4, split].  The group holds rows [r0, r4); its
+    wave w computes rows [r_w, r_(w+1)), unless ``split`` is 1: then the group
+    is the single long row r0 and its four waves share that row's steps."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     lib = _lib.load()
     n = ctypes.c_int64(0)
     _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, group_nnz, None, 0,
                                           ctypes.byref(n)))
-    out = np.zeros((max(n.value, 1), 5), np.int64)
+    out = np.zeros((max(n.value, 1), 6), np.int64)
     _lib.check(lib.dose_partition_preview(rp.ctypes.data, rp.size - 1, group_nnz,
                                           out.ctypes.data, n.value, ctypes.byref(n)))
     return out[:n.value]

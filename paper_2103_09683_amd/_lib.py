@@ -42,7 +42,8 @@ class MatrixInfo(ctypes.Structure):
                 ("group_nnz_t", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("n_groups_t", ctypes.c_int64), ("n_groups_windowed_t", ctypes.c_int64),
                 ("device_bytes", ctypes.c_uint64), ("spmv_bytes", ctypes.c_uint64),
-                ("adjoint_bytes", ctypes.c_uint64)]
+                ("adjoint_bytes", ctypes.c_uint64), ("n_groups_split", ctypes.c_int64),
+                ("n_groups_split_t", ctypes.c_int64)]
 
 
 class BatchItem(ctypes.Structure):

@@ -233,18 +233,28 @@ std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int gr
   std::vector<GroupDesc> G;
   G.reserve(static_cast<size_t>(rp[n_rows] / group_nnz + n_rows / kMaxGroupRows + 16));
   const int64_t kRowCost = 16;
+  // rows longer than one wave's share become split groups of their own
+  const int64_t long_row = std::max<int64_t>(group_nnz / kGroupWaves, kSplitMinNnz);
   int64_t r = 0;
   while (r < n_rows) {
     const int64_t start = r;
+    GroupDesc g{};
+    g.nnz_base = static_cast<uint64_t>(rp[start]);
+    if (rp[r + 1] - rp[r] > long_row) {
+      g.split = 1;
+      g.row[0] = static_cast<uint32_t>(r);
+      for (int w = 1; w <= kGroupWaves; ++w) g.row[w] = static_cast<uint32_t>(r + 1);
+      G.push_back(g);
+      ++r;
+      continue;
+    }
     int64_t nnz = 0;
     while (r < n_rows && r - start < kMaxGroupRows) {
       const int64_t l = rp[r + 1] - rp[r];
-      if (r > start && nnz + l > group_nnz) break;
+      if (l > long_row || (r > start && nnz + l > group_nnz)) break;
       nnz += l;
       ++r;
     }
-    GroupDesc g{};
-    g.nnz_base = static_cast<uint64_t>(rp[start]);
     const int64_t total = nnz + kRowCost * (r - start);
     int64_t q = start;
     g.row[0] = static_cast<uint32_t>(start);
@@ -266,7 +276,7 @@ struct Operand {
   DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
   DevBuf groups;
   int32_t group_nnz = 0;
-  int64_t n_groups = 0, n_windowed = 0;
+  int64_t n_groups = 0, n_windowed = 0, n_split = 0;
   int32_t win_floats[3] = {0, 0, 0};  // LDS window size for 1, 2 and 4 vectors
 
   uint64_t bytes() const { return val.bytes() + col.bytes() + row_ptr.bytes() + groups.bytes(); }
@@ -301,11 +311,12 @@ void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
   // LDS per workgroup: the largest window within the cap; groups with larger
   // windows read x from global memory
   const int64_t cap = window_cap_floats();
-  int64_t windowed = 0;
+  int64_t windowed = 0, split = 0;
   int64_t wf[3] = {0, 0, 0};
   const int rhs[3] = {1, 2, 4};
   for (const GroupDesc& g : G) {
     windowed += g.clen > 0 && window_floats(g.clen, 1) <= cap;
+    split += g.split;
     for (int i = 0; i < 3; ++i) {
       const int64_t f = window_floats(g.clen, rhs[i]);
       if (f <= cap) wf[i] = std::max(wf[i], f);
@@ -315,6 +326,7 @@ void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
   op.group_nnz = group_nnz;
   op.n_groups = static_cast<int64_t>(G.size());
   op.n_windowed = windowed;
+  op.n_split = split;
   for (int i = 0; i < 3; ++i) op.win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);
 }
 
@@ -641,8 +653,9 @@ dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32
     *n_groups = static_cast<int64_t>(G.size());
     for (int64_t i = 0; i < std::min<int64_t>(cap, *n_groups); ++i) {
       const GroupDesc& g = G[i];
-      int64_t* o = groups + i * (kGroupWaves + 1);
+      int64_t* o = groups + i * (kGroupWaves + 2);
       for (int w = 0; w <= kGroupWaves; ++w) o[w] = g.row[w];
+      o[kGroupWaves + 1] = g.split;
     }
   });
 }
@@ -744,6 +757,8 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
     info->spmv_bytes = A.nnz * per_nnz + (A.n_rows + 1) * 4 + A.n_rows * scale_b + 4 * A.n_cols + 4 * A.n_rows;
     // A^T reads the scale of A's rows through its columns: 4 B per column of A^T
+    info->n_groups_split = A.n_split;
+    info->n_groups_split_t = m->has_t ? m->AT.n_split : 0;
     info->adjoint_bytes = m->has_t ? A.nnz * per_nnz + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
   });
 }

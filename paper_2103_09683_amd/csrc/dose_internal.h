@@ -21,14 +21,29 @@ constexpr int64_t kMaxGroupRows = 16384;
 // inside the allocation.
 constexpr int64_t kStreamPad = 64;
 
-// One workgroup's work: a run of whole rows, split into one contiguous share
-// per wave, and the window of columns its entries touch.
+// Steps of a row (one step: 64 lanes x 8 entries) and how they are summed:
+// the lane sums of step s meet in a fixed wave reduction, giving T_s; the
+// row is (W_0 + W_1) + (W_2 + W_3) with W_j the in-order sum of the T_s with
+// s = j (mod 4).  The order depends only on the row, so a row summed by one
+// wave and a row shared by the four waves of a split group (wave j takes the
+// steps s = j mod 4) give the same bits.
+constexpr int kStepEntries = 64 * kChunk;
+constexpr int kRowSlots = 4;
+static_assert(kRowSlots == kGroupWaves, "a split row gives each wave one slot");
+// A row longer than max(group_nnz / 4, kSplitMinNnz) entries forms a split
+// group of its own.
+constexpr int64_t kSplitMinNnz = 4 * kStepEntries;
+
+// One workgroup's work, and the window of columns its entries touch.  Either
+// a run of whole rows split into one contiguous share per wave, or (split)
+// one long row shared by all waves.
 struct alignas(64) GroupDesc {
   uint64_t nnz_base;              // first entry of the group
-  uint32_t row[kGroupWaves + 1];  // wave w takes rows [row[w], row[w+1])
+  uint32_t row[kGroupWaves + 1];  // wave w takes rows [row[w], row[w+1]); split: the row is row[0]
   uint32_t cmin;                  // smallest column of the group's entries
   uint32_t clen;                  // largest minus smallest column plus 1 (0: no entries)
-  uint32_t pad[7];
+  uint32_t split;                 // 1: one row shared by all waves
+  uint32_t pad[6];
 };
 static_assert(sizeof(GroupDesc) == 64, "GroupDesc layout");
 

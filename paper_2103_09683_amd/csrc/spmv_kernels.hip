@@ -5,23 +5,26 @@
 // uses one 32-lane warp per row, Sec. III).  The gfx950 design:
 //
 //   * A workgroup (four wave64 waves) takes a *row group*: a run of whole rows
-//     holding about group_nnz entries.  Dose rows of neighbouring voxels touch
-//     a narrow range of spots, so the group's columns span a short window of
-//     x; the workgroup copies that window into LDS once and every gather is
-//     an LDS read.  A group whose window does not fit reads x from global
-//     memory instead (8 consecutive columns with two 16-byte loads).
-//   * Each wave owns a contiguous share of the group's rows and walks its
-//     non-empty rows (listed 64 at a time with a ballot; empty rows get +0
-//     with coalesced stores).  For a row, lane l takes the 8-entry chunks
-//     l, l+64, ... counted from the row's first entry rounded down to a
-//     multiple of 8, loading 8 codes with one 16-byte non-temporal load
-//     (8-byte for E4M3) and 8 column indices with two.
+//     holding about group_nnz entries, or one long row (a split group).  Dose
+//     rows of neighbouring voxels touch a narrow range of spots, so the
+//     group's columns span a short window of x; the workgroup copies that
+//     window into LDS once and every gather is an LDS read.  A group whose
+//     window does not fit reads x from global memory instead (8 consecutive
+//     columns with two 16-byte loads).
+//   * In a run of rows each wave owns a contiguous share of the rows and
+//     walks its non-empty rows (listed 64 at a time with a ballot; empty rows
+//     get +0 with coalesced stores).  A row is cut into steps of 64 chunks of
+//     8 entries, counted from its first entry rounded down to a multiple of
+//     8; lane l of step s loads chunk 64 s + l: 8 codes with one 16-byte
+//     non-temporal load (8-byte for E4M3) and 8 column indices with two.  In
+//     a split group wave j takes the steps s = j (mod 4) of the row.
 //   * Software pipelining: the loads of the wave's next (row, step) are
 //     issued before the current one is decoded and multiplied, so every wave
-//     keeps a row of loads in flight.
-//   * Summation order: a lane adds its chunk's 8 products pairwise, adds the
-//     chunk sums of its steps in order, and the 64 lane sums meet in a fixed
-//     xor tree.  The order depends only on the row's entries and alignment --
+//     keeps a step of loads in flight.
+//   * Summation order: a lane adds its chunk's 8 products pairwise; the 64
+//     lane sums of a step meet in a fixed DPP reduction (T_s); W_j adds the
+//     T_s with s = j (mod 4) in order, and the row is (W_0 + W_1) + (W_2 +
+//     W_3).  The order depends only on the row's entries and alignment --
 //     not on the partition, the launch or timing -- and nothing is atomic, so
 //     equal inputs give equal bits (Sec. II-D), and batched products equal
 //     plain ones bit for bit.
@@ -107,6 +110,7 @@ template <int VF>
 struct Chunk {
   Codes<VF> codes;
   uint4 ca, cb;
+  float sc;  // the row's scale (E4M3 A)
 };
 
 // LDS slot of window column t: one padding slot every 8 columns keeps the
@@ -157,11 +161,11 @@ __device__ __forceinline__ XVec<NRHS> load_x_window(const float* xw, int t) {
   return r;
 }
 
-// Sum of the 64 lanes in a fixed order, with DPP moves: within each row of 16
-// lanes, shifts by 1, 2, 4 and 8 leave the row's sum in its lane 15; two row
-// broadcasts then add rows 0..2 into lane 63.  Lanes shifted in from outside
-// a row (or from disabled rows) contribute 0.  Returns lane 63's value.
-__device__ __forceinline__ float wave_sum(float v) {
+// Sum of the 64 lanes in a fixed order, left in lane 63, with DPP moves:
+// within each row of 16 lanes, shifts by 1, 2, 4 and 8 leave the row's sum in
+// its lane 15; two row broadcasts then add rows 0..2 into lane 63.  Lanes
+// shifted in from outside a row (or from disabled rows) contribute 0.
+__device__ __forceinline__ float wave_reduce(float v) {
   constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 1, 0xf, 0xf, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 2, 0xf, 0xf, false));
@@ -169,7 +173,7 @@ __device__ __forceinline__ float wave_sum(float v) {
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 8, 0xf, 0xf, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowBcast15, 0xa, 0xf, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowBcast31, 0xc, 0xf, false));
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+  return v;
 }
 
 // Position of the wave in its rows: the current 64-row window of row offsets
@@ -189,6 +193,7 @@ struct Unit {
   uint64_t ks, ke;  // its entries [ks, ke)
   uint64_t ka;      // ks rounded down to a multiple of 8
   int step, nsteps;
+  int stride;       // steps between this wave's steps of the row (1, or 4 in a split group)
 };
 
 template <int NRHS>
@@ -210,191 +215,314 @@ __device__ __forceinline__ void load_window_rows(const SpmvArgs& a, RowCursor& r
   rc.mask = __ballot(in && hi > lo);
 }
 
-// Next unit after u (or the first one when u is not valid).
+// Moves the cursor to the next 64-row window of [.., r_end) that holds a
+// non-empty row (the current window when it still has one); returns false
+// at the end of the rows.  Empty rows passed on the way get +0.
 template <int NRHS>
-__device__ __forceinline__ Unit next_unit(const SpmvArgs& a, RowCursor& rc, const Unit& u, uint32_t r_end,
-                                          uint64_t base) {
-  Unit n = u;
-  if (u.valid && u.step + 1 < u.nsteps) {
-    n.step = u.step + 1;
-    return n;
-  }
-  const uint32_t base32 = static_cast<uint32_t>(base);
+__device__ __forceinline__ bool advance_window(const SpmvArgs& a, RowCursor& rc, uint32_t r_end, uint32_t base32) {
   while (rc.mask == 0) {
     const uint32_t wb = rc.wb + kWave;
-    if (wb >= r_end) {
-      n.valid = false;
-      return n;
-    }
+    if (wb >= r_end) return false;
     load_window_rows<NRHS>(a, rc, wb, r_end, base32);
+  }
+  return true;
+}
+
+// Next unit after u (or the first one when u is not valid) within the
+// cursor's current window; not valid when the window is done.  A row's units
+// for this wave are its steps first, first + stride, ...; a wave with no
+// step in a row (first >= its step count, possible only for the one row of a
+// split group) gets no unit.
+__device__ __forceinline__ Unit next_unit(RowCursor& rc, const Unit& u, uint64_t base, int first, int stride) {
+  Unit n = u;
+  if (u.valid && u.step + u.stride < u.nsteps) {
+    n.step = u.step + u.stride;
+    return n;
+  }
+  if (rc.mask == 0) {
+    n.valid = false;
+    return n;
   }
   const int i = __builtin_ctzll(rc.mask);
   rc.mask &= rc.mask - 1;
-  n.valid = true;
   n.row = rc.wb + static_cast<uint32_t>(i);
   n.ks = base + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(rc.lo), i));
   n.ke = base + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(rc.hi), i));
   n.ka = n.ks & ~static_cast<uint64_t>(kChunk - 1);
-  n.step = 0;
-  n.nsteps = static_cast<int>((n.ke - n.ka + kChunk * kWave - 1) / (kChunk * kWave));
+  n.nsteps = static_cast<int>((n.ke - n.ka + kStepEntries - 1) / kStepEntries);
+  n.step = first;
+  n.stride = stride;
+  n.valid = first < n.nsteps;
   return n;
 }
 
-template <int VF>
+// Vector memory instructions complete in issue order for the wait counter, so
+// the loop below issues a fixed set of loads per unit, outside any branch:
+// lanes past the row's end re-read the row's first chunk, and an invalid unit
+// (past the wave's last row) reads chunk 0 of the stream.  The compiler can
+// then wait for exactly the unit being computed while the next one streams.
+template <int VF, int SM>
 __device__ __forceinline__ void load_unit(const SpmvArgs& a, const Unit& u, Chunk<VF>& ch) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
-  if (k0 < u.ke) {
-    ch.codes.load(a.val, k0);
-    ch.ca = ld_nt4(a.col + k0);
-    ch.cb = ld_nt4(a.col + k0 + 4);
+  const uint64_t k = !u.valid ? 0 : k0 < u.ke ? k0 : u.ka;
+  ch.codes.load(a.val, k);
+  ch.ca = ld_nt4(a.col + k);
+  ch.cb = ld_nt4(a.col + k + 4);
+  if constexpr (SM == kScaleRow) ch.sc = a.scale[u.valid ? u.row : 0];
+}
+
+template <int NRHS>
+struct Gathered {
+  XVec<NRHS> x[kChunk];
+  float sc[kChunk];  // column scales (kScaleCol)
+};
+
+__device__ __forceinline__ void chunk_cols(const uint4& ca, const uint4& cb, int (&cols)[kChunk]) {
+  cols[0] = static_cast<int>(ca.x), cols[1] = static_cast<int>(ca.y), cols[2] = static_cast<int>(ca.z);
+  cols[3] = static_cast<int>(ca.w), cols[4] = static_cast<int>(cb.x), cols[5] = static_cast<int>(cb.y);
+  cols[6] = static_cast<int>(cb.z), cols[7] = static_cast<int>(cb.w);
+}
+
+// Global-memory gathers of a unit (x without a window, column scales of an
+// E4M3 A^T).  Issued before the next unit's loads, so that waiting for them
+// leaves those loads in flight.
+template <int VF, int SM, int NRHS, bool WIN>
+__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Unit& u, const Chunk<VF>& ch,
+                                              Gathered<NRHS>& g) {
+  int cols[kChunk];
+  chunk_cols(ch.ca, ch.cb, cols);
+  if constexpr (!WIN) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
+    const bool full = u.valid && k0 >= u.ks && k0 + kChunk <= u.ke;
+    if (NRHS == 1 && full && cols[7] - cols[0] == kChunk - 1) {
+      // a run of 8 consecutive columns: two 16-byte loads of x
+      const float4 x0 = *reinterpret_cast<const float4*>(a.x + cols[0]);
+      const float4 x1 = *reinterpret_cast<const float4*>(a.x + cols[0] + 4);
+      g.x[0].v[0] = x0.x, g.x[1].v[0] = x0.y, g.x[2].v[0] = x0.z, g.x[3].v[0] = x0.w;
+      g.x[4].v[0] = x1.x, g.x[5].v[0] = x1.y, g.x[6].v[0] = x1.z, g.x[7].v[0] = x1.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_global<NRHS>(a.x, cols[e]);
+    }
+  }
+  if constexpr (SM == kScaleCol) {
+#pragma unroll
+    for (int e = 0; e < kChunk; ++e) g.sc[e] = a.scale[cols[e]];
   }
 }
 
-// Products of one chunk, summed pairwise, added to the lane's accumulators.
+// The lane's chunk of one unit: its products, summed pairwise (0 for a lane
+// past the row's end).  Every entry of the chunk is decoded and multiplied,
+// also those of neighbouring rows (their columns are valid indices; window
+// positions are clamped into the window), and the products outside the row
+// are replaced by 0 afterwards: no branches, and no Inf or NaN of x leaks in.
 template <int VF, int SM, int NRHS, bool WIN>
-__device__ __forceinline__ void compute_unit(const SpmvArgs& a, const Unit& u, const Chunk<VF>& ch, const float* xw,
-                                             int cmin, int clen, float* acc) {
+__device__ __forceinline__ void compute_unit(const Unit& u, const Chunk<VF>& ch, Gathered<NRHS>& g, const float* xw,
+                                             int cmin, int clen, float* c) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
-  if (k0 >= u.ke) return;
-  // entries e of the chunk with lo <= e < hi belong to the row
-  const int lo = k0 >= u.ks ? 0 : static_cast<int>(u.ks - k0);
+  // entries e of the chunk with lo <= e < hi belong to the row; a unit past
+  // the wave's last one contributes nothing
+  const bool live = u.valid && k0 < u.ke;
+  const int lo = !live ? kChunk : k0 >= u.ks ? 0 : static_cast<int>(u.ks - k0);
   const int hi = u.ke - k0 >= kChunk ? kChunk : static_cast<int>(u.ke - k0);
-  const int cols[kChunk] = {static_cast<int>(ch.ca.x), static_cast<int>(ch.ca.y), static_cast<int>(ch.ca.z),
-                            static_cast<int>(ch.ca.w), static_cast<int>(ch.cb.x), static_cast<int>(ch.cb.y),
-                            static_cast<int>(ch.cb.z), static_cast<int>(ch.cb.w)};
-  // Every entry of the chunk is decoded and multiplied, also those of the
-  // neighbouring rows (their columns are valid indices; window positions are
-  // clamped into the window), and the products outside the row are replaced
-  // by 0 afterwards: no branches, and no Inf or NaN of x leaks in.
-  XVec<NRHS> xv[kChunk];
-  if (!WIN && NRHS == 1 && lo == 0 && hi == kChunk && cols[7] - cols[0] == kChunk - 1) {
-    // a run of 8 consecutive columns: two 16-byte loads of x
-    const float4 x0 = *reinterpret_cast<const float4*>(a.x + cols[0]);
-    const float4 x1 = *reinterpret_cast<const float4*>(a.x + cols[0] + 4);
-    xv[0].v[0] = x0.x, xv[1].v[0] = x0.y, xv[2].v[0] = x0.z, xv[3].v[0] = x0.w;
-    xv[4].v[0] = x1.x, xv[5].v[0] = x1.y, xv[6].v[0] = x1.z, xv[7].v[0] = x1.w;
-  } else {
+  if constexpr (WIN) {
+    int cols[kChunk];
+    chunk_cols(ch.ca, ch.cb, cols);
 #pragma unroll
-    for (int e = 0; e < kChunk; ++e) {
-      if constexpr (WIN) {
-        const int t = min(max(cols[e] - cmin, 0), clen - 1);
-        xv[e] = load_x_window<NRHS>(xw, t);
-      } else {
-        xv[e] = load_x_global<NRHS>(a.x, cols[e]);
-      }
-    }
+    for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_window<NRHS>(xw, min(max(cols[e] - cmin, 0), clen - 1));
   }
   float p[kChunk][NRHS];
 #pragma unroll
   for (int e = 0; e < kChunk; ++e) {
     const bool in = e >= lo && e < hi;
     float d = ch.codes.get(e);
-    if constexpr (SM == kScaleCol) d = d * a.scale[cols[e]];
+    if constexpr (SM == kScaleCol) d = d * g.sc[e];
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) p[e][q] = in ? d * xv[e].v[q] : 0.0f;
+    for (int q = 0; q < NRHS; ++q) p[e][q] = in ? d * g.x[e].v[q] : 0.0f;
   }
 #pragma unroll
   for (int q = 0; q < NRHS; ++q)
-    acc[q] += ((p[0][q] + p[1][q]) + (p[2][q] + p[3][q])) + ((p[4][q] + p[5][q]) + (p[6][q] + p[7][q]));
+    c[q] = ((p[0][q] + p[1][q]) + (p[2][q] + p[3][q])) + ((p[4][q] + p[5][q]) + (p[6][q] + p[7][q]));
 }
 
+// Row value from its four slot sums (valid in lane 63), times the row scale
+// of an E4M3 operand.
 template <int SM, int NRHS>
-__device__ __forceinline__ void finish_row(const SpmvArgs& a, const Unit& u, float* acc) {
-  const int lane = threadIdx.x & (kWave - 1);
-  float tot[NRHS];
+__device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float sc, const float (&tot)[NRHS]) {
+  float* dst = a.y + static_cast<int64_t>(row) * NRHS;
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q) {
-    tot[q] = wave_sum(acc[q]);
-    acc[q] = 0.0f;
-  }
-  if (lane == 0) {
-    const int64_t row = u.row;
-    float* dst = a.y + row * NRHS;
-    if constexpr (SM == kScaleRow) {
-      const float sc = a.scale[row];
-#pragma unroll
-      for (int q = 0; q < NRHS; ++q) dst[q] = tot[q] * sc;
-    } else {
-#pragma unroll
-      for (int q = 0; q < NRHS; ++q) dst[q] = tot[q];
-    }
-  }
+  for (int q = 0; q < NRHS; ++q) dst[q] = SM == kScaleRow ? tot[q] * sc : tot[q];
 }
+
+// Columns of the x window one thread stages with loads issued together.
+constexpr int kWinBatch = 8;
 
 // One wave's rows [r_begin, r_end) of a group whose entries start at `base`,
-// with the loads of the next DEPTH units in flight while a unit is computed.
-// With WIN the workgroup first copies the x window [cmin, cmin + clen) into
-// LDS; every wave issues its first loads before that copy and its barrier,
-// so the copy's latency hides behind the stream.  All waves reach the
-// barrier, also those without rows.
-template <int VF, int SM, int NRHS, bool WIN, int DEPTH>
+// taking steps first, first + stride, ... of each row, with the loads of the
+// next DEPTH units in flight while a unit is computed.  With WIN the
+// workgroup first copies the x window [cmin, cmin + clen) into LDS: its
+// loads go out with the wave's row offsets, the first units' loads follow,
+// and the barrier comes last, so one memory round trip starts the group.
+// All waves reach the barrier, also those without rows.  Without SPLIT each
+// finished row is stored; with SPLIT (one row, this wave's steps only) the
+// wave's slot sum is left in `tot` and the row scale in `sc`.
+template <int VF, int SM, int NRHS, bool WIN, int DEPTH, bool SPLIT>
 __device__ __forceinline__ void wave_rows(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
-                                          float* xw, int cmin, int clen) {
+                                          int first, float* xw, int cmin, int clen, float (&tot)[NRHS], float& sc) {
+  const int stride = SPLIT ? kRowSlots : 1;
+  const uint32_t base32 = static_cast<uint32_t>(base);
   RowCursor rc;
-  Unit us[DEPTH + 1];
+  rc.mask = 0;
+  Unit us[DEPTH + 1] = {};
   Chunk<VF> cs[DEPTH + 1];
 #pragma unroll
-  for (int d = 0; d <= DEPTH; ++d) us[d].valid = false;
-  if (r_begin < r_end) {
-    load_window_rows<NRHS>(a, rc, r_begin, r_end, static_cast<uint32_t>(base));
-    us[0] = next_unit<NRHS>(a, rc, us[0], r_end, base);
-    if (us[0].valid) load_unit<VF>(a, us[0], cs[0]);
-#pragma unroll
-    for (int d = 1; d < DEPTH; ++d)
-      if (us[d - 1].valid) {
-        us[d] = next_unit<NRHS>(a, rc, us[d - 1], r_end, base);
-        if (us[d].valid) load_unit<VF>(a, us[d], cs[d]);
-      }
-  }
+  for (int q = 0; q < NRHS; ++q) tot[q] = 0.0f;
+  sc = 1.0f;
+  XVec<NRHS> wv[kWinBatch];
   if constexpr (WIN) {
-    for (int t = threadIdx.x; t < clen; t += kGroupThreads) {
-      const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
 #pragma unroll
-      for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
-    }
-    __syncthreads();
+    for (int j = 0; j < kWinBatch; ++j)
+      wv[j] = load_x_global<NRHS>(a.x, cmin + min(j * kGroupThreads + static_cast<int>(threadIdx.x), clen - 1));
   }
-  if (!us[0].valid) return;
-  float acc[NRHS];
+  bool rows = false;
+  if (r_begin < r_end) {
+    load_window_rows<NRHS>(a, rc, r_begin, r_end, base32);
+    rows = advance_window<NRHS>(a, rc, r_end, base32);
+  }
+  // slot sums W_j of the current row (meaningful in lane 63)
+  float W[kRowSlots][NRHS];
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q) acc[q] = 0.0f;
+  for (int j = 0; j < kRowSlots; ++j)
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) W[j][q] = 0.0f;
+  // Row windows: the first DEPTH units of a window are loaded, then a ring of
+  // DEPTH + 1 units streams the rest of the window.  Only unit loads (and
+  // gathers) are issued inside the ring, in a fixed number per unit, so the
+  // compiler waits for exactly the unit being computed.
+  bool first_window = true;
   while (true) {
-    if (us[DEPTH - 1].valid) {
-      us[DEPTH] = next_unit<NRHS>(a, rc, us[DEPTH - 1], r_end, base);
-      if (us[DEPTH].valid) load_unit<VF>(a, us[DEPTH], cs[DEPTH]);
-    } else {
-      us[DEPTH].valid = false;
-    }
-    compute_unit<VF, SM, NRHS, WIN>(a, us[0], cs[0], xw, cmin, clen, acc);
-    if (us[0].step + 1 == us[0].nsteps) finish_row<SM, NRHS>(a, us[0], acc);
-    if (!us[1].valid) break;
+    us[0] = next_unit(rc, Unit{}, base, first, stride);
+    load_unit<VF, SM>(a, us[0], cs[0]);
 #pragma unroll
-    for (int d = 0; d < DEPTH; ++d) {
-      us[d] = us[d + 1];
-      cs[d] = cs[d + 1];
+    for (int d = 1; d < DEPTH; ++d) {
+      us[d] = us[d - 1].valid ? next_unit(rc, us[d - 1], base, first, stride) : Unit{};
+      load_unit<VF, SM>(a, us[d], cs[d]);
     }
+    if (first_window) {
+      first_window = false;
+      if constexpr (WIN) {
+        // the window: its first batch arrived with the row offsets
+#pragma unroll
+        for (int j = 0; j < kWinBatch; ++j) {
+          const int t = j * kGroupThreads + static_cast<int>(threadIdx.x);
+          if (t < clen)
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = wv[j].v[q];
+        }
+        for (int t = kWinBatch * kGroupThreads + static_cast<int>(threadIdx.x); t < clen; t += kGroupThreads) {
+          const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
+#pragma unroll
+          for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
+        }
+        __syncthreads();
+      }
+    }
+    if (!us[0].valid) return;
+    // The ring is unrolled, so that every buffer index is a constant and no
+    // loaded register is copied (a copy would have to wait for its load),
+    // and it is left at one place only, so that the compiler's view of the
+    // loads in flight stays exact.
+    while (true) {
+#pragma unroll
+      for (int ph = 0; ph <= DEPTH; ++ph) {
+        const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1), prev = (ph + DEPTH - 1) % (DEPTH + 1);
+        us[nxt] = us[prev].valid ? next_unit(rc, us[prev], base, first, stride) : Unit{};
+        Gathered<NRHS> g;
+        gather_global<VF, SM, NRHS, WIN>(a, us[cur], cs[cur], g);
+        load_unit<VF, SM>(a, us[nxt], cs[nxt]);
+        // keep the scheduler from sinking the loads below the compute
+        __builtin_amdgcn_sched_barrier(0);
+        float c[NRHS];
+        compute_unit<VF, SM, NRHS, WIN>(us[cur], cs[cur], g, xw, cmin, clen, c);
+        const int slot = us[cur].step & (kRowSlots - 1);
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) {
+          const float t = wave_reduce(c[q]);
+#pragma unroll
+          for (int j = 0; j < kRowSlots; ++j) W[j][q] += j == slot ? t : 0.0f;
+        }
+        if (us[cur].valid && us[cur].step + us[cur].stride >= us[cur].nsteps) {
+          // this wave's last step of the row; slots that received nothing
+          // hold +0, and no slot sum is ever -0, so adding them changes nothing
+#pragma unroll
+          for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
+          if constexpr (SM == kScaleRow) sc = cs[cur].sc;
+          if constexpr (!SPLIT) {
+            if ((threadIdx.x & (kWave - 1)) == kWave - 1) store_row<SM, NRHS>(a, us[cur].row, sc, tot);
+#pragma unroll
+            for (int j = 0; j < kRowSlots; ++j)
+#pragma unroll
+              for (int q = 0; q < NRHS; ++q) W[j][q] = 0.0f;
+          }
+        }
+      }
+      // one exit per turn of the ring: a unit past the end in a middle phase
+      // adds 0 and stores nothing
+      if (!us[0].valid) break;
+    }
+    // drain the last (unused) loads, so that the next window's ring starts
+    // with nothing outstanding (vmcnt 0; expcnt and lgkmcnt left alone)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    if (!rows || !advance_window<NRHS>(a, rc, r_end, base32)) return;
   }
 }
 
+// One group on one workgroup.  `part` is LDS for the four slot sums of a
+// split row.
 template <int VF, int SM, int NRHS, int DEPTH>
-__device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw) {
+__device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw, float* part) {
   // wave-uniform index, so that the row bounds below are scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const uint64_t base = gp->nnz_base;
-  const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
   const uint32_t clen = gp->clen;
-  if (clen > 0 && window_floats(clen, NRHS) <= a.win_floats)
-    wave_rows<VF, SM, NRHS, true, DEPTH>(a, base, r0, r1, xw, static_cast<int>(gp->cmin), static_cast<int>(clen));
+  const bool win = clen > 0 && window_floats(clen, NRHS) <= a.win_floats;
+  const int cmin = win ? static_cast<int>(gp->cmin) : 0;
+  float tot[NRHS], sc;
+  if (gp->split == 0) {
+    const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
+    if (win)
+      wave_rows<VF, SM, NRHS, true, DEPTH, false>(a, base, r0, r1, 0, xw, cmin, static_cast<int>(clen), tot, sc);
+    else
+      wave_rows<VF, SM, NRHS, false, DEPTH, false>(a, base, r0, r1, 0, xw, 0, 0, tot, sc);
+    return;
+  }
+  const uint32_t row = gp->row[0];
+  if (win)
+    wave_rows<VF, SM, NRHS, true, DEPTH, true>(a, base, row, row + 1, wave, xw, cmin, static_cast<int>(clen), tot,
+                                               sc);
   else
-    wave_rows<VF, SM, NRHS, false, DEPTH>(a, base, r0, r1, xw, 0, 0);
+    wave_rows<VF, SM, NRHS, false, DEPTH, true>(a, base, row, row + 1, wave, xw, 0, 0, tot, sc);
+  if ((threadIdx.x & (kWave - 1)) == kWave - 1)
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r[NRHS];
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q)
+      r[q] = (part[0 * NRHS + q] + part[1 * NRHS + q]) + (part[2 * NRHS + q] + part[3 * NRHS + q]);
+    store_row<SM, NRHS>(a, row, SM == kScaleRow ? a.scale[row] : 1.0f, r);
+  }
 }
 
 template <int VF, int SM, int NRHS, int DEPTH>
 __global__ __launch_bounds__(kGroupThreads) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
-  run_group<VF, SM, NRHS, DEPTH>(a, a.groups + blockIdx.x, xw);
+  __shared__ float part[kGroupWaves * NRHS];
+  run_group<VF, SM, NRHS, DEPTH>(a, a.groups + blockIdx.x, xw, part);
 }
 
 // Persistent form: workgroups walk a list of (item, group) pairs that may
@@ -403,22 +531,23 @@ template <int VF, int SM, int NRHS, int DEPTH>
 __global__ __launch_bounds__(kGroupThreads) void k_spmv_batched(const SpmvArgs* __restrict__ args,
                                                                 const WorkItem* __restrict__ work, int64_t n_work) {
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
+  __shared__ float part[kGroupWaves * NRHS];
   for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
     const WorkItem wi = work[w];
     const SpmvArgs a = args[wi.item];
-    run_group<VF, SM, NRHS, DEPTH>(a, a.groups + wi.group, xw);
-    __syncthreads();  // the window is reused by the next group
+    run_group<VF, SM, NRHS, DEPTH>(a, a.groups + wi.group, xw, part);
+    __syncthreads();  // the window and the slot sums are reused by the next group
   }
 }
 
 // Units of a wave's rows kept in flight ahead of the one being computed:
-// DOSE_PREFETCH_DEPTH (1..3), default 1 (measured fastest on the clinical
+// DOSE_PREFETCH_DEPTH (1 or 2), default 1 (measured fastest on the clinical
 // beam: deeper rings cost registers without adding bandwidth).
 int prefetch_depth() {
   static const int d = [] {
     const char* e = std::getenv("DOSE_PREFETCH_DEPTH");
     const int v = e ? std::atoi(e) : 1;
-    return v < 1 ? 1 : v > 3 ? 3 : v;
+    return v < 2 ? 1 : 2;
   }();
   return d;
 }
@@ -428,7 +557,6 @@ void launch_depth(const SpmvArgs& a, size_t lds, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
   switch (prefetch_depth()) {
     case 1: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 1>), grid, block, lds, s, a); break;
-    case 3: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 3>), grid, block, lds, s, a); break;
     default: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 2>), grid, block, lds, s, a); break;
   }
 }
@@ -439,7 +567,6 @@ void launch_depth_batched(const SpmvArgs* args, const WorkItem* work, int64_t n_
   const dim3 g(static_cast<unsigned>(grid)), block(kGroupThreads);
   switch (prefetch_depth()) {
     case 1: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 1>), g, block, lds, s, args, work, n_work); break;
-    case 3: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 3>), g, block, lds, s, args, work, n_work); break;
     default: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 2>), g, block, lds, s, args, work, n_work); break;
   }
 }

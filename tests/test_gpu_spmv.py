@@ -106,15 +106,41 @@ def test_partitions_long_rows_and_ragged_tail(fmt, dev):
     rp, cols, vals = _csr_from_lens(rng, lens, 20000, signed=True)
     x = rng.uniform(-1, 1, 20000).astype(np.float32)
     A = dm.DoseMatrix(rp, cols, vals, 20000, fmt)
-    ys = []
+    ys, splits = [], []
     for group_nnz in (1024, 4096, 32768, 1 << 20):
         _say("partition", fmt, group_nnz, rp[-1])
         A.set_partition(group_nnz)
         assert A.info()["group_nnz"] == group_nnz
+        splits.append(A.info()["n_groups_split"])
         ys.append(_check_forward(A, rp, cols, vals, fmt, x)[0])
+    # the long rows are split groups (shared by four waves) or one wave's rows
+    assert splits == [3, 3, 2, 0]
     for y in ys[1:]:
         np.testing.assert_array_equal(_bits(y), _bits(ys[0]))
     A.close()
+
+
+def test_rows_across_many_row_windows(dev):
+    """A wave lists its rows 64 at a time; with short rows and large groups
+    each wave walks many such windows, and the first non-empty row of every
+    window must start from a clean sum (regression: a finished window once
+    leaked its last step into the next window's first row)."""
+    rng = np.random.default_rng(13)
+    lens = rng.integers(1, 40, size=40000)
+    lens[rng.random(lens.size) < 0.5] = 0
+    lens[64::64] = 7   # a non-empty row at many window starts
+    rp, cols, vals = _csr_from_lens(rng, lens, 3000)
+    x = rng.uniform(0, 1, 3000).astype(np.float32)
+    for fmt in FORMATS:
+        A = dm.DoseMatrix(rp, cols, vals, 3000, fmt)
+        ys = []
+        for group_nnz in (1024, 65536, 1 << 20):
+            _say("row windows", fmt, group_nnz)
+            A.set_partition(group_nnz)
+            ys.append(_check_forward(A, rp, cols, vals, fmt, x)[0])
+        for y in ys[1:]:
+            np.testing.assert_array_equal(_bits(y), _bits(ys[0]))
+        A.close()
 
 
 def test_window_and_global_gathers_agree(dev):

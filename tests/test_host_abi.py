@@ -109,20 +109,30 @@ def _random_row_ptr(rng, n_rows, long_rows=()):
 @pytest.mark.parametrize("group_nnz", [1024, 4096, 32768, 1 << 20])
 def test_partition_groups_tile_the_rows(group_nnz):
     rng = np.random.default_rng(group_nnz)
-    rp = _random_row_ptr(rng, 50000, long_rows=[(7, 30000), (4000, 8193), (49999, 100000)])
+    rp = _random_row_ptr(rng, 50000, long_rows=[(7, 30000), (4000, 8193), (4001, 2049), (49999, 100000)])
     G = dm.partition_preview(rp, group_nnz)
+    assert G.shape[1] == 6
     assert G[0, 0] == 0 and G[-1, 4] == rp.size - 1
     assert np.all(G[1:, 0] == G[:-1, 4]), "groups must tile the rows in order"
-    assert np.all(np.diff(G, axis=1) >= 0)
-    for r0, r1, r2, r3, r4 in G:
+    assert np.all(np.diff(G[:, :5], axis=1) >= 0)
+    long_row = max(group_nnz // 4, 2048)
+    lens = np.diff(rp)
+    for r0, r1, r2, r3, r4, split in G:
         nnz = rp[r4] - rp[r0]
         assert 1 <= r4 - r0 <= 16384
-        # a group exceeds group_nnz only when it is a single row
-        assert nnz <= group_nnz or r4 - r0 == 1
+        if split:
+            # a split group is one row, longer than a wave's share
+            assert r4 == r0 + 1 and r1 == r2 == r3 == r4
+            assert lens[r0] > long_row
+            continue
+        assert np.all(lens[r0:r4] <= long_row), "long rows must form split groups"
+        assert nnz <= group_nnz
         # wave shares balance entries + 16 per row, up to one row's cost
         cost = [(rp[b] - rp[a]) + 16 * (b - a) for a, b in ((r0, r1), (r1, r2), (r2, r3), (r3, r4))]
         biggest_row = max((rp[i + 1] - rp[i]) + 16 for i in range(r0, r4))
         assert max(cost) - min(cost) <= 2 * biggest_row + (nnz + 16 * (r4 - r0)) // 4 + 1
+    n_split = int(G[:, 5].sum())
+    assert n_split == int(np.sum(lens > long_row))
 
 
 def test_partition_is_deterministic():
@@ -132,7 +142,7 @@ def test_partition_is_deterministic():
 
 
 def test_partition_empty_inputs():
-    assert dm.partition_preview(np.array([0], np.int64), 1024).shape == (0, 5)
+    assert dm.partition_preview(np.array([0], np.int64), 1024).shape == (0, 6)
     G = dm.partition_preview(np.zeros(40001, np.int64), 1024)
     assert (G[:, 4] - G[:, 0]).tolist() == [16384, 16384, 7232]
 
