@@ -1,7 +1,7 @@
 // SpMV kernels of libdose for gfx950 (CDNA4, wave64).
 //
 // The product is Listing 1 of the paper: y_i = sum over row i's stored
-// entries of data[k] * x[col[k]], one wavefront reducing each row (the paper
+// entries of data[k] * x[col[k]], a wavefront reducing each row (the paper
 // uses one 32-lane warp per row, Sec. III).  The gfx950 design:
 //
 //   * A workgroup (four wave64 waves) takes a *row group*: a run of whole rows
@@ -11,23 +11,22 @@
 //     window into LDS once and every gather is an LDS read.  A group whose
 //     window does not fit reads x from global memory instead (8 consecutive
 //     columns with two 16-byte loads).
-//   * In a run of rows each wave owns a contiguous share of the rows and
-//     walks its non-empty rows (listed 64 at a time with a ballot; empty rows
-//     get +0 with coalesced stores).  A row is cut into steps of 64 chunks of
-//     8 entries, counted from its first entry rounded down to a multiple of
-//     8; lane l of step s loads chunk 64 s + l: 8 codes with one 16-byte
-//     non-temporal load (8-byte for E4M3) and 8 column indices with two.  In
-//     a split group wave j takes the steps s = j (mod 4) of the row.
-//   * Software pipelining: the loads of the wave's next (row, step) are
-//     issued before the current one is decoded and multiplied, so every wave
-//     keeps a step of loads in flight.
-//   * Summation order: a lane adds its chunk's 8 products pairwise; the 64
-//     lane sums of a step meet in a fixed DPP reduction (T_s); W_j adds the
-//     T_s with s = j (mod 4) in order, and the row is (W_0 + W_1) + (W_2 +
-//     W_3).  The order depends only on the row's entries and alignment --
-//     not on the partition, the launch or timing -- and nothing is atomic, so
-//     equal inputs give equal bits (Sec. II-D), and batched products equal
-//     plain ones bit for bit.
+//   * Each wave owns a contiguous share of the group's rows and streams its
+//     entries in *steps* of 512 entries on absolute multiples of 512: lane l
+//     of a step loads the 8-entry chunk 8 l of it, 8 codes with one 16-byte
+//     non-temporal load (8-byte for E4M3) and 8 column indices with two.  Every
+//     entry is loaded once, whatever the row lengths, and the loads of the
+//     next steps are in flight while one is computed.  In a split group wave j
+//     takes the steps j, j+4, ... of the row.
+//   * The rows that meet a step take their entries from it: a lane adds its
+//     chunk's products of the row pairwise, the 64 lane sums meet in a fixed
+//     DPP reduction (T_s), W_j adds the T_s of the row's steps s with
+//     (s - first step of the row) = j (mod 4) in order, and the row is
+//     (W_0 + W_1) + (W_2 + W_3).  The order depends only on the row's entries
+//     and their absolute positions -- not on the partition, the launch or
+//     timing -- and nothing is atomic, so equal inputs give equal bits
+//     (Sec. II-D), a split row equals the same row summed by one wave, and
+//     batched products equal plain ones bit for bit.
 #include "dose_internal.h"
 
 #include <hip/hip_fp16.h>
@@ -176,100 +175,93 @@ __device__ __forceinline__ float wave_reduce(float v) {
   return v;
 }
 
-// Position of the wave in its rows: the current 64-row window of row offsets
-// (lane l holds row wb+l's [lo, hi) relative to the group's first entry) and
-// the non-empty rows of the window not yet started.
+// Positions.  A group's entries are addressed by their position P relative
+// to the group's origin, its first entry rounded down to a multiple of 512:
+// step k of the group covers positions [512 k, 512 k + 512) and lane l of
+// the step the chunk [512 k + 8 l, 512 k + 8 l + 8), so steps and chunks sit
+// on absolute multiples of 512 and 8 entries, whatever the partition.  A
+// group spans fewer than 2^31 - 512 positions.
+
+// The current 64-row window of the wave's rows (lane l: row wb + l's
+// positions [lo, hi)) and its non-empty rows not yet started.
 struct RowCursor {
   uint32_t wb;
   uint64_t mask;
-  uint32_t lo, hi;
+  int lo, hi;
 };
 
-// The streamed unit of work: one step (up to 64 chunks) of one row.  All
-// fields are wave-uniform.
-struct Unit {
-  bool valid;
-  uint32_t row;     // the row
-  uint64_t ks, ke;  // its entries [ks, ke)
-  uint64_t ka;      // ks rounded down to a multiple of 8
-  int step, nsteps;
-  int stride;       // steps between this wave's steps of the row (1, or 4 in a split group)
-};
-
-template <int NRHS>
-__device__ __forceinline__ void load_window_rows(const SpmvArgs& a, RowCursor& rc, uint32_t wb, uint32_t r_end,
-                                                 uint32_t base32) {
+// Row offsets of the 64-row window at wb.  Issued for every lane (rows past
+// r_end re-read the last row), so their number is fixed; r_end > wb.
+__device__ __forceinline__ void fetch_rows(const SpmvArgs& a, RowCursor& rc, uint32_t wb, uint32_t r_end,
+                                           uint32_t origin32) {
   const int lane = threadIdx.x & (kWave - 1);
-  const uint32_t r = wb + lane;
+  const uint32_t r = min(wb + lane, r_end - 1);
+  rc.wb = wb;
+  rc.lo = static_cast<int>(a.row_ptr[r] - origin32);
+  rc.hi = static_cast<int>(a.row_ptr[r + 1] - origin32);
+}
+
+// Lists the fetched window's non-empty rows and writes +0 to its empty ones.
+template <int NRHS>
+__device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, uint32_t r_end) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t r = rc.wb + lane;
   const bool in = r < r_end;
-  const uint32_t lo = in ? a.row_ptr[r] - base32 : 0u;
-  const uint32_t hi = in ? a.row_ptr[r + 1] - base32 : 0u;
-  if (in && hi == lo) {
+  if (in && rc.hi == rc.lo) {
     float* dst = a.y + static_cast<int64_t>(r) * NRHS;
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) dst[q] = 0.0f;
   }
-  rc.wb = wb;
-  rc.lo = lo;
-  rc.hi = hi;
-  rc.mask = __ballot(in && hi > lo);
+  rc.mask = __ballot(in && rc.hi > rc.lo);
 }
 
-// Moves the cursor to the next 64-row window of [.., r_end) that holds a
-// non-empty row (the current window when it still has one); returns false
-// at the end of the rows.  Empty rows passed on the way get +0.
+// The row being summed (wave-uniform): its positions [ks, ke) and its steps
+// kfirst .. klast.
+struct Row {
+  uint32_t row;
+  int ks, ke;
+  int kfirst, klast;
+  bool valid;
+};
+
+// The wave's next non-empty row, moving on to later 64-row windows (and
+// writing +0 to the empty rows passed) when the current one is done.
 template <int NRHS>
-__device__ __forceinline__ bool advance_window(const SpmvArgs& a, RowCursor& rc, uint32_t r_end, uint32_t base32) {
+__device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32_t r_end, uint32_t origin32) {
+  Row n;
   while (rc.mask == 0) {
     const uint32_t wb = rc.wb + kWave;
-    if (wb >= r_end) return false;
-    load_window_rows<NRHS>(a, rc, wb, r_end, base32);
-  }
-  return true;
-}
-
-// Next unit after u (or the first one when u is not valid) within the
-// cursor's current window; not valid when the window is done.  A row's units
-// for this wave are its steps first, first + stride, ...; a wave with no
-// step in a row (first >= its step count, possible only for the one row of a
-// split group) gets no unit.
-__device__ __forceinline__ Unit next_unit(RowCursor& rc, const Unit& u, uint64_t base, int first, int stride) {
-  Unit n = u;
-  if (u.valid && u.step + u.stride < u.nsteps) {
-    n.step = u.step + u.stride;
-    return n;
-  }
-  if (rc.mask == 0) {
-    n.valid = false;
-    return n;
+    if (wb >= r_end) {
+      n.valid = false;
+      return n;
+    }
+    fetch_rows(a, rc, wb, r_end, origin32);
+    settle_rows<NRHS>(a, rc, r_end);
   }
   const int i = __builtin_ctzll(rc.mask);
   rc.mask &= rc.mask - 1;
   n.row = rc.wb + static_cast<uint32_t>(i);
-  n.ks = base + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(rc.lo), i));
-  n.ke = base + static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(rc.hi), i));
-  n.ka = n.ks & ~static_cast<uint64_t>(kChunk - 1);
-  n.nsteps = static_cast<int>((n.ke - n.ka + kStepEntries - 1) / kStepEntries);
-  n.step = first;
-  n.stride = stride;
-  n.valid = first < n.nsteps;
+  n.ks = __builtin_amdgcn_readlane(rc.lo, i);
+  n.ke = __builtin_amdgcn_readlane(rc.hi, i);
+  n.kfirst = n.ks >> 9;
+  n.klast = (n.ke - 1) >> 9;
+  n.valid = true;
   return n;
 }
 
-// Vector memory instructions complete in issue order for the wait counter, so
-// the loop below issues a fixed set of loads per unit, outside any branch:
-// lanes past the row's end re-read the row's first chunk, and an invalid unit
-// (past the wave's last row) reads chunk 0 of the stream.  The compiler can
-// then wait for exactly the unit being computed while the next one streams.
+// One lane's chunk of one step: 8 codes and 8 column indices.
 template <int VF, int SM>
-__device__ __forceinline__ void load_unit(const SpmvArgs& a, const Unit& u, Chunk<VF>& ch) {
+__device__ __forceinline__ void load_step(const SpmvArgs& a, uint64_t origin, int k, int pmin, int pmax,
+                                          Chunk<VF>& ch) {
+  // Always issued (a fixed number of loads per step keeps the compiler's
+  // wait counts exact): chunks outside the wave's entries re-read the
+  // nearest chunk inside them.
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
-  const uint64_t k = !u.valid ? 0 : k0 < u.ke ? k0 : u.ka;
-  ch.codes.load(a.val, k);
-  ch.ca = ld_nt4(a.col + k);
-  ch.cb = ld_nt4(a.col + k + 4);
-  if constexpr (SM == kScaleRow) ch.sc = a.scale[u.valid ? u.row : 0];
+  const int p = min(max(k * kStepEntries + lane * kChunk, pmin), pmax);
+  const uint64_t e = origin + static_cast<uint64_t>(p);
+  ch.codes.load(a.val, e);
+  ch.ca = ld_nt4(a.col + e);
+  ch.cb = ld_nt4(a.col + e + 4);
 }
 
 template <int NRHS>
@@ -284,20 +276,16 @@ __device__ __forceinline__ void chunk_cols(const uint4& ca, const uint4& cb, int
   cols[6] = static_cast<int>(cb.z), cols[7] = static_cast<int>(cb.w);
 }
 
-// Global-memory gathers of a unit (x without a window, column scales of an
-// E4M3 A^T).  Issued before the next unit's loads, so that waiting for them
+// Global-memory gathers of a step (x without a window, column scales of an
+// E4M3 A^T), issued before the next step's loads, so that waiting for them
 // leaves those loads in flight.
 template <int VF, int SM, int NRHS, bool WIN>
-__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Unit& u, const Chunk<VF>& ch,
-                                              Gathered<NRHS>& g) {
+__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF>& ch, Gathered<NRHS>& g) {
   int cols[kChunk];
   chunk_cols(ch.ca, ch.cb, cols);
   if constexpr (!WIN) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
-    const bool full = u.valid && k0 >= u.ks && k0 + kChunk <= u.ke;
-    if (NRHS == 1 && full && cols[7] - cols[0] == kChunk - 1) {
-      // a run of 8 consecutive columns: two 16-byte loads of x
+    if (NRHS == 1 && cols[7] - cols[0] == kChunk - 1) {
+      // 8 consecutive columns (the chunk lies inside one row): two 16-byte loads of x
       const float4 x0 = *reinterpret_cast<const float4*>(a.x + cols[0]);
       const float4 x1 = *reinterpret_cast<const float4*>(a.x + cols[0] + 4);
       g.x[0].v[0] = x0.x, g.x[1].v[0] = x0.y, g.x[2].v[0] = x0.z, g.x[3].v[0] = x0.w;
@@ -313,39 +301,41 @@ __device__ __forceinline__ void gather_global(const SpmvArgs& a, const Unit& u, 
   }
 }
 
-// The lane's chunk of one unit: its products, summed pairwise (0 for a lane
-// past the row's end).  Every entry of the chunk is decoded and multiplied,
-// also those of neighbouring rows (their columns are valid indices; window
-// positions are clamped into the window), and the products outside the row
-// are replaced by 0 afterwards: no branches, and no Inf or NaN of x leaks in.
+// The 8 products of the lane's chunk.  Every entry is decoded and
+// multiplied, also those outside the wave's rows (their columns are valid
+// indices; window positions are clamped into the window); rows take only
+// their own entries afterwards, so no Inf or NaN of x leaks in.
 template <int VF, int SM, int NRHS, bool WIN>
-__device__ __forceinline__ void compute_unit(const Unit& u, const Chunk<VF>& ch, Gathered<NRHS>& g, const float* xw,
-                                             int cmin, int clen, float* c) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t k0 = u.ka + static_cast<uint64_t>(u.step * kWave + lane) * kChunk;
-  // entries e of the chunk with lo <= e < hi belong to the row; a unit past
-  // the wave's last one contributes nothing
-  const bool live = u.valid && k0 < u.ke;
-  const int lo = !live ? kChunk : k0 >= u.ks ? 0 : static_cast<int>(u.ks - k0);
-  const int hi = u.ke - k0 >= kChunk ? kChunk : static_cast<int>(u.ke - k0);
+__device__ __forceinline__ void products(const Chunk<VF>& ch, Gathered<NRHS>& g, const float* xw, int cmin, int clen,
+                                         float (&p)[kChunk][NRHS]) {
   if constexpr (WIN) {
     int cols[kChunk];
     chunk_cols(ch.ca, ch.cb, cols);
 #pragma unroll
     for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_window<NRHS>(xw, min(max(cols[e] - cmin, 0), clen - 1));
   }
-  float p[kChunk][NRHS];
 #pragma unroll
   for (int e = 0; e < kChunk; ++e) {
-    const bool in = e >= lo && e < hi;
     float d = ch.codes.get(e);
     if constexpr (SM == kScaleCol) d = d * g.sc[e];
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) p[e][q] = in ? d * g.x[e].v[q] : 0.0f;
+    for (int q = 0; q < NRHS; ++q) p[e][q] = d * g.x[e].v[q];
   }
+}
+
+// Lane sum of the chunk entries at positions [ks, ke), pairwise over the 8
+// entries (entries outside count as 0).
+template <int NRHS>
+__device__ __forceinline__ void chunk_sum(const float (&p)[kChunk][NRHS], int pn, int ks, int ke, float (&c)[NRHS]) {
+  const int lo = min(max(ks - pn, 0), kChunk), hi = min(max(ke - pn, 0), kChunk);
+  float m[kChunk][NRHS];
+#pragma unroll
+  for (int e = 0; e < kChunk; ++e)
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) m[e][q] = e >= lo && e < hi ? p[e][q] : 0.0f;
 #pragma unroll
   for (int q = 0; q < NRHS; ++q)
-    c[q] = ((p[0][q] + p[1][q]) + (p[2][q] + p[3][q])) + ((p[4][q] + p[5][q]) + (p[6][q] + p[7][q]));
+    c[q] = ((m[0][q] + m[1][q]) + (m[2][q] + m[3][q])) + ((m[4][q] + m[5][q]) + (m[6][q] + m[7][q]));
 }
 
 // Row value from its four slot sums (valid in lane 63), times the row scale
@@ -357,126 +347,109 @@ __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float
   for (int q = 0; q < NRHS; ++q) dst[q] = SM == kScaleRow ? tot[q] * sc : tot[q];
 }
 
-// Columns of the x window one thread stages with loads issued together.
-constexpr int kWinBatch = 8;
-
-// One wave's rows [r_begin, r_end) of a group whose entries start at `base`,
-// taking steps first, first + stride, ... of each row, with the loads of the
-// next DEPTH units in flight while a unit is computed.  With WIN the
-// workgroup first copies the x window [cmin, cmin + clen) into LDS: its
-// loads go out with the wave's row offsets, the first units' loads follow,
-// and the barrier comes last, so one memory round trip starts the group.
-// All waves reach the barrier, also those without rows.  Without SPLIT each
-// finished row is stored; with SPLIT (one row, this wave's steps only) the
-// wave's slot sum is left in `tot` and the row scale in `sc`.
+// One wave's share of a group: rows [r_begin, r_end), or with SPLIT the one
+// row r_begin whose steps first, first + 4, ... this wave takes.  The wave
+// streams its entries step by step with the next DEPTH steps' loads in
+// flight (a ring of DEPTH + 1 chunk buffers, unrolled so that no loaded
+// register is copied, left at one place only so that the compiler's view of
+// the loads in flight stays exact).  In each step the rows that meet it take
+// their entries: the masked lane sums meet in the fixed DPP reduction (T) and
+// T is added to the row's slot (step - first step of the row) mod 4; a row
+// ends with (W_0 + W_1) + (W_2 + W_3).  With WIN the workgroup first copies
+// the x window [cmin, cmin + clen) into LDS: every wave issues its first
+// loads before that copy and its barrier.  All waves reach the barrier.
+// Without SPLIT each finished row is stored; with SPLIT the wave's slot sum
+// is left in `tot` and the row scale in `sc`.
 template <int VF, int SM, int NRHS, bool WIN, int DEPTH, bool SPLIT>
-__device__ __forceinline__ void wave_rows(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
-                                          int first, float* xw, int cmin, int clen, float (&tot)[NRHS], float& sc) {
-  const int stride = SPLIT ? kRowSlots : 1;
-  const uint32_t base32 = static_cast<uint32_t>(base);
-  RowCursor rc;
-  rc.mask = 0;
-  Unit us[DEPTH + 1] = {};
-  Chunk<VF> cs[DEPTH + 1];
+__device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
+                                            int first, float* xw, int cmin, int clen, float (&tot)[NRHS], float& sc) {
+  constexpr int stride = SPLIT ? kRowSlots : 1;
+  const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
+  const uint32_t origin32 = static_cast<uint32_t>(origin);
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) tot[q] = 0.0f;
   sc = 1.0f;
-  XVec<NRHS> wv[kWinBatch];
-  if constexpr (WIN) {
-#pragma unroll
-    for (int j = 0; j < kWinBatch; ++j)
-      wv[j] = load_x_global<NRHS>(a.x, cmin + min(j * kGroupThreads + static_cast<int>(threadIdx.x), clen - 1));
-  }
-  bool rows = false;
+  // the wave's positions [p0, p1), its steps and its first row
+  int p0 = 0, p1 = 0;
+  RowCursor rc;
+  rc.mask = 0;
+  Row cr;
+  cr.valid = false;
   if (r_begin < r_end) {
-    load_window_rows<NRHS>(a, rc, r_begin, r_end, base32);
-    rows = advance_window<NRHS>(a, rc, r_end, base32);
+    p0 = static_cast<int>(a.row_ptr[r_begin] - origin32);
+    p1 = static_cast<int>(a.row_ptr[r_end] - origin32);
+    fetch_rows(a, rc, r_begin, r_end, origin32);
+    settle_rows<NRHS>(a, rc, r_end);
+    rc.wb = r_begin;
+    // next_row moves on from rc.wb + 64 once the first window is done
+    cr = next_row<NRHS>(a, rc, r_end, origin32);
   }
-  // slot sums W_j of the current row (meaningful in lane 63)
+  const int pmin = p0 & ~(kChunk - 1), pmax = max(p1 - 1, p0) & ~(kChunk - 1);
+  const int kbeg = (p0 >> 9) + (SPLIT ? first : 0);
+  const int kend = p1 > p0 ? (p1 - 1) >> 9 : -1;  // the wave's last step (inclusive)
+  Chunk<VF> cs[DEPTH + 1];
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load_step<VF, SM>(a, origin, kbeg + d * stride, pmin, pmax, cs[d]);
+  if constexpr (WIN) {
+    for (int t = threadIdx.x; t < clen; t += kGroupThreads) {
+      const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
+    }
+    __syncthreads();
+  }
+  if (!cr.valid || kbeg > kend) return;
+  const int lane = threadIdx.x & (kWave - 1);
   float W[kRowSlots][NRHS];
 #pragma unroll
-  for (int j = 0; j < kRowSlots; ++j)
+  for (int s = 0; s < kRowSlots; ++s)
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) W[j][q] = 0.0f;
-  // Row windows: the first DEPTH units of a window are loaded, then a ring of
-  // DEPTH + 1 units streams the rest of the window.  Only unit loads (and
-  // gathers) are issued inside the ring, in a fixed number per unit, so the
-  // compiler waits for exactly the unit being computed.
-  bool first_window = true;
+    for (int q = 0; q < NRHS; ++q) W[s][q] = 0.0f;
+  int k = kbeg;
   while (true) {
-    us[0] = next_unit(rc, Unit{}, base, first, stride);
-    load_unit<VF, SM>(a, us[0], cs[0]);
 #pragma unroll
-    for (int d = 1; d < DEPTH; ++d) {
-      us[d] = us[d - 1].valid ? next_unit(rc, us[d - 1], base, first, stride) : Unit{};
-      load_unit<VF, SM>(a, us[d], cs[d]);
-    }
-    if (first_window) {
-      first_window = false;
-      if constexpr (WIN) {
-        // the window: its first batch arrived with the row offsets
-#pragma unroll
-        for (int j = 0; j < kWinBatch; ++j) {
-          const int t = j * kGroupThreads + static_cast<int>(threadIdx.x);
-          if (t < clen)
-#pragma unroll
-            for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = wv[j].v[q];
-        }
-        for (int t = kWinBatch * kGroupThreads + static_cast<int>(threadIdx.x); t < clen; t += kGroupThreads) {
-          const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
-#pragma unroll
-          for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
-        }
-        __syncthreads();
-      }
-    }
-    if (!us[0].valid) return;
-    // The ring is unrolled, so that every buffer index is a constant and no
-    // loaded register is copied (a copy would have to wait for its load),
-    // and it is left at one place only, so that the compiler's view of the
-    // loads in flight stays exact.
-    while (true) {
-#pragma unroll
-      for (int ph = 0; ph <= DEPTH; ++ph) {
-        const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1), prev = (ph + DEPTH - 1) % (DEPTH + 1);
-        us[nxt] = us[prev].valid ? next_unit(rc, us[prev], base, first, stride) : Unit{};
-        Gathered<NRHS> g;
-        gather_global<VF, SM, NRHS, WIN>(a, us[cur], cs[cur], g);
-        load_unit<VF, SM>(a, us[nxt], cs[nxt]);
-        // keep the scheduler from sinking the loads below the compute
-        __builtin_amdgcn_sched_barrier(0);
+    for (int ph = 0; ph <= DEPTH; ++ph) {
+      const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
+      Gathered<NRHS> g;
+      gather_global<VF, SM, NRHS, WIN>(a, cs[cur], g);
+      load_step<VF, SM>(a, origin, k + DEPTH * stride, pmin, pmax, cs[nxt]);
+      // keep the scheduler from sinking the loads below the compute
+      __builtin_amdgcn_sched_barrier(0);
+      float p[kChunk][NRHS];
+      products<VF, SM, NRHS, WIN>(cs[cur], g, xw, cmin, clen, p);
+      const int pn = k * kStepEntries + lane * kChunk;
+      // the rows that meet step k (none once the wave is past its last step)
+      while (k <= kend && cr.valid && cr.ks < (k + 1) * kStepEntries) {
         float c[NRHS];
-        compute_unit<VF, SM, NRHS, WIN>(us[cur], cs[cur], g, xw, cmin, clen, c);
-        const int slot = us[cur].step & (kRowSlots - 1);
+        chunk_sum<NRHS>(p, pn, cr.ks, cr.ke, c);
+        const int slot = (k - cr.kfirst) & (kRowSlots - 1);
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) {
           const float t = wave_reduce(c[q]);
 #pragma unroll
-          for (int j = 0; j < kRowSlots; ++j) W[j][q] += j == slot ? t : 0.0f;
+          for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : 0.0f;
         }
-        if (us[cur].valid && us[cur].step + us[cur].stride >= us[cur].nsteps) {
-          // this wave's last step of the row; slots that received nothing
-          // hold +0, and no slot sum is ever -0, so adding them changes nothing
+        if (k + stride <= cr.klast) break;  // the row goes on in a later step of this wave
+        // the wave's last step of the row; slots that received nothing hold
+        // +0, and no slot sum is ever -0, so adding them changes nothing
 #pragma unroll
-          for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
-          if constexpr (SM == kScaleRow) sc = cs[cur].sc;
-          if constexpr (!SPLIT) {
-            if ((threadIdx.x & (kWave - 1)) == kWave - 1) store_row<SM, NRHS>(a, us[cur].row, sc, tot);
+        for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
+        if constexpr (SM == kScaleRow) sc = a.scale[cr.row];
+        if constexpr (SPLIT) {
+          cr.valid = false;
+        } else {
+          if (lane == kWave - 1) store_row<SM, NRHS>(a, cr.row, sc, tot);
 #pragma unroll
-            for (int j = 0; j < kRowSlots; ++j)
+          for (int s = 0; s < kRowSlots; ++s)
 #pragma unroll
-              for (int q = 0; q < NRHS; ++q) W[j][q] = 0.0f;
-          }
+            for (int q = 0; q < NRHS; ++q) W[s][q] = 0.0f;
+          cr = next_row<NRHS>(a, rc, r_end, origin32);
         }
       }
-      // one exit per turn of the ring: a unit past the end in a middle phase
-      // adds 0 and stores nothing
-      if (!us[0].valid) break;
+      k += stride;
     }
-    // drain the last (unused) loads, so that the next window's ring starts
-    // with nothing outstanding (vmcnt 0; expcnt and lgkmcnt left alone)
-    __builtin_amdgcn_s_waitcnt(0x0F70);
-    if (!rows || !advance_window<NRHS>(a, rc, r_end, base32)) return;
+    // one exit per turn of the ring: steps past the wave's last one do nothing
+    if (k > kend) break;
   }
 }
 
@@ -494,17 +467,17 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
   if (gp->split == 0) {
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
     if (win)
-      wave_rows<VF, SM, NRHS, true, DEPTH, false>(a, base, r0, r1, 0, xw, cmin, static_cast<int>(clen), tot, sc);
+      wave_stream<VF, SM, NRHS, true, DEPTH, false>(a, base, r0, r1, 0, xw, cmin, static_cast<int>(clen), tot, sc);
     else
-      wave_rows<VF, SM, NRHS, false, DEPTH, false>(a, base, r0, r1, 0, xw, 0, 0, tot, sc);
+      wave_stream<VF, SM, NRHS, false, DEPTH, false>(a, base, r0, r1, 0, xw, 0, 0, tot, sc);
     return;
   }
   const uint32_t row = gp->row[0];
   if (win)
-    wave_rows<VF, SM, NRHS, true, DEPTH, true>(a, base, row, row + 1, wave, xw, cmin, static_cast<int>(clen), tot,
-                                               sc);
+    wave_stream<VF, SM, NRHS, true, DEPTH, true>(a, base, row, row + 1, wave, xw, cmin, static_cast<int>(clen), tot,
+                                                 sc);
   else
-    wave_rows<VF, SM, NRHS, false, DEPTH, true>(a, base, row, row + 1, wave, xw, 0, 0, tot, sc);
+    wave_stream<VF, SM, NRHS, false, DEPTH, true>(a, base, row, row + 1, wave, xw, 0, 0, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
