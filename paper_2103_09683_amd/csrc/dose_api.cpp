@@ -244,6 +244,7 @@ std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int gr
       g.split = 1;
       g.row[0] = static_cast<uint32_t>(r);
       for (int w = 1; w <= kGroupWaves; ++w) g.row[w] = static_cast<uint32_t>(r + 1);
+      for (int w = 0; w < kGroupWaves; ++w) g.ent[w] = static_cast<uint32_t>(rp[r + 1] - rp[r]);
       G.push_back(g);
       ++r;
       continue;
@@ -264,6 +265,7 @@ std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int gr
       g.row[w] = static_cast<uint32_t>(q);
     }
     g.row[kGroupWaves] = static_cast<uint32_t>(r);
+    for (int w = 0; w < kGroupWaves; ++w) g.ent[w] = static_cast<uint32_t>(rp[g.row[w + 1]] - rp[start]);
     G.push_back(g);
   }
   return G;

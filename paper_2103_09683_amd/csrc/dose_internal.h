@@ -43,7 +43,8 @@ struct alignas(64) GroupDesc {
   uint32_t cmin;                  // smallest column of the group's entries
   uint32_t clen;                  // largest minus smallest column plus 1 (0: no entries)
   uint32_t split;                 // 1: one row shared by all waves
-  uint32_t pad[6];
+  uint32_t ent[kGroupWaves];      // wave w's entries end at nnz_base + ent[w] (split: ent[3] is the row's length)
+  uint32_t pad[2];
 };
 static_assert(sizeof(GroupDesc) == 64, "GroupDesc layout");
 

@@ -50,6 +50,9 @@ __device__ __forceinline__ uint2 ld_nt2(const void* p) {
   const u32x2 v = __builtin_nontemporal_load(static_cast<const u32x2*>(p));
   return make_uint2(v.x, v.y);
 }
+__device__ __forceinline__ uint32_t ld_nt1(const void* p) {
+  return __builtin_nontemporal_load(static_cast<const uint32_t*>(p));
+}
 
 // ----------------------------------------------------------------- decoding
 __device__ __forceinline__ float dec_fp16(uint32_t h) {
@@ -73,8 +76,10 @@ struct Codes;
 template <>
 struct Codes<kFp16> {
   uint4 w;
-  __device__ __forceinline__ void load(const void* base, uint64_t k0) {
-    w = ld_nt4(static_cast<const uint16_t*>(base) + k0);
+  // entries 0..3 from k1, 4..7 from k2
+  __device__ __forceinline__ void load(const void* base, uint64_t k1, uint64_t k2) {
+    const uint2 h1 = ld_nt2(static_cast<const uint16_t*>(base) + k1), h2 = ld_nt2(static_cast<const uint16_t*>(base) + k2);
+    w = make_uint4(h1.x, h1.y, h2.x, h2.y);
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
@@ -84,8 +89,10 @@ struct Codes<kFp16> {
 template <>
 struct Codes<kBf16> {
   uint4 w;
-  __device__ __forceinline__ void load(const void* base, uint64_t k0) {
-    w = ld_nt4(static_cast<const uint16_t*>(base) + k0);
+  // entries 0..3 from k1, 4..7 from k2
+  __device__ __forceinline__ void load(const void* base, uint64_t k1, uint64_t k2) {
+    const uint2 h1 = ld_nt2(static_cast<const uint16_t*>(base) + k1), h2 = ld_nt2(static_cast<const uint16_t*>(base) + k2);
+    w = make_uint4(h1.x, h1.y, h2.x, h2.y);
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
@@ -95,8 +102,9 @@ struct Codes<kBf16> {
 template <>
 struct Codes<kFp8> {
   uint2 w;
-  __device__ __forceinline__ void load(const void* base, uint64_t k0) {
-    w = ld_nt2(static_cast<const uint8_t*>(base) + k0);
+  // entries 0..3 from k1, 4..7 from k2
+  __device__ __forceinline__ void load(const void* base, uint64_t k1, uint64_t k2) {
+    w = make_uint2(ld_nt1(static_cast<const uint8_t*>(base) + k1), ld_nt1(static_cast<const uint8_t*>(base) + k2));
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 4 ? w.x : w.y;
@@ -104,7 +112,8 @@ struct Codes<kFp8> {
   }
 };
 
-// One lane's share of one (row, step): a chunk of 8 codes and 8 columns.
+// One lane's share of one step: 8 codes and 8 columns, entries 4 l .. 4 l + 3
+// and 256 + 4 l .. 256 + 4 l + 3 of the step for lane l.
 template <int VF>
 struct Chunk {
   Codes<VF> codes;
@@ -249,19 +258,27 @@ __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32
   return n;
 }
 
-// One lane's chunk of one step: 8 codes and 8 column indices.
+// Positions of lane l's two quarter-chunks in step k: every load instruction
+// of a step reads one contiguous range (4 entries per lane), so each cache
+// line is requested once.
+constexpr int kQuarter = kChunk / 2;
+__device__ __forceinline__ int quarter_pos(int k, int lane, int half) {
+  return k * kStepEntries + half * (kStepEntries / 2) + lane * kQuarter;
+}
+
+// One lane's entries of one step: 8 codes and 8 column indices.
 template <int VF, int SM>
 __device__ __forceinline__ void load_step(const SpmvArgs& a, uint64_t origin, int k, int pmin, int pmax,
                                           Chunk<VF>& ch) {
   // Always issued (a fixed number of loads per step keeps the compiler's
-  // wait counts exact): chunks outside the wave's entries re-read the
-  // nearest chunk inside them.
+  // wait counts exact): quarters outside the wave's entries re-read the
+  // nearest quarter inside them.
   const int lane = threadIdx.x & (kWave - 1);
-  const int p = min(max(k * kStepEntries + lane * kChunk, pmin), pmax);
-  const uint64_t e = origin + static_cast<uint64_t>(p);
-  ch.codes.load(a.val, e);
-  ch.ca = ld_nt4(a.col + e);
-  ch.cb = ld_nt4(a.col + e + 4);
+  const uint64_t e1 = origin + static_cast<uint64_t>(min(max(quarter_pos(k, lane, 0), pmin), pmax));
+  const uint64_t e2 = origin + static_cast<uint64_t>(min(max(quarter_pos(k, lane, 1), pmin), pmax));
+  ch.codes.load(a.val, e1, e2);
+  ch.ca = ld_nt4(a.col + e1);
+  ch.cb = ld_nt4(a.col + e2);
 }
 
 template <int NRHS>
@@ -284,15 +301,17 @@ __device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF>
   int cols[kChunk];
   chunk_cols(ch.ca, ch.cb, cols);
   if constexpr (!WIN) {
-    if (NRHS == 1 && cols[7] - cols[0] == kChunk - 1) {
-      // 8 consecutive columns (the chunk lies inside one row): two 16-byte loads of x
-      const float4 x0 = *reinterpret_cast<const float4*>(a.x + cols[0]);
-      const float4 x1 = *reinterpret_cast<const float4*>(a.x + cols[0] + 4);
-      g.x[0].v[0] = x0.x, g.x[1].v[0] = x0.y, g.x[2].v[0] = x0.z, g.x[3].v[0] = x0.w;
-      g.x[4].v[0] = x1.x, g.x[5].v[0] = x1.y, g.x[6].v[0] = x1.z, g.x[7].v[0] = x1.w;
-    } else {
 #pragma unroll
-      for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_global<NRHS>(a.x, cols[e]);
+    for (int h = 0; h < 2; ++h) {
+      const int e0 = h * kQuarter;
+      if (NRHS == 1 && cols[e0 + 3] - cols[e0] == kQuarter - 1) {
+        // 4 consecutive columns (inside one row): one 16-byte load of x
+        const float4 v = *reinterpret_cast<const float4*>(a.x + cols[e0]);
+        g.x[e0].v[0] = v.x, g.x[e0 + 1].v[0] = v.y, g.x[e0 + 2].v[0] = v.z, g.x[e0 + 3].v[0] = v.w;
+      } else {
+#pragma unroll
+        for (int e = e0; e < e0 + kQuarter; ++e) g.x[e] = load_x_global<NRHS>(a.x, cols[e]);
+      }
     }
   }
   if constexpr (SM == kScaleCol) {
@@ -323,16 +342,20 @@ __device__ __forceinline__ void products(const Chunk<VF>& ch, Gathered<NRHS>& g,
   }
 }
 
-// Lane sum of the chunk entries at positions [ks, ke), pairwise over the 8
-// entries (entries outside count as 0).
+// Lane sum of the lane's entries at positions [ks, ke), pairwise over its 8
+// entries (entries outside count as 0).  pn1, pn2: positions of the lane's
+// two quarters.
 template <int NRHS>
-__device__ __forceinline__ void chunk_sum(const float (&p)[kChunk][NRHS], int pn, int ks, int ke, float (&c)[NRHS]) {
-  const int lo = min(max(ks - pn, 0), kChunk), hi = min(max(ke - pn, 0), kChunk);
+__device__ __forceinline__ void chunk_sum(const float (&p)[kChunk][NRHS], int pn1, int pn2, int ks, int ke,
+                                          float (&c)[NRHS]) {
+  const int lo1 = min(max(ks - pn1, 0), kQuarter), hi1 = min(max(ke - pn1, 0), kQuarter);
+  const int lo2 = min(max(ks - pn2, 0), kQuarter) + kQuarter, hi2 = min(max(ke - pn2, 0), kQuarter) + kQuarter;
   float m[kChunk][NRHS];
 #pragma unroll
   for (int e = 0; e < kChunk; ++e)
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) m[e][q] = e >= lo && e < hi ? p[e][q] : 0.0f;
+    for (int q = 0; q < NRHS; ++q)
+      m[e][q] = (e < kQuarter ? e >= lo1 && e < hi1 : e >= lo2 && e < hi2) ? p[e][q] : 0.0f;
 #pragma unroll
   for (int q = 0; q < NRHS; ++q)
     c[q] = ((m[0][q] + m[1][q]) + (m[2][q] + m[3][q])) + ((m[4][q] + m[5][q]) + (m[6][q] + m[7][q]));
@@ -362,34 +385,35 @@ __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float
 // is left in `tot` and the row scale in `sc`.
 template <int VF, int SM, int NRHS, bool WIN, int DEPTH, bool SPLIT>
 __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
-                                            int first, float* xw, int cmin, int clen, float (&tot)[NRHS], float& sc) {
+                                            uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
+                                            float (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
   const uint32_t origin32 = static_cast<uint32_t>(origin);
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) tot[q] = 0.0f;
   sc = 1.0f;
-  // the wave's positions [p0, p1), its steps and its first row
-  int p0 = 0, p1 = 0;
-  RowCursor rc;
-  rc.mask = 0;
-  Row cr;
-  cr.valid = false;
-  if (r_begin < r_end) {
-    p0 = static_cast<int>(a.row_ptr[r_begin] - origin32);
-    p1 = static_cast<int>(a.row_ptr[r_end] - origin32);
-    fetch_rows(a, rc, r_begin, r_end, origin32);
-    settle_rows<NRHS>(a, rc, r_end);
-    rc.wb = r_begin;
-    // next_row moves on from rc.wb + 64 once the first window is done
-    cr = next_row<NRHS>(a, rc, r_end, origin32);
-  }
-  const int pmin = p0 & ~(kChunk - 1), pmax = max(p1 - 1, p0) & ~(kChunk - 1);
+  // the wave's positions [p0, p1) (from the group descriptor, so the first
+  // loads go out at once) and its steps
+  const int shift = static_cast<int>(base - origin);
+  const int p0 = shift + static_cast<int>(e_begin), p1 = shift + static_cast<int>(e_end);
+  const int pmin = p0 & ~(kQuarter - 1), pmax = max(p1 - 1, p0) & ~(kQuarter - 1);
   const int kbeg = (p0 >> 9) + (SPLIT ? first : 0);
   const int kend = p1 > p0 ? (p1 - 1) >> 9 : -1;  // the wave's last step (inclusive)
   Chunk<VF> cs[DEPTH + 1];
 #pragma unroll
   for (int d = 0; d < DEPTH; ++d) load_step<VF, SM>(a, origin, kbeg + d * stride, pmin, pmax, cs[d]);
+  // the wave's first row window and first non-empty row
+  RowCursor rc;
+  rc.mask = 0;
+  Row cr;
+  cr.valid = false;
+  if (r_begin < r_end) {
+    fetch_rows(a, rc, r_begin, r_end, origin32);
+    settle_rows<NRHS>(a, rc, r_end);
+    // next_row moves on from rc.wb + 64 once the first window is done
+    cr = next_row<NRHS>(a, rc, r_end, origin32);
+  }
   if constexpr (WIN) {
     for (int t = threadIdx.x; t < clen; t += kGroupThreads) {
       const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
@@ -417,11 +441,11 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
       __builtin_amdgcn_sched_barrier(0);
       float p[kChunk][NRHS];
       products<VF, SM, NRHS, WIN>(cs[cur], g, xw, cmin, clen, p);
-      const int pn = k * kStepEntries + lane * kChunk;
+      const int pn1 = quarter_pos(k, lane, 0), pn2 = quarter_pos(k, lane, 1);
       // the rows that meet step k (none once the wave is past its last step)
       while (k <= kend && cr.valid && cr.ks < (k + 1) * kStepEntries) {
         float c[NRHS];
-        chunk_sum<NRHS>(p, pn, cr.ks, cr.ke, c);
+        chunk_sum<NRHS>(p, pn1, pn2, cr.ks, cr.ke, c);
         const int slot = (k - cr.kfirst) & (kRowSlots - 1);
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) {
@@ -466,18 +490,20 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
   float tot[NRHS], sc;
   if (gp->split == 0) {
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
+    const uint32_t e0 = wave == 0 ? 0u : gp->ent[wave - 1], e1 = gp->ent[wave];
     if (win)
-      wave_stream<VF, SM, NRHS, true, DEPTH, false>(a, base, r0, r1, 0, xw, cmin, static_cast<int>(clen), tot, sc);
+      wave_stream<VF, SM, NRHS, true, DEPTH, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), tot,
+                                                    sc);
     else
-      wave_stream<VF, SM, NRHS, false, DEPTH, false>(a, base, r0, r1, 0, xw, 0, 0, tot, sc);
+      wave_stream<VF, SM, NRHS, false, DEPTH, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, tot, sc);
     return;
   }
-  const uint32_t row = gp->row[0];
+  const uint32_t row = gp->row[0], len = gp->ent[kGroupWaves - 1];
   if (win)
-    wave_stream<VF, SM, NRHS, true, DEPTH, true>(a, base, row, row + 1, wave, xw, cmin, static_cast<int>(clen), tot,
-                                                 sc);
+    wave_stream<VF, SM, NRHS, true, DEPTH, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
+                                                 tot, sc);
   else
-    wave_stream<VF, SM, NRHS, false, DEPTH, true>(a, base, row, row + 1, wave, xw, 0, 0, tot, sc);
+    wave_stream<VF, SM, NRHS, false, DEPTH, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
