@@ -536,13 +536,6 @@ void check_items(const dose_batch_item* items, int32_t n_items) {
   }
 }
 
-int batched_grid(int64_t n_work) {
-  int dev = 0, cus = 0;
-  HIP_CHECK(hipGetDevice(&dev));
-  HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(n_work, int64_t{cus} * 4)));
-}
-
 // Median time of the plain product of one operand under its current partition.
 double time_partition(dose_matrix_s* m, Operand& op, int sm, int n_rhs, const float* x, float* y, hipStream_t s) {
   const SpmvArgs a = make_args(m, op, sm, n_rhs, x, y);
@@ -610,7 +603,7 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
   plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(WorkItem));
   HIP_CHECK(hipMemcpy(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice));
   if (!work.empty()) HIP_CHECK(hipMemcpy(plan->work.get(), work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-  plan->grid = batched_grid(plan->n_work);
+  plan->grid = 0;  // as many workgroups as are resident
   return plan.release();
 }
 

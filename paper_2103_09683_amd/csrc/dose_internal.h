@@ -89,8 +89,10 @@ struct alignas(8) WorkItem {
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s);
+// Persistent batched launch; grid_cap > 0 limits the workgroups (0: as many
+// as are resident at once).
 hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args,
-                               const WorkItem* d_work, int64_t n_work, int grid, int lds_floats,
+                               const WorkItem* d_work, int64_t n_work, int grid_cap, int lds_floats,
                                hipStream_t s);
 hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const int32_t* col,
                                 const uint32_t* row_ptr, hipStream_t s);

@@ -32,6 +32,9 @@
 #include <hip/hip_fp16.h>
 
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace dose {
 namespace {
@@ -560,14 +563,49 @@ void launch_depth(const SpmvArgs& a, size_t lds, hipStream_t s) {
   }
 }
 
-template <int VF, int SM, int NRHS>
-void launch_depth_batched(const SpmvArgs* args, const WorkItem* work, int64_t n_work, int grid, size_t lds,
-                          hipStream_t s) {
-  const dim3 g(static_cast<unsigned>(grid)), block(kGroupThreads);
-  switch (prefetch_depth()) {
-    case 1: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 1>), g, block, lds, s, args, work, n_work); break;
-    default: hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 2>), g, block, lds, s, args, work, n_work); break;
+// Workgroups of a persistent launch: as many as are resident at once (from
+// the kernel's occupancy at this LDS size), at most one per work item, and
+// at most `cap` when cap > 0.
+template <class K>
+int resident_grid(K kernel, size_t lds, int64_t n_work, int cap) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, size_t>, int> cache;
+  const std::pair<const void*, size_t> key(reinterpret_cast<const void*>(kernel), lds);
+  int per_cu = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      per_cu = it->second;
+    } else {
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kGroupThreads, lds) != hipSuccess) per_cu = 1;
+      per_cu = per_cu < 1 ? 1 : per_cu;
+      cache[key] = per_cu;
+    }
   }
+  int dev = 0, cus = 1;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 1;
+  int64_t g = std::min<int64_t>(n_work, int64_t{cus} * per_cu);
+  if (cap > 0) g = std::min<int64_t>(g, cap);
+  return static_cast<int>(g < 1 ? 1 : g);
+}
+
+template <int VF, int SM, int NRHS, int DEPTH>
+void launch_batched_kernel(const SpmvArgs* args, const WorkItem* work, int64_t n_work, int cap, size_t lds,
+                           hipStream_t s) {
+  auto kernel = k_spmv_batched<VF, SM, NRHS, DEPTH>;
+  const int grid = resident_grid(kernel, lds, n_work, cap);
+  hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(kGroupThreads), lds, s, args, work, n_work);
+}
+
+template <int VF, int SM, int NRHS>
+void launch_depth_batched(const SpmvArgs* args, const WorkItem* work, int64_t n_work, int cap, size_t lds,
+                          hipStream_t s) {
+  if (prefetch_depth() == 1)
+    launch_batched_kernel<VF, SM, NRHS, 1>(args, work, n_work, cap, lds, s);
+  else
+    launch_batched_kernel<VF, SM, NRHS, 2>(args, work, n_work, cap, lds, s);
 }
 
 template <int VF, int SM>
