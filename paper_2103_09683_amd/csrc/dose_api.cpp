@@ -277,6 +277,7 @@ struct Operand {
   std::vector<int64_t> h_row_ptr;
   DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
   DevBuf groups;
+  std::vector<GroupDesc> h_groups;  // host copy (batched plans copy it into their work lists)
   int32_t group_nnz = 0;
   int64_t n_groups = 0, n_windowed = 0, n_split = 0;
   int32_t win_floats[3] = {0, 0, 0};  // LDS window size for 1, 2 and 4 vectors
@@ -286,9 +287,10 @@ struct Operand {
 
 int rhs_slot(int n_rhs) { return n_rhs == 1 ? 0 : n_rhs == 2 ? 1 : 2; }
 
-// Cap on one workgroup's LDS x window, in floats: DOSE_LDS_WINDOW_FLOATS
-// (256 .. kWinFloatsMax), default 4096 (16 KB: eight workgroups per compute
-// unit, and 99.8% of the clinical beam's groups fit).  A smaller cap lets
+// Cap on one workgroup's LDS x window for one vector, in floats:
+// DOSE_LDS_WINDOW_FLOATS (256 .. kWinFloatsMax), default 4096 (16 KB: eight
+// workgroups per compute unit, and 99.8% of the clinical beam's groups fit);
+// n vectors get n times the cap, up to kWinFloatsMax.  A smaller cap lets
 // more workgroups share a compute unit; groups whose window exceeds it
 // gather x from global memory.
 int64_t window_cap_floats() {
@@ -320,13 +322,17 @@ void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
     windowed += g.clen > 0 && window_floats(g.clen, 1) <= cap;
     split += g.split;
     for (int i = 0; i < 3; ++i) {
+      // the cap scales with the vectors: the same columns fit for 1, 2 and 4
+      // (kernels for more vectors hold more registers and fewer workgroups
+      // per compute unit, which leaves them the LDS)
       const int64_t f = window_floats(g.clen, rhs[i]);
-      if (f <= cap) wf[i] = std::max(wf[i], f);
+      if (f <= std::min<int64_t>(cap * rhs[i], kWinFloatsMax)) wf[i] = std::max(wf[i], f);
     }
   }
   op.groups = std::move(groups);
   op.group_nnz = group_nnz;
   op.n_groups = static_cast<int64_t>(G.size());
+  op.h_groups = G;
   op.n_windowed = windowed;
   op.n_split = split;
   for (int i = 0; i < 3; ++i) op.win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);
@@ -503,8 +509,7 @@ struct dose_batch_plan_s {
   int device = 0;
   int vf = 0, sm = 0, n_rhs = 0, lds_floats = 0;
   int64_t n_work = 0;
-  int grid = 0;
-  DevBuf args, work;
+  DevBuf args, work;  // per-item arguments; the groups of all items
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~dose_batch_plan_s() {
@@ -590,26 +595,29 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
       if (seen.emplace(items[i].A, i).second) autotune_matrix(items[i].A, items[i].n_rhs, items[i].x, items[i].y, s);
   }
   std::vector<SpmvArgs> args(n_items);
-  std::vector<WorkItem> work;
+  std::vector<GroupDesc> work;
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_matrix_s* m = items[i].A;
     args[i] = make_args(m, m->A, plan->sm, plan->n_rhs, items[i].x, items[i].y);
     plan->lds_floats = std::max(plan->lds_floats, args[i].win_floats);
-    for (int64_t g = 0; g < m->A.n_groups; ++g)
-      work.push_back(WorkItem{static_cast<uint32_t>(i), static_cast<uint32_t>(g)});
+    for (GroupDesc g : m->A.h_groups) {
+      g.item = static_cast<uint32_t>(i);
+      work.push_back(g);
+    }
   }
   plan->n_work = static_cast<int64_t>(work.size());
+  if (plan->n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
   plan->args = DevBuf(args.size() * sizeof(SpmvArgs));
-  plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(WorkItem));
+  plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
   HIP_CHECK(hipMemcpy(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice));
-  if (!work.empty()) HIP_CHECK(hipMemcpy(plan->work.get(), work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
-  plan->grid = 0;  // as many workgroups as are resident
+  if (!work.empty())
+    HIP_CHECK(hipMemcpy(plan->work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
   return plan.release();
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
-  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->args.get<SpmvArgs>(), p->work.get<WorkItem>(), p->n_work,
-                                p->grid, p->lds_floats, s));
+  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->args.get<SpmvArgs>(), p->work.get<GroupDesc>(), p->n_work,
+                                p->lds_floats, s));
 }
 
 int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4095) / 4096))); }

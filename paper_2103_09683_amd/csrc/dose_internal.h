@@ -44,7 +44,8 @@ struct alignas(64) GroupDesc {
   uint32_t clen;                  // largest minus smallest column plus 1 (0: no entries)
   uint32_t split;                 // 1: one row shared by all waves
   uint32_t ent[kGroupWaves];      // wave w's entries end at nnz_base + ent[w] (split: ent[3] is the row's length)
-  uint32_t pad[2];
+  uint32_t item;                  // batched launches: the item the group belongs to
+  uint32_t pad;
 };
 static_assert(sizeof(GroupDesc) == 64, "GroupDesc layout");
 
@@ -72,8 +73,8 @@ struct SpmvArgs {
   int32_t pad;
 };
 
-// Largest LDS x window of one workgroup, in floats.
-constexpr int kWinFloatsMax = 8192;
+// Largest LDS x window of one workgroup, in floats (48 KB).
+constexpr int kWinFloatsMax = 12288;
 
 // LDS floats a window of `clen` columns needs for n_rhs vectors: one padding
 // slot every 8 columns keeps a wave's stride-8 reads free of bank conflicts.
@@ -81,19 +82,12 @@ __host__ __device__ constexpr int64_t window_floats(uint32_t clen, int n_rhs) {
   return clen == 0 ? 0 : (static_cast<int64_t>(clen - 1) + ((clen - 1) >> 3) + 1) * n_rhs;
 }
 
-// Work item of a batched launch: group `group` of item `item`.
-struct alignas(8) WorkItem {
-  uint32_t item;
-  uint32_t group;
-};
-
 // ------------------------------------------------------------ launchers
 hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s);
-// Persistent batched launch; grid_cap > 0 limits the workgroups (0: as many
-// as are resident at once).
+// Batched launch: one workgroup per entry of d_work, the groups of all items
+// (copies of their descriptors, each naming its item in d_args).
 hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args,
-                               const WorkItem* d_work, int64_t n_work, int grid_cap, int lds_floats,
-                               hipStream_t s);
+                               const GroupDesc* d_work, int64_t n_work, int lds_floats, hipStream_t s);
 hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const int32_t* col,
                                 const uint32_t* row_ptr, hipStream_t s);
 

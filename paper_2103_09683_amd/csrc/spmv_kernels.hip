@@ -32,9 +32,6 @@
 #include <hip/hip_fp16.h>
 
 #include <cstdlib>
-#include <map>
-#include <mutex>
-#include <utility>
 
 namespace dose {
 namespace {
@@ -521,25 +518,21 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
 }
 
 template <int VF, int SM, int NRHS, int DEPTH>
-__global__ __launch_bounds__(kGroupThreads) void k_spmv(SpmvArgs a) {
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
   __shared__ float part[kGroupWaves * NRHS];
   run_group<VF, SM, NRHS, DEPTH>(a, a.groups + blockIdx.x, xw, part);
 }
 
-// Persistent form: workgroups walk a list of (item, group) pairs that may
-// belong to many matrices.
+// Batched form, one launch for many matrices: workgroup b takes entry b of
+// the work list, a copy of a group's descriptor that names its item.
 template <int VF, int SM, int NRHS, int DEPTH>
-__global__ __launch_bounds__(kGroupThreads) void k_spmv_batched(const SpmvArgs* __restrict__ args,
-                                                                const WorkItem* __restrict__ work, int64_t n_work) {
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_batched(
+    const SpmvArgs* __restrict__ args, const GroupDesc* __restrict__ work) {
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   __shared__ float part[kGroupWaves * NRHS];
-  for (int64_t w = blockIdx.x; w < n_work; w += gridDim.x) {
-    const WorkItem wi = work[w];
-    const SpmvArgs a = args[wi.item];
-    run_group<VF, SM, NRHS, DEPTH>(a, a.groups + wi.group, xw, part);
-    __syncthreads();  // the window and the slot sums are reused by the next group
-  }
+  const GroupDesc* gp = work + blockIdx.x;
+  run_group<VF, SM, NRHS, DEPTH>(args[gp->item], gp, xw, part);
 }
 
 // Units of a wave's rows kept in flight ahead of the one being computed:
@@ -563,49 +556,13 @@ void launch_depth(const SpmvArgs& a, size_t lds, hipStream_t s) {
   }
 }
 
-// Workgroups of a persistent launch: as many as are resident at once (from
-// the kernel's occupancy at this LDS size), at most one per work item, and
-// at most `cap` when cap > 0.
-template <class K>
-int resident_grid(K kernel, size_t lds, int64_t n_work, int cap) {
-  static std::mutex mu;
-  static std::map<std::pair<const void*, size_t>, int> cache;
-  const std::pair<const void*, size_t> key(reinterpret_cast<const void*>(kernel), lds);
-  int per_cu = 0;
-  {
-    std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-      per_cu = it->second;
-    } else {
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kGroupThreads, lds) != hipSuccess) per_cu = 1;
-      per_cu = per_cu < 1 ? 1 : per_cu;
-      cache[key] = per_cu;
-    }
-  }
-  int dev = 0, cus = 1;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus = 1;
-  int64_t g = std::min<int64_t>(n_work, int64_t{cus} * per_cu);
-  if (cap > 0) g = std::min<int64_t>(g, cap);
-  return static_cast<int>(g < 1 ? 1 : g);
-}
-
-template <int VF, int SM, int NRHS, int DEPTH>
-void launch_batched_kernel(const SpmvArgs* args, const WorkItem* work, int64_t n_work, int cap, size_t lds,
-                           hipStream_t s) {
-  auto kernel = k_spmv_batched<VF, SM, NRHS, DEPTH>;
-  const int grid = resident_grid(kernel, lds, n_work, cap);
-  hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(grid)), dim3(kGroupThreads), lds, s, args, work, n_work);
-}
-
 template <int VF, int SM, int NRHS>
-void launch_depth_batched(const SpmvArgs* args, const WorkItem* work, int64_t n_work, int cap, size_t lds,
-                          hipStream_t s) {
+void launch_depth_batched(const SpmvArgs* args, const GroupDesc* work, int64_t n_work, size_t lds, hipStream_t s) {
+  const dim3 g(static_cast<unsigned>(n_work)), block(kGroupThreads);
   if (prefetch_depth() == 1)
-    launch_batched_kernel<VF, SM, NRHS, 1>(args, work, n_work, cap, lds, s);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 1>), g, block, lds, s, args, work);
   else
-    launch_batched_kernel<VF, SM, NRHS, 2>(args, work, n_work, cap, lds, s);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 2>), g, block, lds, s, args, work);
 }
 
 template <int VF, int SM>
@@ -621,13 +578,13 @@ hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
 }
 
 template <int VF, int SM>
-hipError_t launch_rhs_batched(int n_rhs, const SpmvArgs* args, const WorkItem* work, int64_t n_work, int grid,
-                              int lds_floats, hipStream_t s) {
+hipError_t launch_rhs_batched(int n_rhs, const SpmvArgs* args, const GroupDesc* work, int64_t n_work, int lds_floats,
+                              hipStream_t s) {
   const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: launch_depth_batched<VF, SM, 1>(args, work, n_work, grid, lds, s); break;
-    case 2: launch_depth_batched<VF, SM, 2>(args, work, n_work, grid, lds, s); break;
-    case 4: launch_depth_batched<VF, SM, 4>(args, work, n_work, grid, lds, s); break;
+    case 1: launch_depth_batched<VF, SM, 1>(args, work, n_work, lds, s); break;
+    case 2: launch_depth_batched<VF, SM, 2>(args, work, n_work, lds, s); break;
+    case 4: launch_depth_batched<VF, SM, 4>(args, work, n_work, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -675,17 +632,17 @@ hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hip
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args, const WorkItem* d_work,
-                               int64_t n_work, int grid, int lds_floats, hipStream_t s) {
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args, const GroupDesc* d_work,
+                               int64_t n_work, int lds_floats, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
+    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, d_args, d_work, n_work, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
+    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, d_args, d_work, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleRow)
-    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, d_args, d_work, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)
-    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, d_args, d_work, n_work, grid, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, d_args, d_work, n_work, lds_floats, s);
   return hipErrorInvalidValue;
 }
 
