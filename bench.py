@@ -28,7 +28,7 @@ METRIC = "dose SpMV GNNZ/s and % HBM roofline, plain vs batched/adjoint at rel e
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_clinical_beam_fp16.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_09683_amd", "csrc", f)
-                  for f in ("spmv_kernels.hip", "dose_internal.h")]
+                  for f in ("spmv_kernels.hip", "dose_internal.h", "dose_api.cpp")]
 
 
 def kernel_source_hash() -> str:
