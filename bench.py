@@ -123,6 +123,9 @@ def main(argv=None):
                     help="grid-depth scale of the 36-matrix robust batch (1.0 = full size)")
     ap.add_argument("--probe-copy-gib", type=float, default=0.0,
                     help="only run the copy probe over this many GiB (counter calibration)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the largest workload (8,388,608 x 60,000, 1.7e9 entries) in the three "
+                         "value formats, forward and adjoint")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -215,6 +218,9 @@ def main(argv=None):
         del v, g, seed
         A.close()  # free the single beam before the batch
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
+        variants["small_plain"] = bench_small(torch, dm, dosegen)
+        if args.sweep:
+            variants["sweep_large"] = bench_sweep(torch, dm, dosegen, args)
         out["variants"] = variants
     if not args.no_cpu:
         # y holds A x: the last write to it (plain loop or iteration) used this x
@@ -255,6 +261,70 @@ def bench_batched(torch, dm, dosegen, args):
         for A in mats:
             A.close()
         del entries
+        torch.cuda.empty_cache()
+    return res
+
+
+def bench_small(torch, dm, dosegen):
+    """The small plain matrix (20,000 x 500, about 40 entries per row; it fits in
+    the caches, so this is launch latency, not bandwidth): mean time of 10,000
+    back-to-back products, and of the plan-optimisation iteration on it (dose,
+    FP64 objective with the target/organ masks, adjoint of the seed, FP64
+    gradient norm)."""
+    spec = dosegen.small_plain()
+    rp, cols, vals = dosegen.csr(spec)
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", transpose=True)
+    x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
+    y = torch.empty(spec.n_rows, dtype=torch.float32, device="cuda")
+    ms = time_launches(lambda: A.spmv(x, y), 10000, 100)
+    p_h, w_h = dosegen.objective_masks(spec.nx, spec.ny, spec.nz)
+    p, w = torch.from_numpy(p_h).cuda(), torch.from_numpy(w_h).cuda()
+    seed = torch.empty_like(y)
+    g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
+    fbuf = torch.empty(1, dtype=torch.float64, device="cuda")
+    nbuf = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def iteration():
+        A.spmv(x, y)
+        dm.objective(y, p, w, seed=seed, out=fbuf)
+        A.adjoint(seed, g)
+        dm.norm2(g, out=nbuf)
+
+    ms_i = time_launches(iteration, 10000, 100)
+    nnz = int(rp[-1])
+    A.close()
+    return {"workload": spec.name, "nnz": nnz, "launches": 10000, "us_per_product": round(ms * 1e3, 2),
+            "GNNZ_per_s": round(nnz / (ms * 1e-3) / 1e9, 2), "us_per_iteration": round(ms_i * 1e3, 2),
+            "note": "cache-resident (the matrix is about 5 MB): latency, not an HBM-roofline figure"}
+
+
+def bench_sweep(torch, dm, dosegen, args):
+    """The largest workload in the three value formats: forward and adjoint
+    throughput of the algorithmic bytes."""
+    spec = dosegen.sweep_large()
+    t0 = time.time()
+    rp, cols, vals = dosegen.csr(spec)
+    log(f"generated {spec.name}: {int(rp[-1])} nnz in {time.time() - t0:.1f}s")
+    x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
+    v = torch.from_numpy(dosegen.signed_values(spec.seed, 3, spec.n_rows)).cuda()
+    y = torch.empty(spec.n_rows, dtype=torch.float32, device="cuda")
+    g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
+    res = {"workload": spec.name, "nnz": int(rp[-1])}
+    for fmt in ("fp16", "bf16", "fp8e4m3_rowscale"):
+        t0 = time.time()
+        A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose=True)
+        log(f"sweep {fmt}: created in {time.time() - t0:.1f}s")
+        info = A.info()
+        ms = time_launches(lambda: A.spmv(x, y), max(20, args.steps // 4), 3)
+        ms_a = time_launches(lambda: A.adjoint(v, g), max(20, args.steps // 4), 3)
+        res[fmt] = {"forward_ms": round(ms, 4), "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
+                    "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
+                    "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                    "adjoint_ms": round(ms_a, 4),
+                    "adjoint_GBps": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
+                    "adjoint_frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                    "spmv_bytes": info["spmv_bytes"], "device_bytes": info["device_bytes"]}
+        A.close()
         torch.cuda.empty_cache()
     return res
 

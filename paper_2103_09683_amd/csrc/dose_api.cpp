@@ -456,10 +456,17 @@ void check_group_nnz(int32_t g) {
 }
 
 // Default row-group size: large enough that staging a group's x window is a
-// small fraction of its stream, small enough for many groups per compute unit.
-int default_group_nnz(int64_t nnz) {
-  int g = 16384;
-  while (g > 4096 && nnz / g < 256 * 8) g >>= 1;
+// small fraction of its stream, small enough for many groups per compute
+// unit.  32K entries when the launch runs at least 24 rounds of resident
+// workgroups (eight per compute unit), so that the last, partial round costs
+// little; 16K otherwise; halved for matrices with fewer groups than resident
+// workgroups.
+int default_group_nnz(int64_t nnz, int device) {
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1) cus = 256;
+  const int64_t resident = int64_t{cus} * 8;
+  int g = nnz / 32768 >= 24 * resident ? 32768 : 16384;
+  while (g > 4096 && nnz / g < resident) g >>= 1;
   return g;
 }
 
@@ -690,9 +697,9 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, d
       HIP_CHECK(hipMemcpyAsync(A.col.get(), csr->col_idx, static_cast<size_t>(A.nnz) * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
     encode_values(m.get(), csr, s);
-    upload_partition(A, default_group_nnz(A.nnz), s);
+    upload_partition(A, default_group_nnz(A.nnz, m->device), s);
     if (flags & DOSE_CREATE_TRANSPOSE) {
-      build_transpose(m.get(), default_group_nnz(A.nnz), s);
+      build_transpose(m.get(), default_group_nnz(A.nnz, m->device), s);
       m->has_t = true;
     }
     HIP_CHECK(hipStreamSynchronize(s));

@@ -143,6 +143,27 @@ def test_rows_across_many_row_windows(dev):
         A.close()
 
 
+def test_many_tiny_rows_per_step(dev):
+    """Rows of 1..8 entries packed densely: a 512-entry step then meets up to
+    hundreds of rows and crosses several 64-row windows, and rows start at
+    every offset of a step's quarters."""
+    rng = np.random.default_rng(14)
+    lens = rng.integers(1, 9, size=30000)
+    lens[rng.random(lens.size) < 0.1] = 0
+    rp, cols, vals = _csr_from_lens(rng, lens, 1000, signed=True)
+    x = rng.uniform(-1, 1, 1000).astype(np.float32)
+    for fmt in FORMATS:
+        A = dm.DoseMatrix(rp, cols, vals, 1000, fmt)
+        ys = []
+        for group_nnz in (1024, 16384, 1 << 20):
+            _say("tiny rows", fmt, group_nnz)
+            A.set_partition(group_nnz)
+            ys.append(_check_forward(A, rp, cols, vals, fmt, x)[0])
+        for y in ys[1:]:
+            np.testing.assert_array_equal(_bits(y), _bits(ys[0]))
+        A.close()
+
+
 def test_window_and_global_gathers_agree(dev):
     """Groups whose column window fits LDS gather x there, the others from
     global memory; both must give the same bits."""
