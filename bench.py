@@ -217,6 +217,7 @@ def main(argv=None):
             "GNNZ_per_s_two_products": round(2 * nnz / (ms_i * 1e-3) / 1e9, 3)}
         del v, g, seed
         A.close()  # free the single beam before the batch
+        variants["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
         variants["small_plain"] = bench_small(torch, dm, dosegen)
         if args.sweep:
@@ -228,6 +229,22 @@ def main(argv=None):
         out["cpu_baseline"] = cpu_baseline(spec, rp, cols, vals, x_h, y_h, args.cpu_budget)
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out))
+
+
+def bench_u16(torch, dm, spec, rp, cols, vals, x, y, args):
+    """The same product with 16-bit column indices (4 bytes per entry in
+    FP16 instead of 6); its result must equal the 32-bit one bit for bit."""
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, args.format, index_format="u16")
+    info = A.info()
+    y16 = torch.empty_like(y)
+    ms = time_launches(lambda: A.spmv(x, y16), args.steps, args.warmup)
+    same = bool(torch.equal(y16.view(torch.int32), y.view(torch.int32)))
+    A.close()
+    gbps = info["spmv_bytes"] / (ms * 1e-3) / 1e9
+    log(f"u16 indices: {ms:.4f} ms/step, {gbps:.0f} GB/s algorithmic, bitwise equal: {same}")
+    return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
+            "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "algorithmic_bytes_per_launch": info["spmv_bytes"], "bitwise_equal_to_i32": same}
 
 
 def bench_batched(torch, dm, dosegen, args):

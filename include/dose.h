@@ -59,9 +59,14 @@ typedef enum {
   DOSE_VAL_FP8E4M3_ROWSCALE = 3  /* OCP E4M3 (max 448) times an FP32 row scale   */
 } dose_value_format;
 
-/* Column index formats. */
+/* Column index formats.  A^T (DOSE_CREATE_TRANSPOSE) always stores 32-bit
+ * indices: its columns are A's rows. */
 typedef enum {
-  DOSE_IDX_I32 = 1 /* 32-bit column indices, as in the paper (Sec. V) */
+  DOSE_IDX_I32 = 1, /* 32-bit column indices, as in the paper (Sec. V)            */
+  DOSE_IDX_U16 = 2  /* 16-bit column indices (n_cols <= 65536, else UNSUPPORTED):
+                       the paper notes that column indices are a large part of
+                       the bytes moved (Sec. V); 4 instead of 6 B per entry in
+                       FP16 */
 } dose_index_format;
 
 /* dose_matrix_create flags */

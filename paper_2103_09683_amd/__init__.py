@@ -24,6 +24,7 @@ __all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", 
 VALUE_FORMATS = {"fp16": _lib.VAL_FP16, "bf16": _lib.VAL_BF16,
                  "fp8e4m3_rowscale": _lib.VAL_FP8E4M3_ROWSCALE}
 VALUE_BYTES = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1}
+INDEX_FORMATS = {"i32": _lib.IDX_I32, "u16": _lib.IDX_U16}
 
 
 def _stream_handle(stream) -> int | None:
@@ -55,11 +56,11 @@ def _csr_struct(row_ptr, cols, vals, n_cols):
     return c, (row_ptr, cols, vals)
 
 
-def csr_validate(row_ptr, cols, vals, n_cols, value_format: str = "fp16") -> int:
+def csr_validate(row_ptr, cols, vals, n_cols, value_format: str = "fp16", index_format: str = "i32") -> int:
     """Host-only validation; returns the dose_status (0 = valid)."""
     c, keep = _csr_struct(row_ptr, cols, vals, n_cols)
     return int(_lib.load().dose_csr_validate(ctypes.byref(c), VALUE_FORMATS[value_format],
-                                             _lib.IDX_I32))
+                                             INDEX_FORMATS[index_format]))
 
 
 def partition_preview(row_ptr, group_nnz: int) -> np.ndarray:
@@ -102,19 +103,22 @@ class DoseMatrix:
     """
 
     def __init__(self, row_ptr, cols, vals, n_cols: int, value_format: str = "fp16",
-                 transpose: bool = False, stream=None):
+                 transpose: bool = False, stream=None, index_format: str = "i32"):
         if value_format not in VALUE_FORMATS:
             raise ValueError(f"unknown value format {value_format!r}")
+        if index_format not in INDEX_FORMATS:
+            raise ValueError(f"unknown index format {index_format!r}")
         self._h = None
         lib = _lib.load()
         c, keep = _csr_struct(row_ptr, cols, vals, n_cols)
         h = ctypes.c_void_p()
         _lib.check(lib.dose_matrix_create(ctypes.byref(c), VALUE_FORMATS[value_format],
-                                          _lib.IDX_I32,
+                                          INDEX_FORMATS[index_format],
                                           _lib.CREATE_TRANSPOSE if transpose else 0,
                                           _stream_handle(stream), ctypes.byref(h)))
         self._h = h
         self.value_format = value_format
+        self.index_format = index_format
         self.n_rows = int(c.n_rows)
         self.n_cols = int(c.n_cols)
         self.nnz = int(c.nnz)

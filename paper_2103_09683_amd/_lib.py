@@ -23,6 +23,7 @@ ERR_INTERNAL = -7
 
 VAL_FP16, VAL_BF16, VAL_FP8E4M3_ROWSCALE = 1, 2, 3
 IDX_I32 = 1
+IDX_U16 = 2
 CREATE_TRANSPOSE = 1
 PART_A, PART_AT = 0, 1
 PLAN_AUTOTUNE = 1

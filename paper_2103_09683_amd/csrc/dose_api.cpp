@@ -159,7 +159,8 @@ bool overflows(int vf, float v) {
 void validate_csr(const dose_csr_host* c, int vf, int xf) {
   if (!c) fail(DOSE_ERR_INVALID_ARGUMENT, "csr is null");
   if (vf != kFp16 && vf != kBf16 && vf != kFp8) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown value format");
-  if (xf != DOSE_IDX_I32) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown index format");
+  if (xf != DOSE_IDX_I32 && xf != DOSE_IDX_U16) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown index format");
+  if (c && xf == DOSE_IDX_U16 && c->n_cols > 65536) fail(DOSE_ERR_UNSUPPORTED, "16-bit indices need n_cols <= 65536");
   if (c->n_rows < 0 || c->n_cols < 0 || c->nnz < 0) fail(DOSE_ERR_INVALID_ARGUMENT, "negative size");
   if (c->n_rows >= (int64_t{1} << 32) - 1) fail(DOSE_ERR_UNSUPPORTED, "more than 2^32-2 rows");
   if (c->n_cols > INT32_MAX) fail(DOSE_ERR_UNSUPPORTED, "more than 2^31-1 columns");
@@ -276,6 +277,7 @@ struct Operand {
   int64_t n_rows = 0, n_cols = 0, nnz = 0;
   std::vector<int64_t> h_row_ptr;
   DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
+  int idx_bytes = 4;         // column index width: 4 (int32) or 2 (uint16)
   DevBuf groups;
   std::vector<GroupDesc> h_groups;  // host copy (batched plans copy it into their work lists)
   int32_t group_nnz = 0;
@@ -307,7 +309,7 @@ void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
   DevBuf groups(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
   if (!G.empty()) {
     HIP_CHECK(hipMemcpyAsync(groups.get(), G.data(), G.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
-    HIP_CHECK(launch_group_windows(groups.get<GroupDesc>(), static_cast<int64_t>(G.size()), op.col.get<int32_t>(),
+    HIP_CHECK(launch_group_windows(groups.get<GroupDesc>(), static_cast<int64_t>(G.size()), op.col.get(), op.idx_bytes,
                                    op.row_ptr.get<uint32_t>(), s));
     HIP_CHECK(hipMemcpyAsync(G.data(), groups.get(), G.size() * sizeof(GroupDesc), hipMemcpyDeviceToHost, s));
   }
@@ -368,7 +370,8 @@ SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs,
   a.win_floats = op.win_floats[rhs_slot(n_rhs)];
   a.groups = op.groups.get<GroupDesc>();
   a.val = op.val.get();
-  a.col = op.col.get<int32_t>();
+  a.col = op.col.get();
+  a.idx_bytes = op.idx_bytes;
   a.row_ptr = op.row_ptr.get<uint32_t>();
   a.scale = sm == kScaleNone ? nullptr : m->row_scale.get<float>();
   a.x = x;
@@ -431,10 +434,18 @@ void build_transpose(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
     int end_bit = 1;
     while (end_bit < 32 && (int64_t{1} << end_bit) < A.n_cols) ++end_bit;
     size_t tmp_bytes = 0;
-    HIP_CHECK(radix_sort_pairs(nullptr, &tmp_bytes, reinterpret_cast<const uint32_t*>(A.col.get()),
+    // sort keys: A's column indices as uint32
+    DevBuf wide;
+    const uint32_t* keys_in = reinterpret_cast<const uint32_t*>(A.col.get());
+    if (A.idx_bytes == 2) {
+      wide = DevBuf(static_cast<size_t>(n) * 4);
+      HIP_CHECK(launch_widen_u16(A.col.get<uint16_t>(), wide.get<uint32_t>(), n, s));
+      keys_in = wide.get<uint32_t>();
+    }
+    HIP_CHECK(radix_sort_pairs(nullptr, &tmp_bytes, keys_in,
                                keys_out.get<uint32_t>(), perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
     DevBuf tmp(tmp_bytes);
-    HIP_CHECK(radix_sort_pairs(tmp.get(), &tmp_bytes, reinterpret_cast<const uint32_t*>(A.col.get()),
+    HIP_CHECK(radix_sort_pairs(tmp.get(), &tmp_bytes, keys_in,
                                keys_out.get<uint32_t>(), perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
     HIP_CHECK(launch_gather_transpose(m->vf, perm_out.get<uint32_t>(), rows.get<uint32_t>(), A.val.get(), T.val.get(),
                                       T.col.get<int32_t>(), n, s));
@@ -514,7 +525,7 @@ void tune_store(const std::string& key, int v) {
 // ------------------------------------------------------------ batch plans
 struct dose_batch_plan_s {
   int device = 0;
-  int vf = 0, sm = 0, n_rhs = 0, lds_floats = 0;
+  int vf = 0, sm = 0, n_rhs = 0, lds_floats = 0, idx_bytes = 4;
   int64_t n_work = 0;
   DevBuf args, work;  // per-item arguments; the groups of all items
   hipGraph_t graph = nullptr;
@@ -536,6 +547,7 @@ void check_items(const dose_batch_item* items, int32_t n_items) {
     if (it.ldx != it.n_rhs || it.ldy != it.n_rhs) fail(DOSE_ERR_UNSUPPORTED, "ldx and ldy must equal n_rhs");
     if ((it.A->A.n_cols > 0 && !it.x) || (it.A->A.n_rows > 0 && !it.y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
     if (it.A->vf != items[0].A->vf) fail(DOSE_ERR_UNSUPPORTED, "items mix value formats");
+    if (it.A->A.idx_bytes != items[0].A->A.idx_bytes) fail(DOSE_ERR_UNSUPPORTED, "items mix index formats");
     if (it.n_rhs != items[0].n_rhs) fail(DOSE_ERR_UNSUPPORTED, "items mix n_rhs");
     if (it.A->device != items[0].A->device) fail(DOSE_ERR_INVALID_ARGUMENT, "items on different devices");
     if (overlaps(it.x, it.A->A.n_cols * it.n_rhs * 4, it.y, it.A->A.n_rows * it.n_rhs * 4))
@@ -596,6 +608,7 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
   plan->vf = m0->vf;
   plan->sm = scale_mode_A(m0);
   plan->n_rhs = items[0].n_rhs;
+  plan->idx_bytes = m0->A.idx_bytes;
   if (flags & DOSE_PLAN_AUTOTUNE) {
     std::map<dose_matrix_s*, int> seen;
     for (int32_t i = 0; i < n_items; ++i)
@@ -623,8 +636,8 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
-  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->args.get<SpmvArgs>(), p->work.get<GroupDesc>(), p->n_work,
-                                p->lds_floats, s));
+  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, p->args.get<SpmvArgs>(), p->work.get<GroupDesc>(),
+                                p->n_work, p->lds_floats, s));
 }
 
 int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4095) / 4096))); }
@@ -688,14 +701,27 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, d
     A.h_row_ptr.assign(csr->row_ptr, csr->row_ptr + csr->n_rows + 1);
     const int vb = value_bytes(vf);
     A.val = DevBuf(padded(A.nnz) * vb);
-    A.col = DevBuf(padded(A.nnz) * sizeof(int32_t));
+    A.idx_bytes = xf == DOSE_IDX_U16 ? 2 : 4;
+    A.col = DevBuf(padded(A.nnz) * A.idx_bytes);
     if (vf == kFp8) m->row_scale = DevBuf(static_cast<size_t>(std::max<int64_t>(A.n_rows, 1)) * sizeof(float));
     HIP_CHECK(hipMemsetAsync(A.val.get(), 0, A.val.bytes(), s));
     HIP_CHECK(hipMemsetAsync(A.col.get(), 0, A.col.bytes(), s));
     upload_row_ptr32(A, s);
-    if (A.nnz > 0)
+    if (A.nnz > 0 && A.idx_bytes == 4)
       HIP_CHECK(hipMemcpyAsync(A.col.get(), csr->col_idx, static_cast<size_t>(A.nnz) * sizeof(int32_t),
                                hipMemcpyHostToDevice, s));
+    if (A.nnz > 0 && A.idx_bytes == 2) {
+      // narrowed on the host in chunks (the indices were validated < 65536)
+      const int64_t chunk = int64_t{1} << 24;
+      std::vector<uint16_t> h(static_cast<size_t>(std::min<int64_t>(chunk, A.nnz)));
+      for (int64_t k0 = 0; k0 < A.nnz; k0 += chunk) {
+        const int64_t n = std::min<int64_t>(chunk, A.nnz - k0);
+        for (int64_t k = 0; k < n; ++k) h[k] = static_cast<uint16_t>(csr->col_idx[k0 + k]);
+        HIP_CHECK(hipMemcpyAsync(A.col.get<uint16_t>() + k0, h.data(), static_cast<size_t>(n) * 2,
+                                 hipMemcpyHostToDevice, s));
+        HIP_CHECK(hipStreamSynchronize(s));  // h is reused
+      }
+    }
     encode_values(m.get(), csr, s);
     upload_partition(A, default_group_nnz(A.nnz, m->device), s);
     if (flags & DOSE_CREATE_TRANSPOSE) {
@@ -731,12 +757,19 @@ dose_status dose_matrix_decode(dose_matrix m, int32_t part, int64_t row_begin, i
     const int64_t nb = op.h_row_ptr[row_begin], ne = op.h_row_ptr[row_end], n = ne - nb;
     for (int64_t i = row_begin; i <= row_end; ++i) row_ptr_out[i - row_begin] = op.h_row_ptr[i] - nb;
     if (n == 0) return;
-    if (col_out)
+    if (col_out && op.idx_bytes == 4)
       HIP_CHECK(hipMemcpy(col_out, op.col.get<int32_t>() + nb, static_cast<size_t>(n) * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (col_out && op.idx_bytes == 2) {
+      std::vector<uint16_t> h(static_cast<size_t>(n));
+      HIP_CHECK(hipMemcpy(h.data(), op.col.get<uint16_t>() + nb, static_cast<size_t>(n) * 2, hipMemcpyDeviceToHost));
+      for (int64_t k = 0; k < n; ++k) col_out[k] = h[k];
+    }
     if (val_out) {
       DevBuf tmp(static_cast<size_t>(n) * sizeof(float));
       const int sm = part == DOSE_PART_A ? scale_mode_A(m) : scale_mode_AT(m);
-      HIP_CHECK(launch_decode(m->vf, sm, op.val.get(), op.col.get<int32_t>(), m->row_scale.get<float>(),
+      // the column scale mode (E4M3 A^T) reads the int32 columns of A^T
+      HIP_CHECK(launch_decode(m->vf, sm, op.val.get(), op.idx_bytes == 4 ? op.col.get<int32_t>() : nullptr,
+                              m->row_scale.get<float>(),
                               op.row_ptr.get<uint32_t>(), row_begin, row_end - row_begin, static_cast<uint64_t>(nb), n,
                               tmp.get<float>(), nullptr));
       HIP_CHECK(hipDeviceSynchronize());
@@ -763,13 +796,14 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     info->n_groups_t = m->has_t ? m->AT.n_groups : 0;
     info->n_groups_windowed_t = m->has_t ? m->AT.n_windowed : 0;
     info->device_bytes = A.bytes() + m->row_scale.bytes() + (m->has_t ? m->AT.bytes() : 0);
-    const uint64_t per_nnz = static_cast<uint64_t>(value_bytes(m->vf)) + 4;
+    const uint64_t per_nnz = static_cast<uint64_t>(value_bytes(m->vf)) + static_cast<uint64_t>(A.idx_bytes);
+    const uint64_t per_nnz_t = static_cast<uint64_t>(value_bytes(m->vf)) + 4;
     const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
     info->spmv_bytes = A.nnz * per_nnz + (A.n_rows + 1) * 4 + A.n_rows * scale_b + 4 * A.n_cols + 4 * A.n_rows;
     // A^T reads the scale of A's rows through its columns: 4 B per column of A^T
     info->n_groups_split = A.n_split;
     info->n_groups_split_t = m->has_t ? m->AT.n_split : 0;
-    info->adjoint_bytes = m->has_t ? A.nnz * per_nnz + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
+    info->adjoint_bytes = m->has_t ? A.nnz * per_nnz_t + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
   });
 }
 

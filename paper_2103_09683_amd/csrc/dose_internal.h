@@ -63,14 +63,14 @@ enum ScaleMode : int {
 struct SpmvArgs {
   const GroupDesc* groups;
   const void* val;          // codes, padded by kStreamPad
-  const int32_t* col;       // padded by kStreamPad
+  const void* col;          // column indices (int32, or uint16 when idx_bytes is 2), padded by kStreamPad
   const uint32_t* row_ptr;  // n_rows+1 offsets modulo 2^32
   const float* scale;       // row or column scale (E4M3), else null
   const float* x;           // [n_cols][n_rhs]
   float* y;                 // [n_rows][n_rhs]
   int64_t n_groups;
   int32_t win_floats;       // LDS floats for the x window (dynamic shared memory)
-  int32_t pad;
+  int32_t idx_bytes;        // 4 or 2
 };
 
 // Largest LDS x window of one workgroup, in floats (48 KB).
@@ -86,10 +86,12 @@ __host__ __device__ constexpr int64_t window_floats(uint32_t clen, int n_rhs) {
 hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s);
 // Batched launch: one workgroup per entry of d_work, the groups of all items
 // (copies of their descriptors, each naming its item in d_args).
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args,
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SpmvArgs* d_args,
                                const GroupDesc* d_work, int64_t n_work, int lds_floats, hipStream_t s);
-hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const int32_t* col,
+hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const void* col, int idx_bytes,
                                 const uint32_t* row_ptr, hipStream_t s);
+// Widens n uint16 column indices to uint32 (transpose keys).
+hipError_t launch_widen_u16(const uint16_t* in, uint32_t* out, int64_t n, hipStream_t s);
 
 // Rows [0, n_rows) of row_ptr (offsets modulo 2^32); entry k of a row sits at
 // src[k - base] and its code goes to dst_codes[k - base].

@@ -121,6 +121,11 @@ __global__ void k_iota(uint32_t* __restrict__ out, int64_t n) {
   if (t < n) out[t] = static_cast<uint32_t>(t);
 }
 
+__global__ void k_widen_u16(const uint16_t* __restrict__ in, uint32_t* __restrict__ out, int64_t n) {
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = in[t];
+}
+
 template <typename T>
 __global__ void k_gather_transpose(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rows,
                                    const T* __restrict__ codes_in, T* __restrict__ codes_out,
@@ -177,6 +182,12 @@ hipError_t launch_row_ids(const uint32_t* row_ptr, int64_t n_rows, uint64_t nnz,
 hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_iota, dim3(blocks_for(n, 256)), dim3(256), 0, s, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen_u16(const uint16_t* in, uint32_t* out, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_widen_u16, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
   return hipGetLastError();
 }
 

@@ -112,12 +112,34 @@ struct Codes<kFp8> {
   }
 };
 
+// Column indices of 4 consecutive entries: four int32 (IX = 4) or four
+// uint16 (IX = 2).
+template <int IX>
+struct ColQuad;
+template <>
+struct ColQuad<4> {
+  uint4 w;
+  __device__ __forceinline__ void load(const void* col, uint64_t k) { w = ld_nt4(static_cast<const int32_t*>(col) + k); }
+  __device__ __forceinline__ void get(int (&c)[4]) const {
+    c[0] = static_cast<int>(w.x), c[1] = static_cast<int>(w.y), c[2] = static_cast<int>(w.z), c[3] = static_cast<int>(w.w);
+  }
+};
+template <>
+struct ColQuad<2> {
+  uint2 w;
+  __device__ __forceinline__ void load(const void* col, uint64_t k) { w = ld_nt2(static_cast<const uint16_t*>(col) + k); }
+  __device__ __forceinline__ void get(int (&c)[4]) const {
+    c[0] = static_cast<int>(w.x & 0xFFFFu), c[1] = static_cast<int>(w.x >> 16);
+    c[2] = static_cast<int>(w.y & 0xFFFFu), c[3] = static_cast<int>(w.y >> 16);
+  }
+};
+
 // One lane's share of one step: 8 codes and 8 columns, entries 4 l .. 4 l + 3
 // and 256 + 4 l .. 256 + 4 l + 3 of the step for lane l.
-template <int VF>
+template <int VF, int IX>
 struct Chunk {
   Codes<VF> codes;
-  uint4 ca, cb;
+  ColQuad<IX> ca, cb;
   float sc;  // the row's scale (E4M3 A)
 };
 
@@ -267,9 +289,9 @@ __device__ __forceinline__ int quarter_pos(int k, int lane, int half) {
 }
 
 // One lane's entries of one step: 8 codes and 8 column indices.
-template <int VF, int SM>
+template <int VF, int SM, int IX>
 __device__ __forceinline__ void load_step(const SpmvArgs& a, uint64_t origin, int k, int pmin, int pmax,
-                                          Chunk<VF>& ch) {
+                                          Chunk<VF, IX>& ch) {
   // Always issued (a fixed number of loads per step keeps the compiler's
   // wait counts exact): quarters outside the wave's entries re-read the
   // nearest quarter inside them.
@@ -277,8 +299,8 @@ __device__ __forceinline__ void load_step(const SpmvArgs& a, uint64_t origin, in
   const uint64_t e1 = origin + static_cast<uint64_t>(min(max(quarter_pos(k, lane, 0), pmin), pmax));
   const uint64_t e2 = origin + static_cast<uint64_t>(min(max(quarter_pos(k, lane, 1), pmin), pmax));
   ch.codes.load(a.val, e1, e2);
-  ch.ca = ld_nt4(a.col + e1);
-  ch.cb = ld_nt4(a.col + e2);
+  ch.ca.load(a.col, e1);
+  ch.cb.load(a.col, e2);
 }
 
 template <int NRHS>
@@ -287,17 +309,20 @@ struct Gathered {
   float sc[kChunk];  // column scales (kScaleCol)
 };
 
-__device__ __forceinline__ void chunk_cols(const uint4& ca, const uint4& cb, int (&cols)[kChunk]) {
-  cols[0] = static_cast<int>(ca.x), cols[1] = static_cast<int>(ca.y), cols[2] = static_cast<int>(ca.z);
-  cols[3] = static_cast<int>(ca.w), cols[4] = static_cast<int>(cb.x), cols[5] = static_cast<int>(cb.y);
-  cols[6] = static_cast<int>(cb.z), cols[7] = static_cast<int>(cb.w);
+template <int IX>
+__device__ __forceinline__ void chunk_cols(const ColQuad<IX>& ca, const ColQuad<IX>& cb, int (&cols)[kChunk]) {
+  int c1[4], c2[4];
+  ca.get(c1);
+  cb.get(c2);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) cols[e] = c1[e], cols[4 + e] = c2[e];
 }
 
 // Global-memory gathers of a step (x without a window, column scales of an
 // E4M3 A^T), issued before the next step's loads, so that waiting for them
 // leaves those loads in flight.
-template <int VF, int SM, int NRHS, bool WIN>
-__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF>& ch, Gathered<NRHS>& g) {
+template <int VF, int SM, int IX, int NRHS, bool WIN>
+__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF, IX>& ch, Gathered<NRHS>& g) {
   int cols[kChunk];
   chunk_cols(ch.ca, ch.cb, cols);
   if constexpr (!WIN) {
@@ -324,8 +349,8 @@ __device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF>
 // multiplied, also those outside the wave's rows (their columns are valid
 // indices; window positions are clamped into the window); rows take only
 // their own entries afterwards, so no Inf or NaN of x leaks in.
-template <int VF, int SM, int NRHS, bool WIN>
-__device__ __forceinline__ void products(const Chunk<VF>& ch, Gathered<NRHS>& g, const float* xw, int cmin, int clen,
+template <int VF, int SM, int IX, int NRHS, bool WIN>
+__device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<NRHS>& g, const float* xw, int cmin, int clen,
                                          float (&p)[kChunk][NRHS]) {
   if constexpr (WIN) {
     int cols[kChunk];
@@ -383,11 +408,16 @@ __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float
 // loads before that copy and its barrier.  All waves reach the barrier.
 // Without SPLIT each finished row is stored; with SPLIT the wave's slot sum
 // is left in `tot` and the row scale in `sc`.
-template <int VF, int SM, int NRHS, bool WIN, int DEPTH, bool SPLIT>
+// Steps whose loads are in flight ahead of the one computed (deeper rings were
+// measured no faster on the clinical beam and the largest workload).
+constexpr int kDepth = 1;
+
+template <int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT>
 __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
                                             float (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
+  constexpr int DEPTH = kDepth;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
   const uint32_t origin32 = static_cast<uint32_t>(origin);
 #pragma unroll
@@ -400,9 +430,9 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   const int pmin = p0 & ~(kQuarter - 1), pmax = max(p1 - 1, p0) & ~(kQuarter - 1);
   const int kbeg = (p0 >> 9) + (SPLIT ? first : 0);
   const int kend = p1 > p0 ? (p1 - 1) >> 9 : -1;  // the wave's last step (inclusive)
-  Chunk<VF> cs[DEPTH + 1];
+  Chunk<VF, IX> cs[DEPTH + 1];
 #pragma unroll
-  for (int d = 0; d < DEPTH; ++d) load_step<VF, SM>(a, origin, kbeg + d * stride, pmin, pmax, cs[d]);
+  for (int d = 0; d < DEPTH; ++d) load_step<VF, SM, IX>(a, origin, kbeg + d * stride, pmin, pmax, cs[d]);
   // the wave's first row window and first non-empty row
   RowCursor rc;
   rc.mask = 0;
@@ -435,12 +465,12 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
     for (int ph = 0; ph <= DEPTH; ++ph) {
       const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
       Gathered<NRHS> g;
-      gather_global<VF, SM, NRHS, WIN>(a, cs[cur], g);
-      load_step<VF, SM>(a, origin, k + DEPTH * stride, pmin, pmax, cs[nxt]);
+      gather_global<VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
+      load_step<VF, SM, IX>(a, origin, k + DEPTH * stride, pmin, pmax, cs[nxt]);
       // keep the scheduler from sinking the loads below the compute
       __builtin_amdgcn_sched_barrier(0);
       float p[kChunk][NRHS];
-      products<VF, SM, NRHS, WIN>(cs[cur], g, xw, cmin, clen, p);
+      products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xw, cmin, clen, p);
       const int pn1 = quarter_pos(k, lane, 0), pn2 = quarter_pos(k, lane, 1);
       // the rows that meet step k (none once the wave is past its last step)
       while (k <= kend && cr.valid && cr.ks < (k + 1) * kStepEntries) {
@@ -479,7 +509,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
 
 // One group on one workgroup.  `part` is LDS for the four slot sums of a
 // split row.
-template <int VF, int SM, int NRHS, int DEPTH>
+template <int VF, int SM, int NRHS, int IX>
 __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw, float* part) {
   // wave-uniform index, so that the row bounds below are scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -492,18 +522,18 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
     const uint32_t e0 = wave == 0 ? 0u : gp->ent[wave - 1], e1 = gp->ent[wave];
     if (win)
-      wave_stream<VF, SM, NRHS, true, DEPTH, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), tot,
+      wave_stream<VF, SM, IX, NRHS, true, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), tot,
                                                     sc);
     else
-      wave_stream<VF, SM, NRHS, false, DEPTH, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, tot, sc);
+      wave_stream<VF, SM, IX, NRHS, false, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, tot, sc);
     return;
   }
   const uint32_t row = gp->row[0], len = gp->ent[kGroupWaves - 1];
   if (win)
-    wave_stream<VF, SM, NRHS, true, DEPTH, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
+    wave_stream<VF, SM, IX, NRHS, true, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
                                                  tot, sc);
   else
-    wave_stream<VF, SM, NRHS, false, DEPTH, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, tot, sc);
+    wave_stream<VF, SM, IX, NRHS, false, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
@@ -517,82 +547,72 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
   }
 }
 
-template <int VF, int SM, int NRHS, int DEPTH>
+template <int VF, int SM, int NRHS, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
   __shared__ float part[kGroupWaves * NRHS];
-  run_group<VF, SM, NRHS, DEPTH>(a, a.groups + blockIdx.x, xw, part);
+  run_group<VF, SM, NRHS, IX>(a, a.groups + blockIdx.x, xw, part);
 }
 
 // Batched form, one launch for many matrices: workgroup b takes entry b of
 // the work list, a copy of a group's descriptor that names its item.
-template <int VF, int SM, int NRHS, int DEPTH>
+template <int VF, int SM, int NRHS, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_batched(
     const SpmvArgs* __restrict__ args, const GroupDesc* __restrict__ work) {
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   __shared__ float part[kGroupWaves * NRHS];
   const GroupDesc* gp = work + blockIdx.x;
-  run_group<VF, SM, NRHS, DEPTH>(args[gp->item], gp, xw, part);
-}
-
-// Units of a wave's rows kept in flight ahead of the one being computed:
-// DOSE_PREFETCH_DEPTH (1 or 2), default 1 (measured fastest on the clinical
-// beam: deeper rings cost registers without adding bandwidth).
-int prefetch_depth() {
-  static const int d = [] {
-    const char* e = std::getenv("DOSE_PREFETCH_DEPTH");
-    const int v = e ? std::atoi(e) : 1;
-    return v < 2 ? 1 : 2;
-  }();
-  return d;
+  run_group<VF, SM, NRHS, IX>(args[gp->item], gp, xw, part);
 }
 
 template <int VF, int SM, int NRHS>
-void launch_depth(const SpmvArgs& a, size_t lds, hipStream_t s) {
+void launch_ix(const SpmvArgs& a, size_t lds, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
-  switch (prefetch_depth()) {
-    case 1: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 1>), grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 2>), grid, block, lds, s, a); break;
-  }
+  if (SM != kScaleCol && a.idx_bytes == 2)
+    hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, SM == kScaleCol ? 4 : 2>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 4>), grid, block, lds, s, a);
 }
 
 template <int VF, int SM, int NRHS>
-void launch_depth_batched(const SpmvArgs* args, const GroupDesc* work, int64_t n_work, size_t lds, hipStream_t s) {
+void launch_ix_batched(int idx_bytes, const SpmvArgs* args, const GroupDesc* work, int64_t n_work, size_t lds,
+                       hipStream_t s) {
   const dim3 g(static_cast<unsigned>(n_work)), block(kGroupThreads);
-  if (prefetch_depth() == 1)
-    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 1>), g, block, lds, s, args, work);
+  if (SM != kScaleCol && idx_bytes == 2)
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, SM == kScaleCol ? 4 : 2>), g, block, lds, s, args, work);
   else
-    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 2>), g, block, lds, s, args, work);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 4>), g, block, lds, s, args, work);
 }
 
 template <int VF, int SM>
 hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
   const size_t lds = static_cast<size_t>(a.win_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: launch_depth<VF, SM, 1>(a, lds, s); break;
-    case 2: launch_depth<VF, SM, 2>(a, lds, s); break;
-    case 4: launch_depth<VF, SM, 4>(a, lds, s); break;
+    case 1: launch_ix<VF, SM, 1>(a, lds, s); break;
+    case 2: launch_ix<VF, SM, 2>(a, lds, s); break;
+    case 4: launch_ix<VF, SM, 4>(a, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <int VF, int SM>
-hipError_t launch_rhs_batched(int n_rhs, const SpmvArgs* args, const GroupDesc* work, int64_t n_work, int lds_floats,
-                              hipStream_t s) {
+hipError_t launch_rhs_batched(int n_rhs, int idx_bytes, const SpmvArgs* args, const GroupDesc* work, int64_t n_work,
+                              int lds_floats, hipStream_t s) {
   const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: launch_depth_batched<VF, SM, 1>(args, work, n_work, lds, s); break;
-    case 2: launch_depth_batched<VF, SM, 2>(args, work, n_work, lds, s); break;
-    case 4: launch_depth_batched<VF, SM, 4>(args, work, n_work, lds, s); break;
+    case 1: launch_ix_batched<VF, SM, 1>(idx_bytes, args, work, n_work, lds, s); break;
+    case 2: launch_ix_batched<VF, SM, 2>(idx_bytes, args, work, n_work, lds, s); break;
+    case 4: launch_ix_batched<VF, SM, 4>(idx_bytes, args, work, n_work, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 // Column window of every group: min and max column over its entries.
+template <class I>
 __global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ groups, int64_t n_groups,
-                                                       const int32_t* __restrict__ col,
+                                                       const I* __restrict__ col,
                                                        const uint32_t* __restrict__ row_ptr) {
   __shared__ int smin[256], smax[256];
   const GroupDesc g = groups[blockIdx.x];
@@ -600,7 +620,7 @@ __global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ g
   const uint64_t n = static_cast<uint64_t>(row_ptr[g.row[kGroupWaves]] - base32);
   int mn = 0x7fffffff, mx = -1;
   for (uint64_t k = threadIdx.x; k < n; k += 256) {
-    const int c = col[g.nnz_base + k];
+    const int c = static_cast<int>(col[g.nnz_base + k]);
     mn = min(mn, c);
     mx = max(mx, c);
   }
@@ -632,25 +652,29 @@ hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hip
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, const SpmvArgs* d_args, const GroupDesc* d_work,
-                               int64_t n_work, int lds_floats, hipStream_t s) {
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SpmvArgs* d_args,
+                               const GroupDesc* d_work, int64_t n_work, int lds_floats, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleRow)
-    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)
-    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const int32_t* col, const uint32_t* row_ptr,
-                                hipStream_t s) {
+hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const void* col, int idx_bytes,
+                                const uint32_t* row_ptr, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_group_windows, dim3(static_cast<unsigned>(n_groups)), dim3(256), 0, s, groups, n_groups, col,
-                     row_ptr);
+  if (idx_bytes == 2)
+    hipLaunchKernelGGL(k_group_windows<uint16_t>, dim3(static_cast<unsigned>(n_groups)), dim3(256), 0, s, groups,
+                       n_groups, static_cast<const uint16_t*>(col), row_ptr);
+  else
+    hipLaunchKernelGGL(k_group_windows<int32_t>, dim3(static_cast<unsigned>(n_groups)), dim3(256), 0, s, groups,
+                       n_groups, static_cast<const int32_t*>(col), row_ptr);
   return hipGetLastError();
 }
 

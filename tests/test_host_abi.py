@@ -185,3 +185,11 @@ def test_storage_model_reproduces_table1_sizes():
         assert round(r["nnz"] / (r["rows"] * r["cols"]) * 100, 2) == r["ratio_pct"], r["beam"]
     assert any(sig3(r["size_gb"] * 1e9 / 6) != r["nnz"] for r in rows)
     assert all(sig3((r["size_gb"] * 1e9 - 4 * r["rows"]) / 8) != r["nnz"] for r in rows)
+
+
+def test_u16_index_validation():
+    rp = np.array([0, 2], np.int64)
+    vals = np.ones(2, np.float32)
+    assert dm.csr_validate(rp, np.array([0, 65535], np.int32), vals, 65536, "fp16", "u16") == 0
+    assert dm.csr_validate(rp, np.array([0, 65535], np.int32), vals, 65537, "fp16", "u16") == _lib.ERR_UNSUPPORTED
+    assert dm.csr_validate(rp, np.array([0, 65536], np.int32), vals, 65537, "fp16", "i32") == 0
