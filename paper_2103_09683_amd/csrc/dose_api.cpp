@@ -242,6 +242,7 @@ std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int gr
     GroupDesc g{};
     g.nnz_base = static_cast<uint64_t>(rp[start]);
     if (rp[r + 1] - rp[r] > long_row) {
+      if (rp[r + 1] - rp[r] >= kMaxRowNnz) fail(DOSE_ERR_UNSUPPORTED, "a row holds 2^28 or more entries");
       g.split = 1;
       g.row[0] = static_cast<uint32_t>(r);
       for (int w = 1; w <= kGroupWaves; ++w) g.row[w] = static_cast<uint32_t>(r + 1);
@@ -349,6 +350,7 @@ void upload_row_ptr32(Operand& op, hipStream_t s) {
 }
 
 size_t padded(int64_t nnz) { return static_cast<size_t>(((nnz + kStreamPad + 63) / 64) * 64); }
+int pad_entries(int64_t nnz) { return static_cast<int>(static_cast<int64_t>(padded(nnz)) - nnz); }
 
 }  // namespace
 
@@ -449,6 +451,7 @@ void build_transpose(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
                                keys_out.get<uint32_t>(), perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
     HIP_CHECK(launch_gather_transpose(m->vf, perm_out.get<uint32_t>(), rows.get<uint32_t>(), A.val.get(), T.val.get(),
                                       T.col.get<int32_t>(), n, s));
+    HIP_CHECK(launch_fill_pad(T.col.get(), 4, n, pad_entries(n), s));
     HIP_CHECK(launch_row_ptr_from_sorted(keys_out.get<uint32_t>(), n, T.n_rows, rp64.get<int64_t>(), s));
     HIP_CHECK(hipStreamSynchronize(s));
   } else {
@@ -722,6 +725,7 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, d
         HIP_CHECK(hipStreamSynchronize(s));  // h is reused
       }
     }
+    HIP_CHECK(launch_fill_pad(A.col.get(), A.idx_bytes, A.nnz, pad_entries(A.nnz), s));
     encode_values(m.get(), csr, s);
     upload_partition(A, default_group_nnz(A.nnz, m->device), s);
     if (flags & DOSE_CREATE_TRANSPOSE) {

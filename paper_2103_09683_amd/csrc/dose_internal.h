@@ -17,9 +17,12 @@ constexpr int kMinGroupNnz = 1024;
 constexpr int kMaxGroupNnz = 1 << 20;
 // Most rows one group may hold (bounds the time a wave spends on empty rows).
 constexpr int64_t kMaxGroupRows = 16384;
-// Padding of the value and index streams: every 8-entry load of a row stays
-// inside the allocation.
+// Padding of the value and index streams: every 4-entry load of a group
+// stays inside the allocation; padding indices repeat the last column.
 constexpr int64_t kStreamPad = 64;
+// Longest row (entries): positions inside a group, in bytes of a 32-bit
+// index stream, stay below 2^31.
+constexpr int64_t kMaxRowNnz = int64_t{1} << 28;
 
 // Steps of a row (one step: 64 lanes x 8 entries) and how they are summed:
 // the lane sums of step s meet in a fixed wave reduction, giving T_s; the
@@ -40,8 +43,8 @@ constexpr int64_t kSplitMinNnz = 4 * kStepEntries;
 struct alignas(64) GroupDesc {
   uint64_t nnz_base;              // first entry of the group
   uint32_t row[kGroupWaves + 1];  // wave w takes rows [row[w], row[w+1]); split: the row is row[0]
-  uint32_t cmin;                  // smallest column of the group's entries
-  uint32_t clen;                  // largest minus smallest column plus 1 (0: no entries)
+  uint32_t cmin;                  // first column of the x window (a multiple of kWinAlign)
+  uint32_t clen;                  // window columns: the loaded entries' largest column - cmin + 1 (0: no entries)
   uint32_t split;                 // 1: one row shared by all waves
   uint32_t ent[kGroupWaves];      // wave w's entries end at nnz_base + ent[w] (split: ent[3] is the row's length)
   uint32_t item;                  // batched launches: the item the group belongs to
@@ -73,6 +76,12 @@ struct SpmvArgs {
   int32_t idx_bytes;        // 4 or 2
 };
 
+// Entries of a quarter: lane l of a step loads the 4 entries at 4 l and at
+// 256 + 4 l of it.
+constexpr int kQuarterEntries = kChunk / 2;
+// A group's x window starts at a multiple of this many columns.
+constexpr int kWinAlign = 8;
+
 // Largest LDS x window of one workgroup, in floats (48 KB).
 constexpr int kWinFloatsMax = 12288;
 
@@ -90,6 +99,9 @@ hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes,
                                const GroupDesc* d_work, int64_t n_work, int lds_floats, hipStream_t s);
 hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const void* col, int idx_bytes,
                                 const uint32_t* row_ptr, hipStream_t s);
+// Sets the n_pad padding indices after entry nnz - 1 to its column (0 when
+// nnz is 0); n_pad <= 1024.
+hipError_t launch_fill_pad(void* col, int idx_bytes, int64_t nnz, int n_pad, hipStream_t s);
 // Widens n uint16 column indices to uint32 (transpose keys).
 hipError_t launch_widen_u16(const uint16_t* in, uint32_t* out, int64_t n, hipStream_t s);
 

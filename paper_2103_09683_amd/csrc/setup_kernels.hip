@@ -126,6 +126,14 @@ __global__ void k_widen_u16(const uint16_t* __restrict__ in, uint32_t* __restric
   if (t < n) out[t] = in[t];
 }
 
+// Padding entries after the last entry take its column, so that a product
+// kernel's loads past a group's end read a column of that group's window.
+template <typename I>
+__global__ void k_fill_pad(I* __restrict__ col, int64_t nnz, int n_pad) {
+  const int t = static_cast<int>(threadIdx.x);
+  if (t < n_pad) col[nnz + t] = nnz > 0 ? col[nnz - 1] : I(0);
+}
+
 template <typename T>
 __global__ void k_gather_transpose(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rows,
                                    const T* __restrict__ codes_in, T* __restrict__ codes_out,
@@ -188,6 +196,16 @@ hipError_t launch_iota(uint32_t* out, int64_t n, hipStream_t s) {
 hipError_t launch_widen_u16(const uint16_t* in, uint32_t* out, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_widen_u16, dim3(blocks_for(n, 256)), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_pad(void* col, int idx_bytes, int64_t nnz, int n_pad, hipStream_t s) {
+  if (n_pad <= 0) return hipSuccess;
+  if (n_pad > 1024) return hipErrorInvalidValue;
+  if (idx_bytes == 2)
+    hipLaunchKernelGGL(k_fill_pad<uint16_t>, dim3(1), dim3(1024), 0, s, static_cast<uint16_t*>(col), nnz, n_pad);
+  else
+    hipLaunchKernelGGL(k_fill_pad<int32_t>, dim3(1), dim3(1024), 0, s, static_cast<int32_t*>(col), nnz, n_pad);
   return hipGetLastError();
 }
 

@@ -9,49 +9,66 @@
 //     rows of neighbouring voxels touch a narrow range of spots, so the
 //     group's columns span a short window of x; the workgroup copies that
 //     window into LDS once and every gather is an LDS read.  A group whose
-//     window does not fit reads x from global memory instead (8 consecutive
-//     columns with two 16-byte loads).
+//     window does not fit reads x from global memory instead.
 //   * Each wave owns a contiguous share of the group's rows and streams its
 //     entries in *steps* of 512 entries on absolute multiples of 512: lane l
-//     of a step loads the 8-entry chunk 8 l of it, 8 codes with one 16-byte
-//     non-temporal load (8-byte for E4M3) and 8 column indices with two.  Every
-//     entry is loaded once, whatever the row lengths, and the loads of the
-//     next steps are in flight while one is computed.  In a split group wave j
-//     takes the steps j, j+4, ... of the row.
-//   * The rows that meet a step take their entries from it: a lane adds its
-//     chunk's products of the row pairwise, the 64 lane sums meet in a fixed
-//     DPP reduction (T_s), W_j adds the T_s of the row's steps s with
-//     (s - first step of the row) = j (mod 4) in order, and the row is
-//     (W_0 + W_1) + (W_2 + W_3).  The order depends only on the row's entries
-//     and their absolute positions -- not on the partition, the launch or
-//     timing -- and nothing is atomic, so equal inputs give equal bits
-//     (Sec. II-D), a split row equals the same row summed by one wave, and
-//     batched products equal plain ones bit for bit.
+//     of a step loads the two 4-entry quarters at 4 l and 256 + 4 l of it
+//     (codes and column indices, non-temporal), so every load instruction
+//     reads one contiguous range and each cache line is requested once.  The
+//     next step's loads are in flight while one is computed.  In a split
+//     group wave j takes the steps j, j+4, ... of the row.
+//   * The kernel is bound by instruction issue as much as by HBM, so the
+//     per-entry work is kept short: FP16 decode and product are one
+//     v_fma_mix, E4M3 is converted by the hardware two codes at a time, the
+//     LDS address of x is a shift and add, and a lane tests whether an entry
+//     belongs to a row with one unsigned compare of its position.
+//   * Summation order, fixed by the row's entries and their absolute
+//     positions only (not by the partition, the launch or timing; nothing is
+//     atomic), so equal inputs give equal bits (Sec. II-D), a split row equals
+//     the same row summed by one wave, and batched products equal plain ones:
+//       - a row meeting at most 4 steps: each lane adds, step by step and
+//         first quarter before second, the pairwise sums of its entries of the
+//         row in each quarter ((a + b) + (c + d), entries outside as +0); the
+//         64 lane sums then meet in one fixed DPP reduction;
+//       - a longer row: per step, the lane sum of its entries of the row
+//         (first-quarter sum + second-quarter sum) goes through the DPP
+//         reduction, giving T_s; W_j adds the T_s of the row's steps s with
+//         (s - first step) = j (mod 4) in order, and the row is
+//         (W_0 + W_1) + (W_2 + W_3).
 #include "dose_internal.h"
 
 #include <hip/hip_fp16.h>
 
 #include <cstdlib>
 
+// Products are rounded before they are summed, in every kernel instance: no
+// multiply-add contraction (it would make the bits depend on which instance
+// summed a row).
+#pragma clang fp contract(off)
+
 namespace dose {
 namespace {
 
 constexpr int kWave = 64;
+constexpr int kQuarter = kQuarterEntries;
+constexpr int kHalf = kStepEntries / 2;  // the second quarter of a lane sits kHalf entries after the first
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-// Streamed data is read once: non-temporal loads.
-__device__ __forceinline__ uint4 ld_nt4(const void* p) {
-  const u32x4 v = __builtin_nontemporal_load(static_cast<const u32x4*>(p));
+// Streamed data is read once: non-temporal loads, at a uniform base plus a
+// 32-bit byte offset per lane.
+__device__ __forceinline__ uint4 ld_nt4(const char* base, uint32_t off) {
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(base + off));
   return make_uint4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ uint2 ld_nt2(const void* p) {
-  const u32x2 v = __builtin_nontemporal_load(static_cast<const u32x2*>(p));
+__device__ __forceinline__ uint2 ld_nt2(const char* base, uint32_t off) {
+  const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(base + off));
   return make_uint2(v.x, v.y);
 }
-__device__ __forceinline__ uint32_t ld_nt1(const void* p) {
-  return __builtin_nontemporal_load(static_cast<const uint32_t*>(p));
+__device__ __forceinline__ uint32_t ld_nt1(const char* base, uint32_t off) {
+  return __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(base + off));
 }
 
 // ----------------------------------------------------------------- decoding
@@ -59,28 +76,19 @@ __device__ __forceinline__ float dec_fp16(uint32_t h) {
   return __half2float(__ushort_as_half(static_cast<unsigned short>(h)));
 }
 
-__device__ __forceinline__ float dec_bf16(uint32_t b) { return __uint_as_float(b << 16); }
-
-// OCP E4M3: E = 0 gives m * 2^-9; otherwise 2^(E-7) * (1 + m/8).  The encoder
-// never emits the NaN code, so no case is needed for it.
-__device__ __forceinline__ float dec_e4m3(uint32_t c) {
-  const uint32_t sign = (c & 0x80u) << 24;
-  const uint32_t E = (c >> 3) & 15u, m = c & 7u;
-  const float mag = E == 0 ? static_cast<float>(m) * 0x1p-9f : __uint_as_float(((E + 120u) << 23) | (m << 20));
-  return __uint_as_float(__float_as_uint(mag) | sign);
-}
-
-// The 8 codes of one chunk, loaded with one non-temporal load.
+// The 8 codes of a lane's step (entries 0..3: first quarter, 4..7: second).
 template <int VF>
 struct Codes;
 template <>
 struct Codes<kFp16> {
+  static constexpr uint32_t kBytes = 2;
   uint4 w;
-  // entries 0..3 from k1, 4..7 from k2
-  __device__ __forceinline__ void load(const void* base, uint64_t k1, uint64_t k2) {
-    const uint2 h1 = ld_nt2(static_cast<const uint16_t*>(base) + k1), h2 = ld_nt2(static_cast<const uint16_t*>(base) + k2);
+  __device__ __forceinline__ void load(const char* base, uint32_t k1, uint32_t k2) {
+    const uint2 h1 = ld_nt2(base, k1 * kBytes), h2 = ld_nt2(base, k2 * kBytes);
     w = make_uint4(h1.x, h1.y, h2.x, h2.y);
   }
+  // the code as binary16 widened to float: fed straight into an FMA it
+  // becomes an operand of v_fma_mix_f32
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
     return dec_fp16((word >> ((e & 1) * 16)) & 0xFFFFu);
@@ -88,27 +96,32 @@ struct Codes<kFp16> {
 };
 template <>
 struct Codes<kBf16> {
+  static constexpr uint32_t kBytes = 2;
   uint4 w;
-  // entries 0..3 from k1, 4..7 from k2
-  __device__ __forceinline__ void load(const void* base, uint64_t k1, uint64_t k2) {
-    const uint2 h1 = ld_nt2(static_cast<const uint16_t*>(base) + k1), h2 = ld_nt2(static_cast<const uint16_t*>(base) + k2);
+  __device__ __forceinline__ void load(const char* base, uint32_t k1, uint32_t k2) {
+    const uint2 h1 = ld_nt2(base, k1 * kBytes), h2 = ld_nt2(base, k2 * kBytes);
     w = make_uint4(h1.x, h1.y, h2.x, h2.y);
   }
   __device__ __forceinline__ float get(int e) const {
     const uint32_t word = e < 2 ? w.x : e < 4 ? w.y : e < 6 ? w.z : w.w;
-    return dec_bf16((word >> ((e & 1) * 16)) & 0xFFFFu);
+    return __uint_as_float((e & 1) ? (word & 0xFFFF0000u) : (word << 16));
   }
 };
 template <>
 struct Codes<kFp8> {
+  static constexpr uint32_t kBytes = 1;
   uint2 w;
-  // entries 0..3 from k1, 4..7 from k2
-  __device__ __forceinline__ void load(const void* base, uint64_t k1, uint64_t k2) {
-    w = make_uint2(ld_nt1(static_cast<const uint8_t*>(base) + k1), ld_nt1(static_cast<const uint8_t*>(base) + k2));
+  __device__ __forceinline__ void load(const char* base, uint32_t k1, uint32_t k2) {
+    w = make_uint2(ld_nt1(base, k1), ld_nt1(base, k2));
   }
-  __device__ __forceinline__ float get(int e) const {
-    const uint32_t word = e < 4 ? w.x : w.y;
-    return dec_e4m3((word >> ((e & 3) * 8)) & 0xFFu);
+  // OCP E4M3 to float by the hardware (exact), two codes per instruction.
+  // The encoder never emits the NaN code.
+  __device__ __forceinline__ void decode(float (&d)[kChunk]) const {
+    const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w.x), false);
+    const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w.x), true);
+    const f32x2 c = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w.y), false);
+    const f32x2 e = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w.y), true);
+    d[0] = a.x, d[1] = a.y, d[2] = b.x, d[3] = b.y, d[4] = c.x, d[5] = c.y, d[6] = e.x, d[7] = e.y;
   }
 };
 
@@ -119,7 +132,7 @@ struct ColQuad;
 template <>
 struct ColQuad<4> {
   uint4 w;
-  __device__ __forceinline__ void load(const void* col, uint64_t k) { w = ld_nt4(static_cast<const int32_t*>(col) + k); }
+  __device__ __forceinline__ void load(const char* col, uint32_t k) { w = ld_nt4(col, k * 4u); }
   __device__ __forceinline__ void get(int (&c)[4]) const {
     c[0] = static_cast<int>(w.x), c[1] = static_cast<int>(w.y), c[2] = static_cast<int>(w.z), c[3] = static_cast<int>(w.w);
   }
@@ -127,7 +140,7 @@ struct ColQuad<4> {
 template <>
 struct ColQuad<2> {
   uint2 w;
-  __device__ __forceinline__ void load(const void* col, uint64_t k) { w = ld_nt2(static_cast<const uint16_t*>(col) + k); }
+  __device__ __forceinline__ void load(const char* col, uint32_t k) { w = ld_nt2(col, k * 2u); }
   __device__ __forceinline__ void get(int (&c)[4]) const {
     c[0] = static_cast<int>(w.x & 0xFFFFu), c[1] = static_cast<int>(w.x >> 16);
     c[2] = static_cast<int>(w.y & 0xFFFFu), c[3] = static_cast<int>(w.y >> 16);
@@ -140,12 +153,18 @@ template <int VF, int IX>
 struct Chunk {
   Codes<VF> codes;
   ColQuad<IX> ca, cb;
-  float sc;  // the row's scale (E4M3 A)
 };
 
-// LDS slot of window column t: one padding slot every 8 columns keeps the
-// stride-8 reads of a wave (lane l reads near column 8l + e) conflict-free.
-__device__ __forceinline__ int win_slot(int t) { return t + (t >> 3); }
+// LDS slot of x window column t (counted from the window's first column, a
+// multiple of 8): one padding slot every 8 columns spreads a wave's reads of
+// nearby columns over more banks.  Since the window starts at a multiple of 8,
+// win_slot(c - cmin) = win_slot(c) - win_slot(cmin): a column's slot is
+// win_slot(c) from a base moved back by win_slot(cmin), one shift, one add
+// and one shift-add to an LDS address.
+__device__ __forceinline__ int win_slot(int t) {
+  const uint32_t u = static_cast<uint32_t>(t);
+  return static_cast<int>(u + (u >> 3));
+}
 
 template <int NRHS>
 struct XVec {
@@ -171,10 +190,16 @@ __device__ __forceinline__ XVec<NRHS> load_x_global(const float* x, int c) {
   return r;
 }
 
+// x of window column c: xb is the window moved back by win_slot(cmin) slots
+// (below the window when cmin > 0; every c read lies inside it).
 template <int NRHS>
-__device__ __forceinline__ XVec<NRHS> load_x_window(const float* xw, int t) {
+__device__ __forceinline__ XVec<NRHS> load_x_window(const float* xb, int c) {
   XVec<NRHS> r;
-  const float* p = xw + win_slot(t) * NRHS;
+  // the slot as an opaque value: the compiler would otherwise spread the
+  // address shift over both terms of the slot (four instructions, not three)
+  int slot = win_slot(c);
+  asm("" : "+v"(slot));
+  const float* p = xb + slot * NRHS;
   if constexpr (NRHS == 1) {
     r.v[0] = p[0];
   } else if constexpr (NRHS == 2) {
@@ -191,27 +216,37 @@ __device__ __forceinline__ XVec<NRHS> load_x_window(const float* xw, int t) {
   return r;
 }
 
-// Sum of the 64 lanes in a fixed order, left in lane 63, with DPP moves:
-// within each row of 16 lanes, shifts by 1, 2, 4 and 8 leave the row's sum in
-// its lane 15; two row broadcasts then add rows 0..2 into lane 63.  Lanes
-// shifted in from outside a row (or from disabled rows) contribute 0.
+// Sum of the 64 lanes in a fixed order, left in lane 63, with DPP: within
+// each row of 16 lanes, shifts by 1, 2, 4 and 8 leave the row's sum in its
+// lane 15 (lanes shifted in from outside a row contribute 0); a row broadcast
+// then adds row 0's sum into row 1 and row 2's into row 3, and a second one
+// adds lane 31 into row 3.  The broadcasts are written as DPP adds whose
+// disabled rows keep their value (the builtin form would cost a move and a
+// separate add each); s_nop 1 gives the two wait states a DPP read of a VGPR
+// needs after a VALU write to it.  All 64 lanes must be active.
 __device__ __forceinline__ float wave_reduce(float v) {
-  constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  constexpr int kRowShr = 0x110;
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 1, 0xf, 0xf, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 2, 0xf, 0xf, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 4, 0xf, 0xf, false));
   v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowShr + 8, 0xf, 0xf, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowBcast15, 0xa, 0xf, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kRowBcast31, 0xc, 0xf, false));
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf\n\t"
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf\n\t"
+      "s_nop 1"
+      : "+v"(v));
   return v;
 }
 
 // Positions.  A group's entries are addressed by their position P relative
 // to the group's origin, its first entry rounded down to a multiple of 512:
-// step k of the group covers positions [512 k, 512 k + 512) and lane l of
-// the step the chunk [512 k + 8 l, 512 k + 8 l + 8), so steps and chunks sit
-// on absolute multiples of 512 and 8 entries, whatever the partition.  A
-// group spans fewer than 2^31 - 512 positions.
+// step k of the group covers positions [512 k, 512 k + 512), and lane l's
+// quarters in it start at 512 k + 4 l and 512 k + 256 + 4 l, so steps and
+// quarters sit on absolute multiples of 512 and 4 entries, whatever the
+// partition.  A group spans fewer than 2^28 + 2^21 positions (rows are
+// shorter than 2^28 entries), so byte offsets of positions fit 32 bits.
 
 // The current 64-row window of the wave's rows (lane l: row wb + l's
 // positions [lo, hi)) and its non-empty rows not yet started.
@@ -246,13 +281,13 @@ __device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, ui
   rc.mask = __ballot(in && rc.hi > rc.lo);
 }
 
-// The row being summed (wave-uniform): its positions [ks, ke) and its steps
-// kfirst .. klast.
+// The row being summed (wave-uniform): its positions [ks, ke), its steps
+// kfirst .. klast, and whether it is long (more than kRowSlots steps).
 struct Row {
   uint32_t row;
   int ks, ke;
   int kfirst, klast;
-  bool valid;
+  bool valid, lng;
 };
 
 // The wave's next non-empty row, moving on to later 64-row windows (and
@@ -276,31 +311,26 @@ __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32
   n.ke = __builtin_amdgcn_readlane(rc.hi, i);
   n.kfirst = n.ks >> 9;
   n.klast = (n.ke - 1) >> 9;
+  n.lng = n.klast - n.kfirst >= kRowSlots;
   n.valid = true;
   return n;
 }
 
-// Positions of lane l's two quarter-chunks in step k: every load instruction
-// of a step reads one contiguous range (4 entries per lane), so each cache
-// line is requested once.
-constexpr int kQuarter = kChunk / 2;
-__device__ __forceinline__ int quarter_pos(int k, int lane, int half) {
-  return k * kStepEntries + half * (kStepEntries / 2) + lane * kQuarter;
-}
-
-// One lane's entries of one step: 8 codes and 8 column indices.
-template <int VF, int SM, int IX>
-__device__ __forceinline__ void load_step(const SpmvArgs& a, uint64_t origin, int k, int pmin, int pmax,
+// One lane's entries of step k: two quarters.  Always issued (a fixed number
+// of loads per step keeps the compiler's wait counts exact); quarters outside
+// the wave's entries re-read the nearest quarter inside them, so the wave
+// requests only its own lines and every column it reads lies in the group's
+// window.  vb, cb: the code and index streams at the group's origin.
+template <int VF, int IX>
+__device__ __forceinline__ void load_step(const char* vb, const char* cb, int k, int pmin, int pmax,
                                           Chunk<VF, IX>& ch) {
-  // Always issued (a fixed number of loads per step keeps the compiler's
-  // wait counts exact): quarters outside the wave's entries re-read the
-  // nearest quarter inside them.
   const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t e1 = origin + static_cast<uint64_t>(min(max(quarter_pos(k, lane, 0), pmin), pmax));
-  const uint64_t e2 = origin + static_cast<uint64_t>(min(max(quarter_pos(k, lane, 1), pmin), pmax));
-  ch.codes.load(a.val, e1, e2);
-  ch.ca.load(a.col, e1);
-  ch.cb.load(a.col, e2);
+  const int pos = k * kStepEntries + lane * kQuarter;
+  const uint32_t e1 = static_cast<uint32_t>(min(max(pos, pmin), pmax));
+  const uint32_t e2 = static_cast<uint32_t>(min(max(pos + kHalf, pmin), pmax));
+  ch.codes.load(vb, e1, e2);
+  ch.ca.load(cb, e1);
+  ch.cb.load(cb, e2);
 }
 
 template <int NRHS>
@@ -345,49 +375,85 @@ __device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF,
   }
 }
 
-// The 8 products of the lane's chunk.  Every entry is decoded and
-// multiplied, also those outside the wave's rows (their columns are valid
-// indices; window positions are clamped into the window); rows take only
-// their own entries afterwards, so no Inf or NaN of x leaks in.
+// The 8 products of the lane's step.  Every entry is decoded and multiplied,
+// also those outside the wave's rows (their columns lie in the window; see
+// load_step); rows select their own entries afterwards, so no Inf or NaN of x
+// leaks into another row.  xb: the window base of load_x_window.
 template <int VF, int SM, int IX, int NRHS, bool WIN>
-__device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<NRHS>& g, const float* xw, int cmin, int clen,
+__device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<NRHS>& g, const float* xb,
                                          float (&p)[kChunk][NRHS]) {
   if constexpr (WIN) {
     int cols[kChunk];
     chunk_cols(ch.ca, ch.cb, cols);
 #pragma unroll
-    for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_window<NRHS>(xw, min(max(cols[e] - cmin, 0), clen - 1));
+    for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_window<NRHS>(xb, cols[e]);
   }
+  if constexpr (VF == kFp16) {
+    // an FMA with +0 rounds the product once, as a multiply does
 #pragma unroll
-  for (int e = 0; e < kChunk; ++e) {
-    float d = ch.codes.get(e);
-    if constexpr (SM == kScaleCol) d = d * g.sc[e];
+    for (int e = 0; e < kChunk; ++e)
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) p[e][q] = d * g.x[e].v[q];
+      for (int q = 0; q < NRHS; ++q) p[e][q] = __builtin_fmaf(ch.codes.get(e), g.x[e].v[q], 0.0f);
+  } else {
+    float d[kChunk];
+    if constexpr (VF == kFp8) {
+      ch.codes.decode(d);
+    } else {
+#pragma unroll
+      for (int e = 0; e < kChunk; ++e) d[e] = ch.codes.get(e);
+    }
+#pragma unroll
+    for (int e = 0; e < kChunk; ++e) {
+      const float de = SM == kScaleCol ? d[e] * g.sc[e] : d[e];
+#pragma unroll
+      for (int q = 0; q < NRHS; ++q) p[e][q] = de * g.x[e].v[q];
+    }
   }
 }
 
-// Lane sum of the lane's entries at positions [ks, ke), pairwise over its 8
-// entries (entries outside count as 0).  pn1, pn2: positions of the lane's
-// two quarters.
-template <int NRHS>
-__device__ __forceinline__ void chunk_sum(const float (&p)[kChunk][NRHS], int pn1, int pn2, int ks, int ke,
-                                          float (&c)[NRHS]) {
-  const int lo1 = min(max(ks - pn1, 0), kQuarter), hi1 = min(max(ke - pn1, 0), kQuarter);
-  const int lo2 = min(max(ks - pn2, 0), kQuarter) + kQuarter, hi2 = min(max(ke - pn2, 0), kQuarter) + kQuarter;
-  float m[kChunk][NRHS];
+// Pairwise sum of quarter H of the lane's products, (a + b) + (c + d), over
+// the entries at positions [ks, ks + len); d0 = the quarter's first position
+// minus ks.  An entry is in when its position minus ks, taken unsigned, is
+// below len; the others count as +0.
+template <int H, int NRHS>
+__device__ __forceinline__ void quarter_sum(const float (&p)[kChunk][NRHS], int d0, uint32_t len, float (&s)[NRHS]) {
+  float m[kQuarter][NRHS];
 #pragma unroll
-  for (int e = 0; e < kChunk; ++e)
+  for (int e = 0; e < kQuarter; ++e) {
+    const bool in = static_cast<uint32_t>(d0 + e) < len;
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q)
-      m[e][q] = (e < kQuarter ? e >= lo1 && e < hi1 : e >= lo2 && e < hi2) ? p[e][q] : 0.0f;
+    for (int q = 0; q < NRHS; ++q) m[e][q] = in ? p[H * kQuarter + e][q] : 0.0f;
+  }
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q)
-    c[q] = ((m[0][q] + m[1][q]) + (m[2][q] + m[3][q])) + ((m[4][q] + m[5][q]) + (m[6][q] + m[7][q]));
+  for (int q = 0; q < NRHS; ++q) s[q] = (m[0][q] + m[1][q]) + (m[2][q] + m[3][q]);
 }
 
-// Row value from its four slot sums (valid in lane 63), times the row scale
-// of an E4M3 operand.
+// The same for a quarter wholly inside the row.
+template <int H, int NRHS>
+__device__ __forceinline__ void quarter_full(const float (&p)[kChunk][NRHS], float (&s)[NRHS]) {
+  constexpr int b = H * kQuarter;
+#pragma unroll
+  for (int q = 0; q < NRHS; ++q) s[q] = (p[b][q] + p[b + 1][q]) + (p[b + 2][q] + p[b + 3][q]);
+}
+
+// A short row's entries in half H of step k (positions [s0 + 256 H, s0 + 256 H
+// + 256)), added to the lane accumulator L; pq = the lane's first quarter
+// position in the step.
+template <int H, int NRHS>
+__device__ __forceinline__ void add_half(const float (&p)[kChunk][NRHS], int s0, int pq, const Row& r,
+                                         float (&L)[NRHS]) {
+  const int hs = s0 + H * kHalf;
+  if (r.ks >= hs + kHalf || r.ke <= hs) return;  // the row misses this half
+  float s[NRHS];
+  if (r.ks <= hs && r.ke >= hs + kHalf)
+    quarter_full<H, NRHS>(p, s);
+  else
+    quarter_sum<H, NRHS>(p, pq + H * kHalf - r.ks, static_cast<uint32_t>(r.ke - r.ks), s);
+#pragma unroll
+  for (int q = 0; q < NRHS; ++q) L[q] += s[q];
+}
+
+// Row value (valid in lane 63) times the row scale of an E4M3 operand.
 template <int SM, int NRHS>
 __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float sc, const float (&tot)[NRHS]) {
   float* dst = a.y + static_cast<int64_t>(row) * NRHS;
@@ -401,13 +467,11 @@ __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float
 // flight (a ring of DEPTH + 1 chunk buffers, unrolled so that no loaded
 // register is copied, left at one place only so that the compiler's view of
 // the loads in flight stays exact).  In each step the rows that meet it take
-// their entries: the masked lane sums meet in the fixed DPP reduction (T) and
-// T is added to the row's slot (step - first step of the row) mod 4; a row
-// ends with (W_0 + W_1) + (W_2 + W_3).  With WIN the workgroup first copies
-// the x window [cmin, cmin + clen) into LDS: every wave issues its first
-// loads before that copy and its barrier.  All waves reach the barrier.
-// Without SPLIT each finished row is stored; with SPLIT the wave's slot sum
-// is left in `tot` and the row scale in `sc`.
+// their entries in the order described at the top of this file.  With WIN
+// the workgroup first copies the x window [cmin, cmin + clen) into LDS:
+// every wave issues its first loads before that copy and its barrier.  All
+// waves reach the barrier.  Without SPLIT each finished row is stored; with
+// SPLIT the wave's slot sum is left in `tot` and the row scale in `sc`.
 // Steps whose loads are in flight ahead of the one computed (deeper rings were
 // measured no faster on the clinical beam and the largest workload).
 constexpr int kDepth = 1;
@@ -417,9 +481,11 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
                                             float (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
-  constexpr int DEPTH = kDepth;
+  constexpr int DEPTH = IX == 2 ? 2 : kDepth;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
   const uint32_t origin32 = static_cast<uint32_t>(origin);
+  const char* vb = static_cast<const char*>(a.val) + origin * Codes<VF>::kBytes;
+  const char* cb = static_cast<const char*>(a.col) + origin * IX;
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) tot[q] = 0.0f;
   sc = 1.0f;
@@ -432,7 +498,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   const int kend = p1 > p0 ? (p1 - 1) >> 9 : -1;  // the wave's last step (inclusive)
   Chunk<VF, IX> cs[DEPTH + 1];
 #pragma unroll
-  for (int d = 0; d < DEPTH; ++d) load_step<VF, SM, IX>(a, origin, kbeg + d * stride, pmin, pmax, cs[d]);
+  for (int d = 0; d < DEPTH; ++d) load_step<VF, IX>(vb, cb, kbeg + d * stride, pmin, pmax, cs[d]);
   // the wave's first row window and first non-empty row
   RowCursor rc;
   rc.mask = 0;
@@ -453,12 +519,16 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
     __syncthreads();
   }
   if (!cr.valid || kbeg > kend) return;
+  const float* xb = xw - win_slot(cmin) * NRHS;
   const int lane = threadIdx.x & (kWave - 1);
-  float W[kRowSlots][NRHS];
+  // long rows: slot sums (valid in lane 63); short rows: lane sums
+  float W[kRowSlots][NRHS], L[NRHS];
 #pragma unroll
-  for (int s = 0; s < kRowSlots; ++s)
+  for (int q = 0; q < NRHS; ++q) {
+    L[q] = -0.0f;
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) W[s][q] = 0.0f;
+    for (int s = 0; s < kRowSlots; ++s) W[s][q] = 0.0f;
+  }
   int k = kbeg;
   while (true) {
 #pragma unroll
@@ -466,37 +536,58 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
       const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
       Gathered<NRHS> g;
       gather_global<VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
-      load_step<VF, SM, IX>(a, origin, k + DEPTH * stride, pmin, pmax, cs[nxt]);
+      load_step<VF, IX>(vb, cb, k + DEPTH * stride, pmin, pmax, cs[nxt]);
       // keep the scheduler from sinking the loads below the compute
       __builtin_amdgcn_sched_barrier(0);
       float p[kChunk][NRHS];
-      products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xw, cmin, clen, p);
-      const int pn1 = quarter_pos(k, lane, 0), pn2 = quarter_pos(k, lane, 1);
+      products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+      const int s0 = k * kStepEntries;
+      const int pq = s0 + lane * kQuarter;
       // the rows that meet step k (none once the wave is past its last step)
-      while (k <= kend && cr.valid && cr.ks < (k + 1) * kStepEntries) {
-        float c[NRHS];
-        chunk_sum<NRHS>(p, pn1, pn2, cr.ks, cr.ke, c);
-        const int slot = (k - cr.kfirst) & (kRowSlots - 1);
+      while (k <= kend && cr.valid && cr.ks < s0 + kStepEntries) {
+        const bool lng = SPLIT || cr.lng;
+        if (lng) {
+          float h0[NRHS], h1[NRHS];
+          if (cr.ks <= s0 && cr.ke >= s0 + kStepEntries) {
+            quarter_full<0, NRHS>(p, h0);
+            quarter_full<1, NRHS>(p, h1);
+          } else {
+            const uint32_t len = static_cast<uint32_t>(cr.ke - cr.ks);
+            quarter_sum<0, NRHS>(p, pq - cr.ks, len, h0);
+            quarter_sum<1, NRHS>(p, pq + kHalf - cr.ks, len, h1);
+          }
+          const int slot = (k - cr.kfirst) & (kRowSlots - 1);
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) {
-          const float t = wave_reduce(c[q]);
+          for (int q = 0; q < NRHS; ++q) {
+            const float t = wave_reduce(h0[q] + h1[q]);
 #pragma unroll
-          for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : 0.0f;
+            for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : 0.0f;
+          }
+        } else {
+          add_half<0, NRHS>(p, s0, pq, cr, L);
+          add_half<1, NRHS>(p, s0, pq, cr, L);
         }
         if (k + stride <= cr.klast) break;  // the row goes on in a later step of this wave
         // the wave's last step of the row; slots that received nothing hold
         // +0, and no slot sum is ever -0, so adding them changes nothing
+        if (lng) {
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
+          for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < NRHS; ++q) tot[q] = wave_reduce(L[q]);
+        }
         if constexpr (SM == kScaleRow) sc = a.scale[cr.row];
         if constexpr (SPLIT) {
           cr.valid = false;
         } else {
           if (lane == kWave - 1) store_row<SM, NRHS>(a, cr.row, sc, tot);
 #pragma unroll
-          for (int s = 0; s < kRowSlots; ++s)
+          for (int q = 0; q < NRHS; ++q) {
+            L[q] = -0.0f;
 #pragma unroll
-            for (int q = 0; q < NRHS; ++q) W[s][q] = 0.0f;
+            for (int s = 0; s < kRowSlots; ++s) W[s][q] = 0.0f;
+          }
           cr = next_row<NRHS>(a, rc, r_end, origin32);
         }
       }
@@ -609,7 +700,10 @@ hipError_t launch_rhs_batched(int n_rhs, int idx_bytes, const SpmvArgs* args, co
   return hipGetLastError();
 }
 
-// Column window of every group: min and max column over its entries.
+// Column window of every group: the smallest and largest column over the
+// entries its waves load -- its own entries widened to whole 4-entry quarters
+// at both ends (the neighbours' entries there, or padding, which repeats the
+// last column) -- with the first column rounded down to a multiple of 8.
 template <class I>
 __global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ groups, int64_t n_groups,
                                                        const I* __restrict__ col,
@@ -618,9 +712,11 @@ __global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ g
   const GroupDesc g = groups[blockIdx.x];
   const uint32_t base32 = static_cast<uint32_t>(g.nnz_base);
   const uint64_t n = static_cast<uint64_t>(row_ptr[g.row[kGroupWaves]] - base32);
+  const uint64_t first = g.nnz_base & ~uint64_t{kQuarterEntries - 1};
+  const uint64_t span = n == 0 ? 0 : ((g.nnz_base + n - 1) | uint64_t{kQuarterEntries - 1}) + 1 - first;
   int mn = 0x7fffffff, mx = -1;
-  for (uint64_t k = threadIdx.x; k < n; k += 256) {
-    const int c = static_cast<int>(col[g.nnz_base + k]);
+  for (uint64_t k = threadIdx.x; k < span; k += 256) {
+    const int c = static_cast<int>(col[first + k]);
     mn = min(mn, c);
     mx = max(mx, c);
   }
@@ -635,8 +731,9 @@ __global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ g
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    groups[blockIdx.x].cmin = smax[0] >= 0 ? static_cast<uint32_t>(smin[0]) : 0u;
-    groups[blockIdx.x].clen = smax[0] >= 0 ? static_cast<uint32_t>(smax[0] - smin[0] + 1) : 0u;
+    const int c0 = smin[0] & ~(kWinAlign - 1);
+    groups[blockIdx.x].cmin = smax[0] >= 0 ? static_cast<uint32_t>(c0) : 0u;
+    groups[blockIdx.x].clen = smax[0] >= 0 ? static_cast<uint32_t>(smax[0] - c0 + 1) : 0u;
   }
   (void)n_groups;
 }
