@@ -79,16 +79,17 @@ struct SpmvArgs {
 // Entries of a quarter: lane l of a step loads the 4 entries at 4 l and at
 // 256 + 4 l of it.
 constexpr int kQuarterEntries = kChunk / 2;
-// A group's x window starts at a multiple of this many columns.
+// A group's x window starts at a multiple of this many columns (so that its
+// copy moves 16-byte pieces of x).
 constexpr int kWinAlign = 8;
 
 // Largest LDS x window of one workgroup, in floats (48 KB).
 constexpr int kWinFloatsMax = 12288;
 
-// LDS floats a window of `clen` columns needs for n_rhs vectors: one padding
-// slot every 8 columns keeps a wave's stride-8 reads free of bank conflicts.
+// LDS floats a window of `clen` columns needs for n_rhs vectors (x's own
+// layout: column-major runs of n_rhs floats).
 __host__ __device__ constexpr int64_t window_floats(uint32_t clen, int n_rhs) {
-  return clen == 0 ? 0 : (static_cast<int64_t>(clen - 1) + ((clen - 1) >> 3) + 1) * n_rhs;
+  return static_cast<int64_t>(clen) * n_rhs;
 }
 
 // ------------------------------------------------------------ launchers

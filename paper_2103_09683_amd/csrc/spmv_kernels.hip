@@ -155,17 +155,6 @@ struct Chunk {
   ColQuad<IX> ca, cb;
 };
 
-// LDS slot of x window column t (counted from the window's first column, a
-// multiple of 8): one padding slot every 8 columns spreads a wave's reads of
-// nearby columns over more banks.  Since the window starts at a multiple of 8,
-// win_slot(c - cmin) = win_slot(c) - win_slot(cmin): a column's slot is
-// win_slot(c) from a base moved back by win_slot(cmin), one shift, one add
-// and one shift-add to an LDS address.
-__device__ __forceinline__ int win_slot(int t) {
-  const uint32_t u = static_cast<uint32_t>(t);
-  return static_cast<int>(u + (u >> 3));
-}
-
 template <int NRHS>
 struct XVec {
   float v[NRHS];
@@ -190,16 +179,14 @@ __device__ __forceinline__ XVec<NRHS> load_x_global(const float* x, int c) {
   return r;
 }
 
-// x of window column c: xb is the window moved back by win_slot(cmin) slots
-// (below the window when cmin > 0; every c read lies inside it).
+// x of window column c: xb is the window moved back by cmin columns (below
+// the window when cmin > 0; every c read lies inside it).
 template <int NRHS>
 __device__ __forceinline__ XVec<NRHS> load_x_window(const float* xb, int c) {
   XVec<NRHS> r;
-  // the slot as an opaque value: the compiler would otherwise spread the
-  // address shift over both terms of the slot (four instructions, not three)
-  int slot = win_slot(c);
-  asm("" : "+v"(slot));
-  const float* p = xb + slot * NRHS;
+  // the column as an opaque value, so that the address is one shift-add
+  asm("" : "+v"(c));
+  const float* p = xb + c * NRHS;
   if constexpr (NRHS == 1) {
     r.v[0] = p[0];
   } else if constexpr (NRHS == 2) {
@@ -468,18 +455,23 @@ __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float
 // register is copied, left at one place only so that the compiler's view of
 // the loads in flight stays exact).  In each step the rows that meet it take
 // their entries in the order described at the top of this file.  With WIN
-// the workgroup first copies the x window [cmin, cmin + clen) into LDS:
-// every wave issues its first loads before that copy and its barrier.  All
-// waves reach the barrier.  Without SPLIT each finished row is stored; with
-// SPLIT the wave's slot sum is left in `tot` and the row scale in `sc`.
+// the workgroup first copies the x window [cmin, cmin + clen) into LDS (x's
+// layout, so a column c is at xw + (c - cmin) * NRHS); every wave issues its
+// first loads before the copy's barrier, which all waves reach.  `safe` is
+// any readable 16-byte aligned address (the group's descriptor).  Without
+// SPLIT each finished row is stored; with SPLIT the wave's slot sum is left in
+// `tot` and the row scale in `sc`.
 // Steps whose loads are in flight ahead of the one computed (deeper rings were
 // measured no faster on the clinical beam and the largest workload).
 constexpr int kDepth = 1;
+// 16-byte pieces of the x window each thread loads at once (a one-vector
+// window of 4096 floats in one batch).
+constexpr int kCopy = 4;
 
 template <int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT>
 __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
-                                            float (&tot)[NRHS], float& sc) {
+                                            const void* safe, float (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
   constexpr int DEPTH = IX == 2 ? 2 : kDepth;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
@@ -496,30 +488,66 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   const int pmin = p0 & ~(kQuarter - 1), pmax = max(p1 - 1, p0) & ~(kQuarter - 1);
   const int kbeg = (p0 >> 9) + (SPLIT ? first : 0);
   const int kend = p1 > p0 ? (p1 - 1) >> 9 : -1;  // the wave's last step (inclusive)
-  Chunk<VF, IX> cs[DEPTH + 1];
-#pragma unroll
-  for (int d = 0; d < DEPTH; ++d) load_step<VF, IX>(vb, cb, kbeg + d * stride, pmin, pmax, cs[d]);
-  // the wave's first row window and first non-empty row
+  // The group's first loads, in the order they are needed: the x window
+  // (16-byte pieces of x, a thread's first kCopy of them at once), the wave's
+  // first 64 row offsets, then the stream's first steps; waiting for the first
+  // two leaves the stream in flight.  Without this order each wait would also
+  // wait for the stream, and a copy loop would wait once per piece.
+  const int nf = clen * NRHS;  // window floats (the window is x's own layout)
+  const int n4 = nf >> 2;      // whole 16-byte pieces (x + cmin * NRHS is 32-byte aligned within x)
+  const float* xs = a.x + static_cast<int64_t>(cmin) * NRHS;
+  // every load is issued (a lane without a piece reads the group descriptor
+  // instead), so that the compiler's count of loads in flight stays exact
+  const int tid = static_cast<int>(threadIdx.x);
+  const float4* xs4 = reinterpret_cast<const float4*>(xs);
+  const float4* safe4 = static_cast<const float4*>(safe);
+  float4 w0, w1, w2, w3;  // pieces tid, tid + 256, tid + 512, tid + 768
+  float wt = 0.0f;
+  if constexpr (WIN) {
+    w0 = *(tid < n4 ? xs4 + tid : safe4);
+    w1 = *(tid + kGroupThreads < n4 ? xs4 + tid + kGroupThreads : safe4);
+    w2 = *(tid + 2 * kGroupThreads < n4 ? xs4 + tid + 2 * kGroupThreads : safe4);
+    w3 = *(tid + 3 * kGroupThreads < n4 ? xs4 + tid + 3 * kGroupThreads : safe4);
+    const int t = 4 * n4 + tid;  // the last nf mod 4 floats
+    wt = *(t < nf ? xs + t : static_cast<const float*>(safe));
+  }
   RowCursor rc;
   rc.mask = 0;
   Row cr;
   cr.valid = false;
-  if (r_begin < r_end) {
-    fetch_rows(a, rc, r_begin, r_end, origin32);
+  const bool has_rows = r_begin < r_end;
+  // issued by every wave (one without rows re-reads a row before r_begin, or
+  // row 0), so that no branch hides it from the compiler's load count
+  fetch_rows(a, rc, r_begin, has_rows ? r_end : max(r_begin, 1u), origin32);
+  // With an LDS window and no global gathers, a step's buffer is refilled
+  // (DEPTH + 1 steps ahead) as soon as its products are formed, before the
+  // step's rows are summed: the row work then delays no load.  Global
+  // gathers must be issued before the next step's loads (so that waiting for
+  // them leaves those loads in flight), so there the buffer of the previous
+  // step is refilled first.
+  constexpr bool kEarly = WIN && SM != kScaleCol;
+  Chunk<VF, IX> cs[DEPTH + 1];
+#pragma unroll
+  for (int d = 0; d < (kEarly ? DEPTH + 1 : DEPTH); ++d) load_step<VF, IX>(vb, cb, kbeg + d * stride, pmin, pmax, cs[d]);
+  if (has_rows) {
+    // the wave's first non-empty row; next_row moves on from rc.wb + 64 once
+    // the first row window is done
     settle_rows<NRHS>(a, rc, r_end);
-    // next_row moves on from rc.wb + 64 once the first window is done
     cr = next_row<NRHS>(a, rc, r_end, origin32);
   }
   if constexpr (WIN) {
-    for (int t = threadIdx.x; t < clen; t += kGroupThreads) {
-      const XVec<NRHS> v = load_x_global<NRHS>(a.x, cmin + t);
-#pragma unroll
-      for (int q = 0; q < NRHS; ++q) xw[win_slot(t) * NRHS + q] = v.v[q];
-    }
+    float4* xw4 = reinterpret_cast<float4*>(xw);
+    if (tid < n4) xw4[tid] = w0;
+    if (tid + kGroupThreads < n4) xw4[tid + kGroupThreads] = w1;
+    if (tid + 2 * kGroupThreads < n4) xw4[tid + 2 * kGroupThreads] = w2;
+    if (tid + 3 * kGroupThreads < n4) xw4[tid + 3 * kGroupThreads] = w3;
+    if (4 * n4 + tid < nf) xw[4 * n4 + tid] = wt;
+    // windows larger than one batch (several vectors)
+    for (int j = tid + kCopy * kGroupThreads; j < n4; j += kGroupThreads) xw4[j] = xs4[j];
     __syncthreads();
   }
   if (!cr.valid || kbeg > kend) return;
-  const float* xb = xw - win_slot(cmin) * NRHS;
+  const float* xb = xw - cmin * NRHS;
   const int lane = threadIdx.x & (kWave - 1);
   // long rows: slot sums (valid in lane 63); short rows: lane sums
   float W[kRowSlots][NRHS], L[NRHS];
@@ -535,12 +563,21 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
     for (int ph = 0; ph <= DEPTH; ++ph) {
       const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
       Gathered<NRHS> g;
-      gather_global<VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
-      load_step<VF, IX>(vb, cb, k + DEPTH * stride, pmin, pmax, cs[nxt]);
-      // keep the scheduler from sinking the loads below the compute
-      __builtin_amdgcn_sched_barrier(0);
       float p[kChunk][NRHS];
-      products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+      if constexpr (kEarly) {
+        products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+        // the barriers keep the scheduler from moving the loads across the
+        // products or sinking them below the row work
+        __builtin_amdgcn_sched_barrier(0);
+        load_step<VF, IX>(vb, cb, k + (DEPTH + 1) * stride, pmin, pmax, cs[cur]);
+        __builtin_amdgcn_sched_barrier(0);
+      } else {
+        gather_global<VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
+        load_step<VF, IX>(vb, cb, k + DEPTH * stride, pmin, pmax, cs[nxt]);
+        // keep the scheduler from sinking the loads below the compute
+        __builtin_amdgcn_sched_barrier(0);
+        products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+      }
       const int s0 = k * kStepEntries;
       const int pq = s0 + lane * kQuarter;
       // the rows that meet step k (none once the wave is past its last step)
@@ -613,18 +650,18 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
     const uint32_t e0 = wave == 0 ? 0u : gp->ent[wave - 1], e1 = gp->ent[wave];
     if (win)
-      wave_stream<VF, SM, IX, NRHS, true, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), tot,
-                                                    sc);
+      wave_stream<VF, SM, IX, NRHS, true, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), gp,
+                                                    tot, sc);
     else
-      wave_stream<VF, SM, IX, NRHS, false, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, tot, sc);
+      wave_stream<VF, SM, IX, NRHS, false, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, gp, tot, sc);
     return;
   }
   const uint32_t row = gp->row[0], len = gp->ent[kGroupWaves - 1];
   if (win)
     wave_stream<VF, SM, IX, NRHS, true, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
-                                                 tot, sc);
+                                                 gp, tot, sc);
   else
-    wave_stream<VF, SM, IX, NRHS, false, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, tot, sc);
+    wave_stream<VF, SM, IX, NRHS, false, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, gp, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
