@@ -461,8 +461,10 @@ __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float
 // any readable 16-byte aligned address (the group's descriptor).  Without
 // SPLIT each finished row is stored; with SPLIT the wave's slot sum is left in
 // `tot` and the row scale in `sc`.
-// Steps whose loads are in flight ahead of the one computed (deeper rings were
-// measured no faster on the clinical beam and the largest workload).
+// Steps whose loads are in flight ahead of the one computed, besides the
+// refill (deeper rings were measured no faster for every value and index
+// format on the clinical beam: the loads they issue past a wave's last step
+// cost more than the added depth gains).
 constexpr int kDepth = 1;
 // 16-byte pieces of the x window each thread loads at once (a one-vector
 // window of 4096 floats in one batch).
@@ -473,7 +475,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
                                             const void* safe, float (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
-  constexpr int DEPTH = IX == 2 ? 2 : kDepth;
+  constexpr int DEPTH = kDepth;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
   const uint32_t origin32 = static_cast<uint32_t>(origin);
   const char* vb = static_cast<const char*>(a.val) + origin * Codes<VF>::kBytes;
