@@ -127,7 +127,9 @@ dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf,
  * row of A, with the same decoded values.  Uses the device that is current
  * on the calling thread; blocks until its uploads on `hip_stream` finish, so
  * the caller may free the host arrays on return.  *out owns all device memory
- * of the matrix until dose_matrix_destroy. */
+ * of the matrix until dose_matrix_destroy.  DOSE_ERR_UNSUPPORTED also when a
+ * row of A (or, with DOSE_CREATE_TRANSPOSE, of A^T: a column of A) holds 2^28
+ * or more entries, or the transpose would hold 2^31 or more. */
 dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf,
                                dose_index_format xf, uint32_t flags, void* hip_stream,
                                dose_matrix* out);
@@ -153,8 +155,10 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info);
 dose_status dose_matrix_destroy(dose_matrix m);
 
 /* y = A x (Listing 1 of the paper; the dose in every voxel).
- * x: device, n_cols FP32.  y: device, n_rows FP32, every entry written (+0 for
- * empty rows).  x and y must not overlap.  Asynchronous on hip_stream. */
+ * x: device, n_cols FP32, 4-byte aligned (16-byte alignment is faster: the
+ * kernels read x in 16-byte pieces).  y: device, n_rows FP32, every entry
+ * written (+0 for empty rows).  x and y must not overlap.  Asynchronous on
+ * hip_stream. */
 dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream);
 
 /* g = A^T v, the gradient of an objective of the dose with respect to the
