@@ -155,8 +155,8 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info);
 dose_status dose_matrix_destroy(dose_matrix m);
 
 /* y = A x (Listing 1 of the paper; the dose in every voxel).
- * x: device, n_cols FP32, 4-byte aligned (16-byte alignment is faster: the
- * kernels read x in 16-byte pieces).  y: device, n_rows FP32, every entry
+ * x: device, n_cols FP32, 4-byte aligned, else DOSE_ERR_INVALID_ARGUMENT
+ * (16-byte alignment is faster: the kernels read x in 16-byte pieces).  y: device, n_rows FP32, every entry
  * written (+0 for empty rows).  x and y must not overlap.  Asynchronous on
  * hip_stream. */
 dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream);
@@ -166,6 +166,7 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
  * (plan optimisation needs gradients every iteration, Sec. I).  Runs the same
  * kernels on the stored transpose: deterministic, no atomics.
  * v: device, n_rows FP32.  g: device, n_cols FP32, every entry written.
+ * Both 4-byte aligned (else DOSE_ERR_INVALID_ARGUMENT, as for x and y).
  * DOSE_ERR_NO_TRANSPOSE without DOSE_CREATE_TRANSPOSE. */
 dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* g, void* hip_stream);
 

@@ -825,6 +825,8 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
     if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
     if ((m->A.n_cols > 0 && !x) || (m->A.n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
     if (overlaps(x, m->A.n_cols * 4, y, m->A.n_rows * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 4 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be 4-byte aligned");
     DeviceGuard g(m->device);
     run_product(m, m->A, scale_mode_A(m), 1, x, y, as_stream(hip_stream));
   });
@@ -836,6 +838,8 @@ dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* gout, void* 
     if (!m->has_t) fail(DOSE_ERR_NO_TRANSPOSE, "matrix was created without DOSE_CREATE_TRANSPOSE");
     if ((m->A.n_rows > 0 && !v) || (m->A.n_cols > 0 && !gout)) fail(DOSE_ERR_INVALID_ARGUMENT, "null v or g");
     if (overlaps(v, m->A.n_rows * 4, gout, m->A.n_cols * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "v and g overlap");
+    if ((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(gout)) % 4 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "v and g must be 4-byte aligned");
     DeviceGuard g(m->device);
     run_product(m, m->AT, scale_mode_AT(m), 1, v, gout, as_stream(hip_stream));
   });

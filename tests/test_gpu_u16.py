@@ -87,3 +87,22 @@ def test_u16_rejects_wide_matrices_and_mixed_batches(dev):
         dm.spmv_batched([(A, x, y1), (B, x, y2)])
     A.close()
     B.close()
+
+
+def test_misaligned_vectors_rejected(dev):
+    """x, y, v, g must be 4-byte aligned: the C ABI rejects others before any
+    launch."""
+    from paper_2103_09683_amd import _lib
+    rp = np.array([0, 2, 3], np.int64)
+    cols = np.array([0, 3, 1], np.int32)
+    vals = np.ones(3, np.float32)
+    A = dm.DoseMatrix(rp, cols, vals, 4, "fp16", transpose=True)
+    buf = torch.zeros(64, device=dev)
+    lib = _lib.load()
+    base = buf.data_ptr()
+    assert lib.dose_spmv(A.handle, base + 2, base + 128, None) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dose_spmv(A.handle, base, base + 130, None) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dose_spmv_adjoint(A.handle, base + 1, base + 128, None) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dose_spmv(A.handle, base, base + 128, None) == _lib.OK
+    torch.cuda.synchronize()
+    A.close()
