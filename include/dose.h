@@ -170,6 +170,20 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
  * DOSE_ERR_NO_TRANSPOSE without DOSE_CREATE_TRANSPOSE. */
 dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* g, void* hip_stream);
 
+/* The same products with FP64 vectors and FP64 products and sums: the
+ * paper's half/double configuration (Sec. II-D: FP16 matrix values, FP64
+ * spot weights and dose).  The stored matrix is the same (any value and
+ * index format); each product is decoded exactly to FP64, the row sums
+ * follow the order of the FP32 products in FP64, and the E4M3 row scale
+ * multiplies the FP64 row sum (forward) or the code in FP32, as in the FP32
+ * adjoint (adjoint).  x (v): device, n_cols (n_rows) FP64; y (g): device,
+ * n_rows (n_cols) FP64, every entry written; all 8-byte aligned, else
+ * DOSE_ERR_INVALID_ARGUMENT; inputs and outputs must not overlap.
+ * Asynchronous on hip_stream.  The adjoint needs DOSE_CREATE_TRANSPOSE
+ * (else DOSE_ERR_NO_TRANSPOSE). */
+dose_status dose_spmv_f64(dose_matrix m, const double* x, double* y, void* hip_stream);
+dose_status dose_spmv_adjoint_f64(dose_matrix m, const double* v, double* g, void* hip_stream);
+
 /* One item of a batched product: y = A x for n_rhs spot-weight vectors,
  * x stored [n_cols][ldx] and y [n_rows][ldy] (vector r at offset r).
  * n_rhs is 1, 2 or 4; ldx == ldy == n_rhs. */

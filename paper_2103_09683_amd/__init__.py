@@ -33,11 +33,11 @@ def _stream_handle(stream) -> int | None:
     return stream.cuda_stream
 
 
-def _dev_ptr(t: torch.Tensor, n: int, name: str, device=None) -> int:
+def _dev_ptr(t: torch.Tensor, n: int, name: str, device=None, dtype=torch.float32) -> int:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA tensor")
-    if t.dtype != torch.float32 or not t.is_contiguous():
-        raise TypeError(f"{name} must be contiguous float32")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous {str(dtype).replace('torch.', '')}")
     if t.numel() != n:
         raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
     if device is not None and t.device != device:
@@ -159,22 +159,27 @@ class DoseMatrix:
         return rp, cols[:n], vals[:n]
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """y = A x (FP32), asynchronous on the current (or given) stream."""
+        """y = A x, asynchronous on the current (or given) stream.  FP32 x
+        gives FP32 y; FP64 x gives FP64 y with FP64 products and sums (the
+        paper's half/double configuration)."""
+        f64 = x.dtype == torch.float64
+        dt = torch.float64 if f64 else torch.float32
         if y is None:
-            y = torch.empty(self.n_rows, dtype=torch.float32, device=x.device)
-        _lib.check(_lib.load().dose_spmv(self.handle, _dev_ptr(x, self.n_cols, "x", self.device),
-                                         _dev_ptr(y, self.n_rows, "y", self.device),
-                                         _stream_handle(stream)))
+            y = torch.empty(self.n_rows, dtype=dt, device=x.device)
+        fn = _lib.load().dose_spmv_f64 if f64 else _lib.load().dose_spmv
+        _lib.check(fn(self.handle, _dev_ptr(x, self.n_cols, "x", self.device, dt),
+                      _dev_ptr(y, self.n_rows, "y", self.device, dt), _stream_handle(stream)))
         return y
 
     def adjoint(self, v: torch.Tensor, g: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """g = A^T v (FP32), asynchronous."""
+        """g = A^T v, asynchronous; FP64 v gives FP64 g as for spmv."""
+        f64 = v.dtype == torch.float64
+        dt = torch.float64 if f64 else torch.float32
         if g is None:
-            g = torch.empty(self.n_cols, dtype=torch.float32, device=v.device)
-        _lib.check(_lib.load().dose_spmv_adjoint(self.handle,
-                                                 _dev_ptr(v, self.n_rows, "v", self.device),
-                                                 _dev_ptr(g, self.n_cols, "g", self.device),
-                                                 _stream_handle(stream)))
+            g = torch.empty(self.n_cols, dtype=dt, device=v.device)
+        fn = _lib.load().dose_spmv_adjoint_f64 if f64 else _lib.load().dose_spmv_adjoint
+        _lib.check(fn(self.handle, _dev_ptr(v, self.n_rows, "v", self.device, dt),
+                      _dev_ptr(g, self.n_cols, "g", self.device, dt), _stream_handle(stream)))
         return g
 
     def close(self) -> None:

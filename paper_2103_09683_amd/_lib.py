@@ -65,6 +65,8 @@ SIGNATURES = {
     "dose_matrix_destroy": ([_vp], _i32),
     "dose_spmv": ([_vp, _vp, _vp, _vp], _i32),
     "dose_spmv_adjoint": ([_vp, _vp, _vp, _vp], _i32),
+    "dose_spmv_f64": ([_vp, _vp, _vp, _vp], _i32),
+    "dose_spmv_adjoint_f64": ([_vp, _vp, _vp, _vp], _i32),
     "dose_spmv_batched": ([ctypes.POINTER(BatchItem), _i32, _vp], _i32),
     "dose_batch_plan_create": ([ctypes.POINTER(BatchItem), _i32, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_batch_plan_launch": ([_vp, _vp], _i32),

@@ -367,7 +367,8 @@ namespace {
 int scale_mode_A(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleRow : kScaleNone; }
 int scale_mode_AT(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleCol : kScaleNone; }
 
-SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const float* x, float* y) {
+// n_rhs sizes the LDS window (an FP64 vector takes the window of two FP32 ones).
+SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const void* x, void* y) {
   SpmvArgs a{};
   a.win_floats = op.win_floats[rhs_slot(n_rhs)];
   a.groups = op.groups.get<GroupDesc>();
@@ -829,6 +830,33 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
       fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be 4-byte aligned");
     DeviceGuard g(m->device);
     run_product(m, m->A, scale_mode_A(m), 1, x, y, as_stream(hip_stream));
+  });
+}
+
+dose_status dose_spmv_f64(dose_matrix m, const double* x, double* y, void* hip_stream) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    if ((m->A.n_cols > 0 && !x) || (m->A.n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
+    if (overlaps(x, m->A.n_cols * 8, y, m->A.n_rows * 8)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 8 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be 8-byte aligned");
+    DeviceGuard g(m->device);
+    const int sm = scale_mode_A(m);
+    HIP_CHECK(launch_spmv_f64(m->vf, sm, make_args(m, m->A, sm, 2, x, y), as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_spmv_adjoint_f64(dose_matrix m, const double* v, double* gout, void* hip_stream) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    if (!m->has_t) fail(DOSE_ERR_NO_TRANSPOSE, "matrix was created without DOSE_CREATE_TRANSPOSE");
+    if ((m->A.n_rows > 0 && !v) || (m->A.n_cols > 0 && !gout)) fail(DOSE_ERR_INVALID_ARGUMENT, "null v or g");
+    if (overlaps(v, m->A.n_rows * 8, gout, m->A.n_cols * 8)) fail(DOSE_ERR_INVALID_ARGUMENT, "v and g overlap");
+    if ((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(gout)) % 8 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "v and g must be 8-byte aligned");
+    DeviceGuard g(m->device);
+    const int sm = scale_mode_AT(m);
+    HIP_CHECK(launch_spmv_f64(m->vf, sm, make_args(m, m->AT, sm, 2, v, gout), as_stream(hip_stream)));
   });
 }
 

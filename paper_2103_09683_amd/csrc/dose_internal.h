@@ -69,10 +69,10 @@ struct SpmvArgs {
   const void* col;          // column indices (int32, or uint16 when idx_bytes is 2), padded by kStreamPad
   const uint32_t* row_ptr;  // n_rows+1 offsets modulo 2^32
   const float* scale;       // row or column scale (E4M3), else null
-  const float* x;           // [n_cols][n_rhs]
-  float* y;                 // [n_rows][n_rhs]
+  const void* x;            // [n_cols][n_rhs] FP32, or [n_cols] FP64 (launch_spmv_f64)
+  void* y;                  // [n_rows][n_rhs] FP32, or [n_rows] FP64
   int64_t n_groups;
-  int32_t win_floats;       // LDS floats for the x window (dynamic shared memory)
+  int32_t win_floats;       // LDS 4-byte words for the x window (dynamic shared memory)
   int32_t idx_bytes;        // 4 or 2
 };
 
@@ -94,6 +94,9 @@ __host__ __device__ constexpr int64_t window_floats(uint32_t clen, int n_rhs) {
 
 // ------------------------------------------------------------ launchers
 hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s);
+// One FP64 vector: x, y FP64, products and sums FP64; a.win_floats sized as
+// for two FP32 vectors (a window column is 8 bytes).
+hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_t s);
 // Batched launch: one workgroup per entry of d_work, the groups of all items
 // (copies of their descriptors, each naming its item in d_args).
 hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SpmvArgs* d_args,

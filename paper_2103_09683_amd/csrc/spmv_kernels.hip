@@ -155,14 +155,16 @@ struct Chunk {
   ColQuad<IX> ca, cb;
 };
 
-template <int NRHS>
+// The vector type: FP32, or FP64 for the FP64 product (one vector).
+template <class T, int NRHS>
 struct XVec {
-  float v[NRHS];
+  T v[NRHS];
 };
 
-template <int NRHS>
-__device__ __forceinline__ XVec<NRHS> load_x_global(const float* x, int c) {
-  XVec<NRHS> r;
+template <class T, int NRHS>
+__device__ __forceinline__ XVec<T, NRHS> load_x_global(const T* x, int c) {
+  static_assert(NRHS == 1 || sizeof(T) == 4, "several vectors are FP32");
+  XVec<T, NRHS> r;
   if constexpr (NRHS == 1) {
     r.v[0] = x[c];
   } else if constexpr (NRHS == 2) {
@@ -181,12 +183,13 @@ __device__ __forceinline__ XVec<NRHS> load_x_global(const float* x, int c) {
 
 // x of window column c: xb is the window moved back by cmin columns (below
 // the window when cmin > 0; every c read lies inside it).
-template <int NRHS>
-__device__ __forceinline__ XVec<NRHS> load_x_window(const float* xb, int c) {
-  XVec<NRHS> r;
+template <class T, int NRHS>
+__device__ __forceinline__ XVec<T, NRHS> load_x_window(const T* xb, int c) {
+  static_assert(NRHS == 1 || sizeof(T) == 4, "several vectors are FP32");
+  XVec<T, NRHS> r;
   // the column as an opaque value, so that the address is one shift-add
   asm("" : "+v"(c));
-  const float* p = xb + c * NRHS;
+  const T* p = xb + c * NRHS;
   if constexpr (NRHS == 1) {
     r.v[0] = p[0];
   } else if constexpr (NRHS == 2) {
@@ -227,6 +230,25 @@ __device__ __forceinline__ float wave_reduce(float v) {
   return v;
 }
 
+// The same tree for FP64 values, each DPP move taking the two halves.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u), CTRL, ROW_MASK, 0xf, false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u >> 32), CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+__device__ __forceinline__ double wave_reduce(double v) {
+  constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+  v += dpp_f64<kRowShr + 1, 0xf>(v);
+  v += dpp_f64<kRowShr + 2, 0xf>(v);
+  v += dpp_f64<kRowShr + 4, 0xf>(v);
+  v += dpp_f64<kRowShr + 8, 0xf>(v);
+  v += dpp_f64<kRowBcast15, 0xa>(v);
+  v += dpp_f64<kRowBcast31, 0xc>(v);
+  return v;
+}
+
 // Positions.  A group's entries are addressed by their position P relative
 // to the group's origin, its first entry rounded down to a multiple of 512:
 // step k of the group covers positions [512 k, 512 k + 512), and lane l's
@@ -255,15 +277,15 @@ __device__ __forceinline__ void fetch_rows(const SpmvArgs& a, RowCursor& rc, uin
 }
 
 // Lists the fetched window's non-empty rows and writes +0 to its empty ones.
-template <int NRHS>
+template <class T, int NRHS>
 __device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, uint32_t r_end) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t r = rc.wb + lane;
   const bool in = r < r_end;
   if (in && rc.hi == rc.lo) {
-    float* dst = a.y + static_cast<int64_t>(r) * NRHS;
+    T* dst = static_cast<T*>(a.y) + static_cast<int64_t>(r) * NRHS;
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) dst[q] = 0.0f;
+    for (int q = 0; q < NRHS; ++q) dst[q] = T(0);
   }
   rc.mask = __ballot(in && rc.hi > rc.lo);
 }
@@ -279,7 +301,7 @@ struct Row {
 
 // The wave's next non-empty row, moving on to later 64-row windows (and
 // writing +0 to the empty rows passed) when the current one is done.
-template <int NRHS>
+template <class T, int NRHS>
 __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32_t r_end, uint32_t origin32) {
   Row n;
   while (rc.mask == 0) {
@@ -289,7 +311,7 @@ __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32
       return n;
     }
     fetch_rows(a, rc, wb, r_end, origin32);
-    settle_rows<NRHS>(a, rc, r_end);
+    settle_rows<T, NRHS>(a, rc, r_end);
   }
   const int i = __builtin_ctzll(rc.mask);
   rc.mask &= rc.mask - 1;
@@ -320,9 +342,9 @@ __device__ __forceinline__ void load_step(const char* vb, const char* cb, int k,
   ch.cb.load(cb, e2);
 }
 
-template <int NRHS>
+template <class T, int NRHS>
 struct Gathered {
-  XVec<NRHS> x[kChunk];
+  XVec<T, NRHS> x[kChunk];
   float sc[kChunk];  // column scales (kScaleCol)
 };
 
@@ -338,21 +360,22 @@ __device__ __forceinline__ void chunk_cols(const ColQuad<IX>& ca, const ColQuad<
 // Global-memory gathers of a step (x without a window, column scales of an
 // E4M3 A^T), issued before the next step's loads, so that waiting for them
 // leaves those loads in flight.
-template <int VF, int SM, int IX, int NRHS, bool WIN>
-__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF, IX>& ch, Gathered<NRHS>& g) {
+template <class T, int VF, int SM, int IX, int NRHS, bool WIN>
+__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF, IX>& ch, Gathered<T, NRHS>& g) {
   int cols[kChunk];
   chunk_cols(ch.ca, ch.cb, cols);
+  const T* x = static_cast<const T*>(a.x);
   if constexpr (!WIN) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e0 = h * kQuarter;
-      if (NRHS == 1 && cols[e0 + 3] - cols[e0] == kQuarter - 1) {
+      if (NRHS == 1 && sizeof(T) == 4 && cols[e0 + 3] - cols[e0] == kQuarter - 1) {
         // 4 consecutive columns (inside one row): one 16-byte load of x
-        const float4 v = *reinterpret_cast<const float4*>(a.x + cols[e0]);
+        const float4 v = *reinterpret_cast<const float4*>(x + cols[e0]);
         g.x[e0].v[0] = v.x, g.x[e0 + 1].v[0] = v.y, g.x[e0 + 2].v[0] = v.z, g.x[e0 + 3].v[0] = v.w;
       } else {
 #pragma unroll
-        for (int e = e0; e < e0 + kQuarter; ++e) g.x[e] = load_x_global<NRHS>(a.x, cols[e]);
+        for (int e = e0; e < e0 + kQuarter; ++e) g.x[e] = load_x_global<T, NRHS>(x, cols[e]);
       }
     }
   }
@@ -366,16 +389,16 @@ __device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF,
 // also those outside the wave's rows (their columns lie in the window; see
 // load_step); rows select their own entries afterwards, so no Inf or NaN of x
 // leaks into another row.  xb: the window base of load_x_window.
-template <int VF, int SM, int IX, int NRHS, bool WIN>
-__device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<NRHS>& g, const float* xb,
-                                         float (&p)[kChunk][NRHS]) {
+template <class T, int VF, int SM, int IX, int NRHS, bool WIN>
+__device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<T, NRHS>& g, const T* xb,
+                                         T (&p)[kChunk][NRHS]) {
   if constexpr (WIN) {
     int cols[kChunk];
     chunk_cols(ch.ca, ch.cb, cols);
 #pragma unroll
-    for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_window<NRHS>(xb, cols[e]);
+    for (int e = 0; e < kChunk; ++e) g.x[e] = load_x_window<T, NRHS>(xb, cols[e]);
   }
-  if constexpr (VF == kFp16) {
+  if constexpr (VF == kFp16 && sizeof(T) == 4) {
     // an FMA with +0 rounds the product once, as a multiply does
 #pragma unroll
     for (int e = 0; e < kChunk; ++e)
@@ -393,7 +416,7 @@ __device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<NRHS>
     for (int e = 0; e < kChunk; ++e) {
       const float de = SM == kScaleCol ? d[e] * g.sc[e] : d[e];
 #pragma unroll
-      for (int q = 0; q < NRHS; ++q) p[e][q] = de * g.x[e].v[q];
+      for (int q = 0; q < NRHS; ++q) p[e][q] = static_cast<T>(de) * g.x[e].v[q];
     }
   }
 }
@@ -402,22 +425,22 @@ __device__ __forceinline__ void products(const Chunk<VF, IX>& ch, Gathered<NRHS>
 // the entries at positions [ks, ks + len); d0 = the quarter's first position
 // minus ks.  An entry is in when its position minus ks, taken unsigned, is
 // below len; the others count as +0.
-template <int H, int NRHS>
-__device__ __forceinline__ void quarter_sum(const float (&p)[kChunk][NRHS], int d0, uint32_t len, float (&s)[NRHS]) {
-  float m[kQuarter][NRHS];
+template <class T, int H, int NRHS>
+__device__ __forceinline__ void quarter_sum(const T (&p)[kChunk][NRHS], int d0, uint32_t len, T (&s)[NRHS]) {
+  T m[kQuarter][NRHS];
 #pragma unroll
   for (int e = 0; e < kQuarter; ++e) {
     const bool in = static_cast<uint32_t>(d0 + e) < len;
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) m[e][q] = in ? p[H * kQuarter + e][q] : 0.0f;
+    for (int q = 0; q < NRHS; ++q) m[e][q] = in ? p[H * kQuarter + e][q] : T(0);
   }
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) s[q] = (m[0][q] + m[1][q]) + (m[2][q] + m[3][q]);
 }
 
 // The same for a quarter wholly inside the row.
-template <int H, int NRHS>
-__device__ __forceinline__ void quarter_full(const float (&p)[kChunk][NRHS], float (&s)[NRHS]) {
+template <class T, int H, int NRHS>
+__device__ __forceinline__ void quarter_full(const T (&p)[kChunk][NRHS], T (&s)[NRHS]) {
   constexpr int b = H * kQuarter;
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) s[q] = (p[b][q] + p[b + 1][q]) + (p[b + 2][q] + p[b + 3][q]);
@@ -426,26 +449,26 @@ __device__ __forceinline__ void quarter_full(const float (&p)[kChunk][NRHS], flo
 // A short row's entries in half H of step k (positions [s0 + 256 H, s0 + 256 H
 // + 256)), added to the lane accumulator L; pq = the lane's first quarter
 // position in the step.
-template <int H, int NRHS>
-__device__ __forceinline__ void add_half(const float (&p)[kChunk][NRHS], int s0, int pq, const Row& r,
-                                         float (&L)[NRHS]) {
+template <class T, int H, int NRHS>
+__device__ __forceinline__ void add_half(const T (&p)[kChunk][NRHS], int s0, int pq, const Row& r,
+                                         T (&L)[NRHS]) {
   const int hs = s0 + H * kHalf;
   if (r.ks >= hs + kHalf || r.ke <= hs) return;  // the row misses this half
-  float s[NRHS];
+  T s[NRHS];
   if (r.ks <= hs && r.ke >= hs + kHalf)
-    quarter_full<H, NRHS>(p, s);
+    quarter_full<T, H, NRHS>(p, s);
   else
-    quarter_sum<H, NRHS>(p, pq + H * kHalf - r.ks, static_cast<uint32_t>(r.ke - r.ks), s);
+    quarter_sum<T, H, NRHS>(p, pq + H * kHalf - r.ks, static_cast<uint32_t>(r.ke - r.ks), s);
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) L[q] += s[q];
 }
 
 // Row value (valid in lane 63) times the row scale of an E4M3 operand.
-template <int SM, int NRHS>
-__device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float sc, const float (&tot)[NRHS]) {
-  float* dst = a.y + static_cast<int64_t>(row) * NRHS;
+template <class T, int SM, int NRHS>
+__device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float sc, const T (&tot)[NRHS]) {
+  T* dst = static_cast<T*>(a.y) + static_cast<int64_t>(row) * NRHS;
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q) dst[q] = SM == kScaleRow ? tot[q] * sc : tot[q];
+  for (int q = 0; q < NRHS; ++q) dst[q] = SM == kScaleRow ? tot[q] * static_cast<T>(sc) : tot[q];
 }
 
 // One wave's share of a group: rows [r_begin, r_end), or with SPLIT the one
@@ -470,10 +493,10 @@ constexpr int kDepth = 1;
 // window of 4096 floats in one batch).
 constexpr int kCopy = 4;
 
-template <int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT>
+template <class T, int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT>
 __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
-                                            const void* safe, float (&tot)[NRHS], float& sc) {
+                                            const void* safe, T (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
   constexpr int DEPTH = kDepth;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
@@ -481,7 +504,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   const char* vb = static_cast<const char*>(a.val) + origin * Codes<VF>::kBytes;
   const char* cb = static_cast<const char*>(a.col) + origin * IX;
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q) tot[q] = 0.0f;
+  for (int q = 0; q < NRHS; ++q) tot[q] = T(0);
   sc = 1.0f;
   // the wave's positions [p0, p1) (from the group descriptor, so the first
   // loads go out at once) and its steps
@@ -495,9 +518,11 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   // first 64 row offsets, then the stream's first steps; waiting for the first
   // two leaves the stream in flight.  Without this order each wait would also
   // wait for the stream, and a copy loop would wait once per piece.
-  const int nf = clen * NRHS;  // window floats (the window is x's own layout)
-  const int n4 = nf >> 2;      // whole 16-byte pieces (x + cmin * NRHS is 32-byte aligned within x)
-  const float* xs = a.x + static_cast<int64_t>(cmin) * NRHS;
+  // window words of 4 bytes (the window is x's own layout), whole 16-byte
+  // pieces (x + cmin * NRHS is 32-byte aligned within x)
+  const int nf = clen * NRHS * static_cast<int>(sizeof(T) / 4);
+  const int n4 = nf >> 2;
+  const float* xs = reinterpret_cast<const float*>(static_cast<const T*>(a.x) + static_cast<int64_t>(cmin) * NRHS);
   // every load is issued (a lane without a piece reads the group descriptor
   // instead), so that the compiler's count of loads in flight stays exact
   const int tid = static_cast<int>(threadIdx.x);
@@ -534,8 +559,8 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   if (has_rows) {
     // the wave's first non-empty row; next_row moves on from rc.wb + 64 once
     // the first row window is done
-    settle_rows<NRHS>(a, rc, r_end);
-    cr = next_row<NRHS>(a, rc, r_end, origin32);
+    settle_rows<T, NRHS>(a, rc, r_end);
+    cr = next_row<T, NRHS>(a, rc, r_end, origin32);
   }
   if constexpr (WIN) {
     float4* xw4 = reinterpret_cast<float4*>(xw);
@@ -549,36 +574,36 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
     __syncthreads();
   }
   if (!cr.valid || kbeg > kend) return;
-  const float* xb = xw - cmin * NRHS;
+  const T* xb = reinterpret_cast<const T*>(xw) - cmin * NRHS;
   const int lane = threadIdx.x & (kWave - 1);
   // long rows: slot sums (valid in lane 63); short rows: lane sums
-  float W[kRowSlots][NRHS], L[NRHS];
+  T W[kRowSlots][NRHS], L[NRHS];
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) {
-    L[q] = -0.0f;
+    L[q] = T(-0.0);
 #pragma unroll
-    for (int s = 0; s < kRowSlots; ++s) W[s][q] = 0.0f;
+    for (int s = 0; s < kRowSlots; ++s) W[s][q] = T(0);
   }
   int k = kbeg;
   while (true) {
 #pragma unroll
     for (int ph = 0; ph <= DEPTH; ++ph) {
       const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
-      Gathered<NRHS> g;
-      float p[kChunk][NRHS];
+      Gathered<T, NRHS> g;
+      T p[kChunk][NRHS];
       if constexpr (kEarly) {
-        products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+        products<T, VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
         // the barriers keep the scheduler from moving the loads across the
         // products or sinking them below the row work
         __builtin_amdgcn_sched_barrier(0);
         load_step<VF, IX>(vb, cb, k + (DEPTH + 1) * stride, pmin, pmax, cs[cur]);
         __builtin_amdgcn_sched_barrier(0);
       } else {
-        gather_global<VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
+        gather_global<T, VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
         load_step<VF, IX>(vb, cb, k + DEPTH * stride, pmin, pmax, cs[nxt]);
         // keep the scheduler from sinking the loads below the compute
         __builtin_amdgcn_sched_barrier(0);
-        products<VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+        products<T, VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
       }
       const int s0 = k * kStepEntries;
       const int pq = s0 + lane * kQuarter;
@@ -586,25 +611,25 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
       while (k <= kend && cr.valid && cr.ks < s0 + kStepEntries) {
         const bool lng = SPLIT || cr.lng;
         if (lng) {
-          float h0[NRHS], h1[NRHS];
+          T h0[NRHS], h1[NRHS];
           if (cr.ks <= s0 && cr.ke >= s0 + kStepEntries) {
-            quarter_full<0, NRHS>(p, h0);
-            quarter_full<1, NRHS>(p, h1);
+            quarter_full<T, 0, NRHS>(p, h0);
+            quarter_full<T, 1, NRHS>(p, h1);
           } else {
             const uint32_t len = static_cast<uint32_t>(cr.ke - cr.ks);
-            quarter_sum<0, NRHS>(p, pq - cr.ks, len, h0);
-            quarter_sum<1, NRHS>(p, pq + kHalf - cr.ks, len, h1);
+            quarter_sum<T, 0, NRHS>(p, pq - cr.ks, len, h0);
+            quarter_sum<T, 1, NRHS>(p, pq + kHalf - cr.ks, len, h1);
           }
           const int slot = (k - cr.kfirst) & (kRowSlots - 1);
 #pragma unroll
           for (int q = 0; q < NRHS; ++q) {
-            const float t = wave_reduce(h0[q] + h1[q]);
+            const T t = wave_reduce(h0[q] + h1[q]);
 #pragma unroll
-            for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : 0.0f;
+            for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : T(0);
           }
         } else {
-          add_half<0, NRHS>(p, s0, pq, cr, L);
-          add_half<1, NRHS>(p, s0, pq, cr, L);
+          add_half<T, 0, NRHS>(p, s0, pq, cr, L);
+          add_half<T, 1, NRHS>(p, s0, pq, cr, L);
         }
         if (k + stride <= cr.klast) break;  // the row goes on in a later step of this wave
         // the wave's last step of the row; slots that received nothing hold
@@ -620,14 +645,14 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
         if constexpr (SPLIT) {
           cr.valid = false;
         } else {
-          if (lane == kWave - 1) store_row<SM, NRHS>(a, cr.row, sc, tot);
+          if (lane == kWave - 1) store_row<T, SM, NRHS>(a, cr.row, sc, tot);
 #pragma unroll
           for (int q = 0; q < NRHS; ++q) {
-            L[q] = -0.0f;
+            L[q] = T(-0.0);
 #pragma unroll
-            for (int s = 0; s < kRowSlots; ++s) W[s][q] = 0.0f;
+            for (int s = 0; s < kRowSlots; ++s) W[s][q] = T(0);
           }
-          cr = next_row<NRHS>(a, rc, r_end, origin32);
+          cr = next_row<T, NRHS>(a, rc, r_end, origin32);
         }
       }
       k += stride;
@@ -639,41 +664,42 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
 
 // One group on one workgroup.  `part` is LDS for the four slot sums of a
 // split row.
-template <int VF, int SM, int NRHS, int IX>
-__device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw, float* part) {
+template <class T, int VF, int SM, int NRHS, int IX>
+__device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw, T* part) {
   // wave-uniform index, so that the row bounds below are scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
   const uint64_t base = gp->nnz_base;
   const uint32_t clen = gp->clen;
-  const bool win = clen > 0 && window_floats(clen, NRHS) <= a.win_floats;
+  const bool win = clen > 0 && window_floats(clen, NRHS * static_cast<int>(sizeof(T) / 4)) <= a.win_floats;
   const int cmin = win ? static_cast<int>(gp->cmin) : 0;
-  float tot[NRHS], sc;
+  T tot[NRHS];
+  float sc;
   if (gp->split == 0) {
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
     const uint32_t e0 = wave == 0 ? 0u : gp->ent[wave - 1], e1 = gp->ent[wave];
     if (win)
-      wave_stream<VF, SM, IX, NRHS, true, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), gp,
+      wave_stream<T, VF, SM, IX, NRHS, true, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), gp,
                                                     tot, sc);
     else
-      wave_stream<VF, SM, IX, NRHS, false, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, gp, tot, sc);
+      wave_stream<T, VF, SM, IX, NRHS, false, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, gp, tot, sc);
     return;
   }
   const uint32_t row = gp->row[0], len = gp->ent[kGroupWaves - 1];
   if (win)
-    wave_stream<VF, SM, IX, NRHS, true, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
+    wave_stream<T, VF, SM, IX, NRHS, true, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
                                                  gp, tot, sc);
   else
-    wave_stream<VF, SM, IX, NRHS, false, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, gp, tot, sc);
+    wave_stream<T, VF, SM, IX, NRHS, false, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, gp, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
   __syncthreads();
   if (threadIdx.x == 0) {
-    float r[NRHS];
+    T r[NRHS];
 #pragma unroll
     for (int q = 0; q < NRHS; ++q)
       r[q] = (part[0 * NRHS + q] + part[1 * NRHS + q]) + (part[2 * NRHS + q] + part[3 * NRHS + q]);
-    store_row<SM, NRHS>(a, row, SM == kScaleRow ? a.scale[row] : 1.0f, r);
+    store_row<T, SM, NRHS>(a, row, SM == kScaleRow ? a.scale[row] : 1.0f, r);
   }
 }
 
@@ -681,7 +707,16 @@ template <int VF, int SM, int NRHS, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
   __shared__ float part[kGroupWaves * NRHS];
-  run_group<VF, SM, NRHS, IX>(a, a.groups + blockIdx.x, xw, part);
+  run_group<float, VF, SM, NRHS, IX>(a, a.groups + blockIdx.x, xw, part);
+}
+
+// FP64 x and y, FP64 products and sums (one vector): the paper's
+// half/double configuration (Sec. II-D).
+template <int VF, int SM, int IX>
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_f64(SpmvArgs a) {
+  extern __shared__ __align__(16) float xw[];  // a.win_floats 4-byte words
+  __shared__ double part[kGroupWaves];
+  run_group<double, VF, SM, 1, IX>(a, a.groups + blockIdx.x, xw, part);
 }
 
 // Batched form, one launch for many matrices: workgroup b takes entry b of
@@ -692,7 +727,7 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   __shared__ float part[kGroupWaves * NRHS];
   const GroupDesc* gp = work + blockIdx.x;
-  run_group<VF, SM, NRHS, IX>(args[gp->item], gp, xw, part);
+  run_group<float, VF, SM, NRHS, IX>(args[gp->item], gp, xw, part);
 }
 
 template <int VF, int SM, int NRHS>
@@ -785,6 +820,26 @@ hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hip
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_rhs<kBf16, kScaleNone>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleRow) return launch_rhs<kFp8, kScaleRow>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleCol) return launch_rhs<kFp8, kScaleCol>(n_rhs, a, s);
+  return hipErrorInvalidValue;
+}
+
+template <int VF, int SM>
+hipError_t launch_f64(const SpmvArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
+  const size_t lds = static_cast<size_t>(a.win_floats) * sizeof(float);
+  if (SM != kScaleCol && a.idx_bytes == 2)
+    hipLaunchKernelGGL((k_spmv_f64<VF, SM, SM == kScaleCol ? 4 : 2>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((k_spmv_f64<VF, SM, 4>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_t s) {
+  if (a.n_groups <= 0) return hipSuccess;
+  if (vf == kFp16 && scale_mode == kScaleNone) return launch_f64<kFp16, kScaleNone>(a, s);
+  if (vf == kBf16 && scale_mode == kScaleNone) return launch_f64<kBf16, kScaleNone>(a, s);
+  if (vf == kFp8 && scale_mode == kScaleRow) return launch_f64<kFp8, kScaleRow>(a, s);
+  if (vf == kFp8 && scale_mode == kScaleCol) return launch_f64<kFp8, kScaleCol>(a, s);
   return hipErrorInvalidValue;
 }
 
