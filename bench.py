@@ -218,6 +218,7 @@ def main(argv=None):
         del v, g, seed
         A.close()  # free the single beam before the batch
         variants["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
+        variants["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
         variants["small_plain"] = bench_small(torch, dm, dosegen)
         if args.sweep:
@@ -245,6 +246,28 @@ def bench_u16(torch, dm, spec, rp, cols, vals, x, y, args):
     return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
             "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
             "algorithmic_bytes_per_launch": info["spmv_bytes"], "bitwise_equal_to_i32": same}
+
+
+def bench_f64(torch, dm, spec, rp, cols, vals, x_h, args):
+    """The paper's half/double configuration (Sec. II-D): the same FP16 matrix
+    with FP64 spot weights and dose, FP64 products and sums.  Algorithmic bytes
+    per product: 6 nnz + 4 (n_rows + 1) + 8 n_rows + 8 n_cols (the paper's
+    6 nnz + 12 nr + 8 nc)."""
+    import numpy as np
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, args.format)
+    info = A.info()
+    x64 = torch.from_numpy(x_h.astype(np.float64)).cuda()
+    y64 = torch.empty(spec.n_rows, dtype=torch.float64, device="cuda")
+    ms = time_launches(lambda: A.spmv(x64, y64), args.steps, args.warmup)
+    A.close()
+    vb = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1}[args.format]
+    sb = 4 if args.format == "fp8e4m3_rowscale" else 0
+    nbytes = info["nnz"] * (vb + 4) + 4 * (spec.n_rows + 1) + spec.n_rows * sb + 8 * spec.n_cols + 8 * spec.n_rows
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    log(f"half/double: {ms:.4f} ms/step, {gbps:.0f} GB/s algorithmic")
+    return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
+            "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "algorithmic_bytes_per_launch": nbytes, "x_y_accumulate": "f64"}
 
 
 def bench_batched(torch, dm, dosegen, args):
