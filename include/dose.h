@@ -52,11 +52,13 @@ enum {
   DOSE_ERR_INTERNAL = -7
 };
 
-/* Stored value formats.  Decoding is exact in FP32 for all three. */
+/* Stored value formats.  Decoding is exact in FP32 for all four. */
 typedef enum {
   DOSE_VAL_FP16 = 1,             /* IEEE binary16, the paper's format (Sec. II-D) */
   DOSE_VAL_BF16 = 2,             /* bfloat16                                     */
-  DOSE_VAL_FP8E4M3_ROWSCALE = 3  /* OCP E4M3 (max 448) times an FP32 row scale   */
+  DOSE_VAL_FP8E4M3_ROWSCALE = 3, /* OCP E4M3 (max 448) times an FP32 row scale   */
+  DOSE_VAL_FP32 = 4              /* FP32 values as given: the paper's Single
+                                    control (Sec. V), 4 bytes per value        */
 } dose_value_format;
 
 /* Column index formats.  A^T (DOSE_CREATE_TRANSPOSE) always stores 32-bit

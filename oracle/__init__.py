@@ -5,7 +5,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 library: the arithmetic lives in ``dose_oracle.c`` (plain C, FP64), written
 from the definitions cited there; this module only marshals numpy arrays.
 
-Value formats are named by strings here ("fp16", "bf16", "fp8e4m3_rowscale")
+Value formats are named by strings here ("fp16", "bf16", "fp8e4m3_rowscale",
+"fp32")
 so that no enumeration is shared with the library.
 """
 from __future__ import annotations
@@ -21,7 +22,7 @@ _SRC = os.path.join(_HERE, "dose_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-FORMATS = {"fp16": 1, "bf16": 2, "fp8e4m3_rowscale": 3}
+FORMATS = {"fp16": 1, "bf16": 2, "fp8e4m3_rowscale": 3, "fp32": 4}
 
 
 def build() -> str:

@@ -187,7 +187,8 @@ void or_e4m3_decode_n(const uint8_t* c, int64_t n, double* out) {
 
 /* Decoded matrix entries (as FP32, which holds every decoded value exactly)
  * for a CSR matrix whose FP32 source values are `vals`.
- * fmt: 1 = binary16, 2 = bfloat16, 3 = E4M3 with per-row scale.
+ * fmt: 1 = binary16, 2 = bfloat16, 3 = E4M3 with per-row scale, 4 = the FP32
+ * values themselves (the paper's Single configuration, Sec. V).
  * For fmt 3, `scale_out` (n_rows entries) receives the row scales. */
 int or_decode_matrix(int fmt, int64_t n_rows, const int64_t* row_ptr, const float* vals,
                      float* dec_out, float* scale_out) {
@@ -205,6 +206,8 @@ int or_decode_matrix(int fmt, int64_t n_rows, const int64_t* row_ptr, const floa
         float q = (float)or_e4m3_decode(or_e4m3_encode_sat(t)); /* exact in FP32 */
         dec_out[k] = q * s;                                  /* fl32(q * s) */
       }
+    } else if (fmt == 4) {
+      for (int64_t k = b; k < e; ++k) dec_out[k] = vals[k];
     } else {
       return -1;
     }

@@ -22,8 +22,8 @@ __all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", 
            "dose", "VALUE_FORMATS"]
 
 VALUE_FORMATS = {"fp16": _lib.VAL_FP16, "bf16": _lib.VAL_BF16,
-                 "fp8e4m3_rowscale": _lib.VAL_FP8E4M3_ROWSCALE}
-VALUE_BYTES = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1}
+                 "fp8e4m3_rowscale": _lib.VAL_FP8E4M3_ROWSCALE, "fp32": _lib.VAL_FP32}
+VALUE_BYTES = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1, "fp32": 4}
 INDEX_FORMATS = {"i32": _lib.IDX_I32, "u16": _lib.IDX_U16}
 
 

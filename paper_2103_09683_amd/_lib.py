@@ -21,7 +21,7 @@ ERR_OUT_OF_MEMORY = -5
 ERR_HIP = -6
 ERR_INTERNAL = -7
 
-VAL_FP16, VAL_BF16, VAL_FP8E4M3_ROWSCALE = 1, 2, 3
+VAL_FP16, VAL_BF16, VAL_FP8E4M3_ROWSCALE, VAL_FP32 = 1, 2, 3, 4
 IDX_I32 = 1
 IDX_U16 = 2
 CREATE_TRANSPOSE = 1

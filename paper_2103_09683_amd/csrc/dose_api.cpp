@@ -138,7 +138,7 @@ class DeviceGuard {
 
 hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
-int value_bytes(int vf) { return vf == kFp8 ? 1 : 2; }
+int value_bytes(int vf) { return vf == kFp8 ? 1 : vf == kFp32 ? 4 : 2; }
 
 // ------------------------------------------------------------- validation
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
@@ -158,7 +158,7 @@ bool overflows(int vf, float v) {
 
 void validate_csr(const dose_csr_host* c, int vf, int xf) {
   if (!c) fail(DOSE_ERR_INVALID_ARGUMENT, "csr is null");
-  if (vf != kFp16 && vf != kBf16 && vf != kFp8) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown value format");
+  if (vf != kFp16 && vf != kBf16 && vf != kFp8 && vf != kFp32) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown value format");
   if (xf != DOSE_IDX_I32 && xf != DOSE_IDX_U16) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown index format");
   if (c && xf == DOSE_IDX_U16 && c->n_cols > 65536) fail(DOSE_ERR_UNSUPPORTED, "16-bit indices need n_cols <= 65536");
   if (c->n_rows < 0 || c->n_cols < 0 || c->nnz < 0) fail(DOSE_ERR_INVALID_ARGUMENT, "negative size");

@@ -53,7 +53,7 @@ struct alignas(64) GroupDesc {
 static_assert(sizeof(GroupDesc) == 64, "GroupDesc layout");
 
 // Value formats (numbers as in dose.h).
-enum ValueFormat : int { kFp16 = 1, kBf16 = 2, kFp8 = 3 };
+enum ValueFormat : int { kFp16 = 1, kBf16 = 2, kFp8 = 3, kFp32 = 4 };
 
 // How an E4M3 operand's scale enters the product.
 enum ScaleMode : int {

@@ -49,6 +49,7 @@ __device__ __forceinline__ float dec_code(int vf, const void* codes, uint64_t k)
   if (vf == kFp16)
     return __half2float(__ushort_as_half(static_cast<const uint16_t*>(codes)[k]));
   if (vf == kBf16) return __uint_as_float(static_cast<uint32_t>(static_cast<const uint16_t*>(codes)[k]) << 16);
+  if (vf == kFp32) return static_cast<const float*>(codes)[k];
   const uint32_t c = static_cast<const uint8_t*>(codes)[k];
   const uint32_t sign = (c & 0x80u) << 24;
   const uint32_t E = (c >> 3) & 15u, m = c & 7u;
@@ -76,6 +77,9 @@ __global__ __launch_bounds__(256) void k_encode_rows(const uint32_t* __restrict_
     if (lane == 0) row_scale[row] = s;
     uint8_t* d8 = static_cast<uint8_t*>(dst);
     for (uint32_t k = b + lane; k < e; k += 64) d8[k] = enc_e4m3(src[k] / s);
+  } else if constexpr (VF == kFp32) {
+    float* d32 = static_cast<float*>(dst);
+    for (uint32_t k = b + lane; k < e; k += 64) d32[k] = src[k];
   } else {
     uint16_t* d16 = static_cast<uint16_t*>(dst);
     for (uint32_t k = b + lane; k < e; k += 64)
@@ -167,6 +171,7 @@ hipError_t launch_encode_rows(int vf, const uint32_t* row_ptr, uint32_t base, in
     case kFp16: hipLaunchKernelGGL(k_encode_rows<kFp16>, grid, block, 0, s, row_ptr, base, n_rows, src, dst_codes, row_scale); break;
     case kBf16: hipLaunchKernelGGL(k_encode_rows<kBf16>, grid, block, 0, s, row_ptr, base, n_rows, src, dst_codes, row_scale); break;
     case kFp8: hipLaunchKernelGGL(k_encode_rows<kFp8>, grid, block, 0, s, row_ptr, base, n_rows, src, dst_codes, row_scale); break;
+    case kFp32: hipLaunchKernelGGL(k_encode_rows<kFp32>, grid, block, 0, s, row_ptr, base, n_rows, src, dst_codes, row_scale); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -216,6 +221,9 @@ hipError_t launch_gather_transpose(int vf, const uint32_t* perm, const uint32_t*
   if (vf == kFp8)
     hipLaunchKernelGGL(k_gather_transpose<uint8_t>, grid, block, 0, s, perm, rows,
                        static_cast<const uint8_t*>(codes_in), static_cast<uint8_t*>(codes_out), col_out, n);
+  else if (vf == kFp32)
+    hipLaunchKernelGGL(k_gather_transpose<uint32_t>, grid, block, 0, s, perm, rows,
+                       static_cast<const uint32_t*>(codes_in), static_cast<uint32_t*>(codes_out), col_out, n);
   else
     hipLaunchKernelGGL(k_gather_transpose<uint16_t>, grid, block, 0, s, perm, rows,
                        static_cast<const uint16_t*>(codes_in), static_cast<uint16_t*>(codes_out), col_out, n);

@@ -125,6 +125,21 @@ struct Codes<kFp8> {
   }
 };
 
+template <>
+struct Codes<kFp32> {
+  static constexpr uint32_t kBytes = 4;
+  uint4 wa, wb;
+  __device__ __forceinline__ void load(const char* base, uint32_t k1, uint32_t k2) {
+    wa = ld_nt4(base, k1 * kBytes);
+    wb = ld_nt4(base, k2 * kBytes);
+  }
+  __device__ __forceinline__ float get(int e) const {
+    const uint4& w = e < 4 ? wa : wb;
+    const int i = e & 3;
+    return __uint_as_float(i == 0 ? w.x : i == 1 ? w.y : i == 2 ? w.z : w.w);
+  }
+};
+
 // Column indices of 4 consecutive entries: four int32 (IX = 4) or four
 // uint16 (IX = 2).
 template <int IX>
@@ -818,6 +833,7 @@ hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hip
   if (a.n_groups <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone) return launch_rhs<kFp16, kScaleNone>(n_rhs, a, s);
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_rhs<kBf16, kScaleNone>(n_rhs, a, s);
+  if (vf == kFp32 && scale_mode == kScaleNone) return launch_rhs<kFp32, kScaleNone>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleRow) return launch_rhs<kFp8, kScaleRow>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleCol) return launch_rhs<kFp8, kScaleCol>(n_rhs, a, s);
   return hipErrorInvalidValue;
@@ -838,6 +854,7 @@ hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_
   if (a.n_groups <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone) return launch_f64<kFp16, kScaleNone>(a, s);
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_f64<kBf16, kScaleNone>(a, s);
+  if (vf == kFp32 && scale_mode == kScaleNone) return launch_f64<kFp32, kScaleNone>(a, s);
   if (vf == kFp8 && scale_mode == kScaleRow) return launch_f64<kFp8, kScaleRow>(a, s);
   if (vf == kFp8 && scale_mode == kScaleCol) return launch_f64<kFp8, kScaleCol>(a, s);
   return hipErrorInvalidValue;
@@ -850,6 +867,8 @@ hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes,
     return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)
     return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
+  if (vf == kFp32 && scale_mode == kScaleNone)
+    return launch_rhs_batched<kFp32, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleRow)
     return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)

@@ -359,3 +359,14 @@ def test_gradient_matches_central_finite_differences():
         assert abs(fd - grad[j]) <= 1e-9 * max(1.0, abs(f(x)))
         bound_j = 2.0 ** -23 * float(np.abs(d64[:, j]) @ np.abs(seed))
         assert abs(g_oracle[j] - grad[j]) <= bound_j + 1e-12
+
+
+def test_fp32_format_is_the_values_themselves():
+    """The Single control stores the FP32 source values: its decoded matrix is
+    the input, bit for bit (signed zeros, subnormals and large values
+    included)."""
+    rp = np.array([0, 3, 3, 7], np.int64)
+    vals = np.array([1.5, -0.0, 3.4028235e38, 1e-45, -2.5e-40, 7.0, 0.1], np.float32)
+    dec, scales = oracle.decode_matrix("fp32", rp, vals)
+    assert scales is None
+    np.testing.assert_array_equal(dec.view(np.uint32), vals.view(np.uint32))
