@@ -115,7 +115,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--format", default="fp16", choices=["fp16", "bf16", "fp8e4m3_rowscale"])
+    ap.add_argument("--format", default="fp16", choices=["fp16", "bf16", "fp8e4m3_rowscale", "fp32"])
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--no-variants", action="store_true", help="time the plain product only")
@@ -219,6 +219,7 @@ def main(argv=None):
         A.close()  # free the single beam before the batch
         variants["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
         variants["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
+        variants["single_fp32_values"] = bench_single(torch, dm, spec, rp, cols, vals, x, y, args)
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
         variants["small_plain"] = bench_small(torch, dm, dosegen)
         if args.sweep:
@@ -268,6 +269,21 @@ def bench_f64(torch, dm, spec, rp, cols, vals, x_h, args):
     return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
             "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
             "algorithmic_bytes_per_launch": nbytes, "x_y_accumulate": "f64"}
+
+
+def bench_single(torch, dm, spec, rp, cols, vals, x, y, args):
+    """The paper's Single control (Sec. V): FP32 matrix values (8 bytes per
+    entry with int32 indices), FP32 spot weights and dose."""
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp32")
+    info = A.info()
+    y32 = torch.empty_like(y)
+    ms = time_launches(lambda: A.spmv(x, y32), args.steps, args.warmup)
+    A.close()
+    gbps = info["spmv_bytes"] / (ms * 1e-3) / 1e9
+    log(f"single (FP32 values): {ms:.4f} ms/step, {gbps:.0f} GB/s algorithmic")
+    return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
+            "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "algorithmic_bytes_per_launch": info["spmv_bytes"]}
 
 
 def bench_batched(torch, dm, dosegen, args):
