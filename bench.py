@@ -31,11 +31,35 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_09683_amd", "csrc", f)
                   for f in ("spmv_kernels.hip", "dose_internal.h", "dose_api.cpp")]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments and blank space: what the compiler sees."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        if text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif text[i] == '"':
+            j = i + 1
+            while j < n and text[j] != '"':
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(text[i])
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the product kernel's code (comments and spacing excluded): the
+    HBM traffic record is valid while it matches."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+        with open(p, encoding="utf-8") as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -7,7 +7,7 @@
 
 namespace dose {
 
-// Entries one lane loads per step of a row: 8 codes and 8 column indices.
+// Entries one lane loads per step: two quarters of 4 codes and 4 column indices.
 constexpr int kChunk = 8;
 // Waves of one SpMV workgroup, and its threads.
 constexpr int kGroupWaves = 4;
@@ -24,12 +24,14 @@ constexpr int64_t kStreamPad = 64;
 // index stream, stay below 2^31.
 constexpr int64_t kMaxRowNnz = int64_t{1} << 28;
 
-// Steps of a row (one step: 64 lanes x 8 entries) and how they are summed:
-// the lane sums of step s meet in a fixed wave reduction, giving T_s; the
-// row is (W_0 + W_1) + (W_2 + W_3) with W_j the in-order sum of the T_s with
-// s = j (mod 4).  The order depends only on the row, so a row summed by one
-// wave and a row shared by the four waves of a split group (wave j takes the
-// steps s = j mod 4) give the same bits.
+// Steps (one step: 64 lanes x 8 entries, on absolute multiples of 512) and
+// how a row longer than kRowSlots steps is summed: the lane sums of step s
+// meet in a fixed wave reduction, giving T_s; the row is (W_0 + W_1) +
+// (W_2 + W_3) with W_j the in-order sum of the T_s with s = j (mod 4) counted
+// from the row's first step.  The order depends only on the row, so a row
+// summed by one wave and a row shared by the four waves of a split group
+// (wave j takes the steps s = j mod 4) give the same bits.  Rows of at most
+// kRowSlots steps (never split) sum per lane first and reduce once.
 constexpr int kStepEntries = 64 * kChunk;
 constexpr int kRowSlots = 4;
 static_assert(kRowSlots == kGroupWaves, "a split row gives each wave one slot");

@@ -15,21 +15,26 @@
 //     of a step loads the two 4-entry quarters at 4 l and 256 + 4 l of it
 //     (codes and column indices, non-temporal), so every load instruction
 //     reads one contiguous range and each cache line is requested once.  The
-//     next step's loads are in flight while one is computed.  In a split
-//     group wave j takes the steps j, j+4, ... of the row.
-//   * The kernel is bound by instruction issue as much as by HBM, so the
-//     per-entry work is kept short: FP16 decode and product are one
-//     v_fma_mix, E4M3 is converted by the hardware two codes at a time, the
-//     LDS address of x is a shift and add, and a lane tests whether an entry
-//     belongs to a row with one unsigned compare of its position.
+//     next step's loads are in flight while one is computed, and with an LDS
+//     window a step's buffer is refilled as soon as its products are formed.
+//     In a split group wave j takes the steps j, j+4, ... of the row.
+//   * Instruction issue and the compute between a step's arrival and its
+//     refill set the pace as much as HBM does, so the per-entry work is kept
+//     short: FP16 decode and product are one v_fma_mix, E4M3 is converted by
+//     the hardware two codes at a time, the LDS address of x is one
+//     shift-add, and a lane tests whether an entry belongs to a row with one
+//     unsigned compare of its position.
+//   * The same kernels, instantiated for FP64 vectors (k_spmv_f64), give FP64
+//     products and sums in the same order.
 //   * Summation order, fixed by the row's entries and their absolute
 //     positions only (not by the partition, the launch or timing; nothing is
 //     atomic), so equal inputs give equal bits (Sec. II-D), a split row equals
 //     the same row summed by one wave, and batched products equal plain ones:
 //       - a row meeting at most 4 steps: each lane adds, step by step and
 //         first quarter before second, the pairwise sums of its entries of the
-//         row in each quarter ((a + b) + (c + d), entries outside as +0); the
-//         64 lane sums then meet in one fixed DPP reduction;
+//         row in each quarter that holds any of them ((a + b) + (c + d),
+//         entries outside the row as +0), starting from -0; the 64 lane sums
+//         then meet in one fixed DPP reduction;
 //       - a longer row: per step, the lane sum of its entries of the row
 //         (first-quarter sum + second-quarter sum) goes through the DPP
 //         reduction, giving T_s; W_j adds the T_s of the row's steps s with
