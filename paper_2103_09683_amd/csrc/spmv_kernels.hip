@@ -285,8 +285,8 @@ struct RowCursor {
   int lo, hi;
 };
 
-// Row offsets of the 64-row window at wb.  Issued for every lane (rows past
-// r_end re-read the last row), so their number is fixed; r_end > wb.
+// Row offsets of the 64-row window at wb.  Issued for every lane (rows at or
+// past r_end re-read row r_end - 1), so their number is fixed; r_end >= 1.
 __device__ __forceinline__ void fetch_rows(const SpmvArgs& a, RowCursor& rc, uint32_t wb, uint32_t r_end,
                                            uint32_t origin32) {
   const int lane = threadIdx.x & (kWave - 1);
