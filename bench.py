@@ -84,6 +84,24 @@ def time_launches(fn, steps: int, warmup: int):
     return e0.elapsed_time(e1) / steps
 
 
+def launch_stats(fn, steps: int, warmup: int):
+    """Median and standard deviation of single calls (an event pair around
+    each call on the current stream), beside time_launches' mean."""
+    import statistics
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = [a.elapsed_time(b) for a, b in ev]
+    return statistics.median(t), statistics.pstdev(t)
+
+
 def measured_traffic(bytes_per_launch_alg: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
@@ -209,6 +227,9 @@ def main(argv=None):
                      "kernel": f"k_spmv<{args.format}> (row groups, x window in LDS)"},
     }
 
+    med, sd = launch_stats(lambda: A.spmv(x, y), args.steps, 2)
+    out["ms_per_launch_median"] = round(med, 5)
+    out["ms_per_launch_std"] = round(sd, 5)
     out["hbm_read_ceiling_GBps"] = round(hbm_read_ceiling(torch, dm), 1)
     out["roofline"]["frac_of_read_ceiling"] = round(achieved / out["hbm_read_ceiling_GBps"], 4)
 
@@ -244,6 +265,7 @@ def main(argv=None):
         variants["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
         variants["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
         variants["single_fp32_values"] = bench_single(torch, dm, spec, rp, cols, vals, x, y, args)
+        variants["bias_controls"] = bench_bias_controls(torch, dm, dosegen, spec, x, args)
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
         variants["small_plain"] = bench_small(torch, dm, dosegen)
         if args.sweep:
@@ -308,6 +330,28 @@ def bench_single(torch, dm, spec, rp, cols, vals, x, y, args):
     return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
             "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
             "algorithmic_bytes_per_launch": info["spmv_bytes"]}
+
+
+def bench_bias_controls(torch, dm, dosegen, spec, x, args):
+    """The clinical beam's shape with the beam along x (neighbouring rows no
+    longer share spots, so row groups gather x over wider windows) and with the
+    paper's irregular row lengths (sigma 1.0, rows up to 16,000 entries)."""
+    res = {}
+    for var in (dosegen.beam_along_x(spec), dosegen.paper_irregular(spec)):
+        rp, cols, vals = dosegen.csr(var)
+        A = dm.DoseMatrix(rp, cols, vals, var.n_cols, args.format)
+        info = A.info()
+        y = torch.empty(var.n_rows, dtype=torch.float32, device="cuda")
+        ms = time_launches(lambda: A.spmv(x, y), args.steps, args.warmup)
+        A.close()
+        gbps = info["spmv_bytes"] / (ms * 1e-3) / 1e9
+        log(f"{var.name}: {ms:.4f} ms/step, {gbps:.0f} GB/s algorithmic")
+        res[var.name] = {"ms": round(ms, 5), "nnz": info["nnz"], "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
+                         "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+                         "n_groups": info["n_groups"], "n_groups_x_in_lds": info["n_groups_windowed"],
+                         "n_groups_split": info["n_groups_split"], "max_row_nnz": int((rp[1:] - rp[:-1]).max())}
+        del rp, cols, vals
+    return res
 
 
 def bench_batched(torch, dm, dosegen, args):

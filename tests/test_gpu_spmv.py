@@ -361,3 +361,26 @@ def test_clinical_beam_full_size_sampled(dev):
     # property at every row: empty rows exactly +0, others positive
     assert np.all(_bits(y[lens == 0]) == 0) and np.all(y[lens > 0] > 0)
     A.close()
+
+
+@pytest.mark.parametrize("variant", ["beam_along_x", "paper_irregular"])
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp8e4m3_rowscale"])
+def test_bias_control_workloads(variant, fmt, dev):
+    """The generator's bias controls at a small size: the beam along x (rows
+    of neighbouring voxels no longer share spots) and the paper's irregular
+    row lengths (sigma 1.0, rows up to 16,000 entries).  Parity with the
+    oracle and bitwise equality under other partitions."""
+    base = dosegen.Spec("bias_small", 48, 48, 32, 60, 50, 120.0, 0.6, seed=dosegen.SEED0 + 7)
+    spec = getattr(dosegen, variant)(base)
+    rp, cols, vals = dosegen.csr(spec)
+    _say("bias control", variant, fmt, int(rp[-1]), int(np.diff(rp).max()))
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt)
+    x_h = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
+    x = torch.from_numpy(x_h).cuda()
+    y = A.spmv(x).cpu().numpy()
+    dec, _ = oracle.decode_matrix(fmt, rp, vals)
+    assert oracle.max_rel_err(y, oracle.spmv(rp, cols, dec, x_h)) <= TOL
+    for g in (2048, 65536):
+        A.set_partition(g)
+        np.testing.assert_array_equal(A.spmv(x).cpu().numpy().view(np.uint32), y.view(np.uint32))
+    A.close()
