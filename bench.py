@@ -450,6 +450,17 @@ def bench_sweep(torch, dm, dosegen, args):
                     "spmv_bytes": info["spmv_bytes"], "device_bytes": info["device_bytes"]}
         A.close()
         torch.cuda.empty_cache()
+        # 16-bit column indices (60,000 spots), forward only
+        A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, index_format="u16")
+        info = A.info()
+        ms = time_launches(lambda: A.spmv(x, y), max(20, args.steps // 4), 3)
+        res[fmt + "_u16"] = {"forward_ms": round(ms, 4),
+                             "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
+                             "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
+                             "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                             "spmv_bytes": info["spmv_bytes"]}
+        A.close()
+        torch.cuda.empty_cache()
     return res
 
 
