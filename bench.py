@@ -6,10 +6,16 @@ in the paper's format (FP16 values, int32 column indices), FP32 x, y and
 accumulation.  One step is one plain product over the whole matrix with the
 inputs resident in HBM.  Prints ONE JSON line.
 
-The same line carries the adjoint g = A^T v, one plan-optimisation iteration
-(dose, FP64 objective, adjoint, FP64 gradient norm) and the batched
-robust-scenario product as variants, the roofline of the dominant kernel,
-a read-only HBM ceiling probe, and the CPU oracle timed on the host.
+The same line carries, as variants: the adjoint g = A^T v, one
+plan-optimisation iteration (dose, FP64 objective, adjoint, FP64 gradient
+norm), the product with 16-bit column indices, the paper's half/double
+(FP64 spot weights and dose) and Single (FP32 values) configurations, the
+bias controls (beam along x, irregular row lengths), the batched
+robust-scenario product and a small cache-resident matrix; besides them the
+roofline of the dominant kernel (with the HBM traffic the committed rocprofv3
+record gives while the kernel code is unchanged), the median and standard
+deviation of single launches, a read-only HBM ceiling probe, and the CPU
+oracle timed on the host.  --sweep adds the largest workload.
 """
 from __future__ import annotations
 

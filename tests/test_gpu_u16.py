@@ -106,3 +106,30 @@ def test_misaligned_vectors_rejected(dev):
     assert lib.dose_spmv(A.handle, base, base + 128, None) == _lib.OK
     torch.cuda.synchronize()
     A.close()
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp8e4m3_rowscale"])
+def test_u16_columns_up_to_65535(fmt, dev):
+    """16-bit indices at their limit: n_cols = 65536, columns up to 65535 in
+    both halves of the packed index words; equal to the 32-bit path."""
+    rng = np.random.default_rng(16)
+    n_rows, n_cols = 700, 65536
+    lens = rng.integers(0, 300, n_rows)
+    lens[::7] = 0
+    rp = np.zeros(n_rows + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    cols = np.concatenate([np.sort(rng.choice(np.arange(65000, 65536), l, replace=False)) if i % 2
+                           else np.sort(rng.choice(n_cols, l, replace=False)) for i, l in enumerate(lens)]).astype(np.int32)
+    vals = rng.lognormal(-3, 1, rp[-1]).astype(np.float32)
+    assert cols.max() >= 65500
+    A32 = dm.DoseMatrix(rp, cols, vals, n_cols, fmt, transpose=True)
+    A16 = dm.DoseMatrix(rp, cols, vals, n_cols, fmt, transpose=True, index_format="u16")
+    np.testing.assert_array_equal(A16.decode()[1], cols)
+    x = torch.from_numpy(rng.random(n_cols).astype(np.float32)).cuda()
+    v = torch.from_numpy(rng.standard_normal(n_rows).astype(np.float32)).cuda()
+    np.testing.assert_array_equal(_bits(A16.spmv(x).cpu().numpy()), _bits(A32.spmv(x).cpu().numpy()))
+    np.testing.assert_array_equal(_bits(A16.adjoint(v).cpu().numpy()), _bits(A32.adjoint(v).cpu().numpy()))
+    dec, _ = oracle.decode_matrix(fmt, rp, vals)
+    assert oracle.max_rel_err(A16.spmv(x).cpu().numpy(), oracle.spmv(rp, cols, dec, x.cpu().numpy())) <= TOL
+    A16.close()
+    A32.close()

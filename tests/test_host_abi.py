@@ -193,3 +193,14 @@ def test_u16_index_validation():
     assert dm.csr_validate(rp, np.array([0, 65535], np.int32), vals, 65536, "fp16", "u16") == 0
     assert dm.csr_validate(rp, np.array([0, 65535], np.int32), vals, 65537, "fp16", "u16") == _lib.ERR_UNSUPPORTED
     assert dm.csr_validate(rp, np.array([0, 65536], np.int32), vals, 65537, "fp16", "i32") == 0
+
+
+def test_row_length_limit_in_partition():
+    """A row of 2^28 or more entries is rejected by the partition (positions in
+    a group are 32-bit byte offsets); one entry fewer is a split group."""
+    ok = np.array([0, (1 << 28) - 1], np.int64)
+    p = dm.partition_preview(ok, 16384)
+    assert p.shape[0] == 1 and p[0, 5] == 1
+    bad = np.array([0, 1 << 28], np.int64)
+    with pytest.raises(dm.DoseError):
+        dm.partition_preview(bad, 16384)
