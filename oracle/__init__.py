@@ -70,6 +70,8 @@ def load_library(path: str):
         "or_objective": ([i64, vp, vp, vp], ctypes.c_double),
         "or_objective_seed": ([i64, vp, vp, vp, vp], None),
         "or_norm2": ([i64, vp], ctypes.c_double),
+        "or_beam_sum": ([i32, i64, vp, vp], None),
+        "or_robust": ([i32, vp, vp, vp, vp, vp], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -207,6 +209,33 @@ def objective_seed(d, p, w) -> np.ndarray:
     out = np.empty(max(dd.size, 1), np.float64)
     _load().or_objective_seed(dd.size, pdd, ppp, pww, out.ctypes.data)
     return out[:dd.size]
+
+
+def beam_sum(part) -> np.ndarray:
+    """Scenario dose from its beams' doses: part is (n_beams, n); returns the
+    FP64 sum over beams for every voxel."""
+    pa = np.ascontiguousarray(np.asarray(part, np.float64))
+    if pa.ndim != 2:
+        raise ValueError("part must be (n_beams, n)")
+    out = np.empty(max(pa.shape[1], 1), np.float64)
+    _load().or_beam_sum(pa.shape[0], pa.shape[1], pa.ctypes.data, out.ctypes.data)
+    return out[:pa.shape[1]]
+
+
+def robust(f, prob=None) -> tuple[float, int, float]:
+    """(worst case, first scenario attaining it, expectation) of the scenario
+    objectives f; uniform expectation (sum f / S) when prob is None."""
+    ff = np.ascontiguousarray(np.asarray(f, np.float64))
+    if ff.size < 1:
+        raise ValueError("at least one scenario")
+    pp = None if prob is None else np.ascontiguousarray(np.asarray(prob, np.float64))
+    if pp is not None and pp.size != ff.size:
+        raise ValueError("one probability per scenario")
+    worst, expected = ctypes.c_double(), ctypes.c_double()
+    arg = ctypes.c_int64()
+    _load().or_robust(ff.size, ff.ctypes.data, None if pp is None else pp.ctypes.data,
+                      ctypes.byref(worst), ctypes.byref(arg), ctypes.byref(expected))
+    return worst.value, arg.value, expected.value
 
 
 def norm2(g) -> float:

@@ -29,6 +29,13 @@
  *     iteration needs the dose, the objective and its gradient):
  *     f = sum_v w_v (d_v - p_v)^2 and the adjoint seed 2 w_v (d_v - p_v).
  *
+ *   - Scenario dose and robust objective (Sec. I and II-A: the dose of several
+ *     beams, possibly under several realisations of the uncertainties, is
+ *     needed every iteration).  Each beam has its own deposition matrix over
+ *     the shared dose grid, so the dose of one scenario is the sum of its
+ *     beams' doses.  Over the scenarios' objectives f_s the robust forms are
+ *     the worst case max_s f_s and the expectation sum_s pi_s f_s.
+ *
  * Built with -O2 -fno-fast-math -ffp-contract=off so that the compiler keeps
  * every rounding as written.
  */
@@ -290,4 +297,37 @@ double or_norm2(int64_t n, const double* g) {
   double s = 0.0;
   for (int64_t j = 0; j < n; ++j) s += g[j] * g[j];
   return sqrt(s);
+}
+
+/* Dose of one scenario: d_v = sum_b part[b*n + v] over beams b ascending, in
+ * FP64 (part holds the n-voxel dose of each beam, one after another). */
+void or_beam_sum(int32_t n_beams, int64_t n, const double* part, double* d) {
+  for (int64_t v = 0; v < n; ++v) {
+    double s = 0.0;
+    for (int32_t b = 0; b < n_beams; ++b) s += part[(int64_t)b * n + v];
+    d[v] = s;
+  }
+}
+
+/* Robust forms of the scenario objectives f_0..f_{S-1}: the worst case
+ * max_s f_s with the first scenario attaining it, and the expectation
+ * sum_s pi_s f_s in ascending s, or (sum_s f_s) / S when prob is NULL. */
+void or_robust(int32_t n_scen, const double* f, const double* prob, double* worst, int64_t* arg,
+               double* expected) {
+  double w = f[0], e = 0.0;
+  int64_t a = 0;
+  for (int32_t s = 1; s < n_scen; ++s)
+    if (f[s] > w) {
+      w = f[s];
+      a = s;
+    }
+  if (prob) {
+    for (int32_t s = 0; s < n_scen; ++s) e += prob[s] * f[s];
+  } else {
+    for (int32_t s = 0; s < n_scen; ++s) e += f[s];
+    e = e / (double)n_scen;
+  }
+  *worst = w;
+  *arg = a;
+  *expected = e;
 }

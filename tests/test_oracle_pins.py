@@ -370,3 +370,78 @@ def test_fp32_format_is_the_values_themselves():
     dec, scales = oracle.decode_matrix("fp32", rp, vals)
     assert scales is None
     np.testing.assert_array_equal(dec.view(np.uint32), vals.view(np.uint32))
+
+
+# --------------------------------------------------------------------------
+# scenario dose and robust objective
+# --------------------------------------------------------------------------
+def _csr_of_dense(dense):
+    mask = dense != 0
+    rp = np.zeros(dense.shape[0] + 1, np.int64)
+    np.cumsum(mask.sum(1), out=rp[1:])
+    return rp, np.nonzero(mask)[1].astype(np.int32), dense[mask].astype(np.float32)
+
+
+def test_beam_sum_equals_product_with_side_by_side_beams():
+    """Placing a scenario's beam matrices side by side (one column block per
+    beam) and their spot weights end to end gives one matrix whose product is
+    the scenario dose.  Small integers keep every sum exact, so a dropped beam,
+    a beam read twice or a transposed (beam, voxel) index fails."""
+    rng = np.random.default_rng(900)
+    n_rows, widths = 60, [7, 11, 5, 9]
+    doses, blocks, xs = [], [], []
+    for nc in widths:
+        dense = np.where(rng.random((n_rows, nc)) < 0.4, rng.integers(1, 9, (n_rows, nc)), 0)
+        dense = dense.astype(np.float32)
+        dense[rng.random(n_rows) < 0.2] = 0.0
+        x = rng.integers(0, 5, nc).astype(np.float32)
+        rp, cols, vals = _csr_of_dense(dense)
+        dec, _ = oracle.decode_matrix("fp16", rp, vals)
+        doses.append(oracle.spmv(rp, cols, dec, x))
+        blocks.append(dense)
+        xs.append(x)
+    big, xb = np.hstack(blocks), np.concatenate(xs)
+    rp, cols, vals = _csr_of_dense(big)
+    dec, _ = oracle.decode_matrix("fp16", rp, vals)
+    d = oracle.beam_sum(np.stack(doses))
+    np.testing.assert_array_equal(d, oracle.spmv(rp, cols, dec, xb))
+    np.testing.assert_array_equal(d, _dense_python(big.astype(np.float64), xb))
+    np.testing.assert_array_equal(oracle.beam_sum(np.stack(doses[:1])), doses[0])
+
+
+def test_beam_sum_is_the_correctly_rounded_sum_of_few_terms():
+    rng = np.random.default_rng(901)
+    part = rng.uniform(2.0 ** -10, 1, (4, 1000)).astype(np.float32).astype(np.float64)
+    d = oracle.beam_sum(part)
+    ref = np.array([math.fsum(part[:, v]) for v in range(part.shape[1])])
+    # four FP32 terms in [2^-10, 1): every bit of the exact sum lies between
+    # 2^1 and 2^-33, so the FP64 sum is exact and equals the rounded one
+    np.testing.assert_array_equal(d, ref)
+
+
+def test_robust_closed_forms():
+    assert oracle.robust([3.0, 7.0, 5.0], [0.5, 0.25, 0.25]) == (7.0, 1, 4.5)
+    assert oracle.robust([4.0]) == (4.0, 0, 4.0)
+    worst, arg, expected = oracle.robust([2.0, 9.0, 9.0])
+    assert (worst, arg) == (9.0, 1)  # ties go to the first scenario
+    assert expected == 20.0 / 3.0
+    f = [1.5, 8.25, 3.0, 8.0]
+    for k in range(4):
+        onehot = np.zeros(4)
+        onehot[k] = 1.0
+        assert oracle.robust(f, onehot) == (8.25, 1, f[k])
+
+
+def test_robust_expectation_vs_exact_fractions():
+    from fractions import Fraction
+    rng = np.random.default_rng(902)
+    for _ in range(20):
+        n = int(rng.integers(1, 12))
+        fi, pi = rng.integers(0, 4000, n), rng.integers(0, 65, n)
+        f, prob = fi / 4.0, pi / 64.0
+        worst, arg, expected = oracle.robust(f, prob)
+        # every product and partial sum is a multiple of 1/256 below 2^24: exact in FP64
+        assert expected == float(sum(Fraction(int(a), 4) * Fraction(int(b), 64) for a, b in zip(fi, pi)))
+        assert worst == f.max() and arg == int(np.argmax(f))
+        _, _, mean = oracle.robust(f)
+        assert mean == float(Fraction(int(fi.sum()), 4)) / n
