@@ -11,7 +11,9 @@ plan-optimisation iteration (dose, FP64 objective, adjoint, FP64 gradient
 norm), the product with 16-bit column indices, the paper's half/double
 (FP64 spot weights and dose) and Single (FP32 values) configurations, the
 bias controls (beam along x, irregular row lengths), the batched
-robust-scenario product and a small cache-resident matrix; besides them the
+robust-scenario product, the robust-plan step (9 scenarios x 4 beams on one
+dose grid, then the scenario epilogue) and a small cache-resident matrix;
+besides them the
 roofline of the dominant kernel (with the HBM traffic the committed rocprofv3
 record gives while the kernel code is unchanged), the median and standard
 deviation of single launches, a read-only HBM ceiling probe, and the CPU
@@ -273,6 +275,7 @@ def main(argv=None):
         variants["single_fp32_values"] = bench_single(torch, dm, spec, rp, cols, vals, x, y, args)
         variants["bias_controls"] = bench_bias_controls(torch, dm, dosegen, spec, x, args)
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
+        variants["robust_scenarios"] = bench_scenarios(torch, dm, dosegen, args)
         variants["small_plain"] = bench_small(torch, dm, dosegen)
         if args.sweep:
             variants["sweep_large"] = bench_sweep(torch, dm, dosegen, args)
@@ -392,6 +395,75 @@ def bench_batched(torch, dm, dosegen, args):
             A.close()
         del entries
         torch.cuda.empty_cache()
+    return res
+
+
+def bench_scenarios(torch, dm, dosegen, args):
+    """The robust-plan step: 9 setup-shift scenarios x 4 beams on one shared
+    dose grid (128 x 128 x 64 * batch_scale voxels), the 36 beam doses in one
+    autotuned batched graph launch, then the epilogue (scenario doses, seeds,
+    FP64 scenario objectives, worst case and expectation).  Reports the step,
+    the epilogue alone and its share; epilogue algorithmic bytes are the beam
+    doses read once, p and w read once, scenario doses and seeds written once."""
+    import numpy as np
+    n_scen, n_beams = 9, 4
+    specs = dosegen.robust_scenarios(args.batch_scale, n_scen, n_beams)
+    n = specs[0].n_rows
+    xs = [torch.from_numpy(dosegen.spot_weights(dosegen.SEED0 + 6, b, specs[b].n_cols)).cuda()
+          for b in range(n_beams)]
+    part = torch.empty(n_scen, n_beams, n, dtype=torch.float32, device="cuda")
+    mats, entries, nnz_tot = [], [], 0
+    for m, sp in enumerate(specs):
+        rp, cols, vals = dosegen.csr(sp)
+        A = dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16")
+        mats.append(A)
+        s, b = divmod(m, n_beams)
+        entries.append((A, xs[b], part[s, b]))
+        nnz_tot += int(rp[-1])
+    g = np.random.default_rng(6)
+    p = torch.from_numpy(g.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)).cuda()
+    w = torch.from_numpy(g.choice([1.0, 10.0], size=n).astype(np.float32)).cuda()
+    prob = torch.full((n_scen,), 1.0 / n_scen, dtype=torch.float64, device="cuda")
+    d_out = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
+    seed = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
+    out = torch.empty(n_scen + 3, dtype=torch.float64, device="cuda")
+    plan = dm.BatchPlan(entries, autotune=True)
+
+    def epilogue():
+        dm.scenario_objective(part, p, w, prob=prob, d_out=d_out, seed=seed, out=out)
+
+    def step():
+        plan.launch()
+        epilogue()
+
+    reps = max(10, args.steps // 10)
+    ms_step = time_launches(step, reps, 3)
+    ms_epi = time_launches(epilogue, reps, 3)
+    epi_bytes = 4 * n * (n_scen * n_beams + 2 + 2 * n_scen)
+    res = {"ms_step": round(ms_step, 4), "ms_epilogue": round(ms_epi, 4),
+           "epilogue_share": round(ms_epi / ms_step, 4), "scenarios": n_scen, "beams": n_beams,
+           "voxels": n, "nnz": nnz_tot, "GNNZ_per_s": round(nnz_tot / (ms_step * 1e-3) / 1e9, 2),
+           "epilogue_GBps_algorithmic": round(epi_bytes / (ms_epi * 1e-3) / 1e9, 1),
+           "batch_scale": args.batch_scale}
+    plan.close()
+    for A in mats:
+        A.close()
+    del entries, part, d_out, seed
+    torch.cuda.empty_cache()
+    # the epilogue alone on the full 128 x 128 x 64 grid (beam doses uniform in [0, 1))
+    n = 128 * 128 * 64
+    part = torch.rand(n_scen, n_beams, n, dtype=torch.float32, device="cuda")
+    p = torch.from_numpy(g.choice([0.0, 2.0], size=n).astype(np.float32)).cuda()
+    w = torch.from_numpy(g.choice([1.0, 10.0], size=n).astype(np.float32)).cuda()
+    d_out = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
+    seed = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
+    ms_full = time_launches(epilogue, reps, 3)
+    full_bytes = 4 * n * (n_scen * n_beams + 2 + 2 * n_scen)
+    res["epilogue_full_grid"] = {"voxels": n, "ms": round(ms_full, 4), "algorithmic_bytes": full_bytes,
+                                 "GBps_algorithmic": round(full_bytes / (ms_full * 1e-3) / 1e9, 1),
+                                 "frac": round(full_bytes / (ms_full * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    del part, d_out, seed
+    torch.cuda.empty_cache()
     return res
 
 

@@ -229,6 +229,32 @@ def robust_batch(scale: float = 1.0) -> list[Spec]:
     return specs
 
 
+def robust_scenarios(scale: float = 1.0, n_scen: int = 9, n_beams: int = 4, nx: int = 128, ny: int = 128,
+                     spots_per_line: int = 250) -> list[Spec]:
+    """n_scen setup-shift scenarios x n_beams beams on ONE shared dose grid,
+    scenario-major (matrix s * n_beams + b is beam b under scenario s).
+
+    Every beam of a scenario deposits into the same nx x ny x nz voxels
+    (nz = 64 * scale), so a scenario's dose is the sum of its beams' doses.
+    Beam b keeps its spots (20-100 scanlines of ``spots_per_line``) and its
+    mean row length (50-250 over all rows, 60% empty) in every scenario;
+    scenario s shifts the footprint on a 3x3 pattern and draws its own values;
+    the beam axis alternates with b.
+    """
+    rng = np.random.default_rng(SEED0 + 6)
+    nz = max(2, int(round(64 * scale)))
+    beams = [(int(rng.integers(20, 101)), float(rng.uniform(50.0, 250.0))) for _ in range(n_beams)]
+    specs = []
+    for s in range(n_scen):
+        du = 0.02 * ((s % 3) - 1)
+        dv = 0.02 * (((s // 3) % 3) - 1)
+        for b, (n_lines, mean) in enumerate(beams):
+            specs.append(Spec(f"scenario_s{s}_b{b}", nx, ny, nz, n_lines, spots_per_line, mean, 0.6,
+                              beam_axis=b % 2, shift_u=du, shift_v=dv, seed=SEED0 + 6,
+                              matrix_id=s * n_beams + b))
+    return specs
+
+
 def objective_masks(nx: int = 25, ny: int = 25, nz: int = 32):
     """Prescription p and weights w on the dose grid (row = ix + nx*(iy + ny*iz)).
 

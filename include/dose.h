@@ -223,6 +223,29 @@ dose_status dose_batch_plan_destroy(dose_batch_plan p);
 dose_status dose_objective(int64_t n, const float* d, const float* p, const float* w,
                            float* seed, double* f_out, void* hip_stream);
 
+/* Robust-optimisation epilogue (Sec. I, II-A: the dose of several beams under
+ * several realisations of the uncertainties is needed every iteration).
+ * n_scen scenarios of n_beams beams each share one dose grid of n voxels.
+ *   part:  device FP32 [n_scen][n_beams][n], the beam doses (for instance the
+ *          outputs of one dose_spmv_batched call, one item per beam).
+ *   d_s,v  = part[s][0][v] + part[s][1][v] + ..., in ascending beam order in
+ *          FP32; written to d_out [n_scen][n] unless d_out is NULL.
+ *   f_s    = sum_v w_v (d_s,v - p_v)^2, FP64, the fixed-order two-pass
+ *          reduction of dose_objective (with one scenario of one beam, the
+ *          same f bit for bit).
+ *   seed (may be NULL): FP32 [n_scen][n], seed_s,v = 2 w_v (d_s,v - p_v).
+ *   out:   device, n_scen + 3 doubles: f_0 .. f_{n_scen-1}, then the worst
+ *          case max_s f_s, the expectation sum_s prob_s f_s (ascending s;
+ *          (sum_s f_s) / n_scen when prob is NULL), then the index of the
+ *          first scenario attaining the worst case.
+ *   prob:  device, n_scen doubles, or NULL.
+ * p, w: device FP32 [n].  Float arrays 4-byte, double arrays 8-byte aligned;
+ * 1 <= n_scen, n_beams <= 65536; outputs must not overlap inputs or each
+ * other; else DOSE_ERR_INVALID_ARGUMENT.  Asynchronous on hip_stream. */
+dose_status dose_scenario_objective(int32_t n_scen, int32_t n_beams, int64_t n, const float* part,
+                                    const float* p, const float* w, const double* prob, float* d_out,
+                                    float* seed, double* out, void* hip_stream);
+
 /* out = sqrt(sum_j g_j^2) in FP64, fixed-order two-pass reduction.
  * g: device, n FP32.  out: device, one double.  Asynchronous. */
 dose_status dose_norm2(int64_t n, const float* g, double* out, void* hip_stream);

@@ -252,6 +252,31 @@ def objective(d, p, w, seed: torch.Tensor | None = None, out: torch.Tensor | Non
     return out
 
 
+def scenario_objective(part: torch.Tensor, p, w, prob: torch.Tensor | None = None,
+                       d_out: torch.Tensor | None = None, seed: torch.Tensor | None = None,
+                       out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Robust epilogue over the beam doses ``part`` (n_scen, n_beams, n), FP32.
+
+    Returns a float64 tensor of n_scen + 3 values on the device: the scenario
+    objectives f_s = sum w (d_s - p)^2 with d_s the FP32 sum of the
+    scenario's beam doses in ascending beam order, then max_s f_s, the
+    expectation sum_s prob_s f_s (uniform without ``prob``) and the index of
+    the first worst scenario.  Writes d_s into ``d_out`` (n_scen, n) and the
+    FP32 seeds 2 w (d_s - p) into ``seed`` (n_scen, n) if given."""
+    if part.dim() != 3:
+        raise ValueError("part must be (n_scen, n_beams, n)")
+    n_scen, n_beams, n = part.shape
+    if out is None:
+        out = torch.empty(n_scen + 3, dtype=torch.float64, device=part.device)
+    _lib.check(_lib.load().dose_scenario_objective(
+        n_scen, n_beams, n, _dev_ptr(part, part.numel(), "part"), _dev_ptr(p, n, "p"), _dev_ptr(w, n, "w"),
+        _dev_ptr(prob, n_scen, "prob", dtype=torch.float64) if prob is not None else None,
+        _dev_ptr(d_out, n_scen * n, "d_out") if d_out is not None else None,
+        _dev_ptr(seed, n_scen * n, "seed") if seed is not None else None,
+        _dev_ptr(out, n_scen + 3, "out", dtype=torch.float64), _stream_handle(stream)))
+    return out
+
+
 def norm2(g: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """sqrt(sum g^2) in FP64 on the device."""
     if out is None:

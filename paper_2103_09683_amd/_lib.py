@@ -73,6 +73,7 @@ SIGNATURES = {
     "dose_batch_plan_destroy": ([_vp], _i32),
     "dose_objective": ([_i64, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_norm2": ([_i64, _vp, _vp, _vp], _i32),
+    "dose_scenario_objective": ([_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_probe_stream_read": ([_vp, _u64, _vp, _vp], _i32),
     "dose_probe_copy": ([_vp, _vp, _u64, _vp], _i32),
     "dose_partition_preview": ([_vp, _i64, _i32, _vp, _i64, ctypes.POINTER(_i64)], _i32),

@@ -135,6 +135,12 @@ hipError_t radix_sort_pairs(void* tmp, size_t* tmp_bytes, const uint32_t* keys_i
 hipError_t launch_objective(int64_t n, const float* d, const float* p, const float* w,
                             float* seed, double* partial, int n_partial, double* f_out,
                             hipStream_t s);
+// Robust epilogue over n_scen scenarios of n_beams beams each: part is
+// [n_scen][n_beams][n] beam doses; partial holds n_scen * n_partial doubles;
+// out receives n_scen objectives, then worst case, expectation, worst index.
+hipError_t launch_scenario(int n_scen, int n_beams, int64_t n, const float* part, const float* p,
+                           const float* w, const double* prob, float* d_out, float* seed,
+                           double* partial, int n_partial, double* out, hipStream_t s);
 hipError_t launch_norm2(int64_t n, const float* g, double* partial, int n_partial, double* out,
                         hipStream_t s);
 hipError_t launch_probe_read(const void* buf, uint64_t bytes, float* sink, hipStream_t s);

@@ -1,8 +1,9 @@
 // Scalar reductions of plan optimisation and measurement probes.
 //
-// The quadratic objective f = sum_v w_v (d_v - p_v)^2 and the gradient norm
-// are accumulated in FP64 with a two-pass reduction whose order depends only
-// on n: pass 1 gives workgroup b the fixed range [b*C, (b+1)*C) and reduces
+// The quadratic objective f = sum_v w_v (d_v - p_v)^2 (of one dose vector, or
+// of every scenario of a robust plan, whose dose is the sum of its beams'
+// doses) and the gradient norm are accumulated in FP64 with a two-pass
+// reduction whose order depends only on n: pass 1 gives workgroup b the fixed range [b*C, (b+1)*C) and reduces
 // it with a fixed per-thread stride and a fixed LDS tree; pass 2 reduces the
 // partials the same way in one workgroup.  No atomics (Sec. II-D).
 #include "dose_internal.h"
@@ -31,24 +32,62 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-__global__ __launch_bounds__(kRedThreads) void k_objective_pass1(int64_t n, int64_t chunk,
-                                                                 const float* __restrict__ d,
-                                                                 const float* __restrict__ p,
-                                                                 const float* __restrict__ w,
-                                                                 float* __restrict__ seed,
-                                                                 double* __restrict__ partial) {
+// acc + w_i (d - p_i)^2 in FP64; stores d and the seed 2 w_i (d - p_i) of
+// voxel i of the scenario starting at so, where asked for.
+__device__ __forceinline__ double objective_term(double acc, float d, int64_t i, int64_t so,
+                                                 const float* __restrict__ p, const float* __restrict__ w,
+                                                 float* __restrict__ d_out, float* __restrict__ seed) {
+  if (d_out) d_out[so + i] = d;
+  const double r = static_cast<double>(d) - static_cast<double>(p[i]);
+  const double wi = static_cast<double>(w[i]);
+  if (seed) seed[so + i] = static_cast<float>(2.0 * wi * r);
+  return acc + wi * r * r;
+}
+
+// Scenario pass 1.  Workgroup x takes scenario s = x % n_scen and row chunk
+// c = x / n_scen (the scenarios of one chunk run side by side, so p and w are
+// read from HBM about once).  The dose of voxel i in scenario s is the sum of
+// the scenario's beam doses part[s][b][i], added in ascending b in FP32; the
+// FP64 objective terms then reduce as for one objective into partial[s][c].
+// With n_scen = n_beams = 1 this is the plain objective of one dose vector.
+__global__ __launch_bounds__(kRedThreads) void k_scenario_pass1(int n_scen, int n_beams, int64_t n,
+                                                                int64_t chunk, int n_chunks,
+                                                                const float* __restrict__ part,
+                                                                const float* __restrict__ p,
+                                                                const float* __restrict__ w,
+                                                                float* __restrict__ d_out,
+                                                                float* __restrict__ seed,
+                                                                double* __restrict__ partial) {
   __shared__ double sh[kRedThreads];
-  const int64_t b0 = static_cast<int64_t>(blockIdx.x) * chunk;
+  const int s = static_cast<int>(blockIdx.x % static_cast<unsigned>(n_scen));
+  const int c = static_cast<int>(blockIdx.x / static_cast<unsigned>(n_scen));
+  const int64_t b0 = static_cast<int64_t>(c) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  const float* ps = part + static_cast<int64_t>(s) * n_beams * n;
+  const int64_t so = static_cast<int64_t>(s) * n;
+  // Thread t takes voxels b0 + t + 256 k in ascending k; four of them at a
+  // time, so that four independent loads per beam are in flight.
   double acc = 0.0;
-  for (int64_t i = b0 + threadIdx.x; i < b1; i += kRedThreads) {
-    const double r = static_cast<double>(d[i]) - static_cast<double>(p[i]);
-    const double wi = static_cast<double>(w[i]);
-    acc += wi * r * r;
-    if (seed) seed[i] = static_cast<float>(2.0 * wi * r);
+  int64_t i = b0 + threadIdx.x;
+  for (; i + 3 * kRedThreads < b1; i += 4 * kRedThreads) {
+    float d[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) d[u] = ps[i + u * kRedThreads];
+    for (int b = 1; b < n_beams; ++b) {
+      const float* pb = ps + static_cast<int64_t>(b) * n;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) d[u] += pb[i + u * kRedThreads];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = objective_term(acc, d[u], i + u * kRedThreads, so, p, w, d_out, seed);
   }
-  const double s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  for (; i < b1; i += kRedThreads) {
+    float d = ps[i];
+    for (int b = 1; b < n_beams; ++b) d += ps[static_cast<int64_t>(b) * n + i];
+    acc = objective_term(acc, d, i, so, p, w, d_out, seed);
+  }
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[static_cast<int64_t>(s) * n_chunks + c] = t;
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_sumsq_pass1(int64_t n, int64_t chunk,
@@ -73,6 +112,43 @@ __global__ __launch_bounds__(kRedThreads) void k_pass2(const double* __restrict_
   for (int i = threadIdx.x; i < n_partial; i += kRedThreads) acc += partial[i];
   const double s = block_sum(acc, sh);
   if (threadIdx.x == 0) out[0] = take_sqrt ? sqrt(s) : s;
+}
+
+// Scenario pass 2, one workgroup: f_s from partial[s][*] in the order of
+// k_pass2, then the robust forms in ascending s: worst case max_s f_s (ties
+// to the first scenario, whose index is stored as a double) and expectation
+// sum_s prob_s f_s, or (sum_s f_s) / n_scen without probabilities.
+__global__ __launch_bounds__(kRedThreads) void k_scenario_pass2(const double* __restrict__ partial,
+                                                                int n_partial, int n_scen,
+                                                                const double* __restrict__ prob,
+                                                                double* __restrict__ out) {
+#pragma clang fp contract(off)
+  __shared__ double sh[kRedThreads];
+  for (int s = 0; s < n_scen; ++s) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n_partial; i += kRedThreads)
+      acc += partial[static_cast<int64_t>(s) * n_partial + i];
+    const double f = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[s] = f;
+  }
+  if (threadIdx.x == 0) {
+    double worst = out[0], e = 0.0;
+    int arg = 0;
+    for (int s = 1; s < n_scen; ++s)
+      if (out[s] > worst) {
+        worst = out[s];
+        arg = s;
+      }
+    if (prob) {
+      for (int s = 0; s < n_scen; ++s) e += prob[s] * out[s];
+    } else {
+      for (int s = 0; s < n_scen; ++s) e += out[s];
+      e = e / static_cast<double>(n_scen);
+    }
+    out[n_scen] = worst;
+    out[n_scen + 1] = e;
+    out[n_scen + 2] = static_cast<double>(arg);
+  }
 }
 
 // Read-only stream with 16-byte non-temporal loads (as the SpMV streams its
@@ -110,9 +186,22 @@ hipError_t launch_objective(int64_t n, const float* d, const float* p, const flo
                             double* partial, int n_partial, double* f_out, hipStream_t s) {
   const int64_t chunk = n_partial > 0 ? (n + n_partial - 1) / n_partial : 0;
   if (n > 0)
-    hipLaunchKernelGGL(k_objective_pass1, dim3(n_partial), dim3(kRedThreads), 0, s, n, chunk, d, p, w, seed,
-                       partial);
+    hipLaunchKernelGGL(k_scenario_pass1, dim3(n_partial), dim3(kRedThreads), 0, s, 1, 1, n, chunk, n_partial, d,
+                       p, w, static_cast<float*>(nullptr), seed, partial);
   hipLaunchKernelGGL(k_pass2, dim3(1), dim3(kRedThreads), 0, s, partial, n > 0 ? n_partial : 0, 0, f_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scenario(int n_scen, int n_beams, int64_t n, const float* part, const float* p, const float* w,
+                           const double* prob, float* d_out, float* seed, double* partial, int n_partial,
+                           double* out, hipStream_t s) {
+  const int64_t chunk = n_partial > 0 ? (n + n_partial - 1) / n_partial : 0;
+  if (n > 0)
+    hipLaunchKernelGGL(k_scenario_pass1, dim3(static_cast<unsigned>(n_partial) * static_cast<unsigned>(n_scen)),
+                       dim3(kRedThreads), 0, s, n_scen, n_beams, n, chunk, n_partial, part, p, w, d_out, seed,
+                       partial);
+  hipLaunchKernelGGL(k_scenario_pass2, dim3(1), dim3(kRedThreads), 0, s, partial, n > 0 ? n_partial : 0, n_scen,
+                     prob, out);
   return hipGetLastError();
 }
 

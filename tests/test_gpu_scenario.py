@@ -1,0 +1,179 @@
+"""GPU parity of the robust-optimisation epilogue (scenario dose as the sum of
+its beams' doses, per-scenario FP64 objective, worst case and expectation)
+against the CPU oracle.
+
+The beam doses come from one batched launch (one item per beam and scenario)
+and are themselves checked against the oracle's products (relative 1e-5).  On
+the GPU's own beam doses the epilogue must give: the scenario dose bit for bit
+as the FP32 sum in ascending beam order, within (n_beams - 1) 2^-24 of the
+oracle's FP64 sum (all doses are non-negative); each f_s within 1e-13 of the
+oracle's objective of the same FP32 dose (only the FP64 summation order
+differs); the seeds bit for bit; the worst case, its scenario and the
+expectation exactly as the oracle forms them from the GPU's f_s.
+"""
+import numpy as np
+import pytest
+import torch
+
+import dosegen
+import oracle
+import paper_2103_09683_amd as dm
+from paper_2103_09683_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, np.float32).view(np.uint32)
+
+
+def _scenario_case(n_scen, n_beams, fmt="fp16"):
+    """A shared 41 x 40 x 7 grid (11,480 voxels: three reduction chunks, the
+    last one ragged) with n_scen x n_beams beam matrices."""
+    specs = dosegen.robust_scenarios(7 / 64, n_scen, n_beams, nx=41, ny=40, spots_per_line=20)
+    mats, host, xs = [], [], []
+    for b in range(n_beams):
+        xs.append(dosegen.spot_weights(dosegen.SEED0 + 6, b, specs[b].n_cols))
+    for sp in specs:
+        rp, cols, vals = dosegen.csr(sp)
+        mats.append(dm.DoseMatrix(rp, cols, vals, sp.n_cols, fmt))
+        host.append((rp, cols, vals))
+    n = specs[0].n_rows
+    g = np.random.default_rng(77)
+    p = g.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)
+    w = g.choice([1.0, 10.0], size=n).astype(np.float32)
+    return specs, mats, host, xs, p, w
+
+
+def _beam_doses(mats, xs, n_scen, n_beams, n):
+    part = torch.empty(n_scen, n_beams, n, dtype=torch.float32, device="cuda")
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    dm.spmv_batched([(mats[s * n_beams + b], xd[b], part[s, b]) for s in range(n_scen) for b in range(n_beams)])
+    return part
+
+
+@pytest.mark.parametrize("n_scen,n_beams,with_prob", [(3, 2, True), (4, 3, False), (9, 4, True)])
+def test_scenario_epilogue_parity(dev, n_scen, n_beams, with_prob):
+    _say(f"scenario epilogue: {n_scen} scenarios x {n_beams} beams, prob={with_prob}")
+    specs, mats, host, xs, p, w = _scenario_case(n_scen, n_beams)
+    n = specs[0].n_rows
+    part = _beam_doses(mats, xs, n_scen, n_beams, n)
+    pd, wd = torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda()
+    prob_h = np.random.default_rng(5).integers(1, 9, n_scen).astype(np.float64)
+    prob_h /= prob_h.sum()
+    prob = torch.from_numpy(prob_h).cuda() if with_prob else None
+    d_out = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+    seed = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+    out = dm.scenario_objective(part, pd, wd, prob=prob, d_out=d_out, seed=seed).cpu().numpy()
+    part_h = part.cpu().numpy()
+    d_h, seed_h = d_out.cpu().numpy(), seed.cpu().numpy()
+
+    # beam doses against the oracle's products
+    d_ref = np.zeros((n_scen, n))
+    for s in range(n_scen):
+        for b in range(n_beams):
+            rp, cols, vals = host[s * n_beams + b]
+            dec, _ = oracle.decode_matrix("fp16", rp, vals)
+            y_ref = oracle.spmv(rp, cols, dec, xs[b])
+            assert oracle.max_rel_err(part_h[s, b], y_ref) <= TOL
+            d_ref[s] += y_ref
+
+    f_gpu = out[:n_scen]
+    for s in range(n_scen):
+        # the FP32 sum in ascending beam order, bit for bit
+        acc = part_h[s, 0].copy()
+        for b in range(1, n_beams):
+            acc = acc + part_h[s, b]
+        np.testing.assert_array_equal(_bits(d_h[s]), _bits(acc))
+        # within (n_beams - 1) FP32 roundings of the oracle's sum of the same beam doses
+        exact = oracle.beam_sum(part_h[s].astype(np.float64))
+        assert oracle.max_rel_err(d_h[s], exact) <= max(n_beams - 1, 0) * 2.0 ** -24 * 1.0001
+        d64 = d_h[s].astype(np.float64)
+        f_ref = oracle.objective(d64, p, w)
+        assert abs(f_gpu[s] - f_ref) <= 1e-13 * abs(f_ref)
+        np.testing.assert_array_equal(_bits(seed_h[s]), _bits(oracle.objective_seed(d64, p, w).astype(np.float32)))
+        # end to end against the oracle's FP64 scenario dose: each voxel's dose
+        # is within TOL + n_beams 2^-24 relative (all terms are non-negative)
+        delta = (TOL + n_beams * 2.0 ** -24) * d_ref[s]
+        bound = np.sum(w * (2 * np.abs(d_ref[s] - p) * delta + delta * delta))
+        assert abs(f_gpu[s] - oracle.objective(d_ref[s], p, w)) <= bound + 1e-9
+
+    worst, arg, expected = oracle.robust(f_gpu, prob_h if with_prob else None)
+    assert out[n_scen] == worst and int(out[n_scen + 2]) == arg and out[n_scen + 2] == float(arg)
+    assert out[n_scen + 1] == expected
+    for A in mats:
+        A.close()
+
+
+def test_single_scenario_single_beam_equals_objective(dev):
+    """One scenario of one beam is the plain objective, bit for bit; the epilogue
+    is repeatable bit for bit and works without its optional outputs."""
+    specs, mats, host, xs, p, w = _scenario_case(1, 1)
+    n = specs[0].n_rows
+    part = _beam_doses(mats, xs, 1, 1, n)
+    pd, wd = torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda()
+    d_out = torch.empty(1, n, dtype=torch.float32, device=dev)
+    seed = torch.empty(1, n, dtype=torch.float32, device=dev)
+    out = dm.scenario_objective(part, pd, wd, d_out=d_out, seed=seed).cpu().numpy()
+    seed1 = torch.empty(n, dtype=torch.float32, device=dev)
+    f1 = dm.objective(part[0, 0], pd, wd, seed=seed1).item()
+    assert out[0] == f1 and out[1] == f1 and out[2] == f1 and out[3] == 0.0
+    np.testing.assert_array_equal(_bits(d_out.cpu().numpy()[0]), _bits(part.cpu().numpy()[0, 0]))
+    np.testing.assert_array_equal(_bits(seed.cpu().numpy()[0]), _bits(seed1.cpu().numpy()))
+    again = dm.scenario_objective(part, pd, wd).cpu().numpy()
+    np.testing.assert_array_equal(again, out)
+    mats[0].close()
+
+
+def test_worst_case_ties_and_empty_grid(dev):
+    """Identical scenarios tie: the first is the worst; an empty grid gives zeros."""
+    n = 5000
+    g = np.random.default_rng(3)
+    one = g.uniform(0, 70, n).astype(np.float32)
+    part = torch.from_numpy(np.stack([np.stack([one * 0.5, one * 0.5])] * 3)).cuda()  # 3 x 2 x n
+    p = torch.from_numpy(np.full(n, 30.0, np.float32)).cuda()
+    w = torch.ones(n, device=dev)
+    out = dm.scenario_objective(part, p, w).cpu().numpy()
+    assert out[0] == out[1] == out[2] and out[3] == out[0] and out[5] == 0.0
+    assert out[4] == (out[0] + out[1] + out[2]) / 3.0
+    z = torch.empty(4, 2, 0, device=dev)
+    e = torch.empty(0, device=dev)
+    out = dm.scenario_objective(z, e, e).cpu().numpy()
+    np.testing.assert_array_equal(out, np.zeros(7))
+
+
+def test_scenario_argument_errors(dev):
+    n = 1000
+    part = torch.ones(2, 3, n, device=dev)
+    p, w = torch.zeros(n, device=dev), torch.ones(n, device=dev)
+    d_out = torch.empty(2, n, device=dev)
+    with pytest.raises(dm.DoseError):  # no scenario
+        dm.scenario_objective(torch.ones(0, 3, n, device=dev), p, w)
+    with pytest.raises(dm.DoseError):  # seed and dose written to the same memory
+        dm.scenario_objective(part, p, w, d_out=d_out, seed=d_out)
+    out = torch.empty(8, dtype=torch.float64, device=dev)
+    # scenario doses written over the beam doses
+    st = _lib.load().dose_scenario_objective(2, 3, n, part.data_ptr(), p.data_ptr(), w.data_ptr(), None,
+                                             part.data_ptr(), None, out.data_ptr(), None)
+    assert st == -1
+    for bad in [
+        (0, 3, n, part.data_ptr()),          # no scenario
+        (2, 0, n, part.data_ptr()),          # no beam
+        (2, 3, -1, part.data_ptr()),         # negative size
+        (65537, 1, 1, part.data_ptr()),      # too many scenarios
+        (2, 3, n, part.data_ptr() + 2),      # misaligned beam doses
+        (2, 3, n, None),                     # null beam doses
+    ]:
+        st = _lib.load().dose_scenario_objective(*bad, p.data_ptr(), w.data_ptr(), None, None, None,
+                                                 out.data_ptr(), None)
+        assert st == -1, bad
+    st = _lib.load().dose_scenario_objective(2, 3, n, part.data_ptr(), p.data_ptr(), w.data_ptr(), None, None,
+                                             None, out.data_ptr() + 4, None)  # misaligned doubles
+    assert st == -1
+    torch.cuda.synchronize()

@@ -60,6 +60,18 @@ MUTANTS = [
     ("transpose lists rows in descending order",
      "  for (int64_t i = 0; i < n_rows; ++i)\n    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {\n      int64_t j = col[k];",
      "  for (int64_t i = n_rows - 1; i >= 0; --i)\n    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {\n      int64_t j = col[k];"),
+    ("beam sum skips the last beam",
+     "for (int32_t b = 0; b < n_beams; ++b) s += part[(int64_t)b * n + v];",
+     "for (int32_t b = 0; b + 1 < n_beams; ++b) s += part[(int64_t)b * n + v];"),
+    ("beam sum with (voxel, beam) order transposed",
+     "for (int32_t b = 0; b < n_beams; ++b) s += part[(int64_t)b * n + v];",
+     "for (int32_t b = 0; b < n_beams; ++b) s += part[v * n_beams + b];"),
+    ("worst case takes the last of tied scenarios",
+     "    if (f[s] > w) {",
+     "    if (f[s] >= w) {"),
+    ("expectation ignores the probabilities",
+     "for (int32_t s = 0; s < n_scen; ++s) e += prob[s] * f[s];",
+     "for (int32_t s = 0; s < n_scen; ++s) e += f[s] / n_scen;"),
 ]
 
 CHECKS = [
@@ -76,6 +88,10 @@ CHECKS = [
     pins.test_transpose_structure,
     pins.test_objective_closed_form_and_seed,
     pins.test_gradient_matches_central_finite_differences,
+    pins.test_beam_sum_equals_product_with_side_by_side_beams,
+    pins.test_beam_sum_is_the_correctly_rounded_sum_of_few_terms,
+    pins.test_robust_closed_forms,
+    pins.test_robust_expectation_vs_exact_fractions,
 ]
 
 
