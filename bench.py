@@ -173,6 +173,8 @@ def main(argv=None):
                     help="grid-depth scale of the 36-matrix robust batch (1.0 = full size)")
     ap.add_argument("--probe-copy-gib", type=float, default=0.0,
                     help="only run the copy probe over this many GiB (counter calibration)")
+    ap.add_argument("--scenario-epilogue", action="store_true",
+                    help="only time the robust-plan epilogue on the full 1,048,576-voxel grid")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the largest workload (8,388,608 x 60,000, 1.7e9 entries) in the three "
                          "value formats, forward and adjoint")
@@ -198,6 +200,10 @@ def main(argv=None):
         ms = time_launches(lambda: dm.probe_copy(src, dst), 10, 2)
         print(json.dumps({"probe": "copy", "bytes_each_way": n * 4, "ms": ms,
                           "GBps_read_plus_write": 2 * n * 4 / (ms * 1e-3) / 1e9}))
+        return
+
+    if args.scenario_epilogue:
+        print(json.dumps({"scenario_epilogue": bench_epilogue_full(torch, dm, args.steps)}))
         return
 
     spec = dosegen.clinical_beam()
@@ -450,21 +456,31 @@ def bench_scenarios(torch, dm, dosegen, args):
         A.close()
     del entries, part, d_out, seed
     torch.cuda.empty_cache()
-    # the epilogue alone on the full 128 x 128 x 64 grid (beam doses uniform in [0, 1))
-    n = 128 * 128 * 64
+    res["epilogue_full_grid"] = bench_epilogue_full(torch, dm, reps)
+    return res
+
+
+def bench_epilogue_full(torch, dm, reps: int):
+    """The scenario epilogue alone on the full 128 x 128 x 64 grid: 9 scenarios
+    x 4 beams of beam doses uniform in [0, 1), scenario doses and seeds written."""
+    import numpy as np
+    n_scen, n_beams, n = 9, 4, 128 * 128 * 64
+    g = np.random.default_rng(7)
     part = torch.rand(n_scen, n_beams, n, dtype=torch.float32, device="cuda")
     p = torch.from_numpy(g.choice([0.0, 2.0], size=n).astype(np.float32)).cuda()
     w = torch.from_numpy(g.choice([1.0, 10.0], size=n).astype(np.float32)).cuda()
+    prob = torch.full((n_scen,), 1.0 / n_scen, dtype=torch.float64, device="cuda")
     d_out = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
     seed = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
-    ms_full = time_launches(epilogue, reps, 3)
-    full_bytes = 4 * n * (n_scen * n_beams + 2 + 2 * n_scen)
-    res["epilogue_full_grid"] = {"voxels": n, "ms": round(ms_full, 4), "algorithmic_bytes": full_bytes,
-                                 "GBps_algorithmic": round(full_bytes / (ms_full * 1e-3) / 1e9, 1),
-                                 "frac": round(full_bytes / (ms_full * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    out = torch.empty(n_scen + 3, dtype=torch.float64, device="cuda")
+    ms = time_launches(lambda: dm.scenario_objective(part, p, w, prob=prob, d_out=d_out, seed=seed, out=out),
+                       reps, 3)
+    nbytes = 4 * n * (n_scen * n_beams + 2 + 2 * n_scen)
     del part, d_out, seed
     torch.cuda.empty_cache()
-    return res
+    return {"voxels": n, "scenarios": n_scen, "beams": n_beams, "ms": round(ms, 4), "algorithmic_bytes": nbytes,
+            "GBps_algorithmic": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
 def bench_small(torch, dm, dosegen):

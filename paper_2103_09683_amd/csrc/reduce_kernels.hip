@@ -115,23 +115,45 @@ __global__ __launch_bounds__(kRedThreads) void k_pass2(const double* __restrict_
 }
 
 // Scenario pass 2, one workgroup: f_s from partial[s][*] in the order of
-// k_pass2, then the robust forms in ascending s: worst case max_s f_s (ties
+// k_pass2 (thread t adds partials t, t + 256, ... in ascending order, then the
+// same LDS tree), eight scenarios at a time so that their loads and trees
+// overlap; then the robust forms in ascending s: worst case max_s f_s (ties
 // to the first scenario, whose index is stored as a double) and expectation
 // sum_s prob_s f_s, or (sum_s f_s) / n_scen without probabilities.
+constexpr int kScenBatch = 8;
+
 __global__ __launch_bounds__(kRedThreads) void k_scenario_pass2(const double* __restrict__ partial,
                                                                 int n_partial, int n_scen,
                                                                 const double* __restrict__ prob,
                                                                 double* __restrict__ out) {
 #pragma clang fp contract(off)
-  __shared__ double sh[kRedThreads];
-  for (int s = 0; s < n_scen; ++s) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n_partial; i += kRedThreads)
-      acc += partial[static_cast<int64_t>(s) * n_partial + i];
-    const double f = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[s] = f;
+  __shared__ double sh[kScenBatch][kRedThreads];
+  const int t = threadIdx.x;
+  for (int s0 = 0; s0 < n_scen; s0 += kScenBatch) {
+    const int ns = n_scen - s0 < kScenBatch ? n_scen - s0 : kScenBatch;
+    double acc[kScenBatch];
+#pragma unroll
+    for (int j = 0; j < kScenBatch; ++j) acc[j] = 0.0;
+    for (int i = t; i < n_partial; i += kRedThreads) {
+#pragma unroll
+      for (int j = 0; j < kScenBatch; ++j)
+        if (j < ns) acc[j] += partial[static_cast<int64_t>(s0 + j) * n_partial + i];
+    }
+#pragma unroll
+    for (int j = 0; j < kScenBatch; ++j) sh[j][t] = acc[j];
+    __syncthreads();
+    for (int w = kRedThreads / 2; w > 0; w >>= 1) {
+      if (t < w) {
+#pragma unroll
+        for (int j = 0; j < kScenBatch; ++j) sh[j][t] = sh[j][t] + sh[j][t + w];
+      }
+      __syncthreads();
+    }
+    if (t == 0)
+      for (int j = 0; j < ns; ++j) out[s0 + j] = sh[j][0];
+    __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     double worst = out[0], e = 0.0;
     int arg = 0;
     for (int s = 1; s < n_scen; ++s)
