@@ -32,24 +32,41 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-// acc + w_i (d - p_i)^2 in FP64; stores d and the seed 2 w_i (d - p_i) of
-// voxel i of the scenario starting at so, where asked for.
-__device__ __forceinline__ double objective_term(double acc, float d, int64_t i, int64_t so,
-                                                 const float* __restrict__ p, const float* __restrict__ w,
-                                                 float* __restrict__ d_out, float* __restrict__ seed) {
-  if (d_out) d_out[so + i] = d;
-  const double r = static_cast<double>(d) - static_cast<double>(p[i]);
-  const double wi = static_cast<double>(w[i]);
-  if (seed) seed[so + i] = static_cast<float>(2.0 * wi * r);
+// acc + w (d - p)^2 in FP64; the seed 2 w (d - p) rounded to FP32 in sd.
+__device__ __forceinline__ double add_term(double acc, float d, float pf, float wf, float& sd) {
+  const double r = static_cast<double>(d) - static_cast<double>(pf);
+  const double wi = static_cast<double>(wf);
+  sd = static_cast<float>(2.0 * wi * r);
   return acc + wi * r * r;
 }
 
-// Scenario pass 1.  Workgroup x takes scenario s = x % n_scen and row chunk
+__device__ __forceinline__ float4 ld4(const float* q) { return *reinterpret_cast<const float4*>(q); }
+__device__ __forceinline__ float4 ld4_nt(const float* q) {
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(q));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void add4(float4& d, const float4 e) {
+  d.x += e.x;
+  d.y += e.y;
+  d.z += e.z;
+  d.w += e.w;
+}
+
+// Scenario pass 1.  Workgroup x takes scenario s = x % n_scen and voxel chunk
 // c = x / n_scen (the scenarios of one chunk run side by side, so p and w are
-// read from HBM about once).  The dose of voxel i in scenario s is the sum of
-// the scenario's beam doses part[s][b][i], added in ascending b in FP32; the
-// FP64 objective terms then reduce as for one objective into partial[s][c].
-// With n_scen = n_beams = 1 this is the plain objective of one dose vector.
+// read from HBM about once); chunks are multiples of 4 voxels.  The dose of
+// voxel i in scenario s is the sum of the scenario's beam doses part[s][b][i],
+// added in ascending b in FP32.  Thread t takes the 4-voxel vectors
+// t, t + 256, t + 512, ... of its chunk and adds their FP64 objective terms in
+// that order (voxels of a vector in ascending order) before the LDS tree into
+// partial[s][c].  VEC (n a multiple of 4, every array 16-byte aligned) moves
+// each vector with one 16-byte access, two vectors at a time, with the loads
+// of all beams in flight together when the beam count is a template
+// argument (NB); otherwise the
+// same order with 4-byte accesses.  So the result depends only on n, never on
+// the path.  With n_scen = n_beams = 1 this is the objective of one dose vector.
+template <bool VEC, int NB>  // NB > 0: n_beams == NB, known at compile time
 __global__ __launch_bounds__(kRedThreads) void k_scenario_pass1(int n_scen, int n_beams, int64_t n,
                                                                 int64_t chunk, int n_chunks,
                                                                 const float* __restrict__ part,
@@ -63,28 +80,75 @@ __global__ __launch_bounds__(kRedThreads) void k_scenario_pass1(int n_scen, int 
   const int c = static_cast<int>(blockIdx.x / static_cast<unsigned>(n_scen));
   const int64_t b0 = static_cast<int64_t>(c) * chunk;
   const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
+  const int64_t nv = b1 > b0 ? (b1 - b0 + 3) / 4 : 0;
   const float* ps = part + static_cast<int64_t>(s) * n_beams * n;
   const int64_t so = static_cast<int64_t>(s) * n;
-  // Thread t takes voxels b0 + t + 256 k in ascending k; four of them at a
-  // time, so that four independent loads per beam are in flight.
   double acc = 0.0;
-  int64_t i = b0 + threadIdx.x;
-  for (; i + 3 * kRedThreads < b1; i += 4 * kRedThreads) {
-    float d[4];
+  if constexpr (VEC) {
+    auto finish = [&](const float4 d, const int64_t i, const float4 pv, const float4 wv) {
+      float4 sd;
+      acc = add_term(acc, d.x, pv.x, wv.x, sd.x);
+      acc = add_term(acc, d.y, pv.y, wv.y, sd.y);
+      acc = add_term(acc, d.z, pv.z, wv.z, sd.z);
+      acc = add_term(acc, d.w, pv.w, wv.w, sd.w);
+      if (d_out) *reinterpret_cast<float4*>(d_out + so + i) = d;
+      if (seed) *reinterpret_cast<float4*>(seed + so + i) = sd;
+    };
+    int64_t v = threadIdx.x;
+    for (; v + kRedThreads < nv; v += 2 * kRedThreads) {
+      const int64_t i0 = b0 + 4 * v, i1 = i0 + 4 * kRedThreads;
+      const float4 p0 = ld4(p + i0), w0 = ld4(w + i0), p1 = ld4(p + i1), w1 = ld4(w + i1);
+      float4 d0 = ld4_nt(ps + i0), d1 = ld4_nt(ps + i1);
+      if constexpr (NB > 0) {
+        // every beam's loads issue before the first add
 #pragma unroll
-    for (int u = 0; u < 4; ++u) d[u] = ps[i + u * kRedThreads];
-    for (int b = 1; b < n_beams; ++b) {
-      const float* pb = ps + static_cast<int64_t>(b) * n;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) d[u] += pb[i + u * kRedThreads];
+        for (int b = 1; b < NB; ++b) {
+          const float* pb = ps + static_cast<int64_t>(b) * n;
+          const float4 e0 = ld4_nt(pb + i0), e1 = ld4_nt(pb + i1);
+          add4(d0, e0);
+          add4(d1, e1);
+        }
+      } else {
+        for (int b = 1; b < n_beams; ++b) {
+          const float* pb = ps + static_cast<int64_t>(b) * n;
+          const float4 e0 = ld4_nt(pb + i0), e1 = ld4_nt(pb + i1);
+          add4(d0, e0);
+          add4(d1, e1);
+        }
+      }
+      finish(d0, i0, p0, w0);
+      finish(d1, i1, p1, w1);
     }
+    if (v < nv) {
+      const int64_t i0 = b0 + 4 * v;
+      const float4 p0 = ld4(p + i0), w0 = ld4(w + i0);
+      float4 d0 = ld4_nt(ps + i0);
+      for (int b = 1; b < n_beams; ++b) add4(d0, ld4_nt(ps + static_cast<int64_t>(b) * n + i0));
+      finish(d0, i0, p0, w0);
+    }
+  } else {
+    for (int64_t v = threadIdx.x; v < nv; v += kRedThreads) {
+      const int64_t i0 = b0 + 4 * v;
+      float d[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = objective_term(acc, d[u], i + u * kRedThreads, so, p, w, d_out, seed);
-  }
-  for (; i < b1; i += kRedThreads) {
-    float d = ps[i];
-    for (int b = 1; b < n_beams; ++b) d += ps[static_cast<int64_t>(b) * n + i];
-    acc = objective_term(acc, d, i, so, p, w, d_out, seed);
+      for (int j = 0; j < 4; ++j) d[j] = i0 + j < b1 ? ps[i0 + j] : 0.0f;
+      for (int b = 1; b < n_beams; ++b) {
+        const float* pb = ps + static_cast<int64_t>(b) * n;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (i0 + j < b1) d[j] += pb[i0 + j];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t i = i0 + j;
+        if (i < b1) {
+          float sd;
+          acc = add_term(acc, d[j], p[i], w[i], sd);
+          if (d_out) d_out[so + i] = d[j];
+          if (seed) seed[so + i] = sd;
+        }
+      }
+    }
   }
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) partial[static_cast<int64_t>(s) * n_chunks + c] = t;
@@ -204,12 +268,41 @@ __global__ __launch_bounds__(256) void k_probe_copy(const uint4* __restrict__ sr
 
 }  // namespace
 
+namespace {
+bool aligned16(const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; }
+
+// Pass 1 over n_scen scenarios (chunks of whole 4-voxel vectors), then the
+// given pass 2.
+void scenario_pass1(int n_scen, int n_beams, int64_t n, const float* part, const float* p, const float* w,
+                    float* d_out, float* seed, double* partial, int n_partial, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t chunk = (n + n_partial - 1) / n_partial;
+  chunk = (chunk + 3) / 4 * 4;
+  const bool vec = n % 4 == 0 && aligned16(part) && aligned16(p) && aligned16(w) && aligned16(d_out) &&
+                   aligned16(seed);
+  const dim3 grid(static_cast<unsigned>(n_partial) * static_cast<unsigned>(n_scen));
+  auto go = [&](auto kernel) {
+    hipLaunchKernelGGL(kernel, grid, dim3(kRedThreads), 0, s, n_scen, n_beams, n, chunk, n_partial, part, p, w,
+                       d_out, seed, partial);
+  };
+  if (!vec) return go(k_scenario_pass1<false, 0>);
+  switch (n_beams) {
+    case 1: return go(k_scenario_pass1<true, 1>);
+    case 2: return go(k_scenario_pass1<true, 2>);
+    case 3: return go(k_scenario_pass1<true, 3>);
+    case 4: return go(k_scenario_pass1<true, 4>);
+    case 5: return go(k_scenario_pass1<true, 5>);
+    case 6: return go(k_scenario_pass1<true, 6>);
+    case 7: return go(k_scenario_pass1<true, 7>);
+    case 8: return go(k_scenario_pass1<true, 8>);
+    default: return go(k_scenario_pass1<true, 0>);
+  }
+}
+}  // namespace
+
 hipError_t launch_objective(int64_t n, const float* d, const float* p, const float* w, float* seed,
                             double* partial, int n_partial, double* f_out, hipStream_t s) {
-  const int64_t chunk = n_partial > 0 ? (n + n_partial - 1) / n_partial : 0;
-  if (n > 0)
-    hipLaunchKernelGGL(k_scenario_pass1, dim3(n_partial), dim3(kRedThreads), 0, s, 1, 1, n, chunk, n_partial, d,
-                       p, w, static_cast<float*>(nullptr), seed, partial);
+  scenario_pass1(1, 1, n, d, p, w, nullptr, seed, partial, n_partial, s);
   hipLaunchKernelGGL(k_pass2, dim3(1), dim3(kRedThreads), 0, s, partial, n > 0 ? n_partial : 0, 0, f_out);
   return hipGetLastError();
 }
@@ -217,11 +310,7 @@ hipError_t launch_objective(int64_t n, const float* d, const float* p, const flo
 hipError_t launch_scenario(int n_scen, int n_beams, int64_t n, const float* part, const float* p, const float* w,
                            const double* prob, float* d_out, float* seed, double* partial, int n_partial,
                            double* out, hipStream_t s) {
-  const int64_t chunk = n_partial > 0 ? (n + n_partial - 1) / n_partial : 0;
-  if (n > 0)
-    hipLaunchKernelGGL(k_scenario_pass1, dim3(static_cast<unsigned>(n_partial) * static_cast<unsigned>(n_scen)),
-                       dim3(kRedThreads), 0, s, n_scen, n_beams, n, chunk, n_partial, part, p, w, d_out, seed,
-                       partial);
+  scenario_pass1(n_scen, n_beams, n, part, p, w, d_out, seed, partial, n_partial, s);
   hipLaunchKernelGGL(k_scenario_pass2, dim3(1), dim3(kRedThreads), 0, s, partial, n > 0 ? n_partial : 0, n_scen,
                      prob, out);
   return hipGetLastError();

@@ -177,3 +177,82 @@ def test_scenario_argument_errors(dev):
                                              None, out.data_ptr() + 4, None)  # misaligned doubles
     assert st == -1
     torch.cuda.synchronize()
+
+
+def _random_epilogue_inputs(n_scen, n_beams, n, seed=11):
+    g = np.random.default_rng(seed)
+    part = g.uniform(0, 30, (n_scen, n_beams, n)).astype(np.float32)
+    part[:, :, g.random(n) < 0.3] = 0.0  # voxels outside every beam
+    p = g.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)
+    w = g.choice([1.0, 10.0], size=n).astype(np.float32)
+    return part, p, w
+
+
+def _offset(a: np.ndarray, floats: int):
+    """A contiguous device copy of a whose data starts `floats` floats into its buffer."""
+    buf = torch.empty(a.size + floats, dtype=torch.float32, device="cuda")
+    t = buf[floats:].view(a.shape)
+    t.copy_(torch.from_numpy(a))
+    return t
+
+
+@pytest.mark.parametrize("n", [10003, 4097, 6])
+def test_ragged_grid_parity(dev, n):
+    """A voxel count that is not a multiple of 4 takes the 4-byte path: the same
+    checks against the oracle as above."""
+    n_scen, n_beams = 5, 3
+    _say(f"scenario epilogue ragged grid: n={n}")
+    part_h, p, w = _random_epilogue_inputs(n_scen, n_beams, n)
+    prob_h = np.array([0.1, 0.3, 0.2, 0.25, 0.15])
+    d_out = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+    seed = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+    out = dm.scenario_objective(torch.from_numpy(part_h).cuda(), torch.from_numpy(p).cuda(),
+                                torch.from_numpy(w).cuda(), prob=torch.from_numpy(prob_h).cuda(),
+                                d_out=d_out, seed=seed).cpu().numpy()
+    d_h, seed_h = d_out.cpu().numpy(), seed.cpu().numpy()
+    for s in range(n_scen):
+        acc = part_h[s, 0].copy()
+        for b in range(1, n_beams):
+            acc = acc + part_h[s, b]
+        np.testing.assert_array_equal(_bits(d_h[s]), _bits(acc))
+        assert oracle.max_rel_err(d_h[s], oracle.beam_sum(part_h[s].astype(np.float64))) <= 2.0001 * 2.0 ** -24
+        d64 = d_h[s].astype(np.float64)
+        f_ref = oracle.objective(d64, p, w)
+        assert abs(out[s] - f_ref) <= 1e-13 * abs(f_ref)
+        np.testing.assert_array_equal(_bits(seed_h[s]), _bits(oracle.objective_seed(d64, p, w).astype(np.float32)))
+    worst, arg, expected = oracle.robust(out[:n_scen], prob_h)
+    assert out[n_scen] == worst and out[n_scen + 1] == expected and int(out[n_scen + 2]) == arg
+
+
+@pytest.mark.parametrize("n_beams", [3, 9])
+def test_aligned_and_misaligned_arrays_agree_bitwise(dev, n_beams):
+    """The 16-byte path (aligned arrays, n a multiple of 4; the beam count a
+    template argument up to 8 beams, a loop beyond) and the 4-byte path add the
+    same terms in the same order: every output is bitwise equal, and the
+    scenario doses are the FP32 sums in ascending beam order."""
+    n_scen, n = 4, 12288
+    _say(f"scenario epilogue aligned vs misaligned: {n_beams} beams")
+    part_h, p, w = _random_epilogue_inputs(n_scen, n_beams, n, seed=12)
+    res = []
+    for off in (0, 1):
+        d_out = _offset(np.zeros((n_scen, n), np.float32), off)
+        seed = _offset(np.zeros((n_scen, n), np.float32), off)
+        out = dm.scenario_objective(_offset(part_h, off), _offset(p, off), _offset(w, off), d_out=d_out,
+                                    seed=seed).cpu().numpy()
+        res.append((out, d_out.cpu().numpy(), seed.cpu().numpy()))
+    np.testing.assert_array_equal(res[0][0], res[1][0])
+    np.testing.assert_array_equal(_bits(res[0][1]), _bits(res[1][1]))
+    np.testing.assert_array_equal(_bits(res[0][2]), _bits(res[1][2]))
+    for s in range(n_scen):
+        acc = part_h[s, 0].copy()
+        for b in range(1, n_beams):
+            acc = acc + part_h[s, b]
+        np.testing.assert_array_equal(_bits(res[0][1][s]), _bits(acc))
+        f_ref = oracle.objective(res[0][1][s].astype(np.float64), p, w)
+        assert abs(res[0][0][s] - f_ref) <= 1e-13 * abs(f_ref)
+    # the plain objective takes the same two paths
+    d = part_h[0, 0]
+    f_al = dm.objective(_offset(d, 0), _offset(p, 0), _offset(w, 0)).item()
+    f_mis = dm.objective(_offset(d, 1), _offset(p, 1), _offset(w, 1)).item()
+    assert f_al == f_mis == dm.scenario_objective(_offset(part_h[:1, :1].copy(), 0), _offset(p, 0),
+                                                  _offset(w, 0)).cpu().numpy()[0]
