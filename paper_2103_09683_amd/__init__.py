@@ -17,7 +17,8 @@ import torch
 from . import _lib
 from ._lib import DoseError
 
-__all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", "norm2",
+__all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
+           "ScenarioObjective",
            "csr_validate", "partition_preview", "byte_model", "DoseSpMV", "DoseObjective",
            "dose", "VALUE_FORMATS"]
 
@@ -324,6 +325,41 @@ class DoseObjective(torch.autograd.Function):
     def backward(ctx, gf):
         (seed,) = ctx.saved_tensors
         return seed * gf.float(), None, None
+
+
+class ScenarioObjective(torch.autograd.Function):
+    """Robust objective of the beam doses part (n_scen, n_beams, n): the
+    expectation sum_s prob_s f_s (mode "expected"; the mean without prob) or
+    the worst case max_s f_s (mode "worst"), f_s = sum w (d_s - p)^2 with d_s
+    the scenario's beam sum.  d/dpart[s, b] = c_s 2 w (d_s - p) for every beam
+    b, with c_s = prob_s (expected) or 1 for the first worst scenario and 0
+    otherwise (worst)."""
+
+    @staticmethod
+    def forward(ctx, part, p, w, prob=None, mode: str = "expected"):
+        if mode not in ("expected", "worst"):
+            raise ValueError("mode is 'expected' or 'worst'")
+        part = part.contiguous()
+        n_scen, n_beams, n = part.shape
+        seed = torch.empty(n_scen, n, dtype=torch.float32, device=part.device)
+        out = scenario_objective(part, p.contiguous(), w.contiguous(),
+                                 prob=None if prob is None else prob.contiguous(), seed=seed)
+        if mode == "expected":
+            c = prob if prob is not None else torch.full((n_scen,), 1.0 / n_scen, dtype=torch.float64,
+                                                         device=part.device)
+            f = out[n_scen + 1]
+        else:
+            c = (torch.arange(n_scen, device=part.device) == out[n_scen + 2].long()).to(torch.float64)
+            f = out[n_scen]
+        ctx.save_for_backward(seed, c)
+        ctx.n_beams = n_beams
+        return f.reshape(())
+
+    @staticmethod
+    def backward(ctx, gf):
+        seed, c = ctx.saved_tensors
+        g = seed * (c * gf.double()).float()[:, None]
+        return g[:, None, :].expand(-1, ctx.n_beams, -1), None, None, None, None
 
 
 def dose(x: torch.Tensor, A: DoseMatrix) -> torch.Tensor:

@@ -256,3 +256,56 @@ def test_aligned_and_misaligned_arrays_agree_bitwise(dev, n_beams):
     f_mis = dm.objective(_offset(d, 1), _offset(p, 1), _offset(w, 1)).item()
     assert f_al == f_mis == dm.scenario_objective(_offset(part_h[:1, :1].copy(), 0), _offset(p, 0),
                                                   _offset(w, 0)).cpu().numpy()[0]
+
+
+@pytest.mark.parametrize("mode", ["expected", "worst"])
+def test_robust_gradient_through_autograd(dev, mode):
+    """x_b -> beam doses (DoseSpMV) -> robust objective (ScenarioObjective): the
+    spot-weight gradient of beam b must be sum_s c_s A_sb^T seed_s, with the
+    GPU's own seeds and c_s the probabilities (expected) or the worst
+    scenario's indicator (worst), each adjoint within 1e-5 of |A|^T |c seed|
+    (the adjoint's bound) plus the FP32 sum over scenarios."""
+    n_scen, n_beams = 3, 2
+    _say(f"robust gradient: mode={mode}")
+    specs = dosegen.robust_scenarios(7 / 64, n_scen, n_beams, nx=41, ny=40, spots_per_line=20)
+    mats, host = [], []
+    for sp in specs:
+        rp, cols, vals = dosegen.csr(sp)
+        mats.append(dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16", transpose=True))
+        host.append((rp, cols, vals))
+    n = specs[0].n_rows
+    g = np.random.default_rng(78)
+    pd = torch.from_numpy(g.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)).cuda()
+    wd = torch.from_numpy(g.choice([1.0, 10.0], size=n).astype(np.float32)).cuda()
+    prob_h = np.array([0.5, 0.2, 0.3])
+    prob = torch.from_numpy(prob_h).cuda()
+    xs = [torch.from_numpy(dosegen.spot_weights(dosegen.SEED0 + 6, b, specs[b].n_cols)).cuda().requires_grad_(True)
+          for b in range(n_beams)]
+    part = torch.stack([torch.stack([dm.dose(xs[b], mats[s * n_beams + b]) for b in range(n_beams)])
+                        for s in range(n_scen)])
+    f = dm.ScenarioObjective.apply(part, pd, wd, prob if mode == "expected" else None, mode)
+    f.backward()
+
+    seed = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+    out = dm.scenario_objective(part.detach(), pd, wd, prob=prob, seed=seed).cpu().numpy()
+    seed_h = seed.cpu().numpy().astype(np.float64)
+    if mode == "expected":
+        assert f.item() == out[n_scen + 1]
+        c = prob_h
+    else:
+        assert f.item() == out[n_scen]
+        c = np.zeros(n_scen)
+        c[int(out[n_scen + 2])] = 1.0
+    for b in range(n_beams):
+        n_cols = specs[b].n_cols
+        g_ref = np.zeros(n_cols)
+        scale = np.zeros(n_cols)
+        for s in range(n_scen):
+            rp, cols, vals = host[s * n_beams + b]
+            dec, _ = oracle.decode_matrix("fp16", rp, vals)
+            g_ref += c[s] * oracle.spmv_T(rp, cols, dec, seed_h[s], n_cols)
+            scale += abs(c[s]) * oracle.spmv_T(rp, cols, np.abs(dec), np.abs(seed_h[s]), n_cols)
+        grad = xs[b].grad.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(grad - g_ref) <= (TOL + (n_scen + 1) * 2.0 ** -24) * scale + 1e-30)
+    for A in mats:
+        A.close()
