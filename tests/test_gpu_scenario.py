@@ -309,3 +309,52 @@ def test_robust_gradient_through_autograd(dev, mode):
         assert np.all(np.abs(grad - g_ref) <= (TOL + (n_scen + 1) * 2.0 ** -24) * scale + 1e-30)
     for A in mats:
         A.close()
+
+
+def test_robust_step_at_bench_size(dev):
+    """The robust-plan step as the bench times it: 9 scenarios x 4 beams on the
+    128 x 128 x 6 grid (98,304 voxels, about 4.8e8 stored entries), all beam
+    doses in one autotuned graph plan, then the epilogue.  Every beam dose is
+    checked against the oracle's product (relative 1e-5), the epilogue against
+    the oracle on the GPU's beam doses as above."""
+    n_scen, n_beams = 9, 4
+    specs = dosegen.robust_scenarios(0.1, n_scen, n_beams)
+    n = specs[0].n_rows
+    _say(f"robust step at bench size: {n} voxels, {len(specs)} matrices")
+    xs_h = [dosegen.spot_weights(dosegen.SEED0 + 6, b, specs[b].n_cols) for b in range(n_beams)]
+    xs = [torch.from_numpy(x).cuda() for x in xs_h]
+    part = torch.empty(n_scen, n_beams, n, dtype=torch.float32, device=dev)
+    mats, entries, y_ref = [], [], []
+    for m, sp in enumerate(specs):
+        rp, cols, vals = dosegen.csr(sp)
+        A = dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16")
+        mats.append(A)
+        s, b = divmod(m, n_beams)
+        entries.append((A, xs[b], part[s, b]))
+        dec, _ = oracle.decode_matrix("fp16", rp, vals)
+        y_ref.append(oracle.spmv(rp, cols, dec, xs_h[b]))
+        del rp, cols, vals, dec
+    plan = dm.BatchPlan(entries, autotune=True)
+    plan.launch()
+    g = np.random.default_rng(6)
+    p = g.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)
+    w = g.choice([1.0, 10.0], size=n).astype(np.float32)
+    d_out = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+    out = dm.scenario_objective(part, torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda(),
+                                d_out=d_out).cpu().numpy()
+    part_h, d_h = part.cpu().numpy(), d_out.cpu().numpy()
+    for m in range(len(specs)):
+        s, b = divmod(m, n_beams)
+        assert oracle.max_rel_err(part_h[s, b], y_ref[m]) <= TOL, specs[m].name
+    for s in range(n_scen):
+        acc = part_h[s, 0].copy()
+        for b in range(1, n_beams):
+            acc = acc + part_h[s, b]
+        np.testing.assert_array_equal(_bits(d_h[s]), _bits(acc))
+        f_ref = oracle.objective(d_h[s].astype(np.float64), p, w)
+        assert abs(out[s] - f_ref) <= 1e-13 * abs(f_ref)
+    worst, arg, expected = oracle.robust(out[:n_scen])
+    assert out[n_scen] == worst and out[n_scen + 1] == expected and int(out[n_scen + 2]) == arg
+    plan.close()
+    for A in mats:
+        A.close()

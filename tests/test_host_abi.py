@@ -204,3 +204,29 @@ def test_row_length_limit_in_partition():
     bad = np.array([0, 1 << 28], np.int64)
     with pytest.raises(dm.DoseError):
         dm.partition_preview(bad, 16384)
+
+
+def test_scenario_objective_rejects_bad_arguments_before_any_device_work():
+    """Argument checks of the robust-plan epilogue run on the host first: bad
+    counts, sizes, null or misaligned arrays, overlapping outputs and inputs
+    return INVALID_ARGUMENT (the pointers below are never dereferenced)."""
+    lib = _lib.load()
+    f = lib.dose_scenario_objective
+    buf = np.zeros(4096, np.float64)  # host memory, only used as distinct addresses
+    base = buf.ctypes.data
+    part, p, w, out = base, base + 8192, base + 12288, base + 16384
+    ok = dict(n_scen=2, n_beams=2, n=64, part=part, p=p, w=w, prob=None, d_out=None, seed=None, out=out)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n_scen"], a["n_beams"], a["n"], a["part"], a["p"], a["w"], a["prob"], a["d_out"],
+                 a["seed"], a["out"], None)
+
+    bad = [dict(n_scen=0), dict(n_beams=0), dict(n_scen=65537), dict(n_beams=65537), dict(n=-1),
+           dict(out=None), dict(part=None), dict(p=None), dict(w=None), dict(part=part + 2),
+           dict(out=out + 4), dict(prob=out + 4 + 8 * 64), dict(d_out=part),
+           dict(d_out=base + 20480, seed=base + 20480 + 4), dict(seed=p),
+           dict(n=2 ** 61)]
+    for kw in bad:
+        assert call(**kw) == _lib.ERR_INVALID_ARGUMENT, kw
+        assert lib.dose_last_error()
