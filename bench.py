@@ -13,11 +13,11 @@ norm), the product with 16-bit column indices, the paper's half/double
 bias controls (beam along x, irregular row lengths), the batched
 robust-scenario product, the robust-plan step (9 scenarios x 4 beams on one
 dose grid, then the scenario epilogue) and a small cache-resident matrix;
-besides them the
-roofline of the dominant kernel (with the HBM traffic the committed rocprofv3
-record gives while the kernel code is unchanged), the median and standard
-deviation of single launches, a read-only HBM ceiling probe, and the CPU
-oracle timed on the host.  --sweep adds the largest workload.
+besides them the roofline of the dominant kernel (with the HBM traffic the
+committed rocprofv3 record gives while the kernel code is unchanged), the
+median and standard deviation of single launches, a read-only HBM ceiling
+probe, and the CPU oracle timed on the host.  --sweep adds the largest workload; --robust-step and
+--scenario-epilogue time only the robust-plan step or its epilogue.
 """
 from __future__ import annotations
 
@@ -175,6 +175,8 @@ def main(argv=None):
                     help="only run the copy probe over this many GiB (counter calibration)")
     ap.add_argument("--scenario-epilogue", action="store_true",
                     help="only time the robust-plan epilogue on the full 1,048,576-voxel grid")
+    ap.add_argument("--robust-step", action="store_true",
+                    help="only time the robust-plan step (9 scenarios x 4 beams, then the epilogue)")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the largest workload (8,388,608 x 60,000, 1.7e9 entries) in the three "
                          "value formats, forward and adjoint")
@@ -204,6 +206,9 @@ def main(argv=None):
 
     if args.scenario_epilogue:
         print(json.dumps({"scenario_epilogue": bench_epilogue_full(torch, dm, args.steps)}))
+        return
+    if args.robust_step:
+        print(json.dumps({"robust_scenarios": bench_scenarios(torch, dm, dosegen, args)}))
         return
 
     spec = dosegen.clinical_beam()
