@@ -3,9 +3,11 @@
 // The quadratic objective f = sum_v w_v (d_v - p_v)^2 (of one dose vector, or
 // of every scenario of a robust plan, whose dose is the sum of its beams'
 // doses) and the gradient norm are accumulated in FP64 with a two-pass
-// reduction whose order depends only on n: pass 1 gives workgroup b the fixed range [b*C, (b+1)*C) and reduces
-// it with a fixed per-thread stride and a fixed LDS tree; pass 2 reduces the
-// partials the same way in one workgroup.  No atomics (Sec. II-D).
+// reduction whose order depends only on n: pass 1 gives workgroup b the fixed
+// range [b*C, (b+1)*C), in which each thread adds its terms in a fixed order
+// (the norm: elements t, t + 256, ...; the objective: 4-element vectors t,
+// t + 256, ..., C a multiple of 4) before a fixed LDS tree; pass 2 reduces
+// the partials the same way in one workgroup.  No atomics (Sec. II-D).
 #include "dose_internal.h"
 
 namespace dose {
