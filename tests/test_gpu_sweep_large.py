@@ -73,7 +73,12 @@ def test_sweep_large_forward_and_adjoint(sweep, fmt, dev):
     _say("forward done")
     dec, _ = oracle.decode_matrix(fmt, srp, svals)
     y_ref = oracle.spmv(srp, scols, dec, x_h)
-    assert oracle.max_rel_err(y[rows], y_ref) <= TOL, fmt
+    err = oracle.max_rel_err(y[rows], y_ref)
+    # reported only: the format's own error (oracle on decoded vs on FP32 source values)
+    src, _ = oracle.decode_matrix("fp32", srp, svals)
+    fmt_err = oracle.max_rel_err(y_ref, oracle.spmv(srp, scols, src, x_h)) if fmt != "fp32" else 0.0
+    _say(f"{fmt}: forward max rel err {err:.3e} on {rows.size} sampled rows; format error {fmt_err:.3e}")
+    assert err <= TOL, fmt
     lens = np.diff(rp)
     assert np.all(_bits(y[lens == 0]) == 0) and np.all(y[lens > 0] > 0)
 
@@ -85,7 +90,9 @@ def test_sweep_large_forward_and_adjoint(sweep, fmt, dev):
     _say("adjoint done")
     g_ref = oracle.spmv_T(srp, scols, dec, v_s, spec.n_cols)
     scale = oracle.spmv_T(srp, scols, np.abs(dec), np.abs(v_s), spec.n_cols)
-    assert oracle.max_scaled_err(g, g_ref, scale) <= TOL, fmt
+    err_a = oracle.max_scaled_err(g, g_ref, scale)
+    _say(f"{fmt}: adjoint max scaled err {err_a:.3e} over all {spec.n_cols} spots")
+    assert err_a <= TOL, fmt
 
     # adjointness at full size with a dense signed v (A >= 0 and x >= 0, so
     # |A| |x| = A x = y)

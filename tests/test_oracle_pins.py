@@ -445,3 +445,45 @@ def test_robust_expectation_vs_exact_fractions():
         assert worst == f.max() and arg == int(np.argmax(f))
         _, _, mean = oracle.robust(f)
         assert mean == float(Fraction(int(fi.sum()), 4)) / n
+
+
+# --------------------------------------------------------------------------
+# format error: the oracle on decoded values against the oracle on the FP32
+# source values (reported, and held to each format's rounding bound)
+# --------------------------------------------------------------------------
+def test_format_error_within_each_formats_rounding_bound(capsys):
+    """Per row, |y(decoded) - y(source)| <= sum_k e_k x_k with the per-entry
+    rounding bound e_k of the format: FP16 max(2^-11 |a|, 2^-25) (normal and
+    subnormal half-ulp), BF16 2^-8 |a|, E4M3 with row scale s
+    (2^-4 + 2^-22) |a| + 2^-10 s (1 + 2^-22) (half-ulp of normal and
+    subnormal codes of a/s, plus the FP32 roundings of a/s and q s).  The
+    largest relative format error over non-empty rows is printed."""
+    import dosegen
+    spec = dosegen.small_plain()
+    rp, cols, vals = dosegen.csr(spec)
+    x = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
+    src, _ = oracle.decode_matrix("fp32", rp, vals)
+    y_src = oracle.spmv(rp, cols, src, x)
+    a = np.abs(vals.astype(np.float64))
+    lens = np.diff(rp)
+    row_of = np.repeat(np.arange(lens.size), lens)
+    report = {}
+    for fmt in ("fp16", "bf16", "fp8e4m3_rowscale"):
+        dec, scale = oracle.decode_matrix(fmt, rp, vals)
+        y = oracle.spmv(rp, cols, dec, x)
+        if fmt == "fp16":
+            e = np.maximum(2.0 ** -11 * a, 2.0 ** -25)
+        elif fmt == "bf16":
+            e = 2.0 ** -8 * a
+        else:
+            s = np.asarray(scale, np.float64)[row_of]
+            e = (2.0 ** -4 + 2.0 ** -22) * a + 2.0 ** -10 * s * (1 + 2.0 ** -22)
+        bound = np.bincount(row_of, weights=e * x[cols].astype(np.float64), minlength=lens.size)
+        assert np.all(np.abs(y - y_src) <= bound * (1 + 1e-9) + 1e-300), fmt
+        nz = y_src != 0
+        report[fmt] = float(np.max(np.abs(y[nz] - y_src[nz]) / y_src[nz]))
+    with capsys.disabled():
+        print(f"\nformat error (max relative, {spec.name}): " +
+              ", ".join(f"{k} {v:.3e}" for k, v in report.items()))
+    # the formats' unit roundoffs order the errors
+    assert report["fp16"] < report["bf16"] < report["fp8e4m3_rowscale"]
