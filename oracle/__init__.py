@@ -244,30 +244,47 @@ def norm2(g) -> float:
 
 
 # ----------------------------------------------------------------- error metrics
+# The parity bar of the dose product (Listing 1's per-voxel sum, FP32 against
+# the FP64 definition): a per-voxel relative error, or, for signed inputs, the
+# error scaled componentwise by |A| |x|.  Both are maxima over all entries; an
+# entry whose reference (or scale) is exactly zero must itself be zero (either
+# sign; where the sign is fixed, as for empty rows, tests check the bits), and
+# a non-finite result is never within any bound.
 def max_rel_err(y, y_ref) -> float:
-    """max_i |y_i - y*_i| / |y*_i| over rows with y*_i != 0; rows with y*_i == 0
-    must hold exactly 0 in y (returns inf otherwise)."""
-    y = np.asarray(y, np.float64)
-    y_ref = np.asarray(y_ref, np.float64)
-    zero = y_ref == 0.0
-    if np.any(y[zero] != 0.0):
+    """max_i |y_i - y*_i| / |y*_i| over entries with y*_i != 0; returns inf if
+    an entry with y*_i == 0 is not 0 in y, or if any y_i is not finite."""
+    y = np.asarray(y, np.float64).reshape(-1)
+    y_ref = np.asarray(y_ref, np.float64).reshape(-1)
+    if y.shape != y_ref.shape:
+        raise ValueError("y and y_ref differ in size")
+    if not np.all(np.isfinite(y)):
         return float("inf")
-    nz = ~zero
-    if not np.any(nz):
+    ref_zero = y_ref == 0.0
+    if np.any(y[ref_zero] != 0.0):
+        return float("inf")
+    keep = ~ref_zero
+    if not np.any(keep):
         return 0.0
-    return float(np.max(np.abs(y[nz] - y_ref[nz]) / np.abs(y_ref[nz])))
+    rel = np.abs(y[keep] - y_ref[keep]) / np.abs(y_ref[keep])
+    return float(np.max(rel))
 
 
 def max_scaled_err(y, y_ref, scale) -> float:
-    """max_j |y_j - y*_j| / scale_j with scale = |A| |x| (componentwise); entries
-    with scale_j == 0 must be exactly 0."""
-    y = np.asarray(y, np.float64)
-    y_ref = np.asarray(y_ref, np.float64)
-    scale = np.asarray(scale, np.float64)
-    zero = scale == 0.0
-    if np.any(y[zero] != 0.0):
+    """max_j |y_j - y*_j| / scale_j with scale = |A| |x| (componentwise);
+    returns inf if an entry with scale_j == 0 is not 0 in y, or if any y_j is
+    not finite."""
+    y = np.asarray(y, np.float64).reshape(-1)
+    y_ref = np.asarray(y_ref, np.float64).reshape(-1)
+    scale = np.asarray(scale, np.float64).reshape(-1)
+    if y.shape != y_ref.shape or y.shape != scale.shape:
+        raise ValueError("y, y_ref and scale differ in size")
+    if not np.all(np.isfinite(y)):
         return float("inf")
-    nz = ~zero
-    if not np.any(nz):
+    scale_zero = scale == 0.0
+    if np.any(y[scale_zero] != 0.0):
+        return float("inf")
+    held = ~scale_zero
+    if not np.any(held):
         return 0.0
-    return float(np.max(np.abs(y[nz] - y_ref[nz]) / scale[nz]))
+    scaled = np.abs(y[held] - y_ref[held]) / scale[held]
+    return float(np.max(scaled))

@@ -4,13 +4,20 @@ Each case plants one mistake in a copy of the oracle's C source (on the CPU,
 in a temporary directory), builds it, points the oracle module at the copy and
 runs the pin checks of test_oracle_pins.py; at least one must fail.  The
 planted mistakes never index outside the arrays the checks pass.
+
+The error metrics (the parity gate, written in Python in the oracle package)
+are mutated the same way: one mistake in a copy of the package's source,
+executed as a separate module whose metric functions replace the oracle's,
+and the pins of test_oracle_metrics.py must catch it.
 """
 import os
 import subprocess
+import types
 
 import pytest
 
 import oracle
+import test_oracle_metrics as metric_pins
 import test_oracle_pins as pins
 
 # (name, text in dose_oracle.c, replacement)
@@ -122,3 +129,68 @@ def test_unmutated_copy_passes_every_check(tmp_path, monkeypatch):
     for check in CHECKS:
         check()
     assert os.path.exists(so)
+
+
+# (name, function, text in that function of oracle/__init__.py, replacement)
+METRIC_MUTANTS = [
+    ("relative error divided by the result",
+     "max_rel_err", "/ np.abs(y_ref[keep])", "/ np.abs(y[keep])"),
+    ("relative error: mean instead of maximum",
+     "max_rel_err", "return float(np.max(rel))", "return float(np.mean(rel))"),
+    ("relative error: zero-reference rule inverted",
+     "max_rel_err", "if np.any(y[ref_zero] != 0.0):", "if np.any(y[ref_zero] == 0.0):"),
+    ("relative error: zero-reference rule dropped",
+     "max_rel_err", "if np.any(y[ref_zero] != 0.0):", "if False:"),
+    ("relative error: signed difference",
+     "max_rel_err", "np.abs(y[keep] - y_ref[keep])", "(y[keep] - y_ref[keep])"),
+    ("relative error: non-finite results pass",
+     "max_rel_err", "if not np.all(np.isfinite(y)):", "if False:"),
+    ("scaled error divided by the reference",
+     "max_scaled_err", "/ scale[held]", "/ np.abs(y_ref[held])"),
+    ("scaled error: mean instead of maximum",
+     "max_scaled_err", "return float(np.max(scaled))", "return float(np.mean(scaled))"),
+    ("scaled error: zero-scale rule inverted",
+     "max_scaled_err", "if np.any(y[scale_zero] != 0.0):", "if np.any(y[scale_zero] == 0.0):"),
+    ("scaled error: signed difference",
+     "max_scaled_err", "np.abs(y[held] - y_ref[held])", "(y[held] - y_ref[held])"),
+    ("scaled error: non-finite results pass",
+     "max_scaled_err", "if not np.all(np.isfinite(y)):", "if False:"),
+]
+
+
+def _function_span(src, name):
+    start = src.index(f"def {name}(")
+    end = src.find("\ndef ", start + 1)
+    return start, (len(src) if end < 0 else end)
+
+
+def _mutated_module(src):
+    mod = types.ModuleType("oracle_mutant")
+    mod.__file__ = oracle.__file__
+    exec(compile(src, "oracle_mutant", "exec"), mod.__dict__)
+    return mod
+
+
+@pytest.mark.parametrize("name,func,old,new", METRIC_MUTANTS, ids=[m[0] for m in METRIC_MUTANTS])
+def test_metric_pins_catch_planted_mistake(name, func, old, new, monkeypatch):
+    src = open(oracle.__file__).read()
+    a, b = _function_span(src, func)
+    body = src[a:b]
+    assert body.count(old) == 1, f"mutation site not found: {name}"
+    mod = _mutated_module(src[:a] + body.replace(old, new) + src[b:])
+    monkeypatch.setattr(oracle, func, getattr(mod, func))
+    caught = []
+    for check in metric_pins.CHECKS:
+        try:
+            check()
+        except AssertionError:
+            caught.append(check.__name__)
+    assert caught, f"no pin caught: {name}"
+
+
+def test_unmutated_metrics_pass_every_check(monkeypatch):
+    mod = _mutated_module(open(oracle.__file__).read())
+    monkeypatch.setattr(oracle, "max_rel_err", mod.max_rel_err)
+    monkeypatch.setattr(oracle, "max_scaled_err", mod.max_scaled_err)
+    for check in metric_pins.CHECKS:
+        check()
