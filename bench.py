@@ -1,23 +1,27 @@
 """Benchmark of the dose product d = A x on one MI355X.
 
-Default workload: one clinical-scale beam, 128^3 = 2,097,152 voxels x 25,000
-spots, ~200 stored entries per row over all rows (60% of rows empty), stored
-in the paper's format (FP16 values, int32 column indices), FP32 x, y and
-accumulation.  One step is one plain product over the whole matrix with the
-inputs resident in HBM.  Prints ONE JSON line.
+Default workload (the headline): the largest single-GPU dose matrix,
+256 x 256 x 128 = 8,388,608 voxels x 60,000 spots, ~200 stored entries per
+row over all rows (60% of rows empty, 1.68e9 entries), stored in the paper's
+format (FP16 values, int32 column indices) and multiplied in the paper's
+half/double arithmetic (FP64 spot weights, FP64 products, sums and dose).
+One step is one product over the whole matrix with the inputs resident in
+HBM.  Prints ONE JSON line.
 
-The same line carries, as variants: the adjoint g = A^T v, one
-plan-optimisation iteration (dose, FP64 objective, adjoint, FP64 gradient
-norm), the product with 16-bit column indices, the paper's half/double
-(FP64 spot weights and dose) and Single (FP32 values) configurations, the
-bias controls (beam along x, irregular row lengths), the batched
-robust-scenario product, the robust-plan step (9 scenarios x 4 beams on one
-dose grid, then the scenario epilogue) and a small cache-resident matrix;
-besides them the roofline of the dominant kernel (with the HBM traffic the
-committed rocprofv3 record gives while the kernel code is unchanged), the
-median and standard deviation of single launches, a read-only HBM ceiling
-probe, and the CPU oracle timed on the host.  --sweep adds the largest workload; --robust-step and
---scenario-epilogue time only the robust-plan step or its epilogue.
+The same line carries, as variants: on the same matrix the FP32-vector
+product in FP16, BF16 and E4M3 values (32- and 16-bit indices) and the
+adjoints; on one clinical-scale beam (2,097,152 x 25,000) the FP32, 16-bit
+index, half/double and Single (FP32 values) products, the adjoint, one
+plan-optimisation iteration and the bias controls (beam along x, irregular
+row lengths); the batched robust-scenario product at full size (36 matrices,
+4 spot-weight vectors each, one autotuned graph launch); the robust-plan step
+(9 scenarios x 4 beams on one dose grid, then the scenario epilogue); and a
+small cache-resident matrix.  Besides them: the roofline of the dominant
+kernel (with the HBM traffic the committed rocprofv3 record gives while the
+kernel code is unchanged), the median and standard deviation of single
+launches, a read-only HBM ceiling probe, and the CPU oracle timed on the
+host, one thread and all threads.  --robust-step and --scenario-epilogue time
+only the robust-plan step or its epilogue; --quick skips the variants.
 """
 from __future__ import annotations
 
@@ -34,7 +38,7 @@ if ROOT not in sys.path:
 
 METRIC = "dose SpMV GNNZ/s and % HBM roofline, plain vs batched/adjoint at rel err ≤1e-5"
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_clinical_beam_fp16.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_f64_sweep_large_fp16.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_09683_amd", "csrc", f)
                   for f in ("spmv_kernels.hip", "dose_internal.h", "dose_api.cpp")]
 
@@ -134,30 +138,201 @@ def hbm_read_ceiling(torch, dm, gib: float = 4.0) -> float:
 
 
 def cpu_baseline(spec, rp, cols, vals, x, y_gpu, budget_s: float):
-    """The CPU oracle (plain FP64 CSR product, one thread) on the same matrix,
-    repeated to fill about `budget_s` seconds; also checks the GPU dose on a
-    seeded row sample against the oracle's."""
+    """The CPU oracle (plain FP64 CSR product over the decoded FP16 values) on
+    the same matrix and spot weights, timed on all host threads (rows shared
+    among them) and on one thread, each repeated to fill about budget_s / 2
+    seconds; also the GPU dose against the oracle's, on every row."""
     import numpy as np
 
     import oracle
     dec, _ = oracle.decode_matrix("fp16", rp, vals)
-    t0 = time.perf_counter()
-    y_ref = oracle.spmv(rp, cols, dec, x)
-    t1 = time.perf_counter()
-    reps = 1
-    while (t1 - t0) < budget_s and reps < 50:
-        oracle.spmv(rp, cols, dec, x)
-        reps += 1
+    nnz = int(rp[-1])
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        y = fn(rp, cols, dec, x)
         t1 = time.perf_counter()
-    sec = (t1 - t0) / reps
-    rng = np.random.default_rng(11)
-    rows = rng.integers(0, rp.size - 1, 20000)
-    err = oracle.max_rel_err(y_gpu[rows], y_ref[rows])
-    full_err = oracle.max_rel_err(y_gpu, y_ref)
-    return {"value": round(rp[-1] / sec / 1e9, 4), "unit": "GNNZ/s", "cores": 1, "kind": "oracle",
-            "sample": f"full {spec.name} matrix ({int(rp[-1])} nnz), {reps} passes of the single-thread "
-                      f"FP64 oracle, {sec:.3f} s per pass",
-            "max_rel_err_vs_gpu": full_err, "max_rel_err_vs_gpu_20k_rows": err}
+        reps = 1
+        while (t1 - t0) < budget_s / 2 and reps < 50:
+            fn(rp, cols, dec, x)
+            reps += 1
+            t1 = time.perf_counter()
+        return y, (t1 - t0) / reps, reps
+
+    y_ref, sec_all, reps_all = timed(oracle.spmv_parallel)
+    _, sec_one, reps_one = timed(oracle.spmv)
+    threads = oracle.num_threads()
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count()
+    err = oracle.max_rel_err(y_gpu, y_ref)
+    return {"value": round(nnz / sec_all / 1e9, 4), "unit": "GNNZ/s", "cores": threads, "kind": "oracle",
+            "sample": f"full {spec.name} matrix ({nnz} nnz, FP16 values decoded), FP64 sums: {reps_all} passes "
+                      f"with the rows shared among {threads} OpenMP threads, {sec_all:.3f} s per pass; "
+                      f"{reps_one} single-thread passes, {sec_one:.3f} s per pass",
+            "single_thread_GNNZ_per_s": round(nnz / sec_one / 1e9, 4),
+            "host_cpus": os.cpu_count(), "host_cpus_usable": affinity,
+            "max_rel_err_gpu_vs_oracle": err}
+
+
+def bench_headline(torch, dm, dosegen, args):
+    """The largest workload in the paper's format and arithmetic: FP16 values,
+    int32 indices, FP64 spot weights and dose (dose_spmv_f64).  Returns the
+    matrix and its host arrays for the variants on the same matrix."""
+    import numpy as np
+    spec = dosegen.sweep_large()
+    t0 = time.time()
+    rp, cols, vals = dosegen.csr(spec)
+    log(f"generated {spec.name}: {int(rp[-1])} nnz in {time.time() - t0:.1f}s")
+    x_h = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
+    t0 = time.time()
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", transpose=not args.quick)
+    log(f"created matrix (fp16) in {time.time() - t0:.1f}s: {A.info()}")
+    info = A.info()
+    nnz = info["nnz"]
+    x64 = torch.from_numpy(x_h.astype(np.float64)).cuda()
+    y64 = torch.empty(spec.n_rows, dtype=torch.float64, device="cuda")
+    ms = time_launches(lambda: A.spmv(x64, y64), args.steps, args.warmup)
+    nbytes = dm.byte_model(nnz, spec.n_rows, spec.n_cols, value_bytes=2, index_bytes=4, row_ptr_bytes=4,
+                           x_bytes=8, y_bytes=8) + 4
+    gnnz = nnz / (ms * 1e-3) / 1e9
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    log(f"headline half/double: {ms:.4f} ms/step, {gnnz:.1f} GNNZ/s, {achieved:.0f} GB/s algorithmic")
+    med, sd = launch_stats(lambda: A.spmv(x64, y64), args.steps, 2)
+    out = {
+        "metric": METRIC, "value": round(gnnz, 3), "unit": "GNNZ/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded ray-run dose-deposition matrix; the paper's patient matrices are not public)",
+        "config": {"workload": spec.name, "n_rows": spec.n_rows, "n_cols": spec.n_cols, "nnz": nnz,
+                   "empty_row_frac": float(np.mean(np.diff(rp) == 0)),
+                   "value_format": "fp16", "index_format": "i32", "x_y": "f64", "accumulate": "f64",
+                   "arithmetic": "half/double (Sec. II-D)",
+                   "group_nnz": info["group_nnz"], "n_groups": info["n_groups"],
+                   "n_groups_x_in_lds": info["n_groups_windowed"], "n_groups_split": info["n_groups_split"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": measured_traffic(nbytes), "algorithmic_bytes_per_launch": nbytes,
+                     "byte_model": "6 nnz + 4 (n_rows + 1) + 8 n_rows + 8 n_cols (the paper's 6 nnz + 12 nr + 8 nc)",
+                     "kernel": "k_spmv_f64<fp16, int32> (row groups, x window in LDS)"},
+        "ms_per_launch_median": round(med, 5), "ms_per_launch_std": round(sd, 5),
+    }
+    return out, spec, A, rp, cols, vals, x_h, y64
+
+
+def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
+    """On the headline matrix: FP32 vectors in FP16 (the stored A), the
+    adjoint in FP32 and FP64; then BF16 and E4M3 values (forward and adjoint)
+    and 16-bit indices in the three formats (forward)."""
+    import numpy as np
+    reps = max(20, args.steps)
+    x = torch.from_numpy(x_h).cuda()
+    v_h = dosegen_signed(spec)
+    v = torch.from_numpy(v_h).cuda()
+    y = torch.empty(spec.n_rows, dtype=torch.float32, device="cuda")
+    g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
+    res = {"workload": spec.name}
+
+    def entry(M):
+        info = M.info()
+        ms = time_launches(lambda: M.spmv(x, y), reps, 3)
+        e = {"forward_ms": round(ms, 4), "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
+             "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
+             "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+             "spmv_bytes": info["spmv_bytes"]}
+        if info["has_transpose"]:
+            ms_a = time_launches(lambda: M.adjoint(v, g), reps, 3)
+            e.update({"adjoint_ms": round(ms_a, 4),
+                      "adjoint_GBps": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
+                      "adjoint_frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                      "n_groups_t_x_in_lds": info["n_groups_windowed_t"], "n_groups_t": info["n_groups_t"]})
+        return e
+
+    res["fp16"] = entry(A)
+    v64 = v.double()
+    g64 = torch.empty(spec.n_cols, dtype=torch.float64, device="cuda")
+    ms = time_launches(lambda: A.adjoint(v64, g64), reps, 3)
+    ab = A.info()["adjoint_bytes"] + 4 * (spec.n_rows + spec.n_cols)
+    res["fp16"]["adjoint_f64_ms"] = round(ms, 4)
+    res["fp16"]["adjoint_f64_frac"] = round(ab / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+    A.close()
+    torch.cuda.empty_cache()
+    for fmt in ("bf16", "fp8e4m3_rowscale"):
+        t0 = time.time()
+        M = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose=True)
+        log(f"{spec.name} {fmt}: created in {time.time() - t0:.1f}s")
+        res[fmt] = entry(M)
+        M.close()
+        torch.cuda.empty_cache()
+    for fmt in ("fp16", "bf16", "fp8e4m3_rowscale"):
+        M = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, index_format="u16")
+        res[fmt + "_u16"] = entry(M)
+        M.close()
+        torch.cuda.empty_cache()
+    log(f"{spec.name} variants: " + json.dumps(res))
+    return res
+
+
+def dosegen_signed(spec):
+    import dosegen
+    return dosegen.signed_values(spec.seed, 3, spec.n_rows)
+
+
+def bench_clinical(torch, dm, dosegen, args):
+    """One clinical-scale beam (2,097,152 x 25,000, 4.2e8 entries): the FP32
+    product in the paper's format, its adjoint, one plan-optimisation
+    iteration, 16-bit indices, half/double, Single, and the bias controls."""
+    import numpy as np
+    spec = dosegen.clinical_beam()
+    rp, cols, vals = dosegen.csr(spec)
+    x_h = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", transpose=True)
+    info = A.info()
+    nnz = info["nnz"]
+    x = torch.from_numpy(x_h).cuda()
+    y = torch.empty(spec.n_rows, dtype=torch.float32, device="cuda")
+    ms = time_launches(lambda: A.spmv(x, y), args.steps, args.warmup)
+    res = {"workload": spec.name, "nnz": nnz, "ms": round(ms, 5),
+           "GNNZ_per_s": round(nnz / (ms * 1e-3) / 1e9, 3),
+           "GBps_algorithmic": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
+           "frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+           "x_y_accumulate": "f32", "group_nnz": info["group_nnz"], "n_groups": info["n_groups"],
+           "n_groups_x_in_lds": info["n_groups_windowed"]}
+    log(f"clinical beam FP32: {ms:.4f} ms/step")
+    v = torch.from_numpy(dosegen.signed_values(spec.seed, 1, spec.n_rows)).cuda()
+    g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
+    ms_a = time_launches(lambda: A.adjoint(v, g), args.steps, args.warmup)
+    res["adjoint"] = {"ms": round(ms_a, 5), "GNNZ_per_s": round(nnz / (ms_a * 1e-3) / 1e9, 3),
+                      "GBps_algorithmic": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
+                      "frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                      "group_nnz_t": info["group_nnz_t"], "n_groups_t": info["n_groups_t"],
+                      "n_groups_t_x_in_lds": info["n_groups_windowed_t"],
+                      "n_groups_t_split": info["n_groups_split_t"]}
+    p_h, w_h = dosegen.objective_masks(spec.nx, spec.ny, spec.nz)
+    p, w = torch.from_numpy(p_h).cuda(), torch.from_numpy(w_h).cuda()
+    seed = torch.empty_like(y)
+    fbuf = torch.empty(1, dtype=torch.float64, device="cuda")
+    nbuf = torch.empty(1, dtype=torch.float64, device="cuda")
+
+    def iteration():
+        A.spmv(x, y)
+        dm.objective(y, p, w, seed=seed, out=fbuf)
+        A.adjoint(seed, g)
+        dm.norm2(g, out=nbuf)
+
+    ms_i = time_launches(iteration, max(20, args.steps // 4), args.warmup)
+    res["optimisation_iteration"] = {
+        "ms": round(ms_i, 5), "what": "dose A x, FP64 objective + FP32 seed, adjoint A^T seed, FP64 norm",
+        "GNNZ_per_s_two_products": round(2 * nnz / (ms_i * 1e-3) / 1e9, 3)}
+    A.spmv(x, y)
+    del v, g, seed
+    A.close()
+    res["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
+    res["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
+    res["single_fp32_values"] = bench_single(torch, dm, spec, rp, cols, vals, x, y, args)
+    res["bias_controls"] = bench_bias_controls(torch, dm, dosegen, spec, x, args)
+    return res
 
 
 def main(argv=None):
@@ -165,21 +340,19 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--format", default="fp16", choices=["fp16", "bf16", "fp8e4m3_rowscale", "fp32"])
-    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle CPU work")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle CPU work")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
-    ap.add_argument("--no-variants", action="store_true", help="time the plain product only")
-    ap.add_argument("--batch-scale", type=float, default=0.1,
+    ap.add_argument("--quick", action="store_true", help="time the headline product only")
+    ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="grid-depth scale of the 36-matrix robust batch (1.0 = full size)")
+    ap.add_argument("--scenario-scale", type=float, default=0.1,
+                    help="grid-depth scale of the robust-plan step (1.0 = 128 x 128 x 64 voxels)")
     ap.add_argument("--probe-copy-gib", type=float, default=0.0,
                     help="only run the copy probe over this many GiB (counter calibration)")
     ap.add_argument("--scenario-epilogue", action="store_true",
                     help="only time the robust-plan epilogue on the full 1,048,576-voxel grid")
     ap.add_argument("--robust-step", action="store_true",
                     help="only time the robust-plan step (9 scenarios x 4 beams, then the epilogue)")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also time the largest workload (8,388,608 x 60,000, 1.7e9 entries) in the three "
-                         "value formats, forward and adjoint")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -188,7 +361,6 @@ def main(argv=None):
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import dosegen
@@ -211,89 +383,21 @@ def main(argv=None):
         print(json.dumps({"robust_scenarios": bench_scenarios(torch, dm, dosegen, args)}))
         return
 
-    spec = dosegen.clinical_beam()
-    t0 = time.time()
-    rp, cols, vals = dosegen.csr(spec)
-    log(f"generated {spec.name}: {int(rp[-1])} nnz in {time.time() - t0:.1f}s")
-    x_h = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
-    t0 = time.time()
-    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, args.format, transpose=not args.no_variants)
-    log(f"created matrix ({args.format}) in {time.time() - t0:.1f}s: {A.info()}")
-    x = torch.from_numpy(x_h).cuda()
-    y = torch.empty(spec.n_rows, dtype=torch.float32, device="cuda")
-    info = A.info()
-    nnz = info["nnz"]
-
-    ms = time_launches(lambda: A.spmv(x, y), args.steps, args.warmup)
-    gnnz = nnz / (ms * 1e-3) / 1e9
-    achieved = info["spmv_bytes"] / (ms * 1e-3) / 1e9
-    traffic = measured_traffic(info["spmv_bytes"])
-    log(f"plain: {ms:.4f} ms/step, {gnnz:.1f} GNNZ/s, {achieved:.0f} GB/s algorithmic")
-
-    out = {
-        "metric": METRIC, "value": round(gnnz, 3), "unit": "GNNZ/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (seeded ray-run dose-deposition matrix; the paper's patient matrices are not public)",
-        "config": {"workload": spec.name, "n_rows": spec.n_rows, "n_cols": spec.n_cols, "nnz": nnz,
-                   "empty_row_frac": float(np.mean(np.diff(rp) == 0)),
-                   "value_format": args.format, "index_format": "i32", "accumulate": "f32",
-                   "group_nnz": info["group_nnz"], "n_groups": info["n_groups"],
-                   "n_groups_x_in_lds": info["n_groups_windowed"], "n_groups_split": info["n_groups_split"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic, "algorithmic_bytes_per_launch": info["spmv_bytes"],
-                     "kernel": f"k_spmv<{args.format}> (row groups, x window in LDS)"},
-    }
-
-    med, sd = launch_stats(lambda: A.spmv(x, y), args.steps, 2)
-    out["ms_per_launch_median"] = round(med, 5)
-    out["ms_per_launch_std"] = round(sd, 5)
+    out, spec, A, rp, cols, vals, x_h, y64 = bench_headline(torch, dm, dosegen, args)
+    y_h = y64.cpu().numpy()
     out["hbm_read_ceiling_GBps"] = round(hbm_read_ceiling(torch, dm), 1)
-    out["roofline"]["frac_of_read_ceiling"] = round(achieved / out["hbm_read_ceiling_GBps"], 4)
-
-    if not args.no_variants:
+    out["roofline"]["frac_of_read_ceiling"] = round(out["roofline"]["achieved"] / out["hbm_read_ceiling_GBps"], 4)
+    if not args.quick:
         variants = {}
-        v = torch.from_numpy(dosegen.signed_values(spec.seed, 1, spec.n_rows)).cuda()
-        g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
-        ms_a = time_launches(lambda: A.adjoint(v, g), args.steps, args.warmup)
-        variants["adjoint"] = {"ms": round(ms_a, 5), "GNNZ_per_s": round(nnz / (ms_a * 1e-3) / 1e9, 3),
-                               "GBps_algorithmic": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
-                               "frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                               "group_nnz_t": info["group_nnz_t"], "n_groups_t": info["n_groups_t"],
-                               "n_groups_t_x_in_lds": info["n_groups_windowed_t"],
-                               "n_groups_t_split": info["n_groups_split_t"]}
-        p_h, w_h = dosegen.objective_masks(spec.nx, spec.ny, spec.nz)
-        p, w = torch.from_numpy(p_h).cuda(), torch.from_numpy(w_h).cuda()
-        seed = torch.empty_like(y)
-        fbuf = torch.empty(1, dtype=torch.float64, device="cuda")
-        nbuf = torch.empty(1, dtype=torch.float64, device="cuda")
-
-        def iteration():
-            A.spmv(x, y)
-            dm.objective(y, p, w, seed=seed, out=fbuf)
-            A.adjoint(seed, g)
-            dm.norm2(g, out=nbuf)
-
-        ms_i = time_launches(iteration, max(20, args.steps // 4), args.warmup)
-        variants["optimisation_iteration"] = {
-            "ms": round(ms_i, 5), "what": "dose A x, FP64 objective + FP32 seed, adjoint A^T seed, FP64 norm",
-            "GNNZ_per_s_two_products": round(2 * nnz / (ms_i * 1e-3) / 1e9, 3)}
-        del v, g, seed
-        A.close()  # free the single beam before the batch
-        variants["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
-        variants["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
-        variants["single_fp32_values"] = bench_single(torch, dm, spec, rp, cols, vals, x, y, args)
-        variants["bias_controls"] = bench_bias_controls(torch, dm, dosegen, spec, x, args)
+        variants["same_matrix"] = bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args)
+        variants["clinical_beam"] = bench_clinical(torch, dm, dosegen, args)
         variants["batched"] = bench_batched(torch, dm, dosegen, args)
         variants["robust_scenarios"] = bench_scenarios(torch, dm, dosegen, args)
         variants["small_plain"] = bench_small(torch, dm, dosegen)
-        if args.sweep:
-            variants["sweep_large"] = bench_sweep(torch, dm, dosegen, args)
         out["variants"] = variants
+    else:
+        A.close()
     if not args.no_cpu:
-        # y holds A x: the last write to it (plain loop or iteration) used this x
-        y_h = y.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(spec, rp, cols, vals, x_h, y_h, args.cpu_budget)
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out))
@@ -302,7 +406,7 @@ def main(argv=None):
 def bench_u16(torch, dm, spec, rp, cols, vals, x, y, args):
     """The same product with 16-bit column indices (4 bytes per entry in
     FP16 instead of 6); its result must equal the 32-bit one bit for bit."""
-    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, args.format, index_format="u16")
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", index_format="u16")
     info = A.info()
     y16 = torch.empty_like(y)
     ms = time_launches(lambda: A.spmv(x, y16), args.steps, args.warmup)
@@ -321,15 +425,13 @@ def bench_f64(torch, dm, spec, rp, cols, vals, x_h, args):
     per product: 6 nnz + 4 (n_rows + 1) + 8 n_rows + 8 n_cols (the paper's
     6 nnz + 12 nr + 8 nc)."""
     import numpy as np
-    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, args.format)
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16")
     info = A.info()
     x64 = torch.from_numpy(x_h.astype(np.float64)).cuda()
     y64 = torch.empty(spec.n_rows, dtype=torch.float64, device="cuda")
     ms = time_launches(lambda: A.spmv(x64, y64), args.steps, args.warmup)
     A.close()
-    vb = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1}[args.format]
-    sb = 4 if args.format == "fp8e4m3_rowscale" else 0
-    nbytes = info["nnz"] * (vb + 4) + 4 * (spec.n_rows + 1) + spec.n_rows * sb + 8 * spec.n_cols + 8 * spec.n_rows
+    nbytes = info["nnz"] * 6 + 4 * (spec.n_rows + 1) + 8 * spec.n_cols + 8 * spec.n_rows
     gbps = nbytes / (ms * 1e-3) / 1e9
     log(f"half/double: {ms:.4f} ms/step, {gbps:.0f} GB/s algorithmic")
     return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
@@ -359,7 +461,7 @@ def bench_bias_controls(torch, dm, dosegen, spec, x, args):
     res = {}
     for var in (dosegen.beam_along_x(spec), dosegen.paper_irregular(spec)):
         rp, cols, vals = dosegen.csr(var)
-        A = dm.DoseMatrix(rp, cols, vals, var.n_cols, args.format)
+        A = dm.DoseMatrix(rp, cols, vals, var.n_cols, "fp16")
         info = A.info()
         y = torch.empty(var.n_rows, dtype=torch.float32, device="cuda")
         ms = time_launches(lambda: A.spmv(x, y), args.steps, args.warmup)
@@ -411,14 +513,14 @@ def bench_batched(torch, dm, dosegen, args):
 
 def bench_scenarios(torch, dm, dosegen, args):
     """The robust-plan step: 9 setup-shift scenarios x 4 beams on one shared
-    dose grid (128 x 128 x 64 * batch_scale voxels), the 36 beam doses in one
+    dose grid (128 x 128 x 64 * scenario_scale voxels), the 36 beam doses in one
     autotuned batched graph launch, then the epilogue (scenario doses, seeds,
     FP64 scenario objectives, worst case and expectation).  Reports the step,
     the epilogue alone and its share; epilogue algorithmic bytes are the beam
     doses read once, p and w read once, scenario doses and seeds written once."""
     import numpy as np
     n_scen, n_beams = 9, 4
-    specs = dosegen.robust_scenarios(args.batch_scale, n_scen, n_beams)
+    specs = dosegen.robust_scenarios(args.scenario_scale, n_scen, n_beams)
     n = specs[0].n_rows
     xs = [torch.from_numpy(dosegen.spot_weights(dosegen.SEED0 + 6, b, specs[b].n_cols)).cuda()
           for b in range(n_beams)]
@@ -455,7 +557,7 @@ def bench_scenarios(torch, dm, dosegen, args):
            "epilogue_share": round(ms_epi / ms_step, 4), "scenarios": n_scen, "beams": n_beams,
            "voxels": n, "nnz": nnz_tot, "GNNZ_per_s": round(nnz_tot / (ms_step * 1e-3) / 1e9, 2),
            "epilogue_GBps_algorithmic": round(epi_bytes / (ms_epi * 1e-3) / 1e9, 1),
-           "batch_scale": args.batch_scale}
+           "scenario_scale": args.scenario_scale}
     plan.close()
     for A in mats:
         A.close()
@@ -519,48 +621,6 @@ def bench_small(torch, dm, dosegen):
     return {"workload": spec.name, "nnz": nnz, "launches": 10000, "us_per_product": round(ms * 1e3, 2),
             "GNNZ_per_s": round(nnz / (ms * 1e-3) / 1e9, 2), "us_per_iteration": round(ms_i * 1e3, 2),
             "note": "cache-resident (the matrix is about 5 MB): latency, not an HBM-roofline figure"}
-
-
-def bench_sweep(torch, dm, dosegen, args):
-    """The largest workload in the three value formats: forward and adjoint
-    throughput of the algorithmic bytes."""
-    spec = dosegen.sweep_large()
-    t0 = time.time()
-    rp, cols, vals = dosegen.csr(spec)
-    log(f"generated {spec.name}: {int(rp[-1])} nnz in {time.time() - t0:.1f}s")
-    x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
-    v = torch.from_numpy(dosegen.signed_values(spec.seed, 3, spec.n_rows)).cuda()
-    y = torch.empty(spec.n_rows, dtype=torch.float32, device="cuda")
-    g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
-    res = {"workload": spec.name, "nnz": int(rp[-1])}
-    for fmt in ("fp16", "bf16", "fp8e4m3_rowscale"):
-        t0 = time.time()
-        A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose=True)
-        log(f"sweep {fmt}: created in {time.time() - t0:.1f}s")
-        info = A.info()
-        ms = time_launches(lambda: A.spmv(x, y), max(20, args.steps // 4), 3)
-        ms_a = time_launches(lambda: A.adjoint(v, g), max(20, args.steps // 4), 3)
-        res[fmt] = {"forward_ms": round(ms, 4), "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
-                    "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
-                    "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                    "adjoint_ms": round(ms_a, 4),
-                    "adjoint_GBps": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
-                    "adjoint_frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                    "spmv_bytes": info["spmv_bytes"], "device_bytes": info["device_bytes"]}
-        A.close()
-        torch.cuda.empty_cache()
-        # 16-bit column indices (60,000 spots), forward only
-        A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, index_format="u16")
-        info = A.info()
-        ms = time_launches(lambda: A.spmv(x, y), max(20, args.steps // 4), 3)
-        res[fmt + "_u16"] = {"forward_ms": round(ms, 4),
-                             "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
-                             "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
-                             "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                             "spmv_bytes": info["spmv_bytes"]}
-        A.close()
-        torch.cuda.empty_cache()
-    return res
 
 
 if __name__ == "__main__":

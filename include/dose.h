@@ -140,7 +140,10 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf,
  * group_nnz entries (a power of two, 1024 .. 2^20; a longer row is a group of
  * its own).  A group is the work of one workgroup.  The partition changes
  * speed only: every row is summed in an order fixed by its own entries, so
- * products are bitwise identical under any partition.  Synchronous. */
+ * products are bitwise identical under any partition.  Synchronous: waits
+ * for the device first.  The one call that changes a matrix after creation:
+ * it must not overlap products on the same matrix issued from other threads.
+ * Batch plans keep copies of the partition they were built with. */
 dose_status dose_matrix_set_partition(dose_matrix m, int32_t group_nnz, int32_t group_nnz_t);
 
 /* Copy rows [row_begin, row_end) of the stored operand `part` (DOSE_PART_A or
@@ -199,17 +202,33 @@ typedef struct {
   int64_t ldy;
 } dose_batch_item;
 
-/* All items in one persistent launch (robust optimisation needs the dose of
- * many scenarios and beams every iteration, Sec. I, II-A).  Each y is bitwise
- * what dose_spmv gives per vector (rows are summed in the same order).  Items must not
- * share outputs. */
+/* All items in one launch (robust optimisation needs the dose of many
+ * scenarios and beams every iteration, Sec. I, II-A: one matrix per beam and
+ * scenario, Sec. II-B).  Each y is bitwise what dose_spmv gives per vector
+ * (rows are summed in the same order).  Items must not share outputs; x and y
+ * of an item must not overlap and must be aligned to n_rhs floats; all items
+ * share one value format, one index format and one n_rhs, and live on one
+ * device (else DOSE_ERR_UNSUPPORTED or DOSE_ERR_INVALID_ARGUMENT).
+ * Asynchronous on hip_stream: the items' arguments travel to the device
+ * through a library-owned pinned ring of 16 slots (kept until the process
+ * ends), so the call returns once the launch is queued; it waits only when
+ * the launch that used the same slot 16 calls earlier has not finished.  At
+ * most 2,048 items per call (DOSE_ERR_UNSUPPORTED beyond; a batch plan takes
+ * any number).  Not for HIP graph capture: capture a batch plan instead. */
 dose_status dose_spmv_batched(const dose_batch_item* items, int32_t n_items, void* hip_stream);
 
-/* Plans: the work list of a batch is built once on the device and the launch
- * is captured into a HIP graph that dose_batch_plan_launch replays.  With
- * DOSE_PLAN_AUTOTUNE each distinct matrix is first re-partitioned to the
- * fastest block size found by timing candidates on `hip_stream` (x/y of the
- * items are used as scratch for the timing runs). */
+/* Plans (the same batched product, repeated every optimisation iteration,
+ * Sec. I, II-A): the work list of a batch is built once on the device and the
+ * launch is captured into a HIP graph that dose_batch_plan_launch replays on
+ * hip_stream (asynchronous).  The plan keeps the items' pointers: their x and
+ * y must stay valid while the plan is used.  With DOSE_PLAN_AUTOTUNE each
+ * distinct matrix is timed under candidate row-group sizes on `hip_stream`
+ * (x/y of the items are used as scratch for the timing runs; the choice
+ * persists in the text file named by DOSE_TUNE_CACHE, if set) and the plan
+ * keeps its own copy of the fastest partition: the matrix is not changed, so
+ * products on other streams may use it meanwhile, as for any product.  The
+ * paper sweeps its thread-block size for the same reason (Sec. V-A); the
+ * partition changes speed only, never the result.  create is synchronous. */
 enum { DOSE_PLAN_AUTOTUNE = 1u };
 dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items, uint32_t flags,
                                    void* hip_stream, dose_batch_plan* out);
@@ -218,8 +237,13 @@ dose_status dose_batch_plan_destroy(dose_batch_plan p);
 
 /* Quadratic plan objective f = sum_v w_v (d_v - p_v)^2, accumulated in FP64
  * with a fixed-order two-pass reduction, and the adjoint seed
- * seed_v = 2 w_v (d_v - p_v) in FP32 (may be NULL).
- * d, p, w: device, n FP32.  f_out: device, one double.  Asynchronous. */
+ * seed_v = 2 w_v (d_v - p_v) in FP32 (may be NULL).  Plan optimisation
+ * evaluates the objective and its gradient from the dose every iteration
+ * (Sec. I); the paper fixes no objective, so this is the usual quadratic
+ * penalty of the dose against a prescription p with voxel weights w.
+ * d, p, w: device, n FP32.  f_out: device, one double.  Asynchronous on
+ * hip_stream; a partial-sum buffer of at most 8 KB is taken from the
+ * stream-ordered allocator and returned in stream order. */
 dose_status dose_objective(int64_t n, const float* d, const float* p, const float* w,
                            float* seed, double* f_out, void* hip_stream);
 
@@ -246,9 +270,31 @@ dose_status dose_scenario_objective(int32_t n_scen, int32_t n_beams, int64_t n, 
                                     const float* p, const float* w, const double* prob, float* d_out,
                                     float* seed, double* out, void* hip_stream);
 
-/* out = sqrt(sum_j g_j^2) in FP64, fixed-order two-pass reduction.
- * g: device, n FP32.  out: device, one double.  Asynchronous. */
+/* out = sqrt(sum_j g_j^2) in FP64, fixed-order two-pass reduction: the size
+ * of the gradient an optimiser needs every iteration (Sec. I).
+ * g: device, n FP32.  out: device, one double.  Asynchronous on hip_stream
+ * (partial sums as for dose_objective). */
 dose_status dose_norm2(int64_t n, const float* g, double* out, void* hip_stream);
+
+/* Seeds of the robust objective's gradient (Sec. I, II-A: the gradient of the
+ * robust plan objective every iteration).  The derivative of the expectation
+ * with respect to scenario s's dose is prob_s (1/n_scen when prob is NULL)
+ * times the scenario's seed; that of the worst case is the seed of the first
+ * worst scenario (its index in out[n_scen + 2], as dose_scenario_objective
+ * writes it) and 0 for the others.  So
+ *   wseed[s][v] = fl32(c_s * g * seed[s][v]),  formed in FP64, rounded once,
+ * with g = *grad_scale (an outer derivative; 1 when grad_scale is NULL).
+ * Every beam b of scenario s then has gradient seed wseed[s] (its adjoint
+ * gives that beam's spot-weight gradient under scenario s).
+ * mode: DOSE_ROBUST_EXPECTED or DOSE_ROBUST_WORST.  out: device, n_scen + 3
+ * doubles (needed for the worst case, else may be NULL).  prob: device,
+ * n_scen doubles or NULL.  seed, wseed: device FP32 [n_scen][n]; wseed may be
+ * seed itself, else must not overlap it or the other inputs.  Float arrays
+ * 4-byte, double arrays 8-byte aligned; 1 <= n_scen <= 65536.  Errors:
+ * DOSE_ERR_INVALID_ARGUMENT.  Asynchronous on hip_stream. */
+enum { DOSE_ROBUST_EXPECTED = 0, DOSE_ROBUST_WORST = 1 };
+dose_status dose_robust_seed(int32_t n_scen, int64_t n, int32_t mode, const double* out, const double* prob,
+                             const double* grad_scale, const float* seed, float* wseed, void* hip_stream);
 
 /* Measurement kernels (not part of the dose path): read `bytes` of device
  * memory with 16-byte loads and write one float per workgroup to `sink`

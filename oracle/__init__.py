@@ -28,7 +28,7 @@ FORMATS = {"fp16": 1, "bf16": 2, "fp8e4m3_rowscale": 3, "fp32": 4}
 def build() -> str:
     """Compile liboracle.so with gcc, keeping every rounding as written."""
     tmp = _LIB_PATH + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC",
+    subprocess.check_call(["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
                            "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -64,6 +64,8 @@ def load_library(path: str):
         "or_decode_matrix": ([ctypes.c_int, i64, vp, vp, vp, vp], ctypes.c_int),
         "or_row_dot": ([i64, vp, vp, vp], ctypes.c_double),
         "or_spmv": ([i64, vp, vp, vp, vp, vp], None),
+        "or_spmv_rows_parallel": ([i64, vp, vp, vp, vp, vp], None),
+        "or_num_threads": ([], ctypes.c_int),
         "or_spmv_multi": ([i64, i32, vp, vp, vp, vp, vp], None),
         "or_spmv_T": ([i64, i64, vp, vp, vp, vp, vp], None),
         "or_transpose": ([i64, i64, vp, vp, vp, vp, vp, vp], None),
@@ -72,6 +74,7 @@ def load_library(path: str):
         "or_norm2": ([i64, vp], ctypes.c_double),
         "or_beam_sum": ([i32, i64, vp, vp], None),
         "or_robust": ([i32, vp, vp, vp, vp, vp], None),
+        "or_robust_weights": ([i32, vp, vp, i32, vp], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -161,6 +164,22 @@ def spmv(row_ptr, cols, dec, x) -> np.ndarray:
     return y[:rp.size - 1]
 
 
+def spmv_parallel(row_ptr, cols, dec, x) -> np.ndarray:
+    """spmv with the rows shared among the host's threads (same sums)."""
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    xx, px = _c(x, np.float32)
+    y = np.empty(max(rp.size - 1, 1), np.float64)
+    _load().or_spmv_rows_parallel(rp.size - 1, prp, pc, pd, px, y.ctypes.data)
+    return y[:rp.size - 1]
+
+
+def num_threads() -> int:
+    """Threads spmv_parallel uses."""
+    return int(_load().or_num_threads())
+
+
 def spmv_multi(row_ptr, cols, dec, x2d) -> np.ndarray:
     """x2d is [n_cols][n_rhs]; returns [n_rows][n_rhs] in FP64."""
     rp, prp = _c(row_ptr, np.int64)
@@ -236,6 +255,24 @@ def robust(f, prob=None) -> tuple[float, int, float]:
     _load().or_robust(ff.size, ff.ctypes.data, None if pp is None else pp.ctypes.data,
                       ctypes.byref(worst), ctypes.byref(arg), ctypes.byref(expected))
     return worst.value, arg.value, expected.value
+
+
+def robust_weights(f, prob=None, mode: str = "expected") -> np.ndarray:
+    """Weights c_s of the robust forms: the derivative of the expectation
+    (mode "expected") or of the worst case (mode "worst") with respect to
+    each scenario's objective f_s."""
+    ff = np.ascontiguousarray(np.asarray(f, np.float64))
+    if ff.size < 1:
+        raise ValueError("at least one scenario")
+    if mode not in ("expected", "worst"):
+        raise ValueError(mode)
+    pp = None if prob is None else np.ascontiguousarray(np.asarray(prob, np.float64))
+    if pp is not None and pp.size != ff.size:
+        raise ValueError("one probability per scenario")
+    c = np.empty(ff.size, np.float64)
+    _load().or_robust_weights(ff.size, ff.ctypes.data, None if pp is None else pp.ctypes.data,
+                              1 if mode == "worst" else 0, c.ctypes.data)
+    return c
 
 
 def norm2(g) -> float:

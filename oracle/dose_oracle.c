@@ -34,12 +34,19 @@
  *     needed every iteration).  Each beam has its own deposition matrix over
  *     the shared dose grid, so the dose of one scenario is the sum of its
  *     beams' doses.  Over the scenarios' objectives f_s the robust forms are
- *     the worst case max_s f_s and the expectation sum_s pi_s f_s.
+ *     the worst case max_s f_s and the expectation sum_s pi_s f_s.  Their
+ *     derivatives with respect to scenario s's objective are the weights c_s:
+ *     pi_s (1/S without probabilities) for the expectation; for the worst
+ *     case 1 for the first scenario attaining the maximum and 0 otherwise.
+ *     The gradient seed of scenario s's dose is c_s times its own seed.
  *
  * Built with -O2 -fno-fast-math -ffp-contract=off so that the compiler keeps
  * every rounding as written.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <string.h>
 
@@ -237,6 +244,25 @@ void or_spmv(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const f
     y[i] = or_row_dot(row_ptr[i + 1] - row_ptr[i], col + row_ptr[i], dec + row_ptr[i], x);
 }
 
+/* The same product with the rows shared among threads (OpenMP; rows are
+ * independent, so every y[i] is the same sum as in or_spmv).  Used to time
+ * the oracle on all host cores; without OpenMP it is or_spmv. */
+void or_spmv_rows_parallel(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const float* dec,
+                           const float* x, double* y) {
+#pragma omp parallel for schedule(dynamic, 4096)
+  for (int64_t i = 0; i < n_rows; ++i)
+    y[i] = or_row_dot(row_ptr[i + 1] - row_ptr[i], col + row_ptr[i], dec + row_ptr[i], x);
+}
+
+/* Threads or_spmv_rows_parallel uses (1 without OpenMP). */
+int or_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* Same product for a multi-vector x stored [n_cols][n_rhs] -> y [n_rows][n_rhs]. */
 void or_spmv_multi(int64_t n_rows, int32_t n_rhs, const int64_t* row_ptr, const int32_t* col,
                    const float* dec, const float* x, double* y) {
@@ -330,4 +356,18 @@ void or_robust(int32_t n_scen, const double* f, const double* prob, double* wors
   *worst = w;
   *arg = a;
   *expected = e;
+}
+
+/* Weights c_s of the robust forms (their derivatives with respect to f_s):
+ * worst != 0: 1 for the first s attaining max f_s, else 0; worst == 0:
+ * prob[s], or 1/n_scen without probabilities. */
+void or_robust_weights(int32_t n_scen, const double* f, const double* prob, int32_t worst, double* c) {
+  if (worst) {
+    int32_t a = 0;
+    for (int32_t s = 1; s < n_scen; ++s)
+      if (f[s] > f[a]) a = s;
+    for (int32_t s = 0; s < n_scen; ++s) c[s] = s == a ? 1.0 : 0.0;
+  } else {
+    for (int32_t s = 0; s < n_scen; ++s) c[s] = prob ? prob[s] : 1.0 / (double)n_scen;
+  }
 }

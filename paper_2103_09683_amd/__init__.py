@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import DoseError
 
 __all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
-           "ScenarioObjective",
+           "ScenarioObjective", "robust_seed",
            "csr_validate", "partition_preview", "byte_model", "DoseSpMV", "DoseObjective",
            "dose", "VALUE_FORMATS"]
 
@@ -196,11 +196,21 @@ class DoseMatrix:
 
 
 def _items(entries):
+    """Batch items of (DoseMatrix, x, y) triples: x is (n_cols,) or
+    (n_cols, n_rhs) and y (n_rows,) or (n_rows, n_rhs), both contiguous FP32
+    on the matrix's device (the kernels read x as [n_cols][n_rhs])."""
     arr = (_lib.BatchItem * len(entries))()
     for i, (A, x, y) in enumerate(entries):
+        for name, t in (("x", x), ("y", y)):
+            if not isinstance(t, torch.Tensor) or t.dim() not in (1, 2):
+                raise TypeError(f"item {i}: {name} must be a 1- or 2-dimensional tensor")
         n_rhs = 1 if x.dim() == 1 else x.shape[1]
-        _dev_ptr(x.reshape(-1), A.n_cols * n_rhs, "x", A.device)
-        _dev_ptr(y.reshape(-1), A.n_rows * n_rhs, "y", A.device)
+        if x.shape != ((A.n_cols,) if x.dim() == 1 else (A.n_cols, n_rhs)):
+            raise ValueError(f"item {i}: x has shape {tuple(x.shape)}, expected ({A.n_cols}[, n_rhs])")
+        if y.shape != ((A.n_rows,) if x.dim() == 1 else (A.n_rows, n_rhs)):
+            raise ValueError(f"item {i}: y has shape {tuple(y.shape)}, expected the rows of x's layout")
+        _dev_ptr(x, A.n_cols * n_rhs, "x", A.device)
+        _dev_ptr(y, A.n_rows * n_rhs, "y", A.device)
         arr[i] = _lib.BatchItem(A.handle, n_rhs, 0, x.data_ptr(), n_rhs, y.data_ptr(), n_rhs)
     return arr
 
@@ -278,6 +288,30 @@ def scenario_objective(part: torch.Tensor, p, w, prob: torch.Tensor | None = Non
     return out
 
 
+def robust_seed(seed: torch.Tensor, mode: str = "expected", out: torch.Tensor | None = None,
+                prob: torch.Tensor | None = None, grad_scale: torch.Tensor | None = None,
+                wseed: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Seeds of the robust objective's gradient, (n_scen, n) FP32: scenario s's
+    seed times c_s g, with c_s = prob_s (uniform without ``prob``) for mode
+    "expected", or 1 for the first worst scenario (index read from ``out`` of
+    :func:`scenario_objective`) and 0 for the others for mode "worst"; g is
+    the one-element FP64 tensor ``grad_scale`` (1 without it)."""
+    if mode not in ("expected", "worst"):
+        raise ValueError("mode is 'expected' or 'worst'")
+    if seed.dim() != 2:
+        raise ValueError("seed must be (n_scen, n)")
+    n_scen, n = seed.shape
+    if wseed is None:
+        wseed = torch.empty_like(seed)
+    _lib.check(_lib.load().dose_robust_seed(
+        n_scen, n, _lib.ROBUST_WORST if mode == "worst" else _lib.ROBUST_EXPECTED,
+        _dev_ptr(out, n_scen + 3, "out", dtype=torch.float64) if out is not None else None,
+        _dev_ptr(prob, n_scen, "prob", dtype=torch.float64) if prob is not None else None,
+        _dev_ptr(grad_scale, 1, "grad_scale", dtype=torch.float64) if grad_scale is not None else None,
+        _dev_ptr(seed, n_scen * n, "seed"), _dev_ptr(wseed, n_scen * n, "wseed"), _stream_handle(stream)))
+    return wseed
+
+
 def norm2(g: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """sqrt(sum g^2) in FP64 on the device."""
     if out is None:
@@ -299,16 +333,20 @@ def probe_copy(src: torch.Tensor, dst: torch.Tensor, stream=None) -> None:
 
 
 class DoseSpMV(torch.autograd.Function):
-    """d = A x with dL/dx = A^T dL/dd (the matrix needs transpose=True for backward)."""
+    """d = A x with dL/dx = A^T dL/dd (the matrix needs transpose=True for
+    backward).  FP32 x runs the FP32 products; FP64 x the FP64 ones (the
+    paper's half/double configuration), forward and backward."""
 
     @staticmethod
     def forward(ctx, x, A):
         ctx.A = A
+        ctx.f64 = x.dtype == torch.float64
         return A.spmv(x.contiguous())
 
     @staticmethod
     def backward(ctx, gd):
-        return ctx.A.adjoint(gd.contiguous().float()), None
+        gd = gd.contiguous().to(torch.float64 if ctx.f64 else torch.float32)
+        return ctx.A.adjoint(gd), None
 
 
 class DoseObjective(torch.autograd.Function):
@@ -324,7 +362,9 @@ class DoseObjective(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gf):
         (seed,) = ctx.saved_tensors
-        return seed * gf.float(), None, None
+        # one scenario's expectation: the seed times the outer derivative
+        g = robust_seed(seed.view(1, -1), "expected", grad_scale=gf.to(torch.float64).reshape(1).contiguous())
+        return g.view(-1), None, None
 
 
 class ScenarioObjective(torch.autograd.Function):
@@ -333,7 +373,7 @@ class ScenarioObjective(torch.autograd.Function):
     the worst case max_s f_s (mode "worst"), f_s = sum w (d_s - p)^2 with d_s
     the scenario's beam sum.  d/dpart[s, b] = c_s 2 w (d_s - p) for every beam
     b, with c_s = prob_s (expected) or 1 for the first worst scenario and 0
-    otherwise (worst)."""
+    otherwise (worst); the library forms these seeds (dose_robust_seed)."""
 
     @staticmethod
     def forward(ctx, part, p, w, prob=None, mode: str = "expected"):
@@ -342,23 +382,18 @@ class ScenarioObjective(torch.autograd.Function):
         part = part.contiguous()
         n_scen, n_beams, n = part.shape
         seed = torch.empty(n_scen, n, dtype=torch.float32, device=part.device)
-        out = scenario_objective(part, p.contiguous(), w.contiguous(),
-                                 prob=None if prob is None else prob.contiguous(), seed=seed)
-        if mode == "expected":
-            c = prob if prob is not None else torch.full((n_scen,), 1.0 / n_scen, dtype=torch.float64,
-                                                         device=part.device)
-            f = out[n_scen + 1]
-        else:
-            c = (torch.arange(n_scen, device=part.device) == out[n_scen + 2].long()).to(torch.float64)
-            f = out[n_scen]
-        ctx.save_for_backward(seed, c)
+        prob = None if prob is None else prob.contiguous()
+        out = scenario_objective(part, p.contiguous(), w.contiguous(), prob=prob, seed=seed)
+        ctx.save_for_backward(seed, out, prob)
         ctx.n_beams = n_beams
-        return f.reshape(())
+        ctx.mode = mode
+        return out[n_scen + 1] if mode == "expected" else out[n_scen]
 
     @staticmethod
     def backward(ctx, gf):
-        seed, c = ctx.saved_tensors
-        g = seed * (c * gf.double()).float()[:, None]
+        seed, out, prob = ctx.saved_tensors
+        g = robust_seed(seed, ctx.mode, out=out, prob=prob,
+                        grad_scale=gf.to(torch.float64).reshape(1).contiguous())
         return g[:, None, :].expand(-1, ctx.n_beams, -1), None, None, None, None
 
 

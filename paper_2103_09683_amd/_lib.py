@@ -27,6 +27,7 @@ IDX_U16 = 2
 CREATE_TRANSPOSE = 1
 PART_A, PART_AT = 0, 1
 PLAN_AUTOTUNE = 1
+ROBUST_EXPECTED, ROBUST_WORST = 0, 1
 
 
 class CsrHost(ctypes.Structure):
@@ -73,6 +74,7 @@ SIGNATURES = {
     "dose_batch_plan_destroy": ([_vp], _i32),
     "dose_objective": ([_i64, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_norm2": ([_i64, _vp, _vp, _vp], _i32),
+    "dose_robust_seed": ([_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_scenario_objective": ([_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_probe_stream_read": ([_vp, _u64, _vp, _vp], _i32),
     "dose_probe_copy": ([_vp, _vp, _u64, _vp], _i32),

@@ -274,18 +274,25 @@ std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int gr
 }
 
 // ------------------------------------------------------------- operands
+// A row-group partition of one operand: the device descriptors of its groups
+// (with their x windows), a host copy (batched plans copy it into their work
+// lists) and what the launch needs to know about it.
+struct Partition {
+  DevBuf groups;
+  std::vector<GroupDesc> h_groups;
+  int32_t group_nnz = 0;
+  int64_t n_groups = 0, n_windowed = 0, n_split = 0;
+  int32_t win_floats[3] = {0, 0, 0};  // LDS window size for 1, 2 and 4 vectors
+};
+
 struct Operand {
   int64_t n_rows = 0, n_cols = 0, nnz = 0;
   std::vector<int64_t> h_row_ptr;
   DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
   int idx_bytes = 4;         // column index width: 4 (int32) or 2 (uint16)
-  DevBuf groups;
-  std::vector<GroupDesc> h_groups;  // host copy (batched plans copy it into their work lists)
-  int32_t group_nnz = 0;
-  int64_t n_groups = 0, n_windowed = 0, n_split = 0;
-  int32_t win_floats[3] = {0, 0, 0};  // LDS window size for 1, 2 and 4 vectors
+  Partition part;            // the partition plain products use
 
-  uint64_t bytes() const { return val.bytes() + col.bytes() + row_ptr.bytes() + groups.bytes(); }
+  uint64_t bytes() const { return val.bytes() + col.bytes() + row_ptr.bytes() + part.groups.bytes(); }
 };
 
 int rhs_slot(int n_rhs) { return n_rhs == 1 ? 0 : n_rhs == 2 ? 1 : 2; }
@@ -305,14 +312,17 @@ int64_t window_cap_floats() {
   return cap;
 }
 
-void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
+// The partition of an operand into groups of about group_nnz entries, with
+// every group's x window computed on the device.  Synchronous on s.
+Partition make_partition(const Operand& op, int group_nnz, hipStream_t s) {
   std::vector<GroupDesc> G = build_partition(op.h_row_ptr.data(), op.n_rows, group_nnz);
-  DevBuf groups(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
+  Partition P;
+  P.groups = DevBuf(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
   if (!G.empty()) {
-    HIP_CHECK(hipMemcpyAsync(groups.get(), G.data(), G.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
-    HIP_CHECK(launch_group_windows(groups.get<GroupDesc>(), static_cast<int64_t>(G.size()), op.col.get(), op.idx_bytes,
-                                   op.row_ptr.get<uint32_t>(), s));
-    HIP_CHECK(hipMemcpyAsync(G.data(), groups.get(), G.size() * sizeof(GroupDesc), hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(P.groups.get(), G.data(), G.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_group_windows(P.groups.get<GroupDesc>(), static_cast<int64_t>(G.size()), op.col.get(),
+                                   op.idx_bytes, op.row_ptr.get<uint32_t>(), s));
+    HIP_CHECK(hipMemcpyAsync(G.data(), P.groups.get(), G.size() * sizeof(GroupDesc), hipMemcpyDeviceToHost, s));
   }
   HIP_CHECK(hipStreamSynchronize(s));
   // LDS per workgroup: the largest window within the cap; groups with larger
@@ -332,14 +342,16 @@ void upload_partition(Operand& op, int group_nnz, hipStream_t s) {
       if (f <= std::min<int64_t>(cap * rhs[i], kWinFloatsMax)) wf[i] = std::max(wf[i], f);
     }
   }
-  op.groups = std::move(groups);
-  op.group_nnz = group_nnz;
-  op.n_groups = static_cast<int64_t>(G.size());
-  op.h_groups = G;
-  op.n_windowed = windowed;
-  op.n_split = split;
-  for (int i = 0; i < 3; ++i) op.win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);
+  P.group_nnz = group_nnz;
+  P.n_groups = static_cast<int64_t>(G.size());
+  P.h_groups = std::move(G);
+  P.n_windowed = windowed;
+  P.n_split = split;
+  for (int i = 0; i < 3; ++i) P.win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);
+  return P;
 }
+
+void upload_partition(Operand& op, int group_nnz, hipStream_t s) { op.part = make_partition(op, group_nnz, s); }
 
 void upload_row_ptr32(Operand& op, hipStream_t s) {
   std::vector<uint32_t> rp32(op.h_row_ptr.size());
@@ -367,11 +379,24 @@ namespace {
 int scale_mode_A(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleRow : kScaleNone; }
 int scale_mode_AT(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleCol : kScaleNone; }
 
+// Dies of the chip that workgroups are dealt to in turn (DOSE_XCD_BLOCKS,
+// default 8 for the MI355X's eight XCDs; 1 turns the regrouping off).  Only
+// the order in which groups are dispatched depends on it, never a result.
+int xcd_blocks() {
+  static const int d = [] {
+    const char* e = std::getenv("DOSE_XCD_BLOCKS");
+    const int v = e ? std::atoi(e) : 8;
+    return std::max(1, std::min(64, v));
+  }();
+  return d;
+}
+
 // n_rhs sizes the LDS window (an FP64 vector takes the window of two FP32 ones).
-SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const void* x, void* y) {
+SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, const Partition& P, int sm, int n_rhs, const void* x,
+                   void* y) {
   SpmvArgs a{};
-  a.win_floats = op.win_floats[rhs_slot(n_rhs)];
-  a.groups = op.groups.get<GroupDesc>();
+  a.win_floats = P.win_floats[rhs_slot(n_rhs)];
+  a.groups = P.groups.get<GroupDesc>();
   a.val = op.val.get();
   a.col = op.col.get();
   a.idx_bytes = op.idx_bytes;
@@ -379,8 +404,12 @@ SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs,
   a.scale = sm == kScaleNone ? nullptr : m->row_scale.get<float>();
   a.x = x;
   a.y = y;
-  a.n_groups = op.n_groups;
+  a.n_groups = P.n_groups;
+  a.xcd_blocks = xcd_blocks();
   return a;
+}
+SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const void* x, void* y) {
+  return make_args(m, op, op.part, sm, n_rhs, x, y);
 }
 
 // Encode A's FP32 source values into its code stream, a row range at a time.
@@ -532,6 +561,7 @@ struct dose_batch_plan_s {
   int vf = 0, sm = 0, n_rhs = 0, lds_floats = 0, idx_bytes = 4;
   int64_t n_work = 0;
   DevBuf args, work;  // per-item arguments; the groups of all items
+  std::vector<std::unique_ptr<Partition>> parts;  // autotuned partitions the work list was built from
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~dose_batch_plan_s() {
@@ -564,9 +594,10 @@ void check_items(const dose_batch_item* items, int32_t n_items) {
   }
 }
 
-// Median time of the plain product of one operand under its current partition.
-double time_partition(dose_matrix_s* m, Operand& op, int sm, int n_rhs, const float* x, float* y, hipStream_t s) {
-  const SpmvArgs a = make_args(m, op, sm, n_rhs, x, y);
+// Median time of the plain product of one operand under partition P.
+double time_partition(dose_matrix_s* m, const Operand& op, const Partition& P, int sm, int n_rhs, const float* x,
+                      float* y, hipStream_t s) {
+  const SpmvArgs a = make_args(m, op, P, sm, n_rhs, x, y);
   hipEvent_t e0, e1;
   HIP_CHECK(hipEventCreate(&e0));
   HIP_CHECK(hipEventCreate(&e1));
@@ -586,22 +617,29 @@ double time_partition(dose_matrix_s* m, Operand& op, int sm, int n_rhs, const fl
   return ts[ts.size() / 2];
 }
 
-// Pick the row-group size by timing candidates (the result does not depend on
-// it: every row is summed in the same order under any partition).
-void autotune_matrix(dose_matrix_s* m, int n_rhs, const float* x, float* y, hipStream_t s) {
-  Operand& op = m->A;
+// The fastest row-group size for a matrix's products with n_rhs vectors,
+// found by timing candidate partitions built for this purpose (the result
+// does not depend on the partition: every row is summed in the same order
+// under any of them).  The matrix itself is left as it is, so products on
+// other streams may use it meanwhile.  Returns the chosen partition, or null
+// when the matrix's own partition already has the chosen size.
+std::unique_ptr<Partition> autotune_matrix(dose_matrix_s* m, int n_rhs, const float* x, float* y, hipStream_t s) {
+  const Operand& op = m->A;
   const std::string key = tune_key(m, op, n_rhs);
   int best = tune_lookup(key);
+  std::unique_ptr<Partition> best_p;
   if (best == 0) {
     double best_t = 1e30;
     for (int g = 8192; g <= 65536; g *= 2) {
-      upload_partition(op, g, s);
-      const double t = time_partition(m, op, scale_mode_A(m), n_rhs, x, y, s);
-      if (t < best_t) best_t = t, best = g;
+      auto P = std::make_unique<Partition>(make_partition(op, g, s));
+      const double t = time_partition(m, op, *P, scale_mode_A(m), n_rhs, x, y, s);
+      if (t < best_t) best_t = t, best = g, best_p = std::move(P);
     }
     tune_store(key, best);
   }
-  if (op.group_nnz != best) upload_partition(op, best, s);
+  if (op.part.group_nnz == best) return nullptr;
+  if (!best_p) best_p = std::make_unique<Partition>(make_partition(op, best, s));
+  return best_p;
 }
 
 dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uint32_t flags, hipStream_t s) {
@@ -613,18 +651,29 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
   plan->sm = scale_mode_A(m0);
   plan->n_rhs = items[0].n_rhs;
   plan->idx_bytes = m0->A.idx_bytes;
-  if (flags & DOSE_PLAN_AUTOTUNE) {
-    std::map<dose_matrix_s*, int> seen;
-    for (int32_t i = 0; i < n_items; ++i)
-      if (seen.emplace(items[i].A, i).second) autotune_matrix(items[i].A, items[i].n_rhs, items[i].x, items[i].y, s);
+  // the partition each distinct matrix runs under in this plan
+  std::map<const dose_matrix_s*, const Partition*> part_of;
+  for (int32_t i = 0; i < n_items; ++i) {
+    dose_matrix_s* m = items[i].A;
+    if (part_of.count(m)) continue;
+    const Partition* P = &m->A.part;
+    if (flags & DOSE_PLAN_AUTOTUNE) {
+      std::unique_ptr<Partition> tuned = autotune_matrix(m, items[i].n_rhs, items[i].x, items[i].y, s);
+      if (tuned) {
+        P = tuned.get();
+        plan->parts.push_back(std::move(tuned));
+      }
+    }
+    part_of[m] = P;
   }
   std::vector<SpmvArgs> args(n_items);
   std::vector<GroupDesc> work;
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_matrix_s* m = items[i].A;
-    args[i] = make_args(m, m->A, plan->sm, plan->n_rhs, items[i].x, items[i].y);
+    const Partition& P = *part_of[m];
+    args[i] = make_args(m, m->A, P, plan->sm, plan->n_rhs, items[i].x, items[i].y);
     plan->lds_floats = std::max(plan->lds_floats, args[i].win_floats);
-    for (GroupDesc g : m->A.h_groups) {
+    for (GroupDesc g : P.h_groups) {
       g.item = static_cast<uint32_t>(i);
       work.push_back(g);
     }
@@ -633,15 +682,107 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
   if (plan->n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
   plan->args = DevBuf(args.size() * sizeof(SpmvArgs));
   plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
-  HIP_CHECK(hipMemcpy(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice));
+  HIP_CHECK(hipMemcpyAsync(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
   if (!work.empty())
-    HIP_CHECK(hipMemcpy(plan->work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpyAsync(plan->work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipStreamSynchronize(s));
   return plan.release();
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
-  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, p->args.get<SpmvArgs>(), p->work.get<GroupDesc>(),
-                                p->n_work, p->lds_floats, s));
+  BatchTable t{};
+  t.args = p->args.get<SpmvArgs>();
+  t.work = p->work.get<GroupDesc>();
+  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, p->n_work, p->lds_floats, s));
+}
+
+// ------------------------------------------------- item tables of batched calls
+// dose_spmv_batched hands its items' arguments to the kernel through a table
+// in device memory: the first workgroup of every item (n_items + 1 ascending
+// entries, the last one the total) followed by the items' SpmvArgs, each
+// naming the matrix's own row groups.  The table is written into a slot of a
+// pinned host ring and copied to the same slot of a device ring on the
+// caller's stream, so the call returns without waiting for the GPU; an event
+// recorded after the launch keeps a slot from being reused before its launch
+// has finished.  One ring per device, kept until the process ends.
+constexpr int kRingSlots = 16;
+constexpr size_t kRingSlotBytes = size_t{256} << 10;
+constexpr int32_t kMaxCallItems = 2048;
+static_assert((kMaxCallItems + 1) * sizeof(uint32_t) + 16 + kMaxCallItems * sizeof(SpmvArgs) <= kRingSlotBytes,
+              "a slot holds the table of the largest call");
+
+struct ItemRing {
+  std::mutex mu;
+  char* host = nullptr;  // pinned
+  char* dev = nullptr;
+  hipEvent_t done[kRingSlots] = {};
+  uint64_t next = 0;
+};
+
+std::mutex g_ring_mu;
+std::map<int, std::unique_ptr<ItemRing>> g_rings;
+
+ItemRing& ring_for(int device) {
+  std::lock_guard<std::mutex> lk(g_ring_mu);
+  auto& r = g_rings[device];
+  if (!r) {
+    auto nr = std::make_unique<ItemRing>();
+    const size_t bytes = kRingSlots * kRingSlotBytes;
+    if (hipHostMalloc(reinterpret_cast<void**>(&nr->host), bytes, hipHostMallocDefault) != hipSuccess)
+      fail(DOSE_ERR_OUT_OF_MEMORY, "pinned item ring");
+    try {
+      nr->dev = static_cast<char*>(dev_alloc(bytes));
+      for (auto& e : nr->done) HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    } catch (...) {
+      (void)hipHostFree(nr->host);
+      if (nr->dev) (void)hipFree(nr->dev);
+      throw;
+    }
+    r = std::move(nr);
+  }
+  return *r;
+}
+
+void launch_items(const dose_batch_item* items, int32_t n_items, hipStream_t s) {
+  if (n_items > kMaxCallItems)
+    fail(DOSE_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxCallItems) + " items in one call (use a batch plan)");
+  const dose_matrix_s* m0 = items[0].A;
+  const int sm = scale_mode_A(m0), n_rhs = items[0].n_rhs;
+  // table layout: first[n_items + 1] (u32), padded to 16 bytes, then the args
+  const size_t args_off = (static_cast<size_t>(n_items + 1) * sizeof(uint32_t) + 15) / 16 * 16;
+  const size_t bytes = args_off + static_cast<size_t>(n_items) * sizeof(SpmvArgs);
+  std::vector<uint32_t> first(static_cast<size_t>(n_items) + 1);
+  std::vector<SpmvArgs> args(static_cast<size_t>(n_items));
+  int64_t total = 0;
+  int lds = 0;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_matrix_s* m = items[i].A;
+    first[i] = static_cast<uint32_t>(total);
+    args[i] = make_args(m, m->A, sm, n_rhs, items[i].x, items[i].y);
+    lds = std::max(lds, args[i].win_floats);
+    total += m->A.part.n_groups;
+    if (total > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
+  }
+  first[n_items] = static_cast<uint32_t>(total);
+  if (total == 0) return;
+  ItemRing& R = ring_for(m0->device);
+  std::lock_guard<std::mutex> lk(R.mu);
+  const int slot = static_cast<int>(R.next++ % kRingSlots);
+  HIP_CHECK(hipEventSynchronize(R.done[slot]));  // the slot's previous launch has finished
+  char* h = R.host + slot * kRingSlotBytes;
+  char* d = R.dev + slot * kRingSlotBytes;
+  std::memcpy(h, first.data(), first.size() * sizeof(uint32_t));
+  std::memcpy(h + args_off, args.data(), args.size() * sizeof(SpmvArgs));
+  HIP_CHECK(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+  BatchTable t{};
+  t.args = reinterpret_cast<const SpmvArgs*>(d + args_off);
+  t.first = reinterpret_cast<const uint32_t*>(d);
+  t.n_items = n_items;
+  const hipError_t e = launch_spmv_batched(m0->vf, sm, n_rhs, m0->A.idx_bytes, t, total, lds, s);
+  // recorded even when the launch failed, so that the slot is free again
+  const hipError_t er = hipEventRecord(R.done[slot], s);
+  HIP_CHECK(e);
+  HIP_CHECK(er);
 }
 
 constexpr int32_t kMaxScenarios = 65536;  // also the limit on beams per scenario
@@ -796,20 +937,20 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     info->value_format = m->vf;
     info->index_format = m->xf;
     info->has_transpose = m->has_t ? 1 : 0;
-    info->group_nnz = A.group_nnz;
-    info->n_groups = A.n_groups;
-    info->n_groups_windowed = A.n_windowed;
-    info->group_nnz_t = m->has_t ? m->AT.group_nnz : 0;
-    info->n_groups_t = m->has_t ? m->AT.n_groups : 0;
-    info->n_groups_windowed_t = m->has_t ? m->AT.n_windowed : 0;
+    info->group_nnz = A.part.group_nnz;
+    info->n_groups = A.part.n_groups;
+    info->n_groups_windowed = A.part.n_windowed;
+    info->group_nnz_t = m->has_t ? m->AT.part.group_nnz : 0;
+    info->n_groups_t = m->has_t ? m->AT.part.n_groups : 0;
+    info->n_groups_windowed_t = m->has_t ? m->AT.part.n_windowed : 0;
     info->device_bytes = A.bytes() + m->row_scale.bytes() + (m->has_t ? m->AT.bytes() : 0);
     const uint64_t per_nnz = static_cast<uint64_t>(value_bytes(m->vf)) + static_cast<uint64_t>(A.idx_bytes);
     const uint64_t per_nnz_t = static_cast<uint64_t>(value_bytes(m->vf)) + 4;
     const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
     info->spmv_bytes = A.nnz * per_nnz + (A.n_rows + 1) * 4 + A.n_rows * scale_b + 4 * A.n_cols + 4 * A.n_rows;
     // A^T reads the scale of A's rows through its columns: 4 B per column of A^T
-    info->n_groups_split = A.n_split;
-    info->n_groups_split_t = m->has_t ? m->AT.n_split : 0;
+    info->n_groups_split = A.part.n_split;
+    info->n_groups_split_t = m->has_t ? m->AT.part.n_split : 0;
     info->adjoint_bytes = m->has_t ? A.nnz * per_nnz_t + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
   });
 }
@@ -879,10 +1020,7 @@ dose_status dose_spmv_batched(const dose_batch_item* items, int32_t n_items, voi
   return guarded([&] {
     check_items(items, n_items);
     DeviceGuard g(items[0].A->device);
-    std::unique_ptr<dose_batch_plan_s> p(build_plan(items, n_items, 0, as_stream(hip_stream)));
-    enqueue_plan(p.get(), as_stream(hip_stream));
-    // the plan's device buffers must outlive the launch
-    HIP_CHECK(hipStreamSynchronize(as_stream(hip_stream)));
+    launch_items(items, n_items, as_stream(hip_stream));
   });
 }
 
@@ -984,6 +1122,35 @@ dose_status dose_scenario_objective(int32_t n_scen, int32_t n_beams, int64_t n, 
     hipError_t e = launch_scenario(n_scen, n_beams, n, part, p, w, prob, d_out, seed, partial, np, out, s);
     (void)hipFreeAsync(partial, s);
     HIP_CHECK(e);
+  });
+}
+
+dose_status dose_robust_seed(int32_t n_scen, int64_t n, int32_t mode, const double* out, const double* prob,
+                             const double* grad_scale, const float* seed, float* wseed, void* hip_stream) {
+  return guarded([&] {
+    if (n_scen < 1 || n_scen > kMaxScenarios || n < 0) fail(DOSE_ERR_INVALID_ARGUMENT, "bad scenario count or size");
+    if (mode != DOSE_ROBUST_EXPECTED && mode != DOSE_ROBUST_WORST) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown mode");
+    if (mode == DOSE_ROBUST_WORST && !out) fail(DOSE_ERR_INVALID_ARGUMENT, "the worst case needs out");
+    if (n > 0 && (!seed || !wseed)) fail(DOSE_ERR_INVALID_ARGUMENT, "null seed or wseed");
+    if (n > INT64_MAX / 4 / n_scen) fail(DOSE_ERR_INVALID_ARGUMENT, "seeds too large");
+    const uintptr_t a4 = reinterpret_cast<uintptr_t>(seed) | reinterpret_cast<uintptr_t>(wseed);
+    const uintptr_t a8 = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(prob) |
+                         reinterpret_cast<uintptr_t>(grad_scale);
+    if (a4 % 4 != 0 || a8 % 8 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "float arrays must be 4-byte and double arrays 8-byte aligned");
+    const size_t sn = static_cast<size_t>(n_scen) * static_cast<size_t>(n) * 4;
+    if (seed != wseed && overlaps(seed, sn, wseed, sn))
+      fail(DOSE_ERR_INVALID_ARGUMENT, "wseed overlaps seed without being seed");
+    const struct {
+      const void* ptr;
+      size_t bytes;
+    } in[3] = {{out, out ? static_cast<size_t>(n_scen + 3) * 8 : 0},
+               {prob, prob ? static_cast<size_t>(n_scen) * 8 : 0},
+               {grad_scale, grad_scale ? size_t{8} : 0}};
+    for (const auto& i : in)
+      if (i.ptr && overlaps(wseed, sn, i.ptr, i.bytes)) fail(DOSE_ERR_INVALID_ARGUMENT, "wseed overlaps an input");
+    HIP_CHECK(launch_robust_seed(n_scen, n, mode == DOSE_ROBUST_WORST ? 1 : 0, out, prob, grad_scale, seed, wseed,
+                                 as_stream(hip_stream)));
   });
 }
 

@@ -76,6 +76,10 @@ struct SpmvArgs {
   int64_t n_groups;
   int32_t win_floats;       // LDS 4-byte words for the x window (dynamic shared memory)
   int32_t idx_bytes;        // 4 or 2
+  int32_t xcd_blocks;       // 0, or 8: workgroups go to the chip's 8 dies round-robin; give each die
+                            // one contiguous eighth of the groups (so its L2 sees one eighth of the
+                            // gathered vector); the order of every row's sum is unchanged
+  int32_t pad0;
 };
 
 // Entries of a quarter: lane l of a step loads the 4 entries at 4 l and at
@@ -99,10 +103,21 @@ hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hip
 // One FP64 vector: x, y FP64, products and sums FP64; a.win_floats sized as
 // for two FP32 vectors (a window column is 8 bytes).
 hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_t s);
-// Batched launch: one workgroup per entry of d_work, the groups of all items
-// (copies of their descriptors, each naming its item in d_args).
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SpmvArgs* d_args,
-                               const GroupDesc* d_work, int64_t n_work, int lds_floats, hipStream_t s);
+// The items of a batched launch, in device memory.  Either a work list (one
+// descriptor copy per workgroup, naming its item: batch plans) or, when work
+// is null, the first workgroup of every item (n_items + 1 ascending entries,
+// the last one the total), each item's workgroups taking its matrix's own
+// row groups (args[i].groups) in order.
+struct BatchTable {
+  const SpmvArgs* args;
+  const GroupDesc* work;
+  const uint32_t* first;
+  int32_t n_items;
+};
+
+// Batched launch: n_work workgroups over the groups of all items.
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const BatchTable& t, int64_t n_work,
+                               int lds_floats, hipStream_t s);
 hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const void* col, int idx_bytes,
                                 const uint32_t* row_ptr, hipStream_t s);
 // Sets the n_pad padding indices after entry nnz - 1 to its column (0 when
@@ -143,6 +158,10 @@ hipError_t launch_scenario(int n_scen, int n_beams, int64_t n, const float* part
                            double* partial, int n_partial, double* out, hipStream_t s);
 hipError_t launch_norm2(int64_t n, const float* g, double* partial, int n_partial, double* out,
                         hipStream_t s);
+// wseed[s][v] = fl32(c_s * g * seed[s][v]) for the expectation (worst = 0)
+// or the worst case (worst = 1) of n_scen scenarios of n voxels.
+hipError_t launch_robust_seed(int n_scen, int64_t n, int worst, const double* out, const double* prob,
+                              const double* gscale, const float* seed, float* wseed, hipStream_t s);
 hipError_t launch_probe_read(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
 hipError_t launch_probe_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 

@@ -239,6 +239,41 @@ __global__ __launch_bounds__(kRedThreads) void k_scenario_pass2(const double* __
   }
 }
 
+// Seeds of the robust gradient: the derivative of the robust objective with
+// respect to scenario s's dose is c_s times that scenario's seed, c_s = prob_s
+// (1 / n_scen without probabilities) for the expectation, and for the worst
+// case 1 for the scenario whose index k_scenario_pass2 stored in out[n_scen
+// + 2] and 0 for the others.  wseed[s][v] = fl32(c_s g seed[s][v]), the
+// product formed in FP64 (exact for c_s in {0, 1}) and rounded once; g is the
+// caller's outer derivative (1 when absent).  Workgroups stride over
+// (scenario, 1024-voxel chunk) pairs, four voxels per thread.
+constexpr int kSeedChunk = 4 * kRedThreads;
+
+__global__ __launch_bounds__(kRedThreads) void k_robust_seed(int n_scen, int64_t n, int64_t n_chunks, int worst,
+                                                             const double* __restrict__ out,
+                                                             const double* __restrict__ prob,
+                                                             const double* __restrict__ gscale,
+                                                             const float* seed, float* wseed) {
+  const int64_t total = n_chunks * n_scen;
+  for (int64_t job = blockIdx.x; job < total; job += gridDim.x) {
+    const int s = static_cast<int>(job / n_chunks);
+    const int64_t chunk = job - static_cast<int64_t>(s) * n_chunks;
+    double c;
+    if (worst)
+      c = s == static_cast<int>(out[n_scen + 2]) ? 1.0 : 0.0;
+    else
+      c = prob ? prob[s] : 1.0 / static_cast<double>(n_scen);
+    const double cg = gscale ? c * gscale[0] : c;
+    const int64_t base = static_cast<int64_t>(s) * n;
+    const int64_t v0 = chunk * kSeedChunk + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t v = v0 + j * kRedThreads;
+      if (v < n) wseed[base + v] = static_cast<float>(cg * static_cast<double>(seed[base + v]));
+    }
+  }
+}
+
 // Read-only stream with 16-byte non-temporal loads (as the SpMV streams its
 // matrix); the store happens only if the data XORs to a fixed improbable
 // pattern, which keeps the loads alive.
@@ -315,6 +350,17 @@ hipError_t launch_scenario(int n_scen, int n_beams, int64_t n, const float* part
   scenario_pass1(n_scen, n_beams, n, part, p, w, d_out, seed, partial, n_partial, s);
   hipLaunchKernelGGL(k_scenario_pass2, dim3(1), dim3(kRedThreads), 0, s, partial, n > 0 ? n_partial : 0, n_scen,
                      prob, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_robust_seed(int n_scen, int64_t n, int worst, const double* out, const double* prob,
+                              const double* gscale, const float* seed, float* wseed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t n_chunks = (n + kSeedChunk - 1) / kSeedChunk;
+  const int64_t jobs = n_chunks * n_scen;
+  const unsigned grid = static_cast<unsigned>(jobs < 65536 ? jobs : 65536);
+  hipLaunchKernelGGL(k_robust_seed, dim3(grid), dim3(kRedThreads), 0, s, n_scen, n, n_chunks, worst, out, prob,
+                     gscale, seed, wseed);
   return hipGetLastError();
 }
 

@@ -723,11 +723,24 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
   }
 }
 
+// The group workgroup b takes.  With a.xcd_blocks = D (the dies workgroups
+// are dealt to in turn, b going to die b mod D), die x takes the groups
+// [x q + min(x, r), ...) of a split of the n groups into D contiguous runs
+// (q = n / D, r = n mod D, the first r runs one longer), in order: a
+// bijection of [0, n), so every group is taken once.
+__device__ __forceinline__ int64_t group_of_block(const SpmvArgs& a, uint32_t b) {
+  const int D = a.xcd_blocks;
+  if (D <= 1) return b;
+  const int64_t q = a.n_groups / D, r = a.n_groups % D;
+  const int64_t x = b % static_cast<uint32_t>(D), i = b / static_cast<uint32_t>(D);
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <int VF, int SM, int NRHS, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
   __shared__ float part[kGroupWaves * NRHS];
-  run_group<float, VF, SM, NRHS, IX>(a, a.groups + blockIdx.x, xw, part);
+  run_group<float, VF, SM, NRHS, IX>(a, a.groups + group_of_block(a, blockIdx.x), xw, part);
 }
 
 // FP64 x and y, FP64 products and sums (one vector): the paper's
@@ -736,18 +749,41 @@ template <int VF, int SM, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_f64(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats 4-byte words
   __shared__ double part[kGroupWaves];
-  run_group<double, VF, SM, 1, IX>(a, a.groups + blockIdx.x, xw, part);
+  run_group<double, VF, SM, 1, IX>(a, a.groups + group_of_block(a, blockIdx.x), xw, part);
+}
+
+// The item a workgroup of a batched launch belongs to without a work list:
+// the last item whose first workgroup is at or before b (items without groups
+// share their first workgroup with the next item and are never chosen).  The
+// lanes compare 64 entries of the ascending table at a time.
+__device__ __forceinline__ int find_item(const uint32_t* __restrict__ first, int n_items, uint32_t b) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int below = 0;  // entries i < n_items with first[i] <= b
+  for (int i0 = 0; i0 < n_items; i0 += kWave) {
+    const int i = i0 + lane;
+    const bool le = i < n_items && first[i] <= b;
+    const int c = __popcll(__ballot(le));
+    below += c;
+    if (c < kWave) break;
+  }
+  return below - 1;
 }
 
 // Batched form, one launch for many matrices: workgroup b takes entry b of
-// the work list, a copy of a group's descriptor that names its item.
+// the work list (a copy of a group's descriptor that names its item), or,
+// without a work list, group b - first[i] of item i's matrix.
 template <int VF, int SM, int NRHS, int IX>
-__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_batched(
-    const SpmvArgs* __restrict__ args, const GroupDesc* __restrict__ work) {
+__global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_batched(BatchTable t) {
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   __shared__ float part[kGroupWaves * NRHS];
-  const GroupDesc* gp = work + blockIdx.x;
-  run_group<float, VF, SM, NRHS, IX>(args[gp->item], gp, xw, part);
+  if (t.work) {
+    const GroupDesc* gp = t.work + blockIdx.x;
+    run_group<float, VF, SM, NRHS, IX>(t.args[gp->item], gp, xw, part);
+  } else {
+    const int i = __builtin_amdgcn_readfirstlane(find_item(t.first, t.n_items, blockIdx.x));
+    const SpmvArgs& a = t.args[i];
+    run_group<float, VF, SM, NRHS, IX>(a, a.groups + (blockIdx.x - t.first[i]), xw, part);
+  }
 }
 
 template <int VF, int SM, int NRHS>
@@ -760,13 +796,12 @@ void launch_ix(const SpmvArgs& a, size_t lds, hipStream_t s) {
 }
 
 template <int VF, int SM, int NRHS>
-void launch_ix_batched(int idx_bytes, const SpmvArgs* args, const GroupDesc* work, int64_t n_work, size_t lds,
-                       hipStream_t s) {
+void launch_ix_batched(int idx_bytes, const BatchTable& t, int64_t n_work, size_t lds, hipStream_t s) {
   const dim3 g(static_cast<unsigned>(n_work)), block(kGroupThreads);
   if (SM != kScaleCol && idx_bytes == 2)
-    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, SM == kScaleCol ? 4 : 2>), g, block, lds, s, args, work);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, SM == kScaleCol ? 4 : 2>), g, block, lds, s, t);
   else
-    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 4>), g, block, lds, s, args, work);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 4>), g, block, lds, s, t);
 }
 
 template <int VF, int SM>
@@ -782,13 +817,13 @@ hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
 }
 
 template <int VF, int SM>
-hipError_t launch_rhs_batched(int n_rhs, int idx_bytes, const SpmvArgs* args, const GroupDesc* work, int64_t n_work,
-                              int lds_floats, hipStream_t s) {
+hipError_t launch_rhs_batched(int n_rhs, int idx_bytes, const BatchTable& t, int64_t n_work, int lds_floats,
+                              hipStream_t s) {
   const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
   switch (n_rhs) {
-    case 1: launch_ix_batched<VF, SM, 1>(idx_bytes, args, work, n_work, lds, s); break;
-    case 2: launch_ix_batched<VF, SM, 2>(idx_bytes, args, work, n_work, lds, s); break;
-    case 4: launch_ix_batched<VF, SM, 4>(idx_bytes, args, work, n_work, lds, s); break;
+    case 1: launch_ix_batched<VF, SM, 1>(idx_bytes, t, n_work, lds, s); break;
+    case 2: launch_ix_batched<VF, SM, 2>(idx_bytes, t, n_work, lds, s); break;
+    case 4: launch_ix_batched<VF, SM, 4>(idx_bytes, t, n_work, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -865,19 +900,19 @@ hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SpmvArgs* d_args,
-                               const GroupDesc* d_work, int64_t n_work, int lds_floats, hipStream_t s) {
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const BatchTable& t, int64_t n_work,
+                               int lds_floats, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp32 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp32, kScaleNone>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp32, kScaleNone>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleRow)
-    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)
-    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, idx_bytes, d_args, d_work, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
   return hipErrorInvalidValue;
 }
 

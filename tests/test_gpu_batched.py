@@ -101,11 +101,16 @@ def test_autotuned_plan_stays_within_tolerance(dev, tmp_path, monkeypatch):
     for A, (s, rp, cols, vals) in zip(mats, host):
         X = torch.from_numpy(np.stack([dosegen.spot_weights(s.seed, r, s.n_cols) for r in range(4)], 1)).cuda()
         entries.append((A, X.contiguous(), torch.zeros(s.n_rows, 4, device=dev)))
+    before = [A.info()["group_nnz"] for A in mats]
     plan = dm.BatchPlan(entries, autotune=True)
     plan.launch()
     torch.cuda.synchronize()
-    for (A, X, Y), (s, rp, cols, vals) in zip(entries, host):
-        assert A.info()["group_nnz"] in (8192, 16384, 32768, 65536)
+    for (A, X, Y), (s, rp, cols, vals), g0 in zip(entries, host, before):
+        # the plan runs its own copy of the chosen partition; the matrix keeps its own
+        assert A.info()["group_nnz"] == g0
+        for r in range(4):
+            y_plain = A.spmv(X[:, r].contiguous()).cpu().numpy()
+            np.testing.assert_array_equal(_bits(Y[:, r].cpu().numpy()), _bits(y_plain))
         dec, _ = oracle.decode_matrix("bf16", rp, vals)
         Y_ref = oracle.spmv_multi(rp, cols, dec, X.cpu().numpy())
         for r in range(4):

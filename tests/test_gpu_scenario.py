@@ -291,11 +291,9 @@ def test_robust_gradient_through_autograd(dev, mode):
     seed_h = seed.cpu().numpy().astype(np.float64)
     if mode == "expected":
         assert f.item() == out[n_scen + 1]
-        c = prob_h
     else:
         assert f.item() == out[n_scen]
-        c = np.zeros(n_scen)
-        c[int(out[n_scen + 2])] = 1.0
+    c = oracle.robust_weights(out[:n_scen], prob_h if mode == "expected" else None, mode)
     for b in range(n_beams):
         n_cols = specs[b].n_cols
         g_ref = np.zeros(n_cols)

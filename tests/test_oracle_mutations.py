@@ -79,6 +79,15 @@ MUTANTS = [
     ("expectation ignores the probabilities",
      "for (int32_t s = 0; s < n_scen; ++s) e += prob[s] * f[s];",
      "for (int32_t s = 0; s < n_scen; ++s) e += f[s] / n_scen;"),
+    ("worst-case weight on the last of tied scenarios",
+     "      if (f[s] > f[a]) a = s;",
+     "      if (f[s] >= f[a]) a = s;"),
+    ("expectation weights ignore the probabilities",
+     "c[s] = prob ? prob[s] : 1.0 / (double)n_scen;",
+     "c[s] = 1.0 / (double)n_scen;"),
+    ("worst-case weight on the least scenario",
+     "      if (f[s] > f[a]) a = s;",
+     "      if (f[s] < f[a]) a = s;"),
 ]
 
 CHECKS = [
@@ -99,6 +108,7 @@ CHECKS = [
     pins.test_beam_sum_is_the_correctly_rounded_sum_of_few_terms,
     pins.test_robust_closed_forms,
     pins.test_robust_expectation_vs_exact_fractions,
+    pins.test_robust_weights_are_the_derivatives_of_the_robust_forms,
 ]
 
 

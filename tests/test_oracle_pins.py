@@ -309,6 +309,24 @@ def test_transpose_structure():
     np.testing.assert_array_equal(dT, d32.T)
 
 
+def test_spmv_parallel_equals_sequential_bitwise():
+    """The all-core timing variant sums every row exactly as the sequential
+    oracle (rows are independent): equal bits, on a matrix with empty rows
+    and rows long enough to be split among threads' chunks."""
+    rng = np.random.default_rng(12)
+    lens = rng.integers(0, 60, 20000)
+    lens[::7] = 0
+    rp = np.zeros(lens.size + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    cols = np.concatenate([np.sort(rng.choice(900, L, replace=False)) for L in lens]).astype(np.int32)
+    dec = rng.random(rp[-1]).astype(np.float32)
+    x = rng.random(900).astype(np.float32)
+    a = oracle.spmv(rp, cols, dec, x)
+    b = oracle.spmv_parallel(rp, cols, dec, x)
+    np.testing.assert_array_equal(a.view(np.uint64), b.view(np.uint64))
+    assert oracle.num_threads() >= 1
+
+
 def test_spmv_multi_matches_columns_of_single():
     rng = np.random.default_rng(700)
     dense, rp, cols, vals = _random_csr(rng, 30, 12, 0.4)
@@ -445,6 +463,37 @@ def test_robust_expectation_vs_exact_fractions():
         assert worst == f.max() and arg == int(np.argmax(f))
         _, _, mean = oracle.robust(f)
         assert mean == float(Fraction(int(fi.sum()), 4)) / n
+
+
+def test_robust_weights_are_the_derivatives_of_the_robust_forms():
+    """c_s = d(robust form)/d f_s, checked by one-sided differences of the
+    oracle's robust forms with a dyadic step (exact: every value is a
+    multiple of 1/64 well below 2^40) away from ties, and the first-scenario
+    convention on ties."""
+    rng = np.random.default_rng(77)
+    h = 1.0 / 64.0
+    for _ in range(20):
+        n = int(rng.integers(1, 10))
+        f = rng.permutation(n).astype(np.float64) * 4.0 + 1.0  # distinct: no ties
+        prob = rng.integers(0, 65, n) / 64.0
+        for mode in ("expected", "worst"):
+            for pr in ((prob, None) if mode == "expected" else (None,)):
+                c = oracle.robust_weights(f, pr, mode)
+                for s in range(n):
+                    fp = f.copy()
+                    fp[s] += h
+                    w0, _, e0 = oracle.robust(f, pr)
+                    w1, _, e1 = oracle.robust(fp, pr)
+                    slope = ((e1 - e0) if mode == "expected" else (w1 - w0)) / h
+                    if mode == "expected" and pr is None:
+                        # the mean: (sum f) / n rounds; the slope is 1/n up to that rounding
+                        assert abs(slope - c[s]) <= 1e-9 and c[s] == 1.0 / n
+                    else:
+                        assert slope == c[s], (mode, n, s, slope, c[s])
+    # ties: the first worst scenario takes the whole weight
+    np.testing.assert_array_equal(oracle.robust_weights([2.0, 9.0, 9.0, 1.0], mode="worst"), [0, 1, 0, 0])
+    np.testing.assert_array_equal(oracle.robust_weights([5.0], mode="worst"), [1.0])
+    np.testing.assert_array_equal(oracle.robust_weights([5.0, 6.0], [0.75, 0.25]), [0.75, 0.25])
 
 
 # --------------------------------------------------------------------------
