@@ -787,6 +787,37 @@ void launch_items(const dose_batch_item* items, int32_t n_items, hipStream_t s) 
 
 constexpr int32_t kMaxScenarios = 65536;  // also the limit on beams per scenario
 
+// Argument checks of the scenario epilogue (both entry points).
+void check_scenario_args(int32_t n_scen, int32_t n_beams, int64_t n, const float* part, const float* p, const float* w,
+                         const double* prob, const float* d_out, const float* seed, const double* out) {
+  if (n_scen < 1 || n_scen > kMaxScenarios || n_beams < 1 || n_beams > kMaxScenarios || n < 0 || !out)
+    fail(DOSE_ERR_INVALID_ARGUMENT, "bad scenario count, beam count, size or null output");
+  if (n > INT64_MAX / 4 / n_scen / n_beams) fail(DOSE_ERR_INVALID_ARGUMENT, "beam doses too large");
+  if (n > 0 && (!part || !p || !w)) fail(DOSE_ERR_INVALID_ARGUMENT, "null input");
+  const uintptr_t a4 = reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(p) |
+                       reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(d_out) |
+                       reinterpret_cast<uintptr_t>(seed);
+  const uintptr_t a8 = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(prob);
+  if (a4 % 4 != 0 || a8 % 8 != 0)
+    fail(DOSE_ERR_INVALID_ARGUMENT, "float arrays must be 4-byte and double arrays 8-byte aligned");
+  const size_t sn = static_cast<size_t>(n_scen) * static_cast<size_t>(n) * 4;
+  const struct {
+    const void* ptr;
+    size_t bytes;
+  } in[4] = {{part, sn * static_cast<size_t>(n_beams)}, {p, static_cast<size_t>(n) * 4},
+             {w, static_cast<size_t>(n) * 4}, {prob, prob ? static_cast<size_t>(n_scen) * 8 : 0}},
+    outs[3] = {{d_out, d_out ? sn : 0}, {seed, seed ? sn : 0}, {out, static_cast<size_t>(n_scen + 3) * 8}};
+  for (int i = 0; i < 3; ++i) {
+    if (!outs[i].ptr || outs[i].bytes == 0) continue;
+    for (int j = 0; j < 4; ++j)
+      if (in[j].ptr && in[j].bytes && overlaps(outs[i].ptr, outs[i].bytes, in[j].ptr, in[j].bytes))
+        fail(DOSE_ERR_INVALID_ARGUMENT, "outputs must not overlap inputs");
+    for (int j = i + 1; j < 3; ++j)
+      if (outs[j].ptr && outs[j].bytes && overlaps(outs[i].ptr, outs[i].bytes, outs[j].ptr, outs[j].bytes))
+        fail(DOSE_ERR_INVALID_ARGUMENT, "outputs must not overlap each other");
+  }
+}
+
 int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(1024, (n + 4095) / 4096))); }
 
 }  // namespace
@@ -1089,32 +1120,7 @@ dose_status dose_scenario_objective(int32_t n_scen, int32_t n_beams, int64_t n, 
                                     const float* w, const double* prob, float* d_out, float* seed, double* out,
                                     void* hip_stream) {
   return guarded([&] {
-    if (n_scen < 1 || n_scen > kMaxScenarios || n_beams < 1 || n_beams > kMaxScenarios || n < 0 || !out)
-      fail(DOSE_ERR_INVALID_ARGUMENT, "bad scenario count, beam count, size or null output");
-    if (n > INT64_MAX / 4 / n_scen / n_beams) fail(DOSE_ERR_INVALID_ARGUMENT, "beam doses too large");
-    if (n > 0 && (!part || !p || !w)) fail(DOSE_ERR_INVALID_ARGUMENT, "null input");
-    const uintptr_t a4 = reinterpret_cast<uintptr_t>(part) | reinterpret_cast<uintptr_t>(p) |
-                         reinterpret_cast<uintptr_t>(w) | reinterpret_cast<uintptr_t>(d_out) |
-                         reinterpret_cast<uintptr_t>(seed);
-    const uintptr_t a8 = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(prob);
-    if (a4 % 4 != 0 || a8 % 8 != 0)
-      fail(DOSE_ERR_INVALID_ARGUMENT, "float arrays must be 4-byte and double arrays 8-byte aligned");
-    const size_t sn = static_cast<size_t>(n_scen) * static_cast<size_t>(n) * 4;
-    const struct {
-      const void* ptr;
-      size_t bytes;
-    } in[4] = {{part, sn * static_cast<size_t>(n_beams)}, {p, static_cast<size_t>(n) * 4},
-               {w, static_cast<size_t>(n) * 4}, {prob, prob ? static_cast<size_t>(n_scen) * 8 : 0}},
-      outs[3] = {{d_out, d_out ? sn : 0}, {seed, seed ? sn : 0}, {out, static_cast<size_t>(n_scen + 3) * 8}};
-    for (int i = 0; i < 3; ++i) {
-      if (!outs[i].ptr || outs[i].bytes == 0) continue;
-      for (int j = 0; j < 4; ++j)
-        if (in[j].ptr && in[j].bytes && overlaps(outs[i].ptr, outs[i].bytes, in[j].ptr, in[j].bytes))
-          fail(DOSE_ERR_INVALID_ARGUMENT, "outputs must not overlap inputs");
-      for (int j = i + 1; j < 3; ++j)
-        if (outs[j].ptr && outs[j].bytes && overlaps(outs[i].ptr, outs[i].bytes, outs[j].ptr, outs[j].bytes))
-          fail(DOSE_ERR_INVALID_ARGUMENT, "outputs must not overlap each other");
-    }
+    check_scenario_args(n_scen, n_beams, n, part, p, w, prob, d_out, seed, out);
     hipStream_t s = as_stream(hip_stream);
     const int np = n_partial_for(n);
     double* partial = nullptr;
