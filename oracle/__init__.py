@@ -75,6 +75,11 @@ def load_library(path: str):
         "or_beam_sum": ([i32, i64, vp, vp], None),
         "or_robust": ([i32, vp, vp, vp, vp, vp], None),
         "or_robust_weights": ([i32, vp, vp, i32, vp], None),
+        "or_sell_layout": ([i64, vp, i64, i64, vp, vp], None),
+        "or_sell_pack": ([i64, vp, vp, vp, i64, vp, vp, vp, vp], None),
+        "or_sell_spmv": ([i64, i64, vp, vp, vp, vp, vp, vp], None),
+        "or_runs_encode": ([i64, vp, vp, vp, vp, vp], i64),
+        "or_runs_decode": ([i64, vp, vp, vp, vp], None),
     }
     for name, (args, res) in sigs.items():
         f = getattr(lib, name)
@@ -190,6 +195,68 @@ def spmv_multi(row_ptr, cols, dec, x2d) -> np.ndarray:
     y = np.empty((max(rp.size - 1, 1), n_rhs), np.float64)
     _load().or_spmv_multi(rp.size - 1, n_rhs, prp, pc, pd, px, y.ctypes.data)
     return y[:rp.size - 1]
+
+
+# ------------------------------------------------------ SELL-C-sigma, runs
+def sell_layout(row_ptr, C: int, sigma: int):
+    """SELL-C-sigma layout (Kreutzer et al. 2014): (perm, width).  perm[k] is
+    the row at sorted position k (descending length inside windows of sigma
+    rows, ties in ascending row order); width[c] the longest row of chunk c
+    (positions [c C, c C + C))."""
+    rp, prp = _c(row_ptr, np.int64)
+    n = rp.size - 1
+    perm = np.empty(max(n, 1), np.int64)
+    width = np.empty(max((n + C - 1) // C, 1), np.int64)
+    _load().or_sell_layout(n, prp, C, sigma, perm.ctypes.data, width.ctypes.data)
+    return perm[:n], width[:(n + C - 1) // C]
+
+
+def sell_pack(row_ptr, cols, dec, C: int, perm, width):
+    """Column-major padded chunk arrays (values, columns; padding 0 and -1)."""
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    d, pd = _c(dec, np.float32)
+    pm, ppm = _c(perm, np.int64)
+    wd, pwd = _c(width, np.int64)
+    total = int(C * wd.sum())
+    sval = np.empty(max(total, 1), np.float32)
+    scol = np.empty(max(total, 1), np.int32)
+    _load().or_sell_pack(rp.size - 1, prp, pc, pd, C, ppm, pwd, sval.ctypes.data, scol.ctypes.data)
+    return sval[:total], scol[:total]
+
+
+def sell_spmv(n_rows: int, C: int, perm, width, sval, scol, x) -> np.ndarray:
+    """y = A x in FP64 over the packed SELL-C-sigma arrays."""
+    pm, ppm = _c(perm, np.int64)
+    wd, pwd = _c(width, np.int64)
+    sv, psv = _c(sval, np.float32)
+    sc, psc = _c(scol, np.int32)
+    xx, px = _c(x, np.float32)
+    y = np.empty(max(n_rows, 1), np.float64)
+    _load().or_sell_spmv(n_rows, C, ppm, pwd, psv, psc, px, y.ctypes.data)
+    return y[:n_rows]
+
+
+def runs_encode(row_ptr, cols):
+    """Maximal runs of consecutive columns of every row: (run_ptr, start, len)."""
+    rp, prp = _c(row_ptr, np.int64)
+    c, pc = _c(cols, np.int32)
+    n = rp.size - 1
+    run_ptr = np.empty(n + 1, np.int64)
+    start = np.empty(max(c.size, 1), np.int32)
+    length = np.empty(max(c.size, 1), np.int32)
+    nr = int(_load().or_runs_encode(n, prp, pc, run_ptr.ctypes.data, start.ctypes.data, length.ctypes.data))
+    return run_ptr, start[:nr], length[:nr]
+
+
+def runs_decode(run_ptr, start, length) -> np.ndarray:
+    """The columns the runs describe, row after row."""
+    rp, prp = _c(run_ptr, np.int64)
+    st, pst = _c(start, np.int32)
+    ln, pln = _c(length, np.int32)
+    cols = np.empty(max(int(ln.sum()), 1), np.int32)
+    _load().or_runs_decode(rp.size - 1, prp, pst, pln, cols.ctypes.data)
+    return cols[:int(ln.sum())]
 
 
 def spmv_T(row_ptr, cols, dec, v, n_cols: int) -> np.ndarray:

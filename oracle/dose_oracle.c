@@ -371,3 +371,124 @@ void or_robust_weights(int32_t n_scen, const double* f, const double* prob, int3
     for (int32_t s = 0; s < n_scen; ++s) c[s] = prob ? prob[s] : 1.0 / (double)n_scen;
   }
 }
+
+/* ------------------------------------------------------------------ */
+/* SELL-C-sigma storage (Kreutzer et al., SIAM J. Sci. Comput. 36(5),   */
+/* 2014), the SIMD-oriented sparse format the paper names as the next   */
+/* one to investigate for dose matrices (Sec. II-C, Sec. VII).          */
+/* ------------------------------------------------------------------ */
+/* The layout: the rows are taken in consecutive windows of sigma rows (the
+ * last window may be shorter); inside a window the rows are ordered by
+ * descending length, rows of equal length keeping their ascending order.
+ * The resulting sequence perm[0 .. n_rows) is cut into chunks of C
+ * consecutive positions (the last chunk may hold fewer rows); a chunk's
+ * width is the length of its longest row.  perm: n_rows entries;
+ * width: ceil(n_rows / C) entries.  The sort is a plain insertion sort: slow
+ * and obviously stable. */
+void or_sell_layout(int64_t n_rows, const int64_t* row_ptr, int64_t C, int64_t sigma, int64_t* perm,
+                    int64_t* width) {
+  for (int64_t w0 = 0; w0 < n_rows; w0 += sigma) {
+    int64_t w1 = w0 + sigma < n_rows ? w0 + sigma : n_rows;
+    for (int64_t k = w0; k < w1; ++k) {
+      int64_t r = k, len = row_ptr[r + 1] - row_ptr[r];
+      int64_t q = k;
+      /* move r before every earlier row of the window that is strictly shorter */
+      while (q > w0 && row_ptr[perm[q - 1] + 1] - row_ptr[perm[q - 1]] < len) {
+        perm[q] = perm[q - 1];
+        --q;
+      }
+      perm[q] = r;
+    }
+  }
+  for (int64_t c = 0; c * C < n_rows; ++c) {
+    int64_t wmax = 0;
+    for (int64_t i = c * C; i < (c + 1) * C && i < n_rows; ++i) {
+      int64_t len = row_ptr[perm[i] + 1] - row_ptr[perm[i]];
+      if (len > wmax) wmax = len;
+    }
+    width[c] = wmax;
+  }
+}
+
+/* The packed SELL-C-sigma arrays: chunk c starts at off_c = C * (width_0 +
+ * ... + width_(c-1)); entry j of the row at chunk position i (0 <= i < C)
+ * sits at off_c + j * C + i (column-major inside the chunk).  Slots past a
+ * row's length (and rows past n_rows in the last chunk) are padding: value
+ * 0 and column -1.  val, col: C * sum(width) entries. */
+void or_sell_pack(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, const float* dec, int64_t C,
+                  const int64_t* perm, const int64_t* width, float* sval, int32_t* scol) {
+  int64_t off = 0;
+  for (int64_t c = 0; c * C < n_rows; ++c) {
+    for (int64_t j = 0; j < width[c]; ++j)
+      for (int64_t i = 0; i < C; ++i) {
+        int64_t slot = off + j * C + i, pos = c * C + i;
+        sval[slot] = 0.0f;
+        scol[slot] = -1;
+        if (pos < n_rows) {
+          int64_t r = perm[pos];
+          if (j < row_ptr[r + 1] - row_ptr[r]) {
+            sval[slot] = dec[row_ptr[r] + j];
+            scol[slot] = col[row_ptr[r] + j];
+          }
+        }
+      }
+    off += C * width[c];
+  }
+}
+
+/* y = A x over the packed arrays: the row at chunk position i gets the sum,
+ * in ascending j, of its non-padding slots (FP64, from +0), stored at its
+ * original index perm[c * C + i]. */
+void or_sell_spmv(int64_t n_rows, int64_t C, const int64_t* perm, const int64_t* width, const float* sval,
+                  const int32_t* scol, const float* x, double* y) {
+  int64_t off = 0;
+  for (int64_t c = 0; c * C < n_rows; ++c) {
+    for (int64_t i = 0; i < C && c * C + i < n_rows; ++i) {
+      double acc = 0.0;
+      for (int64_t j = 0; j < width[c]; ++j) {
+        int64_t slot = off + j * C + i;
+        if (scol[slot] >= 0) acc += (double)sval[slot] * (double)x[scol[slot]];
+      }
+      y[perm[c * C + i]] = acc;
+    }
+    off += C * width[c];
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Run-length column indices.  In a dose row the stored spots form a    */
+/* few runs of consecutive columns (a pencil beam's spots along one     */
+/* scanline), so the row's columns are described by (start, length)    */
+/* pairs: the maximal runs c, c+1, ..., c+L-1 of consecutive columns,   */
+/* in the row's order.  The paper notes that column indices are a       */
+/* large part of the bytes moved (Sec. V); runs shrink them.            */
+/* ------------------------------------------------------------------ */
+/* run_ptr: n_rows + 1 offsets into start/len (run_ptr[0] = 0); start, len:
+ * room for nnz runs.  Returns the number of runs. */
+int64_t or_runs_encode(int64_t n_rows, const int64_t* row_ptr, const int32_t* col, int64_t* run_ptr,
+                       int32_t* start, int32_t* len) {
+  int64_t n = 0;
+  run_ptr[0] = 0;
+  for (int64_t i = 0; i < n_rows; ++i) {
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      if (k > row_ptr[i] && col[k] == col[k - 1] + 1) {
+        len[n - 1] += 1; /* continues the current run */
+      } else {
+        start[n] = col[k];
+        len[n] = 1;
+        ++n;
+      }
+    }
+    run_ptr[i + 1] = n;
+  }
+  return n;
+}
+
+/* The columns the runs describe, row after row. */
+void or_runs_decode(int64_t n_rows, const int64_t* run_ptr, const int32_t* start, const int32_t* len,
+                    int32_t* col) {
+  int64_t k = 0;
+  for (int64_t i = 0; i < n_rows; ++i)
+    for (int64_t r = run_ptr[i]; r < run_ptr[i + 1]; ++r)
+      for (int32_t t = 0; t < len[r]; ++t) col[k++] = start[r] + t;
+}

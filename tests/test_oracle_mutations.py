@@ -19,6 +19,7 @@ import pytest
 import oracle
 import test_oracle_metrics as metric_pins
 import test_oracle_pins as pins
+import test_oracle_sell_runs as sell_pins
 
 # (name, text in dose_oracle.c, replacement)
 MUTANTS = [
@@ -88,6 +89,33 @@ MUTANTS = [
     ("worst-case weight on the least scenario",
      "      if (f[s] > f[a]) a = s;",
      "      if (f[s] < f[a]) a = s;"),
+    ("SELL sort ascending",
+     "while (q > w0 && row_ptr[perm[q - 1] + 1] - row_ptr[perm[q - 1]] < len) {",
+     "while (q > w0 && row_ptr[perm[q - 1] + 1] - row_ptr[perm[q - 1]] > len) {"),
+    ("SELL sort not stable",
+     "while (q > w0 && row_ptr[perm[q - 1] + 1] - row_ptr[perm[q - 1]] < len) {",
+     "while (q > w0 && row_ptr[perm[q - 1] + 1] - row_ptr[perm[q - 1]] <= len) {"),
+    ("SELL sort across windows",
+     "      while (q > w0 && row_ptr",
+     "      while (q > 0 && row_ptr"),
+    ("SELL width misses the chunk's last row",
+     "for (int64_t i = c * C; i < (c + 1) * C && i < n_rows; ++i) {",
+     "for (int64_t i = c * C; i + 1 < (c + 1) * C && i < n_rows; ++i) {"),
+    ("SELL pack row-major inside a chunk",
+     "int64_t slot = off + j * C + i, pos = c * C + i;",
+     "int64_t slot = off + i * width[c] + j, pos = c * C + i;"),
+    ("SELL product stored at the sorted position",
+     "      y[perm[c * C + i]] = acc;",
+     "      y[c * C + i] = acc;"),
+    ("runs: a break not detected",
+     "if (k > row_ptr[i] && col[k] == col[k - 1] + 1) {",
+     "if (k > row_ptr[i] && col[k] >= col[k - 1] + 1) {"),
+    ("runs continue across rows",
+     "if (k > row_ptr[i] && col[k] == col[k - 1] + 1) {",
+     "if (k > 0 && col[k] == col[k - 1] + 1) {"),
+    ("runs decode off by one",
+     "for (int32_t t = 0; t < len[r]; ++t) col[k++] = start[r] + t;",
+     "for (int32_t t = 0; t < len[r]; ++t) col[k++] = start[r] + t + (t > 0);"),
 ]
 
 CHECKS = [
@@ -109,6 +137,12 @@ CHECKS = [
     pins.test_robust_closed_forms,
     pins.test_robust_expectation_vs_exact_fractions,
     pins.test_robust_weights_are_the_derivatives_of_the_robust_forms,
+    sell_pins.test_sell_layout_hand_worked_example,
+    sell_pins.test_sell_layout_ties_keep_row_order,
+    sell_pins.test_sell_layout_is_windowed_stable_argsort,
+    sell_pins.test_sell_pack_holds_every_entry_once_and_product_equals_csr_bitwise,
+    sell_pins.test_runs_hand_worked_example,
+    sell_pins.test_runs_count_maximality_and_decode_on_dose_rows,
 ]
 
 
