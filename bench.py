@@ -331,6 +331,7 @@ def bench_clinical(torch, dm, dosegen, args):
     res["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
     res["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
     res["single_fp32_values"] = bench_single(torch, dm, spec, rp, cols, vals, x, y, args)
+    res["sell_c_sigma"] = bench_sell(torch, dm, spec, rp, cols, vals, x, y, args)
     res["bias_controls"] = bench_bias_controls(torch, dm, dosegen, spec, x, args)
     return res
 
@@ -452,6 +453,38 @@ def bench_single(torch, dm, spec, rp, cols, vals, x, y, args):
     return {"ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
             "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
             "algorithmic_bytes_per_launch": info["spmv_bytes"]}
+
+
+def bench_sell(torch, dm, spec, rp, cols, vals, x, y_csr, args, sigmas=(256, 4096)):
+    """SELL-C-sigma storage (C = 64; the format the paper names as the next
+    to try, Sec. II-C, VII) of the same matrix, FP16 values, int32, 16-bit and
+    run-length column indices: GNNZ/s, the fraction of 8 TB/s of the
+    algorithmic bytes (every code, index or run and row offset once, x and y
+    once) and of the bytes the SELL product streams (padding, per-row position
+    records), and the largest relative difference from the CSR dose (both are
+    within 1e-5 of the oracle)."""
+    res = {}
+    for sigma in sigmas:
+        for idx in ("i32", "u16", "runs"):
+            S = dm.SellMatrix(rp, cols, vals, spec.n_cols, "fp16", sigma=sigma, index_format=idx)
+            info = S.info()
+            ys = torch.empty_like(y_csr)
+            ms = time_launches(lambda: S.spmv(x, ys), args.steps, args.warmup)
+            d = (ys.double() - y_csr.double()).abs()
+            rel = float((d / y_csr.double().abs().clamp_min(1e-300)).max())
+            S.close()
+            gb = info["spmv_bytes"] / (ms * 1e-3) / 1e9
+            sb = info["stream_bytes"] / (ms * 1e-3) / 1e9
+            log(f"sell sigma {sigma} {idx}: {ms:.4f} ms/step, {gb:.0f} GB/s (CSR model), {sb:.0f} GB/s streamed")
+            res[f"sigma{sigma}_{idx}"] = {
+                "ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
+                "GBps_algorithmic": round(gb, 1), "frac": round(gb / HBM_PEAK_GBPS, 4),
+                "GBps_streamed": round(sb, 1), "frac_streamed": round(sb / HBM_PEAK_GBPS, 4),
+                "padding_frac": round(info["stored_slots"] / max(info["nnz"], 1) - 1, 4),
+                "algorithmic_bytes_per_launch": info["spmv_bytes"], "n_runs": info["n_runs"],
+                "n_groups": info["n_groups"], "n_groups_windowed": info["n_groups_windowed"],
+                "max_rel_diff_vs_csr": rel}
+    return res
 
 
 def bench_bias_controls(torch, dm, dosegen, spec, x, args):

@@ -65,10 +65,17 @@ typedef enum {
  * indices: its columns are A's rows. */
 typedef enum {
   DOSE_IDX_I32 = 1, /* 32-bit column indices, as in the paper (Sec. V)            */
-  DOSE_IDX_U16 = 2  /* 16-bit column indices (n_cols <= 65536, else UNSUPPORTED):
+  DOSE_IDX_U16 = 2, /* 16-bit column indices (n_cols <= 65536, else UNSUPPORTED):
                        the paper notes that column indices are a large part of
                        the bytes moved (Sec. V); 4 instead of 6 B per entry in
                        FP16 */
+  DOSE_IDX_RUNS = 3 /* run-length column indices, SELL-C-sigma only: each row's
+                       columns as its maximal runs of consecutive columns (a
+                       dose row holds a few: the spots of a scanline, Sec. II-B),
+                       8 B per run instead of 2 or 4 B per entry; at most 2048
+                       runs per 256 rows of the sorted order (else
+                       DOSE_ERR_UNSUPPORTED); dose_matrix_create refuses it
+                       (DOSE_ERR_UNSUPPORTED) */
 } dose_index_format;
 
 /* dose_matrix_create flags */
@@ -312,6 +319,85 @@ dose_status dose_probe_copy(const void* src, void* dst, uint64_t bytes, void* hi
  * in *n_groups. */
 dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32_t group_nnz,
                                    int64_t* groups, int64_t cap, int64_t* n_groups);
+
+/* ----------------------------------------------------------- SELL-C-sigma
+ * The SIMD-oriented sparse format the paper names as the next one to try for
+ * dose matrices (Sec. II-C, Sec. VII): SELL-C-sigma (Kreutzer et al., SIAM
+ * J. Sci. Comput. 36(5), 2014) with C = 64, one row per lane of a wave64.
+ * The rows are taken in consecutive windows of sigma rows, each window
+ * ordered by descending row length (rows of equal length keep their order),
+ * and the resulting sequence of rows is cut into chunks of 64 positions; a
+ * chunk is as wide as its longest row.  The device stores each chunk's
+ * entries in slices of 8 entries per row (a lane's 8 codes are contiguous);
+ * dose_sell_decode returns Kreutzer's column-major layout. */
+typedef struct dose_sell_s* dose_sell;
+
+typedef struct {
+  int64_t n_rows, n_cols, nnz;
+  int32_t value_format, index_format;
+  int32_t chunk_rows;         /* C = 64                                       */
+  int32_t sigma;
+  int64_t n_chunks;           /* ceil(n_rows / 64)                            */
+  int64_t n_groups;           /* workgroups of a product: 4 chunks each       */
+  int64_t n_groups_windowed;  /* groups whose x window fits in LDS            */
+  int64_t std_slots;          /* 64 * sum of chunk widths: Kreutzer's layout  */
+  int64_t n_runs;             /* DOSE_IDX_RUNS: runs stored (else 0)          */
+  int64_t stored_slots;       /* slots held on the device (widths rounded up
+                                 to whole slices of 8)                        */
+  uint64_t device_bytes;
+  uint64_t spmv_bytes;        /* algorithmic bytes of one product: every code,
+                                 index and row offset read once, x read and y
+                                 written once, as in dose_matrix_info (with
+                                 DOSE_IDX_RUNS: nnz * value + 8 per run + 4 per
+                                 row offset + scale + 4 n_cols + 4 n_rows)     */
+  uint64_t stream_bytes;      /* what one SELL product reads and writes:
+                                 stored_slots * (value + index) + 8 per row
+                                 (its position's row and length), + 8 per run
+                                 and 4 per row with DOSE_IDX_RUNS, + scale +
+                                 4 n_cols + 4 n_rows                           */
+} dose_sell_info_t;
+
+/* Host-only layout for a row_ptr: perm[k] (n_rows entries) is the row at
+ * sorted position k, width[c] (ceil(n_rows / 64) entries) the length of the
+ * longest row of chunk c.  sigma in [1, 2^31).  No GPU is touched. */
+dose_status dose_sell_layout(const int64_t* row_ptr, int64_t n_rows, int32_t sigma, int64_t* perm,
+                             int64_t* width);
+
+/* Builds the SELL-C-sigma form of a host CSR matrix on the current device
+ * (validated and encoded as by dose_matrix_create, including the E4M3 row
+ * scale).  Synchronous, like dose_matrix_create; *out owns the device
+ * memory until dose_sell_destroy.  DOSE_ERR_UNSUPPORTED beyond 2^32 - 2 rows
+ * or 2^32 slices. */
+dose_status dose_sell_create(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf,
+                             int32_t sigma, void* hip_stream, dose_sell* out);
+
+dose_status dose_sell_info(dose_sell m, dose_sell_info_t* info);
+
+/* Kreutzer's layout on the host, values decoded to FP32: perm (n_rows) and
+ * width (n_chunks) as dose_sell_layout gives them; val, col (std_slots
+ * entries): entry j of the row at position c * 64 + i at
+ * 64 * (width_0 + ... + width_(c-1)) + 64 j + i, slots past the row's end
+ * 0 and column -1.  Synchronous. */
+dose_status dose_sell_decode(dose_sell m, int64_t* perm, int64_t* width, float* val, int32_t* col);
+
+/* DOSE_IDX_RUNS: the stored runs, read back from the device, by row of A (not
+ * by sorted position): run_ptr (host, n_rows + 1, [0] = 0), start and length
+ * (host, n_runs each): row i's columns are start[r], ..., start[r] +
+ * length[r] - 1 for r in [run_ptr[i], run_ptr[i + 1]), in order, each run
+ * maximal.  DOSE_ERR_INVALID_ARGUMENT for other index formats.  Synchronous. */
+dose_status dose_sell_runs(dose_sell m, int64_t* run_ptr, int32_t* start, int32_t* length);
+
+/* y = A x over the SELL-C-sigma form (the product of Listing 1 in another
+ * storage order).  x: device, n_cols FP32; y: device, n_rows FP32, every
+ * entry written (+0 for empty rows); both 4-byte aligned, not overlapping
+ * (else DOSE_ERR_INVALID_ARGUMENT).  Rows are summed in an order fixed by
+ * the layout (FP32; see the product kernel), so results repeat bit for bit
+ * and the three index formats give the same bits.  Asynchronous on
+ * hip_stream. */
+dose_status dose_sell_spmv(dose_sell m, const float* x, float* y, void* hip_stream);
+
+/* Frees the device memory after synchronising the device. */
+dose_status dose_sell_destroy(dose_sell m);
 
 const char* dose_status_string(dose_status s);
 const char* dose_last_error(void);

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import DoseError
 
-__all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
+__all__ = ["DoseError", "DoseMatrix", "SellMatrix", "sell_layout", "BatchPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
            "ScenarioObjective", "robust_seed",
            "csr_validate", "partition_preview", "byte_model", "DoseSpMV", "DoseObjective",
            "dose", "VALUE_FORMATS"]
@@ -25,7 +25,7 @@ __all__ = ["DoseError", "DoseMatrix", "BatchPlan", "spmv_batched", "objective", 
 VALUE_FORMATS = {"fp16": _lib.VAL_FP16, "bf16": _lib.VAL_BF16,
                  "fp8e4m3_rowscale": _lib.VAL_FP8E4M3_ROWSCALE, "fp32": _lib.VAL_FP32}
 VALUE_BYTES = {"fp16": 2, "bf16": 2, "fp8e4m3_rowscale": 1, "fp32": 4}
-INDEX_FORMATS = {"i32": _lib.IDX_I32, "u16": _lib.IDX_U16}
+INDEX_FORMATS = {"i32": _lib.IDX_I32, "u16": _lib.IDX_U16, "runs": _lib.IDX_RUNS}
 
 
 def _stream_handle(stream) -> int | None:
@@ -186,6 +186,99 @@ class DoseMatrix:
     def close(self) -> None:
         if self._h is not None:
             _lib.check(_lib.load().dose_matrix_destroy(self._h.value))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sell_layout(row_ptr, sigma: int):
+    """SELL-C-sigma layout the library builds (host only, C = 64): (perm,
+    width), perm[k] the row at sorted position k, width[c] the longest row of
+    chunk c."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    n = rp.size - 1
+    perm = np.empty(max(n, 1), np.int64)
+    width = np.empty(max((n + 63) // 64, 1), np.int64)
+    _lib.check(_lib.load().dose_sell_layout(rp.ctypes.data, n, int(sigma), perm.ctypes.data, width.ctypes.data))
+    return perm[:n], width[:(n + 63) // 64]
+
+
+class SellMatrix:
+    """A dose-deposition matrix in SELL-C-sigma storage (C = 64) on the
+    current HIP device: the same host CSR arrays and value/index formats as
+    :class:`DoseMatrix`, rows sorted by length inside windows of ``sigma``."""
+
+    def __init__(self, row_ptr, cols, vals, n_cols: int, value_format: str = "fp16", sigma: int = 256,
+                 index_format: str = "i32", stream=None):
+        if value_format not in VALUE_FORMATS:
+            raise ValueError(f"unknown value format {value_format!r}")
+        if index_format not in INDEX_FORMATS:
+            raise ValueError(f"unknown index format {index_format!r}")
+        self._h = None
+        c, keep = _csr_struct(row_ptr, cols, vals, n_cols)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().dose_sell_create(ctypes.byref(c), VALUE_FORMATS[value_format],
+                                                INDEX_FORMATS[index_format], int(sigma),
+                                                _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
+        self.value_format = value_format
+        self.index_format = index_format
+        self.sigma = int(sigma)
+        self.n_rows = int(c.n_rows)
+        self.n_cols = int(c.n_cols)
+        self.nnz = int(c.nnz)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    @property
+    def handle(self) -> int:
+        if self._h is None:
+            raise RuntimeError("matrix is closed")
+        return self._h.value
+
+    def info(self) -> dict:
+        inf = _lib.SellInfo()
+        _lib.check(_lib.load().dose_sell_info(self.handle, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in _lib.SellInfo._fields_}
+
+    def decode(self):
+        """(perm, width, val, col) in Kreutzer's column-major layout, values
+        decoded to FP32; padding slots hold 0 and column -1."""
+        inf = self.info()
+        perm = np.empty(max(self.n_rows, 1), np.int64)
+        width = np.empty(max(inf["n_chunks"], 1), np.int64)
+        val = np.empty(max(inf["std_slots"], 1), np.float32)
+        col = np.empty(max(inf["std_slots"], 1), np.int32)
+        _lib.check(_lib.load().dose_sell_decode(self.handle, perm.ctypes.data, width.ctypes.data,
+                                                val.ctypes.data, col.ctypes.data))
+        n = inf["std_slots"]
+        return perm[:self.n_rows], width[:inf["n_chunks"]], val[:n], col[:n]
+
+    def runs(self):
+        """Run-length indices (index format "runs") read back from the device,
+        by row: (run_ptr, start, length)."""
+        inf = self.info()
+        run_ptr = np.empty(self.n_rows + 1, np.int64)
+        start = np.empty(max(inf["n_runs"], 1), np.int32)
+        length = np.empty(max(inf["n_runs"], 1), np.int32)
+        _lib.check(_lib.load().dose_sell_runs(self.handle, run_ptr.ctypes.data, start.ctypes.data,
+                                              length.ctypes.data))
+        return run_ptr, start[:inf["n_runs"]], length[:inf["n_runs"]]
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """y = A x (FP32), asynchronous on the current (or given) stream."""
+        if y is None:
+            y = torch.empty(self.n_rows, dtype=torch.float32, device=x.device)
+        _lib.check(_lib.load().dose_sell_spmv(self.handle, _dev_ptr(x, self.n_cols, "x", self.device),
+                                              _dev_ptr(y, self.n_rows, "y", self.device), _stream_handle(stream)))
+        return y
+
+    def close(self) -> None:
+        if self._h is not None:
+            _lib.check(_lib.load().dose_sell_destroy(self._h.value))
             self._h = None
 
     def __del__(self):

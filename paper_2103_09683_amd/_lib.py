@@ -24,6 +24,7 @@ ERR_INTERNAL = -7
 VAL_FP16, VAL_BF16, VAL_FP8E4M3_ROWSCALE, VAL_FP32 = 1, 2, 3, 4
 IDX_I32 = 1
 IDX_U16 = 2
+IDX_RUNS = 3
 CREATE_TRANSPOSE = 1
 PART_A, PART_AT = 0, 1
 PLAN_AUTOTUNE = 1
@@ -54,6 +55,16 @@ class BatchItem(ctypes.Structure):
                 ("ldy", ctypes.c_int64)]
 
 
+class SellInfo(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("value_format", ctypes.c_int32), ("index_format", ctypes.c_int32),
+                ("chunk_rows", ctypes.c_int32), ("sigma", ctypes.c_int32),
+                ("n_chunks", ctypes.c_int64), ("n_groups", ctypes.c_int64),
+                ("n_groups_windowed", ctypes.c_int64), ("std_slots", ctypes.c_int64),
+                ("n_runs", ctypes.c_int64), ("stored_slots", ctypes.c_int64), ("device_bytes", ctypes.c_uint64),
+                ("spmv_bytes", ctypes.c_uint64), ("stream_bytes", ctypes.c_uint64)]
+
+
 # name -> (argtypes, restype); every entry point declared in include/dose.h
 _vp, _i32, _i64, _u32, _u64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
                                ctypes.c_uint64)
@@ -79,6 +90,13 @@ SIGNATURES = {
     "dose_probe_stream_read": ([_vp, _u64, _vp, _vp], _i32),
     "dose_probe_copy": ([_vp, _vp, _u64, _vp], _i32),
     "dose_partition_preview": ([_vp, _i64, _i32, _vp, _i64, ctypes.POINTER(_i64)], _i32),
+    "dose_sell_layout": ([_vp, _i64, _i32, _vp, _vp], _i32),
+    "dose_sell_create": ([ctypes.POINTER(CsrHost), _i32, _i32, _i32, _vp, ctypes.POINTER(_vp)], _i32),
+    "dose_sell_info": ([_vp, ctypes.POINTER(SellInfo)], _i32),
+    "dose_sell_decode": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "dose_sell_runs": ([_vp, _vp, _vp, _vp], _i32),
+    "dose_sell_spmv": ([_vp, _vp, _vp, _vp], _i32),
+    "dose_sell_destroy": ([_vp], _i32),
     "dose_status_string": ([_i32], ctypes.c_char_p),
     "dose_last_error": ([], ctypes.c_char_p),
 }

@@ -159,7 +159,8 @@ bool overflows(int vf, float v) {
 void validate_csr(const dose_csr_host* c, int vf, int xf) {
   if (!c) fail(DOSE_ERR_INVALID_ARGUMENT, "csr is null");
   if (vf != kFp16 && vf != kBf16 && vf != kFp8 && vf != kFp32) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown value format");
-  if (xf != DOSE_IDX_I32 && xf != DOSE_IDX_U16) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown index format");
+  if (xf != DOSE_IDX_I32 && xf != DOSE_IDX_U16 && xf != DOSE_IDX_RUNS)
+    fail(DOSE_ERR_INVALID_ARGUMENT, "unknown index format");
   if (c && xf == DOSE_IDX_U16 && c->n_cols > 65536) fail(DOSE_ERR_UNSUPPORTED, "16-bit indices need n_cols <= 65536");
   if (c->n_rows < 0 || c->n_cols < 0 || c->nnz < 0) fail(DOSE_ERR_INVALID_ARGUMENT, "negative size");
   if (c->n_rows >= (int64_t{1} << 32) - 1) fail(DOSE_ERR_UNSUPPORTED, "more than 2^32-2 rows");
@@ -822,6 +823,145 @@ int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std:
 
 }  // namespace
 
+namespace {
+// A's streams on the current device: validated host CSR uploaded, codes
+// encoded, indices padded; no partition yet.  Synchronous on s.
+std::unique_ptr<dose_matrix_s> upload_encode_A(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf,
+                                               hipStream_t s) {
+  auto m = std::make_unique<dose_matrix_s>();
+  HIP_CHECK(hipGetDevice(&m->device));
+  m->vf = vf;
+  m->xf = xf;
+  Operand& A = m->A;
+  A.n_rows = csr->n_rows;
+  A.n_cols = csr->n_cols;
+  A.nnz = csr->nnz;
+  A.h_row_ptr.assign(csr->row_ptr, csr->row_ptr + csr->n_rows + 1);
+  const int vb = value_bytes(vf);
+  A.val = DevBuf(padded(A.nnz) * vb);
+  A.idx_bytes = xf == DOSE_IDX_U16 ? 2 : 4;
+  A.col = DevBuf(padded(A.nnz) * A.idx_bytes);
+  if (m->vf == kFp8) m->row_scale = DevBuf(static_cast<size_t>(std::max<int64_t>(A.n_rows, 1)) * sizeof(float));
+  HIP_CHECK(hipMemsetAsync(A.val.get(), 0, A.val.bytes(), s));
+  HIP_CHECK(hipMemsetAsync(A.col.get(), 0, A.col.bytes(), s));
+  upload_row_ptr32(A, s);
+  if (A.nnz > 0 && A.idx_bytes == 4)
+    HIP_CHECK(hipMemcpyAsync(A.col.get(), csr->col_idx, static_cast<size_t>(A.nnz) * sizeof(int32_t),
+                             hipMemcpyHostToDevice, s));
+  if (A.nnz > 0 && A.idx_bytes == 2) {
+    // narrowed on the host in chunks (the indices were validated < 65536)
+    const int64_t chunk = int64_t{1} << 24;
+    std::vector<uint16_t> h(static_cast<size_t>(std::min<int64_t>(chunk, A.nnz)));
+    for (int64_t k0 = 0; k0 < A.nnz; k0 += chunk) {
+      const int64_t n = std::min<int64_t>(chunk, A.nnz - k0);
+      for (int64_t k = 0; k < n; ++k) h[k] = static_cast<uint16_t>(csr->col_idx[k0 + k]);
+      HIP_CHECK(hipMemcpyAsync(A.col.get<uint16_t>() + k0, h.data(), static_cast<size_t>(n) * 2,
+                               hipMemcpyHostToDevice, s));
+      HIP_CHECK(hipStreamSynchronize(s));  // h is reused
+    }
+  }
+  HIP_CHECK(launch_fill_pad(A.col.get(), A.idx_bytes, A.nnz, pad_entries(A.nnz), s));
+  encode_values(m.get(), csr, s);
+  return m;
+}
+}  // namespace
+
+namespace {
+
+// ------------------------------------------------------------ SELL-C-sigma
+// Host layout of SELL-C-sigma (C = 64): the sigma-sorted row order and the
+// chunks' widths, as Kreutzer et al. define them: rows in consecutive windows
+// of sigma rows, each window ordered by descending length (equal lengths keep
+// ascending row order), the sequence cut into chunks of 64 positions.
+struct SellLayout {
+  std::vector<uint32_t> perm;  // row at each position
+  std::vector<int64_t> width;  // longest row of each chunk
+};
+
+SellLayout sell_layout(const int64_t* rp, int64_t n_rows, int64_t sigma) {
+  SellLayout L;
+  L.perm.resize(static_cast<size_t>(n_rows));
+  const int64_t n_win = sigma > 0 ? (n_rows + sigma - 1) / sigma : 0;
+  auto work = [&](int64_t w_begin, int64_t w_end) {
+    for (int64_t w = w_begin; w < w_end; ++w) {
+      const int64_t r0 = w * sigma, r1 = std::min(n_rows, r0 + sigma);
+      for (int64_t r = r0; r < r1; ++r) L.perm[r] = static_cast<uint32_t>(r);
+      std::stable_sort(L.perm.begin() + r0, L.perm.begin() + r1, [&](uint32_t a, uint32_t b) {
+        return rp[a + 1] - rp[a] > rp[b + 1] - rp[b];
+      });
+    }
+  };
+  const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(16, n_win / 64));
+  if (parts == 1) {
+    work(0, n_win);
+  } else {
+    std::vector<std::thread> th;
+    for (int64_t p = 0; p < parts; ++p) th.emplace_back(work, n_win * p / parts, n_win * (p + 1) / parts);
+    for (auto& t : th) t.join();
+  }
+  const int64_t n_chunks = (n_rows + kSellC - 1) / kSellC;
+  L.width.assign(static_cast<size_t>(n_chunks), 0);
+  for (int64_t i = 0; i < n_rows; ++i) {
+    const uint32_t r = L.perm[i];
+    L.width[i / kSellC] = std::max(L.width[i / kSellC], rp[r + 1] - rp[r]);
+  }
+  return L;
+}
+
+// Most runs of one group of 256 row positions with run-length indices (the
+// group's runs are staged in LDS: 8 B each).
+constexpr int64_t kSellMaxGroupRuns = 2048;
+
+void check_sigma(int64_t sigma) {
+  if (sigma < 1 || sigma > INT32_MAX) fail(DOSE_ERR_INVALID_ARGUMENT, "sigma must be in [1, 2^31)");
+}
+
+}  // namespace
+
+struct dose_sell_s {
+  int device = 0;
+  int vf = 0, xf = 0;
+  int32_t sigma = 1;
+  int64_t n_rows = 0, n_cols = 0, nnz = 0;
+  int64_t n_chunks = 0;  // ceil(n_rows / 64)
+  int64_t n_groups = 0;  // ceil(n_chunks / 4); the chunk and position arrays are padded to whole groups
+  int64_t n_slices = 0, n_windowed = 0;
+  int64_t std_slots = 0;  // 64 * sum of the chunks' widths (Kreutzer's layout)
+  int32_t win_floats = 0, idx_bytes = 4;  // idx_bytes 0: run-length indices
+  int64_t n_runs = 0;
+  int32_t lds_runs = 0;  // most runs of one group
+  std::vector<SellChunk> h_chunks;
+  std::vector<uint32_t> h_perm, h_len;
+  std::vector<int64_t> h_width;
+  DevBuf val, col, chunks, win, perm, len, row_scale, run_ptr, runs;
+};
+
+namespace {
+
+SellArgs sell_args(const dose_sell_s* m, const float* x, float* y) {
+  SellArgs a{};
+  a.chunks = m->chunks.get<SellChunk>();
+  a.win = m->win.get<uint32_t>();
+  a.val = m->val.get();
+  a.col = m->col.get();
+  a.perm = m->perm.get<uint32_t>();
+  a.len = m->len.get<uint32_t>();
+  a.scale = m->vf == kFp8 ? m->row_scale.get<float>() : nullptr;
+  a.run_ptr = m->run_ptr.get<uint32_t>();
+  a.runs = m->runs.get<SellRun>();
+  a.x = x;
+  a.y = y;
+  a.n_groups = m->n_groups;
+  a.win_floats = m->win_floats;
+  a.idx_bytes = m->idx_bytes;
+  a.xcd_blocks = xcd_blocks();
+  a.lds_runs = m->lds_runs;
+  a.n_cols = static_cast<int32_t>(std::min<int64_t>(m->n_cols, INT32_MAX));
+  return a;
+}
+
+}  // namespace
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -866,42 +1006,11 @@ dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, d
   return guarded([&] {
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
     *out = nullptr;
+    if (xf == DOSE_IDX_RUNS) fail(DOSE_ERR_UNSUPPORTED, "run-length indices are a SELL-C-sigma format (dose_sell_create)");
     validate_csr(csr, vf, xf);
     hipStream_t s = as_stream(hip_stream);
-    auto m = std::make_unique<dose_matrix_s>();
-    HIP_CHECK(hipGetDevice(&m->device));
-    m->vf = vf;
-    m->xf = xf;
+    auto m = upload_encode_A(csr, vf, xf, s);
     Operand& A = m->A;
-    A.n_rows = csr->n_rows;
-    A.n_cols = csr->n_cols;
-    A.nnz = csr->nnz;
-    A.h_row_ptr.assign(csr->row_ptr, csr->row_ptr + csr->n_rows + 1);
-    const int vb = value_bytes(vf);
-    A.val = DevBuf(padded(A.nnz) * vb);
-    A.idx_bytes = xf == DOSE_IDX_U16 ? 2 : 4;
-    A.col = DevBuf(padded(A.nnz) * A.idx_bytes);
-    if (vf == kFp8) m->row_scale = DevBuf(static_cast<size_t>(std::max<int64_t>(A.n_rows, 1)) * sizeof(float));
-    HIP_CHECK(hipMemsetAsync(A.val.get(), 0, A.val.bytes(), s));
-    HIP_CHECK(hipMemsetAsync(A.col.get(), 0, A.col.bytes(), s));
-    upload_row_ptr32(A, s);
-    if (A.nnz > 0 && A.idx_bytes == 4)
-      HIP_CHECK(hipMemcpyAsync(A.col.get(), csr->col_idx, static_cast<size_t>(A.nnz) * sizeof(int32_t),
-                               hipMemcpyHostToDevice, s));
-    if (A.nnz > 0 && A.idx_bytes == 2) {
-      // narrowed on the host in chunks (the indices were validated < 65536)
-      const int64_t chunk = int64_t{1} << 24;
-      std::vector<uint16_t> h(static_cast<size_t>(std::min<int64_t>(chunk, A.nnz)));
-      for (int64_t k0 = 0; k0 < A.nnz; k0 += chunk) {
-        const int64_t n = std::min<int64_t>(chunk, A.nnz - k0);
-        for (int64_t k = 0; k < n; ++k) h[k] = static_cast<uint16_t>(csr->col_idx[k0 + k]);
-        HIP_CHECK(hipMemcpyAsync(A.col.get<uint16_t>() + k0, h.data(), static_cast<size_t>(n) * 2,
-                                 hipMemcpyHostToDevice, s));
-        HIP_CHECK(hipStreamSynchronize(s));  // h is reused
-      }
-    }
-    HIP_CHECK(launch_fill_pad(A.col.get(), A.idx_bytes, A.nnz, pad_entries(A.nnz), s));
-    encode_values(m.get(), csr, s);
     upload_partition(A, default_group_nnz(A.nnz, m->device), s);
     if (flags & DOSE_CREATE_TRANSPOSE) {
       build_transpose(m.get(), default_group_nnz(A.nnz, m->device), s);
@@ -1185,6 +1294,312 @@ dose_status dose_probe_copy(const void* src, void* dst, uint64_t bytes, void* hi
     if (!src || !dst) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
     if (overlaps(src, bytes, dst, bytes)) fail(DOSE_ERR_INVALID_ARGUMENT, "src and dst overlap");
     HIP_CHECK(launch_probe_copy(src, dst, bytes, as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_sell_layout(const int64_t* row_ptr, int64_t n_rows, int32_t sigma, int64_t* perm, int64_t* width) {
+  return guarded([&] {
+    if (!row_ptr || n_rows < 0 || (n_rows > 0 && (!perm || !width))) fail(DOSE_ERR_INVALID_ARGUMENT, "bad argument");
+    check_sigma(sigma);
+    if (n_rows > int64_t{0xFFFFFFFE}) fail(DOSE_ERR_UNSUPPORTED, "more than 2^32 - 2 rows");
+    for (int64_t i = 0; i < n_rows; ++i)
+      if (row_ptr[i + 1] < row_ptr[i]) fail(DOSE_ERR_BAD_CSR, "row_ptr decreases at row " + std::to_string(i));
+    SellLayout L = sell_layout(row_ptr, n_rows, sigma);
+    for (int64_t i = 0; i < n_rows; ++i) perm[i] = L.perm[i];
+    for (size_t c = 0; c < L.width.size(); ++c) width[c] = L.width[c];
+  });
+}
+
+dose_status dose_sell_create(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf, int32_t sigma,
+                             void* hip_stream, dose_sell* out) {
+  return guarded([&] {
+    if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    check_sigma(sigma);
+    validate_csr(csr, vf, xf);
+    const bool runs = xf == DOSE_IDX_RUNS;
+    hipStream_t s = as_stream(hip_stream);
+    const int64_t* rp = csr->row_ptr;
+    auto m = std::make_unique<dose_sell_s>();
+    HIP_CHECK(hipGetDevice(&m->device));
+    m->vf = vf;
+    m->xf = xf;
+    m->sigma = sigma;
+    m->n_rows = csr->n_rows;
+    m->n_cols = csr->n_cols;
+    m->nnz = csr->nnz;
+    m->idx_bytes = runs ? 0 : xf == DOSE_IDX_U16 ? 2 : 4;
+    SellLayout L = sell_layout(rp, csr->n_rows, sigma);
+    m->n_chunks = static_cast<int64_t>(L.width.size());
+    m->n_groups = (m->n_chunks + kSellGroupChunks - 1) / kSellGroupChunks;
+    if (m->n_groups > INT32_MAX) fail(DOSE_ERR_UNSUPPORTED, "too many chunks");
+    const int64_t n_pos = m->n_groups * kSellGroupRows, n_ch = m->n_groups * kSellGroupChunks;
+    // positions: row, length and first entry (padding positions: no row)
+    m->h_perm.assign(static_cast<size_t>(n_pos), 0xFFFFFFFFu);
+    m->h_len.assign(static_cast<size_t>(n_pos), 0u);
+    std::vector<uint64_t> start(static_cast<size_t>(n_pos), 0);
+    for (int64_t i = 0; i < m->n_rows; ++i) {
+      const uint32_t r = L.perm[i];
+      m->h_perm[i] = r;
+      m->h_len[i] = static_cast<uint32_t>(rp[r + 1] - rp[r]);
+      start[i] = static_cast<uint64_t>(rp[r]);
+    }
+    // chunks: slices and shortest row
+    m->h_chunks.assign(static_cast<size_t>(n_ch), SellChunk{});
+    m->h_width = L.width;
+    uint64_t slices = 0;
+    for (int64_t c = 0; c < n_ch; ++c) {
+      SellChunk& ch = m->h_chunks[c];
+      const int64_t w = c < m->n_chunks ? L.width[c] : 0;
+      m->std_slots += kSellC * w;
+      ch.slice0 = static_cast<uint32_t>(slices);
+      ch.n_slices = static_cast<uint32_t>((w + kSellLaneEntries - 1) / kSellLaneEntries);
+      uint32_t mn = 0xFFFFFFFFu;
+      for (int i = 0; i < kSellC; ++i) mn = std::min(mn, m->h_len[c * kSellC + i]);
+      ch.min_len = mn;
+      slices += ch.n_slices;
+      if (slices >= uint64_t{0xFFFFFFFF}) fail(DOSE_ERR_UNSUPPORTED, "SELL storage beyond 2^32 slices");
+    }
+    m->n_slices = static_cast<int64_t>(slices);
+    // group windows: every entry's column lies in [first column, last column]
+    // of its row (columns ascend), so the rows' ends bound the window
+    std::vector<uint32_t> win(static_cast<size_t>(2 * m->n_groups), 0u), pad_col(static_cast<size_t>(m->n_groups), 0u);
+    const int64_t cap = window_cap_floats();
+    int64_t wf = 0;
+    for (int64_t g = 0; g < m->n_groups; ++g) {
+      int64_t lo = INT64_MAX, hi = -1;
+      for (int64_t i = g * kSellGroupRows; i < (g + 1) * kSellGroupRows; ++i) {
+        if (m->h_len[i] == 0) continue;
+        const uint32_t r = m->h_perm[i];
+        lo = std::min<int64_t>(lo, csr->col_idx[rp[r]]);
+        hi = std::max<int64_t>(hi, csr->col_idx[rp[r + 1] - 1]);
+      }
+      if (hi < 0) continue;
+      const int64_t cmin = lo & ~int64_t{kWinAlign - 1};
+      const int64_t clen = hi - cmin + 1;
+      win[2 * g] = static_cast<uint32_t>(cmin);
+      win[2 * g + 1] = static_cast<uint32_t>(clen);
+      pad_col[g] = static_cast<uint32_t>(cmin);
+      if (clen <= cap) {
+        ++m->n_windowed;
+        wf = std::max(wf, clen);
+      }
+    }
+    m->win_floats = static_cast<int32_t>((wf + 3) / 4 * 4);
+    // run-length indices: every position's maximal runs of consecutive
+    // columns, as (end position in the row, column - position)
+    std::vector<uint32_t> h_run_ptr;
+    std::vector<SellRun> h_runs;
+    if (runs) {
+      std::vector<uint64_t> cnt(static_cast<size_t>(n_pos) + 1, 0);
+      for (int64_t i = 0; i < m->n_rows; ++i) {
+        const uint32_t r = m->h_perm[i];
+        uint64_t n = rp[r + 1] > rp[r] ? 1 : 0;
+        for (int64_t k = rp[r] + 1; k < rp[r + 1]; ++k) n += csr->col_idx[k] != csr->col_idx[k - 1] + 1;
+        cnt[i + 1] = n;
+      }
+      for (int64_t i = 0; i < n_pos; ++i) cnt[i + 1] += cnt[i];
+      if (cnt[n_pos] >= uint64_t{0xFFFFFFFF}) fail(DOSE_ERR_UNSUPPORTED, "more than 2^32 - 2 runs");
+      m->n_runs = static_cast<int64_t>(cnt[n_pos]);
+      h_run_ptr.assign(cnt.begin(), cnt.end());
+      h_runs.resize(static_cast<size_t>(std::max<int64_t>(m->n_runs, 1)));
+      for (int64_t i = 0; i < m->n_rows; ++i) {
+        const uint32_t r = m->h_perm[i];
+        uint64_t o = cnt[i];
+        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+          const int32_t pos = static_cast<int32_t>(k - rp[r]);
+          if (k > rp[r] && csr->col_idx[k] == csr->col_idx[k - 1] + 1) {
+            h_runs[o - 1].end = pos + 1;
+          } else {
+            h_runs[o].end = pos + 1;
+            h_runs[o].delta = csr->col_idx[k] - pos;
+            ++o;
+          }
+        }
+      }
+      for (int64_t g = 0; g < m->n_groups; ++g) {
+        const int64_t nr = static_cast<int64_t>(cnt[(g + 1) * kSellGroupRows] - cnt[g * kSellGroupRows]);
+        if (nr > kSellMaxGroupRuns)
+          fail(DOSE_ERR_UNSUPPORTED, "run-length indices: more than " + std::to_string(kSellMaxGroupRuns) +
+                                         " runs in 256 rows of the sorted order");
+        m->lds_runs = std::max<int32_t>(m->lds_runs, static_cast<int32_t>(nr));
+      }
+    }
+    // device: A's CSR streams, then the scatter into the slice layout
+    auto A = upload_encode_A(csr, vf, runs ? DOSE_IDX_I32 : xf, s);
+    const int vb = value_bytes(vf);
+    const size_t n_ent = static_cast<size_t>(m->n_slices + 1) * kSellSliceEntries;
+    m->val = DevBuf(n_ent * vb);
+    m->col = DevBuf(n_ent * m->idx_bytes);
+    if (runs) {
+      m->run_ptr = DevBuf(h_run_ptr.size() * sizeof(uint32_t));
+      m->runs = DevBuf(h_runs.size() * sizeof(SellRun));
+      HIP_CHECK(hipMemcpyAsync(m->run_ptr.get(), h_run_ptr.data(), m->run_ptr.bytes(), hipMemcpyHostToDevice, s));
+      HIP_CHECK(hipMemcpyAsync(m->runs.get(), h_runs.data(), m->runs.bytes(), hipMemcpyHostToDevice, s));
+    }
+    m->chunks = DevBuf(m->h_chunks.size() * sizeof(SellChunk));
+    m->win = DevBuf(win.size() * sizeof(uint32_t));
+    m->perm = DevBuf(static_cast<size_t>(n_pos) * sizeof(uint32_t));
+    m->len = DevBuf(static_cast<size_t>(n_pos) * sizeof(uint32_t));
+    DevBuf d_start(static_cast<size_t>(n_pos) * sizeof(uint64_t)), d_pad(pad_col.size() * sizeof(uint32_t));
+    HIP_CHECK(hipMemsetAsync(m->val.get(), 0, m->val.bytes(), s));
+    HIP_CHECK(hipMemsetAsync(m->col.get(), 0, m->col.bytes(), s));
+    HIP_CHECK(hipMemcpyAsync(m->chunks.get(), m->h_chunks.data(), m->chunks.bytes(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(m->win.get(), win.data(), m->win.bytes(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(m->perm.get(), m->h_perm.data(), m->perm.bytes(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(m->len.get(), m->h_len.data(), m->len.bytes(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(d_start.get(), start.data(), d_start.bytes(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(d_pad.get(), pad_col.data(), d_pad.bytes(), hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_sell_pack(vf, runs ? 4 : m->idx_bytes, m->chunks.get<SellChunk>(), n_ch, d_start.get<uint64_t>(),
+                               m->len.get<uint32_t>(), d_pad.get<uint32_t>(), A->A.val.get(), A->A.col.get(),
+                               m->val.get(), runs ? nullptr : m->col.get(), s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    m->row_scale = std::move(A->row_scale);
+    *out = m.release();
+  });
+}
+
+dose_status dose_sell_info(dose_sell m, dose_sell_info_t* info) {
+  return guarded([&] {
+    if (!m || !info) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_rows = m->n_rows;
+    info->n_cols = m->n_cols;
+    info->nnz = m->nnz;
+    info->value_format = m->vf;
+    info->index_format = m->xf;
+    info->chunk_rows = kSellC;
+    info->sigma = m->sigma;
+    info->n_chunks = m->n_chunks;
+    info->n_groups = m->n_groups;
+    info->n_groups_windowed = m->n_windowed;
+    info->std_slots = m->std_slots;
+    info->n_runs = m->n_runs;
+    info->stored_slots = m->n_slices * kSellSliceEntries;
+    info->device_bytes = m->val.bytes() + m->col.bytes() + m->chunks.bytes() + m->win.bytes() + m->perm.bytes() +
+                         m->len.bytes() + m->row_scale.bytes() + m->run_ptr.bytes() + m->runs.bytes();
+    const uint64_t per = static_cast<uint64_t>(value_bytes(m->vf)) + static_cast<uint64_t>(m->idx_bytes);
+    const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
+    const uint64_t nr = static_cast<uint64_t>(m->n_rows), nc = static_cast<uint64_t>(m->n_cols);
+    const uint64_t run_b = 8 * static_cast<uint64_t>(m->n_runs);
+    info->spmv_bytes = static_cast<uint64_t>(m->nnz) * per + run_b + (nr + 1) * 4 + nr * scale_b + 4 * nc + 4 * nr;
+    info->stream_bytes = static_cast<uint64_t>(info->stored_slots) * per + nr * 8 + (m->idx_bytes ? 0 : run_b + nr * 4) +
+                         nr * scale_b + 4 * nc + 4 * nr;
+  });
+}
+
+dose_status dose_sell_decode(dose_sell m, int64_t* perm, int64_t* width, float* val, int32_t* col) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    if (m->n_rows > 0 && (!perm || !width)) fail(DOSE_ERR_INVALID_ARGUMENT, "null perm or width");
+    if (m->std_slots > 0 && (!val || !col)) fail(DOSE_ERR_INVALID_ARGUMENT, "null val or col");
+    for (int64_t i = 0; i < m->n_rows; ++i) perm[i] = m->h_perm[i];
+    for (int64_t c = 0; c < m->n_chunks; ++c) width[c] = m->h_width[c];
+    if (m->std_slots == 0) return;
+    DeviceGuard g(m->device);
+    const size_t n_ent = static_cast<size_t>(m->n_slices) * kSellSliceEntries;
+    DevBuf dec(n_ent * sizeof(float));
+    HIP_CHECK(launch_sell_decode(m->vf, m->chunks.get<SellChunk>(), m->n_groups * kSellGroupChunks,
+                                 m->perm.get<uint32_t>(), m->len.get<uint32_t>(), m->val.get(),
+                                 m->row_scale.get<float>(), dec.get<float>(), nullptr));
+    HIP_CHECK(hipDeviceSynchronize());
+    std::vector<float> hv(n_ent);
+    HIP_CHECK(hipMemcpy(hv.data(), dec.get(), n_ent * sizeof(float), hipMemcpyDeviceToHost));
+    std::vector<int32_t> hc(n_ent);
+    if (m->idx_bytes == 0) {
+      // columns from the device's runs: position + delta of the run holding it
+      std::vector<uint32_t> hrp(static_cast<size_t>(m->n_groups) * kSellGroupRows + 1);
+      std::vector<SellRun> hr(static_cast<size_t>(std::max<int64_t>(m->n_runs, 1)));
+      HIP_CHECK(hipMemcpy(hrp.data(), m->run_ptr.get(), hrp.size() * 4, hipMemcpyDeviceToHost));
+      HIP_CHECK(hipMemcpy(hr.data(), m->runs.get(), hr.size() * sizeof(SellRun), hipMemcpyDeviceToHost));
+      for (int64_t c = 0; c < m->n_chunks; ++c)
+        for (int i = 0; i < kSellC; ++i) {
+          const int64_t p = c * kSellC + i;
+          uint32_t q = hrp[p];
+          for (uint32_t j = 0; j < m->h_len[p]; ++j) {
+            while (q + 1 < hrp[p + 1] && static_cast<int64_t>(j) >= hr[q].end) ++q;
+            const size_t dst = (static_cast<size_t>(m->h_chunks[c].slice0) + j / kSellLaneEntries) * kSellSliceEntries +
+                               static_cast<size_t>(i) * kSellLaneEntries + j % kSellLaneEntries;
+            hc[dst] = static_cast<int32_t>(j) + hr[q].delta;
+          }
+        }
+    } else if (m->idx_bytes == 4) {
+      HIP_CHECK(hipMemcpy(hc.data(), m->col.get(), n_ent * 4, hipMemcpyDeviceToHost));
+    } else {
+      std::vector<uint16_t> h16(n_ent);
+      HIP_CHECK(hipMemcpy(h16.data(), m->col.get(), n_ent * 2, hipMemcpyDeviceToHost));
+      for (size_t k = 0; k < n_ent; ++k) hc[k] = h16[k];
+    }
+    // Kreutzer's layout: entry j of the row at chunk position i at
+    // off_c + j * 64 + i; slots past the row's end hold 0 and column -1
+    int64_t off = 0;
+    for (int64_t c = 0; c < m->n_chunks; ++c) {
+      const SellChunk& ch = m->h_chunks[c];
+      for (int64_t j = 0; j < m->h_width[c]; ++j)
+        for (int i = 0; i < kSellC; ++i) {
+          const int64_t slot = off + j * kSellC + i;
+          const uint32_t L = m->h_len[c * kSellC + i];
+          const size_t src = (static_cast<size_t>(ch.slice0) + static_cast<size_t>(j / kSellLaneEntries)) *
+                                 kSellSliceEntries + static_cast<size_t>(i) * kSellLaneEntries +
+                             static_cast<size_t>(j % kSellLaneEntries);
+          val[slot] = j < L ? hv[src] : 0.0f;
+          col[slot] = j < L ? hc[src] : -1;
+        }
+      off += kSellC * m->h_width[c];
+    }
+  });
+}
+
+dose_status dose_sell_runs(dose_sell m, int64_t* run_ptr, int32_t* start, int32_t* length) {
+  return guarded([&] {
+    if (!m || !run_ptr) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
+    if (m->idx_bytes != 0) fail(DOSE_ERR_INVALID_ARGUMENT, "the matrix has no run-length indices");
+    if (m->n_runs > 0 && (!start || !length)) fail(DOSE_ERR_INVALID_ARGUMENT, "null start or length");
+    DeviceGuard g(m->device);
+    std::vector<uint32_t> hrp(static_cast<size_t>(m->n_groups) * kSellGroupRows + 1);
+    std::vector<SellRun> hr(static_cast<size_t>(std::max<int64_t>(m->n_runs, 1)));
+    HIP_CHECK(hipMemcpy(hrp.data(), m->run_ptr.get(), hrp.size() * 4, hipMemcpyDeviceToHost));
+    HIP_CHECK(hipMemcpy(hr.data(), m->runs.get(), hr.size() * sizeof(SellRun), hipMemcpyDeviceToHost));
+    // by row: position p holds row h_perm[p]
+    std::vector<int64_t> pos_of(static_cast<size_t>(m->n_rows));
+    for (int64_t p = 0; p < m->n_rows; ++p) pos_of[m->h_perm[p]] = p;
+    run_ptr[0] = 0;
+    for (int64_t r = 0; r < m->n_rows; ++r) {
+      const int64_t p = pos_of[r];
+      int64_t o = run_ptr[r];
+      int32_t begin = 0;
+      for (uint32_t q = hrp[p]; q < hrp[p + 1]; ++q) {
+        start[o] = begin + hr[q].delta;
+        length[o] = hr[q].end - begin;
+        begin = hr[q].end;
+        ++o;
+      }
+      run_ptr[r + 1] = o;
+    }
+  });
+}
+
+dose_status dose_sell_spmv(dose_sell m, const float* x, float* y, void* hip_stream) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    if ((m->n_cols > 0 && !x) || (m->n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
+    if (overlaps(x, m->n_cols * 4, y, m->n_rows * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 4 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be 4-byte aligned");
+    DeviceGuard g(m->device);
+    HIP_CHECK(launch_sell_spmv(m->vf, m->vf == kFp8 ? kScaleRow : kScaleNone, sell_args(m, x, y),
+                               as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_sell_destroy(dose_sell m) {
+  return guarded([&] {
+    if (!m) return;
+    {
+      DeviceGuard g(m->device);
+      (void)hipDeviceSynchronize();
+    }
+    delete m;
   });
 }
 

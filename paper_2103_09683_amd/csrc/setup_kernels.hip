@@ -161,6 +161,78 @@ __global__ void k_row_ptr_from_sorted(const uint32_t* __restrict__ keys, int64_t
 
 unsigned blocks_for(int64_t n, int per) { return static_cast<unsigned>((n + per - 1) / per); }
 
+// SELL-C-sigma slice layout (dose_internal.h): one 64-thread block per
+// chunk, thread i = the row at chunk position i, writing its 8 entries of
+// every slice of the chunk.  Entries past the row's end get code 0 and the
+// group's padding column.
+template <typename C, typename I>
+__global__ __launch_bounds__(64) void k_sell_pack(const SellChunk* __restrict__ chunks,
+                                                  const uint64_t* __restrict__ start,
+                                                  const uint32_t* __restrict__ len,
+                                                  const uint32_t* __restrict__ pad_col,
+                                                  const C* __restrict__ codes_in, const I* __restrict__ col_in,
+                                                  C* __restrict__ codes_out, I* __restrict__ col_out) {
+  const int64_t c = blockIdx.x;
+  const int i = static_cast<int>(threadIdx.x);
+  const int64_t pos = c * kSellC + i;
+  const SellChunk ch = chunks[c];
+  const uint32_t L = len[pos];
+  const uint64_t b = start[pos];
+  const I pad = col_out ? static_cast<I>(pad_col[c / kSellGroupChunks]) : I(0);
+  for (uint32_t sl = 0; sl < ch.n_slices; ++sl) {
+    const uint64_t o = (static_cast<uint64_t>(ch.slice0) + sl) * kSellSliceEntries + static_cast<uint64_t>(i) * kSellLaneEntries;
+    for (int e = 0; e < kSellLaneEntries; ++e) {
+      const uint32_t j = sl * kSellLaneEntries + static_cast<uint32_t>(e);
+      codes_out[o + e] = j < L ? codes_in[b + j] : C(0);
+      if (col_out) col_out[o + e] = j < L ? col_in[b + j] : pad;
+    }
+  }
+}
+
+// Decoded values of the slice layout: code times its row's scale (E4M3),
+// 0 in padding slots.
+template <int VF>
+__global__ __launch_bounds__(64) void k_sell_decode(const SellChunk* __restrict__ chunks,
+                                                    const uint32_t* __restrict__ perm,
+                                                    const uint32_t* __restrict__ len,
+                                                    const void* __restrict__ codes,
+                                                    const float* __restrict__ row_scale, float* __restrict__ out) {
+  const int64_t c = blockIdx.x;
+  const int i = static_cast<int>(threadIdx.x);
+  const int64_t pos = c * kSellC + i;
+  const SellChunk ch = chunks[c];
+  const uint32_t L = len[pos];
+  const float sc = VF == kFp8 && L > 0 ? row_scale[perm[pos]] : 1.0f;
+  for (uint32_t sl = 0; sl < ch.n_slices; ++sl) {
+    const uint64_t o = (static_cast<uint64_t>(ch.slice0) + sl) * kSellSliceEntries + static_cast<uint64_t>(i) * kSellLaneEntries;
+    for (int e = 0; e < kSellLaneEntries; ++e) {
+      const uint32_t j = sl * kSellLaneEntries + static_cast<uint32_t>(e);
+      float d = 0.0f;
+      if (j < L) {
+        d = dec_code(VF, codes, o + e);
+        if (VF == kFp8) d = d * sc;
+      }
+      out[o + e] = d;
+    }
+  }
+}
+
+template <typename C>
+hipError_t sell_pack_ix(int idx_bytes, const SellChunk* chunks, int64_t n_chunks, const uint64_t* start,
+                        const uint32_t* len, const uint32_t* pad_col, const void* codes_in, const void* col_in,
+                        void* codes_out, void* col_out, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(n_chunks)), block(kSellC);
+  if (idx_bytes == 2)
+    hipLaunchKernelGGL((k_sell_pack<C, uint16_t>), grid, block, 0, s, chunks, start, len, pad_col,
+                       static_cast<const C*>(codes_in), static_cast<const uint16_t*>(col_in),
+                       static_cast<C*>(codes_out), static_cast<uint16_t*>(col_out));
+  else
+    hipLaunchKernelGGL((k_sell_pack<C, int32_t>), grid, block, 0, s, chunks, start, len, pad_col,
+                       static_cast<const C*>(codes_in), static_cast<const int32_t*>(col_in),
+                       static_cast<C*>(codes_out), static_cast<int32_t*>(col_out));
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_encode_rows(int vf, const uint32_t* row_ptr, uint32_t base, int64_t n_rows, const float* src,
@@ -241,6 +313,37 @@ hipError_t radix_sort_pairs(void* tmp, size_t* tmp_bytes, const uint32_t* keys_i
                             const uint32_t* vals_in, uint32_t* vals_out, int64_t n, int end_bit, hipStream_t s) {
   return hipcub::DeviceRadixSort::SortPairs(tmp, *tmp_bytes, keys_in, keys_out, vals_in, vals_out,
                                             static_cast<int>(n), 0, end_bit, s);
+}
+
+hipError_t launch_sell_pack(int vf, int idx_bytes, const SellChunk* chunks, int64_t n_chunks, const uint64_t* start,
+                            const uint32_t* len, const uint32_t* pad_col, const void* codes_in, const void* col_in,
+                            void* codes_out, void* col_out, hipStream_t s) {
+  if (n_chunks <= 0) return hipSuccess;
+  if (n_chunks > INT32_MAX) return hipErrorInvalidValue;
+  if (vf == kFp8)
+    return sell_pack_ix<uint8_t>(idx_bytes, chunks, n_chunks, start, len, pad_col, codes_in, col_in, codes_out,
+                                 col_out, s);
+  if (vf == kFp32)
+    return sell_pack_ix<uint32_t>(idx_bytes, chunks, n_chunks, start, len, pad_col, codes_in, col_in, codes_out,
+                                  col_out, s);
+  return sell_pack_ix<uint16_t>(idx_bytes, chunks, n_chunks, start, len, pad_col, codes_in, col_in, codes_out,
+                                col_out, s);
+}
+
+hipError_t launch_sell_decode(int vf, const SellChunk* chunks, int64_t n_chunks, const uint32_t* perm,
+                              const uint32_t* len, const void* codes, const float* row_scale, float* out,
+                              hipStream_t s) {
+  if (n_chunks <= 0) return hipSuccess;
+  if (n_chunks > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(n_chunks)), block(kSellC);
+  switch (vf) {
+    case kFp16: hipLaunchKernelGGL(k_sell_decode<kFp16>, grid, block, 0, s, chunks, perm, len, codes, row_scale, out); break;
+    case kBf16: hipLaunchKernelGGL(k_sell_decode<kBf16>, grid, block, 0, s, chunks, perm, len, codes, row_scale, out); break;
+    case kFp8: hipLaunchKernelGGL(k_sell_decode<kFp8>, grid, block, 0, s, chunks, perm, len, codes, row_scale, out); break;
+    case kFp32: hipLaunchKernelGGL(k_sell_decode<kFp32>, grid, block, 0, s, chunks, perm, len, codes, row_scale, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace dose
