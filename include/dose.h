@@ -277,6 +277,23 @@ dose_status dose_scenario_objective(int32_t n_scen, int32_t n_beams, int64_t n, 
                                     const float* p, const float* w, const double* prob, float* d_out,
                                     float* seed, double* out, void* hip_stream);
 
+/* The same epilogue for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * partial sums live in a library-owned static device array of 65,536 doubles
+ * (512 KB, one per device, held until the process ends) instead of the
+ * stream-ordered allocation; nothing is allocated, on the device or the host.
+ * Limit: n_scen * p <= 65,536 with p = min(1024, max(1, ceil(n / 4096)))
+ * partial sums per scenario (at most 64 scenarios for n above 4,190,208
+ * voxels), else DOSE_ERR_INVALID_ARGUMENT.  Results are bit for bit those of
+ * dose_scenario_objective.  Every call on one device shares the array, so
+ * calls that overlap on one device (on different streams, or from different
+ * threads) race and must be ordered by the caller; each call rewrites every
+ * partial sum it reads, so nothing carries over from an earlier call.  Other
+ * arguments and errors as for dose_scenario_objective.  Asynchronous. */
+dose_status dose_scenario_objective_noalloc(int32_t n_scen, int32_t n_beams, int64_t n, const float* part,
+                                            const float* p, const float* w, const double* prob,
+                                            float* d_out, float* seed, double* out, void* hip_stream);
+
 /* out = sqrt(sum_j g_j^2) in FP64, fixed-order two-pass reduction: the size
  * of the gradient an optimiser needs every iteration (Sec. I).
  * g: device, n FP32.  out: device, one double.  Asynchronous on hip_stream

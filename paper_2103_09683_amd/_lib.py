@@ -87,6 +87,7 @@ SIGNATURES = {
     "dose_norm2": ([_i64, _vp, _vp, _vp], _i32),
     "dose_robust_seed": ([_i32, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_scenario_objective": ([_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "dose_scenario_objective_noalloc": ([_i32, _i32, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_probe_stream_read": ([_vp, _u64, _vp, _vp], _i32),
     "dose_probe_copy": ([_vp, _vp, _u64, _vp], _i32),
     "dose_partition_preview": ([_vp, _i64, _i32, _vp, _i64, ctypes.POINTER(_i64)], _i32),

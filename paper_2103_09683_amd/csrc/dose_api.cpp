@@ -962,6 +962,37 @@ SellArgs sell_args(const dose_sell_s* m, const float* x, float* y) {
 
 }  // namespace
 
+// ------------------------------------------------ static scratch (no allocation)
+// The partial sums of dose_scenario_objective_noalloc live in this array:
+// each device that runs the library holds its own copy until the process
+// ends.  Host code must not pass the array's name to a kernel (on the host
+// it is a stand-in, not a device address): its address on each device comes
+// from hipGetSymbolAddress, taken once per device with that device current.
+constexpr int64_t kScratchDoubles = 65536;  // 512 KB: 64 scenarios x 1024 partial sums
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on the current device (looked up once per
+// device; the lookup allocates nothing).
+double* scratch_on_current_device() {
+  int dev = 0;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(DOSE_ERR_UNSUPPORTED, "device ordinal beyond 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) fail(DOSE_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -1237,6 +1268,23 @@ dose_status dose_scenario_objective(int32_t n_scen, int32_t n_beams, int64_t n, 
     hipError_t e = launch_scenario(n_scen, n_beams, n, part, p, w, prob, d_out, seed, partial, np, out, s);
     (void)hipFreeAsync(partial, s);
     HIP_CHECK(e);
+  });
+}
+
+dose_status dose_scenario_objective_noalloc(int32_t n_scen, int32_t n_beams, int64_t n, const float* part,
+                                            const float* p, const float* w, const double* prob, float* d_out,
+                                            float* seed, double* out, void* hip_stream) {
+  return guarded([&] {
+    check_scenario_args(n_scen, n_beams, n, part, p, w, prob, d_out, seed, out);
+    const int np = n_partial_for(n);
+    if (static_cast<int64_t>(np) * n_scen > kScratchDoubles)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "n_scen * partial sums exceed the static scratch (65,536 doubles: at most 64 "
+                                      "scenarios, or more when n is small)");
+    double* partial = scratch_on_current_device();
+    // every partial sum the second pass reads is written by the first, so
+    // nothing needs clearing between calls
+    HIP_CHECK(launch_scenario(n_scen, n_beams, n, part, p, w, prob, d_out, seed, partial, np, out,
+                              as_stream(hip_stream)));
   });
 }
 
