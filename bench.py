@@ -40,7 +40,7 @@ METRIC = "dose SpMV GNNZ/s and % HBM roofline, plain vs batched/adjoint at rel e
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_spmv_f64_sweep_large_fp16.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2103_09683_amd", "csrc", f)
-                  for f in ("spmv_kernels.hip", "dose_internal.h", "dose_api.cpp")]
+                  for f in ("spmv_kernels.hip", "dose_internal.h")]
 
 
 def _code_only(text: str) -> str:
@@ -354,6 +354,11 @@ def main(argv=None):
                     help="only time the robust-plan epilogue on the full 1,048,576-voxel grid")
     ap.add_argument("--robust-step", action="store_true",
                     help="only time the robust-plan step (9 scenarios x 4 beams, then the epilogue)")
+    ap.add_argument("--sell-sigmas", default="1024,4096,16384", help="sigmas of the SELL-C-sigma variants")
+    ap.add_argument("--sell-index", default="i32,u16,runs", help="index formats of the SELL-C-sigma variants")
+    ap.add_argument("--part", choices=["clinical", "adjoint", "batched", "sell"],
+                    help="only one part: the clinical-beam variants, the clinical-beam adjoint, the full-size "
+                         "batched robust scenarios, or the SELL-C-sigma variants on the clinical beam")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -383,6 +388,9 @@ def main(argv=None):
     if args.robust_step:
         print(json.dumps({"robust_scenarios": bench_scenarios(torch, dm, dosegen, args)}))
         return
+    if args.part:
+        print(json.dumps({args.part: bench_part(torch, dm, dosegen, args)}))
+        return
 
     out, spec, A, rp, cols, vals, x_h, y64 = bench_headline(torch, dm, dosegen, args)
     y_h = y64.cpu().numpy()
@@ -402,6 +410,34 @@ def main(argv=None):
         out["cpu_baseline"] = cpu_baseline(spec, rp, cols, vals, x_h, y_h, args.cpu_budget)
         out["cpu_baseline"]["gpu_over_cpu"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out))
+
+
+def bench_part(torch, dm, dosegen, args):
+    """One part of the bench alone (for profiling runs)."""
+    if args.part == "clinical":
+        return bench_clinical(torch, dm, dosegen, args)
+    if args.part == "batched":
+        return bench_batched(torch, dm, dosegen, args)
+    spec = dosegen.clinical_beam()
+    rp, cols, vals = dosegen.csr(spec)
+    x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
+    if args.part == "sell":
+        A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16")
+        y = A.spmv(x)
+        A.close()
+        return bench_sell(torch, dm, spec, rp, cols, vals, x, y, args)
+    # the adjoint of the clinical beam (FP16, FP32 vectors)
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", transpose=True)
+    info = A.info()
+    v = torch.from_numpy(dosegen.signed_values(spec.seed, 1, spec.n_rows)).cuda()
+    g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
+    ms = time_launches(lambda: A.adjoint(v, g), args.steps, args.warmup)
+    A.close()
+    gbps = info["adjoint_bytes"] / (ms * 1e-3) / 1e9
+    return {"workload": spec.name, "ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
+            "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "algorithmic_bytes_per_launch": info["adjoint_bytes"], "n_groups_t": info["n_groups_t"],
+            "n_groups_t_split": info["n_groups_split_t"]}
 
 
 def bench_u16(torch, dm, spec, rp, cols, vals, x, y, args):
@@ -455,7 +491,7 @@ def bench_single(torch, dm, spec, rp, cols, vals, x, y, args):
             "algorithmic_bytes_per_launch": info["spmv_bytes"]}
 
 
-def bench_sell(torch, dm, spec, rp, cols, vals, x, y_csr, args, sigmas=(256, 4096)):
+def bench_sell(torch, dm, spec, rp, cols, vals, x, y_csr, args):
     """SELL-C-sigma storage (C = 64; the format the paper names as the next
     to try, Sec. II-C, VII) of the same matrix, FP16 values, int32, 16-bit and
     run-length column indices: GNNZ/s, the fraction of 8 TB/s of the
@@ -464,8 +500,8 @@ def bench_sell(torch, dm, spec, rp, cols, vals, x, y_csr, args, sigmas=(256, 409
     records), and the largest relative difference from the CSR dose (both are
     within 1e-5 of the oracle)."""
     res = {}
-    for sigma in sigmas:
-        for idx in ("i32", "u16", "runs"):
+    for sigma in [int(v) for v in args.sell_sigmas.split(",")]:
+        for idx in args.sell_index.split(","):
             S = dm.SellMatrix(rp, cols, vals, spec.n_cols, "fp16", sigma=sigma, index_format=idx)
             info = S.info()
             ys = torch.empty_like(y_csr)

@@ -72,10 +72,9 @@ typedef enum {
   DOSE_IDX_RUNS = 3 /* run-length column indices, SELL-C-sigma only: each row's
                        columns as its maximal runs of consecutive columns (a
                        dose row holds a few: the spots of a scanline, Sec. II-B),
-                       8 B per run instead of 2 or 4 B per entry; at most 2048
-                       runs per 256 rows of the sorted order (else
-                       DOSE_ERR_UNSUPPORTED); dose_matrix_create refuses it
-                       (DOSE_ERR_UNSUPPORTED) */
+                       8 B per run instead of 2 or 4 B per entry; at most 1024
+                       runs per chunk of 64 rows (else DOSE_ERR_UNSUPPORTED);
+                       dose_matrix_create refuses it (DOSE_ERR_UNSUPPORTED) */
 } dose_index_format;
 
 /* dose_matrix_create flags */

@@ -25,6 +25,7 @@
 
 #include "../../include/dose.h"
 #include "dose_internal.h"
+#include "sell_internal.h"
 
 using namespace dose;
 
@@ -380,13 +381,17 @@ namespace {
 int scale_mode_A(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleRow : kScaleNone; }
 int scale_mode_AT(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleCol : kScaleNone; }
 
-// Dies of the chip that workgroups are dealt to in turn (DOSE_XCD_BLOCKS,
-// default 8 for the MI355X's eight XCDs; 1 turns the regrouping off).  Only
-// the order in which groups are dispatched depends on it, never a result.
+// Dies of the chip that workgroups are dealt to in turn (DOSE_XCD_BLOCKS:
+// 8, the MI355X's eight XCDs, gives each die a contiguous eighth of the row
+// groups so that its L2 sees an eighth of x; default 1, dispatch order).
+// Only the order in which groups are dispatched depends on it, never a
+// result.  Regrouping measured slower: the largest workload's half/double
+// product 1.690 ms against 1.648 ms, the clinical beam's adjoint 0.80 ms
+// against 0.69 ms; products on A^T never regroup.
 int xcd_blocks() {
   static const int d = [] {
     const char* e = std::getenv("DOSE_XCD_BLOCKS");
-    const int v = e ? std::atoi(e) : 8;
+    const int v = e ? std::atoi(e) : 1;
     return std::max(1, std::min(64, v));
   }();
   return d;
@@ -406,7 +411,7 @@ SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, const Partition& P
   a.x = x;
   a.y = y;
   a.n_groups = P.n_groups;
-  a.xcd_blocks = xcd_blocks();
+  a.xcd_blocks = &op == &m->AT ? 1 : xcd_blocks();
   return a;
 }
 SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const void* x, void* y) {
@@ -908,9 +913,9 @@ SellLayout sell_layout(const int64_t* rp, int64_t n_rows, int64_t sigma) {
   return L;
 }
 
-// Most runs of one group of 256 row positions with run-length indices (the
-// group's runs are staged in LDS: 8 B each).
-constexpr int64_t kSellMaxGroupRuns = 2048;
+// Most runs of one chunk of 64 row positions with run-length indices (the
+// chunk's runs are staged in LDS: 8 B each).
+constexpr int64_t kSellMaxGroupRuns = 1024;
 
 void check_sigma(int64_t sigma) {
   if (sigma < 1 || sigma > INT32_MAX) fail(DOSE_ERR_INVALID_ARGUMENT, "sigma must be in [1, 2^31)");
@@ -1469,7 +1474,7 @@ dose_status dose_sell_create(const dose_csr_host* csr, dose_value_format vf, dos
         const int64_t nr = static_cast<int64_t>(cnt[(g + 1) * kSellGroupRows] - cnt[g * kSellGroupRows]);
         if (nr > kSellMaxGroupRuns)
           fail(DOSE_ERR_UNSUPPORTED, "run-length indices: more than " + std::to_string(kSellMaxGroupRuns) +
-                                         " runs in 256 rows of the sorted order");
+                                         " runs in one chunk of 64 rows");
         m->lds_runs = std::max<int32_t>(m->lds_runs, static_cast<int32_t>(nr));
       }
     }
@@ -1572,7 +1577,14 @@ dose_status dose_sell_decode(dose_sell m, int64_t* perm, int64_t* width, float* 
           }
         }
     } else if (m->idx_bytes == 4) {
-      HIP_CHECK(hipMemcpy(hc.data(), m->col.get(), n_ent * 4, hipMemcpyDeviceToHost));
+      // the two halves of each slice (sell_slot) back into a row's 8 entries together
+      std::vector<int32_t> raw(n_ent);
+      HIP_CHECK(hipMemcpy(raw.data(), m->col.get(), n_ent * 4, hipMemcpyDeviceToHost));
+      for (size_t sl = 0; sl < n_ent / kSellSliceEntries; ++sl)
+        for (int i = 0; i < kSellC; ++i)
+          for (int e = 0; e < kSellLaneEntries; ++e)
+            hc[sl * kSellSliceEntries + static_cast<size_t>(i) * kSellLaneEntries + e] =
+                raw[sl * kSellSliceEntries + sell_slot(4, i, e)];
     } else {
       std::vector<uint16_t> h16(n_ent);
       HIP_CHECK(hipMemcpy(h16.data(), m->col.get(), n_ent * 2, hipMemcpyDeviceToHost));

@@ -165,72 +165,4 @@ hipError_t launch_robust_seed(int n_scen, int64_t n, int worst, const double* ou
 hipError_t launch_probe_read(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
 hipError_t launch_probe_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 
-// ------------------------------------------------------------ SELL-C-sigma
-// The rows, in sigma-sorted order (descending length inside windows of sigma
-// rows), are cut into chunks of kSellC = 64 row positions, one per lane of a
-// wave.  A chunk stores its rows' entries in slices: slice j of the chunk is
-// kSellSliceEntries consecutive entries, and the row at chunk position i
-// holds its entries 8 j .. 8 j + 7 at offset 8 i of the slice (one 16-byte
-// load of FP16 codes per lane).  A chunk has ceil(width / 8) slices, width
-// being its longest row; slots past a row's end hold code 0 and the first
-// column of the chunk's group window.  A workgroup takes a group of
-// kSellGroupChunks consecutive chunks and one x window.
-constexpr int kSellC = 64;
-constexpr int kSellLaneEntries = 8;
-constexpr int kSellSliceEntries = kSellC * kSellLaneEntries;
-constexpr int kSellGroupChunks = 4;
-constexpr int kSellGroupRows = kSellC * kSellGroupChunks;
-
-struct alignas(16) SellChunk {
-  uint32_t slice0;    // first slice of the chunk (slices of all chunks are consecutive)
-  uint32_t n_slices;  // ceil(width / 8)
-  uint32_t min_len;   // shortest row of the chunk (slices below min_len / 8 hold no padding)
-  uint32_t pad;
-};
-static_assert(sizeof(SellChunk) == 16, "SellChunk layout");
-
-// Run-length column indices (index width 0): the row at position p has the
-// runs run_ptr[p] .. run_ptr[p + 1] - 1; a run is (end, delta): the row's
-// entries at positions below `end` (and at or past the previous run's end)
-// have column position + delta.
-struct alignas(8) SellRun {
-  int32_t end;
-  int32_t delta;
-};
-
-struct SellArgs {
-  const SellChunk* chunks;  // n_groups * kSellGroupChunks (the last group padded with empty chunks)
-  const uint32_t* win;      // per group: cmin, clen (x window [cmin, cmin + clen); clen 0: no entries)
-  const void* val;          // codes in the slice layout, padded by one slice
-  const void* col;          // column indices (int32 or uint16), same layout
-  const uint32_t* perm;     // per row position: its row (n_rows for positions past the last row)
-  const uint32_t* len;      // per row position: its row's length
-  const float* scale;       // E4M3: row scale by row; else null
-  const uint32_t* run_ptr;  // run-length indices: n_positions + 1 offsets into runs
-  const SellRun* runs;
-  const float* x;
-  float* y;
-  int64_t n_groups;
-  int32_t win_floats;       // LDS window floats (0: no group uses the LDS window)
-  int32_t idx_bytes;        // 4, 2, or 0 (run-length indices)
-  int32_t xcd_blocks;
-  int32_t lds_runs;         // run-length indices: most runs of one group (LDS records)
-  int32_t n_cols;
-  int32_t pad0;
-};
-
-hipError_t launch_sell_spmv(int vf, int scale_mode, const SellArgs& a, hipStream_t s);
-// Scatter of CSR codes and columns into the slice layout.  start: per row
-// position, the row's first entry in the CSR streams; pad_col: per group,
-// the column written into padding slots.
-hipError_t launch_sell_pack(int vf, int idx_bytes, const SellChunk* chunks, int64_t n_chunks,
-                            const uint64_t* start, const uint32_t* len, const uint32_t* pad_col,
-                            const void* codes_in, const void* col_in, void* codes_out, void* col_out,
-                            hipStream_t s);
-// Decoded FP32 values of the slice layout (E4M3 codes times their row's
-// scale); padding slots give 0.
-hipError_t launch_sell_decode(int vf, const SellChunk* chunks, int64_t n_chunks, const uint32_t* perm,
-                              const uint32_t* len, const void* codes, const float* row_scale, float* out,
-                              hipStream_t s);
-
 }  // namespace dose

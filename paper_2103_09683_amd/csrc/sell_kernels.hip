@@ -8,24 +8,28 @@
 // wave stream their rows side by side.  Here a chunk stores its entries in
 // slices of 8 per lane (dose_internal.h): a lane reads its row's next 8 codes
 // with one 16-byte load (FP16), and a wave's load instruction covers 1 KB of
-// consecutive codes.
+// consecutive codes (or indices).
 //
-//   * A workgroup (four waves) takes a group of four consecutive chunks and
-//     copies the group's x window into LDS once (the rows of a sigma window
-//     are neighbouring voxels, so their spots lie in a narrow range); a group
-//     whose window exceeds the LDS cap gathers x from global memory.
-//   * The group's slices, chunk after chunk, are dealt to the waves in turn
-//     (wave j takes slices j, j + 4, ...), so a wide chunk keeps all four
-//     waves busy; the next slice's loads are in flight while one is computed.
+//   * A workgroup (four waves) takes one chunk and copies the chunk's x
+//     window into LDS once (the rows of a sigma window are neighbouring
+//     voxels, so their spots lie in a narrow range); a chunk whose window
+//     exceeds the LDS cap gathers x from global memory.
+//   * The chunk's slices are dealt to the waves in turn (wave j takes slices
+//     j, j + 4, ...); the next slices' loads are in flight while one is
+//     computed.
+//   * Run-length column indices: the chunk's runs are staged in LDS; a lane
+//     keeps a cursor on its row's runs, and a slice whose 8 entries lie in
+//     one run (the common case) reads 8 consecutive x from one LDS address.
 //   * Summation order, fixed by the stored layout (so equal inputs give equal
 //     bits): a lane's 8 products of a slice add pairwise, ((p0 + p1) +
 //     (p2 + p3)) + ((p4 + p5) + (p6 + p7)), slots past the row's end counting
-//     as +0; each wave adds its slice sums of a chunk in order, eight at a
+//     as +0; each wave adds its slice sums of the row in order, eight at a
 //     time into an inner sum that is then added to an outer one (the FP32
 //     error of a row of L entries stays below (14 + L / 256) * 2^-24 of
 //     sum |a x|); the four waves' sums of a row meet as (S0 + S1) + (S2 + S3).
-//     Empty rows get +0.
+//     The order depends only on the row's own entries.  Empty rows get +0.
 #include "dose_internal.h"
+#include "sell_internal.h"
 
 #include <hip/hip_fp16.h>
 
@@ -62,6 +66,15 @@ struct Lane8 {
   uint4 i0, i1;  // indices (i1: int32 only)
 };
 
+// Slices in flight per wave (one being computed, the others loading): about
+// 128 bytes per lane, so that the narrower streams keep as many bytes in
+// flight as the wide ones (a lane's slice is 8 codes plus 8 indices).
+template <int VF, int IX>
+constexpr int ring_depth() {
+  constexpr int bytes = kSellLaneEntries * (code_bytes<VF>() + IX);
+  return 128 / bytes < 2 ? 2 : 128 / bytes > 4 ? 4 : 128 / bytes;
+}
+
 // Loads lane `lane`'s part of slice `slice` (wave-uniform).
 template <int VF, int IX>
 __device__ __forceinline__ void load_slice(const char* val, const char* col, uint32_t slice, int lane,
@@ -74,14 +87,14 @@ __device__ __forceinline__ void load_slice(const char* val, const char* col, uin
     const uint2 v = ld_nt2(vb, o);
     L.c0 = make_uint4(v.x, v.y, 0u, 0u);
   } else if constexpr (VF == kFp32) {
-    L.c0 = ld_nt4(vb, o * 4u);
-    L.c1 = ld_nt4(vb, o * 4u + 16u);
+    L.c0 = ld_nt4(vb, sell_slot(4, lane, 0) * 4u);
+    L.c1 = ld_nt4(vb, sell_slot(4, lane, 4) * 4u);
   } else {
     L.c0 = ld_nt4(vb, o * 2u);
   }
   if constexpr (IX == 4) {
-    L.i0 = ld_nt4(cb, o * 4u);
-    L.i1 = ld_nt4(cb, o * 4u + 16u);
+    L.i0 = ld_nt4(cb, sell_slot(4, lane, 0) * 4u);
+    L.i1 = ld_nt4(cb, sell_slot(4, lane, 4) * 4u);
   } else if constexpr (IX == 2) {
     L.i0 = ld_nt4(cb, o * 2u);
   }
@@ -168,75 +181,88 @@ __device__ __forceinline__ T pick4(int c, T v0, T v1, T v2, T v3) {
   return c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : v3;
 }
 
+// Columns of a lane's 8 entries at positions P .. P + 7 of its row from the
+// row's runs (rare path: some entry lies beyond the run after the current
+// one): walk the runs from the current one; entries past the row take the
+// padding column.
+__device__ __forceinline__ void walk_runs(const SellRun* lruns, int ri, int re, int cur_end, int cur_delta, int P,
+                                          int cmin, int (&cols)[kSellLaneEntries]) {
+  int j = ri, ce = cur_end, cd = cur_delta;
+  for (int e = 0; e < kSellLaneEntries; ++e) {
+    const int p = P + e;
+    while (p >= ce && j + 1 < re) {
+      ++j;
+      ce = lruns[j].end, cd = lruns[j].delta;
+    }
+    const int cv = p < ce ? p + cd : cmin;
+    // registers, not memory: select into the array element
+#pragma unroll
+    for (int k = 0; k < kSellLaneEntries; ++k) cols[k] = k == e ? cv : cols[k];
+  }
+}
+
 template <int VF, int SM, int IX, bool WIN>
-__device__ __forceinline__ void sell_group(const SellArgs& a, int64_t g, float* xw,
-                                           float (*part)[kGroupWaves][kWave]) {
+__device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* xw, float (*part)[kWave]) {
   const int tid = static_cast<int>(threadIdx.x);
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
-  const SellChunk* chs = a.chunks + g * kSellGroupChunks;
-  const uint32_t slice0 = chs[0].slice0;
-  const int b1 = static_cast<int>(chs[0].n_slices);
-  const int b2 = b1 + static_cast<int>(chs[1].n_slices);
-  const int b3 = b2 + static_cast<int>(chs[2].n_slices);
-  const int T = b3 + static_cast<int>(chs[3].n_slices);
-  const uint32_t m0 = chs[0].min_len, m1 = chs[1].min_len, m2 = chs[2].min_len, m3 = chs[3].min_len;
-  const int64_t pos0 = g * kSellGroupRows;
-  // this thread's row position at the end, and the lane's row lengths in the
-  // four chunks (a wave's slices may belong to any of them)
-  const uint32_t my_row = a.perm[pos0 + tid];
-  const uint32_t len0 = a.len[pos0 + lane], len1 = a.len[pos0 + kWave + lane];
-  const uint32_t len2 = a.len[pos0 + 2 * kWave + lane], len3 = a.len[pos0 + 3 * kWave + lane];
+  const SellChunk* ch = a.chunks + c;
+  const uint32_t slice0 = ch->slice0;
+  const int T = static_cast<int>(ch->n_slices);
+  const uint32_t min_len = ch->min_len;
+  const int64_t pos = c * kSellC + lane;
+  // the lane's row (written by the first wave at the end) and its length
+  const uint32_t my_row = a.perm[pos];
+  const int len = static_cast<int>(a.len[pos]);
   const char* val = static_cast<const char*>(a.val);
   const char* col = static_cast<const char*>(a.col);
-  // run-length indices: the group's runs (staged in LDS after the window) and
-  // each lane's run range in the four chunks, relative to the group's first run
+  // run-length indices: the chunk's runs (staged in LDS after the window) and
+  // the lane's run range, relative to the chunk's first run
   SellRun* lruns = reinterpret_cast<SellRun*>(xw + a.win_floats + kSellLaneEntries);
-  int nruns = 0, rb0 = 0, rb1 = 0, rb2 = 0, rb3 = 0, re0 = 0, re1 = 0, re2 = 0, re3 = 0;
+  int nruns = 0, rb = 0, re = 0;
   SellRun q0{}, q1{};
+  uint32_t g0 = 0;
   if constexpr (IX == 0) {
-    const uint32_t g0 = a.run_ptr[pos0];
-    nruns = static_cast<int>(a.run_ptr[pos0 + kSellGroupRows] - g0);
-    const uint32_t* rp = a.run_ptr + pos0 + lane;
-    rb0 = static_cast<int>(rp[0] - g0), re0 = static_cast<int>(rp[1] - g0);
-    rb1 = static_cast<int>(rp[kWave] - g0), re1 = static_cast<int>(rp[kWave + 1] - g0);
-    rb2 = static_cast<int>(rp[2 * kWave] - g0), re2 = static_cast<int>(rp[2 * kWave + 1] - g0);
-    rb3 = static_cast<int>(rp[3 * kWave] - g0), re3 = static_cast<int>(rp[3 * kWave + 1] - g0);
+    g0 = a.run_ptr[c * kSellC];
+    nruns = static_cast<int>(a.run_ptr[(c + 1) * kSellC] - g0);
+    rb = static_cast<int>(a.run_ptr[pos] - g0);
+    re = static_cast<int>(a.run_ptr[pos + 1] - g0);
     const SellRun* gr = a.runs + g0;
-    const SellRun* safe = reinterpret_cast<const SellRun*>(chs);
+    const SellRun* safe = reinterpret_cast<const SellRun*>(ch);
     q0 = *(tid < nruns ? gr + tid : safe);
     q1 = *(tid + kGroupThreads < nruns ? gr + tid + kGroupThreads : safe);
   }
-  // Loads in the order they are needed: the x window (16-byte pieces, a
-  // thread's first four at once; a thread without a piece reads the chunk
-  // records instead, so that the number of loads is fixed), then the wave's
-  // first two slices; waiting for the window leaves the slices in flight.
-  int cmin = 0, clen = 0, n4 = 0;
+  // Loads in the order they are needed, every one issued whatever the chunk
+  // (a thread without a window piece reads the chunk record instead; a chunk
+  // without slices re-reads its first slice position, inside the padded
+  // streams), so that the compiler's count of loads in flight stays exact and
+  // waiting for the window leaves the slices in flight: the x window (16-byte
+  // pieces, a thread's first four at once), then the wave's first NB slices.
+  const int cmin = static_cast<int>(a.win[2 * c]);  // also the padding column
+  int clen = 0, n4 = 0;
   const float* xs = a.x;
   float4 w0, w1, w2, w3;
   float wt = 0.0f;
   if constexpr (WIN) {
-    cmin = static_cast<int>(a.win[2 * g]);
-    clen = static_cast<int>(a.win[2 * g + 1]);
+    clen = static_cast<int>(a.win[2 * c + 1]);
     xs = a.x + cmin;
     n4 = clen >> 2;
     const float4* xs4 = reinterpret_cast<const float4*>(xs);
-    const float4* safe4 = reinterpret_cast<const float4*>(chs);
+    const float4* safe4 = reinterpret_cast<const float4*>(ch);
     w0 = *(tid < n4 ? xs4 + tid : safe4);
     w1 = *(tid + kGroupThreads < n4 ? xs4 + tid + kGroupThreads : safe4);
     w2 = *(tid + 2 * kGroupThreads < n4 ? xs4 + tid + 2 * kGroupThreads : safe4);
     w3 = *(tid + 3 * kGroupThreads < n4 ? xs4 + tid + 3 * kGroupThreads : safe4);
     const int tt = 4 * n4 + tid;
-    wt = *(tt < clen ? xs + tt : reinterpret_cast<const float*>(chs));
-  } else {
-    cmin = static_cast<int>(a.win[2 * g]);  // the padding column, a valid column of the group
+    wt = *(tt < clen ? xs + tt : reinterpret_cast<const float*>(ch));
   }
-  Lane8<VF, IX> r0, r1;
-  const bool has = wave < T;
-  if (has) {
-    load_slice<VF, IX>(val, col, slice0 + static_cast<uint32_t>(wave), lane, r0);
-    load_slice<VF, IX>(val, col, slice0 + static_cast<uint32_t>(min(wave + kGroupWaves, T - 1)), lane, r1);
-  }
+  constexpr int NB = ring_depth<VF, IX>();
+  // slice k of the wave, clamped to the chunk's last (or, without slices, its
+  // first slice position)
+  auto slice_of = [&](int t) { return slice0 + static_cast<uint32_t>(max(min(t, T - 1), 0)); };
+  Lane8<VF, IX> r[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) load_slice<VF, IX>(val, col, slice_of(wave + k * kGroupWaves), lane, r[k]);
   if constexpr (WIN) {
     float4* xw4 = reinterpret_cast<float4*>(xw);
     const float4* xs4 = reinterpret_cast<const float4*>(xs);
@@ -251,99 +277,89 @@ __device__ __forceinline__ void sell_group(const SellArgs& a, int64_t g, float* 
   if constexpr (IX == 0) {
     if (tid < nruns) lruns[tid] = q0;
     if (tid + kGroupThreads < nruns) lruns[tid + kGroupThreads] = q1;
-    for (int j = tid + 2 * kGroupThreads; j < nruns; j += kGroupThreads) lruns[j] = a.runs[a.run_ptr[pos0] + j];
+    for (int j = tid + 2 * kGroupThreads; j < nruns; j += kGroupThreads) lruns[j] = a.runs[g0 + j];
   }
-#pragma unroll
-  for (int c = 0; c < kSellGroupChunks; ++c) part[c][wave][lane] = 0.0f;
+  part[wave][lane] = 0.0f;
   __syncthreads();
-  if (has) {
+  if (wave < T) {
     const float* xb = xw - cmin;
     float inner = 0.0f, outer = 0.0f;
-    int cnt = 0, cc = -1;
-    // run cursor of the lane's row in chunk cc: run ri (of [ri, rend)) ends
-    // at cur_end, with column = position + cur_delta
-    int ri = 0, rend = 0, cur_end = 0, cur_delta = 0;
+    int cnt = 0;
+    // run cursor: run ri (of the lane's [rb, re)) ends at cur_end and its
+    // entries have column = position + cur_delta; the next run (nx_end,
+    // nx_delta) is held too (nx_end = cur_end when there is none)
+    int ri = rb, cur_end = 0, cur_delta = 0, nx_end = 0, nx_delta = 0;
+    auto next_run = [&]() {
+      nx_end = cur_end, nx_delta = 0;
+      if (ri + 1 < re) nx_end = lruns[ri + 1].end, nx_delta = lruns[ri + 1].delta;
+    };
+    if constexpr (IX == 0) {
+      if (ri < re) cur_end = lruns[ri].end, cur_delta = lruns[ri].delta;
+      next_run();
+    }
     int t = wave;
-    // one slice: the columns, products, refill of its buffer with the slice
-    // two turns ahead, then the slice sum into the current chunk's sums
+    // one slice (a step past the chunk's slices only refills its buffer):
+    // the columns, products, refill with the slice NB turns ahead, then the
+    // slice sum
     auto step = [&](Lane8<VF, IX>& buf) {
-      const int c = (t >= b1) + (t >= b2) + (t >= b3);
-      if (c != cc) {
-        if (cc >= 0) part[cc][wave][lane] = outer + inner;
-        inner = 0.0f, outer = 0.0f, cnt = 0;
-        cc = c;
+      const bool live = t < T;
+      const int P = t * kSellLaneEntries;
+      float pr[kSellLaneEntries];
+      if (live) {
+        int cols[kSellLaneEntries];
         if constexpr (IX == 0) {
-          ri = pick4(c, rb0, rb1, rb2, rb3);
-          rend = pick4(c, re0, re1, re2, re3);
-          cur_end = 0, cur_delta = 0;
-          if (ri < rend) cur_end = lruns[ri].end, cur_delta = lruns[ri].delta;
-        }
-      }
-      const int sl = t - pick4(c, 0, b1, b2, b3);
-      const int lenc = static_cast<int>(pick4(c, len0, len1, len2, len3));
-      int cols[kSellLaneEntries];
-      if constexpr (IX == 0) {
-        const int P = sl * kSellLaneEntries;
-        while (cur_end <= P && ri + 1 < rend) {
-          ++ri;
-          cur_end = lruns[ri].end, cur_delta = lruns[ri].delta;
-        }
-        // a lane whose 8 entries lie in one run (or, with the LDS window
-        // padded by 8 columns, wholly past its row) reads 8 consecutive x
-        const bool past = WIN && P >= lenc;
-        const bool run8 = past || P + kSellLaneEntries <= cur_end;
-        if (__ballot(!run8) == 0) {
-          const int base = past ? cmin : P + cur_delta;
-#pragma unroll
-          for (int e = 0; e < kSellLaneEntries; ++e) cols[e] = base + e;
-        } else {
-          // some lane's run ends inside the slice: walk the runs entry by
-          // entry; entries past the row take the group's padding column
-          int j = ri, ce = cur_end, cd = cur_delta;
+          while (cur_end <= P && ri + 1 < re) {
+            ++ri;
+            cur_end = nx_end, cur_delta = nx_delta;
+            next_run();
+          }
+          // an entry lies in the current run, in the next one, or past the
+          // row (padding column)
 #pragma unroll
           for (int e = 0; e < kSellLaneEntries; ++e) {
-            const int pos = P + e;
-            while (pos >= ce && j + 1 < rend) {
-              ++j;
-              ce = lruns[j].end, cd = lruns[j].delta;
-            }
-            cols[e] = pos < ce ? pos + cd : cmin;
+            const int p = P + e;
+            cols[e] = p < cur_end ? p + cur_delta : p < nx_end ? p + nx_delta : cmin;
           }
+          // an entry beyond the next run and inside the row: walk the runs
+          const bool far = P + kSellLaneEntries > nx_end && nx_end < len;
+          if (__ballot(far) != 0) {
+            if (far) walk_runs(lruns, ri, re, cur_end, cur_delta, P, cmin, cols);
+          }
+        } else {
+          lane_cols(buf, cols);
         }
-      } else {
-        lane_cols(buf, cols);
+        slice_products<VF, IX, WIN>(buf, cols, xb, a.x, pr);
       }
-      float p[kSellLaneEntries];
-      slice_products<VF, IX, WIN>(buf, cols, xb, a.x, p);
       __builtin_amdgcn_sched_barrier(0);
-      load_slice<VF, IX>(val, col, slice0 + static_cast<uint32_t>(min(t + 2 * kGroupWaves, T - 1)), lane, buf);
+      load_slice<VF, IX>(val, col, slice_of(t + NB * kGroupWaves), lane, buf);
       __builtin_amdgcn_sched_barrier(0);
-      if (static_cast<uint32_t>(sl + 1) * kSellLaneEntries > pick4(c, m0, m1, m2, m3)) {
-        // some lane's row ends in or before this slice
-        const int lim = lenc - sl * kSellLaneEntries;
+      if (live) {
+        if (static_cast<uint32_t>(P + kSellLaneEntries) > min_len) {
+          // some lane's row ends in or before this slice
+          const int lim = len - P;
 #pragma unroll
-        for (int e = 0; e < kSellLaneEntries; ++e) p[e] = e < lim ? p[e] : 0.0f;
-      }
-      inner += slice_sum(p);
-      if (++cnt == 8) {
-        outer += inner;
-        inner = 0.0f;
-        cnt = 0;
+          for (int e = 0; e < kSellLaneEntries; ++e) pr[e] = e < lim ? pr[e] : 0.0f;
+        }
+        inner += slice_sum(pr);
+        if (++cnt == 8) {
+          outer += inner;
+          inner = 0.0f;
+          cnt = 0;
+        }
       }
       t += kGroupWaves;
     };
+    // one exit per turn of the ring
     while (true) {
-      step(r0);
-      if (t >= T) break;
-      step(r1);
+#pragma unroll
+      for (int k = 0; k < NB; ++k) step(r[k]);
       if (t >= T) break;
     }
-    part[cc][wave][lane] = outer + inner;
+    part[wave][lane] = outer + inner;
   }
   __syncthreads();
-  if (my_row != 0xFFFFFFFFu) {
-    const int c = tid / kWave;
-    float v = (part[c][0][lane] + part[c][1][lane]) + (part[c][2][lane] + part[c][3][lane]);
+  if (wave == 0 && my_row != 0xFFFFFFFFu) {
+    float v = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
     if constexpr (SM == kScaleRow) v = v * a.scale[my_row];
     a.y[my_row] = v;
   }
@@ -352,13 +368,13 @@ __device__ __forceinline__ void sell_group(const SellArgs& a, int64_t g, float* 
 template <int VF, int SM, int IX>
 __global__ __launch_bounds__(kGroupThreads) void k_sell(SellArgs a) {
   extern __shared__ __align__(16) float xw[];
-  __shared__ float part[kSellGroupChunks][kGroupWaves][kWave];
-  const int64_t g = sell_group_of_block(a, blockIdx.x);
-  const uint32_t clen = a.win[2 * g + 1];
+  __shared__ float part[kGroupWaves][kWave];
+  const int64_t c = sell_group_of_block(a, blockIdx.x);
+  const uint32_t clen = a.win[2 * c + 1];
   if (clen > 0 && static_cast<int64_t>(clen) <= a.win_floats)
-    sell_group<VF, SM, IX, true>(a, g, xw, part);
+    sell_chunk<VF, SM, IX, true>(a, c, xw, part);
   else
-    sell_group<VF, SM, IX, false>(a, g, xw, part);
+    sell_chunk<VF, SM, IX, false>(a, c, xw, part);
 }
 
 template <int VF, int SM>

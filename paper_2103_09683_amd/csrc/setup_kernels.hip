@@ -5,6 +5,7 @@
 // round-to-nearest-even conversion, bfloat16 and OCP E4M3 by integer rounding
 // of the FP32 bit pattern (nearest, ties to even; E4M3 saturates at 448).
 #include "dose_internal.h"
+#include "sell_internal.h"
 
 #include <hip/hip_fp16.h>
 
@@ -180,17 +181,18 @@ __global__ __launch_bounds__(64) void k_sell_pack(const SellChunk* __restrict__ 
   const uint64_t b = start[pos];
   const I pad = col_out ? static_cast<I>(pad_col[c / kSellGroupChunks]) : I(0);
   for (uint32_t sl = 0; sl < ch.n_slices; ++sl) {
-    const uint64_t o = (static_cast<uint64_t>(ch.slice0) + sl) * kSellSliceEntries + static_cast<uint64_t>(i) * kSellLaneEntries;
+    const uint64_t o = (static_cast<uint64_t>(ch.slice0) + sl) * kSellSliceEntries;
     for (int e = 0; e < kSellLaneEntries; ++e) {
       const uint32_t j = sl * kSellLaneEntries + static_cast<uint32_t>(e);
-      codes_out[o + e] = j < L ? codes_in[b + j] : C(0);
-      if (col_out) col_out[o + e] = j < L ? col_in[b + j] : pad;
+      codes_out[o + sell_slot(sizeof(C), i, e)] = j < L ? codes_in[b + j] : C(0);
+      if (col_out) col_out[o + sell_slot(sizeof(I), i, e)] = j < L ? col_in[b + j] : pad;
     }
   }
 }
 
-// Decoded values of the slice layout: code times its row's scale (E4M3),
-// 0 in padding slots.
+// Decoded values of the slice layout, written with a row's 8 entries of a
+// slice together (offset 8 i + e, whatever the code width): code times its
+// row's scale (E4M3), 0 in padding slots.
 template <int VF>
 __global__ __launch_bounds__(64) void k_sell_decode(const SellChunk* __restrict__ chunks,
                                                     const uint32_t* __restrict__ perm,
@@ -204,15 +206,16 @@ __global__ __launch_bounds__(64) void k_sell_decode(const SellChunk* __restrict_
   const uint32_t L = len[pos];
   const float sc = VF == kFp8 && L > 0 ? row_scale[perm[pos]] : 1.0f;
   for (uint32_t sl = 0; sl < ch.n_slices; ++sl) {
-    const uint64_t o = (static_cast<uint64_t>(ch.slice0) + sl) * kSellSliceEntries + static_cast<uint64_t>(i) * kSellLaneEntries;
+    const uint64_t o = (static_cast<uint64_t>(ch.slice0) + sl) * kSellSliceEntries;
+    const int vb = VF == kFp8 ? 1 : VF == kFp32 ? 4 : 2;
     for (int e = 0; e < kSellLaneEntries; ++e) {
       const uint32_t j = sl * kSellLaneEntries + static_cast<uint32_t>(e);
       float d = 0.0f;
       if (j < L) {
-        d = dec_code(VF, codes, o + e);
+        d = dec_code(VF, codes, o + sell_slot(vb, i, e));
         if (VF == kFp8) d = d * sc;
       }
-      out[o + e] = d;
+      out[o + static_cast<uint64_t>(i) * kSellLaneEntries + e] = d;
     }
   }
 }

@@ -345,7 +345,7 @@ def test_runs_window_and_global_groups(dev):
 
 
 def test_runs_limits(dev):
-    # columns with no runs: 256 rows of 20 scattered entries exceed 2048 runs
+    # columns with no runs: 64 rows of 20 scattered entries exceed 1024 runs
     rng = np.random.default_rng(50)
     rp, cols, vals = _csr(rng, np.full(256, 20), 60000)
     with pytest.raises(dm.DoseError) as e:
