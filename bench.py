@@ -354,7 +354,7 @@ def main(argv=None):
                     help="only time the robust-plan epilogue on the full 1,048,576-voxel grid")
     ap.add_argument("--robust-step", action="store_true",
                     help="only time the robust-plan step (9 scenarios x 4 beams, then the epilogue)")
-    ap.add_argument("--sell-sigmas", default="1024,4096,16384", help="sigmas of the SELL-C-sigma variants")
+    ap.add_argument("--sell-sigmas", default="16384,65536", help="sigmas of the SELL-C-sigma variants")
     ap.add_argument("--sell-index", default="i32,u16,runs", help="index formats of the SELL-C-sigma variants")
     ap.add_argument("--part", choices=["clinical", "adjoint", "batched", "sell"],
                     help="only one part: the clinical-beam variants, the clinical-beam adjoint, the full-size "

@@ -52,7 +52,10 @@ enum {
   DOSE_ERR_INTERNAL = -7
 };
 
-/* Stored value formats.  Decoding is exact in FP32 for all four. */
+/* Stored value formats.  Decoding is exact in FP32 for all four.  Entry
+ * points take formats as int32_t values of these enumerations, so that an
+ * unknown value is an error (DOSE_ERR_INVALID_ARGUMENT), not undefined
+ * behaviour of an out-of-range enumeration. */
 typedef enum {
   DOSE_VAL_FP16 = 1,             /* IEEE binary16, the paper's format (Sec. II-D) */
   DOSE_VAL_BF16 = 2,             /* bfloat16                                     */
@@ -122,8 +125,8 @@ typedef struct {
  * range and order, finite values) and range (binary16 and bfloat16 values
  * must not round to infinity).  No GPU is touched.  Returns DOSE_OK,
  * DOSE_ERR_BAD_CSR, DOSE_ERR_UNSUPPORTED or DOSE_ERR_INVALID_ARGUMENT. */
-dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf,
-                              dose_index_format xf);
+dose_status dose_csr_validate(const dose_csr_host* csr, int32_t vf /* dose_value_format */,
+                              int32_t xf /* dose_index_format */);
 
 /* Encode a host CSR matrix into device streams (Sec. II-C: the conversion to
  * CSR happens once, before optimisation).  Validates first (as above).  The
@@ -138,8 +141,8 @@ dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf,
  * of the matrix until dose_matrix_destroy.  DOSE_ERR_UNSUPPORTED also when a
  * row of A (or, with DOSE_CREATE_TRANSPOSE, of A^T: a column of A) holds 2^28
  * or more entries, or the transpose would hold 2^31 or more. */
-dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf,
-                               dose_index_format xf, uint32_t flags, void* hip_stream,
+dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf /* dose_value_format */,
+                               int32_t xf /* dose_index_format */, uint32_t flags, void* hip_stream,
                                dose_matrix* out);
 
 /* Re-partition a matrix (A, and A^T if stored) into row groups of about
@@ -384,7 +387,8 @@ dose_status dose_sell_layout(const int64_t* row_ptr, int64_t n_rows, int32_t sig
  * scale).  Synchronous, like dose_matrix_create; *out owns the device
  * memory until dose_sell_destroy.  DOSE_ERR_UNSUPPORTED beyond 2^32 - 2 rows
  * or 2^32 slices. */
-dose_status dose_sell_create(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf,
+dose_status dose_sell_create(const dose_csr_host* csr, int32_t vf /* dose_value_format */,
+                             int32_t xf /* dose_index_format */,
                              int32_t sigma, void* hip_stream, dose_sell* out);
 
 dose_status dose_sell_info(dose_sell m, dose_sell_info_t* info);

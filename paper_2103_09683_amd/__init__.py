@@ -212,7 +212,7 @@ class SellMatrix:
     current HIP device: the same host CSR arrays and value/index formats as
     :class:`DoseMatrix`, rows sorted by length inside windows of ``sigma``."""
 
-    def __init__(self, row_ptr, cols, vals, n_cols: int, value_format: str = "fp16", sigma: int = 256,
+    def __init__(self, row_ptr, cols, vals, n_cols: int, value_format: str = "fp16", sigma: int = 65536,
                  index_format: str = "i32", stream=None):
         if value_format not in VALUE_FORMATS:
             raise ValueError(f"unknown value format {value_format!r}")

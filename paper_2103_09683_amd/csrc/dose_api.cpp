@@ -72,21 +72,27 @@ dose_status guarded(F&& f) {
 }
 
 // --------------------------------------------------- allocation fault injection
-// DOSE_FAULT_INJECT=alloc:<n> makes the n-th device allocation (1-based,
-// counted from process start) report out-of-memory, to test cleanup paths.
-std::atomic<int64_t> g_alloc_count{0};
-int64_t fault_alloc_index() {
-  static const int64_t idx = [] {
-    const char* e = std::getenv("DOSE_FAULT_INJECT");
-    if (!e || std::strncmp(e, "alloc:", 6) != 0) return int64_t{-1};
-    return static_cast<int64_t>(std::atoll(e + 6));
-  }();
-  return idx;
+// DOSE_FAULT_INJECT=alloc:<n> makes the n-th device allocation, counted from
+// the moment the variable took that value, report out-of-memory (to test
+// cleanup paths); read at every allocation, so a process can arm it again.
+std::mutex g_fault_mu;
+std::string g_fault_spec;
+int64_t g_fault_count = 0;
+
+bool injected_fault() {
+  std::lock_guard<std::mutex> lk(g_fault_mu);
+  const char* e = std::getenv("DOSE_FAULT_INJECT");
+  const std::string spec = e ? e : "";
+  if (spec != g_fault_spec) {
+    g_fault_spec = spec;
+    g_fault_count = 0;
+  }
+  if (spec.compare(0, 6, "alloc:") != 0) return false;
+  return ++g_fault_count == std::atoll(spec.c_str() + 6);
 }
 
 void* dev_alloc(size_t bytes) {
-  const int64_t n = ++g_alloc_count;
-  if (n == fault_alloc_index()) fail(DOSE_ERR_OUT_OF_MEMORY, "injected allocation failure");
+  if (injected_fault()) fail(DOSE_ERR_OUT_OF_MEMORY, "injected allocation failure");
   void* p = nullptr;
   HIP_CHECK(hipMalloc(&p, bytes == 0 ? 256 : bytes));
   return p;
@@ -381,20 +387,21 @@ namespace {
 int scale_mode_A(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleRow : kScaleNone; }
 int scale_mode_AT(const dose_matrix_s* m) { return m->vf == kFp8 ? kScaleCol : kScaleNone; }
 
-// Dies of the chip that workgroups are dealt to in turn (DOSE_XCD_BLOCKS:
-// 8, the MI355X's eight XCDs, gives each die a contiguous eighth of the row
-// groups so that its L2 sees an eighth of x; default 1, dispatch order).
-// Only the order in which groups are dispatched depends on it, never a
-// result.  Regrouping measured slower: the largest workload's half/double
-// product 1.690 ms against 1.648 ms, the clinical beam's adjoint 0.80 ms
-// against 0.69 ms; products on A^T never regroup.
-int xcd_blocks() {
+// Dies of the chip that workgroups are dealt to in turn (DOSE_XCD_BLOCKS):
+// 8, the MI355X's eight XCDs, gives each die a contiguous run of the work
+// items so that its L2 sees one part of x (and, for SELL-C-sigma, the rows
+// one sigma window writes); 1 keeps the dispatch order.  Only the order in
+// which work items are dispatched depends on it, never a result.  Measured:
+// CSR products are faster without it (the largest workload's half/double
+// product 1.648 ms against 1.690 ms, the clinical beam's adjoint 0.69 ms
+// against 0.80 ms: default 1, and never on A^T), SELL-C-sigma products with
+// it (the clinical beam, sigma 4096: 0.72 ms against 1.12 ms: default 8).
+int xcd_blocks(int dflt) {
   static const int d = [] {
     const char* e = std::getenv("DOSE_XCD_BLOCKS");
-    const int v = e ? std::atoi(e) : 1;
-    return std::max(1, std::min(64, v));
+    return e ? std::max(1, std::min(64, std::atoi(e))) : 0;
   }();
-  return d;
+  return d > 0 ? d : dflt;
 }
 
 // n_rhs sizes the LDS window (an FP64 vector takes the window of two FP32 ones).
@@ -411,7 +418,7 @@ SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, const Partition& P
   a.x = x;
   a.y = y;
   a.n_groups = P.n_groups;
-  a.xcd_blocks = &op == &m->AT ? 1 : xcd_blocks();
+  a.xcd_blocks = &op == &m->AT ? 1 : xcd_blocks(1);
   return a;
 }
 SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const void* x, void* y) {
@@ -831,7 +838,7 @@ int n_partial_for(int64_t n) { return static_cast<int>(std::max<int64_t>(1, std:
 namespace {
 // A's streams on the current device: validated host CSR uploaded, codes
 // encoded, indices padded; no partition yet.  Synchronous on s.
-std::unique_ptr<dose_matrix_s> upload_encode_A(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf,
+std::unique_ptr<dose_matrix_s> upload_encode_A(const dose_csr_host* csr, int32_t vf, int32_t xf,
                                                hipStream_t s) {
   auto m = std::make_unique<dose_matrix_s>();
   HIP_CHECK(hipGetDevice(&m->device));
@@ -935,10 +942,11 @@ struct dose_sell_s {
   int32_t win_floats = 0, idx_bytes = 4;  // idx_bytes 0: run-length indices
   int64_t n_runs = 0;
   int32_t lds_runs = 0;  // most runs of one group
+  int64_t n_work = 0, n_zero = 0;  // chunks with entries, chunks without
   std::vector<SellChunk> h_chunks;
   std::vector<uint32_t> h_perm, h_len;
   std::vector<int64_t> h_width;
-  DevBuf val, col, chunks, win, perm, len, row_scale, run_ptr, runs;
+  DevBuf val, col, chunks, win, perm, len, row_scale, run_ptr, runs, work;
 };
 
 namespace {
@@ -954,12 +962,15 @@ SellArgs sell_args(const dose_sell_s* m, const float* x, float* y) {
   a.scale = m->vf == kFp8 ? m->row_scale.get<float>() : nullptr;
   a.run_ptr = m->run_ptr.get<uint32_t>();
   a.runs = m->runs.get<SellRun>();
+  a.work = m->work.get<uint32_t>();
+  a.zero = m->work.get<uint32_t>() + m->n_work;
   a.x = x;
   a.y = y;
-  a.n_groups = m->n_groups;
+  a.n_groups = m->n_work;
+  a.n_zero = m->n_zero;
   a.win_floats = m->win_floats;
   a.idx_bytes = m->idx_bytes;
-  a.xcd_blocks = xcd_blocks();
+  a.xcd_blocks = xcd_blocks(8);
   a.lds_runs = m->lds_runs;
   a.n_cols = static_cast<int32_t>(std::min<int64_t>(m->n_cols, INT32_MAX));
   return a;
@@ -1017,7 +1028,7 @@ const char* dose_status_string(dose_status s) {
 
 const char* dose_last_error(void) { return g_last_error.c_str(); }
 
-dose_status dose_csr_validate(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf) {
+dose_status dose_csr_validate(const dose_csr_host* csr, int32_t vf, int32_t xf) {
   return guarded([&] { validate_csr(csr, vf, xf); });
 }
 
@@ -1037,7 +1048,7 @@ dose_status dose_partition_preview(const int64_t* row_ptr, int64_t n_rows, int32
   });
 }
 
-dose_status dose_matrix_create(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf, uint32_t flags,
+dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf, int32_t xf, uint32_t flags,
                                void* hip_stream, dose_matrix* out) {
   return guarded([&] {
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
@@ -1363,7 +1374,7 @@ dose_status dose_sell_layout(const int64_t* row_ptr, int64_t n_rows, int32_t sig
   });
 }
 
-dose_status dose_sell_create(const dose_csr_host* csr, dose_value_format vf, dose_index_format xf, int32_t sigma,
+dose_status dose_sell_create(const dose_csr_host* csr, int32_t vf, int32_t xf, int32_t sigma,
                              void* hip_stream, dose_sell* out) {
   return guarded([&] {
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
@@ -1491,6 +1502,18 @@ dose_status dose_sell_create(const dose_csr_host* csr, dose_value_format vf, dos
       HIP_CHECK(hipMemcpyAsync(m->runs.get(), h_runs.data(), m->runs.bytes(), hipMemcpyHostToDevice, s));
     }
     m->chunks = DevBuf(m->h_chunks.size() * sizeof(SellChunk));
+    // the launch's work: chunks holding entries, then those without
+    std::vector<uint32_t> work;
+    work.reserve(static_cast<size_t>(n_ch));
+    for (int64_t c = 0; c < n_ch; ++c)
+      if (m->h_chunks[c].n_slices > 0) work.push_back(static_cast<uint32_t>(c));
+    m->n_work = static_cast<int64_t>(work.size());
+    for (int64_t c = 0; c < n_ch; ++c)
+      if (m->h_chunks[c].n_slices == 0) work.push_back(static_cast<uint32_t>(c));
+    m->n_zero = n_ch - m->n_work;
+    m->work = DevBuf(std::max<size_t>(work.size(), 1) * sizeof(uint32_t));
+    if (!work.empty())
+      HIP_CHECK(hipMemcpyAsync(m->work.get(), work.data(), work.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     m->win = DevBuf(win.size() * sizeof(uint32_t));
     m->perm = DevBuf(static_cast<size_t>(n_pos) * sizeof(uint32_t));
     m->len = DevBuf(static_cast<size_t>(n_pos) * sizeof(uint32_t));
@@ -1530,7 +1553,8 @@ dose_status dose_sell_info(dose_sell m, dose_sell_info_t* info) {
     info->n_runs = m->n_runs;
     info->stored_slots = m->n_slices * kSellSliceEntries;
     info->device_bytes = m->val.bytes() + m->col.bytes() + m->chunks.bytes() + m->win.bytes() + m->perm.bytes() +
-                         m->len.bytes() + m->row_scale.bytes() + m->run_ptr.bytes() + m->runs.bytes();
+                         m->len.bytes() + m->row_scale.bytes() + m->run_ptr.bytes() + m->runs.bytes() +
+                         m->work.bytes();
     const uint64_t per = static_cast<uint64_t>(value_bytes(m->vf)) + static_cast<uint64_t>(m->idx_bytes);
     const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
     const uint64_t nr = static_cast<uint64_t>(m->n_rows), nc = static_cast<uint64_t>(m->n_cols);

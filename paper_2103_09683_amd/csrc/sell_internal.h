@@ -59,9 +59,12 @@ struct SellArgs {
   const float* scale;       // E4M3: row scale by row; else null
   const uint32_t* run_ptr;  // run-length indices: n_positions + 1 offsets into runs
   const SellRun* runs;
+  const uint32_t* work;     // the chunks holding entries, ascending (one workgroup each)
+  const uint32_t* zero;     // the chunks without entries (their rows get +0; 4 per workgroup)
   const float* x;
   float* y;
-  int64_t n_groups;
+  int64_t n_groups;         // chunks holding entries
+  int64_t n_zero;           // chunks without entries
   int32_t win_floats;       // LDS window floats (0: no group uses the LDS window)
   int32_t idx_bytes;        // 4, 2, or 0 (run-length indices)
   int32_t xcd_blocks;

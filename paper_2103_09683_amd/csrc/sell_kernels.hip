@@ -365,11 +365,22 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
   }
 }
 
+// Workgroups [0, n_groups) take the chunks holding entries (through the die
+// regrouping); the rest write +0 to the rows of four chunks without entries
+// each.
 template <int VF, int SM, int IX>
 __global__ __launch_bounds__(kGroupThreads) void k_sell(SellArgs a) {
   extern __shared__ __align__(16) float xw[];
   __shared__ float part[kGroupWaves][kWave];
-  const int64_t c = sell_group_of_block(a, blockIdx.x);
+  if (blockIdx.x >= a.n_groups) {
+    const int64_t z = (static_cast<int64_t>(blockIdx.x) - a.n_groups) * kGroupWaves + threadIdx.x / kWave;
+    if (z < a.n_zero) {
+      const uint32_t row = a.perm[static_cast<int64_t>(a.zero[z]) * kSellC + (threadIdx.x & (kWave - 1))];
+      if (row != 0xFFFFFFFFu) a.y[row] = 0.0f;
+    }
+    return;
+  }
+  const int64_t c = a.work[sell_group_of_block(a, blockIdx.x)];
   const uint32_t clen = a.win[2 * c + 1];
   if (clen > 0 && static_cast<int64_t>(clen) <= a.win_floats)
     sell_chunk<VF, SM, IX, true>(a, c, xw, part);
@@ -379,7 +390,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_sell(SellArgs a) {
 
 template <int VF, int SM>
 hipError_t launch_vf(const SellArgs& a, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
+  const dim3 grid(static_cast<unsigned>(a.n_groups + (a.n_zero + kGroupWaves - 1) / kGroupWaves)),
+      block(kGroupThreads);
   if (a.idx_bytes == 0) {
     // the window padded by one lane's entries, then the group's runs
     const size_t lds = (static_cast<size_t>(a.win_floats) + kSellLaneEntries) * sizeof(float) +
@@ -398,7 +410,7 @@ hipError_t launch_vf(const SellArgs& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_sell_spmv(int vf, int scale_mode, const SellArgs& a, hipStream_t s) {
-  if (a.n_groups <= 0) return hipSuccess;
+  if (a.n_groups <= 0 && a.n_zero <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone) return launch_vf<kFp16, kScaleNone>(a, s);
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_vf<kBf16, kScaleNone>(a, s);
   if (vf == kFp32 && scale_mode == kScaleNone) return launch_vf<kFp32, kScaleNone>(a, s);
