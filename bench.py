@@ -621,8 +621,27 @@ def bench_scenarios(torch, dm, dosegen, args):
     reps = max(10, args.steps // 10)
     ms_step = time_launches(step, reps, 3)
     ms_epi = time_launches(epilogue, reps, 3)
+    # the beam sum done by the products: one launch per beam (the first
+    # storing, the others adding), then the epilogue on the scenario doses
+    d_f = torch.empty(n_scen, n, dtype=torch.float32, device="cuda")
+    fplan = dm.ScenarioPlan([[mats[s * n_beams + b] for b in range(n_beams)] for s in range(n_scen)],
+                            [[xs[b] for b in range(n_beams)] for _ in range(n_scen)], d_f, autotune=True)
+    out_f = torch.empty_like(out)
+
+    def step_fused():
+        fplan.launch()
+        dm.scenario_objective(d_f.view(n_scen, 1, n), p, w, prob=prob, seed=seed, out=out_f)
+
+    ms_fused = time_launches(step_fused, reps, 3)
+    step()
+    step_fused()
+    torch.cuda.synchronize()
+    fused_equal = bool(torch.equal(d_f.view(torch.int32), d_out.view(torch.int32))) and \
+        bool(torch.equal(out_f.view(torch.int64), out.view(torch.int64)))
+    fplan.close()
     epi_bytes = 4 * n * (n_scen * n_beams + 2 + 2 * n_scen)
     res = {"ms_step": round(ms_step, 4), "ms_epilogue": round(ms_epi, 4),
+           "ms_step_beam_sum_in_products": round(ms_fused, 4), "beam_sum_in_products_bitwise_equal": fused_equal,
            "epilogue_share": round(ms_epi / ms_step, 4), "scenarios": n_scen, "beams": n_beams,
            "voxels": n, "nnz": nnz_tot, "GNNZ_per_s": round(nnz_tot / (ms_step * 1e-3) / 1e9, 2),
            "epilogue_GBps_algorithmic": round(epi_bytes / (ms_epi * 1e-3) / 1e9, 1),
@@ -630,7 +649,7 @@ def bench_scenarios(torch, dm, dosegen, args):
     plan.close()
     for A in mats:
         A.close()
-    del entries, part, d_out, seed
+    del entries, part, d_out, seed, d_f
     torch.cuda.empty_cache()
     res["epilogue_full_grid"] = bench_epilogue_full(torch, dm, reps)
     return res

@@ -242,6 +242,30 @@ enum { DOSE_PLAN_AUTOTUNE = 1u };
 dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items, uint32_t flags,
                                    void* hip_stream, dose_batch_plan* out);
 dose_status dose_batch_plan_launch(dose_batch_plan p, void* hip_stream);
+
+/* Scenario doses of a robust plan in one plan launch, the beam sum done by
+ * the products themselves (Sec. I, II-A: the dose of every beam under every
+ * scenario, every iteration; one matrix per beam, Sec. II-B).  Scenario s's
+ * dose is d[s][v] = A_{s,0} x_{s,0} + A_{s,1} x_{s,1} + ... at voxel v, the
+ * FP32 sum of its beam doses in ascending beam order: the same bits as the
+ * beam products of dose_spmv_batched followed by the beam sum of
+ * dose_scenario_objective (whose d_out it equals), without writing or reading
+ * the beam doses.  The plan holds one launch per beam, in beam order, over
+ * all scenarios: beam 0's products store the voxel doses, every later beam's
+ * products add theirs to them (empty rows add +0); the launches are captured
+ * in one HIP graph that dose_batch_plan_launch replays.
+ *   mats: host array of n_scen * n_beams matrices, [s * n_beams + b], all
+ *         with the same number of rows (voxels) and one value and index format.
+ *   x:    host array of n_scen * n_beams device pointers, FP32 spot weights
+ *         of each matrix (the same beam may share them across scenarios).
+ *   d:    device FP32 [n_scen][n_rows], written; must not overlap any x.
+ * flags: DOSE_PLAN_AUTOTUNE as for dose_batch_plan_create (d is the timing
+ * runs' scratch).  Synchronous; the plan keeps the pointers.  Errors as for
+ * dose_batch_plan_create; DOSE_ERR_INVALID_ARGUMENT also for matrices of
+ * different row counts.  Destroy with dose_batch_plan_destroy. */
+dose_status dose_scenario_plan_create(const dose_matrix* mats, const float* const* x, int32_t n_scen,
+                                      int32_t n_beams, float* d, uint32_t flags, void* hip_stream,
+                                      dose_batch_plan* out);
 dose_status dose_batch_plan_destroy(dose_batch_plan p);
 
 /* Quadratic plan objective f = sum_v w_v (d_v - p_v)^2, accumulated in FP64

@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import DoseError
 
-__all__ = ["DoseError", "DoseMatrix", "SellMatrix", "sell_layout", "BatchPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
+__all__ = ["DoseError", "DoseMatrix", "SellMatrix", "sell_layout", "BatchPlan", "ScenarioPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
            "ScenarioObjective", "robust_seed",
            "csr_validate", "partition_preview", "byte_model", "DoseSpMV", "DoseObjective",
            "dose", "VALUE_FORMATS"]
@@ -340,6 +340,36 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class ScenarioPlan(BatchPlan):
+    """Scenario doses of a robust plan in one graph launch: ``d[s] = sum_b
+    A[s][b] x[s][b]`` (FP32, ascending beam order, the beam sum done by the
+    products: one launch per beam, the first storing, the others adding).
+    ``mats`` and ``xs`` are n_scen x n_beams nested lists (DoseMatrix, FP32
+    spot-weight tensors); ``d`` is (n_scen, n_rows) FP32."""
+
+    def __init__(self, mats, xs, d: torch.Tensor, autotune: bool = False, stream=None):
+        self._h = None
+        n_scen, n_beams = len(mats), len(mats[0])
+        if len(xs) != n_scen or any(len(row) != n_beams for row in mats) or any(len(row) != n_beams for row in xs):
+            raise ValueError("mats and xs must be n_scen x n_beams")
+        flat = [mats[s][b] for s in range(n_scen) for b in range(n_beams)]
+        fx = [xs[s][b] for s in range(n_scen) for b in range(n_beams)]
+        n = flat[0].n_rows
+        if d.shape != (n_scen, n):
+            raise ValueError(f"d has shape {tuple(d.shape)}, expected ({n_scen}, {n})")
+        _dev_ptr(d, n_scen * n, "d", flat[0].device)
+        for A, x in zip(flat, fx):
+            _dev_ptr(x, A.n_cols, "x", A.device)
+        self._keep = (flat, fx, d)
+        ha = (ctypes.c_void_p * len(flat))(*[A.handle for A in flat])
+        hx = (ctypes.c_void_p * len(fx))(*[x.data_ptr() for x in fx])
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().dose_scenario_plan_create(ha, hx, n_scen, n_beams, d.data_ptr(),
+                                                         _lib.PLAN_AUTOTUNE if autotune else 0,
+                                                         _stream_handle(stream), ctypes.byref(h)))
+        self._h = h
 
 
 def objective(d, p, w, seed: torch.Tensor | None = None, out: torch.Tensor | None = None,

@@ -82,6 +82,7 @@ SIGNATURES = {
     "dose_spmv_batched": ([ctypes.POINTER(BatchItem), _i32, _vp], _i32),
     "dose_batch_plan_create": ([ctypes.POINTER(BatchItem), _i32, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_batch_plan_launch": ([_vp, _vp], _i32),
+    "dose_scenario_plan_create": ([_vp, _vp, _i32, _i32, _vp, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_batch_plan_destroy": ([_vp], _i32),
     "dose_objective": ([_i64, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
     "dose_norm2": ([_i64, _vp, _vp, _vp], _i32),

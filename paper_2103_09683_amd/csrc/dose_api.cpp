@@ -569,12 +569,19 @@ void tune_store(const std::string& key, int v) {
 }  // namespace
 
 // ------------------------------------------------------------ batch plans
+// One launch of a plan: the arguments of its items and the groups of all of
+// them (a work list of descriptor copies naming their item).
+struct PlanLayer {
+  int lds_floats = 0;
+  int64_t n_work = 0;
+  DevBuf args, work;
+};
+
 struct dose_batch_plan_s {
   int device = 0;
-  int vf = 0, sm = 0, n_rhs = 0, lds_floats = 0, idx_bytes = 4;
-  int64_t n_work = 0;
-  DevBuf args, work;  // per-item arguments; the groups of all items
-  std::vector<std::unique_ptr<Partition>> parts;  // autotuned partitions the work list was built from
+  int vf = 0, sm = 0, n_rhs = 0, idx_bytes = 4;
+  std::vector<PlanLayer> layers;  // launched one after another (one layer for a batch plan)
+  std::vector<std::unique_ptr<Partition>> parts;  // autotuned partitions the work lists were built from
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~dose_batch_plan_s() {
@@ -655,16 +662,11 @@ std::unique_ptr<Partition> autotune_matrix(dose_matrix_s* m, int n_rhs, const fl
   return best_p;
 }
 
-dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uint32_t flags, hipStream_t s) {
-  check_items(items, n_items);
-  auto plan = std::make_unique<dose_batch_plan_s>();
-  const dose_matrix_s* m0 = items[0].A;
-  plan->device = m0->device;
-  plan->vf = m0->vf;
-  plan->sm = scale_mode_A(m0);
-  plan->n_rhs = items[0].n_rhs;
-  plan->idx_bytes = m0->A.idx_bytes;
-  // the partition each distinct matrix runs under in this plan
+// The partition each distinct matrix of the items runs under in a plan: its
+// own, or with DOSE_PLAN_AUTOTUNE a tuned copy the plan keeps.
+std::map<const dose_matrix_s*, const Partition*> plan_partitions(dose_batch_plan_s* plan,
+                                                                 const dose_batch_item* items, int32_t n_items,
+                                                                 uint32_t flags, hipStream_t s) {
   std::map<const dose_matrix_s*, const Partition*> part_of;
   for (int32_t i = 0; i < n_items; ++i) {
     dose_matrix_s* m = items[i].A;
@@ -679,34 +681,87 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
     }
     part_of[m] = P;
   }
-  std::vector<SpmvArgs> args(n_items);
+  return part_of;
+}
+
+// One launch over the groups of all items; with accumulate, each item's
+// products are added to what its y holds.
+PlanLayer make_layer(const dose_batch_plan_s* plan, const dose_batch_item* items, int32_t n_items,
+                     const std::map<const dose_matrix_s*, const Partition*>& part_of, int accumulate,
+                     hipStream_t s) {
+  PlanLayer L;
+  std::vector<SpmvArgs> args(static_cast<size_t>(n_items));
   std::vector<GroupDesc> work;
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_matrix_s* m = items[i].A;
-    const Partition& P = *part_of[m];
+    const Partition& P = *part_of.at(m);
     args[i] = make_args(m, m->A, P, plan->sm, plan->n_rhs, items[i].x, items[i].y);
-    plan->lds_floats = std::max(plan->lds_floats, args[i].win_floats);
+    args[i].accumulate = accumulate;
+    L.lds_floats = std::max(L.lds_floats, args[i].win_floats);
     for (GroupDesc g : P.h_groups) {
       g.item = static_cast<uint32_t>(i);
       work.push_back(g);
     }
   }
-  plan->n_work = static_cast<int64_t>(work.size());
-  if (plan->n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
-  plan->args = DevBuf(args.size() * sizeof(SpmvArgs));
-  plan->work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
-  HIP_CHECK(hipMemcpyAsync(plan->args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
+  L.n_work = static_cast<int64_t>(work.size());
+  if (L.n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
+  L.args = DevBuf(args.size() * sizeof(SpmvArgs));
+  L.work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
+  HIP_CHECK(hipMemcpyAsync(L.args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
   if (!work.empty())
-    HIP_CHECK(hipMemcpyAsync(plan->work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(L.work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
   HIP_CHECK(hipStreamSynchronize(s));
+  return L;
+}
+
+std::unique_ptr<dose_batch_plan_s> new_plan(const dose_batch_item* items) {
+  auto plan = std::make_unique<dose_batch_plan_s>();
+  const dose_matrix_s* m0 = items[0].A;
+  plan->device = m0->device;
+  plan->vf = m0->vf;
+  plan->sm = scale_mode_A(m0);
+  plan->n_rhs = items[0].n_rhs;
+  plan->idx_bytes = m0->A.idx_bytes;
+  return plan;
+}
+
+dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uint32_t flags, hipStream_t s) {
+  check_items(items, n_items);
+  auto plan = new_plan(items);
+  const auto part_of = plan_partitions(plan.get(), items, n_items, flags, s);
+  plan->layers.push_back(make_layer(plan.get(), items, n_items, part_of, 0, s));
   return plan.release();
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
-  BatchTable t{};
-  t.args = p->args.get<SpmvArgs>();
-  t.work = p->work.get<GroupDesc>();
-  HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, p->n_work, p->lds_floats, s));
+  for (const PlanLayer& L : p->layers) {
+    BatchTable t{};
+    t.args = L.args.get<SpmvArgs>();
+    t.work = L.work.get<GroupDesc>();
+    HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, L.n_work, L.lds_floats, s));
+  }
+}
+
+// Captures a built plan's launches into its HIP graph.
+void capture_plan(dose_batch_plan_s* p) {
+  hipStream_t cap;
+  HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    try {
+      enqueue_plan(p, cap);
+    } catch (...) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(cap, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      (void)hipStreamDestroy(cap);
+      throw;
+    }
+    e = hipStreamEndCapture(cap, &p->graph);
+  }
+  (void)hipStreamDestroy(cap);
+  HIP_CHECK(e);
+  HIP_CHECK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
 }
 
 // ------------------------------------------------- item tables of batched calls
@@ -1219,25 +1274,59 @@ dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items
     check_items(items, n_items);
     DeviceGuard g(items[0].A->device);
     std::unique_ptr<dose_batch_plan_s> p(build_plan(items, n_items, flags, as_stream(hip_stream)));
-    hipStream_t cap;
-    HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      try {
-        enqueue_plan(p.get(), cap);
-      } catch (...) {
-        hipGraph_t tmp = nullptr;
-        (void)hipStreamEndCapture(cap, &tmp);
-        if (tmp) (void)hipGraphDestroy(tmp);
-        (void)hipStreamDestroy(cap);
-        throw;
-      }
-      e = hipStreamEndCapture(cap, &p->graph);
-    }
-    (void)hipStreamDestroy(cap);
-    HIP_CHECK(e);
-    HIP_CHECK(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    capture_plan(p.get());
     *out = p.release();
+  });
+}
+
+dose_status dose_scenario_plan_create(const dose_matrix* mats, const float* const* x, int32_t n_scen,
+                                      int32_t n_beams, float* d, uint32_t flags, void* hip_stream,
+                                      dose_batch_plan* out) {
+  return guarded([&] {
+    if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    if (!mats || !x || n_scen < 1 || n_beams < 1 || n_scen > kMaxScenarios || n_beams > kMaxScenarios)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "bad matrices, spot weights or counts");
+    const int64_t n_items = static_cast<int64_t>(n_scen) * n_beams;
+    if (n_items > INT32_MAX) fail(DOSE_ERR_INVALID_ARGUMENT, "too many items");
+    for (int64_t i = 0; i < n_items; ++i)
+      if (!mats[i]) fail(DOSE_ERR_INVALID_ARGUMENT, "null matrix");
+    const int64_t n = mats[0]->A.n_rows;
+    if (n > 0 && !d) fail(DOSE_ERR_INVALID_ARGUMENT, "d is null");
+    const size_t d_bytes = static_cast<size_t>(n_scen) * static_cast<size_t>(n) * 4;
+    // items of beam b: (scenario s, beam b) for every s, writing scenario s's dose
+    std::vector<dose_batch_item> items(static_cast<size_t>(n_items));
+    for (int32_t s = 0; s < n_scen; ++s)
+      for (int32_t b = 0; b < n_beams; ++b) {
+        const int64_t i = static_cast<int64_t>(s) * n_beams + b;
+        if (mats[i]->A.n_rows != n) fail(DOSE_ERR_INVALID_ARGUMENT, "beam matrices of different dose grids");
+        if (overlaps(x[i], mats[i]->A.n_cols * 4, d, d_bytes)) fail(DOSE_ERR_INVALID_ARGUMENT, "x overlaps d");
+        dose_batch_item& it = items[static_cast<size_t>(b) * n_scen + s];
+        it = dose_batch_item{};
+        it.A = mats[i];
+        it.n_rhs = 1;
+        it.x = x[i];
+        it.ldx = 1;
+        it.y = d + static_cast<int64_t>(s) * n;
+        it.ldy = 1;
+      }
+    for (int32_t b = 0; b < n_beams; ++b) check_items(items.data() + static_cast<size_t>(b) * n_scen, n_scen);
+    for (int64_t i = 0; i < n_items; ++i)
+      if (mats[i]->vf != mats[0]->vf || mats[i]->A.idx_bytes != mats[0]->A.idx_bytes ||
+          mats[i]->device != mats[0]->device)
+        fail(DOSE_ERR_UNSUPPORTED, "beam matrices mix formats or devices");
+    DeviceGuard g(items[0].A->device);
+    hipStream_t s = as_stream(hip_stream);
+    auto plan = new_plan(items.data());
+    const auto part_of = plan_partitions(plan.get(), items.data(), static_cast<int32_t>(n_items), flags, s);
+    // one launch per beam, in ascending beam order: the first stores, the
+    // others add, so that each voxel's dose is the FP32 sum of its beam doses
+    // in ascending beam order
+    for (int32_t b = 0; b < n_beams; ++b)
+      plan->layers.push_back(make_layer(plan.get(), items.data() + static_cast<size_t>(b) * n_scen, n_scen, part_of,
+                                        b > 0 ? 1 : 0, s));
+    capture_plan(plan.get());
+    *out = plan.release();
   });
 }
 
@@ -1456,31 +1545,43 @@ dose_status dose_sell_create(const dose_csr_host* csr, int32_t vf, int32_t xf, i
     std::vector<SellRun> h_runs;
     if (runs) {
       std::vector<uint64_t> cnt(static_cast<size_t>(n_pos) + 1, 0);
-      for (int64_t i = 0; i < m->n_rows; ++i) {
-        const uint32_t r = m->h_perm[i];
-        uint64_t n = rp[r + 1] > rp[r] ? 1 : 0;
-        for (int64_t k = rp[r] + 1; k < rp[r + 1]; ++k) n += csr->col_idx[k] != csr->col_idx[k - 1] + 1;
-        cnt[i + 1] = n;
-      }
+      // rows split among host threads (each position's runs depend on its row only)
+      const int64_t parts = std::max<int64_t>(1, std::min<int64_t>(16, m->n_rows / 65536));
+      auto in_parallel = [&](auto&& body) {
+        if (parts == 1) return body(int64_t{0}, m->n_rows);
+        std::vector<std::thread> th;
+        for (int64_t q = 0; q < parts; ++q) th.emplace_back(body, m->n_rows * q / parts, m->n_rows * (q + 1) / parts);
+        for (auto& t : th) t.join();
+      };
+      in_parallel([&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+          const uint32_t r = m->h_perm[i];
+          uint64_t n = rp[r + 1] > rp[r] ? 1 : 0;
+          for (int64_t k = rp[r] + 1; k < rp[r + 1]; ++k) n += csr->col_idx[k] != csr->col_idx[k - 1] + 1;
+          cnt[i + 1] = n;
+        }
+      });
       for (int64_t i = 0; i < n_pos; ++i) cnt[i + 1] += cnt[i];
       if (cnt[n_pos] >= uint64_t{0xFFFFFFFF}) fail(DOSE_ERR_UNSUPPORTED, "more than 2^32 - 2 runs");
       m->n_runs = static_cast<int64_t>(cnt[n_pos]);
       h_run_ptr.assign(cnt.begin(), cnt.end());
       h_runs.resize(static_cast<size_t>(std::max<int64_t>(m->n_runs, 1)));
-      for (int64_t i = 0; i < m->n_rows; ++i) {
-        const uint32_t r = m->h_perm[i];
-        uint64_t o = cnt[i];
-        for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
-          const int32_t pos = static_cast<int32_t>(k - rp[r]);
-          if (k > rp[r] && csr->col_idx[k] == csr->col_idx[k - 1] + 1) {
-            h_runs[o - 1].end = pos + 1;
-          } else {
-            h_runs[o].end = pos + 1;
-            h_runs[o].delta = csr->col_idx[k] - pos;
-            ++o;
+      in_parallel([&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+          const uint32_t r = m->h_perm[i];
+          uint64_t o = cnt[i];
+          for (int64_t k = rp[r]; k < rp[r + 1]; ++k) {
+            const int32_t pos = static_cast<int32_t>(k - rp[r]);
+            if (k > rp[r] && csr->col_idx[k] == csr->col_idx[k - 1] + 1) {
+              h_runs[o - 1].end = pos + 1;
+            } else {
+              h_runs[o].end = pos + 1;
+              h_runs[o].delta = csr->col_idx[k] - pos;
+              ++o;
+            }
           }
         }
-      }
+      });
       for (int64_t g = 0; g < m->n_groups; ++g) {
         const int64_t nr = static_cast<int64_t>(cnt[(g + 1) * kSellGroupRows] - cnt[g * kSellGroupRows]);
         if (nr > kSellMaxGroupRuns)

@@ -79,7 +79,7 @@ struct SpmvArgs {
   int32_t xcd_blocks;       // 0, or 8: workgroups go to the chip's 8 dies round-robin; give each die
                             // one contiguous eighth of the groups (so its L2 sees one eighth of the
                             // gathered vector); the order of every row's sum is unchanged
-  int32_t pad0;
+  int32_t accumulate;       // 1: y[row] = y[row] + row value (empty rows: + 0) instead of the value
 };
 
 // Entries of a quarter: lane l of a step loads the 4 entries at 4 l and at

@@ -304,8 +304,10 @@ __device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, ui
   const bool in = r < r_end;
   if (in && rc.hi == rc.lo) {
     T* dst = static_cast<T*>(a.y) + static_cast<int64_t>(r) * NRHS;
+    // accumulating products add +0 (so that a -0 already there becomes +0,
+    // as in a sum of doses)
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) dst[q] = T(0);
+    for (int q = 0; q < NRHS; ++q) dst[q] = a.accumulate ? dst[q] + T(0) : T(0);
   }
   rc.mask = __ballot(in && rc.hi > rc.lo);
 }
@@ -483,12 +485,17 @@ __device__ __forceinline__ void add_half(const T (&p)[kChunk][NRHS], int s0, int
   for (int q = 0; q < NRHS; ++q) L[q] += s[q];
 }
 
-// Row value (valid in lane 63) times the row scale of an E4M3 operand.
+// Row value (valid in lane 63) times the row scale of an E4M3 operand, stored
+// or (a.accumulate: products of several matrices into one y, one launch after
+// another) added to what y holds.
 template <class T, int SM, int NRHS>
 __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float sc, const T (&tot)[NRHS]) {
   T* dst = static_cast<T*>(a.y) + static_cast<int64_t>(row) * NRHS;
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q) dst[q] = SM == kScaleRow ? tot[q] * static_cast<T>(sc) : tot[q];
+  for (int q = 0; q < NRHS; ++q) {
+    const T v = SM == kScaleRow ? tot[q] * static_cast<T>(sc) : tot[q];
+    dst[q] = a.accumulate ? dst[q] + v : v;
+  }
 }
 
 // One wave's share of a group: rows [r_begin, r_end), or with SPLIT the one
@@ -574,6 +581,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   // step is refilled first.
   constexpr bool kEarly = WIN && SM != kScaleCol;
   Chunk<VF, IX> cs[DEPTH + 1];
+  Gathered<T, NRHS> g;
 #pragma unroll
   for (int d = 0; d < (kEarly ? DEPTH + 1 : DEPTH); ++d) load_step<VF, IX>(vb, cb, kbeg + d * stride, pmin, pmax, cs[d]);
   if (has_rows) {
@@ -605,80 +613,96 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
     for (int s = 0; s < kRowSlots; ++s) W[s][q] = T(0);
   }
   int k = kbeg;
-  while (true) {
+  // the rows that meet step k take their entries of the step's products p
+  // (none once the wave is past its last step)
+  auto rows_of_step = [&](const T (&p)[kChunk][NRHS]) {
+    const int s0 = k * kStepEntries;
+    const int pq = s0 + lane * kQuarter;
+    while (k <= kend && cr.valid && cr.ks < s0 + kStepEntries) {
+      const bool lng = SPLIT || cr.lng;
+      if (lng) {
+        T h0[NRHS], h1[NRHS];
+        if (cr.ks <= s0 && cr.ke >= s0 + kStepEntries) {
+          quarter_full<T, 0, NRHS>(p, h0);
+          quarter_full<T, 1, NRHS>(p, h1);
+        } else {
+          const uint32_t len = static_cast<uint32_t>(cr.ke - cr.ks);
+          quarter_sum<T, 0, NRHS>(p, pq - cr.ks, len, h0);
+          quarter_sum<T, 1, NRHS>(p, pq + kHalf - cr.ks, len, h1);
+        }
+        const int slot = (k - cr.kfirst) & (kRowSlots - 1);
 #pragma unroll
-    for (int ph = 0; ph <= DEPTH; ++ph) {
-      const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
-      Gathered<T, NRHS> g;
-      T p[kChunk][NRHS];
-      if constexpr (kEarly) {
-        products<T, VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+        for (int q = 0; q < NRHS; ++q) {
+          const T t = wave_reduce(h0[q] + h1[q]);
+#pragma unroll
+          for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : T(0);
+        }
+      } else {
+        add_half<T, 0, NRHS>(p, s0, pq, cr, L);
+        add_half<T, 1, NRHS>(p, s0, pq, cr, L);
+      }
+      if (k + stride <= cr.klast) break;  // the row goes on in a later step of this wave
+      // the wave's last step of the row; slots that received nothing hold
+      // +0, and no slot sum is ever -0, so adding them changes nothing
+      if (lng) {
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) tot[q] = wave_reduce(L[q]);
+      }
+      if constexpr (SM == kScaleRow) sc = a.scale[cr.row];
+      if constexpr (SPLIT) {
+        cr.valid = false;
+      } else {
+        if (lane == kWave - 1) store_row<T, SM, NRHS>(a, cr.row, sc, tot);
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) {
+          L[q] = T(-0.0);
+#pragma unroll
+          for (int s = 0; s < kRowSlots; ++s) W[s][q] = T(0);
+        }
+        cr = next_row<T, NRHS>(a, rc, r_end, origin32);
+      }
+    }
+  };
+  if constexpr (kEarly) {
+    while (true) {
+#pragma unroll
+      for (int ph = 0; ph <= DEPTH; ++ph) {
+        T p[kChunk][NRHS];
+        products<T, VF, SM, IX, NRHS, WIN>(cs[ph], g, xb, p);
         // the barriers keep the scheduler from moving the loads across the
         // products or sinking them below the row work
         __builtin_amdgcn_sched_barrier(0);
-        load_step<VF, IX>(vb, cb, k + (DEPTH + 1) * stride, pmin, pmax, cs[cur]);
+        load_step<VF, IX>(vb, cb, k + (DEPTH + 1) * stride, pmin, pmax, cs[ph]);
         __builtin_amdgcn_sched_barrier(0);
-      } else {
+        rows_of_step(p);
+        k += stride;
+      }
+      // one exit per turn of the ring: steps past the wave's last one do nothing
+      if (k > kend) break;
+    }
+  } else {
+    // the gathers of a step must go out before the next step's loads (so
+    // that waiting for them leaves those loads in flight): the buffer of the
+    // previous step is refilled first
+    while (true) {
+#pragma unroll
+      for (int ph = 0; ph <= DEPTH; ++ph) {
+        const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
+        T p[kChunk][NRHS];
         gather_global<T, VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
         load_step<VF, IX>(vb, cb, k + DEPTH * stride, pmin, pmax, cs[nxt]);
         // keep the scheduler from sinking the loads below the compute
         __builtin_amdgcn_sched_barrier(0);
         products<T, VF, SM, IX, NRHS, WIN>(cs[cur], g, xb, p);
+        rows_of_step(p);
+        k += stride;
       }
-      const int s0 = k * kStepEntries;
-      const int pq = s0 + lane * kQuarter;
-      // the rows that meet step k (none once the wave is past its last step)
-      while (k <= kend && cr.valid && cr.ks < s0 + kStepEntries) {
-        const bool lng = SPLIT || cr.lng;
-        if (lng) {
-          T h0[NRHS], h1[NRHS];
-          if (cr.ks <= s0 && cr.ke >= s0 + kStepEntries) {
-            quarter_full<T, 0, NRHS>(p, h0);
-            quarter_full<T, 1, NRHS>(p, h1);
-          } else {
-            const uint32_t len = static_cast<uint32_t>(cr.ke - cr.ks);
-            quarter_sum<T, 0, NRHS>(p, pq - cr.ks, len, h0);
-            quarter_sum<T, 1, NRHS>(p, pq + kHalf - cr.ks, len, h1);
-          }
-          const int slot = (k - cr.kfirst) & (kRowSlots - 1);
-#pragma unroll
-          for (int q = 0; q < NRHS; ++q) {
-            const T t = wave_reduce(h0[q] + h1[q]);
-#pragma unroll
-            for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : T(0);
-          }
-        } else {
-          add_half<T, 0, NRHS>(p, s0, pq, cr, L);
-          add_half<T, 1, NRHS>(p, s0, pq, cr, L);
-        }
-        if (k + stride <= cr.klast) break;  // the row goes on in a later step of this wave
-        // the wave's last step of the row; slots that received nothing hold
-        // +0, and no slot sum is ever -0, so adding them changes nothing
-        if (lng) {
-#pragma unroll
-          for (int q = 0; q < NRHS; ++q) tot[q] = (W[0][q] + W[1][q]) + (W[2][q] + W[3][q]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < NRHS; ++q) tot[q] = wave_reduce(L[q]);
-        }
-        if constexpr (SM == kScaleRow) sc = a.scale[cr.row];
-        if constexpr (SPLIT) {
-          cr.valid = false;
-        } else {
-          if (lane == kWave - 1) store_row<T, SM, NRHS>(a, cr.row, sc, tot);
-#pragma unroll
-          for (int q = 0; q < NRHS; ++q) {
-            L[q] = T(-0.0);
-#pragma unroll
-            for (int s = 0; s < kRowSlots; ++s) W[s][q] = T(0);
-          }
-          cr = next_row<T, NRHS>(a, rc, r_end, origin32);
-        }
-      }
-      k += stride;
+      // one exit per turn of the ring: steps past the wave's last one do nothing
+      if (k > kend) break;
     }
-    // one exit per turn of the ring: steps past the wave's last one do nothing
-    if (k > kend) break;
   }
 }
 

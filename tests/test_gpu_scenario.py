@@ -356,3 +356,61 @@ def test_robust_step_at_bench_size(dev):
     plan.close()
     for A in mats:
         A.close()
+
+
+@pytest.mark.parametrize("n_scen,n_beams", [(3, 2), (9, 4)])
+@pytest.mark.parametrize("autotune", [False, True])
+def test_scenario_plan_sums_beams_in_the_products(n_scen, n_beams, autotune, dev):
+    """The scenario plan (one launch per beam, the first storing, the others
+    adding) gives each scenario's dose bit for bit as the beam products
+    followed by the epilogue's FP32 beam sum, on every graph replay (with
+    eager work between replays), and so the same objectives."""
+    specs, mats, host, xs, p, w = _scenario_case(n_scen, n_beams)
+    n = specs[0].n_rows
+    pd, wd = torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda()
+    part = _beam_doses(mats, xs, n_scen, n_beams, n)
+    d_ref = torch.empty(n_scen, n, device=dev)
+    out_ref = dm.scenario_objective(part, pd, wd, d_out=d_ref)
+    torch.cuda.synchronize()
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    d = torch.full((n_scen, n), float("nan"), device=dev)
+    plan = dm.ScenarioPlan([[mats[s * n_beams + b] for b in range(n_beams)] for s in range(n_scen)],
+                           [[xd[b] for b in range(n_beams)] for _ in range(n_scen)], d, autotune=autotune)
+    for rep in range(3):
+        d.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(d.cpu().numpy()), _bits(d_ref.cpu().numpy())), rep
+        junk = torch.rand(1 << 20, device=dev).sum()  # eager work between replays
+        del junk
+    out = dm.scenario_objective(d.view(n_scen, 1, n), pd, wd)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), out_ref.cpu().numpy().view(np.uint64))
+    plan.close()
+    for A in mats:
+        A.close()
+
+
+def test_scenario_plan_argument_errors(dev):
+    specs, mats, host, xs, p, w = _scenario_case(2, 2)
+    n = specs[0].n_rows
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    grid = [[mats[s * 2 + b] for b in range(2)] for s in range(2)]
+    with pytest.raises(ValueError):
+        dm.ScenarioPlan(grid, [[xd[0], xd[1]]], torch.empty(2, n, device=dev))
+    with pytest.raises(ValueError):
+        dm.ScenarioPlan(grid, [[xd[0], xd[1]]] * 2, torch.empty(3, n, device=dev))
+    lib = _lib.load()
+    import ctypes
+    ha = (ctypes.c_void_p * 4)(*[A.handle for s in grid for A in s])
+    hx = (ctypes.c_void_p * 4)(*[x.data_ptr() for x in (xd[0], xd[1], xd[0], xd[1])])
+    h = ctypes.c_void_p()
+    d = torch.empty(2, n, device=dev)
+    assert lib.dose_scenario_plan_create(ha, hx, 0, 2, d.data_ptr(), 0, None, ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
+    assert lib.dose_scenario_plan_create(None, hx, 2, 2, d.data_ptr(), 0, None, ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
+    # d overlapping a spot-weight vector
+    hx2 = (ctypes.c_void_p * 4)(*[d.data_ptr()] * 4)
+    assert lib.dose_scenario_plan_create(ha, hx2, 2, 2, d.data_ptr(), 0, None, ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
+    for A in mats:
+        A.close()
