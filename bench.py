@@ -545,37 +545,86 @@ def bench_bias_controls(torch, dm, dosegen, spec, x, args):
     return res
 
 
+BATCH_SELL_SIGMA = 16384
+
+
 def bench_batched(torch, dm, dosegen, args):
+    """The 36 beam x scenario matrices of a robust plan, four spot-weight
+    vectors each, in one autotuned CSR plan launch (FP16 and BF16), and the
+    FP16 matrices in SELL-C-sigma form (sigma 16,384, 16-bit indices; 32-bit
+    beyond 65,536 columns) in one SELL plan launch.  With four vectors the
+    SELL kernel is bound by its per-entry work rather than by HBM, and
+    16-bit indices beat run-length ones there (1.74 against 2.06 ms at a
+    quarter of the batch); sigma 16,384 keeps a chunk's rows near one
+    another, so nearly every chunk's four-vector x window fits in LDS
+    (65,536: 2.80 ms).
+    Algorithmic bytes: the paper format's 6 bytes per entry and 4 per row
+    offset, x and y read / written once (four vectors); the SELL line also
+    gives its own format's algorithmic bytes."""
     import numpy as np
     specs = dosegen.robust_batch(args.batch_scale)
     res = {}
     for fmt in ("fp16", "bf16"):
-        mats, entries, nnz_tot, bytes_tot = [], [], 0, 0
+        mats, sells, entries, sentries = [], [], [], []
+        nnz_tot = bytes_tot = sell_bytes = 0
+        sell_idx = set()
         t0 = time.time()
         for s in specs:
             rp, cols, vals = dosegen.csr(s)
             A = dm.DoseMatrix(rp, cols, vals, s.n_cols, fmt)
             X = torch.from_numpy(np.stack([dosegen.spot_weights(s.seed, 4 * s.matrix_id + r, s.n_cols)
-                                           for r in range(4)], 1)).cuda()
+                                           for r in range(4)], 1)).cuda().contiguous()
             Y = torch.empty(s.n_rows, 4, dtype=torch.float32, device="cuda")
             mats.append(A)
-            entries.append((A, X.contiguous(), Y))
+            entries.append((A, X, Y))
             inf = A.info()
             nnz_tot += inf["nnz"]
-            bytes_tot += inf["nnz"] * 6 + (inf["n_rows"] + 1) * 4 + 4 * (4 * inf["n_cols"] + 4 * inf["n_rows"])
+            extra = 4 * (4 * inf["n_cols"] + 4 * inf["n_rows"])
+            bytes_tot += inf["nnz"] * 6 + (inf["n_rows"] + 1) * 4 + extra
+            if fmt == "fp16":
+                S = dm.SellMatrix(rp, cols, vals, s.n_cols, fmt, sigma=BATCH_SELL_SIGMA,
+                                  index_format="u16" if s.n_cols <= 65536 else "i32")
+                sell_idx.add(S.index_format)
+                sells.append(S)
+                sentries.append((S, X, torch.empty_like(Y)))
+                # the format's own bytes for one vector, plus three more of x and y
+                sell_bytes += S.info()["spmv_bytes"] + 3 * 4 * (inf["n_cols"] + inf["n_rows"])
+            del rp, cols, vals
         log(f"batched {fmt}: 36 matrices, {nnz_tot} nnz, built in {time.time() - t0:.1f}s")
         plan = dm.BatchPlan(entries, autotune=True)
-        ms = time_launches(plan.launch, max(10, args.steps // 10), 3)
+        reps = max(10, args.steps // 10)
+        ms = time_launches(plan.launch, reps, 3)
         res[fmt] = {"ms": round(ms, 4), "matrices": len(specs), "n_rhs": 4, "nnz": nnz_tot,
                     "GNNZ_rhs_per_s": round(4 * nnz_tot / (ms * 1e-3) / 1e9, 2),
                     "GNNZ_per_s": round(nnz_tot / (ms * 1e-3) / 1e9, 2),
                     "GBps_algorithmic": round(bytes_tot / (ms * 1e-3) / 1e9, 1),
                     "frac": round(bytes_tot / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
                     "batch_scale": args.batch_scale}
+        log(f"batched {fmt} CSR: {ms:.4f} ms, {res[fmt]['frac']:.3f} of 8 TB/s")
         plan.close()
-        for A in mats:
-            A.close()
-        del entries
+        if sells:
+            splan = dm.SellBatchPlan(sentries)
+            ms_s = time_launches(splan.launch, reps, 3)
+            splan.close()
+            torch.cuda.synchronize()
+            rel = 0.0
+            for (_, _, Yc), (_, _, Ys) in zip(entries, sentries):
+                d = (Ys.double() - Yc.double()).abs() / Yc.double().abs().clamp_min(1e-300)
+                rel = max(rel, float(d.max()) if d.numel() else 0.0)
+            res[fmt + "_sell"] = {
+                "ms": round(ms_s, 4), "index": "/".join(sorted(sell_idx)), "sigma": BATCH_SELL_SIGMA, "n_rhs": 4,
+                "GNNZ_rhs_per_s": round(4 * nnz_tot / (ms_s * 1e-3) / 1e9, 2),
+                "GNNZ_per_s": round(nnz_tot / (ms_s * 1e-3) / 1e9, 2),
+                "GBps_paper_format_bytes": round(bytes_tot / (ms_s * 1e-3) / 1e9, 1),
+                "frac_paper_format_bytes": round(bytes_tot / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "GBps_algorithmic": round(sell_bytes / (ms_s * 1e-3) / 1e9, 1),
+                "frac": round(sell_bytes / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                "speedup_vs_csr": round(ms / ms_s, 3), "max_rel_diff_vs_csr": rel}
+            log(f"batched {fmt} SELL ({res[fmt + '_sell']['index']}): {ms_s:.4f} ms, "
+                f"{ms / ms_s:.2f}x the CSR plan, max rel diff {rel:.2e}")
+        for M in mats + sells:
+            M.close()
+        del entries, sentries
         torch.cuda.empty_cache()
     return res
 

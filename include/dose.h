@@ -381,7 +381,8 @@ typedef struct {
   int32_t chunk_rows;         /* C = 64                                       */
   int32_t sigma;
   int64_t n_chunks;           /* ceil(n_rows / 64)                            */
-  int64_t n_groups;           /* workgroups of a product: 4 chunks each       */
+  int64_t n_groups;           /* row groups: one chunk each (chunk count
+                                 rounded up to whole groups)                  */
   int64_t n_groups_windowed;  /* groups whose x window fits in LDS            */
   int64_t std_slots;          /* 64 * sum of chunk widths: Kreutzer's layout  */
   int64_t n_runs;             /* DOSE_IDX_RUNS: runs stored (else 0)          */
@@ -439,6 +440,40 @@ dose_status dose_sell_runs(dose_sell m, int64_t* run_ptr, int32_t* start, int32_
  * and the three index formats give the same bits.  Asynchronous on
  * hip_stream. */
 dose_status dose_sell_spmv(dose_sell m, const float* x, float* y, void* hip_stream);
+
+/* Y = A X for n_rhs spot-weight vectors at once (n_rhs 1, 2 or 4; the
+ * multi-vector product of robust planning, Sec. I, II-A): x device
+ * [n_cols][n_rhs], y device [n_rows][n_rhs] FP32, row-major (vector r at
+ * offset r), both aligned to n_rhs floats, not overlapping (else
+ * DOSE_ERR_INVALID_ARGUMENT); n_cols * n_rhs below 2^31 (else
+ * DOSE_ERR_UNSUPPORTED).  Every entry is read once; each vector's rows are
+ * summed in dose_sell_spmv's order, so column r of y is bitwise
+ * dose_sell_spmv of column r of x.  Asynchronous on hip_stream. */
+dose_status dose_sell_spmv_multi(dose_sell m, int32_t n_rhs, const float* x, float* y, void* hip_stream);
+
+/* One item of a batched SELL-C-sigma product: Y = S X as for
+ * dose_sell_spmv_multi, with ldx == ldy == n_rhs. */
+typedef struct {
+  dose_sell S;
+  int32_t n_rhs;
+  int32_t reserved;
+  const float* x; /* device */
+  int64_t ldx;
+  float* y;       /* device */
+  int64_t ldy;
+} dose_sell_batch_item;
+
+/* A plan of many SELL-C-sigma products in ONE launch (the batch of matrices
+ * robust optimisation multiplies every iteration, Sec. I, II-A, II-B): the
+ * chunks of every item form one work list on the device, captured into a HIP
+ * graph that dose_batch_plan_launch replays (destroy with
+ * dose_batch_plan_destroy).  Each y is bitwise dose_sell_spmv_multi's.  All
+ * items share one value format, one index format and one n_rhs and live on
+ * one device (else DOSE_ERR_UNSUPPORTED / DOSE_ERR_INVALID_ARGUMENT); no y
+ * may overlap another item's y or any item's x.  flags must be 0.  The plan
+ * keeps the items' pointers.  Synchronous. */
+dose_status dose_sell_batch_plan_create(const dose_sell_batch_item* items, int32_t n_items, uint32_t flags,
+                                        void* hip_stream, dose_batch_plan* out);
 
 /* Frees the device memory after synchronising the device. */
 dose_status dose_sell_destroy(dose_sell m);

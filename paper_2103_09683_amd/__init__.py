@@ -17,7 +17,7 @@ import torch
 from . import _lib
 from ._lib import DoseError
 
-__all__ = ["DoseError", "DoseMatrix", "SellMatrix", "sell_layout", "BatchPlan", "ScenarioPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
+__all__ = ["DoseError", "DoseMatrix", "SellMatrix", "sell_layout", "BatchPlan", "SellBatchPlan", "ScenarioPlan", "spmv_batched", "objective", "norm2", "scenario_objective",
            "ScenarioObjective", "robust_seed",
            "csr_validate", "partition_preview", "byte_model", "DoseSpMV", "DoseObjective",
            "dose", "VALUE_FORMATS"]
@@ -269,7 +269,22 @@ class SellMatrix:
         return run_ptr, start[:inf["n_runs"]], length[:inf["n_runs"]]
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """y = A x (FP32), asynchronous on the current (or given) stream."""
+        """y = A x (FP32), asynchronous on the current (or given) stream.  x of
+        shape (n_cols,) gives y (n_rows,); x (n_cols, n_rhs) with n_rhs 1, 2
+        or 4 gives y (n_rows, n_rhs), each column bitwise the product of x's
+        column."""
+        if x.dim() == 2:
+            n_rhs = x.shape[1]
+            if x.shape[0] != self.n_cols:
+                raise ValueError(f"x has shape {tuple(x.shape)}, expected ({self.n_cols}, n_rhs)")
+            if y is None:
+                y = torch.empty(self.n_rows, n_rhs, dtype=torch.float32, device=x.device)
+            if y.shape != (self.n_rows, n_rhs):
+                raise ValueError(f"y has shape {tuple(y.shape)}, expected ({self.n_rows}, {n_rhs})")
+            _lib.check(_lib.load().dose_sell_spmv_multi(
+                self.handle, n_rhs, _dev_ptr(x, self.n_cols * n_rhs, "x", self.device),
+                _dev_ptr(y, self.n_rows * n_rhs, "y", self.device), _stream_handle(stream)))
+            return y
         if y is None:
             y = torch.empty(self.n_rows, dtype=torch.float32, device=x.device)
         _lib.check(_lib.load().dose_sell_spmv(self.handle, _dev_ptr(x, self.n_cols, "x", self.device),
@@ -340,6 +355,33 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+class SellBatchPlan(BatchPlan):
+    """Many SELL-C-sigma products in one launch, captured into a HIP graph:
+    entries are (SellMatrix, x, y) with x (n_cols,) or (n_cols, n_rhs) and y
+    (n_rows,) or (n_rows, n_rhs), contiguous FP32 on the matrix's device."""
+
+    def __init__(self, entries, stream=None):
+        self._h = None
+        self._keep = list(entries)
+        arr = (_lib.SellBatchItem * len(entries))()
+        for i, (S, x, y) in enumerate(entries):
+            for name, t in (("x", x), ("y", y)):
+                if not isinstance(t, torch.Tensor) or t.dim() not in (1, 2):
+                    raise TypeError(f"item {i}: {name} must be a 1- or 2-dimensional tensor")
+            n_rhs = 1 if x.dim() == 1 else x.shape[1]
+            if x.shape != ((S.n_cols,) if x.dim() == 1 else (S.n_cols, n_rhs)):
+                raise ValueError(f"item {i}: x has shape {tuple(x.shape)}, expected ({S.n_cols}[, n_rhs])")
+            if y.shape != ((S.n_rows,) if x.dim() == 1 else (S.n_rows, n_rhs)):
+                raise ValueError(f"item {i}: y has shape {tuple(y.shape)}, expected the rows of x's layout")
+            _dev_ptr(x, S.n_cols * n_rhs, "x", S.device)
+            _dev_ptr(y, S.n_rows * n_rhs, "y", S.device)
+            arr[i] = _lib.SellBatchItem(S.handle, n_rhs, 0, x.data_ptr(), n_rhs, y.data_ptr(), n_rhs)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().dose_sell_batch_plan_create(arr, len(entries), 0, _stream_handle(stream),
+                                                           ctypes.byref(h)))
+        self._h = h
 
 
 class ScenarioPlan(BatchPlan):

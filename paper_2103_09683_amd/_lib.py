@@ -55,6 +55,12 @@ class BatchItem(ctypes.Structure):
                 ("ldy", ctypes.c_int64)]
 
 
+class SellBatchItem(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_void_p), ("n_rhs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p),
+                ("ldy", ctypes.c_int64)]
+
+
 class SellInfo(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("value_format", ctypes.c_int32), ("index_format", ctypes.c_int32),
@@ -98,6 +104,8 @@ SIGNATURES = {
     "dose_sell_decode": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "dose_sell_runs": ([_vp, _vp, _vp, _vp], _i32),
     "dose_sell_spmv": ([_vp, _vp, _vp, _vp], _i32),
+    "dose_sell_spmv_multi": ([_vp, _i32, _vp, _vp, _vp], _i32),
+    "dose_sell_batch_plan_create": ([ctypes.POINTER(SellBatchItem), _i32, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_sell_destroy": ([_vp], _i32),
     "dose_status_string": ([_i32], ctypes.c_char_p),
     "dose_last_error": ([], ctypes.c_char_p),

@@ -577,10 +577,20 @@ struct PlanLayer {
   DevBuf args, work;
 };
 
+// The launch of a SELL-C-sigma plan: its items' arguments and (item, chunk)
+// work lists.
+struct SellPlanLayer {
+  int64_t n_work = 0, n_zero = 0;
+  size_t lds_bytes = 0;
+  int xcd = 1;
+  DevBuf args, work, zero;
+};
+
 struct dose_batch_plan_s {
   int device = 0;
   int vf = 0, sm = 0, n_rhs = 0, idx_bytes = 4;
   std::vector<PlanLayer> layers;  // launched one after another (one layer for a batch plan)
+  std::vector<SellPlanLayer> sell_layers;  // a SELL-C-sigma plan's launch (then layers is empty)
   std::vector<std::unique_ptr<Partition>> parts;  // autotuned partitions the work lists were built from
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -739,6 +749,16 @@ void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
     t.args = L.args.get<SpmvArgs>();
     t.work = L.work.get<GroupDesc>();
     HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, L.n_work, L.lds_floats, s));
+  }
+  for (const SellPlanLayer& L : p->sell_layers) {
+    SellBatchTable t{};
+    t.args = L.args.get<SellArgs>();
+    t.work = L.work.get<uint2>();
+    t.zero = L.zero.get<uint2>();
+    t.n_work = L.n_work;
+    t.n_zero = L.n_zero;
+    t.xcd_blocks = L.xcd;
+    HIP_CHECK(launch_sell_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, L.lds_bytes, s));
   }
 }
 
@@ -994,7 +1014,8 @@ struct dose_sell_s {
   int64_t n_groups = 0;  // ceil(n_chunks / 4); the chunk and position arrays are padded to whole groups
   int64_t n_slices = 0, n_windowed = 0;
   int64_t std_slots = 0;  // 64 * sum of the chunks' widths (Kreutzer's layout)
-  int32_t win_floats = 0, idx_bytes = 4;  // idx_bytes 0: run-length indices
+  int32_t win_floats[3] = {0, 0, 0};  // LDS window floats for 1, 2 and 4 vectors
+  int32_t idx_bytes = 4;               // 0: run-length indices
   int64_t n_runs = 0;
   int32_t lds_runs = 0;  // most runs of one group
   int64_t n_work = 0, n_zero = 0;  // chunks with entries, chunks without
@@ -1006,7 +1027,7 @@ struct dose_sell_s {
 
 namespace {
 
-SellArgs sell_args(const dose_sell_s* m, const float* x, float* y) {
+SellArgs sell_args(const dose_sell_s* m, int n_rhs, const float* x, float* y) {
   SellArgs a{};
   a.chunks = m->chunks.get<SellChunk>();
   a.win = m->win.get<uint32_t>();
@@ -1023,12 +1044,87 @@ SellArgs sell_args(const dose_sell_s* m, const float* x, float* y) {
   a.y = y;
   a.n_groups = m->n_work;
   a.n_zero = m->n_zero;
-  a.win_floats = m->win_floats;
+  a.win_floats = m->win_floats[rhs_slot(n_rhs)];
   a.idx_bytes = m->idx_bytes;
   a.xcd_blocks = xcd_blocks(8);
   a.lds_runs = m->lds_runs;
   a.n_cols = static_cast<int32_t>(std::min<int64_t>(m->n_cols, INT32_MAX));
   return a;
+}
+
+// Arguments of a SELL-C-sigma product with n_rhs row-major vectors.
+void check_sell_product(const dose_sell_s* m, int32_t n_rhs, const float* x, const float* y) {
+  if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+  if (n_rhs != 1 && n_rhs != 2 && n_rhs != 4) fail(DOSE_ERR_UNSUPPORTED, "n_rhs must be 1, 2 or 4");
+  if ((m->n_cols > 0 && !x) || (m->n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
+  if (m->n_cols > INT32_MAX / n_rhs) fail(DOSE_ERR_UNSUPPORTED, "n_cols * n_rhs must stay below 2^31");
+  if (overlaps(x, m->n_cols * n_rhs * 4, y, m->n_rows * n_rhs * 4))
+    fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % (4 * static_cast<uintptr_t>(n_rhs)) != 0)
+    fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be aligned to n_rhs floats");
+}
+
+void check_sell_items(const dose_sell_batch_item* items, int32_t n_items) {
+  if (!items || n_items <= 0) fail(DOSE_ERR_INVALID_ARGUMENT, "no items");
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_sell_batch_item& it = items[i];
+    if (!it.S) fail(DOSE_ERR_INVALID_ARGUMENT, "item without matrix");
+    if (it.ldx != it.n_rhs || it.ldy != it.n_rhs) fail(DOSE_ERR_UNSUPPORTED, "ldx and ldy must equal n_rhs");
+    check_sell_product(it.S, it.n_rhs, it.x, it.y);
+    const dose_sell_s* m0 = items[0].S;
+    if (it.S->vf != m0->vf) fail(DOSE_ERR_UNSUPPORTED, "items mix value formats");
+    if (it.S->idx_bytes != m0->idx_bytes) fail(DOSE_ERR_UNSUPPORTED, "items mix index formats");
+    if (it.n_rhs != items[0].n_rhs) fail(DOSE_ERR_UNSUPPORTED, "items mix n_rhs");
+    if (it.S->device != m0->device) fail(DOSE_ERR_INVALID_ARGUMENT, "items on different devices");
+    const int64_t yb = it.S->n_rows * it.n_rhs * 4;
+    for (int32_t j = 0; j < n_items; ++j) {
+      const dose_sell_batch_item& o = items[j];
+      if (!o.S) continue;
+      // one launch reads every x while it writes every y
+      if (overlaps(o.x, o.S->n_cols * o.n_rhs * 4, it.y, yb)) fail(DOSE_ERR_INVALID_ARGUMENT, "a y overlaps an x");
+      if (j < i && overlaps(o.y, o.S->n_rows * o.n_rhs * 4, it.y, yb))
+        fail(DOSE_ERR_INVALID_ARGUMENT, "items share outputs");
+    }
+  }
+}
+
+// One launch over the chunks of all items: those holding entries, item by
+// item in chunk order, then those without (their rows get +0).
+dose_batch_plan_s* build_sell_plan(const dose_sell_batch_item* items, int32_t n_items, hipStream_t s) {
+  auto plan = std::make_unique<dose_batch_plan_s>();
+  const dose_sell_s* m0 = items[0].S;
+  plan->device = m0->device;
+  plan->vf = m0->vf;
+  plan->sm = m0->vf == kFp8 ? kScaleRow : kScaleNone;
+  plan->n_rhs = items[0].n_rhs;
+  plan->idx_bytes = m0->idx_bytes;
+  SellPlanLayer L;
+  std::vector<SellArgs> args(static_cast<size_t>(n_items));
+  std::vector<uint2> work, zero;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_sell_s* m = items[i].S;
+    args[i] = sell_args(m, plan->n_rhs, items[i].x, items[i].y);
+    L.lds_bytes = std::max(L.lds_bytes, sell_launch_lds_bytes(args[i]));
+    for (size_t c = 0; c < m->h_chunks.size(); ++c)
+      (m->h_chunks[c].n_slices > 0 ? work : zero).push_back(make_uint2(static_cast<uint32_t>(i),
+                                                                       static_cast<uint32_t>(c)));
+  }
+  L.n_work = static_cast<int64_t>(work.size());
+  L.n_zero = static_cast<int64_t>(zero.size());
+  if (L.n_work + (L.n_zero + kGroupWaves - 1) / kGroupWaves > int64_t{0x7fffffff})
+    fail(DOSE_ERR_UNSUPPORTED, "too many chunks for one launch");
+  L.xcd = xcd_blocks(8);
+  L.args = DevBuf(args.size() * sizeof(SellArgs));
+  L.work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(uint2));
+  L.zero = DevBuf(std::max<size_t>(1, zero.size()) * sizeof(uint2));
+  HIP_CHECK(hipMemcpyAsync(L.args.get(), args.data(), args.size() * sizeof(SellArgs), hipMemcpyHostToDevice, s));
+  if (!work.empty())
+    HIP_CHECK(hipMemcpyAsync(L.work.get(), work.data(), work.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+  if (!zero.empty())
+    HIP_CHECK(hipMemcpyAsync(L.zero.get(), zero.data(), zero.size() * sizeof(uint2), hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  plan->sell_layers.push_back(std::move(L));
+  return plan.release();
 }
 
 }  // namespace
@@ -1518,7 +1614,7 @@ dose_status dose_sell_create(const dose_csr_host* csr, int32_t vf, int32_t xf, i
     // of its row (columns ascend), so the rows' ends bound the window
     std::vector<uint32_t> win(static_cast<size_t>(2 * m->n_groups), 0u), pad_col(static_cast<size_t>(m->n_groups), 0u);
     const int64_t cap = window_cap_floats();
-    int64_t wf = 0;
+    int64_t wf[3] = {0, 0, 0};
     for (int64_t g = 0; g < m->n_groups; ++g) {
       int64_t lo = INT64_MAX, hi = -1;
       for (int64_t i = g * kSellGroupRows; i < (g + 1) * kSellGroupRows; ++i) {
@@ -1533,12 +1629,15 @@ dose_status dose_sell_create(const dose_csr_host* csr, int32_t vf, int32_t xf, i
       win[2 * g] = static_cast<uint32_t>(cmin);
       win[2 * g + 1] = static_cast<uint32_t>(clen);
       pad_col[g] = static_cast<uint32_t>(cmin);
-      if (clen <= cap) {
-        ++m->n_windowed;
-        wf = std::max(wf, clen);
+      if (clen <= cap) ++m->n_windowed;
+      // as for CSR row groups, the cap scales with the vectors (up to the
+      // largest LDS window)
+      for (int i = 0; i < 3; ++i) {
+        const int64_t f = clen << i;
+        if (f <= std::min<int64_t>(cap << i, kWinFloatsMax)) wf[i] = std::max(wf[i], f);
       }
     }
-    m->win_floats = static_cast<int32_t>((wf + 3) / 4 * 4);
+    for (int i = 0; i < 3; ++i) m->win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);
     // run-length indices: every position's maximal runs of consecutive
     // columns, as (end position in the row, column - position)
     std::vector<uint32_t> h_run_ptr;
@@ -1766,14 +1865,33 @@ dose_status dose_sell_runs(dose_sell m, int64_t* run_ptr, int32_t* start, int32_
 
 dose_status dose_sell_spmv(dose_sell m, const float* x, float* y, void* hip_stream) {
   return guarded([&] {
-    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
-    if ((m->n_cols > 0 && !x) || (m->n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
-    if (overlaps(x, m->n_cols * 4, y, m->n_rows * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
-    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 4 != 0)
-      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be 4-byte aligned");
+    check_sell_product(m, 1, x, y);
     DeviceGuard g(m->device);
-    HIP_CHECK(launch_sell_spmv(m->vf, m->vf == kFp8 ? kScaleRow : kScaleNone, sell_args(m, x, y),
+    HIP_CHECK(launch_sell_spmv(m->vf, m->vf == kFp8 ? kScaleRow : kScaleNone, 1, sell_args(m, 1, x, y),
                                as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_sell_spmv_multi(dose_sell m, int32_t n_rhs, const float* x, float* y, void* hip_stream) {
+  return guarded([&] {
+    check_sell_product(m, n_rhs, x, y);
+    DeviceGuard g(m->device);
+    HIP_CHECK(launch_sell_spmv(m->vf, m->vf == kFp8 ? kScaleRow : kScaleNone, n_rhs, sell_args(m, n_rhs, x, y),
+                               as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_sell_batch_plan_create(const dose_sell_batch_item* items, int32_t n_items, uint32_t flags,
+                                        void* hip_stream, dose_batch_plan* out) {
+  return guarded([&] {
+    if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    if (flags != 0) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
+    check_sell_items(items, n_items);
+    DeviceGuard g(items[0].S->device);
+    std::unique_ptr<dose_batch_plan_s> p(build_sell_plan(items, n_items, as_stream(hip_stream)));
+    capture_plan(p.get());
+    *out = p.release();
   });
 }
 

@@ -61,11 +61,11 @@ struct SellArgs {
   const SellRun* runs;
   const uint32_t* work;     // the chunks holding entries, ascending (one workgroup each)
   const uint32_t* zero;     // the chunks without entries (their rows get +0; 4 per workgroup)
-  const float* x;
-  float* y;
+  const float* x;           // [n_cols][n_rhs] FP32
+  float* y;                 // [n_rows][n_rhs] FP32
   int64_t n_groups;         // chunks holding entries
   int64_t n_zero;           // chunks without entries
-  int32_t win_floats;       // LDS window floats (0: no group uses the LDS window)
+  int32_t win_floats;       // LDS window floats for the launch's n_rhs (0: no group uses the LDS window)
   int32_t idx_bytes;        // 4, 2, or 0 (run-length indices)
   int32_t xcd_blocks;
   int32_t lds_runs;         // run-length indices: most runs of one group (LDS records)
@@ -73,7 +73,25 @@ struct SellArgs {
   int32_t pad0;
 };
 
-hipError_t launch_sell_spmv(int vf, int scale_mode, const SellArgs& a, hipStream_t s);
+// The chunks of many matrices in one launch: work and zero hold (item,
+// chunk) pairs, the chunks holding entries and those without; args, one
+// SellArgs per item (all of one value and index format and n_rhs).
+struct SellBatchTable {
+  const SellArgs* args;
+  const uint2* work;
+  const uint2* zero;
+  int64_t n_work;
+  int64_t n_zero;
+  int32_t xcd_blocks;
+  int32_t pad0;
+};
+
+// y = A x for n_rhs (1, 2 or 4) row-major vectors.
+hipError_t launch_sell_spmv(int vf, int scale_mode, int n_rhs, const SellArgs& a, hipStream_t s);
+hipError_t launch_sell_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SellBatchTable& t,
+                               size_t lds_bytes, hipStream_t s);
+// Dynamic LDS bytes of a launch of a (the largest over a batch's items).
+size_t sell_launch_lds_bytes(const SellArgs& a);
 // Scatter of CSR codes and columns into the slice layout.  start: per row
 // position, the row's first entry in the CSR streams; pad_col: per group,
 // the column written into padding slots.

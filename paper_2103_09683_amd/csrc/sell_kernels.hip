@@ -20,6 +20,11 @@
 //   * Run-length column indices: the chunk's runs are staged in LDS; a lane
 //     keeps a cursor on its row's runs, and a slice whose 8 entries lie in
 //     one run (the common case) reads 8 consecutive x from one LDS address.
+//   * Several vectors (n_rhs = 2 or 4, x and y row-major [.][n_rhs]): every
+//     entry is loaded once and multiplied by the n_rhs values of its column
+//     (one LDS read); each vector's sums follow the order below, so the
+//     product equals n_rhs single-vector products bit for bit.  A batched
+//     launch takes the chunks of many matrices from one work list.
 //   * Summation order, fixed by the stored layout (so equal inputs give equal
 //     bits): a lane's 8 products of a slice add pairwise, ((p0 + p1) +
 //     (p2 + p3)) + ((p4 + p5) + (p6 + p7)), slots past the row's end counting
@@ -116,61 +121,96 @@ __device__ __forceinline__ void lane_cols(const Lane8<VF, IX>& L, int (&c)[kSell
   for (int e = 0; e < kSellLaneEntries; ++e) asm("" : "+v"(c[e]));  // keep each LDS address one shift-add
 }
 
-// The lane's 8 products of a slice: decoded code times x of its column.
-// x comes from the LDS window (xb: the window moved back by cmin columns) or
-// from global memory.
-template <int VF, int IX, bool WIN>
-__device__ __forceinline__ void slice_products(const Lane8<VF, IX>& L, const int (&c)[kSellLaneEntries],
-                                               const float* xb, const float* x, float (&p)[kSellLaneEntries]) {
-  float xv[kSellLaneEntries];
-#pragma unroll
-  for (int e = 0; e < kSellLaneEntries; ++e) {
-    if constexpr (WIN) {
-      xv[e] = xb[c[e]];
-    } else {
-      xv[e] = x[c[e]];
-    }
+// The n_rhs values of x at p (row-major x: 4 n_rhs-byte aligned).
+template <int NRHS>
+struct XV {
+  float v[NRHS];
+};
+template <int NRHS>
+__device__ __forceinline__ XV<NRHS> x_at(const float* p) {
+  XV<NRHS> r;
+  if constexpr (NRHS == 1) {
+    r.v[0] = p[0];
+  } else if constexpr (NRHS == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    r.v[0] = t.x, r.v[1] = t.y;
+  } else {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    r.v[0] = t.x, r.v[1] = t.y, r.v[2] = t.z, r.v[3] = t.w;
   }
+  return r;
+}
+
+// The lane's 8 decoded codes of a slice (E4M3 without its row scale).
+template <int VF, int IX>
+__device__ __forceinline__ void slice_codes(const Lane8<VF, IX>& L, float (&d)[kSellLaneEntries]) {
   if constexpr (VF == kFp16) {
     const uint32_t w[4] = {L.c0.x, L.c0.y, L.c0.z, L.c0.w};
 #pragma unroll
-    for (int e = 0; e < kSellLaneEntries; ++e) {
-      const float d = __half2float(__ushort_as_half(static_cast<unsigned short>((w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu)));
-      // an FMA with +0 rounds the product once, as a multiply does (v_fma_mix)
-      p[e] = __builtin_fmaf(d, xv[e], 0.0f);
-    }
+    for (int e = 0; e < kSellLaneEntries; ++e)
+      d[e] = __half2float(__ushort_as_half(static_cast<unsigned short>((w[e >> 1] >> ((e & 1) * 16)) & 0xFFFFu)));
   } else if constexpr (VF == kBf16) {
     const uint32_t w[4] = {L.c0.x, L.c0.y, L.c0.z, L.c0.w};
 #pragma unroll
     for (int e = 0; e < kSellLaneEntries; ++e) {
       const uint32_t word = w[e >> 1];
-      p[e] = __uint_as_float((e & 1) ? (word & 0xFFFF0000u) : (word << 16)) * xv[e];
+      d[e] = __uint_as_float((e & 1) ? (word & 0xFFFF0000u) : (word << 16));
     }
   } else if constexpr (VF == kFp8) {
     const f32x2 a = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(L.c0.x), false);
     const f32x2 b = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(L.c0.x), true);
     const f32x2 cc = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(L.c0.y), false);
-    const f32x2 d = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(L.c0.y), true);
-    const float q[8] = {a.x, a.y, b.x, b.y, cc.x, cc.y, d.x, d.y};
-#pragma unroll
-    for (int e = 0; e < kSellLaneEntries; ++e) p[e] = q[e] * xv[e];
+    const f32x2 dd = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(L.c0.y), true);
+    d[0] = a.x, d[1] = a.y, d[2] = b.x, d[3] = b.y, d[4] = cc.x, d[5] = cc.y, d[6] = dd.x, d[7] = dd.y;
   } else {
     const uint32_t w[8] = {L.c0.x, L.c0.y, L.c0.z, L.c0.w, L.c1.x, L.c1.y, L.c1.z, L.c1.w};
 #pragma unroll
-    for (int e = 0; e < kSellLaneEntries; ++e) p[e] = __uint_as_float(w[e]) * xv[e];
+    for (int e = 0; e < kSellLaneEntries; ++e) d[e] = __uint_as_float(w[e]);
   }
 }
 
-__device__ __forceinline__ float slice_sum(const float (&p)[kSellLaneEntries]) {
-  return ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+// The lane's 8 products of a slice for each vector: decoded code times x of
+// its column, rounded once.  x comes from the LDS window (xb: the window
+// moved back by cmin columns) or from global memory.
+template <int VF, int IX, bool WIN, int NRHS>
+__device__ __forceinline__ void slice_products(const Lane8<VF, IX>& L, const int (&c)[kSellLaneEntries],
+                                               const float* xb, const float* x,
+                                               float (&p)[kSellLaneEntries][NRHS]) {
+  XV<NRHS> xv[kSellLaneEntries];
+#pragma unroll
+  for (int e = 0; e < kSellLaneEntries; ++e) {
+    if constexpr (WIN) {
+      xv[e] = x_at<NRHS>(xb + c[e] * NRHS);
+    } else {
+      xv[e] = x_at<NRHS>(x + static_cast<int64_t>(c[e]) * NRHS);
+    }
+  }
+  float d[kSellLaneEntries];
+  slice_codes<VF, IX>(L, d);
+#pragma unroll
+  for (int e = 0; e < kSellLaneEntries; ++e)
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) {
+      if constexpr (VF == kFp16) {
+        // an FMA with +0 rounds the product once, as a multiply does (v_fma_mix)
+        p[e][q] = __builtin_fmaf(d[e], xv[e].v[q], 0.0f);
+      } else {
+        p[e][q] = d[e] * xv[e].v[q];
+      }
+    }
 }
 
-// The workgroup of group b (see group_of_block in the CSR kernels: with D
-// dies dealt workgroups in turn, die x takes one contiguous run of groups).
-__device__ __forceinline__ int64_t sell_group_of_block(const SellArgs& a, uint32_t b) {
-  const int D = a.xcd_blocks;
+template <int NRHS>
+__device__ __forceinline__ float slice_sum(const float (&p)[kSellLaneEntries][NRHS], int q) {
+  return ((p[0][q] + p[1][q]) + (p[2][q] + p[3][q])) + ((p[4][q] + p[5][q]) + (p[6][q] + p[7][q]));
+}
+
+// The work item of workgroup b of n (see group_of_block in the CSR kernels:
+// with D dies dealt workgroups in turn, die x takes one contiguous run of
+// the items).
+__device__ __forceinline__ int64_t sell_group_of_block(int D, int64_t n, uint32_t b) {
   if (D <= 1) return b;
-  const int64_t q = a.n_groups / D, r = a.n_groups % D;
+  const int64_t q = n / D, r = n % D;
   const int64_t x = b % static_cast<uint32_t>(D), i = b / static_cast<uint32_t>(D);
   return x * q + (x < r ? x : r) + i;
 }
@@ -201,8 +241,22 @@ __device__ __forceinline__ void walk_runs(const SellRun* lruns, int ri, int re, 
   }
 }
 
-template <int VF, int SM, int IX, bool WIN>
-__device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* xw, float (*part)[kWave]) {
+// Stores a row's n_rhs values (y row-major, 4 n_rhs-byte aligned).
+template <int NRHS>
+__device__ __forceinline__ void store_rhs(float* dst, const float (&v)[NRHS]) {
+  if constexpr (NRHS == 1) {
+    dst[0] = v[0];
+  } else if constexpr (NRHS == 2) {
+    *reinterpret_cast<float2*>(dst) = make_float2(v[0], v[1]);
+  } else {
+    *reinterpret_cast<float4*>(dst) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+
+// Chunk c of a's matrix on one workgroup.  part: LDS for the waves' row
+// sums, kGroupWaves * NRHS * 64 floats.
+template <int VF, int SM, int IX, bool WIN, int NRHS>
+__device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* xw, float* part) {
   const int tid = static_cast<int>(threadIdx.x);
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -239,14 +293,14 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
   // waiting for the window leaves the slices in flight: the x window (16-byte
   // pieces, a thread's first four at once), then the wave's first NB slices.
   const int cmin = static_cast<int>(a.win[2 * c]);  // also the padding column
-  int clen = 0, n4 = 0;
+  int nf = 0, n4 = 0;  // window floats (its columns times NRHS), whole 16-byte pieces
   const float* xs = a.x;
   float4 w0, w1, w2, w3;
   float wt = 0.0f;
   if constexpr (WIN) {
-    clen = static_cast<int>(a.win[2 * c + 1]);
-    xs = a.x + cmin;
-    n4 = clen >> 2;
+    nf = static_cast<int>(a.win[2 * c + 1]) * NRHS;
+    xs = a.x + static_cast<int64_t>(cmin) * NRHS;
+    n4 = nf >> 2;
     const float4* xs4 = reinterpret_cast<const float4*>(xs);
     const float4* safe4 = reinterpret_cast<const float4*>(ch);
     w0 = *(tid < n4 ? xs4 + tid : safe4);
@@ -254,7 +308,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     w2 = *(tid + 2 * kGroupThreads < n4 ? xs4 + tid + 2 * kGroupThreads : safe4);
     w3 = *(tid + 3 * kGroupThreads < n4 ? xs4 + tid + 3 * kGroupThreads : safe4);
     const int tt = 4 * n4 + tid;
-    wt = *(tt < clen ? xs + tt : reinterpret_cast<const float*>(ch));
+    wt = *(tt < nf ? xs + tt : reinterpret_cast<const float*>(ch));
   }
   constexpr int NB = ring_depth<VF, IX>();
   // slice k of the wave, clamped to the chunk's last (or, without slices, its
@@ -270,7 +324,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     if (tid + kGroupThreads < n4) xw4[tid + kGroupThreads] = w1;
     if (tid + 2 * kGroupThreads < n4) xw4[tid + 2 * kGroupThreads] = w2;
     if (tid + 3 * kGroupThreads < n4) xw4[tid + 3 * kGroupThreads] = w3;
-    if (4 * n4 + tid < clen) xw[4 * n4 + tid] = wt;
+    if (4 * n4 + tid < nf) xw[4 * n4 + tid] = wt;
     // windows larger than one batch
     for (int j = tid + 4 * kGroupThreads; j < n4; j += kGroupThreads) xw4[j] = xs4[j];
   }
@@ -279,11 +333,14 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     if (tid + kGroupThreads < nruns) lruns[tid + kGroupThreads] = q1;
     for (int j = tid + 2 * kGroupThreads; j < nruns; j += kGroupThreads) lruns[j] = a.runs[g0 + j];
   }
-  part[wave][lane] = 0.0f;
+#pragma unroll
+  for (int q = 0; q < NRHS; ++q) part[(wave * NRHS + q) * kWave + lane] = 0.0f;
   __syncthreads();
   if (wave < T) {
-    const float* xb = xw - cmin;
-    float inner = 0.0f, outer = 0.0f;
+    const float* xb = xw - cmin * NRHS;
+    float inner[NRHS], outer[NRHS];
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) inner[q] = 0.0f, outer[q] = 0.0f;
     int cnt = 0;
     // run cursor: run ri (of the lane's [rb, re)) ends at cur_end and its
     // entries have column = position + cur_delta; the next run (nx_end,
@@ -304,7 +361,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     auto step = [&](Lane8<VF, IX>& buf) {
       const bool live = t < T;
       const int P = t * kSellLaneEntries;
-      float pr[kSellLaneEntries];
+      float pr[kSellLaneEntries][NRHS];
       if (live) {
         int cols[kSellLaneEntries];
         if constexpr (IX == 0) {
@@ -328,7 +385,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
         } else {
           lane_cols(buf, cols);
         }
-        slice_products<VF, IX, WIN>(buf, cols, xb, a.x, pr);
+        slice_products<VF, IX, WIN, NRHS>(buf, cols, xb, a.x, pr);
       }
       __builtin_amdgcn_sched_barrier(0);
       load_slice<VF, IX>(val, col, slice_of(t + NB * kGroupWaves), lane, buf);
@@ -338,12 +395,18 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
           // some lane's row ends in or before this slice
           const int lim = len - P;
 #pragma unroll
-          for (int e = 0; e < kSellLaneEntries; ++e) pr[e] = e < lim ? pr[e] : 0.0f;
+          for (int e = 0; e < kSellLaneEntries; ++e)
+#pragma unroll
+            for (int q = 0; q < NRHS; ++q) pr[e][q] = e < lim ? pr[e][q] : 0.0f;
         }
-        inner += slice_sum(pr);
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) inner[q] += slice_sum<NRHS>(pr, q);
         if (++cnt == 8) {
-          outer += inner;
-          inner = 0.0f;
+#pragma unroll
+          for (int q = 0; q < NRHS; ++q) {
+            outer[q] += inner[q];
+            inner[q] = 0.0f;
+          }
           cnt = 0;
         }
       }
@@ -355,66 +418,155 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
       for (int k = 0; k < NB; ++k) step(r[k]);
       if (t >= T) break;
     }
-    part[wave][lane] = outer + inner;
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) part[(wave * NRHS + q) * kWave + lane] = outer[q] + inner[q];
   }
   __syncthreads();
   if (wave == 0 && my_row != 0xFFFFFFFFu) {
-    float v = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
-    if constexpr (SM == kScaleRow) v = v * a.scale[my_row];
-    a.y[my_row] = v;
+    float v[NRHS];
+#pragma unroll
+    for (int q = 0; q < NRHS; ++q) {
+      const float* pq = part + q * kWave + lane;
+      v[q] = (pq[0 * NRHS * kWave] + pq[1 * NRHS * kWave]) + (pq[2 * NRHS * kWave] + pq[3 * NRHS * kWave]);
+      if constexpr (SM == kScaleRow) v[q] = v[q] * a.scale[my_row];
+    }
+    store_rhs<NRHS>(a.y + static_cast<int64_t>(my_row) * NRHS, v);
+  }
+}
+
+// Chunk c of a's matrix on one workgroup: through the LDS window when the
+// chunk's window, for NRHS vectors, fits a's.
+template <int VF, int SM, int IX, int NRHS>
+__device__ __forceinline__ void sell_run_chunk(const SellArgs& a, int64_t c, float* xw, float* part) {
+  const uint32_t clen = a.win[2 * c + 1];
+  if (clen > 0 && static_cast<int64_t>(clen) * NRHS <= a.win_floats)
+    sell_chunk<VF, SM, IX, true, NRHS>(a, c, xw, part);
+  else
+    sell_chunk<VF, SM, IX, false, NRHS>(a, c, xw, part);
+}
+
+// +0 to the rows of chunk c of a's matrix (one wave).
+template <int NRHS>
+__device__ __forceinline__ void sell_zero_rows(const SellArgs& a, int64_t c) {
+  const uint32_t row = a.perm[c * kSellC + (threadIdx.x & (kWave - 1))];
+  if (row != 0xFFFFFFFFu) {
+    const float z[NRHS] = {};
+    store_rhs<NRHS>(a.y + static_cast<int64_t>(row) * NRHS, z);
   }
 }
 
 // Workgroups [0, n_groups) take the chunks holding entries (through the die
 // regrouping); the rest write +0 to the rows of four chunks without entries
 // each.
-template <int VF, int SM, int IX>
+template <int VF, int SM, int IX, int NRHS>
 __global__ __launch_bounds__(kGroupThreads) void k_sell(SellArgs a) {
   extern __shared__ __align__(16) float xw[];
-  __shared__ float part[kGroupWaves][kWave];
+  __shared__ float part[kGroupWaves * NRHS * kWave];
   if (blockIdx.x >= a.n_groups) {
     const int64_t z = (static_cast<int64_t>(blockIdx.x) - a.n_groups) * kGroupWaves + threadIdx.x / kWave;
-    if (z < a.n_zero) {
-      const uint32_t row = a.perm[static_cast<int64_t>(a.zero[z]) * kSellC + (threadIdx.x & (kWave - 1))];
-      if (row != 0xFFFFFFFFu) a.y[row] = 0.0f;
+    if (z < a.n_zero) sell_zero_rows<NRHS>(a, a.zero[z]);
+    return;
+  }
+  sell_run_chunk<VF, SM, IX, NRHS>(a, a.work[sell_group_of_block(a.xcd_blocks, a.n_groups, blockIdx.x)], xw, part);
+}
+
+// Batched form: the same over the work lists of many matrices, each entry
+// naming its item.
+template <int VF, int SM, int IX, int NRHS>
+__global__ __launch_bounds__(kGroupThreads) void k_sell_batched(SellBatchTable t) {
+  extern __shared__ __align__(16) float xw[];
+  __shared__ float part[kGroupWaves * NRHS * kWave];
+  if (blockIdx.x >= t.n_work) {
+    const int64_t z = (static_cast<int64_t>(blockIdx.x) - t.n_work) * kGroupWaves + threadIdx.x / kWave;
+    if (z < t.n_zero) {
+      const uint2 w = t.zero[z];
+      sell_zero_rows<NRHS>(t.args[w.x], w.y);
     }
     return;
   }
-  const int64_t c = a.work[sell_group_of_block(a, blockIdx.x)];
-  const uint32_t clen = a.win[2 * c + 1];
-  if (clen > 0 && static_cast<int64_t>(clen) <= a.win_floats)
-    sell_chunk<VF, SM, IX, true>(a, c, xw, part);
+  const uint2 w = t.work[sell_group_of_block(t.xcd_blocks, t.n_work, blockIdx.x)];
+  sell_run_chunk<VF, SM, IX, NRHS>(t.args[w.x], w.y, xw, part);
+}
+
+// LDS of a launch: the window, then (run-length indices) one lane's entries
+// of padding and the chunk's runs.
+size_t sell_lds_bytes(const SellArgs& a) {
+  if (a.idx_bytes != 0) return static_cast<size_t>(a.win_floats) * sizeof(float);
+  return (static_cast<size_t>(a.win_floats) + kSellLaneEntries) * sizeof(float) +
+         static_cast<size_t>(a.lds_runs) * sizeof(SellRun);
+}
+
+template <int VF, int SM, int NRHS>
+void launch_ix(const SellArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.n_groups + (a.n_zero + kGroupWaves - 1) / kGroupWaves)),
+      block(kGroupThreads);
+  const size_t lds = sell_lds_bytes(a);
+  if (a.idx_bytes == 0)
+    hipLaunchKernelGGL((k_sell<VF, SM, 0, NRHS>), grid, block, lds, s, a);
+  else if (a.idx_bytes == 2)
+    hipLaunchKernelGGL((k_sell<VF, SM, 2, NRHS>), grid, block, lds, s, a);
   else
-    sell_chunk<VF, SM, IX, false>(a, c, xw, part);
+    hipLaunchKernelGGL((k_sell<VF, SM, 4, NRHS>), grid, block, lds, s, a);
+}
+
+template <int VF, int SM, int NRHS>
+void launch_ix_batched(int idx_bytes, const SellBatchTable& t, size_t lds, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(t.n_work + (t.n_zero + kGroupWaves - 1) / kGroupWaves)),
+      block(kGroupThreads);
+  if (idx_bytes == 0)
+    hipLaunchKernelGGL((k_sell_batched<VF, SM, 0, NRHS>), grid, block, lds, s, t);
+  else if (idx_bytes == 2)
+    hipLaunchKernelGGL((k_sell_batched<VF, SM, 2, NRHS>), grid, block, lds, s, t);
+  else
+    hipLaunchKernelGGL((k_sell_batched<VF, SM, 4, NRHS>), grid, block, lds, s, t);
 }
 
 template <int VF, int SM>
-hipError_t launch_vf(const SellArgs& a, hipStream_t s) {
-  const dim3 grid(static_cast<unsigned>(a.n_groups + (a.n_zero + kGroupWaves - 1) / kGroupWaves)),
-      block(kGroupThreads);
-  if (a.idx_bytes == 0) {
-    // the window padded by one lane's entries, then the group's runs
-    const size_t lds = (static_cast<size_t>(a.win_floats) + kSellLaneEntries) * sizeof(float) +
-                       static_cast<size_t>(a.lds_runs) * sizeof(SellRun);
-    hipLaunchKernelGGL((k_sell<VF, SM, 0>), grid, block, lds, s, a);
-    return hipGetLastError();
+hipError_t launch_vf(int n_rhs, const SellArgs& a, hipStream_t s) {
+  switch (n_rhs) {
+    case 1: launch_ix<VF, SM, 1>(a, s); break;
+    case 2: launch_ix<VF, SM, 2>(a, s); break;
+    case 4: launch_ix<VF, SM, 4>(a, s); break;
+    default: return hipErrorInvalidValue;
   }
-  const size_t lds = static_cast<size_t>(a.win_floats) * sizeof(float);
-  if (a.idx_bytes == 2)
-    hipLaunchKernelGGL((k_sell<VF, SM, 2>), grid, block, lds, s, a);
-  else
-    hipLaunchKernelGGL((k_sell<VF, SM, 4>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <int VF, int SM>
+hipError_t launch_vf_batched(int n_rhs, int idx_bytes, const SellBatchTable& t, size_t lds, hipStream_t s) {
+  switch (n_rhs) {
+    case 1: launch_ix_batched<VF, SM, 1>(idx_bytes, t, lds, s); break;
+    case 2: launch_ix_batched<VF, SM, 2>(idx_bytes, t, lds, s); break;
+    case 4: launch_ix_batched<VF, SM, 4>(idx_bytes, t, lds, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_sell_spmv(int vf, int scale_mode, const SellArgs& a, hipStream_t s) {
+size_t sell_launch_lds_bytes(const SellArgs& a) { return sell_lds_bytes(a); }
+
+hipError_t launch_sell_spmv(int vf, int scale_mode, int n_rhs, const SellArgs& a, hipStream_t s) {
   if (a.n_groups <= 0 && a.n_zero <= 0) return hipSuccess;
-  if (vf == kFp16 && scale_mode == kScaleNone) return launch_vf<kFp16, kScaleNone>(a, s);
-  if (vf == kBf16 && scale_mode == kScaleNone) return launch_vf<kBf16, kScaleNone>(a, s);
-  if (vf == kFp32 && scale_mode == kScaleNone) return launch_vf<kFp32, kScaleNone>(a, s);
-  if (vf == kFp8 && scale_mode == kScaleRow) return launch_vf<kFp8, kScaleRow>(a, s);
+  if (vf == kFp16 && scale_mode == kScaleNone) return launch_vf<kFp16, kScaleNone>(n_rhs, a, s);
+  if (vf == kBf16 && scale_mode == kScaleNone) return launch_vf<kBf16, kScaleNone>(n_rhs, a, s);
+  if (vf == kFp32 && scale_mode == kScaleNone) return launch_vf<kFp32, kScaleNone>(n_rhs, a, s);
+  if (vf == kFp8 && scale_mode == kScaleRow) return launch_vf<kFp8, kScaleRow>(n_rhs, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sell_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SellBatchTable& t,
+                               size_t lds_bytes, hipStream_t s) {
+  if (t.n_work <= 0 && t.n_zero <= 0) return hipSuccess;
+  if (vf == kFp16 && scale_mode == kScaleNone)
+    return launch_vf_batched<kFp16, kScaleNone>(n_rhs, idx_bytes, t, lds_bytes, s);
+  if (vf == kBf16 && scale_mode == kScaleNone)
+    return launch_vf_batched<kBf16, kScaleNone>(n_rhs, idx_bytes, t, lds_bytes, s);
+  if (vf == kFp32 && scale_mode == kScaleNone)
+    return launch_vf_batched<kFp32, kScaleNone>(n_rhs, idx_bytes, t, lds_bytes, s);
+  if (vf == kFp8 && scale_mode == kScaleRow)
+    return launch_vf_batched<kFp8, kScaleRow>(n_rhs, idx_bytes, t, lds_bytes, s);
   return hipErrorInvalidValue;
 }
 
