@@ -545,19 +545,18 @@ def bench_bias_controls(torch, dm, dosegen, spec, x, args):
     return res
 
 
-BATCH_SELL_SIGMA = 16384
+BATCH_SELL_SIGMA = 8192
 
 
 def bench_batched(torch, dm, dosegen, args):
     """The 36 beam x scenario matrices of a robust plan, four spot-weight
     vectors each, in one autotuned CSR plan launch (FP16 and BF16), and the
-    FP16 matrices in SELL-C-sigma form (sigma 16,384, 16-bit indices; 32-bit
-    beyond 65,536 columns) in one SELL plan launch.  With four vectors the
-    SELL kernel is bound by its per-entry work rather than by HBM, and
-    16-bit indices beat run-length ones there (1.74 against 2.06 ms at a
-    quarter of the batch); sigma 16,384 keeps a chunk's rows near one
-    another, so nearly every chunk's four-vector x window fits in LDS
-    (65,536: 2.80 ms).
+    FP16 matrices in SELL-C-sigma form (sigma 8,192, run-length indices;
+    16-bit ones where a chunk holds too many runs) in one SELL plan launch.
+    Sigma 8,192 keeps a chunk's rows near one another, so nearly every
+    chunk's four-vector x window fits in LDS (at a quarter of the batch:
+    1.38 ms, against 1.54 ms at 16,384, 2.80 ms at 65,536 and 1.67 ms with
+    16-bit indices at 16,384).
     Algorithmic bytes: the paper format's 6 bytes per entry and 4 per row
     offset, x and y read / written once (four vectors); the SELL line also
     gives its own format's algorithmic bytes."""
@@ -582,8 +581,11 @@ def bench_batched(torch, dm, dosegen, args):
             extra = 4 * (4 * inf["n_cols"] + 4 * inf["n_rows"])
             bytes_tot += inf["nnz"] * 6 + (inf["n_rows"] + 1) * 4 + extra
             if fmt == "fp16":
-                S = dm.SellMatrix(rp, cols, vals, s.n_cols, fmt, sigma=BATCH_SELL_SIGMA,
-                                  index_format="u16" if s.n_cols <= 65536 else "i32")
+                try:
+                    S = dm.SellMatrix(rp, cols, vals, s.n_cols, fmt, sigma=BATCH_SELL_SIGMA, index_format="runs")
+                except dm.DoseError:
+                    S = dm.SellMatrix(rp, cols, vals, s.n_cols, fmt, sigma=BATCH_SELL_SIGMA,
+                                      index_format="u16" if s.n_cols <= 65536 else "i32")
                 sell_idx.add(S.index_format)
                 sells.append(S)
                 sentries.append((S, X, torch.empty_like(Y)))

@@ -308,7 +308,8 @@ int rhs_slot(int n_rhs) { return n_rhs == 1 ? 0 : n_rhs == 2 ? 1 : 2; }
 // Cap on one workgroup's LDS x window for one vector, in floats:
 // DOSE_LDS_WINDOW_FLOATS (256 .. kWinFloatsMax), default 4096 (16 KB: eight
 // workgroups per compute unit, and 99.8% of the clinical beam's groups fit);
-// n vectors get n times the cap, up to kWinFloatsMax.  A smaller cap lets
+// n vectors get n times the cap, up to kWinFloatsMax (row groups) or
+// kSellWinFloatsMax (SELL-C-sigma chunks).  A smaller cap lets
 // more workgroups share a compute unit; groups whose window exceeds it
 // gather x from global memory.
 int64_t window_cap_floats() {
@@ -1630,11 +1631,11 @@ dose_status dose_sell_create(const dose_csr_host* csr, int32_t vf, int32_t xf, i
       win[2 * g + 1] = static_cast<uint32_t>(clen);
       pad_col[g] = static_cast<uint32_t>(cmin);
       if (clen <= cap) ++m->n_windowed;
-      // as for CSR row groups, the cap scales with the vectors (up to the
-      // largest LDS window)
+      // as for CSR row groups, the cap scales with the vectors, up to the
+      // largest SELL window (a launch's LDS is sized for its widest window)
       for (int i = 0; i < 3; ++i) {
         const int64_t f = clen << i;
-        if (f <= std::min<int64_t>(cap << i, kWinFloatsMax)) wf[i] = std::max(wf[i], f);
+        if (f <= std::min<int64_t>(cap << i, kSellWinFloatsMax)) wf[i] = std::max(wf[i], f);
       }
     }
     for (int i = 0; i < 3; ++i) m->win_floats[i] = static_cast<int32_t>((wf[i] + 3) / 4 * 4);

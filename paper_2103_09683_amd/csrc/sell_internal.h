@@ -32,6 +32,12 @@ __host__ __device__ constexpr uint32_t sell_slot(int bytes, int lane, int e) {
                     : static_cast<uint32_t>(lane * kSellLaneEntries + e);
 }
 
+// Largest LDS x window of a SELL-C-sigma workgroup, in floats (32 KB): with
+// the row sums' 1 KB per vector, four workgroups of the four-vector kernel
+// (the most its registers allow) fit in a compute unit's 160 KB of LDS.
+// Chunks with wider windows gather x from global memory.
+constexpr int kSellWinFloatsMax = 8192;
+
 struct alignas(16) SellChunk {
   uint32_t slice0;    // first slice of the chunk (slices of all chunks are consecutive)
   uint32_t n_slices;  // ceil(width / 8)

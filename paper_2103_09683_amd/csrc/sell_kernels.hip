@@ -73,11 +73,15 @@ struct Lane8 {
 
 // Slices in flight per wave (one being computed, the others loading): about
 // 128 bytes per lane, so that the narrower streams keep as many bytes in
-// flight as the wide ones (a lane's slice is 8 codes plus 8 indices).
-template <int VF, int IX>
+// flight as the wide ones (a lane's slice is 8 codes plus 8 indices).  With
+// four vectors two slices: each vector's products take registers, and a
+// deeper ring was measured slower (the 36-matrix batch at a quarter scale,
+// 16-bit indices: 1.74 against 1.67 ms).
+template <int VF, int IX, int NRHS>
 constexpr int ring_depth() {
   constexpr int bytes = kSellLaneEntries * (code_bytes<VF>() + IX);
-  return 128 / bytes < 2 ? 2 : 128 / bytes > 4 ? 4 : 128 / bytes;
+  constexpr int d = 128 / bytes < 2 ? 2 : 128 / bytes > 4 ? 4 : 128 / bytes;
+  return NRHS == 4 ? 2 : d;
 }
 
 // Loads lane `lane`'s part of slice `slice` (wave-uniform).
@@ -310,7 +314,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     const int tt = 4 * n4 + tid;
     wt = *(tt < nf ? xs + tt : reinterpret_cast<const float*>(ch));
   }
-  constexpr int NB = ring_depth<VF, IX>();
+  constexpr int NB = ring_depth<VF, IX, NRHS>();
   // slice k of the wave, clamped to the chunk's last (or, without slices, its
   // first slice position)
   auto slice_of = [&](int t) { return slice0 + static_cast<uint32_t>(max(min(t, T - 1), 0)); };
