@@ -574,6 +574,7 @@ void tune_store(const std::string& key, int v) {
 // them (a work list of descriptor copies naming their item).
 struct PlanLayer {
   int lds_floats = 0;
+  int accumulate = 0;  // 1: the launch adds its items' products to what their y hold
   int64_t n_work = 0;
   DevBuf args, work;
 };
@@ -701,13 +702,13 @@ PlanLayer make_layer(const dose_batch_plan_s* plan, const dose_batch_item* items
                      const std::map<const dose_matrix_s*, const Partition*>& part_of, int accumulate,
                      hipStream_t s) {
   PlanLayer L;
+  L.accumulate = accumulate;
   std::vector<SpmvArgs> args(static_cast<size_t>(n_items));
   std::vector<GroupDesc> work;
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_matrix_s* m = items[i].A;
     const Partition& P = *part_of.at(m);
     args[i] = make_args(m, m->A, P, plan->sm, plan->n_rhs, items[i].x, items[i].y);
-    args[i].accumulate = accumulate;
     L.lds_floats = std::max(L.lds_floats, args[i].win_floats);
     for (GroupDesc g : P.h_groups) {
       g.item = static_cast<uint32_t>(i);
@@ -749,7 +750,7 @@ void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
     BatchTable t{};
     t.args = L.args.get<SpmvArgs>();
     t.work = L.work.get<GroupDesc>();
-    HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, L.n_work, L.lds_floats, s));
+    HIP_CHECK(launch_spmv_batched(p->vf, p->sm, p->n_rhs, L.accumulate, p->idx_bytes, t, L.n_work, L.lds_floats, s));
   }
   for (const SellPlanLayer& L : p->sell_layers) {
     SellBatchTable t{};
@@ -867,7 +868,7 @@ void launch_items(const dose_batch_item* items, int32_t n_items, hipStream_t s) 
   t.args = reinterpret_cast<const SpmvArgs*>(d + args_off);
   t.first = reinterpret_cast<const uint32_t*>(d);
   t.n_items = n_items;
-  const hipError_t e = launch_spmv_batched(m0->vf, sm, n_rhs, m0->A.idx_bytes, t, total, lds, s);
+  const hipError_t e = launch_spmv_batched(m0->vf, sm, n_rhs, 0, m0->A.idx_bytes, t, total, lds, s);
   // recorded even when the launch failed, so that the slot is free again
   const hipError_t er = hipEventRecord(R.done[slot], s);
   HIP_CHECK(e);

@@ -79,7 +79,7 @@ struct SpmvArgs {
   int32_t xcd_blocks;       // 0, or 8: workgroups go to the chip's 8 dies round-robin; give each die
                             // one contiguous eighth of the groups (so its L2 sees one eighth of the
                             // gathered vector); the order of every row's sum is unchanged
-  int32_t accumulate;       // 1: y[row] = y[row] + row value (empty rows: + 0) instead of the value
+  int32_t pad0;
 };
 
 // Entries of a quarter: lane l of a step loads the 4 entries at 4 l and at
@@ -115,9 +115,11 @@ struct BatchTable {
   int32_t n_items;
 };
 
-// Batched launch: n_work workgroups over the groups of all items.
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const BatchTable& t, int64_t n_work,
-                               int lds_floats, hipStream_t s);
+// Batched launch: n_work workgroups over the groups of all items.  With
+// accumulate (one vector only) every row value is added to what y holds
+// (empty rows: + 0) instead of stored.
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int accumulate, int idx_bytes, const BatchTable& t,
+                               int64_t n_work, int lds_floats, hipStream_t s);
 hipError_t launch_group_windows(GroupDesc* groups, int64_t n_groups, const void* col, int idx_bytes,
                                 const uint32_t* row_ptr, hipStream_t s);
 // Sets the n_pad padding indices after entry nnz - 1 to its column (0 when

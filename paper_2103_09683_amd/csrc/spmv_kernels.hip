@@ -296,8 +296,11 @@ __device__ __forceinline__ void fetch_rows(const SpmvArgs& a, RowCursor& rc, uin
   rc.hi = static_cast<int>(a.row_ptr[r + 1] - origin32);
 }
 
-// Lists the fetched window's non-empty rows and writes +0 to its empty ones.
-template <class T, int NRHS>
+// Lists the fetched window's non-empty rows and writes +0 to its empty ones
+// (ACC: adds +0 to them).  ACC is a template parameter, not a run-time flag:
+// as a flag, the compiler loaded y unconditionally and waited for all loads
+// in flight at every window, stream prefetch included.
+template <class T, int NRHS, bool ACC>
 __device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, uint32_t r_end) {
   const int lane = threadIdx.x & (kWave - 1);
   const uint32_t r = rc.wb + lane;
@@ -307,7 +310,7 @@ __device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, ui
     // accumulating products add +0 (so that a -0 already there becomes +0,
     // as in a sum of doses)
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) dst[q] = a.accumulate ? dst[q] + T(0) : T(0);
+    for (int q = 0; q < NRHS; ++q) dst[q] = ACC ? dst[q] + T(0) : T(0);
   }
   rc.mask = __ballot(in && rc.hi > rc.lo);
 }
@@ -323,7 +326,7 @@ struct Row {
 
 // The wave's next non-empty row, moving on to later 64-row windows (and
 // writing +0 to the empty rows passed) when the current one is done.
-template <class T, int NRHS>
+template <class T, int NRHS, bool ACC>
 __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32_t r_end, uint32_t origin32) {
   Row n;
   while (rc.mask == 0) {
@@ -333,7 +336,7 @@ __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32
       return n;
     }
     fetch_rows(a, rc, wb, r_end, origin32);
-    settle_rows<T, NRHS>(a, rc, r_end);
+    settle_rows<T, NRHS, ACC>(a, rc, r_end);
   }
   const int i = __builtin_ctzll(rc.mask);
   rc.mask &= rc.mask - 1;
@@ -486,15 +489,15 @@ __device__ __forceinline__ void add_half(const T (&p)[kChunk][NRHS], int s0, int
 }
 
 // Row value (valid in lane 63) times the row scale of an E4M3 operand, stored
-// or (a.accumulate: products of several matrices into one y, one launch after
+// or (ACC: products of several matrices into one y, one launch after
 // another) added to what y holds.
-template <class T, int SM, int NRHS>
+template <class T, int SM, int NRHS, bool ACC>
 __device__ __forceinline__ void store_row(const SpmvArgs& a, uint32_t row, float sc, const T (&tot)[NRHS]) {
   T* dst = static_cast<T*>(a.y) + static_cast<int64_t>(row) * NRHS;
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) {
     const T v = SM == kScaleRow ? tot[q] * static_cast<T>(sc) : tot[q];
-    dst[q] = a.accumulate ? dst[q] + v : v;
+    dst[q] = ACC ? dst[q] + v : v;
   }
 }
 
@@ -520,7 +523,7 @@ constexpr int kDepth = 1;
 // window of 4096 floats in one batch).
 constexpr int kCopy = 4;
 
-template <class T, int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT>
+template <class T, int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT, bool ACC>
 __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
                                             const void* safe, T (&tot)[NRHS], float& sc) {
@@ -587,8 +590,8 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   if (has_rows) {
     // the wave's first non-empty row; next_row moves on from rc.wb + 64 once
     // the first row window is done
-    settle_rows<T, NRHS>(a, rc, r_end);
-    cr = next_row<T, NRHS>(a, rc, r_end, origin32);
+    settle_rows<T, NRHS, ACC>(a, rc, r_end);
+    cr = next_row<T, NRHS, ACC>(a, rc, r_end, origin32);
   }
   if constexpr (WIN) {
     float4* xw4 = reinterpret_cast<float4*>(xw);
@@ -655,14 +658,14 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
       if constexpr (SPLIT) {
         cr.valid = false;
       } else {
-        if (lane == kWave - 1) store_row<T, SM, NRHS>(a, cr.row, sc, tot);
+        if (lane == kWave - 1) store_row<T, SM, NRHS, ACC>(a, cr.row, sc, tot);
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) {
           L[q] = T(-0.0);
 #pragma unroll
           for (int s = 0; s < kRowSlots; ++s) W[s][q] = T(0);
         }
-        cr = next_row<T, NRHS>(a, rc, r_end, origin32);
+        cr = next_row<T, NRHS, ACC>(a, rc, r_end, origin32);
       }
     }
   };
@@ -708,7 +711,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
 
 // One group on one workgroup.  `part` is LDS for the four slot sums of a
 // split row.
-template <class T, int VF, int SM, int NRHS, int IX>
+template <class T, int VF, int SM, int NRHS, int IX, bool ACC>
 __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp, float* xw, T* part) {
   // wave-uniform index, so that the row bounds below are scalar loads
   const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / kWave);
@@ -722,18 +725,18 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
     const uint32_t e0 = wave == 0 ? 0u : gp->ent[wave - 1], e1 = gp->ent[wave];
     if (win)
-      wave_stream<T, VF, SM, IX, NRHS, true, false>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), gp,
+      wave_stream<T, VF, SM, IX, NRHS, true, false, ACC>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), gp,
                                                     tot, sc);
     else
-      wave_stream<T, VF, SM, IX, NRHS, false, false>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, gp, tot, sc);
+      wave_stream<T, VF, SM, IX, NRHS, false, false, ACC>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, gp, tot, sc);
     return;
   }
   const uint32_t row = gp->row[0], len = gp->ent[kGroupWaves - 1];
   if (win)
-    wave_stream<T, VF, SM, IX, NRHS, true, true>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
+    wave_stream<T, VF, SM, IX, NRHS, true, true, ACC>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
                                                  gp, tot, sc);
   else
-    wave_stream<T, VF, SM, IX, NRHS, false, true>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, gp, tot, sc);
+    wave_stream<T, VF, SM, IX, NRHS, false, true, ACC>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, gp, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
@@ -743,7 +746,7 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
 #pragma unroll
     for (int q = 0; q < NRHS; ++q)
       r[q] = (part[0 * NRHS + q] + part[1 * NRHS + q]) + (part[2 * NRHS + q] + part[3 * NRHS + q]);
-    store_row<T, SM, NRHS>(a, row, SM == kScaleRow ? a.scale[row] : 1.0f, r);
+    store_row<T, SM, NRHS, ACC>(a, row, SM == kScaleRow ? a.scale[row] : 1.0f, r);
   }
 }
 
@@ -764,7 +767,7 @@ template <int VF, int SM, int NRHS, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats floats
   __shared__ float part[kGroupWaves * NRHS];
-  run_group<float, VF, SM, NRHS, IX>(a, a.groups + group_of_block(a, blockIdx.x), xw, part);
+  run_group<float, VF, SM, NRHS, IX, false>(a, a.groups + group_of_block(a, blockIdx.x), xw, part);
 }
 
 // FP64 x and y, FP64 products and sums (one vector): the paper's
@@ -773,7 +776,7 @@ template <int VF, int SM, int IX>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_f64(SpmvArgs a) {
   extern __shared__ __align__(16) float xw[];  // a.win_floats 4-byte words
   __shared__ double part[kGroupWaves];
-  run_group<double, VF, SM, 1, IX>(a, a.groups + group_of_block(a, blockIdx.x), xw, part);
+  run_group<double, VF, SM, 1, IX, false>(a, a.groups + group_of_block(a, blockIdx.x), xw, part);
 }
 
 // The item a workgroup of a batched launch belongs to without a work list:
@@ -795,18 +798,19 @@ __device__ __forceinline__ int find_item(const uint32_t* __restrict__ first, int
 
 // Batched form, one launch for many matrices: workgroup b takes entry b of
 // the work list (a copy of a group's descriptor that names its item), or,
-// without a work list, group b - first[i] of item i's matrix.
-template <int VF, int SM, int NRHS, int IX>
+// without a work list, group b - first[i] of item i's matrix.  ACC: every
+// row value is added to what y holds (one vector only).
+template <int VF, int SM, int NRHS, int IX, bool ACC>
 __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_spmv_batched(BatchTable t) {
   extern __shared__ __align__(16) float xw[];  // the largest win_floats of the items
   __shared__ float part[kGroupWaves * NRHS];
   if (t.work) {
     const GroupDesc* gp = t.work + blockIdx.x;
-    run_group<float, VF, SM, NRHS, IX>(t.args[gp->item], gp, xw, part);
+    run_group<float, VF, SM, NRHS, IX, ACC>(t.args[gp->item], gp, xw, part);
   } else {
     const int i = __builtin_amdgcn_readfirstlane(find_item(t.first, t.n_items, blockIdx.x));
     const SpmvArgs& a = t.args[i];
-    run_group<float, VF, SM, NRHS, IX>(a, a.groups + (blockIdx.x - t.first[i]), xw, part);
+    run_group<float, VF, SM, NRHS, IX, ACC>(a, a.groups + (blockIdx.x - t.first[i]), xw, part);
   }
 }
 
@@ -819,13 +823,13 @@ void launch_ix(const SpmvArgs& a, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((k_spmv<VF, SM, NRHS, 4>), grid, block, lds, s, a);
 }
 
-template <int VF, int SM, int NRHS>
+template <int VF, int SM, int NRHS, bool ACC>
 void launch_ix_batched(int idx_bytes, const BatchTable& t, int64_t n_work, size_t lds, hipStream_t s) {
   const dim3 g(static_cast<unsigned>(n_work)), block(kGroupThreads);
   if (SM != kScaleCol && idx_bytes == 2)
-    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, SM == kScaleCol ? 4 : 2>), g, block, lds, s, t);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, SM == kScaleCol ? 4 : 2, ACC>), g, block, lds, s, t);
   else
-    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 4>), g, block, lds, s, t);
+    hipLaunchKernelGGL((k_spmv_batched<VF, SM, NRHS, 4, ACC>), g, block, lds, s, t);
 }
 
 template <int VF, int SM>
@@ -841,13 +845,19 @@ hipError_t launch_rhs(int n_rhs, const SpmvArgs& a, hipStream_t s) {
 }
 
 template <int VF, int SM>
-hipError_t launch_rhs_batched(int n_rhs, int idx_bytes, const BatchTable& t, int64_t n_work, int lds_floats,
-                              hipStream_t s) {
+hipError_t launch_rhs_batched(int n_rhs, int accumulate, int idx_bytes, const BatchTable& t, int64_t n_work,
+                              int lds_floats, hipStream_t s) {
   const size_t lds = static_cast<size_t>(lds_floats) * sizeof(float);
+  if (accumulate && n_rhs != 1) return hipErrorInvalidValue;
   switch (n_rhs) {
-    case 1: launch_ix_batched<VF, SM, 1>(idx_bytes, t, n_work, lds, s); break;
-    case 2: launch_ix_batched<VF, SM, 2>(idx_bytes, t, n_work, lds, s); break;
-    case 4: launch_ix_batched<VF, SM, 4>(idx_bytes, t, n_work, lds, s); break;
+    case 1:
+      if (accumulate)
+        launch_ix_batched<VF, SM, 1, true>(idx_bytes, t, n_work, lds, s);
+      else
+        launch_ix_batched<VF, SM, 1, false>(idx_bytes, t, n_work, lds, s);
+      break;
+    case 2: launch_ix_batched<VF, SM, 2, false>(idx_bytes, t, n_work, lds, s); break;
+    case 4: launch_ix_batched<VF, SM, 4, false>(idx_bytes, t, n_work, lds, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -924,19 +934,19 @@ hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const BatchTable& t, int64_t n_work,
-                               int lds_floats, hipStream_t s) {
+hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int accumulate, int idx_bytes, const BatchTable& t,
+                               int64_t n_work, int lds_floats, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
   if (vf == kFp16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
+    return launch_rhs_batched<kBf16, kScaleNone>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp32 && scale_mode == kScaleNone)
-    return launch_rhs_batched<kFp32, kScaleNone>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp32, kScaleNone>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleRow)
-    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)
-    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, idx_bytes, t, n_work, lds_floats, s);
+    return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   return hipErrorInvalidValue;
 }
 
