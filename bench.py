@@ -223,8 +223,10 @@ def bench_headline(torch, dm, dosegen, args):
 
 def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
     """On the headline matrix: FP32 vectors in FP16 (the stored A), the
-    adjoint in FP32 and FP64; then BF16 and E4M3 values (forward and adjoint)
-    and 16-bit indices in the three formats (forward)."""
+    adjoint in FP32 and FP64; then BF16 and E4M3 values (forward and adjoint),
+    16-bit indices in the three formats (forward), and the FP16 matrix in
+    SELL-C-sigma form (sigma 65,536) with run-length and 16-bit indices, one
+    and four vectors."""
     import numpy as np
     reps = max(20, args.steps)
     x = torch.from_numpy(x_h).cuda()
@@ -270,6 +272,25 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
         res[fmt + "_u16"] = entry(M)
         M.close()
         torch.cuda.empty_cache()
+    X = torch.from_numpy(np.stack([x_h] + [dosegen_weights(spec, r) for r in range(1, 4)], 1)).cuda().contiguous()
+    Y = torch.empty(spec.n_rows, 4, dtype=torch.float32, device="cuda")
+    for idx in ("runs", "u16"):
+        t0 = time.time()
+        S = dm.SellMatrix(rp, cols, vals, spec.n_cols, "fp16", sigma=65536, index_format=idx)
+        log(f"{spec.name} SELL {idx}: created in {time.time() - t0:.1f}s")
+        info = S.info()
+        ms = time_launches(lambda: S.spmv(x, y), reps, 3)
+        ms4 = time_launches(lambda: S.spmv(X, Y), max(10, reps // 4), 3)
+        b4 = info["spmv_bytes"] + 3 * 4 * (spec.n_cols + spec.n_rows)
+        res["fp16_sell_" + idx] = {
+            "sigma": 65536, "forward_ms": round(ms, 4), "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
+            "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
+            "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "spmv_bytes": info["spmv_bytes"], "padding_frac": round(info["stored_slots"] / max(info["nnz"], 1) - 1, 4),
+            "four_vectors_ms": round(ms4, 4), "four_vectors_GNNZ_per_s": round(info["nnz"] / (ms4 * 1e-3) / 1e9, 1),
+            "four_vectors_frac": round(b4 / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        S.close()
+        torch.cuda.empty_cache()
     log(f"{spec.name} variants: " + json.dumps(res))
     return res
 
@@ -277,6 +298,11 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
 def dosegen_signed(spec):
     import dosegen
     return dosegen.signed_values(spec.seed, 3, spec.n_rows)
+
+
+def dosegen_weights(spec, r):
+    import dosegen
+    return dosegen.spot_weights(spec.seed, r, spec.n_cols)
 
 
 def bench_clinical(torch, dm, dosegen, args):
@@ -637,7 +663,11 @@ def bench_scenarios(torch, dm, dosegen, args):
     autotuned batched graph launch, then the epilogue (scenario doses, seeds,
     FP64 scenario objectives, worst case and expectation).  Reports the step,
     the epilogue alone and its share; epilogue algorithmic bytes are the beam
-    doses read once, p and w read once, scenario doses and seeds written once."""
+    doses read once, p and w read once, scenario doses and seeds written once.
+    Also the step with the beam sum done by the products, and the step with
+    the beam products of one SELL-C-sigma plan launch (run-length indices;
+    the largest relative difference of its scenario doses from the CSR
+    step's)."""
     import numpy as np
     n_scen, n_beams = 9, 4
     specs = dosegen.robust_scenarios(args.scenario_scale, n_scen, n_beams)
@@ -645,13 +675,21 @@ def bench_scenarios(torch, dm, dosegen, args):
     xs = [torch.from_numpy(dosegen.spot_weights(dosegen.SEED0 + 6, b, specs[b].n_cols)).cuda()
           for b in range(n_beams)]
     part = torch.empty(n_scen, n_beams, n, dtype=torch.float32, device="cuda")
-    mats, entries, nnz_tot = [], [], 0
+    part_s = torch.empty_like(part)
+    mats, entries, sells, sentries, nnz_tot = [], [], [], [], 0
     for m, sp in enumerate(specs):
         rp, cols, vals = dosegen.csr(sp)
         A = dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16")
         mats.append(A)
         s, b = divmod(m, n_beams)
         entries.append((A, xs[b], part[s, b]))
+        # the same beam products in SELL-C-sigma form (run-length indices)
+        try:
+            S = dm.SellMatrix(rp, cols, vals, sp.n_cols, "fp16", sigma=BATCH_SELL_SIGMA, index_format="runs")
+        except dm.DoseError:
+            S = dm.SellMatrix(rp, cols, vals, sp.n_cols, "fp16", sigma=BATCH_SELL_SIGMA, index_format="u16")
+        sells.append(S)
+        sentries.append((S, xs[b], part_s[s, b]))
         nnz_tot += int(rp[-1])
     g = np.random.default_rng(6)
     p = torch.from_numpy(g.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)).cuda()
@@ -690,9 +728,27 @@ def bench_scenarios(torch, dm, dosegen, args):
     fused_equal = bool(torch.equal(d_f.view(torch.int32), d_out.view(torch.int32))) and \
         bool(torch.equal(out_f.view(torch.int64), out.view(torch.int64)))
     fplan.close()
+    # the step with the beam products of one SELL-C-sigma plan launch
+    splan = dm.SellBatchPlan(sentries)
+    d_s, seed_s, out_s = torch.empty_like(d_out), torch.empty_like(seed), torch.empty_like(out)
+
+    def step_sell():
+        splan.launch()
+        dm.scenario_objective(part_s, p, w, prob=prob, d_out=d_s, seed=seed_s, out=out_s)
+
+    ms_sell = time_launches(step_sell, reps, 3)
+    step()
+    step_sell()
+    torch.cuda.synchronize()
+    sell_rel = float(((d_s.double() - d_out.double()).abs() / d_out.double().abs().clamp_min(1e-300)).max())
+    splan.close()
+    for S in sells:
+        S.close()
     epi_bytes = 4 * n * (n_scen * n_beams + 2 + 2 * n_scen)
     res = {"ms_step": round(ms_step, 4), "ms_epilogue": round(ms_epi, 4),
            "ms_step_beam_sum_in_products": round(ms_fused, 4), "beam_sum_in_products_bitwise_equal": fused_equal,
+           "ms_step_sell_runs": round(ms_sell, 4), "sell_sigma": BATCH_SELL_SIGMA,
+           "sell_max_rel_diff_of_scenario_doses": sell_rel,
            "epilogue_share": round(ms_epi / ms_step, 4), "scenarios": n_scen, "beams": n_beams,
            "voxels": n, "nnz": nnz_tot, "GNNZ_per_s": round(nnz_tot / (ms_step * 1e-3) / 1e9, 2),
            "epilogue_GBps_algorithmic": round(epi_bytes / (ms_epi * 1e-3) / 1e9, 1),
@@ -700,7 +756,7 @@ def bench_scenarios(torch, dm, dosegen, args):
     plan.close()
     for A in mats:
         A.close()
-    del entries, part, d_out, seed, d_f
+    del entries, sentries, part, part_s, d_out, seed, d_f, d_s, seed_s
     torch.cuda.empty_cache()
     res["epilogue_full_grid"] = bench_epilogue_full(torch, dm, reps)
     return res

@@ -81,7 +81,16 @@ typedef enum {
 } dose_index_format;
 
 /* dose_matrix_create flags */
-enum { DOSE_CREATE_TRANSPOSE = 1u }; /* also store A^T for dose_spmv_adjoint */
+enum {
+  DOSE_CREATE_TRANSPOSE = 1u, /* also store A^T for dose_spmv_adjoint */
+  DOSE_CREATE_AUTOTUNE = 2u   /* time the plain one-vector product (and the adjoint
+                                 with DOSE_CREATE_TRANSPOSE) under row groups of 8K,
+                                 16K, 32K and 64K entries on hip_stream and keep the
+                                 fastest, as the paper sweeps its thread-block size
+                                 (Sec. V-A); a choice stored in the DOSE_TUNE_CACHE
+                                 file is reused.  Speed only: products are bitwise
+                                 the same under any partition. */
+};
 
 /* Which stored operand dose_matrix_decode reads. */
 enum { DOSE_PART_A = 0, DOSE_PART_AT = 1 };

@@ -26,6 +26,7 @@ IDX_I32 = 1
 IDX_U16 = 2
 IDX_RUNS = 3
 CREATE_TRANSPOSE = 1
+CREATE_AUTOTUNE = 2
 PART_A, PART_AT = 0, 1
 PLAN_AUTOTUNE = 1
 ROBUST_EXPECTED, ROBUST_WORST = 0, 1

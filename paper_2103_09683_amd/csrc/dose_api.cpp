@@ -655,8 +655,8 @@ double time_partition(dose_matrix_s* m, const Operand& op, const Partition& P, i
 // under any of them).  The matrix itself is left as it is, so products on
 // other streams may use it meanwhile.  Returns the chosen partition, or null
 // when the matrix's own partition already has the chosen size.
-std::unique_ptr<Partition> autotune_matrix(dose_matrix_s* m, int n_rhs, const float* x, float* y, hipStream_t s) {
-  const Operand& op = m->A;
+std::unique_ptr<Partition> autotune_operand(dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const float* x,
+                                            float* y, hipStream_t s) {
   const std::string key = tune_key(m, op, n_rhs);
   int best = tune_lookup(key);
   std::unique_ptr<Partition> best_p;
@@ -664,7 +664,7 @@ std::unique_ptr<Partition> autotune_matrix(dose_matrix_s* m, int n_rhs, const fl
     double best_t = 1e30;
     for (int g = 8192; g <= 65536; g *= 2) {
       auto P = std::make_unique<Partition>(make_partition(op, g, s));
-      const double t = time_partition(m, op, *P, scale_mode_A(m), n_rhs, x, y, s);
+      const double t = time_partition(m, op, *P, sm, n_rhs, x, y, s);
       if (t < best_t) best_t = t, best = g, best_p = std::move(P);
     }
     tune_store(key, best);
@@ -672,6 +672,10 @@ std::unique_ptr<Partition> autotune_matrix(dose_matrix_s* m, int n_rhs, const fl
   if (op.part.group_nnz == best) return nullptr;
   if (!best_p) best_p = std::make_unique<Partition>(make_partition(op, best, s));
   return best_p;
+}
+
+std::unique_ptr<Partition> autotune_matrix(dose_matrix_s* m, int n_rhs, const float* x, float* y, hipStream_t s) {
+  return autotune_operand(m, m->A, scale_mode_A(m), n_rhs, x, y, s);
 }
 
 // The partition each distinct matrix of the items runs under in a plan: its
@@ -1207,6 +1211,8 @@ dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf, int32_t xf,
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
     *out = nullptr;
     if (xf == DOSE_IDX_RUNS) fail(DOSE_ERR_UNSUPPORTED, "run-length indices are a SELL-C-sigma format (dose_sell_create)");
+    if (flags & ~static_cast<uint32_t>(DOSE_CREATE_TRANSPOSE | DOSE_CREATE_AUTOTUNE))
+      fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
     validate_csr(csr, vf, xf);
     hipStream_t s = as_stream(hip_stream);
     auto m = upload_encode_A(csr, vf, xf, s);
@@ -1215,6 +1221,22 @@ dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf, int32_t xf,
     if (flags & DOSE_CREATE_TRANSPOSE) {
       build_transpose(m.get(), default_group_nnz(A.nnz, m->device), s);
       m->has_t = true;
+    }
+    if (flags & DOSE_CREATE_AUTOTUNE) {
+      // the plain one-vector products timed under candidate row-group sizes
+      // (the paper's block-size sweep, Sec. V-A), on scratch vectors of zeros
+      const int64_t nr = std::max<int64_t>(A.n_rows, 1), nc = std::max<int64_t>(A.n_cols, 1);
+      DevBuf xa(static_cast<size_t>(nc) * 4), ya(static_cast<size_t>(nr) * 4);
+      HIP_CHECK(hipMemsetAsync(xa.get(), 0, xa.bytes(), s));
+      HIP_CHECK(hipMemsetAsync(ya.get(), 0, ya.bytes(), s));
+      if (A.nnz > 0) {
+        auto P = autotune_operand(m.get(), A, scale_mode_A(m.get()), 1, xa.get<float>(), ya.get<float>(), s);
+        if (P) A.part = std::move(*P);
+        if (m->has_t) {
+          auto PT = autotune_operand(m.get(), m->AT, scale_mode_AT(m.get()), 1, ya.get<float>(), xa.get<float>(), s);
+          if (PT) m->AT.part = std::move(*PT);
+        }
+      }
     }
     HIP_CHECK(hipStreamSynchronize(s));
     *out = m.release();

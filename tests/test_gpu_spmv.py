@@ -120,6 +120,36 @@ def test_partitions_long_rows_and_ragged_tail(fmt, dev):
     A.close()
 
 
+def test_create_autotune(tmp_path, monkeypatch, dev):
+    """DOSE_CREATE_AUTOTUNE picks a row-group size from the timed candidates
+    for A and A^T; the products are bitwise those of the default partition;
+    the choice is written to and read back from DOSE_TUNE_CACHE; unknown
+    create flags are refused."""
+    monkeypatch.setenv("DOSE_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    rng = np.random.default_rng(12)
+    lens = rng.integers(0, 700, size=40000)
+    lens[rng.random(lens.size) < 0.5] = 0
+    rp, cols, vals = _csr_from_lens(rng, lens, 6000)
+    x = torch.from_numpy(rng.uniform(0, 1, 6000).astype(np.float32)).cuda()
+    v = torch.from_numpy(rng.uniform(-1, 1, lens.size).astype(np.float32)).cuda()
+    A0 = dm.DoseMatrix(rp, cols, vals, 6000, "fp16", transpose=True)
+    for rep in range(2):
+        _say("autotuned create", rep)
+        A1 = dm.DoseMatrix(rp, cols, vals, 6000, "fp16", transpose=True, autotune=True)
+        inf = A1.info()
+        assert inf["group_nnz"] in (8192, 16384, 32768, 65536)
+        assert inf["group_nnz_t"] in (8192, 16384, 32768, 65536)
+        assert np.array_equal(_bits(A1.spmv(x).cpu().numpy()), _bits(A0.spmv(x).cpu().numpy()))
+        assert np.array_equal(_bits(A1.adjoint(v).cpu().numpy()), _bits(A0.adjoint(v).cpu().numpy()))
+        A1.close()
+    assert len((tmp_path / "tune.txt").read_text().split()) == 4  # two keys, each stored once
+    c, keep = dm._csr_struct(rp, cols, vals, 6000)
+    h = dm.ctypes.c_void_p()
+    assert dm._lib.load().dose_matrix_create(dm.ctypes.byref(c), dm._lib.VAL_FP16, dm._lib.IDX_I32, 4, None,
+                                             dm.ctypes.byref(h)) == dm._lib.ERR_INVALID_ARGUMENT
+    A0.close()
+
+
 def test_rows_across_many_row_windows(dev):
     """A wave lists its rows 64 at a time; with short rows and large groups
     each wave walks many such windows, and the first non-empty row of every

@@ -103,3 +103,30 @@ def test_sweep_large_forward_and_adjoint(sweep, fmt, dev):
     bound = float(np.dot(np.abs(vd).astype(np.float64), y.astype(np.float64)))
     assert abs(lhs - rhs) <= 2 * TOL * bound, (fmt, lhs, rhs, bound)
     A.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("idx", ["runs", "u16"])
+def test_sweep_large_sell(sweep, idx, dev):
+    """SELL-C-sigma form (sigma 65,536) of the largest workload: one vector on
+    the sampled rows against the oracle, +0 on every empty row; four vectors
+    bitwise equal to the single-vector products of their columns."""
+    spec, rp, cols, vals, rows, (srp, scols, svals) = sweep
+    t0 = time.time()
+    S = dm.SellMatrix(rp, cols, vals, spec.n_cols, "fp16", sigma=65536, index_format=idx)
+    _say(f"sell {idx} created in {time.time() - t0:.1f}s", S.info())
+    x_h = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
+    y = S.spmv(torch.from_numpy(x_h).cuda()).cpu().numpy()
+    dec, _ = oracle.decode_matrix("fp16", srp, svals)
+    err = oracle.max_rel_err(y[rows], oracle.spmv(srp, scols, dec, x_h))
+    _say(f"sell {idx}: forward max rel err {err:.3e} on {rows.size} sampled rows")
+    assert err <= TOL
+    lens = np.diff(rp)
+    assert np.all(_bits(y[lens == 0]) == 0) and np.all(y[lens > 0] > 0)
+    X = torch.from_numpy(np.stack([dosegen.spot_weights(spec.seed, r, spec.n_cols) for r in range(4)], 1)).cuda()
+    Y = S.spmv(X.contiguous()).cpu().numpy()
+    assert np.array_equal(_bits(Y[:, 0]), _bits(y))
+    for r in range(1, 4):
+        yr = S.spmv(X[:, r].contiguous()).cpu().numpy()
+        assert np.array_equal(_bits(Y[:, r]), _bits(yr)), r
+    S.close()
