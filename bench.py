@@ -226,7 +226,7 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
     adjoint in FP32 and FP64; then BF16 and E4M3 values (forward and adjoint),
     16-bit indices in the three formats (forward), and the FP16 matrix in
     SELL-C-sigma form (sigma 65,536) with run-length and 16-bit indices, one
-    and four vectors."""
+    and four FP32 vectors and one FP64 vector (half/double)."""
     import numpy as np
     reps = max(20, args.steps)
     x = torch.from_numpy(x_h).cuda()
@@ -274,6 +274,8 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
         torch.cuda.empty_cache()
     X = torch.from_numpy(np.stack([x_h] + [dosegen_weights(spec, r) for r in range(1, 4)], 1)).cuda().contiguous()
     Y = torch.empty(spec.n_rows, 4, dtype=torch.float32, device="cuda")
+    x64 = x.double()
+    y64 = torch.empty(spec.n_rows, dtype=torch.float64, device="cuda")
     for idx in ("runs", "u16"):
         t0 = time.time()
         S = dm.SellMatrix(rp, cols, vals, spec.n_cols, "fp16", sigma=65536, index_format=idx)
@@ -281,14 +283,18 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
         info = S.info()
         ms = time_launches(lambda: S.spmv(x, y), reps, 3)
         ms4 = time_launches(lambda: S.spmv(X, Y), max(10, reps // 4), 3)
+        ms64 = time_launches(lambda: S.spmv(x64, y64), max(10, reps // 4), 3)
         b4 = info["spmv_bytes"] + 3 * 4 * (spec.n_cols + spec.n_rows)
+        b64 = info["spmv_bytes"] + 4 * (spec.n_cols + spec.n_rows)  # 8-byte x and y
         res["fp16_sell_" + idx] = {
             "sigma": 65536, "forward_ms": round(ms, 4), "forward_GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 1),
             "forward_GBps": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9, 1),
             "forward_frac": round(info["spmv_bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
             "spmv_bytes": info["spmv_bytes"], "padding_frac": round(info["stored_slots"] / max(info["nnz"], 1) - 1, 4),
             "four_vectors_ms": round(ms4, 4), "four_vectors_GNNZ_per_s": round(info["nnz"] / (ms4 * 1e-3) / 1e9, 1),
-            "four_vectors_frac": round(b4 / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+            "four_vectors_frac": round(b4 / (ms4 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+            "half_double_ms": round(ms64, 4), "half_double_GNNZ_per_s": round(info["nnz"] / (ms64 * 1e-3) / 1e9, 1),
+            "half_double_frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
         S.close()
         torch.cuda.empty_cache()
     log(f"{spec.name} variants: " + json.dumps(res))

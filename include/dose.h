@@ -450,6 +450,14 @@ dose_status dose_sell_runs(dose_sell m, int64_t* run_ptr, int32_t* start, int32_
  * hip_stream. */
 dose_status dose_sell_spmv(dose_sell m, const float* x, float* y, void* hip_stream);
 
+/* y = A x for one FP64 vector over the SELL-C-sigma form: FP64 x (device,
+ * n_cols), FP64 y (device, n_rows, every entry written), FP64 products and
+ * sums in dose_sell_spmv's order (the paper's half/double arithmetic,
+ * Sec. II-D).  Both 8-byte aligned, not overlapping (else
+ * DOSE_ERR_INVALID_ARGUMENT); n_cols below 2^30 (else DOSE_ERR_UNSUPPORTED).
+ * Asynchronous on hip_stream. */
+dose_status dose_sell_spmv_f64(dose_sell m, const double* x, double* y, void* hip_stream);
+
 /* Y = A X for n_rhs spot-weight vectors at once (n_rhs 1, 2 or 4; the
  * multi-vector product of robust planning, Sec. I, II-A): x device
  * [n_cols][n_rhs], y device [n_rows][n_rhs] FP32, row-major (vector r at

@@ -272,10 +272,18 @@ class SellMatrix:
         return run_ptr, start[:inf["n_runs"]], length[:inf["n_runs"]]
 
     def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        """y = A x (FP32), asynchronous on the current (or given) stream.  x of
+        """y = A x, asynchronous on the current (or given) stream.  FP32 x of
         shape (n_cols,) gives y (n_rows,); x (n_cols, n_rhs) with n_rhs 1, 2
         or 4 gives y (n_rows, n_rhs), each column bitwise the product of x's
-        column."""
+        column; FP64 x (n_cols,) gives FP64 y with FP64 products and sums
+        (the paper's half/double configuration)."""
+        if x.dtype == torch.float64:
+            if y is None:
+                y = torch.empty(self.n_rows, dtype=torch.float64, device=x.device)
+            _lib.check(_lib.load().dose_sell_spmv_f64(
+                self.handle, _dev_ptr(x, self.n_cols, "x", self.device, torch.float64),
+                _dev_ptr(y, self.n_rows, "y", self.device, torch.float64), _stream_handle(stream)))
+            return y
         if x.dim() == 2:
             n_rhs = x.shape[1]
             if x.shape[0] != self.n_cols:

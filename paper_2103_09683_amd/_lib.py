@@ -106,6 +106,7 @@ SIGNATURES = {
     "dose_sell_runs": ([_vp, _vp, _vp, _vp], _i32),
     "dose_sell_spmv": ([_vp, _vp, _vp, _vp], _i32),
     "dose_sell_spmv_multi": ([_vp, _i32, _vp, _vp, _vp], _i32),
+    "dose_sell_spmv_f64": ([_vp, _vp, _vp, _vp], _i32),
     "dose_sell_batch_plan_create": ([ctypes.POINTER(SellBatchItem), _i32, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_sell_destroy": ([_vp], _i32),
     "dose_status_string": ([_i32], ctypes.c_char_p),

@@ -1033,7 +1033,8 @@ struct dose_sell_s {
 
 namespace {
 
-SellArgs sell_args(const dose_sell_s* m, int n_rhs, const float* x, float* y) {
+// n_rhs selects the LDS window (2 for one FP64 vector: 8 bytes a column).
+SellArgs sell_args(const dose_sell_s* m, int n_rhs, const void* x, void* y) {
   SellArgs a{};
   a.chunks = m->chunks.get<SellChunk>();
   a.win = m->win.get<uint32_t>();
@@ -1893,6 +1894,20 @@ dose_status dose_sell_spmv(dose_sell m, const float* x, float* y, void* hip_stre
     DeviceGuard g(m->device);
     HIP_CHECK(launch_sell_spmv(m->vf, m->vf == kFp8 ? kScaleRow : kScaleNone, 1, sell_args(m, 1, x, y),
                                as_stream(hip_stream)));
+  });
+}
+
+dose_status dose_sell_spmv_f64(dose_sell m, const double* x, double* y, void* hip_stream) {
+  return guarded([&] {
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "matrix is null");
+    if ((m->n_cols > 0 && !x) || (m->n_rows > 0 && !y)) fail(DOSE_ERR_INVALID_ARGUMENT, "null x or y");
+    if (overlaps(x, m->n_cols * 8, y, m->n_rows * 8)) fail(DOSE_ERR_INVALID_ARGUMENT, "x and y overlap");
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) % 8 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "x and y must be 8-byte aligned");
+    if (m->n_cols > INT32_MAX / 2) fail(DOSE_ERR_UNSUPPORTED, "n_cols must stay below 2^30");
+    DeviceGuard g(m->device);
+    HIP_CHECK(launch_sell_spmv_f64(m->vf, m->vf == kFp8 ? kScaleRow : kScaleNone, sell_args(m, 2, x, y),
+                                   as_stream(hip_stream)));
   });
 }
 

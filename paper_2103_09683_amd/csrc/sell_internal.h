@@ -67,11 +67,12 @@ struct SellArgs {
   const SellRun* runs;
   const uint32_t* work;     // the chunks holding entries, ascending (one workgroup each)
   const uint32_t* zero;     // the chunks without entries (their rows get +0; 4 per workgroup)
-  const float* x;           // [n_cols][n_rhs] FP32
-  float* y;                 // [n_rows][n_rhs] FP32
+  const void* x;            // [n_cols][n_rhs] FP32, or [n_cols] FP64 (launch_sell_spmv_f64)
+  void* y;                  // [n_rows][n_rhs] FP32, or [n_rows] FP64
   int64_t n_groups;         // chunks holding entries
   int64_t n_zero;           // chunks without entries
-  int32_t win_floats;       // LDS window floats for the launch's n_rhs (0: no group uses the LDS window)
+  int32_t win_floats;       // LDS window 4-byte words for the launch's vectors (0: no group uses the LDS
+                            // window); an FP64 vector's window is that of two FP32 ones
   int32_t idx_bytes;        // 4, 2, or 0 (run-length indices)
   int32_t xcd_blocks;
   int32_t lds_runs;         // run-length indices: most runs of one group (LDS records)
@@ -96,6 +97,9 @@ struct SellBatchTable {
 hipError_t launch_sell_spmv(int vf, int scale_mode, int n_rhs, const SellArgs& a, hipStream_t s);
 hipError_t launch_sell_batched(int vf, int scale_mode, int n_rhs, int idx_bytes, const SellBatchTable& t,
                                size_t lds_bytes, hipStream_t s);
+// y = A x for one FP64 vector: FP64 products and sums (a.win_floats as for
+// two FP32 vectors).
+hipError_t launch_sell_spmv_f64(int vf, int scale_mode, const SellArgs& a, hipStream_t s);
 // Dynamic LDS bytes of a launch of a (the largest over a batch's items).
 size_t sell_launch_lds_bytes(const SellArgs& a);
 // Scatter of CSR codes and columns into the slice layout.  start: per row

@@ -125,14 +125,16 @@ __device__ __forceinline__ void lane_cols(const Lane8<VF, IX>& L, int (&c)[kSell
   for (int e = 0; e < kSellLaneEntries; ++e) asm("" : "+v"(c[e]));  // keep each LDS address one shift-add
 }
 
-// The n_rhs values of x at p (row-major x: 4 n_rhs-byte aligned).
-template <int NRHS>
+// The n_rhs values of x at p (row-major x aligned to n_rhs values; V is
+// float, or double for one FP64 vector).
+template <class V, int NRHS>
 struct XV {
-  float v[NRHS];
+  V v[NRHS];
 };
-template <int NRHS>
-__device__ __forceinline__ XV<NRHS> x_at(const float* p) {
-  XV<NRHS> r;
+template <class V, int NRHS>
+__device__ __forceinline__ XV<V, NRHS> x_at(const V* p) {
+  static_assert(NRHS == 1 || sizeof(V) == 4, "several vectors are FP32");
+  XV<V, NRHS> r;
   if constexpr (NRHS == 1) {
     r.v[0] = p[0];
   } else if constexpr (NRHS == 2) {
@@ -174,19 +176,19 @@ __device__ __forceinline__ void slice_codes(const Lane8<VF, IX>& L, float (&d)[k
 }
 
 // The lane's 8 products of a slice for each vector: decoded code times x of
-// its column, rounded once.  x comes from the LDS window (xb: the window
-// moved back by cmin columns) or from global memory.
-template <int VF, int IX, bool WIN, int NRHS>
+// its column, rounded once (in FP64 for an FP64 vector: the decoded code is
+// exact in both).  x comes from the LDS window (xb: the window moved back by
+// cmin columns) or from global memory.
+template <class V, int VF, int IX, bool WIN, int NRHS>
 __device__ __forceinline__ void slice_products(const Lane8<VF, IX>& L, const int (&c)[kSellLaneEntries],
-                                               const float* xb, const float* x,
-                                               float (&p)[kSellLaneEntries][NRHS]) {
-  XV<NRHS> xv[kSellLaneEntries];
+                                               const V* xb, const V* x, V (&p)[kSellLaneEntries][NRHS]) {
+  XV<V, NRHS> xv[kSellLaneEntries];
 #pragma unroll
   for (int e = 0; e < kSellLaneEntries; ++e) {
     if constexpr (WIN) {
-      xv[e] = x_at<NRHS>(xb + c[e] * NRHS);
+      xv[e] = x_at<V, NRHS>(xb + c[e] * NRHS);
     } else {
-      xv[e] = x_at<NRHS>(x + static_cast<int64_t>(c[e]) * NRHS);
+      xv[e] = x_at<V, NRHS>(x + static_cast<int64_t>(c[e]) * NRHS);
     }
   }
   float d[kSellLaneEntries];
@@ -195,17 +197,17 @@ __device__ __forceinline__ void slice_products(const Lane8<VF, IX>& L, const int
   for (int e = 0; e < kSellLaneEntries; ++e)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) {
-      if constexpr (VF == kFp16) {
+      if constexpr (VF == kFp16 && sizeof(V) == 4) {
         // an FMA with +0 rounds the product once, as a multiply does (v_fma_mix)
         p[e][q] = __builtin_fmaf(d[e], xv[e].v[q], 0.0f);
       } else {
-        p[e][q] = d[e] * xv[e].v[q];
+        p[e][q] = static_cast<V>(d[e]) * xv[e].v[q];
       }
     }
 }
 
-template <int NRHS>
-__device__ __forceinline__ float slice_sum(const float (&p)[kSellLaneEntries][NRHS], int q) {
+template <class V, int NRHS>
+__device__ __forceinline__ V slice_sum(const V (&p)[kSellLaneEntries][NRHS], int q) {
   return ((p[0][q] + p[1][q]) + (p[2][q] + p[3][q])) + ((p[4][q] + p[5][q]) + (p[6][q] + p[7][q]));
 }
 
@@ -217,12 +219,6 @@ __device__ __forceinline__ int64_t sell_group_of_block(int D, int64_t n, uint32_
   const int64_t q = n / D, r = n % D;
   const int64_t x = b % static_cast<uint32_t>(D), i = b / static_cast<uint32_t>(D);
   return x * q + (x < r ? x : r) + i;
-}
-
-// Wave-uniform pick of one of four values by a wave-uniform index.
-template <class T>
-__device__ __forceinline__ T pick4(int c, T v0, T v1, T v2, T v3) {
-  return c == 0 ? v0 : c == 1 ? v1 : c == 2 ? v2 : v3;
 }
 
 // Columns of a lane's 8 entries at positions P .. P + 7 of its row from the
@@ -245,9 +241,9 @@ __device__ __forceinline__ void walk_runs(const SellRun* lruns, int ri, int re, 
   }
 }
 
-// Stores a row's n_rhs values (y row-major, 4 n_rhs-byte aligned).
-template <int NRHS>
-__device__ __forceinline__ void store_rhs(float* dst, const float (&v)[NRHS]) {
+// Stores a row's n_rhs values (y row-major, aligned to n_rhs values).
+template <class V, int NRHS>
+__device__ __forceinline__ void store_rhs(V* dst, const V (&v)[NRHS]) {
   if constexpr (NRHS == 1) {
     dst[0] = v[0];
   } else if constexpr (NRHS == 2) {
@@ -258,9 +254,10 @@ __device__ __forceinline__ void store_rhs(float* dst, const float (&v)[NRHS]) {
 }
 
 // Chunk c of a's matrix on one workgroup.  part: LDS for the waves' row
-// sums, kGroupWaves * NRHS * 64 floats.
-template <int VF, int SM, int IX, bool WIN, int NRHS>
-__device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* xw, float* part) {
+// sums, kGroupWaves * NRHS * 64 values.  V: the vectors' type (float, or
+// double for one FP64 vector: FP64 products and sums in the same order).
+template <class V, int VF, int SM, int IX, bool WIN, int NRHS>
+__device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* xw, V* part) {
   const int tid = static_cast<int>(threadIdx.x);
   const int lane = tid & (kWave - 1);
   const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -297,13 +294,14 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
   // waiting for the window leaves the slices in flight: the x window (16-byte
   // pieces, a thread's first four at once), then the wave's first NB slices.
   const int cmin = static_cast<int>(a.win[2 * c]);  // also the padding column
-  int nf = 0, n4 = 0;  // window floats (its columns times NRHS), whole 16-byte pieces
-  const float* xs = a.x;
+  // window 4-byte words (its columns times NRHS, two per FP64 value), whole 16-byte pieces
+  int nf = 0, n4 = 0;
+  const float* xs = static_cast<const float*>(a.x);
   float4 w0, w1, w2, w3;
   float wt = 0.0f;
   if constexpr (WIN) {
-    nf = static_cast<int>(a.win[2 * c + 1]) * NRHS;
-    xs = a.x + static_cast<int64_t>(cmin) * NRHS;
+    nf = static_cast<int>(a.win[2 * c + 1]) * NRHS * static_cast<int>(sizeof(V) / 4);
+    xs = reinterpret_cast<const float*>(static_cast<const V*>(a.x) + static_cast<int64_t>(cmin) * NRHS);
     n4 = nf >> 2;
     const float4* xs4 = reinterpret_cast<const float4*>(xs);
     const float4* safe4 = reinterpret_cast<const float4*>(ch);
@@ -338,13 +336,14 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     for (int j = tid + 2 * kGroupThreads; j < nruns; j += kGroupThreads) lruns[j] = a.runs[g0 + j];
   }
 #pragma unroll
-  for (int q = 0; q < NRHS; ++q) part[(wave * NRHS + q) * kWave + lane] = 0.0f;
+  for (int q = 0; q < NRHS; ++q) part[(wave * NRHS + q) * kWave + lane] = V(0);
   __syncthreads();
   if (wave < T) {
-    const float* xb = xw - cmin * NRHS;
-    float inner[NRHS], outer[NRHS];
+    const V* xb = reinterpret_cast<const V*>(xw) - cmin * NRHS;
+    const V* xg = static_cast<const V*>(a.x);
+    V inner[NRHS], outer[NRHS];
 #pragma unroll
-    for (int q = 0; q < NRHS; ++q) inner[q] = 0.0f, outer[q] = 0.0f;
+    for (int q = 0; q < NRHS; ++q) inner[q] = V(0), outer[q] = V(0);
     int cnt = 0;
     // run cursor: run ri (of the lane's [rb, re)) ends at cur_end and its
     // entries have column = position + cur_delta; the next run (nx_end,
@@ -365,7 +364,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
     auto step = [&](Lane8<VF, IX>& buf) {
       const bool live = t < T;
       const int P = t * kSellLaneEntries;
-      float pr[kSellLaneEntries][NRHS];
+      V pr[kSellLaneEntries][NRHS];
       if (live) {
         int cols[kSellLaneEntries];
         if constexpr (IX == 0) {
@@ -389,7 +388,7 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
         } else {
           lane_cols(buf, cols);
         }
-        slice_products<VF, IX, WIN, NRHS>(buf, cols, xb, a.x, pr);
+        slice_products<V, VF, IX, WIN, NRHS>(buf, cols, xb, xg, pr);
       }
       __builtin_amdgcn_sched_barrier(0);
       load_slice<VF, IX>(val, col, slice_of(t + NB * kGroupWaves), lane, buf);
@@ -401,15 +400,15 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
 #pragma unroll
           for (int e = 0; e < kSellLaneEntries; ++e)
 #pragma unroll
-            for (int q = 0; q < NRHS; ++q) pr[e][q] = e < lim ? pr[e][q] : 0.0f;
+            for (int q = 0; q < NRHS; ++q) pr[e][q] = e < lim ? pr[e][q] : V(0);
         }
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) inner[q] += slice_sum<NRHS>(pr, q);
+        for (int q = 0; q < NRHS; ++q) inner[q] += slice_sum<V, NRHS>(pr, q);
         if (++cnt == 8) {
 #pragma unroll
           for (int q = 0; q < NRHS; ++q) {
             outer[q] += inner[q];
-            inner[q] = 0.0f;
+            inner[q] = V(0);
           }
           cnt = 0;
         }
@@ -427,35 +426,35 @@ __device__ __forceinline__ void sell_chunk(const SellArgs& a, int64_t c, float* 
   }
   __syncthreads();
   if (wave == 0 && my_row != 0xFFFFFFFFu) {
-    float v[NRHS];
+    V v[NRHS];
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) {
-      const float* pq = part + q * kWave + lane;
+      const V* pq = part + q * kWave + lane;
       v[q] = (pq[0 * NRHS * kWave] + pq[1 * NRHS * kWave]) + (pq[2 * NRHS * kWave] + pq[3 * NRHS * kWave]);
-      if constexpr (SM == kScaleRow) v[q] = v[q] * a.scale[my_row];
+      if constexpr (SM == kScaleRow) v[q] = v[q] * static_cast<V>(a.scale[my_row]);
     }
-    store_rhs<NRHS>(a.y + static_cast<int64_t>(my_row) * NRHS, v);
+    store_rhs<V, NRHS>(static_cast<V*>(a.y) + static_cast<int64_t>(my_row) * NRHS, v);
   }
 }
 
 // Chunk c of a's matrix on one workgroup: through the LDS window when the
-// chunk's window, for NRHS vectors, fits a's.
-template <int VF, int SM, int IX, int NRHS>
-__device__ __forceinline__ void sell_run_chunk(const SellArgs& a, int64_t c, float* xw, float* part) {
+// chunk's window, for NRHS vectors of V, fits a's.
+template <class V, int VF, int SM, int IX, int NRHS>
+__device__ __forceinline__ void sell_run_chunk(const SellArgs& a, int64_t c, float* xw, V* part) {
   const uint32_t clen = a.win[2 * c + 1];
-  if (clen > 0 && static_cast<int64_t>(clen) * NRHS <= a.win_floats)
-    sell_chunk<VF, SM, IX, true, NRHS>(a, c, xw, part);
+  if (clen > 0 && static_cast<int64_t>(clen) * NRHS * static_cast<int64_t>(sizeof(V) / 4) <= a.win_floats)
+    sell_chunk<V, VF, SM, IX, true, NRHS>(a, c, xw, part);
   else
-    sell_chunk<VF, SM, IX, false, NRHS>(a, c, xw, part);
+    sell_chunk<V, VF, SM, IX, false, NRHS>(a, c, xw, part);
 }
 
 // +0 to the rows of chunk c of a's matrix (one wave).
-template <int NRHS>
+template <class V, int NRHS>
 __device__ __forceinline__ void sell_zero_rows(const SellArgs& a, int64_t c) {
   const uint32_t row = a.perm[c * kSellC + (threadIdx.x & (kWave - 1))];
   if (row != 0xFFFFFFFFu) {
-    const float z[NRHS] = {};
-    store_rhs<NRHS>(a.y + static_cast<int64_t>(row) * NRHS, z);
+    const V z[NRHS] = {};
+    store_rhs<V, NRHS>(static_cast<V*>(a.y) + static_cast<int64_t>(row) * NRHS, z);
   }
 }
 
@@ -468,10 +467,26 @@ __global__ __launch_bounds__(kGroupThreads) void k_sell(SellArgs a) {
   __shared__ float part[kGroupWaves * NRHS * kWave];
   if (blockIdx.x >= a.n_groups) {
     const int64_t z = (static_cast<int64_t>(blockIdx.x) - a.n_groups) * kGroupWaves + threadIdx.x / kWave;
-    if (z < a.n_zero) sell_zero_rows<NRHS>(a, a.zero[z]);
+    if (z < a.n_zero) sell_zero_rows<float, NRHS>(a, a.zero[z]);
     return;
   }
-  sell_run_chunk<VF, SM, IX, NRHS>(a, a.work[sell_group_of_block(a.xcd_blocks, a.n_groups, blockIdx.x)], xw, part);
+  sell_run_chunk<float, VF, SM, IX, NRHS>(a, a.work[sell_group_of_block(a.xcd_blocks, a.n_groups, blockIdx.x)], xw,
+                                         part);
+}
+
+// One FP64 vector: FP64 x and y, products and sums (the paper's half/double
+// arithmetic, Sec. II-D) in the same order.
+template <int VF, int SM, int IX>
+__global__ __launch_bounds__(kGroupThreads) void k_sell_f64(SellArgs a) {
+  extern __shared__ __align__(16) float xw[];
+  __shared__ double part[kGroupWaves * kWave];
+  if (blockIdx.x >= a.n_groups) {
+    const int64_t z = (static_cast<int64_t>(blockIdx.x) - a.n_groups) * kGroupWaves + threadIdx.x / kWave;
+    if (z < a.n_zero) sell_zero_rows<double, 1>(a, a.zero[z]);
+    return;
+  }
+  sell_run_chunk<double, VF, SM, IX, 1>(a, a.work[sell_group_of_block(a.xcd_blocks, a.n_groups, blockIdx.x)], xw,
+                                        part);
 }
 
 // Batched form: the same over the work lists of many matrices, each entry
@@ -484,12 +499,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_sell_batched(SellBatchTable t
     const int64_t z = (static_cast<int64_t>(blockIdx.x) - t.n_work) * kGroupWaves + threadIdx.x / kWave;
     if (z < t.n_zero) {
       const uint2 w = t.zero[z];
-      sell_zero_rows<NRHS>(t.args[w.x], w.y);
+      sell_zero_rows<float, NRHS>(t.args[w.x], w.y);
     }
     return;
   }
   const uint2 w = t.work[sell_group_of_block(t.xcd_blocks, t.n_work, blockIdx.x)];
-  sell_run_chunk<VF, SM, IX, NRHS>(t.args[w.x], w.y, xw, part);
+  sell_run_chunk<float, VF, SM, IX, NRHS>(t.args[w.x], w.y, xw, part);
 }
 
 // LDS of a launch: the window, then (run-length indices) one lane's entries
@@ -526,6 +541,20 @@ void launch_ix_batched(int idx_bytes, const SellBatchTable& t, size_t lds, hipSt
 }
 
 template <int VF, int SM>
+hipError_t launch_vf_f64(const SellArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(a.n_groups + (a.n_zero + kGroupWaves - 1) / kGroupWaves)),
+      block(kGroupThreads);
+  const size_t lds = sell_lds_bytes(a);
+  if (a.idx_bytes == 0)
+    hipLaunchKernelGGL((k_sell_f64<VF, SM, 0>), grid, block, lds, s, a);
+  else if (a.idx_bytes == 2)
+    hipLaunchKernelGGL((k_sell_f64<VF, SM, 2>), grid, block, lds, s, a);
+  else
+    hipLaunchKernelGGL((k_sell_f64<VF, SM, 4>), grid, block, lds, s, a);
+  return hipGetLastError();
+}
+
+template <int VF, int SM>
 hipError_t launch_vf(int n_rhs, const SellArgs& a, hipStream_t s) {
   switch (n_rhs) {
     case 1: launch_ix<VF, SM, 1>(a, s); break;
@@ -557,6 +586,15 @@ hipError_t launch_sell_spmv(int vf, int scale_mode, int n_rhs, const SellArgs& a
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_vf<kBf16, kScaleNone>(n_rhs, a, s);
   if (vf == kFp32 && scale_mode == kScaleNone) return launch_vf<kFp32, kScaleNone>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleRow) return launch_vf<kFp8, kScaleRow>(n_rhs, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sell_spmv_f64(int vf, int scale_mode, const SellArgs& a, hipStream_t s) {
+  if (a.n_groups <= 0 && a.n_zero <= 0) return hipSuccess;
+  if (vf == kFp16 && scale_mode == kScaleNone) return launch_vf_f64<kFp16, kScaleNone>(a, s);
+  if (vf == kBf16 && scale_mode == kScaleNone) return launch_vf_f64<kBf16, kScaleNone>(a, s);
+  if (vf == kFp32 && scale_mode == kScaleNone) return launch_vf_f64<kFp32, kScaleNone>(a, s);
+  if (vf == kFp8 && scale_mode == kScaleRow) return launch_vf_f64<kFp8, kScaleRow>(a, s);
   return hipErrorInvalidValue;
 }
 

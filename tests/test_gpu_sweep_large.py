@@ -109,8 +109,9 @@ def test_sweep_large_forward_and_adjoint(sweep, fmt, dev):
 @pytest.mark.parametrize("idx", ["runs", "u16"])
 def test_sweep_large_sell(sweep, idx, dev):
     """SELL-C-sigma form (sigma 65,536) of the largest workload: one vector on
-    the sampled rows against the oracle, +0 on every empty row; four vectors
-    bitwise equal to the single-vector products of their columns."""
+    the sampled rows against the oracle, +0 on every empty row; FP64 vectors
+    on the sampled rows; four vectors bitwise equal to the single-vector
+    products of their columns."""
     spec, rp, cols, vals, rows, (srp, scols, svals) = sweep
     t0 = time.time()
     S = dm.SellMatrix(rp, cols, vals, spec.n_cols, "fp16", sigma=65536, index_format=idx)
@@ -123,6 +124,11 @@ def test_sweep_large_sell(sweep, idx, dev):
     assert err <= TOL
     lens = np.diff(rp)
     assert np.all(_bits(y[lens == 0]) == 0) and np.all(y[lens > 0] > 0)
+    # FP64 weights and dose (half/double): the sampled rows within 1e-12
+    y64 = S.spmv(torch.from_numpy(x_h.astype(np.float64)).cuda()).cpu().numpy()
+    err64 = oracle.max_rel_err(y64[rows], oracle.spmv(srp, scols, dec, x_h.astype(np.float64)))
+    _say(f"sell {idx}: FP64 max rel err {err64:.3e}")
+    assert err64 <= 1e-12
     X = torch.from_numpy(np.stack([dosegen.spot_weights(spec.seed, r, spec.n_cols) for r in range(4)], 1)).cuda()
     Y = S.spmv(X.contiguous()).cpu().numpy()
     assert np.array_equal(_bits(Y[:, 0]), _bits(y))
