@@ -316,12 +316,15 @@ __device__ __forceinline__ void settle_rows(const SpmvArgs& a, RowCursor& rc, ui
 }
 
 // The row being summed (wave-uniform): its positions [ks, ke), its steps
-// kfirst .. klast, and whether it is long (more than kRowSlots steps).
+// kfirst .. klast, and whether it is long (more than kRowSlots steps).  A
+// row that is not valid has ks = kNoRow, so that no step takes it.
+constexpr int kNoRow = 0x7fffffff;
 struct Row {
   uint32_t row;
   int ks, ke;
   int kfirst, klast;
-  bool valid, lng;
+  int lng;  // 0 or 1 (an int, so that testing it is one scalar compare)
+  bool valid;
 };
 
 // The wave's next non-empty row, moving on to later 64-row windows (and
@@ -333,6 +336,7 @@ __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32
     const uint32_t wb = rc.wb + kWave;
     if (wb >= r_end) {
       n.valid = false;
+      n.ks = kNoRow;
       return n;
     }
     fetch_rows(a, rc, wb, r_end, origin32);
@@ -345,7 +349,7 @@ __device__ __forceinline__ Row next_row(const SpmvArgs& a, RowCursor& rc, uint32
   n.ke = __builtin_amdgcn_readlane(rc.hi, i);
   n.kfirst = n.ks >> 9;
   n.klast = (n.ke - 1) >> 9;
-  n.lng = n.klast - n.kfirst >= kRowSlots;
+  n.lng = n.klast - n.kfirst >= kRowSlots ? 1 : 0;
   n.valid = true;
   return n;
 }
@@ -471,19 +475,20 @@ __device__ __forceinline__ void quarter_full(const T (&p)[kChunk][NRHS], T (&s)[
   for (int q = 0; q < NRHS; ++q) s[q] = (p[b][q] + p[b + 1][q]) + (p[b + 2][q] + p[b + 3][q]);
 }
 
-// A short row's entries in half H of step k (positions [s0 + 256 H, s0 + 256 H
-// + 256)), added to the lane accumulator L; pq = the lane's first quarter
-// position in the step.
+// A short row's entries in half H of a step it meets (positions [256 H,
+// 256 H + 256) of the step), added to the lane accumulator L.  a, b: the
+// row's positions [ks, ke) relative to the step's start (a < 512, b > 0);
+// lane4: the lane's first quarter position in the step.  Each test is one
+// scalar compare (two-sided ones folded with max), not a pair of compares
+// joined into a lane mask.
 template <class T, int H, int NRHS>
-__device__ __forceinline__ void add_half(const T (&p)[kChunk][NRHS], int s0, int pq, const Row& r,
-                                         T (&L)[NRHS]) {
-  const int hs = s0 + H * kHalf;
-  if (r.ks >= hs + kHalf || r.ke <= hs) return;  // the row misses this half
+__device__ __forceinline__ void add_half(const T (&p)[kChunk][NRHS], int lane4, int a, int b, T (&L)[NRHS]) {
+  if (H == 0 ? a >= kHalf : b <= kHalf) return;  // the row misses this half
   T s[NRHS];
-  if (r.ks <= hs && r.ke >= hs + kHalf)
+  if (max(a - H * kHalf, (H + 1) * kHalf - b) <= 0)  // the half lies inside the row
     quarter_full<T, H, NRHS>(p, s);
   else
-    quarter_sum<T, H, NRHS>(p, pq + H * kHalf - r.ks, static_cast<uint32_t>(r.ke - r.ks), s);
+    quarter_sum<T, H, NRHS>(p, lane4 + H * kHalf - a, static_cast<uint32_t>(b - a), s);
 #pragma unroll
   for (int q = 0; q < NRHS; ++q) L[q] += s[q];
 }
@@ -572,6 +577,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   rc.mask = 0;
   Row cr;
   cr.valid = false;
+  cr.ks = kNoRow;
   const bool has_rows = r_begin < r_end;
   // issued by every wave (one without rows re-reads a row before r_begin, or
   // row 0), so that no branch hides it from the compiler's load count
@@ -620,18 +626,22 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   // (none once the wave is past its last step)
   auto rows_of_step = [&](const T (&p)[kChunk][NRHS]) {
     const int s0 = k * kStepEntries;
-    const int pq = s0 + lane * kQuarter;
-    while (k <= kend && cr.valid && cr.ks < s0 + kStepEntries) {
-      const bool lng = SPLIT || cr.lng;
+    const int lane4 = lane * kQuarter;
+    // rows starting below lim meet the step (no row once the wave is past
+    // its last step; an invalid row starts at kNoRow)
+    const int lim = k <= kend ? s0 + kStepEntries : -kNoRow;
+    while (cr.ks < lim) {
+      const bool lng = SPLIT || cr.lng != 0;
+      const int ra = cr.ks - s0, rb = cr.ke - s0;  // the row relative to the step
       if (lng) {
         T h0[NRHS], h1[NRHS];
-        if (cr.ks <= s0 && cr.ke >= s0 + kStepEntries) {
+        if (max(ra, kStepEntries - rb) <= 0) {
           quarter_full<T, 0, NRHS>(p, h0);
           quarter_full<T, 1, NRHS>(p, h1);
         } else {
-          const uint32_t len = static_cast<uint32_t>(cr.ke - cr.ks);
-          quarter_sum<T, 0, NRHS>(p, pq - cr.ks, len, h0);
-          quarter_sum<T, 1, NRHS>(p, pq + kHalf - cr.ks, len, h1);
+          const uint32_t len = static_cast<uint32_t>(rb - ra);
+          quarter_sum<T, 0, NRHS>(p, lane4 - ra, len, h0);
+          quarter_sum<T, 1, NRHS>(p, lane4 + kHalf - ra, len, h1);
         }
         const int slot = (k - cr.kfirst) & (kRowSlots - 1);
 #pragma unroll
@@ -641,8 +651,8 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
           for (int s = 0; s < kRowSlots; ++s) W[s][q] += s == slot ? t : T(0);
         }
       } else {
-        add_half<T, 0, NRHS>(p, s0, pq, cr, L);
-        add_half<T, 1, NRHS>(p, s0, pq, cr, L);
+        add_half<T, 0, NRHS>(p, lane4, ra, rb, L);
+        add_half<T, 1, NRHS>(p, lane4, ra, rb, L);
       }
       if (k + stride <= cr.klast) break;  // the row goes on in a later step of this wave
       // the wave's last step of the row; slots that received nothing hold
@@ -657,6 +667,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
       if constexpr (SM == kScaleRow) sc = a.scale[cr.row];
       if constexpr (SPLIT) {
         cr.valid = false;
+        cr.ks = kNoRow;
       } else {
         if (lane == kWave - 1) store_row<T, SM, NRHS, ACC>(a, cr.row, sc, tot);
 #pragma unroll
