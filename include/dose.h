@@ -190,7 +190,11 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
  * kernels on the stored transpose: deterministic, no atomics.
  * v: device, n_rows FP32.  g: device, n_cols FP32, every entry written.
  * Both 4-byte aligned (else DOSE_ERR_INVALID_ARGUMENT, as for x and y).
- * DOSE_ERR_NO_TRANSPOSE without DOSE_CREATE_TRANSPOSE. */
+ * DOSE_ERR_NO_TRANSPOSE without DOSE_CREATE_TRANSPOSE.  E4M3 with row
+ * scales: the row scales are applied to v first, u_i = fl32(s_i v_i), and
+ * entry (i, j) adds fl32(q_ij u_i) (two roundings per term, as fl32(fl32(q_ij
+ * s_i) v_i) would have; one gathered value per entry instead of two); the
+ * call takes n_rows * 4 bytes of stream-ordered device memory for u. */
 dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* g, void* hip_stream);
 
 /* The same products with FP64 vectors and FP64 products and sums: the

@@ -1234,7 +1234,9 @@ dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf, int32_t xf,
         auto P = autotune_operand(m.get(), A, scale_mode_A(m.get()), 1, xa.get<float>(), ya.get<float>(), s);
         if (P) A.part = std::move(*P);
         if (m->has_t) {
-          auto PT = autotune_operand(m.get(), m->AT, scale_mode_AT(m.get()), 1, ya.get<float>(), xa.get<float>(), s);
+          // the mode dose_spmv_adjoint runs (E4M3: its seed carries the row scales)
+          const int smt = m->vf == kFp8 ? kScaleNone : scale_mode_AT(m.get());
+          auto PT = autotune_operand(m.get(), m->AT, smt, 1, ya.get<float>(), xa.get<float>(), s);
           if (PT) m->AT.part = std::move(*PT);
         }
       }
@@ -1375,7 +1377,20 @@ dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* gout, void* 
     if ((reinterpret_cast<uintptr_t>(v) | reinterpret_cast<uintptr_t>(gout)) % 4 != 0)
       fail(DOSE_ERR_INVALID_ARGUMENT, "v and g must be 4-byte aligned");
     DeviceGuard g(m->device);
-    run_product(m, m->AT, scale_mode_AT(m), 1, v, gout, as_stream(hip_stream));
+    hipStream_t s = as_stream(hip_stream);
+    if (m->vf != kFp8) {
+      run_product(m, m->AT, scale_mode_AT(m), 1, v, gout, s);
+      return;
+    }
+    // E4M3: the row scales go into the seed first (u_i = fl32(s_i v_i)), so
+    // that each entry of A^T gathers one value; its term is fl32(q u_i)
+    const int64_t n = m->A.n_rows;
+    float* u = nullptr;
+    if (n > 0) HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&u), static_cast<size_t>(n) * 4, s));
+    hipError_t e = launch_scale_vec(n, m->row_scale.get<float>(), v, u, s);
+    if (e == hipSuccess) e = launch_spmv(m->vf, kScaleNone, 1, make_args(m, m->AT, kScaleNone, 1, u, gout), s);
+    if (u) (void)hipFreeAsync(u, s);
+    HIP_CHECK(e);
   });
 }
 

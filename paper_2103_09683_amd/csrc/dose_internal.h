@@ -164,6 +164,8 @@ hipError_t launch_norm2(int64_t n, const float* g, double* partial, int n_partia
 // or the worst case (worst = 1) of n_scen scenarios of n voxels.
 hipError_t launch_robust_seed(int n_scen, int64_t n, int worst, const double* out, const double* prob,
                               const double* gscale, const float* seed, float* wseed, hipStream_t s);
+// u_i = fl32(sc_i * v_i), i < n.
+hipError_t launch_scale_vec(int64_t n, const float* sc, const float* v, float* u, hipStream_t s);
 hipError_t launch_probe_read(const void* buf, uint64_t bytes, float* sink, hipStream_t s);
 hipError_t launch_probe_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 

@@ -274,6 +274,15 @@ __global__ __launch_bounds__(kRedThreads) void k_robust_seed(int n_scen, int64_t
   }
 }
 
+// u_i = fl32(s_i * v_i): an E4M3 matrix's row scales applied to the adjoint's
+// seed, so that the product over A^T gathers one value per entry.
+__global__ __launch_bounds__(256) void k_scale_vec(int64_t n, const float* __restrict__ sc,
+                                                   const float* __restrict__ v, float* __restrict__ u) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    u[i] = sc[i] * v[i];
+}
+
 // Read-only stream with 16-byte non-temporal loads (as the SpMV streams its
 // matrix); the store happens only if the data XORs to a fixed improbable
 // pattern, which keeps the loads alive.
@@ -369,6 +378,14 @@ hipError_t launch_norm2(int64_t n, const float* g, double* partial, int n_partia
   if (n > 0)
     hipLaunchKernelGGL(k_sumsq_pass1, dim3(n_partial), dim3(kRedThreads), 0, s, n, chunk, g, partial);
   hipLaunchKernelGGL(k_pass2, dim3(1), dim3(kRedThreads), 0, s, partial, n > 0 ? n_partial : 0, 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_vec(int64_t n, const float* sc, const float* v, float* u, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t grid = (n + 256 * 4 - 1) / (256 * 4);
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(k_scale_vec, dim3(static_cast<unsigned>(grid)), dim3(256), 0, s, n, sc, v, u);
   return hipGetLastError();
 }
 

@@ -921,6 +921,11 @@ hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hip
   if (vf == kFp32 && scale_mode == kScaleNone) return launch_rhs<kFp32, kScaleNone>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleRow) return launch_rhs<kFp8, kScaleRow>(n_rhs, a, s);
   if (vf == kFp8 && scale_mode == kScaleCol) return launch_rhs<kFp8, kScaleCol>(n_rhs, a, s);
+  if (vf == kFp8 && scale_mode == kScaleNone && n_rhs == 1) {
+    // E4M3 codes without their scale (the FP32 adjoint, whose seed carries the row scales)
+    launch_ix<kFp8, kScaleNone, 1>(a, static_cast<size_t>(a.win_floats) * sizeof(float), s);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 
