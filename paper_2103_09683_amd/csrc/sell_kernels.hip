@@ -6,7 +6,7 @@
 // inside windows of sigma rows and cut into chunks of C = 64 rows, one row per
 // lane of a wave64, so no row needs a cross-lane reduction and the lanes of a
 // wave stream their rows side by side.  Here a chunk stores its entries in
-// slices of 8 per lane (dose_internal.h): a lane reads its row's next 8 codes
+// slices of 8 per lane (sell_internal.h): a lane reads its row's next 8 codes
 // with one 16-byte load (FP16), and a wave's load instruction covers 1 KB of
 // consecutive codes (or indices).
 //
@@ -25,6 +25,8 @@
 //     (one LDS read); each vector's sums follow the order below, so the
 //     product equals n_rhs single-vector products bit for bit.  A batched
 //     launch takes the chunks of many matrices from one work list.
+//   * One FP64 vector (the paper's half/double arithmetic, Sec. II-D): the
+//     same kernel with FP64 x, products, sums and y, in the same order.
 //   * Summation order, fixed by the stored layout (so equal inputs give equal
 //     bits): a lane's 8 products of a slice add pairwise, ((p0 + p1) +
 //     (p2 + p3)) + ((p4 + p5) + (p6 + p7)), slots past the row's end counting
