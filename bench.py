@@ -224,6 +224,7 @@ def bench_headline(torch, dm, dosegen, args):
 def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
     """On the headline matrix: FP32 vectors in FP16 (the stored A), the
     adjoint in FP32 and FP64; then BF16 and E4M3 values (forward and adjoint),
+    the adjoint over A^T in voxel slabs (FP16 and E4M3, FP32 and FP64),
     16-bit indices in the three formats (forward), and the FP16 matrix in
     SELL-C-sigma form (sigma 65,536) with run-length and 16-bit indices, one
     and four FP32 vectors and one FP64 vector (half/double)."""
@@ -246,9 +247,29 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
         if info["has_transpose"]:
             ms_a = time_launches(lambda: M.adjoint(v, g), reps, 3)
             e.update({"adjoint_ms": round(ms_a, 4),
+                      "adjoint_GNNZ_per_s": round(info["nnz"] / (ms_a * 1e-3) / 1e9, 1),
                       "adjoint_GBps": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9, 1),
                       "adjoint_frac": round(info["adjoint_bytes"] / (ms_a * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                      "adjoint_bytes": info["adjoint_bytes"],
                       "n_groups_t_x_in_lds": info["n_groups_windowed_t"], "n_groups_t": info["n_groups_t"]})
+            if info["slab_voxels"]:
+                e["slab_voxels"] = info["slab_voxels"]
+        return e
+
+    def slab_entry(fmt, rows_model_bytes):
+        # the adjoint over A^T in voxel slabs; frac on its own byte model and
+        # on the spot-row model (the paper format's minimum)
+        t0 = time.time()
+        M = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose="slabs")
+        log(f"{spec.name} {fmt} slabs: created in {time.time() - t0:.1f}s")
+        e = entry(M)
+        e["adjoint_frac_spot_row_model"] = round(rows_model_bytes / (e["adjoint_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)
+        ms64 = time_launches(lambda: M.adjoint(v64, g64), reps, 3)
+        e["adjoint_f64_ms"] = round(ms64, 4)
+        e["adjoint_f64_frac"] = round((M.info()["adjoint_bytes"] + 4 * (spec.n_rows + spec.n_cols)) / (ms64 * 1e-3)
+                                      / 1e9 / HBM_PEAK_GBPS, 4)
+        M.close()
+        torch.cuda.empty_cache()
         return e
 
     res["fp16"] = entry(A)
@@ -267,6 +288,8 @@ def bench_same_matrix(torch, dm, spec, A, rp, cols, vals, x_h, args):
         res[fmt] = entry(M)
         M.close()
         torch.cuda.empty_cache()
+    for fmt in ("fp16", "fp8e4m3_rowscale"):
+        res[fmt + "_slabs"] = slab_entry(fmt, res[fmt]["adjoint_bytes"])
     for fmt in ("fp16", "bf16", "fp8e4m3_rowscale"):
         M = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, index_format="u16")
         res[fmt + "_u16"] = entry(M)
@@ -358,7 +381,27 @@ def bench_clinical(torch, dm, dosegen, args):
         "ms": round(ms_i, 5), "what": "dose A x, FP64 objective + FP32 seed, adjoint A^T seed, FP64 norm",
         "GNNZ_per_s_two_products": round(2 * nnz / (ms_i * 1e-3) / 1e9, 3)}
     A.spmv(x, y)
-    del v, g, seed
+    rows_model = info["adjoint_bytes"]
+    A.close()
+    torch.cuda.empty_cache()
+    # the same with A^T in voxel slabs
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", transpose="slabs")
+    info_s = A.info()
+    ms_s = time_launches(lambda: A.adjoint(v, g), args.steps, args.warmup)
+    v64, g64 = v.double(), torch.empty(spec.n_cols, dtype=torch.float64, device="cuda")
+    ms_s64 = time_launches(lambda: A.adjoint(v64, g64), max(20, args.steps // 4), args.warmup)
+    ms_si = time_launches(iteration, max(20, args.steps // 4), args.warmup)
+    res["adjoint_slabs"] = {
+        "ms": round(ms_s, 5), "GNNZ_per_s": round(nnz / (ms_s * 1e-3) / 1e9, 3),
+        "GBps_algorithmic": round(info_s["adjoint_bytes"] / (ms_s * 1e-3) / 1e9, 1),
+        "frac": round(info_s["adjoint_bytes"] / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "frac_spot_row_model": round(rows_model / (ms_s * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "adjoint_bytes": info_s["adjoint_bytes"], "slab_voxels": info_s["slab_voxels"],
+        "group_nnz_t": info_s["group_nnz_t"], "n_groups_t": info_s["n_groups_t"],
+        "n_groups_t_x_in_lds": info_s["n_groups_windowed_t"], "f64_ms": round(ms_s64, 5),
+        "optimisation_iteration_ms": round(ms_si, 5)}
+    log(f"clinical beam adjoint over voxel slabs: {ms_s:.4f} ms, iteration {ms_si:.4f} ms")
+    del v, g, seed, v64, g64
     A.close()
     res["u16_indices"] = bench_u16(torch, dm, spec, rp, cols, vals, x, y, args)
     res["half_double"] = bench_f64(torch, dm, spec, rp, cols, vals, x_h, args)
@@ -388,6 +431,8 @@ def main(argv=None):
                     help="only time the robust-plan step (9 scenarios x 4 beams, then the epilogue)")
     ap.add_argument("--sell-sigmas", default="16384,65536", help="sigmas of the SELL-C-sigma variants")
     ap.add_argument("--sell-index", default="i32,u16,runs", help="index formats of the SELL-C-sigma variants")
+    ap.add_argument("--adjoint-layout", choices=["rows", "slabs"], default="rows",
+                    help="A^T of --part adjoint: one row per spot, or voxel slabs")
     ap.add_argument("--part", choices=["clinical", "adjoint", "batched", "sell"],
                     help="only one part: the clinical-beam variants, the clinical-beam adjoint, the full-size "
                          "batched robust scenarios, or the SELL-C-sigma variants on the clinical beam")
@@ -458,8 +503,10 @@ def bench_part(torch, dm, dosegen, args):
         y = A.spmv(x)
         A.close()
         return bench_sell(torch, dm, spec, rp, cols, vals, x, y, args)
-    # the adjoint of the clinical beam (FP16, FP32 vectors)
-    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16", transpose=True)
+    # the adjoint of the clinical beam (FP16, FP32 vectors), over spot rows
+    # or (--adjoint-layout slabs) voxel slabs
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16",
+                      transpose="slabs" if args.adjoint_layout == "slabs" else True)
     info = A.info()
     v = torch.from_numpy(dosegen.signed_values(spec.seed, 1, spec.n_rows)).cuda()
     g = torch.empty(spec.n_cols, dtype=torch.float32, device="cuda")
@@ -469,7 +516,8 @@ def bench_part(torch, dm, dosegen, args):
     return {"workload": spec.name, "ms": round(ms, 5), "GNNZ_per_s": round(info["nnz"] / (ms * 1e-3) / 1e9, 3),
             "GBps_algorithmic": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBPS, 4),
             "algorithmic_bytes_per_launch": info["adjoint_bytes"], "n_groups_t": info["n_groups_t"],
-            "n_groups_t_split": info["n_groups_split_t"]}
+            "n_groups_t_split": info["n_groups_split_t"], "layout": args.adjoint_layout,
+            "slab_voxels": info["slab_voxels"]}
 
 
 def bench_u16(torch, dm, spec, rp, cols, vals, x, y, args):

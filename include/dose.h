@@ -83,13 +83,29 @@ typedef enum {
 /* dose_matrix_create flags */
 enum {
   DOSE_CREATE_TRANSPOSE = 1u, /* also store A^T for dose_spmv_adjoint */
-  DOSE_CREATE_AUTOTUNE = 2u   /* time the plain one-vector product (and the adjoint
+  DOSE_CREATE_AUTOTUNE = 2u,  /* time the plain one-vector product (and the adjoint
                                  with DOSE_CREATE_TRANSPOSE) under row groups of 8K,
                                  16K, 32K and 64K entries on hip_stream and keep the
                                  fastest, as the paper sweeps its thread-block size
                                  (Sec. V-A); a choice stored in the DOSE_TUNE_CACHE
                                  file is reused.  Speed only: products are bitwise
                                  the same under any partition. */
+  DOSE_CREATE_TRANSPOSE_SLABS = 4u /* store A^T in voxel slabs instead (implies
+                                 DOSE_CREATE_TRANSPOSE): the voxels are cut into
+                                 slabs of W consecutive rows of A (W = the LDS window
+                                 cap, 4096 by default, reported as slab_voxels), and
+                                 A^T gets one row per (slab, spot) pair holding
+                                 entries, slab by slab, so that each row group of the
+                                 adjoint reads v from one slab held in LDS instead
+                                 of gathering it from global memory.  The adjoint
+                                 sums each such row (a partial), then adds spot j's
+                                 partials in ascending slab: deterministic and
+                                 bitwise the same under any partition, but in a
+                                 different order from the spot-row transpose (so
+                                 not bitwise equal to it).  Needs
+                                 ceil(n_rows / W) * n_cols < 2^32 (else
+                                 DOSE_ERR_UNSUPPORTED); dose_matrix_decode of
+                                 DOSE_PART_AT returns DOSE_ERR_UNSUPPORTED. */
 };
 
 /* Which stored operand dose_matrix_decode reads. */
@@ -117,14 +133,17 @@ typedef struct {
   int64_t n_groups_windowed;    /* groups of A whose x window fits in LDS
                                    (single-vector products)                 */
   int32_t group_nnz_t;          /* the same for A^T (0 without transpose)    */
-  int32_t reserved0;
+  int32_t slab_voxels;          /* W of DOSE_CREATE_TRANSPOSE_SLABS, else 0   */
   int64_t n_groups_t, n_groups_windowed_t;
   uint64_t device_bytes;        /* device memory held by the matrix          */
   uint64_t spmv_bytes;          /* algorithmic HBM bytes of one dose_spmv:
                                    nnz*(value+index) + (n_rows+1)*4 row
                                    offsets + n_rows*scale + 4*n_cols (x) +
                                    4*n_rows (y)                             */
-  uint64_t adjoint_bytes;       /* the same for dose_spmv_adjoint on A^T     */
+  uint64_t adjoint_bytes;       /* the same for dose_spmv_adjoint on A^T
+                                   (voxel slabs: plus the padding entries,
+                                   8 B per slab row for its partial and 4 B
+                                   per row and spot for the combine map)    */
   int64_t n_groups_split;       /* split groups of A: one long row whose
                                    steps the four waves share               */
   int64_t n_groups_split_t;     /* the same for A^T                          */
@@ -194,7 +213,9 @@ dose_status dose_spmv(dose_matrix m, const float* x, float* y, void* hip_stream)
  * scales: the row scales are applied to v first, u_i = fl32(s_i v_i), and
  * entry (i, j) adds fl32(q_ij u_i) (two roundings per term, as fl32(fl32(q_ij
  * s_i) v_i) would have; one gathered value per entry instead of two); the
- * call takes n_rows * 4 bytes of stream-ordered device memory for u. */
+ * call takes n_rows * 4 bytes of stream-ordered device memory for u.  With
+ * DOSE_CREATE_TRANSPOSE_SLABS it also takes 4 bytes (FP64: 8) per slab row
+ * for the partials. */
 dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* g, void* hip_stream);
 
 /* The same products with FP64 vectors and FP64 products and sums: the

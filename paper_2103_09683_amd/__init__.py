@@ -100,13 +100,18 @@ class DoseMatrix:
 
     row_ptr (int64, n_rows+1), cols (int32) and vals (float32) are host CSR
     arrays; they are validated, uploaded and encoded once.  With
-    ``transpose=True`` A^T is stored as well for :meth:`adjoint`; with
+    ``transpose=True`` A^T is stored as well for :meth:`adjoint`
+    (``transpose="slabs"``: in voxel slabs, whose adjoint reads the seed from
+    LDS and adds each spot's slab partials in a fixed order); with
     ``autotune=True`` the row-group sizes of the plain products are chosen by
     timing them (speed only: results are bitwise the same).
     """
 
     def __init__(self, row_ptr, cols, vals, n_cols: int, value_format: str = "fp16",
-                 transpose: bool = False, stream=None, index_format: str = "i32", autotune: bool = False):
+                 transpose: bool | str = False, stream=None, index_format: str = "i32", autotune: bool = False):
+        slabs = isinstance(transpose, str)
+        if slabs and transpose != "slabs":
+            raise ValueError(f"transpose must be a bool or 'slabs', not {transpose!r}")
         if value_format not in VALUE_FORMATS:
             raise ValueError(f"unknown value format {value_format!r}")
         if index_format not in INDEX_FORMATS:
@@ -117,7 +122,8 @@ class DoseMatrix:
         h = ctypes.c_void_p()
         _lib.check(lib.dose_matrix_create(ctypes.byref(c), VALUE_FORMATS[value_format],
                                           INDEX_FORMATS[index_format],
-                                          (_lib.CREATE_TRANSPOSE if transpose else 0) |
+                                          (_lib.CREATE_TRANSPOSE if transpose and not slabs else 0) |
+                                          (_lib.CREATE_TRANSPOSE_SLABS if slabs else 0) |
                                           (_lib.CREATE_AUTOTUNE if autotune else 0),
                                           _stream_handle(stream), ctypes.byref(h)))
         self._h = h

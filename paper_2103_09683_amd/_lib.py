@@ -27,6 +27,7 @@ IDX_U16 = 2
 IDX_RUNS = 3
 CREATE_TRANSPOSE = 1
 CREATE_AUTOTUNE = 2
+CREATE_TRANSPOSE_SLABS = 4
 PART_A, PART_AT = 0, 1
 PLAN_AUTOTUNE = 1
 ROBUST_EXPECTED, ROBUST_WORST = 0, 1
@@ -43,7 +44,7 @@ class MatrixInfo(ctypes.Structure):
                 ("value_format", ctypes.c_int32), ("index_format", ctypes.c_int32),
                 ("has_transpose", ctypes.c_int32), ("group_nnz", ctypes.c_int32),
                 ("n_groups", ctypes.c_int64), ("n_groups_windowed", ctypes.c_int64),
-                ("group_nnz_t", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("group_nnz_t", ctypes.c_int32), ("slab_voxels", ctypes.c_int32),
                 ("n_groups_t", ctypes.c_int64), ("n_groups_windowed_t", ctypes.c_int64),
                 ("device_bytes", ctypes.c_uint64), ("spmv_bytes", ctypes.c_uint64),
                 ("adjoint_bytes", ctypes.c_uint64), ("n_groups_split", ctypes.c_int64),

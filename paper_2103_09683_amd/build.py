@@ -16,7 +16,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdose.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["dose_api.cpp", "spmv_kernels.hip", "setup_kernels.hip", "reduce_kernels.hip", "sell_kernels.hip"]
+SOURCES = ["dose_api.cpp", "spmv_kernels.hip", "setup_kernels.hip", "reduce_kernels.hip", "sell_kernels.hip",
+           "slab_kernels.hip"]
 FLAGS = ["-O3", f"--offload-arch={ARCH}", "-fPIC", "-std=c++17", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

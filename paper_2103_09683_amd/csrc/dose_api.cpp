@@ -26,6 +26,7 @@
 #include "../../include/dose.h"
 #include "dose_internal.h"
 #include "sell_internal.h"
+#include "slab_internal.h"
 
 using namespace dose;
 
@@ -237,8 +238,10 @@ void validate_csr(const dose_csr_host* c, int vf, int xf) {
 // kGroupWaves contiguous shares of nearly equal cost (entries plus 16 per
 // row: an empty row still costs an offset load and a store).  The partition
 // only decides which wave computes which row; it never changes the order in
-// which a row is summed.
-std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int group_nnz) {
+// which a row is summed.  brk (optional, one flag per row): a group never
+// runs across a row whose flag is set (it starts a new group).
+std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int group_nnz,
+                                       const uint8_t* brk = nullptr) {
   std::vector<GroupDesc> G;
   G.reserve(static_cast<size_t>(rp[n_rows] / group_nnz + n_rows / kMaxGroupRows + 16));
   const int64_t kRowCost = 16;
@@ -262,7 +265,7 @@ std::vector<GroupDesc> build_partition(const int64_t* rp, int64_t n_rows, int gr
     int64_t nnz = 0;
     while (r < n_rows && r - start < kMaxGroupRows) {
       const int64_t l = rp[r + 1] - rp[r];
-      if (l > long_row || (r > start && nnz + l > group_nnz)) break;
+      if (l > long_row || (r > start && (nnz + l > group_nnz || (brk && brk[r])))) break;
       nnz += l;
       ++r;
     }
@@ -299,6 +302,7 @@ struct Operand {
   DevBuf val, col, row_ptr;  // codes, column indices, offsets mod 2^32
   int idx_bytes = 4;         // column index width: 4 (int32) or 2 (uint16)
   Partition part;            // the partition plain products use
+  std::vector<uint8_t> h_brk;  // rows that start a row group (A^T in slabs: each slab's first row), or empty
 
   uint64_t bytes() const { return val.bytes() + col.bytes() + row_ptr.bytes() + part.groups.bytes(); }
 };
@@ -324,7 +328,8 @@ int64_t window_cap_floats() {
 // The partition of an operand into groups of about group_nnz entries, with
 // every group's x window computed on the device.  Synchronous on s.
 Partition make_partition(const Operand& op, int group_nnz, hipStream_t s) {
-  std::vector<GroupDesc> G = build_partition(op.h_row_ptr.data(), op.n_rows, group_nnz);
+  std::vector<GroupDesc> G =
+      build_partition(op.h_row_ptr.data(), op.n_rows, group_nnz, op.h_brk.empty() ? nullptr : op.h_brk.data());
   Partition P;
   P.groups = DevBuf(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
   if (!G.empty()) {
@@ -381,6 +386,12 @@ struct dose_matrix_s {
   bool has_t = false;
   Operand A, AT;
   DevBuf row_scale;  // E4M3: s_i per row of A
+  // A^T in voxel slabs (slab > 0: slab width in voxels; AT's rows are the
+  // (slab, spot) rows, padding rows included): spot j's rows are
+  // comb_rows[comb_ptr[j] .. comb_ptr[j+1]), in ascending slab
+  int32_t slab = 0;
+  int64_t n_slab_rows = 0, n_slab_pad = 0;  // rows holding entries; padding entries
+  DevBuf comb_ptr, comb_rows;
 };
 
 namespace {
@@ -419,7 +430,7 @@ SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, const Partition& P
   a.x = x;
   a.y = y;
   a.n_groups = P.n_groups;
-  a.xcd_blocks = &op == &m->AT ? 1 : xcd_blocks(1);
+  a.xcd_blocks = &op == &m->AT && m->slab == 0 ? 1 : xcd_blocks(1);
   return a;
 }
 SpmvArgs make_args(const dose_matrix_s* m, const Operand& op, int sm, int n_rhs, const void* x, void* y) {
@@ -503,6 +514,158 @@ void build_transpose(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
   }
   T.h_row_ptr.resize(static_cast<size_t>(T.n_rows + 1));
   HIP_CHECK(hipMemcpyAsync(T.h_row_ptr.data(), rp64.get(), rp64.bytes(), hipMemcpyDeviceToHost, s));
+  HIP_CHECK(hipStreamSynchronize(s));
+  upload_row_ptr32(T, s);
+  upload_partition(T, group_nnz_t, s);
+}
+
+// Slab width of A^T in voxel slabs: the one-vector LDS window cap (so that
+// every row group of a slab reads v from LDS), at most kWinFloatsMax / 2
+// voxels so that an FP64 seed (two floats a voxel) stays windowed too.
+int32_t slab_voxels() {
+  const int64_t w = std::min<int64_t>(window_cap_floats(), kWinFloatsMax / 2);
+  return static_cast<int32_t>(w / kWinAlign * kWinAlign);
+}
+
+// A^T in voxel slabs on the device: A's entries stably sorted by (slab of
+// their voxel, spot), one row per distinct pair, entries in ascending voxel.
+// Each slab's entries are padded to a whole number of 4-entry quarters by a
+// padding row of zero codes at the slab's first voxel, whose partial no spot
+// combines: no quarter a row group loads then reaches into another slab, and
+// (with the partition starting a group at every slab's first row) every
+// group's window lies inside its slab.
+void build_transpose_slabs(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
+  const Operand& A = m->A;
+  Operand& T = m->AT;
+  const int64_t W = slab_voxels();
+  const int64_t n_slabs = (A.n_rows + W - 1) / W;
+  const int64_t nc = A.n_cols;
+  if (n_slabs * nc > int64_t{UINT32_MAX})
+    fail(DOSE_ERR_UNSUPPORTED, "slab transpose needs ceil(n_rows / slab) * n_cols < 2^32");
+  if (A.nnz + (kQuarterEntries - 1) * n_slabs > INT32_MAX) fail(DOSE_ERR_UNSUPPORTED, "transpose needs nnz < 2^31");
+  const int64_t n = A.nnz;
+  std::vector<uint32_t> run_key, run_len;
+  DevBuf rows, keys_out, perm_out;
+  if (n > 0) {
+    rows = DevBuf(static_cast<size_t>(n) * 4);
+    keys_out = DevBuf(static_cast<size_t>(n) * 4);
+    perm_out = DevBuf(static_cast<size_t>(n) * 4);
+    DevBuf keys_in(static_cast<size_t>(n) * 4), perm_in(static_cast<size_t>(n) * 4);
+    HIP_CHECK(launch_row_ids(A.row_ptr.get<uint32_t>(), A.n_rows, static_cast<uint64_t>(n), rows.get<uint32_t>(), s));
+    DevBuf wide;
+    const uint32_t* cols = reinterpret_cast<const uint32_t*>(A.col.get());
+    if (A.idx_bytes == 2) {
+      wide = DevBuf(static_cast<size_t>(n) * 4);
+      HIP_CHECK(launch_widen_u16(A.col.get<uint16_t>(), wide.get<uint32_t>(), n, s));
+      cols = wide.get<uint32_t>();
+    }
+    HIP_CHECK(launch_slab_keys(rows.get<uint32_t>(), cols, static_cast<uint32_t>(W), static_cast<uint32_t>(nc), n,
+                               keys_in.get<uint32_t>(), s));
+    HIP_CHECK(launch_iota(perm_in.get<uint32_t>(), n, s));
+    int end_bit = 1;
+    while (end_bit < 32 && (int64_t{1} << end_bit) < n_slabs * nc) ++end_bit;
+    size_t tmp_bytes = 0;
+    HIP_CHECK(radix_sort_pairs(nullptr, &tmp_bytes, keys_in.get<uint32_t>(), keys_out.get<uint32_t>(),
+                               perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
+    {
+      DevBuf tmp(tmp_bytes);
+      HIP_CHECK(radix_sort_pairs(tmp.get(), &tmp_bytes, keys_in.get<uint32_t>(), keys_out.get<uint32_t>(),
+                                 perm_in.get<uint32_t>(), perm_out.get<uint32_t>(), n, end_bit, s));
+      HIP_CHECK(hipStreamSynchronize(s));
+    }
+    // the distinct (slab, spot) keys and their entry counts
+    const int64_t max_runs = std::min<int64_t>(n, n_slabs * nc);
+    DevBuf uniq(static_cast<size_t>(max_runs) * 4), cnt(static_cast<size_t>(max_runs) * 4), n_runs(4);
+    size_t rle_bytes = 0;
+    HIP_CHECK(run_length_encode(nullptr, &rle_bytes, keys_out.get<uint32_t>(), uniq.get<uint32_t>(),
+                                cnt.get<uint32_t>(), n_runs.get<uint32_t>(), n, s));
+    DevBuf rle_tmp(std::max<size_t>(rle_bytes, 1));
+    HIP_CHECK(run_length_encode(rle_tmp.get(), &rle_bytes, keys_out.get<uint32_t>(), uniq.get<uint32_t>(),
+                                cnt.get<uint32_t>(), n_runs.get<uint32_t>(), n, s));
+    uint32_t h_runs = 0;
+    HIP_CHECK(hipMemcpyAsync(&h_runs, n_runs.get(), 4, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    if (h_runs == 0 || h_runs > max_runs) fail(DOSE_ERR_INTERNAL, "slab transpose: bad run count");
+    run_key.resize(h_runs);
+    run_len.resize(h_runs);
+    HIP_CHECK(hipMemcpyAsync(run_key.data(), uniq.get(), size_t{h_runs} * 4, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipMemcpyAsync(run_len.data(), cnt.get(), size_t{h_runs} * 4, hipMemcpyDeviceToHost, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+  }
+  // rows of the slab form (host): offsets, slab starts, padding, and the
+  // spot each row belongs to
+  std::vector<int64_t>& rp = T.h_row_ptr;
+  std::vector<uint8_t>& brk = T.h_brk;
+  rp.assign(1, 0);
+  brk.clear();
+  std::vector<uint32_t> slab_off(static_cast<size_t>(std::max<int64_t>(n_slabs, 1)), 0), row_spot, pad_pos;
+  std::vector<int32_t> pad_col;
+  int64_t pads = 0;
+  for (size_t i = 0; i < run_key.size();) {
+    const uint32_t t = run_key[i] / static_cast<uint32_t>(nc);
+    slab_off[t] = static_cast<uint32_t>(pads);
+    int64_t tot = 0;
+    for (bool first = true; i < run_key.size() && run_key[i] / static_cast<uint32_t>(nc) == t; ++i, first = false) {
+      brk.push_back(first ? 1 : 0);
+      rp.push_back(rp.back() + run_len[i]);
+      row_spot.push_back(run_key[i] % static_cast<uint32_t>(nc));
+      tot += run_len[i];
+    }
+    const int64_t p = (kQuarterEntries - tot % kQuarterEntries) % kQuarterEntries;
+    if (p > 0) {
+      for (int64_t q = 0; q < p; ++q) {
+        pad_pos.push_back(static_cast<uint32_t>(rp.back() + q));
+        pad_col.push_back(static_cast<int32_t>(t * W));
+      }
+      brk.push_back(0);
+      rp.push_back(rp.back() + p);
+      row_spot.push_back(UINT32_MAX);
+      pads += p;
+    }
+  }
+  T.n_rows = static_cast<int64_t>(rp.size()) - 1;
+  T.n_cols = A.n_rows;
+  T.nnz = n + pads;
+  m->slab = static_cast<int32_t>(W);
+  m->n_slab_pad = pads;
+  m->n_slab_rows = T.n_rows - static_cast<int64_t>(std::count(row_spot.begin(), row_spot.end(), UINT32_MAX));
+  // spot j's rows in ascending slab (rows are in ascending slab)
+  std::vector<uint32_t> cptr(static_cast<size_t>(nc) + 1, 0), crows(static_cast<size_t>(std::max<int64_t>(m->n_slab_rows, 1)));
+  for (uint32_t j : row_spot)
+    if (j != UINT32_MAX) ++cptr[j + 1];
+  for (int64_t j = 0; j < nc; ++j) cptr[j + 1] += cptr[j];
+  {
+    std::vector<uint32_t> fill(cptr.begin(), cptr.end() - 1);
+    for (size_t r = 0; r < row_spot.size(); ++r)
+      if (row_spot[r] != UINT32_MAX) crows[fill[row_spot[r]]++] = static_cast<uint32_t>(r);
+  }
+  const int vb = value_bytes(m->vf);
+  T.val = DevBuf(padded(T.nnz) * vb);
+  T.col = DevBuf(padded(T.nnz) * sizeof(int32_t));
+  T.idx_bytes = 4;
+  HIP_CHECK(hipMemsetAsync(T.val.get(), 0, T.val.bytes(), s));
+  HIP_CHECK(hipMemsetAsync(T.col.get(), 0, T.col.bytes(), s));
+  DevBuf d_off, d_pad_pos, d_pad_col;
+  if (n > 0) {
+    d_off = DevBuf(slab_off.size() * 4);
+    HIP_CHECK(hipMemcpyAsync(d_off.get(), slab_off.data(), slab_off.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_slab_gather(m->vf, perm_out.get<uint32_t>(), rows.get<uint32_t>(), keys_out.get<uint32_t>(),
+                                 static_cast<uint32_t>(nc), d_off.get<uint32_t>(), A.val.get(), T.val.get(),
+                                 T.col.get<int32_t>(), n, s));
+  }
+  if (!pad_pos.empty()) {
+    d_pad_pos = DevBuf(pad_pos.size() * 4);
+    d_pad_col = DevBuf(pad_col.size() * 4);
+    HIP_CHECK(hipMemcpyAsync(d_pad_pos.get(), pad_pos.data(), pad_pos.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipMemcpyAsync(d_pad_col.get(), pad_col.data(), pad_col.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_CHECK(launch_scatter_cols(d_pad_pos.get<uint32_t>(), d_pad_col.get<int32_t>(),
+                                  static_cast<int64_t>(pad_pos.size()), T.col.get<int32_t>(), s));
+  }
+  HIP_CHECK(launch_fill_pad(T.col.get(), 4, T.nnz, pad_entries(T.nnz), s));
+  m->comb_ptr = DevBuf(cptr.size() * 4);
+  m->comb_rows = DevBuf(crows.size() * 4);
+  HIP_CHECK(hipMemcpyAsync(m->comb_ptr.get(), cptr.data(), cptr.size() * 4, hipMemcpyHostToDevice, s));
+  HIP_CHECK(hipMemcpyAsync(m->comb_rows.get(), crows.data(), crows.size() * 4, hipMemcpyHostToDevice, s));
   HIP_CHECK(hipStreamSynchronize(s));
   upload_row_ptr32(T, s);
   upload_partition(T, group_nnz_t, s);
@@ -1213,14 +1376,17 @@ dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf, int32_t xf,
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
     *out = nullptr;
     if (xf == DOSE_IDX_RUNS) fail(DOSE_ERR_UNSUPPORTED, "run-length indices are a SELL-C-sigma format (dose_sell_create)");
-    if (flags & ~static_cast<uint32_t>(DOSE_CREATE_TRANSPOSE | DOSE_CREATE_AUTOTUNE))
+    if (flags & ~static_cast<uint32_t>(DOSE_CREATE_TRANSPOSE | DOSE_CREATE_AUTOTUNE | DOSE_CREATE_TRANSPOSE_SLABS))
       fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
     validate_csr(csr, vf, xf);
     hipStream_t s = as_stream(hip_stream);
     auto m = upload_encode_A(csr, vf, xf, s);
     Operand& A = m->A;
     upload_partition(A, default_group_nnz(A.nnz, m->device), s);
-    if (flags & DOSE_CREATE_TRANSPOSE) {
+    if (flags & DOSE_CREATE_TRANSPOSE_SLABS) {
+      build_transpose_slabs(m.get(), default_group_nnz(A.nnz, m->device), s);
+      m->has_t = true;
+    } else if (flags & DOSE_CREATE_TRANSPOSE) {
       build_transpose(m.get(), default_group_nnz(A.nnz, m->device), s);
       m->has_t = true;
     }
@@ -1234,10 +1400,17 @@ dose_status dose_matrix_create(const dose_csr_host* csr, int32_t vf, int32_t xf,
       if (A.nnz > 0) {
         auto P = autotune_operand(m.get(), A, scale_mode_A(m.get()), 1, xa.get<float>(), ya.get<float>(), s);
         if (P) A.part = std::move(*P);
-        if (m->has_t) {
-          // the mode dose_spmv_adjoint runs (E4M3: its seed carries the row scales)
+        if (m->has_t && m->AT.nnz > 0) {
+          // the mode dose_spmv_adjoint runs (E4M3: its seed carries the row
+          // scales); the slab form writes one partial per row
           const int smt = m->vf == kFp8 ? kScaleNone : scale_mode_AT(m.get());
-          auto PT = autotune_operand(m.get(), m->AT, smt, 1, ya.get<float>(), xa.get<float>(), s);
+          DevBuf part;
+          float* yt = xa.get<float>();
+          if (m->slab > 0) {
+            part = DevBuf(static_cast<size_t>(std::max<int64_t>(m->AT.n_rows, 1)) * 4);
+            yt = part.get<float>();
+          }
+          auto PT = autotune_operand(m.get(), m->AT, smt, 1, ya.get<float>(), yt, s);
           if (PT) m->AT.part = std::move(*PT);
         }
       }
@@ -1265,6 +1438,8 @@ dose_status dose_matrix_decode(dose_matrix m, int32_t part, int64_t row_begin, i
     if (!m || !row_ptr_out) fail(DOSE_ERR_INVALID_ARGUMENT, "null argument");
     if (part != DOSE_PART_A && part != DOSE_PART_AT) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown part");
     if (part == DOSE_PART_AT && !m->has_t) fail(DOSE_ERR_NO_TRANSPOSE, "matrix has no transpose");
+    if (part == DOSE_PART_AT && m->slab > 0)
+      fail(DOSE_ERR_UNSUPPORTED, "A^T is stored in voxel slabs, not one row per spot (decode A instead)");
     const Operand& op = part == DOSE_PART_A ? m->A : m->AT;
     if (row_begin < 0 || row_end < row_begin || row_end > op.n_rows) fail(DOSE_ERR_INVALID_ARGUMENT, "row range");
     DeviceGuard g(m->device);
@@ -1309,7 +1484,9 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     info->group_nnz_t = m->has_t ? m->AT.part.group_nnz : 0;
     info->n_groups_t = m->has_t ? m->AT.part.n_groups : 0;
     info->n_groups_windowed_t = m->has_t ? m->AT.part.n_windowed : 0;
-    info->device_bytes = A.bytes() + m->row_scale.bytes() + (m->has_t ? m->AT.bytes() : 0);
+    info->device_bytes = A.bytes() + m->row_scale.bytes() + (m->has_t ? m->AT.bytes() : 0) + m->comb_ptr.bytes() +
+                         m->comb_rows.bytes();
+    info->slab_voxels = m->slab;
     const uint64_t per_nnz = static_cast<uint64_t>(value_bytes(m->vf)) + static_cast<uint64_t>(A.idx_bytes);
     const uint64_t per_nnz_t = static_cast<uint64_t>(value_bytes(m->vf)) + 4;
     const uint64_t scale_b = m->vf == kFp8 ? 4 : 0;
@@ -1318,6 +1495,13 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     info->n_groups_split = A.part.n_split;
     info->n_groups_split_t = m->has_t ? m->AT.part.n_split : 0;
     info->adjoint_bytes = m->has_t ? A.nnz * per_nnz_t + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
+    if (m->slab > 0) {
+      // voxel slabs: the padding entries, one offset per slab row instead of
+      // per spot, each row's partial written and read back, the combine map
+      const uint64_t rows_t = static_cast<uint64_t>(m->AT.n_rows), rows_real = static_cast<uint64_t>(m->n_slab_rows);
+      info->adjoint_bytes = (A.nnz + m->n_slab_pad) * per_nnz_t + (rows_t + 1) * 4 + A.n_rows * scale_b +
+                            4 * A.n_rows + 8 * rows_t + (A.n_cols + 1) * 4 + 4 * rows_real + 4 * A.n_cols;
+    }
   });
 }
 
@@ -1365,7 +1549,22 @@ dose_status dose_spmv_adjoint_f64(dose_matrix m, const double* v, double* gout, 
       fail(DOSE_ERR_INVALID_ARGUMENT, "v and g must be 8-byte aligned");
     DeviceGuard g(m->device);
     const int sm = scale_mode_AT(m);
-    HIP_CHECK(launch_spmv_f64(m->vf, sm, make_args(m, m->AT, sm, 2, v, gout), as_stream(hip_stream)));
+    hipStream_t s = as_stream(hip_stream);
+    if (m->slab == 0) {
+      HIP_CHECK(launch_spmv_f64(m->vf, sm, make_args(m, m->AT, sm, 2, v, gout), s));
+      return;
+    }
+    // voxel slabs: the rows' FP64 partials, then each spot's sum over its
+    // slabs in ascending order
+    double* part = nullptr;
+    if (m->AT.n_rows > 0)
+      HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&part), static_cast<size_t>(m->AT.n_rows) * 8, s));
+    hipError_t e = launch_spmv_f64(m->vf, sm, make_args(m, m->AT, sm, 2, v, part), s);
+    if (e == hipSuccess)
+      e = launch_slab_combine(true, part, m->comb_ptr.get<uint32_t>(), m->comb_rows.get<uint32_t>(), gout,
+                              m->A.n_cols, s);
+    if (part) (void)hipFreeAsync(part, s);
+    HIP_CHECK(e);
   });
 }
 
@@ -1379,18 +1578,30 @@ dose_status dose_spmv_adjoint(dose_matrix m, const float* v, float* gout, void* 
       fail(DOSE_ERR_INVALID_ARGUMENT, "v and g must be 4-byte aligned");
     DeviceGuard g(m->device);
     hipStream_t s = as_stream(hip_stream);
-    if (m->vf != kFp8) {
+    if (m->vf != kFp8 && m->slab == 0) {
       run_product(m, m->AT, scale_mode_AT(m), 1, v, gout, s);
       return;
     }
     // E4M3: the row scales go into the seed first (u_i = fl32(s_i v_i)), so
-    // that each entry of A^T gathers one value; its term is fl32(q u_i)
-    const int64_t n = m->A.n_rows;
-    float* u = nullptr;
-    if (n > 0) HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&u), static_cast<size_t>(n) * 4, s));
-    hipError_t e = launch_scale_vec(n, m->row_scale.get<float>(), v, u, s);
-    if (e == hipSuccess) e = launch_spmv(m->vf, kScaleNone, 1, make_args(m, m->AT, kScaleNone, 1, u, gout), s);
-    if (u) (void)hipFreeAsync(u, s);
+    // that each entry of A^T gathers one value; its term is fl32(q u_i).
+    // Voxel slabs: the rows' partials, then each spot's sum over its slabs in
+    // ascending order.  One stream-ordered allocation holds u and the partials.
+    const bool fp8 = m->vf == kFp8;
+    const int64_t n_u = fp8 ? m->A.n_rows : 0, n_p = m->slab > 0 ? m->AT.n_rows : 0;
+    float* buf = nullptr;
+    if (n_u + n_p > 0)
+      HIP_CHECK(hipMallocAsync(reinterpret_cast<void**>(&buf), static_cast<size_t>(n_u + n_p) * 4, s));
+    float* u = fp8 ? buf : nullptr;
+    float* part = m->slab > 0 ? buf + n_u : nullptr;
+    hipError_t e = hipSuccess;
+    if (fp8) e = launch_scale_vec(n_u, m->row_scale.get<float>(), v, u, s);
+    const float* x = fp8 ? u : v;
+    const int sm = fp8 ? kScaleNone : scale_mode_AT(m);
+    if (e == hipSuccess) e = launch_spmv(m->vf, sm, 1, make_args(m, m->AT, sm, 1, x, m->slab > 0 ? part : gout), s);
+    if (e == hipSuccess && m->slab > 0)
+      e = launch_slab_combine(false, part, m->comb_ptr.get<uint32_t>(), m->comb_rows.get<uint32_t>(), gout,
+                              m->A.n_cols, s);
+    if (buf) (void)hipFreeAsync(buf, s);
     HIP_CHECK(e);
   });
 }

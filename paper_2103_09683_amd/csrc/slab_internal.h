@@ -1,0 +1,46 @@
+// A^T stored in voxel slabs: the device steps of building it and the combine
+// that finishes its adjoint.
+//
+// The adjoint g = A^T v sums, for every spot j, the entries of column j of A
+// times the seed v over the voxels (Sec. I: a gradient every iteration).  A
+// column of A runs through the whole depth of the dose grid, far wider than
+// an LDS window of v, so the slab form cuts the voxel range into slabs of W
+// consecutive voxels and stores A^T with one row per (slab, spot) pair that
+// holds entries, ordered slab by slab and, within a slab, by spot; each row
+// lists its entries in ascending voxel.  The row products are partial sums
+// P[r] whose row groups each read v from one slab (so from LDS); the spot's
+// result is the sum of its rows' partials in ascending slab order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dose {
+
+// keys[k] = (rows[k] / slab) * n_cols + cols[k]: the (slab, spot) of entry k.
+hipError_t launch_slab_keys(const uint32_t* rows, const uint32_t* cols, uint32_t slab, uint32_t n_cols,
+                            int64_t n, uint32_t* keys, hipStream_t s);
+
+// The distinct keys of a sorted key array and their run lengths (n_runs is
+// written to device memory).  tmp == nullptr: *tmp_bytes gets the scratch size.
+hipError_t run_length_encode(void* tmp, size_t* tmp_bytes, const uint32_t* keys, uint32_t* unique, uint32_t* counts,
+                             uint32_t* n_runs, int64_t n, hipStream_t s);
+
+// Entry k of the key-sorted order (A's entry perm[k], of A's row rows[perm[k]]
+// and key keys[k]) goes to position k + slab_off[keys[k] / n_cols] of the slab
+// stream: its code, and its voxel as the column.
+hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows, const uint32_t* keys,
+                              uint32_t n_cols, const uint32_t* slab_off, const void* codes_in, void* codes_out,
+                              int32_t* col_out, int64_t n, hipStream_t s);
+
+// col_out[pos[i]] = col[i] for i < n (the padding entries of the slabs).
+hipError_t launch_scatter_cols(const uint32_t* pos, const int32_t* col, int64_t n, int32_t* col_out, hipStream_t s);
+
+// g[j] = sum of part[rows[k]] for k from ptr[j] to ptr[j+1] - 1, added in
+// ascending k (ascending slab), starting from +0; f64 selects FP64 partials
+// and results.
+hipError_t launch_slab_combine(bool f64, const void* part, const uint32_t* ptr, const uint32_t* rows, void* g,
+                               int64_t n_cols, hipStream_t s);
+
+}  // namespace dose

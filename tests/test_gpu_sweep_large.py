@@ -10,6 +10,8 @@ GPU, checked against the CPU oracle on a seeded 1% row sample.
   transpose product), while the kernel still walks all of A^T.
 * Adjointness with a dense v at full size: <v, A x> = <A^T v, x> within the
   FP32 bound.
+* The same adjoint checks over A^T in voxel slabs (FP16 and E4M3, FP32 and
+  FP64 seeds).
 """
 import time
 
@@ -96,6 +98,42 @@ def test_sweep_large_forward_and_adjoint(sweep, fmt, dev):
 
     # adjointness at full size with a dense signed v (A >= 0 and x >= 0, so
     # |A| |x| = A x = y)
+    vd = dosegen.signed_values(spec.seed, 3, spec.n_rows)
+    gd = A.adjoint(torch.from_numpy(vd).cuda()).cpu().numpy()
+    lhs = float(np.dot(vd.astype(np.float64), y.astype(np.float64)))
+    rhs = float(np.dot(gd.astype(np.float64), x_h.astype(np.float64)))
+    bound = float(np.dot(np.abs(vd).astype(np.float64), y.astype(np.float64)))
+    assert abs(lhs - rhs) <= 2 * TOL * bound, (fmt, lhs, rhs, bound)
+    A.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("fmt", ["fp16", "fp8e4m3_rowscale"])
+def test_sweep_large_adjoint_slabs(sweep, fmt, dev):
+    """The adjoint over A^T in voxel slabs at full size: every group's seed
+    window in LDS; v on the sampled rows, so that all 60,000 spots are
+    checked (FP32 and FP64 seeds); adjointness with a dense v."""
+    spec, rp, cols, vals, rows, (srp, scols, svals) = sweep
+    t0 = time.time()
+    A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose="slabs")
+    inf = A.info()
+    _say(f"sweep_large slabs {fmt}: created in {time.time() - t0:.1f}s", inf)
+    assert inf["n_groups_windowed_t"] == inf["n_groups_t"] > 0
+    dec, _ = oracle.decode_matrix(fmt, srp, svals)
+    v_s = dosegen.signed_values(spec.seed, 2, rows.size)
+    v = np.zeros(spec.n_rows, np.float32)
+    v[rows] = v_s
+    g_ref = oracle.spmv_T(srp, scols, dec, v_s, spec.n_cols)
+    scale = oracle.spmv_T(srp, scols, np.abs(dec), np.abs(v_s), spec.n_cols)
+    g = A.adjoint(torch.from_numpy(v).cuda()).cpu().numpy()
+    err = oracle.max_scaled_err(g, g_ref, scale)
+    g64 = A.adjoint(torch.from_numpy(v.astype(np.float64)).cuda()).cpu().numpy()
+    err64 = oracle.max_scaled_err(g64, g_ref, scale)
+    _say(f"{fmt} slabs: adjoint max scaled err {err:.3e} (FP64 {err64:.3e}) over all {spec.n_cols} spots")
+    assert err <= TOL, fmt
+    assert err64 <= (2.0 ** -22 if fmt == "fp8e4m3_rowscale" else 1e-12), fmt
+    x_h = dosegen.spot_weights(spec.seed, 0, spec.n_cols)
+    y = A.spmv(torch.from_numpy(x_h).cuda()).cpu().numpy()
     vd = dosegen.signed_values(spec.seed, 3, spec.n_rows)
     gd = A.adjoint(torch.from_numpy(vd).cuda()).cpu().numpy()
     lhs = float(np.dot(vd.astype(np.float64), y.astype(np.float64)))
