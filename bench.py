@@ -433,6 +433,8 @@ def main(argv=None):
     ap.add_argument("--sell-index", default="i32,u16,runs", help="index formats of the SELL-C-sigma variants")
     ap.add_argument("--adjoint-layout", choices=["rows", "slabs"], default="rows",
                     help="A^T of --part adjoint: one row per spot, or voxel slabs")
+    ap.add_argument("--adjoint-workload", choices=["clinical", "largest"], default="clinical",
+                    help="matrix of --part adjoint: the clinical beam or the largest workload")
     ap.add_argument("--part", choices=["clinical", "adjoint", "batched", "sell"],
                     help="only one part: the clinical-beam variants, the clinical-beam adjoint, the full-size "
                          "batched robust scenarios, or the SELL-C-sigma variants on the clinical beam")
@@ -495,7 +497,8 @@ def bench_part(torch, dm, dosegen, args):
         return bench_clinical(torch, dm, dosegen, args)
     if args.part == "batched":
         return bench_batched(torch, dm, dosegen, args)
-    spec = dosegen.clinical_beam()
+    spec = dosegen.sweep_large() if args.part == "adjoint" and args.adjoint_workload == "largest" \
+        else dosegen.clinical_beam()
     rp, cols, vals = dosegen.csr(spec)
     x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
     if args.part == "sell":
@@ -503,8 +506,8 @@ def bench_part(torch, dm, dosegen, args):
         y = A.spmv(x)
         A.close()
         return bench_sell(torch, dm, spec, rp, cols, vals, x, y, args)
-    # the adjoint of the clinical beam (FP16, FP32 vectors), over spot rows
-    # or (--adjoint-layout slabs) voxel slabs
+    # the adjoint of the clinical beam (or --adjoint-workload largest), FP16,
+    # FP32 vectors, over spot rows or (--adjoint-layout slabs) voxel slabs
     A = dm.DoseMatrix(rp, cols, vals, spec.n_cols, "fp16",
                       transpose="slabs" if args.adjoint_layout == "slabs" else True)
     info = A.info()

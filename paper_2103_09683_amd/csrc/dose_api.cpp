@@ -303,6 +303,7 @@ struct Operand {
   int idx_bytes = 4;         // column index width: 4 (int32) or 2 (uint16)
   Partition part;            // the partition plain products use
   std::vector<uint8_t> h_brk;  // rows that start a row group (A^T in slabs: each slab's first row), or empty
+  std::vector<uint32_t> h_row_cbase;  // column of index 0 per row (A^T in slabs: its slab's first voxel), or empty
 
   uint64_t bytes() const { return val.bytes() + col.bytes() + row_ptr.bytes() + part.groups.bytes(); }
 };
@@ -330,6 +331,9 @@ int64_t window_cap_floats() {
 Partition make_partition(const Operand& op, int group_nnz, hipStream_t s) {
   std::vector<GroupDesc> G =
       build_partition(op.h_row_ptr.data(), op.n_rows, group_nnz, op.h_brk.empty() ? nullptr : op.h_brk.data());
+  // a group's rows share one column base (groups never cross a slab)
+  if (!op.h_row_cbase.empty())
+    for (GroupDesc& g : G) g.cbase = op.h_row_cbase[g.row[0]];
   Partition P;
   P.groups = DevBuf(std::max<size_t>(1, G.size()) * sizeof(GroupDesc));
   if (!G.empty()) {
@@ -528,12 +532,13 @@ int32_t slab_voxels() {
 }
 
 // A^T in voxel slabs on the device: A's entries stably sorted by (slab of
-// their voxel, spot), one row per distinct pair, entries in ascending voxel.
-// Each slab's entries are padded to a whole number of 4-entry quarters by a
-// padding row of zero codes at the slab's first voxel, whose partial no spot
-// combines: no quarter a row group loads then reaches into another slab, and
-// (with the partition starting a group at every slab's first row) every
-// group's window lies inside its slab.
+// their voxel, spot), one row per distinct pair, entries in ascending voxel,
+// each column stored as a 16-bit offset from its slab's first voxel (the
+// groups' column base).  Each slab's entries are padded to a whole number of
+// 4-entry quarters by a padding row of zero codes at the slab's first voxel,
+// whose partial no spot combines: no quarter a row group loads then reaches
+// into another slab, and (with the partition starting a group at every
+// slab's first row) every group's window lies inside its slab.
 void build_transpose_slabs(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
   const Operand& A = m->A;
   Operand& T = m->AT;
@@ -598,8 +603,9 @@ void build_transpose_slabs(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
   std::vector<uint8_t>& brk = T.h_brk;
   rp.assign(1, 0);
   brk.clear();
-  std::vector<uint32_t> slab_off(static_cast<size_t>(std::max<int64_t>(n_slabs, 1)), 0), row_spot, pad_pos;
-  std::vector<int32_t> pad_col;
+  std::vector<uint32_t> slab_off(static_cast<size_t>(std::max<int64_t>(n_slabs, 1)), 0), row_spot;
+  std::vector<uint32_t>& cbase = T.h_row_cbase;
+  cbase.clear();
   int64_t pads = 0;
   for (size_t i = 0; i < run_key.size();) {
     const uint32_t t = run_key[i] / static_cast<uint32_t>(nc);
@@ -609,17 +615,17 @@ void build_transpose_slabs(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
       brk.push_back(first ? 1 : 0);
       rp.push_back(rp.back() + run_len[i]);
       row_spot.push_back(run_key[i] % static_cast<uint32_t>(nc));
+      cbase.push_back(static_cast<uint32_t>(t * W));
       tot += run_len[i];
     }
+    // the padding entries keep the zero codes and zero offsets (the slab's
+    // first voxel) of the cleared streams
     const int64_t p = (kQuarterEntries - tot % kQuarterEntries) % kQuarterEntries;
     if (p > 0) {
-      for (int64_t q = 0; q < p; ++q) {
-        pad_pos.push_back(static_cast<uint32_t>(rp.back() + q));
-        pad_col.push_back(static_cast<int32_t>(t * W));
-      }
       brk.push_back(0);
       rp.push_back(rp.back() + p);
       row_spot.push_back(UINT32_MAX);
+      cbase.push_back(static_cast<uint32_t>(t * W));
       pads += p;
     }
   }
@@ -641,27 +647,19 @@ void build_transpose_slabs(dose_matrix_s* m, int group_nnz_t, hipStream_t s) {
   }
   const int vb = value_bytes(m->vf);
   T.val = DevBuf(padded(T.nnz) * vb);
-  T.col = DevBuf(padded(T.nnz) * sizeof(int32_t));
-  T.idx_bytes = 4;
+  T.col = DevBuf(padded(T.nnz) * sizeof(uint16_t));
+  T.idx_bytes = 2;
   HIP_CHECK(hipMemsetAsync(T.val.get(), 0, T.val.bytes(), s));
   HIP_CHECK(hipMemsetAsync(T.col.get(), 0, T.col.bytes(), s));
-  DevBuf d_off, d_pad_pos, d_pad_col;
+  DevBuf d_off;
   if (n > 0) {
     d_off = DevBuf(slab_off.size() * 4);
     HIP_CHECK(hipMemcpyAsync(d_off.get(), slab_off.data(), slab_off.size() * 4, hipMemcpyHostToDevice, s));
     HIP_CHECK(launch_slab_gather(m->vf, perm_out.get<uint32_t>(), rows.get<uint32_t>(), keys_out.get<uint32_t>(),
-                                 static_cast<uint32_t>(nc), d_off.get<uint32_t>(), A.val.get(), T.val.get(),
-                                 T.col.get<int32_t>(), n, s));
+                                 static_cast<uint32_t>(nc), static_cast<uint32_t>(W), d_off.get<uint32_t>(),
+                                 A.val.get(), T.val.get(), T.col.get<uint16_t>(), n, s));
   }
-  if (!pad_pos.empty()) {
-    d_pad_pos = DevBuf(pad_pos.size() * 4);
-    d_pad_col = DevBuf(pad_col.size() * 4);
-    HIP_CHECK(hipMemcpyAsync(d_pad_pos.get(), pad_pos.data(), pad_pos.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_CHECK(hipMemcpyAsync(d_pad_col.get(), pad_col.data(), pad_col.size() * 4, hipMemcpyHostToDevice, s));
-    HIP_CHECK(launch_scatter_cols(d_pad_pos.get<uint32_t>(), d_pad_col.get<int32_t>(),
-                                  static_cast<int64_t>(pad_pos.size()), T.col.get<int32_t>(), s));
-  }
-  HIP_CHECK(launch_fill_pad(T.col.get(), 4, T.nnz, pad_entries(T.nnz), s));
+  HIP_CHECK(launch_fill_pad(T.col.get(), 2, T.nnz, pad_entries(T.nnz), s));
   m->comb_ptr = DevBuf(cptr.size() * 4);
   m->comb_rows = DevBuf(crows.size() * 4);
   HIP_CHECK(hipMemcpyAsync(m->comb_ptr.get(), cptr.data(), cptr.size() * 4, hipMemcpyHostToDevice, s));
@@ -1496,10 +1494,12 @@ dose_status dose_matrix_info(dose_matrix m, dose_matrix_info_t* info) {
     info->n_groups_split_t = m->has_t ? m->AT.part.n_split : 0;
     info->adjoint_bytes = m->has_t ? A.nnz * per_nnz_t + (A.n_cols + 1) * 4 + A.n_rows * scale_b + 4 * A.n_rows + 4 * A.n_cols : 0;
     if (m->slab > 0) {
-      // voxel slabs: the padding entries, one offset per slab row instead of
-      // per spot, each row's partial written and read back, the combine map
+      // voxel slabs: 16-bit indices, the padding entries, one offset per
+      // slab row instead of per spot, each row's partial written and read
+      // back, the combine map
       const uint64_t rows_t = static_cast<uint64_t>(m->AT.n_rows), rows_real = static_cast<uint64_t>(m->n_slab_rows);
-      info->adjoint_bytes = (A.nnz + m->n_slab_pad) * per_nnz_t + (rows_t + 1) * 4 + A.n_rows * scale_b +
+      const uint64_t per_nnz_s = static_cast<uint64_t>(value_bytes(m->vf)) + 2;
+      info->adjoint_bytes = (A.nnz + m->n_slab_pad) * per_nnz_s + (rows_t + 1) * 4 + A.n_rows * scale_b +
                             4 * A.n_rows + 8 * rows_t + (A.n_cols + 1) * 4 + 4 * rows_real + 4 * A.n_cols;
     }
   });

@@ -50,7 +50,8 @@ struct alignas(64) GroupDesc {
   uint32_t split;                 // 1: one row shared by all waves
   uint32_t ent[kGroupWaves];      // wave w's entries end at nnz_base + ent[w] (split: ent[3] is the row's length)
   uint32_t item;                  // batched launches: the item the group belongs to
-  uint32_t pad;
+  uint32_t cbase;                 // column of index 0: 0, or (A^T in voxel slabs, 16-bit slab-local
+                                  // indices) the first voxel of the group's slab
 };
 static_assert(sizeof(GroupDesc) == 64, "GroupDesc layout");
 

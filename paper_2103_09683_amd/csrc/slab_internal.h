@@ -7,7 +7,8 @@
 // an LDS window of v, so the slab form cuts the voxel range into slabs of W
 // consecutive voxels and stores A^T with one row per (slab, spot) pair that
 // holds entries, ordered slab by slab and, within a slab, by spot; each row
-// lists its entries in ascending voxel.  The row products are partial sums
+// lists its entries in ascending voxel, as 16-bit offsets from the slab's
+// first voxel (the row groups' column base).  The row products are partial sums
 // P[r] whose row groups each read v from one slab (so from LDS); the spot's
 // result is the sum of its rows' partials in ascending slab order.
 #pragma once
@@ -28,14 +29,12 @@ hipError_t run_length_encode(void* tmp, size_t* tmp_bytes, const uint32_t* keys,
                              uint32_t* n_runs, int64_t n, hipStream_t s);
 
 // Entry k of the key-sorted order (A's entry perm[k], of A's row rows[perm[k]]
-// and key keys[k]) goes to position k + slab_off[keys[k] / n_cols] of the slab
-// stream: its code, and its voxel as the column.
+// and key keys[k], slab t = keys[k] / n_cols) goes to position k + slab_off[t]
+// of the slab stream: its code, and as its column the voxel's offset from the
+// slab's first voxel, rows[perm[k]] - t * slab (16 bits: slab <= 65536).
 hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows, const uint32_t* keys,
-                              uint32_t n_cols, const uint32_t* slab_off, const void* codes_in, void* codes_out,
-                              int32_t* col_out, int64_t n, hipStream_t s);
-
-// col_out[pos[i]] = col[i] for i < n (the padding entries of the slabs).
-hipError_t launch_scatter_cols(const uint32_t* pos, const int32_t* col, int64_t n, int32_t* col_out, hipStream_t s);
+                              uint32_t n_cols, uint32_t slab, const uint32_t* slab_off, const void* codes_in,
+                              void* codes_out, uint16_t* col_out, int64_t n, hipStream_t s);
 
 // g[j] = sum of part[rows[k]] for k from ptr[j] to ptr[j+1] - 1, added in
 // ascending k (ascending slab), starting from +0; f64 selects FP64 partials

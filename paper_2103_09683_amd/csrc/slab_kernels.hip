@@ -26,21 +26,16 @@ __global__ void k_slab_keys(const uint32_t* __restrict__ rows, const uint32_t* _
 
 template <typename C>
 __global__ void k_slab_gather(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rows,
-                              const uint32_t* __restrict__ keys, uint32_t n_cols,
+                              const uint32_t* __restrict__ keys, uint32_t n_cols, uint32_t slab,
                               const uint32_t* __restrict__ slab_off, const C* __restrict__ codes_in,
-                              C* __restrict__ codes_out, int32_t* __restrict__ col_out, int64_t n) {
+                              C* __restrict__ codes_out, uint16_t* __restrict__ col_out, int64_t n) {
   const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= n) return;
   const uint32_t e = perm[k];
-  const int64_t at = k + slab_off[keys[k] / n_cols];
+  const uint32_t t = keys[k] / n_cols;
+  const int64_t at = k + slab_off[t];
   codes_out[at] = codes_in[e];
-  col_out[at] = static_cast<int32_t>(rows[e]);
-}
-
-__global__ void k_scatter_cols(const uint32_t* __restrict__ pos, const int32_t* __restrict__ col, int64_t n,
-                               int32_t* __restrict__ col_out) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) col_out[pos[i]] = col[i];
+  col_out[at] = static_cast<uint16_t>(rows[e] - t * slab);
 }
 
 // A spot's partials are added one by one in ascending slab; their loads are
@@ -86,26 +81,20 @@ hipError_t run_length_encode(void* tmp, size_t* tmp_bytes, const uint32_t* keys,
 }
 
 hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows, const uint32_t* keys,
-                              uint32_t n_cols, const uint32_t* slab_off, const void* codes_in, void* codes_out,
-                              int32_t* col_out, int64_t n, hipStream_t s) {
+                              uint32_t n_cols, uint32_t slab, const uint32_t* slab_off, const void* codes_in,
+                              void* codes_out, uint16_t* col_out, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (n_cols == 0) return hipErrorInvalidValue;
+  if (n_cols == 0 || slab == 0 || slab > 65536) return hipErrorInvalidValue;
   const dim3 grid(slab_blocks(n, 256)), block(256);
   if (vf == kFp8)
-    hipLaunchKernelGGL(k_slab_gather<uint8_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab_off,
+    hipLaunchKernelGGL(k_slab_gather<uint8_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab, slab_off,
                        static_cast<const uint8_t*>(codes_in), static_cast<uint8_t*>(codes_out), col_out, n);
   else if (vf == kFp32)
-    hipLaunchKernelGGL(k_slab_gather<uint32_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab_off,
+    hipLaunchKernelGGL(k_slab_gather<uint32_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab, slab_off,
                        static_cast<const uint32_t*>(codes_in), static_cast<uint32_t*>(codes_out), col_out, n);
   else
-    hipLaunchKernelGGL(k_slab_gather<uint16_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab_off,
+    hipLaunchKernelGGL(k_slab_gather<uint16_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab, slab_off,
                        static_cast<const uint16_t*>(codes_in), static_cast<uint16_t*>(codes_out), col_out, n);
-  return hipGetLastError();
-}
-
-hipError_t launch_scatter_cols(const uint32_t* pos, const int32_t* col, int64_t n, int32_t* col_out, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_cols, dim3(slab_blocks(n, 256)), dim3(256), 0, s, pos, col, n, col_out);
   return hipGetLastError();
 }
 

@@ -388,12 +388,14 @@ __device__ __forceinline__ void chunk_cols(const ColQuad<IX>& ca, const ColQuad<
 
 // Global-memory gathers of a step (x without a window, column scales of an
 // E4M3 A^T), issued before the next step's loads, so that waiting for them
-// leaves those loads in flight.
+// leaves those loads in flight.  Column c of the step is column cbase + c of
+// x and of the scales.
 template <class T, int VF, int SM, int IX, int NRHS, bool WIN>
-__device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF, IX>& ch, Gathered<T, NRHS>& g) {
+__device__ __forceinline__ void gather_global(const SpmvArgs& a, uint32_t cbase, const Chunk<VF, IX>& ch,
+                                              Gathered<T, NRHS>& g) {
   int cols[kChunk];
   chunk_cols(ch.ca, ch.cb, cols);
-  const T* x = static_cast<const T*>(a.x);
+  const T* x = static_cast<const T*>(a.x) + static_cast<int64_t>(cbase) * NRHS;
   if constexpr (!WIN) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -410,7 +412,7 @@ __device__ __forceinline__ void gather_global(const SpmvArgs& a, const Chunk<VF,
   }
   if constexpr (SM == kScaleCol) {
 #pragma unroll
-    for (int e = 0; e < kChunk; ++e) g.sc[e] = a.scale[cols[e]];
+    for (int e = 0; e < kChunk; ++e) g.sc[e] = a.scale[cbase + cols[e]];
   }
 }
 
@@ -531,7 +533,7 @@ constexpr int kCopy = 4;
 template <class T, int VF, int SM, int IX, int NRHS, bool WIN, bool SPLIT, bool ACC>
 __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, uint32_t r_begin, uint32_t r_end,
                                             uint32_t e_begin, uint32_t e_end, int first, float* xw, int cmin, int clen,
-                                            const void* safe, T (&tot)[NRHS], float& sc) {
+                                            uint32_t cbase, const void* safe, T (&tot)[NRHS], float& sc) {
   constexpr int stride = SPLIT ? kRowSlots : 1;
   constexpr int DEPTH = kDepth;
   const uint64_t origin = base & ~static_cast<uint64_t>(kStepEntries - 1);
@@ -557,7 +559,8 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
   // pieces (x + cmin * NRHS is 32-byte aligned within x)
   const int nf = clen * NRHS * static_cast<int>(sizeof(T) / 4);
   const int n4 = nf >> 2;
-  const float* xs = reinterpret_cast<const float*>(static_cast<const T*>(a.x) + static_cast<int64_t>(cmin) * NRHS);
+  const float* xs =
+      reinterpret_cast<const float*>(static_cast<const T*>(a.x) + (static_cast<int64_t>(cmin) + cbase) * NRHS);
   // every load is issued (a lane without a piece reads the group descriptor
   // instead), so that the compiler's count of loads in flight stays exact
   const int tid = static_cast<int>(threadIdx.x);
@@ -706,7 +709,7 @@ __device__ __forceinline__ void wave_stream(const SpmvArgs& a, uint64_t base, ui
       for (int ph = 0; ph <= DEPTH; ++ph) {
         const int cur = ph, nxt = (ph + DEPTH) % (DEPTH + 1);
         T p[kChunk][NRHS];
-        gather_global<T, VF, SM, IX, NRHS, WIN>(a, cs[cur], g);
+        gather_global<T, VF, SM, IX, NRHS, WIN>(a, cbase, cs[cur], g);
         load_step<VF, IX>(vb, cb, k + DEPTH * stride, pmin, pmax, cs[nxt]);
         // keep the scheduler from sinking the loads below the compute
         __builtin_amdgcn_sched_barrier(0);
@@ -730,24 +733,27 @@ __device__ __forceinline__ void run_group(const SpmvArgs& a, const GroupDesc* gp
   const uint32_t clen = gp->clen;
   const bool win = clen > 0 && window_floats(clen, NRHS * static_cast<int>(sizeof(T) / 4)) <= a.win_floats;
   const int cmin = win ? static_cast<int>(gp->cmin) : 0;
+  // the group's column indices count from cbase (x and an E4M3 column
+  // scale are read from there)
+  const uint32_t cbase = gp->cbase;
   T tot[NRHS];
   float sc;
   if (gp->split == 0) {
     const uint32_t r0 = gp->row[wave], r1 = gp->row[wave + 1];
     const uint32_t e0 = wave == 0 ? 0u : gp->ent[wave - 1], e1 = gp->ent[wave];
     if (win)
-      wave_stream<T, VF, SM, IX, NRHS, true, false, ACC>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen), gp,
-                                                    tot, sc);
+      wave_stream<T, VF, SM, IX, NRHS, true, false, ACC>(a, base, r0, r1, e0, e1, 0, xw, cmin, static_cast<int>(clen),
+                                                    cbase, gp, tot, sc);
     else
-      wave_stream<T, VF, SM, IX, NRHS, false, false, ACC>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, gp, tot, sc);
+      wave_stream<T, VF, SM, IX, NRHS, false, false, ACC>(a, base, r0, r1, e0, e1, 0, xw, 0, 0, cbase, gp, tot, sc);
     return;
   }
   const uint32_t row = gp->row[0], len = gp->ent[kGroupWaves - 1];
   if (win)
     wave_stream<T, VF, SM, IX, NRHS, true, true, ACC>(a, base, row, row + 1, 0, len, wave, xw, cmin, static_cast<int>(clen),
-                                                 gp, tot, sc);
+                                                 cbase, gp, tot, sc);
   else
-    wave_stream<T, VF, SM, IX, NRHS, false, true, ACC>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, gp, tot, sc);
+    wave_stream<T, VF, SM, IX, NRHS, false, true, ACC>(a, base, row, row + 1, 0, len, wave, xw, 0, 0, cbase, gp, tot, sc);
   if ((threadIdx.x & (kWave - 1)) == kWave - 1)
 #pragma unroll
     for (int q = 0; q < NRHS; ++q) part[wave * NRHS + q] = tot[q];
@@ -826,6 +832,8 @@ __global__ __launch_bounds__(kGroupThreads) __attribute__((amdgpu_waves_per_eu(4
 }
 
 template <int VF, int SM, int NRHS>
+// (FP32 vectors with column scales, the spot-row A^T's, are built for int32
+// indices only; launch_spmv refuses other widths.)
 void launch_ix(const SpmvArgs& a, size_t lds, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
   if (SM != kScaleCol && a.idx_bytes == 2)
@@ -916,6 +924,8 @@ __global__ __launch_bounds__(256) void k_group_windows(GroupDesc* __restrict__ g
 
 hipError_t launch_spmv(int vf, int scale_mode, int n_rhs, const SpmvArgs& a, hipStream_t s) {
   if (a.n_groups <= 0) return hipSuccess;
+  if (a.idx_bytes != 4 && a.idx_bytes != 2) return hipErrorInvalidValue;
+  if (scale_mode == kScaleCol && a.idx_bytes != 4) return hipErrorInvalidValue;
   if (vf == kFp16 && scale_mode == kScaleNone) return launch_rhs<kFp16, kScaleNone>(n_rhs, a, s);
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_rhs<kBf16, kScaleNone>(n_rhs, a, s);
   if (vf == kFp32 && scale_mode == kScaleNone) return launch_rhs<kFp32, kScaleNone>(n_rhs, a, s);
@@ -933,8 +943,10 @@ template <int VF, int SM>
 hipError_t launch_f64(const SpmvArgs& a, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(a.n_groups)), block(kGroupThreads);
   const size_t lds = static_cast<size_t>(a.win_floats) * sizeof(float);
-  if (SM != kScaleCol && a.idx_bytes == 2)
-    hipLaunchKernelGGL((k_spmv_f64<VF, SM, SM == kScaleCol ? 4 : 2>), grid, block, lds, s, a);
+  // every scale mode with either index width (column scales with 16-bit
+  // indices: the E4M3 FP64 adjoint over A^T in voxel slabs)
+  if (a.idx_bytes == 2)
+    hipLaunchKernelGGL((k_spmv_f64<VF, SM, 2>), grid, block, lds, s, a);
   else
     hipLaunchKernelGGL((k_spmv_f64<VF, SM, 4>), grid, block, lds, s, a);
   return hipGetLastError();
@@ -942,6 +954,7 @@ hipError_t launch_f64(const SpmvArgs& a, hipStream_t s) {
 
 hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_t s) {
   if (a.n_groups <= 0) return hipSuccess;
+  if (a.idx_bytes != 4 && a.idx_bytes != 2) return hipErrorInvalidValue;
   if (vf == kFp16 && scale_mode == kScaleNone) return launch_f64<kFp16, kScaleNone>(a, s);
   if (vf == kBf16 && scale_mode == kScaleNone) return launch_f64<kBf16, kScaleNone>(a, s);
   if (vf == kFp32 && scale_mode == kScaleNone) return launch_f64<kFp32, kScaleNone>(a, s);
@@ -953,6 +966,8 @@ hipError_t launch_spmv_f64(int vf, int scale_mode, const SpmvArgs& a, hipStream_
 hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int accumulate, int idx_bytes, const BatchTable& t,
                                int64_t n_work, int lds_floats, hipStream_t s) {
   if (n_work <= 0) return hipSuccess;
+  if (idx_bytes != 4 && idx_bytes != 2) return hipErrorInvalidValue;
+  if (scale_mode == kScaleCol && idx_bytes != 4) return hipErrorInvalidValue;
   if (vf == kFp16 && scale_mode == kScaleNone)
     return launch_rhs_batched<kFp16, kScaleNone>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kBf16 && scale_mode == kScaleNone)

@@ -145,7 +145,8 @@ def test_create_autotune(tmp_path, monkeypatch, dev):
     assert len((tmp_path / "tune.txt").read_text().split()) == 4  # two keys, each stored once
     c, keep = dm._csr_struct(rp, cols, vals, 6000)
     h = dm.ctypes.c_void_p()
-    assert dm._lib.load().dose_matrix_create(dm.ctypes.byref(c), dm._lib.VAL_FP16, dm._lib.IDX_I32, 4, None,
+    # 8: the lowest bit no create flag uses
+    assert dm._lib.load().dose_matrix_create(dm.ctypes.byref(c), dm._lib.VAL_FP16, dm._lib.IDX_I32, 8, None,
                                              dm.ctypes.byref(h)) == dm._lib.ERR_INVALID_ARGUMENT
     A0.close()
 
