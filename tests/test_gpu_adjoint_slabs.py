@@ -226,3 +226,29 @@ def test_slab_adjoint_autograd_autotune_and_adjointness(dev):
     assert abs(lhs - rhs) <= 2e-6 * bound
     A.close()
     T.close()
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp8e4m3_rowscale"])
+def test_slab_matrix_forward_plans_and_autotune(fmt, dev):
+    """A matrix whose transpose is stored in voxel slabs keeps A as it is:
+    its forward product, alone and in a batch plan, has the bits of a matrix
+    without transpose; the create-time autotune (which times the E4M3
+    adjoint without column scales) leaves the slab adjoint's bits unchanged."""
+    spec = dosegen.small_plain()
+    rp, cols, vals = dosegen.csr(spec)
+    x = torch.from_numpy(dosegen.spot_weights(spec.seed, 0, spec.n_cols)).cuda()
+    v = torch.from_numpy(dosegen.signed_values(spec.seed, 5, spec.n_rows)).cuda()
+    P = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt)
+    S = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose="slabs")
+    T = dm.DoseMatrix(rp, cols, vals, spec.n_cols, fmt, transpose="slabs", autotune=True)
+    y_ref = P.spmv(x)
+    np.testing.assert_array_equal(_bits(S.spmv(x).cpu().numpy()), _bits(y_ref.cpu().numpy()))
+    Y = torch.full((spec.n_rows, 1), np.nan, device=dev)
+    plan = dm.BatchPlan([(S, x.view(-1, 1).contiguous(), Y)])
+    plan.launch()
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(_bits(Y[:, 0].cpu().numpy()), _bits(y_ref.cpu().numpy()))
+    plan.close()
+    np.testing.assert_array_equal(_bits(T.adjoint(v).cpu().numpy()), _bits(S.adjoint(v).cpu().numpy()))
+    for M in (P, S, T):
+        M.close()
