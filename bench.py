@@ -9,11 +9,12 @@ One step is one product over the whole matrix with the inputs resident in
 HBM.  Prints ONE JSON line.
 
 The same line carries, as variants: on the same matrix the FP32-vector
-product in FP16, BF16 and E4M3 values (32- and 16-bit indices) and the
-adjoints; on one clinical-scale beam (2,097,152 x 25,000) the FP32, 16-bit
-index, half/double and Single (FP32 values) products, the adjoint, one
-plan-optimisation iteration and the bias controls (beam along x, irregular
-row lengths); the batched robust-scenario product at full size (36 matrices,
+product in FP16, BF16 and E4M3 values (32- and 16-bit indices), the
+SELL-C-sigma products, and the adjoints over spot rows and over voxel slabs;
+on one clinical-scale beam (2,097,152 x 25,000) the FP32, 16-bit index,
+half/double and Single (FP32 values) products, the adjoint (both layouts), one
+plan-optimisation iteration (with either adjoint) and the bias controls (beam
+along x, irregular row lengths); the batched robust-scenario product at full size (36 matrices,
 4 spot-weight vectors each, one autotuned graph launch); the robust-plan step
 (9 scenarios x 4 beams on one dose grid, then the scenario epilogue); and a
 small cache-resident matrix.  Besides them: the roofline of the dominant
@@ -21,7 +22,8 @@ kernel (with the HBM traffic the committed rocprofv3 record gives while the
 kernel code is unchanged), the median and standard deviation of single
 launches, a read-only HBM ceiling probe, and the CPU oracle timed on the
 host, one thread and all threads.  --robust-step and --scenario-epilogue time
-only the robust-plan step or its epilogue; --quick skips the variants.
+only the robust-plan step or its epilogue; --part times one part alone (for
+profiling runs); --quick skips the variants.
 """
 from __future__ import annotations
 
