@@ -2,9 +2,10 @@
 makes the n-th device allocation after the variable takes that value fail
 with DOSE_ERR_OUT_OF_MEMORY.  For every n up to the first that lets the call
 succeed, the create call (a CSR matrix with its transpose in E4M3 with row
-scales, a SELL-C-sigma matrix with run-length indices, an autotuned batch
-plan) must fail with that status and leave the device's free memory where it
-was: whatever the call had allocated before the failure is freed."""
+scales, over spot rows or in voxel slabs, a SELL-C-sigma matrix with
+run-length indices, an autotuned batch plan) must fail with that status and
+leave the device's free memory where it was: whatever the call had allocated
+before the failure is freed."""
 import numpy as np
 import pytest
 import torch
@@ -61,6 +62,16 @@ def test_matrix_create_cleans_up(dev, monkeypatch):
     n = _sweep(lambda: dm.DoseMatrix(rp, cols, vals, n_cols, "fp8e4m3_rowscale", transpose=True), monkeypatch)
     print(f"matrix create: {n - 1} allocations failed in turn", flush=True)
     assert n > 8
+
+
+def test_matrix_create_slabs_cleans_up(dev, monkeypatch):
+    # the transpose in voxel slabs: sort, run-length encoding, placement,
+    # combine map and partition, each failing in turn
+    rp, cols, vals, n_cols = _matrix()
+    n = _sweep(lambda: dm.DoseMatrix(rp, cols, vals, n_cols, "fp8e4m3_rowscale", transpose="slabs"),
+               monkeypatch)
+    print(f"matrix create (voxel slabs): {n - 1} allocations failed in turn", flush=True)
+    assert n > 12
 
 
 def test_sell_create_cleans_up(dev, monkeypatch):
