@@ -723,10 +723,13 @@ def bench_scenarios(torch, dm, dosegen, args):
     FP64 scenario objectives, worst case and expectation).  Reports the step,
     the epilogue alone and its share; epilogue algorithmic bytes are the beam
     doses read once, p and w read once, scenario doses and seeds written once.
-    Also the step with the beam sum done by the products, and the step with
+    Also the step with the beam sum done by the products, the step with
     the beam products of one SELL-C-sigma plan launch (run-length indices;
     the largest relative difference of its scenario doses from the CSR
-    step's)."""
+    step's), the gradient half of the iteration (robust seeds, then the 36
+    adjoints in one adjoint plan over spot rows or voxel slabs, or issued one
+    by one) and one whole iteration (the SELL step and the slab gradient
+    plan)."""
     import numpy as np
     n_scen, n_beams = 9, 4
     specs = dosegen.robust_scenarios(args.scenario_scale, n_scen, n_beams)
@@ -735,11 +738,13 @@ def bench_scenarios(torch, dm, dosegen, args):
           for b in range(n_beams)]
     part = torch.empty(n_scen, n_beams, n, dtype=torch.float32, device="cuda")
     part_s = torch.empty_like(part)
-    mats, entries, sells, sentries, nnz_tot = [], [], [], [], 0
+    mats, entries, sells, sentries, slabs, nnz_tot = [], [], [], [], [], 0
     for m, sp in enumerate(specs):
         rp, cols, vals = dosegen.csr(sp)
-        A = dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16")
+        A = dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16", transpose=True)
         mats.append(A)
+        # the gradient's adjoints over A^T in voxel slabs
+        slabs.append(dm.DoseMatrix(rp, cols, vals, sp.n_cols, "fp16", transpose="slabs"))
         s, b = divmod(m, n_beams)
         entries.append((A, xs[b], part[s, b]))
         # the same beam products in SELL-C-sigma form (run-length indices)
@@ -796,6 +801,41 @@ def bench_scenarios(torch, dm, dosegen, args):
         dm.scenario_objective(part_s, p, w, prob=prob, d_out=d_s, seed=seed_s, out=out_s)
 
     ms_sell = time_launches(step_sell, reps, 3)
+    # the gradient half of a robust iteration: the robust seeds (expected
+    # objective), then the adjoint of every scenario's beam matrix with its
+    # scenario's seed (A^T over spot rows, or in voxel slabs); with the SELL
+    # step, one whole iteration
+    wseed = torch.empty_like(seed_s)
+    grads = [torch.empty(specs[m].n_cols, dtype=torch.float32, device="cuda") for m in range(len(specs))]
+    grads_s = [torch.empty_like(gm) for gm in grads]
+
+    def adjoints(ms_, gs_):
+        dm.robust_seed(seed_s, "expected", out=out_s, prob=prob, wseed=wseed)
+        for m, M in enumerate(ms_):
+            M.adjoint(wseed[m // n_beams], gs_[m])
+
+    # the 36 adjoints in one adjoint plan (one graph), or issued one by one
+    aplan_rows = dm.AdjointPlan([(M, wseed[m // n_beams], grads[m]) for m, M in enumerate(mats)])
+    aplan_slabs = dm.AdjointPlan([(M, wseed[m // n_beams], grads_s[m]) for m, M in enumerate(slabs)])
+
+    def gradient(ap):
+        dm.robust_seed(seed_s, "expected", out=out_s, prob=prob, wseed=wseed)
+        ap.launch()
+
+    ms_grad_calls = time_launches(lambda: adjoints(slabs, grads_s), reps, 3)
+    ms_grad_rows = time_launches(lambda: gradient(aplan_rows), reps, 3)
+    ms_grad_slabs = time_launches(lambda: gradient(aplan_slabs), reps, 3)
+
+    def iteration_sell_slabs():
+        step_sell()
+        gradient(aplan_slabs)
+
+    ms_iter = time_launches(iteration_sell_slabs, reps, 3)
+    torch.cuda.synchronize()
+    grad_rel = max(float(((a.double() - b.double()).abs().max() / b.double().abs().max().clamp_min(1e-300)))
+                   for a, b in zip(grads_s, grads))
+    aplan_rows.close()
+    aplan_slabs.close()
     step()
     step_sell()
     torch.cuda.synchronize()
@@ -808,14 +848,19 @@ def bench_scenarios(torch, dm, dosegen, args):
            "ms_step_beam_sum_in_products": round(ms_fused, 4), "beam_sum_in_products_bitwise_equal": fused_equal,
            "ms_step_sell_runs": round(ms_sell, 4), "sell_sigma": BATCH_SELL_SIGMA,
            "sell_max_rel_diff_of_scenario_doses": sell_rel,
+           "ms_gradient_seeds_and_adjoint_plan_spot_rows": round(ms_grad_rows, 4),
+           "ms_gradient_seeds_and_adjoint_plan_slabs": round(ms_grad_slabs, 4),
+           "ms_gradient_seeds_and_36_adjoint_calls_slabs": round(ms_grad_calls, 4),
+           "gradient_slabs_vs_spot_rows_max_rel_diff": grad_rel,
+           "ms_iteration_sell_step_and_slab_gradient_plan": round(ms_iter, 4),
            "epilogue_share": round(ms_epi / ms_step, 4), "scenarios": n_scen, "beams": n_beams,
            "voxels": n, "nnz": nnz_tot, "GNNZ_per_s": round(nnz_tot / (ms_step * 1e-3) / 1e9, 2),
            "epilogue_GBps_algorithmic": round(epi_bytes / (ms_epi * 1e-3) / 1e9, 1),
            "scenario_scale": args.scenario_scale}
     plan.close()
-    for A in mats:
+    for A in mats + slabs:
         A.close()
-    del entries, sentries, part, part_s, d_out, seed, d_f, d_s, seed_s
+    del entries, sentries, part, part_s, d_out, seed, d_f, d_s, seed_s, wseed, grads, grads_s
     torch.cuda.empty_cache()
     res["epilogue_full_grid"] = bench_epilogue_full(torch, dm, reps)
     return res

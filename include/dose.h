@@ -277,6 +277,32 @@ dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items
                                    void* hip_stream, dose_batch_plan* out);
 dose_status dose_batch_plan_launch(dose_batch_plan p, void* hip_stream);
 
+/* One item of an adjoint plan: g = A^T v for a matrix created with
+ * DOSE_CREATE_TRANSPOSE or DOSE_CREATE_TRANSPOSE_SLABS.  v: device, n_rows
+ * FP32; g: device, n_cols FP32, every entry written; both 4-byte aligned. */
+typedef struct {
+  dose_matrix A;
+  int32_t reserved; /* 0 */
+  const float* v;
+  float* g;
+} dose_adjoint_item;
+
+/* An adjoint plan: the gradients of every item (a robust objective needs the
+ * adjoint of every beam's matrix under every scenario each iteration, Sec. I,
+ * II-A) captured once into a HIP graph that dose_batch_plan_launch replays on
+ * hip_stream (asynchronous) and dose_batch_plan_destroy frees: E4M3 seeds
+ * scaled by the row scales, one launch over the row groups of every item's
+ * stored transpose, and (voxel slabs) each item's combine of its slab
+ * partials.  Each g is bitwise what dose_spmv_adjoint writes for its item.
+ * All items: the same value format, the same transpose layout (spot rows or
+ * voxel slabs) and device; an item's v and g apart; no g overlapping another
+ * item's v or g (items may share v).  The plan keeps the items' pointers
+ * (they must stay valid while it is used) and owns its scratch (n_rows
+ * floats per E4M3 item, one per slab row per slab item): overlapping
+ * launches of one plan race.  flags must be 0.  create is synchronous. */
+dose_status dose_adjoint_plan_create(const dose_adjoint_item* items, int32_t n_items, uint32_t flags,
+                                     void* hip_stream, dose_batch_plan* out);
+
 /* Scenario doses of a robust plan in one plan launch, the beam sum done by
  * the products themselves (Sec. I, II-A: the dose of every beam under every
  * scenario, every iteration; one matrix per beam, Sec. II-B).  Scenario s's

@@ -374,6 +374,27 @@ class BatchPlan:
             pass
 
 
+class AdjointPlan(BatchPlan):
+    """The adjoints g = A^T v of several matrices (each created with a
+    transpose, all of one layout and value format) captured into one HIP
+    graph and replayed by :meth:`launch`: entries are (DoseMatrix, v, g) with
+    v (n_rows,) and g (n_cols,) contiguous FP32 on the matrix's device; each
+    g gets the bits of ``A.adjoint(v)``."""
+
+    def __init__(self, entries, stream=None):
+        self._h = None
+        self._keep = list(entries)
+        arr = (_lib.AdjointItem * len(entries))()
+        for i, (A, v, g) in enumerate(entries):
+            _dev_ptr(v, A.n_rows, "v", A.device)
+            _dev_ptr(g, A.n_cols, "g", A.device)
+            arr[i] = _lib.AdjointItem(A.handle, 0, v.data_ptr(), g.data_ptr())
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().dose_adjoint_plan_create(arr, len(entries), 0, _stream_handle(stream),
+                                                        ctypes.byref(h)))
+        self._h = h
+
+
 class SellBatchPlan(BatchPlan):
     """Many SELL-C-sigma products in one launch, captured into a HIP graph:
     entries are (SellMatrix, x, y) with x (n_cols,) or (n_cols, n_rhs) and y

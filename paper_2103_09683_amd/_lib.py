@@ -57,6 +57,11 @@ class BatchItem(ctypes.Structure):
                 ("ldy", ctypes.c_int64)]
 
 
+class AdjointItem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("reserved", ctypes.c_int32), ("v", ctypes.c_void_p),
+                ("g", ctypes.c_void_p)]
+
+
 class SellBatchItem(ctypes.Structure):
     _fields_ = [("S", ctypes.c_void_p), ("n_rhs", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("x", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("y", ctypes.c_void_p),
@@ -90,6 +95,7 @@ SIGNATURES = {
     "dose_spmv_batched": ([ctypes.POINTER(BatchItem), _i32, _vp], _i32),
     "dose_batch_plan_create": ([ctypes.POINTER(BatchItem), _i32, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_batch_plan_launch": ([_vp, _vp], _i32),
+    "dose_adjoint_plan_create": ([ctypes.POINTER(AdjointItem), _i32, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_scenario_plan_create": ([_vp, _vp, _i32, _i32, _vp, _u32, _vp, ctypes.POINTER(_vp)], _i32),
     "dose_batch_plan_destroy": ([_vp], _i32),
     "dose_objective": ([_i64, _vp, _vp, _vp, _vp, _vp, _vp], _i32),

@@ -750,11 +750,30 @@ struct SellPlanLayer {
   DevBuf args, work, zero;
 };
 
+// Adjoint plans: an item's E4M3 seed scaling (u = fl32(s v)) before the
+// launch, and its slab combine (g from the slab rows' partials) after it.
+struct PlanScale {
+  int64_t n = 0;
+  const float *scale = nullptr, *v = nullptr;
+  float* u = nullptr;
+};
+struct PlanCombine {
+  const float* part = nullptr;
+  const uint32_t *ptr = nullptr, *rows = nullptr;
+  float* g = nullptr;
+  int64_t n_cols = 0;
+};
+
 struct dose_batch_plan_s {
   int device = 0;
   int vf = 0, sm = 0, n_rhs = 0, idx_bytes = 4;
+  std::vector<PlanScale> pre;     // adjoint plans: seed scaling before the layers
   std::vector<PlanLayer> layers;  // launched one after another (one layer for a batch plan)
   std::vector<SellPlanLayer> sell_layers;  // a SELL-C-sigma plan's launch (then layers is empty)
+  std::vector<PlanCombine> post;  // adjoint plans: slab combines after the layers
+  DevBuf post_items;              // the same as one table (one launch for all of them)
+  int64_t post_max_cols = 0;
+  DevBuf scratch;                 // adjoint plans: the scaled seeds and slab partials
   std::vector<std::unique_ptr<Partition>> parts;  // autotuned partitions the work lists were built from
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -912,6 +931,7 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
+  for (const PlanScale& c : p->pre) HIP_CHECK(launch_scale_vec(c.n, c.scale, c.v, c.u, s));
   for (const PlanLayer& L : p->layers) {
     BatchTable t{};
     t.args = L.args.get<SpmvArgs>();
@@ -928,6 +948,136 @@ void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
     t.xcd_blocks = L.xcd;
     HIP_CHECK(launch_sell_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, L.lds_bytes, s));
   }
+  if (p->post_items.get())
+    HIP_CHECK(launch_slab_combine_items(p->post_items.get<SlabCombineItem>(), static_cast<int32_t>(p->post.size()),
+                                        p->post_max_cols, s));
+  else
+    for (const PlanCombine& c : p->post)
+      HIP_CHECK(launch_slab_combine(false, c.part, c.ptr, c.rows, c.g, c.n_cols, s));
+}
+
+// The adjoint items of a plan: every matrix with a transpose of the same
+// layout (spot rows or voxel slabs), value format and device; v and g of an
+// item apart, no g shared or overlapping another item's (v may be shared).
+void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items) {
+  if (!items || n_items <= 0) fail(DOSE_ERR_INVALID_ARGUMENT, "no items");
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_adjoint_item& it = items[i];
+    const dose_matrix_s* m = it.A;
+    if (!m) fail(DOSE_ERR_INVALID_ARGUMENT, "item without matrix");
+    if (it.reserved != 0) fail(DOSE_ERR_INVALID_ARGUMENT, "reserved must be 0");
+    if (!m->has_t) fail(DOSE_ERR_NO_TRANSPOSE, "item matrix was created without a transpose");
+    if ((m->A.n_rows > 0 && !it.v) || (m->A.n_cols > 0 && !it.g)) fail(DOSE_ERR_INVALID_ARGUMENT, "null v or g");
+    if ((reinterpret_cast<uintptr_t>(it.v) | reinterpret_cast<uintptr_t>(it.g)) % 4 != 0)
+      fail(DOSE_ERR_INVALID_ARGUMENT, "v and g must be 4-byte aligned");
+    if (overlaps(it.v, m->A.n_rows * 4, it.g, m->A.n_cols * 4)) fail(DOSE_ERR_INVALID_ARGUMENT, "v and g overlap");
+    const dose_matrix_s* m0 = items[0].A;
+    if (m->vf != m0->vf) fail(DOSE_ERR_UNSUPPORTED, "items mix value formats");
+    if ((m->slab > 0) != (m0->slab > 0) || m->AT.idx_bytes != m0->AT.idx_bytes)
+      fail(DOSE_ERR_UNSUPPORTED, "items mix transpose layouts");
+    if (m->device != m0->device) fail(DOSE_ERR_INVALID_ARGUMENT, "items on different devices");
+    for (int32_t j = 0; j < i; ++j) {
+      if (overlaps(items[j].g, items[j].A->A.n_cols * 4, it.g, m->A.n_cols * 4))
+        fail(DOSE_ERR_INVALID_ARGUMENT, "items share outputs");
+      if (overlaps(items[j].v, items[j].A->A.n_rows * 4, it.g, m->A.n_cols * 4) ||
+          overlaps(it.v, m->A.n_rows * 4, items[j].g, items[j].A->A.n_cols * 4))
+        fail(DOSE_ERR_INVALID_ARGUMENT, "an item's g overlaps another item's v");
+    }
+  }
+}
+
+// The adjoints of all items: E4M3 seeds scaled into the plan's scratch, one
+// batched launch over the row groups of every item's transpose (writing g,
+// or the slab partials into the scratch), then the slab combines.
+dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_items, hipStream_t s) {
+  check_adjoint_items(items, n_items);
+  auto plan = std::make_unique<dose_batch_plan_s>();
+  const dose_matrix_s* m0 = items[0].A;
+  const bool fp8 = m0->vf == kFp8, slabs = m0->slab > 0;
+  plan->device = m0->device;
+  plan->vf = m0->vf;
+  plan->sm = fp8 ? kScaleNone : scale_mode_AT(m0);
+  plan->n_rhs = 1;
+  plan->idx_bytes = m0->AT.idx_bytes;
+  // scratch: per item, u (E4M3) then the partials (slabs), each 16-byte aligned
+  auto up4 = [](int64_t n) { return (n + 3) / 4 * 4; };
+  std::vector<int64_t> off_u(static_cast<size_t>(n_items)), off_p(static_cast<size_t>(n_items));
+  int64_t total = 0;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_matrix_s* m = items[i].A;
+    off_u[i] = total;
+    if (fp8) total += up4(m->A.n_rows);
+    off_p[i] = total;
+    if (slabs) total += up4(m->AT.n_rows);
+  }
+  if (total > 0) plan->scratch = DevBuf(static_cast<size_t>(total) * 4);
+  float* sc = plan->scratch.get<float>();
+  // row groups sized for the whole launch (a matrix's own are sized to fill
+  // the chip alone): plan-owned partitions where the sizes differ (the
+  // results do not depend on the partition)
+  int64_t nnz_all = 0;
+  for (int32_t i = 0; i < n_items; ++i) nnz_all += items[i].A->AT.nnz;
+  const int g_plan = default_group_nnz(nnz_all, plan->device);
+  std::map<const dose_matrix_s*, const Partition*> part_of;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_matrix_s* m = items[i].A;
+    if (part_of.count(m)) continue;
+    const Partition* P = &m->AT.part;
+    if (P->group_nnz != g_plan && m->AT.nnz > 0) {
+      plan->parts.push_back(std::make_unique<Partition>(make_partition(m->AT, g_plan, s)));
+      P = plan->parts.back().get();
+    }
+    part_of[m] = P;
+  }
+  PlanLayer L;
+  std::vector<SpmvArgs> args(static_cast<size_t>(n_items));
+  std::vector<GroupDesc> work;
+  for (int32_t i = 0; i < n_items; ++i) {
+    const dose_adjoint_item& it = items[i];
+    const dose_matrix_s* m = it.A;
+    const float* x = it.v;
+    if (fp8 && m->A.n_rows > 0) {
+      PlanScale c;
+      c.n = m->A.n_rows, c.scale = m->row_scale.get<float>(), c.v = it.v, c.u = sc + off_u[i];
+      plan->pre.push_back(c);
+      x = c.u;
+    }
+    float* y = slabs ? sc + off_p[i] : it.g;
+    const Partition& P = *part_of.at(m);
+    args[i] = make_args(m, m->AT, P, plan->sm, 1, x, y);
+    L.lds_floats = std::max(L.lds_floats, args[i].win_floats);
+    for (GroupDesc g : P.h_groups) {
+      g.item = static_cast<uint32_t>(i);
+      work.push_back(g);
+    }
+    if (slabs && m->A.n_cols > 0) {
+      PlanCombine c;
+      c.part = y, c.ptr = m->comb_ptr.get<uint32_t>(), c.rows = m->comb_rows.get<uint32_t>(), c.g = it.g;
+      c.n_cols = m->A.n_cols;
+      plan->post.push_back(c);
+    }
+  }
+  L.n_work = static_cast<int64_t>(work.size());
+  if (L.n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
+  L.args = DevBuf(args.size() * sizeof(SpmvArgs));
+  L.work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
+  HIP_CHECK(hipMemcpyAsync(L.args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
+  if (!work.empty())
+    HIP_CHECK(hipMemcpyAsync(L.work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+  // the combines in one launch (the kernel takes up to 65,535 items)
+  if (!plan->post.empty() && plan->post.size() <= 65535) {
+    std::vector<SlabCombineItem> ci;
+    for (const PlanCombine& c : plan->post) {
+      ci.push_back(SlabCombineItem{c.part, c.ptr, c.rows, c.g, c.n_cols});
+      plan->post_max_cols = std::max(plan->post_max_cols, c.n_cols);
+    }
+    plan->post_items = DevBuf(ci.size() * sizeof(SlabCombineItem));
+    HIP_CHECK(hipMemcpyAsync(plan->post_items.get(), ci.data(), ci.size() * sizeof(SlabCombineItem),
+                             hipMemcpyHostToDevice, s));
+  }
+  HIP_CHECK(hipStreamSynchronize(s));
+  plan->layers.push_back(std::move(L));
+  return plan.release();
 }
 
 // Captures a built plan's launches into its HIP graph.
@@ -1622,6 +1772,20 @@ dose_status dose_batch_plan_create(const dose_batch_item* items, int32_t n_items
     check_items(items, n_items);
     DeviceGuard g(items[0].A->device);
     std::unique_ptr<dose_batch_plan_s> p(build_plan(items, n_items, flags, as_stream(hip_stream)));
+    capture_plan(p.get());
+    *out = p.release();
+  });
+}
+
+dose_status dose_adjoint_plan_create(const dose_adjoint_item* items, int32_t n_items, uint32_t flags,
+                                     void* hip_stream, dose_batch_plan* out) {
+  return guarded([&] {
+    if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
+    *out = nullptr;
+    if (flags != 0) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
+    check_adjoint_items(items, n_items);
+    DeviceGuard g(items[0].A->device);
+    std::unique_ptr<dose_batch_plan_s> p(build_adjoint_plan(items, n_items, as_stream(hip_stream)));
     capture_plan(p.get());
     *out = p.release();
   });

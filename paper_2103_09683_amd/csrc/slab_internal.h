@@ -42,4 +42,15 @@ hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows
 hipError_t launch_slab_combine(bool f64, const void* part, const uint32_t* ptr, const uint32_t* rows, void* g,
                                int64_t n_cols, hipStream_t s);
 
+// The FP32 combines of several slab adjoints in one launch (adjoint plans):
+// item i (items in device memory) as launch_slab_combine would do it.
+struct SlabCombineItem {
+  const float* part;
+  const uint32_t* ptr;
+  const uint32_t* rows;
+  float* g;
+  int64_t n_cols;
+};
+hipError_t launch_slab_combine_items(const SlabCombineItem* items, int32_t n_items, int64_t max_cols, hipStream_t s);
+
 }  // namespace dose

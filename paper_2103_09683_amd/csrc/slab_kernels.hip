@@ -42,11 +42,9 @@ __global__ void k_slab_gather(const uint32_t* __restrict__ perm, const uint32_t*
 // issued eight at a time (the row indices, then the partials) so that a spot
 // of n slabs waits for about n / 4 round trips to memory instead of 2 n.
 template <typename V>
-__global__ void k_slab_combine(const V* __restrict__ part, const uint32_t* __restrict__ ptr,
-                               const uint32_t* __restrict__ rows, V* __restrict__ g, int64_t n_cols) {
+__device__ __forceinline__ void combine_spot(const V* __restrict__ part, const uint32_t* __restrict__ ptr,
+                                             const uint32_t* __restrict__ rows, V* __restrict__ g, int64_t j) {
   constexpr int kBatch = 8;
-  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j >= n_cols) return;
   const uint32_t end = ptr[j + 1];
   uint32_t k = ptr[j];
   V acc = V(0);
@@ -62,6 +60,20 @@ __global__ void k_slab_combine(const V* __restrict__ part, const uint32_t* __res
   }
   for (; k < end; ++k) acc = acc + part[rows[k]];
   g[j] = acc;
+}
+
+template <typename V>
+__global__ void k_slab_combine(const V* __restrict__ part, const uint32_t* __restrict__ ptr,
+                               const uint32_t* __restrict__ rows, V* __restrict__ g, int64_t n_cols) {
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < n_cols) combine_spot(part, ptr, rows, g, j);
+}
+
+// Item blockIdx.y of an adjoint plan; its spots in blocks along x.
+__global__ void k_slab_combine_items(const SlabCombineItem* __restrict__ items) {
+  const SlabCombineItem it = items[blockIdx.y];
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j < it.n_cols) combine_spot(it.part, it.ptr, it.rows, it.g, j);
 }
 
 }  // namespace
@@ -95,6 +107,14 @@ hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows
   else
     hipLaunchKernelGGL(k_slab_gather<uint16_t>, grid, block, 0, s, perm, rows, keys, n_cols, slab, slab_off,
                        static_cast<const uint16_t*>(codes_in), static_cast<uint16_t*>(codes_out), col_out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_slab_combine_items(const SlabCombineItem* items, int32_t n_items, int64_t max_cols, hipStream_t s) {
+  if (n_items <= 0 || max_cols <= 0) return hipSuccess;
+  if (n_items > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_slab_combine_items, dim3(slab_blocks(max_cols, 256), static_cast<unsigned>(n_items)),
+                     dim3(256), 0, s, items);
   return hipGetLastError();
 }
 

@@ -978,6 +978,12 @@ hipError_t launch_spmv_batched(int vf, int scale_mode, int n_rhs, int accumulate
     return launch_rhs_batched<kFp8, kScaleRow>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
   if (vf == kFp8 && scale_mode == kScaleCol)
     return launch_rhs_batched<kFp8, kScaleCol>(n_rhs, accumulate, idx_bytes, t, n_work, lds_floats, s);
+  if (vf == kFp8 && scale_mode == kScaleNone && n_rhs == 1 && !accumulate) {
+    // E4M3 codes without their scale (adjoint plans, whose seeds carry the row scales)
+    launch_ix_batched<kFp8, kScaleNone, 1, false>(idx_bytes, t, n_work, static_cast<size_t>(lds_floats) * sizeof(float),
+                                                   s);
+    return hipGetLastError();
+  }
   return hipErrorInvalidValue;
 }
 

@@ -19,6 +19,7 @@ STRUCTS = {
     "dose_batch_item": _lib.BatchItem,
     "dose_sell_info_t": _lib.SellInfo,
     "dose_sell_batch_item": _lib.SellBatchItem,
+    "dose_adjoint_item": _lib.AdjointItem,
 }
 
 
