@@ -768,6 +768,8 @@ struct dose_batch_plan_s {
   int device = 0;
   int vf = 0, sm = 0, n_rhs = 0, idx_bytes = 4;
   std::vector<PlanScale> pre;     // adjoint plans: seed scaling before the layers
+  DevBuf pre_items;               // the same as one table (one launch for all of them)
+  int64_t pre_max_n = 0;
   std::vector<PlanLayer> layers;  // launched one after another (one layer for a batch plan)
   std::vector<SellPlanLayer> sell_layers;  // a SELL-C-sigma plan's launch (then layers is empty)
   std::vector<PlanCombine> post;  // adjoint plans: slab combines after the layers
@@ -931,7 +933,10 @@ dose_batch_plan_s* build_plan(const dose_batch_item* items, int32_t n_items, uin
 }
 
 void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
-  for (const PlanScale& c : p->pre) HIP_CHECK(launch_scale_vec(c.n, c.scale, c.v, c.u, s));
+  if (p->pre_items.get())
+    HIP_CHECK(launch_scale_items(p->pre_items.get<ScaleItem>(), static_cast<int32_t>(p->pre.size()), p->pre_max_n, s));
+  else
+    for (const PlanScale& c : p->pre) HIP_CHECK(launch_scale_vec(c.n, c.scale, c.v, c.u, s));
   for (const PlanLayer& L : p->layers) {
     BatchTable t{};
     t.args = L.args.get<SpmvArgs>();
@@ -1064,7 +1069,18 @@ dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_
   HIP_CHECK(hipMemcpyAsync(L.args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
   if (!work.empty())
     HIP_CHECK(hipMemcpyAsync(L.work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
-  // the combines in one launch (the kernel takes up to 65,535 items)
+  // the seed scalings, and the combines, in one launch each (the kernels
+  // take up to 65,535 items)
+  if (!plan->pre.empty() && plan->pre.size() <= 65535) {
+    std::vector<ScaleItem> si;
+    for (const PlanScale& c : plan->pre) {
+      si.push_back(ScaleItem{c.scale, c.v, c.u, c.n});
+      plan->pre_max_n = std::max(plan->pre_max_n, c.n);
+    }
+    plan->pre_items = DevBuf(si.size() * sizeof(ScaleItem));
+    HIP_CHECK(hipMemcpyAsync(plan->pre_items.get(), si.data(), si.size() * sizeof(ScaleItem), hipMemcpyHostToDevice,
+                             s));
+  }
   if (!plan->post.empty() && plan->post.size() <= 65535) {
     std::vector<SlabCombineItem> ci;
     for (const PlanCombine& c : plan->post) {

@@ -53,4 +53,15 @@ struct SlabCombineItem {
 };
 hipError_t launch_slab_combine_items(const SlabCombineItem* items, int32_t n_items, int64_t max_cols, hipStream_t s);
 
+// The E4M3 seed scalings of an adjoint plan in one launch: item i (items in
+// device memory) writes u[k] = fl32(scale[k] * v[k]) for k < n, as
+// launch_scale_vec does.
+struct ScaleItem {
+  const float* scale;
+  const float* v;
+  float* u;
+  int64_t n;
+};
+hipError_t launch_scale_items(const ScaleItem* items, int32_t n_items, int64_t max_n, hipStream_t s);
+
 }  // namespace dose

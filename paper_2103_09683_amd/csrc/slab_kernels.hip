@@ -12,6 +12,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 namespace dose {
 namespace {
 
@@ -76,7 +78,25 @@ __global__ void k_slab_combine_items(const SlabCombineItem* __restrict__ items) 
   if (j < it.n_cols) combine_spot(it.part, it.ptr, it.rows, it.g, j);
 }
 
+// Item blockIdx.y of an adjoint plan's seed scalings, its elements strided
+// over the blocks along x.
+__global__ __launch_bounds__(256) void k_scale_items(const ScaleItem* __restrict__ items) {
+  const ScaleItem it = items[blockIdx.y];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < it.n; k += stride)
+    it.u[k] = it.scale[k] * it.v[k];
+}
+
 }  // namespace
+
+hipError_t launch_scale_items(const ScaleItem* items, int32_t n_items, int64_t max_n, hipStream_t s) {
+  if (n_items <= 0 || max_n <= 0) return hipSuccess;
+  if (n_items > 65535) return hipErrorInvalidValue;
+  const int64_t bx = std::min<int64_t>((max_n + 1023) / 1024, 4096);
+  hipLaunchKernelGGL(k_scale_items, dim3(static_cast<unsigned>(bx), static_cast<unsigned>(n_items)), dim3(256), 0, s,
+                     items);
+  return hipGetLastError();
+}
 
 hipError_t launch_slab_keys(const uint32_t* rows, const uint32_t* cols, uint32_t slab, uint32_t n_cols,
                             int64_t n, uint32_t* keys, hipStream_t s) {
