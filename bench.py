@@ -817,6 +817,7 @@ def bench_scenarios(torch, dm, dosegen, args):
     # the 36 adjoints in one adjoint plan (one graph), or issued one by one
     aplan_rows = dm.AdjointPlan([(M, wseed[m // n_beams], grads[m]) for m, M in enumerate(mats)])
     aplan_slabs = dm.AdjointPlan([(M, wseed[m // n_beams], grads_s[m]) for m, M in enumerate(slabs)])
+    aplan_tuned = dm.AdjointPlan([(M, wseed[m // n_beams], grads_s[m]) for m, M in enumerate(slabs)], autotune=True)
 
     def gradient(ap):
         dm.robust_seed(seed_s, "expected", out=out_s, prob=prob, wseed=wseed)
@@ -825,6 +826,7 @@ def bench_scenarios(torch, dm, dosegen, args):
     ms_grad_calls = time_launches(lambda: adjoints(slabs, grads_s), reps, 3)
     ms_grad_rows = time_launches(lambda: gradient(aplan_rows), reps, 3)
     ms_grad_slabs = time_launches(lambda: gradient(aplan_slabs), reps, 3)
+    ms_grad_tuned = time_launches(lambda: gradient(aplan_tuned), reps, 3)
 
     def iteration_sell_slabs():
         step_sell()
@@ -836,6 +838,7 @@ def bench_scenarios(torch, dm, dosegen, args):
                    for a, b in zip(grads_s, grads))
     aplan_rows.close()
     aplan_slabs.close()
+    aplan_tuned.close()
     step()
     step_sell()
     torch.cuda.synchronize()
@@ -850,6 +853,7 @@ def bench_scenarios(torch, dm, dosegen, args):
            "sell_max_rel_diff_of_scenario_doses": sell_rel,
            "ms_gradient_seeds_and_adjoint_plan_spot_rows": round(ms_grad_rows, 4),
            "ms_gradient_seeds_and_adjoint_plan_slabs": round(ms_grad_slabs, 4),
+           "ms_gradient_seeds_and_adjoint_plan_slabs_autotuned": round(ms_grad_tuned, 4),
            "ms_gradient_seeds_and_36_adjoint_calls_slabs": round(ms_grad_calls, 4),
            "gradient_slabs_vs_spot_rows_max_rel_diff": grad_rel,
            "ms_iteration_sell_step_and_slab_gradient_plan": round(ms_iter, 4),

@@ -299,7 +299,12 @@ typedef struct {
  * item's v or g (items may share v).  The plan keeps the items' pointers
  * (they must stay valid while it is used) and owns its scratch (n_rows
  * floats per E4M3 item, one per slab row per slab item): overlapping
- * launches of one plan race.  flags must be 0.  create is synchronous. */
+ * launches of one plan race.  The row groups are sized for the whole launch
+ * (plan-owned partitions); with flags DOSE_PLAN_AUTOTUNE the launch is timed
+ * on hip_stream under groups of 8K, 16K, 32K and 64K entries and the fastest
+ * kept (speed only; the items' g and the plan's scratch are written by the
+ * timing runs).  Other flags: DOSE_ERR_INVALID_ARGUMENT.  create is
+ * synchronous. */
 dose_status dose_adjoint_plan_create(const dose_adjoint_item* items, int32_t n_items, uint32_t flags,
                                      void* hip_stream, dose_batch_plan* out);
 

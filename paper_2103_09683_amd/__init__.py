@@ -379,9 +379,10 @@ class AdjointPlan(BatchPlan):
     transpose, all of one layout and value format) captured into one HIP
     graph and replayed by :meth:`launch`: entries are (DoseMatrix, v, g) with
     v (n_rows,) and g (n_cols,) contiguous FP32 on the matrix's device; each
-    g gets the bits of ``A.adjoint(v)``."""
+    g gets the bits of ``A.adjoint(v)``.  ``autotune=True`` times the launch
+    under candidate row-group sizes first (speed only)."""
 
-    def __init__(self, entries, stream=None):
+    def __init__(self, entries, autotune: bool = False, stream=None):
         self._h = None
         self._keep = list(entries)
         arr = (_lib.AdjointItem * len(entries))()
@@ -390,8 +391,9 @@ class AdjointPlan(BatchPlan):
             _dev_ptr(g, A.n_cols, "g", A.device)
             arr[i] = _lib.AdjointItem(A.handle, 0, v.data_ptr(), g.data_ptr())
         h = ctypes.c_void_p()
-        _lib.check(_lib.load().dose_adjoint_plan_create(arr, len(entries), 0, _stream_handle(stream),
-                                                        ctypes.byref(h)))
+        _lib.check(_lib.load().dose_adjoint_plan_create(arr, len(entries),
+                                                        _lib.PLAN_AUTOTUNE if autotune else 0,
+                                                        _stream_handle(stream), ctypes.byref(h)))
         self._h = h
 
 

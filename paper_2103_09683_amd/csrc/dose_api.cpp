@@ -993,8 +993,13 @@ void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items) {
 
 // The adjoints of all items: E4M3 seeds scaled into the plan's scratch, one
 // batched launch over the row groups of every item's transpose (writing g,
-// or the slab partials into the scratch), then the slab combines.
-dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_items, hipStream_t s) {
+// or the slab partials into the scratch), then the slab combines.  The row
+// groups are sized for the whole launch (a matrix's own are sized to fill the
+// chip alone): plan-owned partitions where the sizes differ, the results
+// not depending on the partition; with DOSE_PLAN_AUTOTUNE the launch is
+// timed under 8K-64K-entry groups and the fastest kept.
+dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_items, uint32_t flags,
+                                      hipStream_t s) {
   check_adjoint_items(items, n_items);
   auto plan = std::make_unique<dose_batch_plan_s>();
   const dose_matrix_s* m0 = items[0].A;
@@ -1007,68 +1012,109 @@ dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_
   // scratch: per item, u (E4M3) then the partials (slabs), each 16-byte aligned
   auto up4 = [](int64_t n) { return (n + 3) / 4 * 4; };
   std::vector<int64_t> off_u(static_cast<size_t>(n_items)), off_p(static_cast<size_t>(n_items));
-  int64_t total = 0;
+  int64_t total = 0, nnz_all = 0;
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_matrix_s* m = items[i].A;
     off_u[i] = total;
     if (fp8) total += up4(m->A.n_rows);
     off_p[i] = total;
     if (slabs) total += up4(m->AT.n_rows);
+    nnz_all += m->AT.nnz;
   }
   if (total > 0) plan->scratch = DevBuf(static_cast<size_t>(total) * 4);
   float* sc = plan->scratch.get<float>();
-  // row groups sized for the whole launch (a matrix's own are sized to fill
-  // the chip alone): plan-owned partitions where the sizes differ (the
-  // results do not depend on the partition)
-  int64_t nnz_all = 0;
-  for (int32_t i = 0; i < n_items; ++i) nnz_all += items[i].A->AT.nnz;
-  const int g_plan = default_group_nnz(nnz_all, plan->device);
-  std::map<const dose_matrix_s*, const Partition*> part_of;
-  for (int32_t i = 0; i < n_items; ++i) {
-    const dose_matrix_s* m = items[i].A;
-    if (part_of.count(m)) continue;
-    const Partition* P = &m->AT.part;
-    if (P->group_nnz != g_plan && m->AT.nnz > 0) {
-      plan->parts.push_back(std::make_unique<Partition>(make_partition(m->AT, g_plan, s)));
-      P = plan->parts.back().get();
-    }
-    part_of[m] = P;
-  }
-  PlanLayer L;
-  std::vector<SpmvArgs> args(static_cast<size_t>(n_items));
-  std::vector<GroupDesc> work;
+  // each item's product input and output, its seed scaling and its combine
+  std::vector<const float*> xs(static_cast<size_t>(n_items));
+  std::vector<float*> ys(static_cast<size_t>(n_items));
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_adjoint_item& it = items[i];
     const dose_matrix_s* m = it.A;
-    const float* x = it.v;
+    xs[i] = it.v;
     if (fp8 && m->A.n_rows > 0) {
       PlanScale c;
       c.n = m->A.n_rows, c.scale = m->row_scale.get<float>(), c.v = it.v, c.u = sc + off_u[i];
       plan->pre.push_back(c);
-      x = c.u;
+      xs[i] = c.u;
     }
-    float* y = slabs ? sc + off_p[i] : it.g;
-    const Partition& P = *part_of.at(m);
-    args[i] = make_args(m, m->AT, P, plan->sm, 1, x, y);
-    L.lds_floats = std::max(L.lds_floats, args[i].win_floats);
-    for (GroupDesc g : P.h_groups) {
-      g.item = static_cast<uint32_t>(i);
-      work.push_back(g);
-    }
+    ys[i] = slabs ? sc + off_p[i] : it.g;
     if (slabs && m->A.n_cols > 0) {
       PlanCombine c;
-      c.part = y, c.ptr = m->comb_ptr.get<uint32_t>(), c.rows = m->comb_rows.get<uint32_t>(), c.g = it.g;
+      c.part = ys[i], c.ptr = m->comb_ptr.get<uint32_t>(), c.rows = m->comb_rows.get<uint32_t>(), c.g = it.g;
       c.n_cols = m->A.n_cols;
       plan->post.push_back(c);
     }
   }
-  L.n_work = static_cast<int64_t>(work.size());
-  if (L.n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
-  L.args = DevBuf(args.size() * sizeof(SpmvArgs));
-  L.work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
-  HIP_CHECK(hipMemcpyAsync(L.args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
-  if (!work.empty())
-    HIP_CHECK(hipMemcpyAsync(L.work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+  // the launch under row groups of about g entries (partitions the plan owns
+  // go to `parts`)
+  auto layer_for = [&](int g, std::vector<std::unique_ptr<Partition>>& parts) {
+    std::map<const dose_matrix_s*, const Partition*> part_of;
+    PlanLayer L;
+    std::vector<SpmvArgs> args(static_cast<size_t>(n_items));
+    std::vector<GroupDesc> work;
+    for (int32_t i = 0; i < n_items; ++i) {
+      const dose_matrix_s* m = items[i].A;
+      if (!part_of.count(m)) {
+        const Partition* P = &m->AT.part;
+        if (P->group_nnz != g && m->AT.nnz > 0) {
+          parts.push_back(std::make_unique<Partition>(make_partition(m->AT, g, s)));
+          P = parts.back().get();
+        }
+        part_of[m] = P;
+      }
+      const Partition& P = *part_of.at(m);
+      args[i] = make_args(m, m->AT, P, plan->sm, 1, xs[i], ys[i]);
+      L.lds_floats = std::max(L.lds_floats, args[i].win_floats);
+      for (GroupDesc gd : P.h_groups) {
+        gd.item = static_cast<uint32_t>(i);
+        work.push_back(gd);
+      }
+    }
+    L.n_work = static_cast<int64_t>(work.size());
+    if (L.n_work > int64_t{0x7fffffff}) fail(DOSE_ERR_UNSUPPORTED, "too many row groups for one launch");
+    L.args = DevBuf(args.size() * sizeof(SpmvArgs));
+    L.work = DevBuf(std::max<size_t>(1, work.size()) * sizeof(GroupDesc));
+    HIP_CHECK(hipMemcpyAsync(L.args.get(), args.data(), args.size() * sizeof(SpmvArgs), hipMemcpyHostToDevice, s));
+    if (!work.empty())
+      HIP_CHECK(hipMemcpyAsync(L.work.get(), work.data(), work.size() * sizeof(GroupDesc), hipMemcpyHostToDevice, s));
+    HIP_CHECK(hipStreamSynchronize(s));
+    return L;
+  };
+  if (!(flags & DOSE_PLAN_AUTOTUNE)) {
+    plan->layers.push_back(layer_for(default_group_nnz(nnz_all, plan->device), plan->parts));
+  } else {
+    // median of 6 timed launches after one untimed, per candidate size
+    hipEvent_t e0, e1;
+    HIP_CHECK(hipEventCreate(&e0));
+    HIP_CHECK(hipEventCreate(&e1));
+    double best_t = 1e30;
+    for (int g = 8192; g <= 65536; g *= 2) {
+      std::vector<std::unique_ptr<Partition>> parts;
+      PlanLayer L = layer_for(g, parts);
+      BatchTable t{};
+      t.args = L.args.get<SpmvArgs>();
+      t.work = L.work.get<GroupDesc>();
+      std::vector<float> ts;
+      for (int rep = 0; rep < 7; ++rep) {
+        HIP_CHECK(hipEventRecord(e0, s));
+        HIP_CHECK(launch_spmv_batched(plan->vf, plan->sm, 1, 0, plan->idx_bytes, t, L.n_work, L.lds_floats, s));
+        HIP_CHECK(hipEventRecord(e1, s));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) ts.push_back(ms);
+      }
+      std::sort(ts.begin(), ts.end());
+      const double t_med = ts[ts.size() / 2];
+      if (t_med < best_t) {
+        best_t = t_med;
+        plan->layers.clear();
+        plan->layers.push_back(std::move(L));
+        plan->parts = std::move(parts);
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
   // the seed scalings, and the combines, in one launch each (the kernels
   // take up to 65,535 items)
   if (!plan->pre.empty() && plan->pre.size() <= 65535) {
@@ -1092,7 +1138,6 @@ dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_
                              hipMemcpyHostToDevice, s));
   }
   HIP_CHECK(hipStreamSynchronize(s));
-  plan->layers.push_back(std::move(L));
   return plan.release();
 }
 
@@ -1798,10 +1843,10 @@ dose_status dose_adjoint_plan_create(const dose_adjoint_item* items, int32_t n_i
   return guarded([&] {
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
     *out = nullptr;
-    if (flags != 0) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
+    if (flags & ~static_cast<uint32_t>(DOSE_PLAN_AUTOTUNE)) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
     check_adjoint_items(items, n_items);
     DeviceGuard g(items[0].A->device);
-    std::unique_ptr<dose_batch_plan_s> p(build_adjoint_plan(items, n_items, as_stream(hip_stream)));
+    std::unique_ptr<dose_batch_plan_s> p(build_adjoint_plan(items, n_items, flags, as_stream(hip_stream)));
     capture_plan(p.get());
     *out = p.release();
   });

@@ -79,6 +79,25 @@ def test_adjoint_plan_bits_and_replays(fmt, transpose, dev):
         A.close()
 
 
+@pytest.mark.parametrize("fmt,transpose", [("fp16", "slabs"), ("fp8e4m3_rowscale", True)])
+def test_adjoint_plan_autotune(fmt, transpose, dev):
+    """DOSE_PLAN_AUTOTUNE picks the row-group size by timing the launch; the
+    bits stay those of the plain adjoints."""
+    mats, _ = _matrices(fmt, transpose)
+    vs = [torch.from_numpy(dosegen.signed_values(dosegen.SEED0, 60 + i, A.n_rows)).cuda() for i, A in enumerate(mats)]
+    gs = [torch.empty(A.n_cols, device=dev) for A in mats]
+    plan = dm.AdjointPlan(list(zip(mats, vs, gs)), autotune=True)
+    for g in gs:
+        g.fill_(np.nan)
+    plan.launch()
+    torch.cuda.synchronize()
+    for i, (A, v, g) in enumerate(zip(mats, vs, gs)):
+        assert torch.equal(_bits(g), _bits(A.adjoint(v))), i
+    plan.close()
+    for A in mats:
+        A.close()
+
+
 def test_adjoint_plan_errors_and_empty(dev):
     mats, _ = _matrices("fp16", "slabs", n=2)
     rows, _ = _matrices("fp16", True, n=1)
@@ -109,7 +128,7 @@ def test_adjoint_plan_errors_and_empty(dev):
     arr = (_lib.AdjointItem * 1)()
     arr[0] = _lib.AdjointItem(mats[0].handle, 0, v[0].data_ptr(), g[0].data_ptr())
     h = dm.ctypes.c_void_p()
-    assert _lib.load().dose_adjoint_plan_create(arr, 1, 1, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
+    assert _lib.load().dose_adjoint_plan_create(arr, 1, 2, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
     arr[0] = _lib.AdjointItem(mats[0].handle, 1, v[0].data_ptr(), g[0].data_ptr())
     assert _lib.load().dose_adjoint_plan_create(arr, 1, 0, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
     assert _lib.load().dose_adjoint_plan_create(arr, 0, 0, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
