@@ -264,7 +264,9 @@ dose_status dose_spmv_batched(const dose_batch_item* items, int32_t n_items, voi
  * Sec. I, II-A): the work list of a batch is built once on the device and the
  * launch is captured into a HIP graph that dose_batch_plan_launch replays on
  * hip_stream (asynchronous).  The plan keeps the items' pointers: their x and
- * y must stay valid while the plan is used.  With DOSE_PLAN_AUTOTUNE each
+ * y, and the matrices themselves (their device streams), must stay valid while
+ * the plan is used; dose_matrix_set_partition on them does not affect it
+ * (the plan holds its own copies of the row-group descriptors).  With DOSE_PLAN_AUTOTUNE each
  * distinct matrix is timed under candidate row-group sizes on `hip_stream`
  * (x/y of the items are used as scratch for the timing runs; the choice
  * persists in the text file named by DOSE_TUNE_CACHE, if set) and the plan
@@ -297,7 +299,8 @@ typedef struct {
  * All items: the same value format, the same transpose layout (spot rows or
  * voxel slabs) and device; an item's v and g apart; no g overlapping another
  * item's v or g (items may share v).  The plan keeps the items' pointers
- * (they must stay valid while it is used) and owns its scratch (n_rows
+ * (v, g and the matrices must stay valid while it is used; re-partitioning
+ * a matrix does not affect it) and owns its scratch (n_rows
  * floats per E4M3 item, one per slab row per slab item): overlapping
  * launches of one plan race.  The row groups are sized for the whole launch
  * (plan-owned partitions); with flags DOSE_PLAN_AUTOTUNE the launch is timed
