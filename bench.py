@@ -728,8 +728,8 @@ def bench_scenarios(torch, dm, dosegen, args):
     the largest relative difference of its scenario doses from the CSR
     step's), the gradient half of the iteration (robust seeds, then the 36
     adjoints in one adjoint plan over spot rows or voxel slabs, or issued one
-    by one) and one whole iteration (the SELL step and the slab gradient
-    plan)."""
+    by one, or with each beam's gradient summed over the scenarios by the
+    plan) and one whole iteration (the SELL step and that last plan)."""
     import numpy as np
     n_scen, n_beams = 9, 4
     specs = dosegen.robust_scenarios(args.scenario_scale, n_scen, n_beams)
@@ -818,6 +818,10 @@ def bench_scenarios(torch, dm, dosegen, args):
     aplan_rows = dm.AdjointPlan([(M, wseed[m // n_beams], grads[m]) for m, M in enumerate(mats)])
     aplan_slabs = dm.AdjointPlan([(M, wseed[m // n_beams], grads_s[m]) for m, M in enumerate(slabs)])
     aplan_tuned = dm.AdjointPlan([(M, wseed[m // n_beams], grads_s[m]) for m, M in enumerate(slabs)], autotune=True)
+    # each beam's gradient summed over the scenarios by the plan itself
+    beam_grads = [torch.empty(specs[b].n_cols, dtype=torch.float32, device="cuda") for b in range(n_beams)]
+    aplan_acc = dm.AdjointPlan([(M, wseed[m // n_beams], beam_grads[m % n_beams]) for m, M in enumerate(slabs)],
+                               accumulate=True)
 
     def gradient(ap):
         dm.robust_seed(seed_s, "expected", out=out_s, prob=prob, wseed=wseed)
@@ -827,10 +831,11 @@ def bench_scenarios(torch, dm, dosegen, args):
     ms_grad_rows = time_launches(lambda: gradient(aplan_rows), reps, 3)
     ms_grad_slabs = time_launches(lambda: gradient(aplan_slabs), reps, 3)
     ms_grad_tuned = time_launches(lambda: gradient(aplan_tuned), reps, 3)
+    ms_grad_acc = time_launches(lambda: gradient(aplan_acc), reps, 3)
 
     def iteration_sell_slabs():
         step_sell()
-        gradient(aplan_slabs)
+        gradient(aplan_acc)
 
     ms_iter = time_launches(iteration_sell_slabs, reps, 3)
     torch.cuda.synchronize()
@@ -839,6 +844,7 @@ def bench_scenarios(torch, dm, dosegen, args):
     aplan_rows.close()
     aplan_slabs.close()
     aplan_tuned.close()
+    aplan_acc.close()
     step()
     step_sell()
     torch.cuda.synchronize()
@@ -854,9 +860,10 @@ def bench_scenarios(torch, dm, dosegen, args):
            "ms_gradient_seeds_and_adjoint_plan_spot_rows": round(ms_grad_rows, 4),
            "ms_gradient_seeds_and_adjoint_plan_slabs": round(ms_grad_slabs, 4),
            "ms_gradient_seeds_and_adjoint_plan_slabs_autotuned": round(ms_grad_tuned, 4),
+           "ms_gradient_seeds_and_adjoint_plan_slabs_beam_sums": round(ms_grad_acc, 4),
            "ms_gradient_seeds_and_36_adjoint_calls_slabs": round(ms_grad_calls, 4),
            "gradient_slabs_vs_spot_rows_max_rel_diff": grad_rel,
-           "ms_iteration_sell_step_and_slab_gradient_plan": round(ms_iter, 4),
+           "ms_iteration_sell_step_and_slab_gradient_plan_beam_sums": round(ms_iter, 4),
            "epilogue_share": round(ms_epi / ms_step, 4), "scenarios": n_scen, "beams": n_beams,
            "voxels": n, "nnz": nnz_tot, "GNNZ_per_s": round(nnz_tot / (ms_step * 1e-3) / 1e9, 2),
            "epilogue_GBps_algorithmic": round(epi_bytes / (ms_epi * 1e-3) / 1e9, 1),

@@ -306,8 +306,15 @@ typedef struct {
  * (plan-owned partitions); with flags DOSE_PLAN_AUTOTUNE the launch is timed
  * on hip_stream under groups of 8K, 16K, 32K and 64K entries and the fastest
  * kept (speed only; the items' g and the plan's scratch are written by the
- * timing runs).  Other flags: DOSE_ERR_INVALID_ARGUMENT.  create is
- * synchronous. */
+ * timing runs).  With DOSE_ADJOINT_ACCUMULATE (voxel slabs only, else
+ * DOSE_ERR_UNSUPPORTED) items may share the very same g (with as many
+ * spots): it receives the sum over those items of A_i^T v_i, formed as one
+ * fixed-order sum from +0 of their slab partials, item by item in item order,
+ * each item's in ascending slab (the robust gradient of a beam: its
+ * matrices under every scenario with each scenario's seed, summed by the
+ * library; at most 65,535 distinct outputs).  Other flags:
+ * DOSE_ERR_INVALID_ARGUMENT.  create is synchronous. */
+enum { DOSE_ADJOINT_ACCUMULATE = 2u };
 dose_status dose_adjoint_plan_create(const dose_adjoint_item* items, int32_t n_items, uint32_t flags,
                                      void* hip_stream, dose_batch_plan* out);
 

@@ -380,9 +380,12 @@ class AdjointPlan(BatchPlan):
     graph and replayed by :meth:`launch`: entries are (DoseMatrix, v, g) with
     v (n_rows,) and g (n_cols,) contiguous FP32 on the matrix's device; each
     g gets the bits of ``A.adjoint(v)``.  ``autotune=True`` times the launch
-    under candidate row-group sizes first (speed only)."""
+    under candidate row-group sizes first (speed only).  ``accumulate=True``
+    (matrices with A^T in voxel slabs): entries sharing the same g tensor sum
+    their adjoints into it, in one fixed order (entry by entry, each in
+    ascending slab)."""
 
-    def __init__(self, entries, autotune: bool = False, stream=None):
+    def __init__(self, entries, autotune: bool = False, accumulate: bool = False, stream=None):
         self._h = None
         self._keep = list(entries)
         arr = (_lib.AdjointItem * len(entries))()
@@ -391,9 +394,9 @@ class AdjointPlan(BatchPlan):
             _dev_ptr(g, A.n_cols, "g", A.device)
             arr[i] = _lib.AdjointItem(A.handle, 0, v.data_ptr(), g.data_ptr())
         h = ctypes.c_void_p()
-        _lib.check(_lib.load().dose_adjoint_plan_create(arr, len(entries),
-                                                        _lib.PLAN_AUTOTUNE if autotune else 0,
-                                                        _stream_handle(stream), ctypes.byref(h)))
+        flags = (_lib.PLAN_AUTOTUNE if autotune else 0) | (_lib.ADJOINT_ACCUMULATE if accumulate else 0)
+        _lib.check(_lib.load().dose_adjoint_plan_create(arr, len(entries), flags, _stream_handle(stream),
+                                                        ctypes.byref(h)))
         self._h = h
 
 

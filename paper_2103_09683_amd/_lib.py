@@ -28,6 +28,7 @@ IDX_RUNS = 3
 CREATE_TRANSPOSE = 1
 CREATE_AUTOTUNE = 2
 CREATE_TRANSPOSE_SLABS = 4
+ADJOINT_ACCUMULATE = 2
 PART_A, PART_AT = 0, 1
 PLAN_AUTOTUNE = 1
 ROBUST_EXPECTED, ROBUST_WORST = 0, 1

@@ -773,7 +773,8 @@ struct dose_batch_plan_s {
   std::vector<PlanLayer> layers;  // launched one after another (one layer for a batch plan)
   std::vector<SellPlanLayer> sell_layers;  // a SELL-C-sigma plan's launch (then layers is empty)
   std::vector<PlanCombine> post;  // adjoint plans: slab combines after the layers
-  DevBuf post_items;              // the same as one table (one launch for all of them)
+  DevBuf post_groups, post_items;  // the same as output groups and items (one launch for all of them)
+  int32_t n_post_groups = 0;
   int64_t post_max_cols = 0;
   DevBuf scratch;                 // adjoint plans: the scaled seeds and slab partials
   std::vector<std::unique_ptr<Partition>> parts;  // autotuned partitions the work lists were built from
@@ -953,9 +954,9 @@ void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
     t.xcd_blocks = L.xcd;
     HIP_CHECK(launch_sell_batched(p->vf, p->sm, p->n_rhs, p->idx_bytes, t, L.lds_bytes, s));
   }
-  if (p->post_items.get())
-    HIP_CHECK(launch_slab_combine_items(p->post_items.get<SlabCombineItem>(), static_cast<int32_t>(p->post.size()),
-                                        p->post_max_cols, s));
+  if (p->post_groups.get())
+    HIP_CHECK(launch_slab_combine_groups(p->post_groups.get<SlabCombineGroup>(), p->n_post_groups,
+                                         p->post_items.get<SlabCombineItem>(), p->post_max_cols, s));
   else
     for (const PlanCombine& c : p->post)
       HIP_CHECK(launch_slab_combine(false, c.part, c.ptr, c.rows, c.g, c.n_cols, s));
@@ -963,8 +964,10 @@ void enqueue_plan(const dose_batch_plan_s* p, hipStream_t s) {
 
 // The adjoint items of a plan: every matrix with a transpose of the same
 // layout (spot rows or voxel slabs), value format and device; v and g of an
-// item apart, no g shared or overlapping another item's (v may be shared).
-void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items) {
+// item apart, no g overlapping another item's v, and no g shared or
+// overlapping another item's g, except (accumulate, voxel slabs) the very
+// same g of items with as many spots.  v may be shared.
+void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items, bool accumulate) {
   if (!items || n_items <= 0) fail(DOSE_ERR_INVALID_ARGUMENT, "no items");
   for (int32_t i = 0; i < n_items; ++i) {
     const dose_adjoint_item& it = items[i];
@@ -981,8 +984,10 @@ void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items) {
     if ((m->slab > 0) != (m0->slab > 0) || m->AT.idx_bytes != m0->AT.idx_bytes)
       fail(DOSE_ERR_UNSUPPORTED, "items mix transpose layouts");
     if (m->device != m0->device) fail(DOSE_ERR_INVALID_ARGUMENT, "items on different devices");
+    if (accumulate && m->slab == 0) fail(DOSE_ERR_UNSUPPORTED, "accumulating adjoint plans need voxel slabs");
     for (int32_t j = 0; j < i; ++j) {
-      if (overlaps(items[j].g, items[j].A->A.n_cols * 4, it.g, m->A.n_cols * 4))
+      const bool same = accumulate && items[j].g == it.g && items[j].A->A.n_cols == m->A.n_cols;
+      if (!same && overlaps(items[j].g, items[j].A->A.n_cols * 4, it.g, m->A.n_cols * 4))
         fail(DOSE_ERR_INVALID_ARGUMENT, "items share outputs");
       if (overlaps(items[j].v, items[j].A->A.n_rows * 4, it.g, m->A.n_cols * 4) ||
           overlaps(it.v, m->A.n_rows * 4, items[j].g, items[j].A->A.n_cols * 4))
@@ -1000,7 +1005,8 @@ void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items) {
 // timed under 8K-64K-entry groups and the fastest kept.
 dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_items, uint32_t flags,
                                       hipStream_t s) {
-  check_adjoint_items(items, n_items);
+  const bool accumulate = (flags & DOSE_ADJOINT_ACCUMULATE) != 0;
+  check_adjoint_items(items, n_items, accumulate);
   auto plan = std::make_unique<dose_batch_plan_s>();
   const dose_matrix_s* m0 = items[0].A;
   const bool fp8 = m0->vf == kFp8, slabs = m0->slab > 0;
@@ -1127,15 +1133,38 @@ dose_batch_plan_s* build_adjoint_plan(const dose_adjoint_item* items, int32_t n_
     HIP_CHECK(hipMemcpyAsync(plan->pre_items.get(), si.data(), si.size() * sizeof(ScaleItem), hipMemcpyHostToDevice,
                              s));
   }
-  if (!plan->post.empty() && plan->post.size() <= 65535) {
-    std::vector<SlabCombineItem> ci;
-    for (const PlanCombine& c : plan->post) {
-      ci.push_back(SlabCombineItem{c.part, c.ptr, c.rows, c.g, c.n_cols});
-      plan->post_max_cols = std::max(plan->post_max_cols, c.n_cols);
+  // the combines as output groups: the items writing one g, in item order
+  // (one item per group unless accumulating)
+  std::vector<SlabCombineGroup> cg;
+  std::vector<SlabCombineItem> ci;
+  {
+    std::map<float*, std::vector<size_t>> by_g;
+    std::vector<float*> order;
+    for (size_t k = 0; k < plan->post.size(); ++k) {
+      float* g = plan->post[k].g;
+      if (!accumulate || !by_g.count(g)) order.push_back(g);
+      by_g[g].push_back(k);
     }
+    for (size_t q = 0; q < order.size(); ++q) {
+      // without accumulate every g is distinct, so each group is one item
+      const std::vector<size_t>& ks = by_g.at(order[q]);
+      SlabCombineGroup G{order[q], plan->post[ks[0]].n_cols, static_cast<int32_t>(ci.size()),
+                         static_cast<int32_t>(ks.size())};
+      for (size_t k : ks) ci.push_back(SlabCombineItem{plan->post[k].part, plan->post[k].ptr, plan->post[k].rows});
+      cg.push_back(G);
+      plan->post_max_cols = std::max(plan->post_max_cols, G.n_cols);
+    }
+  }
+  if (!cg.empty() && cg.size() <= 65535) {
+    plan->n_post_groups = static_cast<int32_t>(cg.size());
+    plan->post_groups = DevBuf(cg.size() * sizeof(SlabCombineGroup));
     plan->post_items = DevBuf(ci.size() * sizeof(SlabCombineItem));
+    HIP_CHECK(hipMemcpyAsync(plan->post_groups.get(), cg.data(), cg.size() * sizeof(SlabCombineGroup),
+                             hipMemcpyHostToDevice, s));
     HIP_CHECK(hipMemcpyAsync(plan->post_items.get(), ci.data(), ci.size() * sizeof(SlabCombineItem),
                              hipMemcpyHostToDevice, s));
+  } else if (accumulate && !cg.empty()) {
+    fail(DOSE_ERR_UNSUPPORTED, "an accumulating adjoint plan takes at most 65,535 outputs");
   }
   HIP_CHECK(hipStreamSynchronize(s));
   return plan.release();
@@ -1843,8 +1872,9 @@ dose_status dose_adjoint_plan_create(const dose_adjoint_item* items, int32_t n_i
   return guarded([&] {
     if (!out) fail(DOSE_ERR_INVALID_ARGUMENT, "out is null");
     *out = nullptr;
-    if (flags & ~static_cast<uint32_t>(DOSE_PLAN_AUTOTUNE)) fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
-    check_adjoint_items(items, n_items);
+    if (flags & ~static_cast<uint32_t>(DOSE_PLAN_AUTOTUNE | DOSE_ADJOINT_ACCUMULATE))
+      fail(DOSE_ERR_INVALID_ARGUMENT, "unknown flags");
+    check_adjoint_items(items, n_items, (flags & DOSE_ADJOINT_ACCUMULATE) != 0);
     DeviceGuard g(items[0].A->device);
     std::unique_ptr<dose_batch_plan_s> p(build_adjoint_plan(items, n_items, flags, as_stream(hip_stream)));
     capture_plan(p.get());

@@ -42,16 +42,23 @@ hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows
 hipError_t launch_slab_combine(bool f64, const void* part, const uint32_t* ptr, const uint32_t* rows, void* g,
                                int64_t n_cols, hipStream_t s);
 
-// The FP32 combines of several slab adjoints in one launch (adjoint plans):
-// item i (items in device memory) as launch_slab_combine would do it.
+// The FP32 combines of several slab adjoints in one launch (adjoint plans).
+// Output group k writes g[j] for j < n_cols: starting from +0, for each of
+// its items i = first .. first + count - 1 in turn, the item's partials of
+// spot j in ascending slab (a group of one item: what launch_slab_combine
+// writes).  Items and groups in device memory.
 struct SlabCombineItem {
   const float* part;
   const uint32_t* ptr;
   const uint32_t* rows;
+};
+struct SlabCombineGroup {
   float* g;
   int64_t n_cols;
+  int32_t first, count;
 };
-hipError_t launch_slab_combine_items(const SlabCombineItem* items, int32_t n_items, int64_t max_cols, hipStream_t s);
+hipError_t launch_slab_combine_groups(const SlabCombineGroup* groups, int32_t n_groups, const SlabCombineItem* items,
+                                      int64_t max_cols, hipStream_t s);
 
 // The E4M3 seed scalings of an adjoint plan in one launch: item i (items in
 // device memory) writes u[k] = fl32(scale[k] * v[k]) for k < n, as

@@ -44,12 +44,11 @@ __global__ void k_slab_gather(const uint32_t* __restrict__ perm, const uint32_t*
 // issued eight at a time (the row indices, then the partials) so that a spot
 // of n slabs waits for about n / 4 round trips to memory instead of 2 n.
 template <typename V>
-__device__ __forceinline__ void combine_spot(const V* __restrict__ part, const uint32_t* __restrict__ ptr,
-                                             const uint32_t* __restrict__ rows, V* __restrict__ g, int64_t j) {
+__device__ __forceinline__ V combine_spot(const V* __restrict__ part, const uint32_t* __restrict__ ptr,
+                                          const uint32_t* __restrict__ rows, int64_t j, V acc) {
   constexpr int kBatch = 8;
   const uint32_t end = ptr[j + 1];
   uint32_t k = ptr[j];
-  V acc = V(0);
   for (; k + kBatch <= end; k += kBatch) {
     uint32_t r[kBatch];
     V p[kBatch];
@@ -61,21 +60,26 @@ __device__ __forceinline__ void combine_spot(const V* __restrict__ part, const u
     for (int i = 0; i < kBatch; ++i) acc = acc + p[i];
   }
   for (; k < end; ++k) acc = acc + part[rows[k]];
-  g[j] = acc;
+  return acc;
 }
 
 template <typename V>
 __global__ void k_slab_combine(const V* __restrict__ part, const uint32_t* __restrict__ ptr,
                                const uint32_t* __restrict__ rows, V* __restrict__ g, int64_t n_cols) {
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j < n_cols) combine_spot(part, ptr, rows, g, j);
+  if (j < n_cols) g[j] = combine_spot(part, ptr, rows, j, V(0));
 }
 
-// Item blockIdx.y of an adjoint plan; its spots in blocks along x.
-__global__ void k_slab_combine_items(const SlabCombineItem* __restrict__ items) {
-  const SlabCombineItem it = items[blockIdx.y];
+// Output group blockIdx.y of an adjoint plan; its spots in blocks along x.
+__global__ void k_slab_combine_groups(const SlabCombineGroup* __restrict__ groups,
+                                      const SlabCombineItem* __restrict__ items) {
+  const SlabCombineGroup G = groups[blockIdx.y];
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (j < it.n_cols) combine_spot(it.part, it.ptr, it.rows, it.g, j);
+  if (j >= G.n_cols) return;
+  float acc = 0.0f;
+  for (int32_t i = G.first; i < G.first + G.count; ++i)
+    acc = combine_spot(items[i].part, items[i].ptr, items[i].rows, j, acc);
+  G.g[j] = acc;
 }
 
 // Item blockIdx.y of an adjoint plan's seed scalings, its elements strided
@@ -130,11 +134,12 @@ hipError_t launch_slab_gather(int vf, const uint32_t* perm, const uint32_t* rows
   return hipGetLastError();
 }
 
-hipError_t launch_slab_combine_items(const SlabCombineItem* items, int32_t n_items, int64_t max_cols, hipStream_t s) {
-  if (n_items <= 0 || max_cols <= 0) return hipSuccess;
-  if (n_items > 65535) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_slab_combine_items, dim3(slab_blocks(max_cols, 256), static_cast<unsigned>(n_items)),
-                     dim3(256), 0, s, items);
+hipError_t launch_slab_combine_groups(const SlabCombineGroup* groups, int32_t n_groups, const SlabCombineItem* items,
+                                      int64_t max_cols, hipStream_t s) {
+  if (n_groups <= 0 || max_cols <= 0) return hipSuccess;
+  if (n_groups > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_slab_combine_groups, dim3(slab_blocks(max_cols, 256), static_cast<unsigned>(n_groups)),
+                     dim3(256), 0, s, groups, items);
   return hipGetLastError();
 }
 

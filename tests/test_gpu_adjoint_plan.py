@@ -84,7 +84,8 @@ def test_adjoint_plan_autotune(fmt, transpose, dev):
     """DOSE_PLAN_AUTOTUNE picks the row-group size by timing the launch; the
     bits stay those of the plain adjoints."""
     mats, _ = _matrices(fmt, transpose)
-    vs = [torch.from_numpy(dosegen.signed_values(dosegen.SEED0, 60 + i, A.n_rows)).cuda() for i, A in enumerate(mats)]
+    vs = [torch.from_numpy(dosegen.signed_values(dosegen.SEED0, 60 + i, A.n_rows)).cuda()
+          for i, A in enumerate(mats)]
     gs = [torch.empty(A.n_cols, device=dev) for A in mats]
     plan = dm.AdjointPlan(list(zip(mats, vs, gs)), autotune=True)
     for g in gs:
@@ -128,7 +129,8 @@ def test_adjoint_plan_errors_and_empty(dev):
     arr = (_lib.AdjointItem * 1)()
     arr[0] = _lib.AdjointItem(mats[0].handle, 0, v[0].data_ptr(), g[0].data_ptr())
     h = dm.ctypes.c_void_p()
-    assert _lib.load().dose_adjoint_plan_create(arr, 1, 2, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
+    # 4: the lowest bit no adjoint-plan flag uses
+    assert _lib.load().dose_adjoint_plan_create(arr, 1, 4, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
     arr[0] = _lib.AdjointItem(mats[0].handle, 1, v[0].data_ptr(), g[0].data_ptr())
     assert _lib.load().dose_adjoint_plan_create(arr, 1, 0, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
     assert _lib.load().dose_adjoint_plan_create(arr, 0, 0, None, dm.ctypes.byref(h)) == _lib.ERR_INVALID_ARGUMENT
@@ -143,4 +145,67 @@ def test_adjoint_plan_errors_and_empty(dev):
     assert torch.equal(_bits(g[0]), _bits(mats[0].adjoint(v[0])))
     plan.close()
     for A in mats + rows + e4 + [plain, E]:
+        A.close()
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp8e4m3_rowscale"])
+def test_adjoint_plan_accumulate(fmt, dev):
+    """DOSE_ADJOINT_ACCUMULATE: each beam's gradient summed over the
+    scenarios by the plan (g_b = sum_s A_sb^T v_s) against the oracle's FP64
+    sum; the same bits on every replay; one item per output gives the plain
+    adjoint's bits; spot rows and partly overlapping outputs are refused."""
+    S, B = 2, 3
+    specs = dosegen.robust_scenarios(0.04, S, B)
+    host = [dosegen.csr(sp) for sp in specs]
+    mats = [dm.DoseMatrix(rp, cols, vals, sp.n_cols, fmt, transpose="slabs")
+            for sp, (rp, cols, vals) in zip(specs, host)]
+    n = mats[0].n_rows
+    vs = [torch.from_numpy(dosegen.signed_values(dosegen.SEED0, 80 + s, n)).cuda() for s in range(S)]
+    gs = [torch.full((specs[b].n_cols,), np.nan, device=dev) for b in range(B)]
+    plan = dm.AdjointPlan([(mats[s * B + b], vs[s], gs[b]) for s in range(S) for b in range(B)], accumulate=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    first = [g.clone() for g in gs]
+    for b in range(B):
+        ref = np.zeros(specs[b].n_cols)
+        scale = np.zeros(specs[b].n_cols)
+        for s in range(S):
+            rp, cols, vals = host[s * B + b]
+            dec, _ = oracle.decode_matrix(fmt, rp, vals)
+            vh = vs[s].cpu().numpy()
+            ref += oracle.spmv_T(rp, cols, dec, vh, specs[b].n_cols)
+            scale += oracle.spmv_T(rp, cols, np.abs(dec), np.abs(vh), specs[b].n_cols)
+        err = oracle.max_scaled_err(gs[b].cpu().numpy(), ref, scale)
+        _say(f"accumulated beam {b} ({fmt}): max scaled err {err:.3e}")
+        assert err <= 1e-5, (b, err)
+    for g in gs:
+        g.fill_(np.nan)
+    plan.launch()
+    torch.cuda.synchronize()
+    for g, f in zip(gs, first):
+        assert torch.equal(_bits(g), _bits(f))
+    plan.close()
+    # one item per output: the plain adjoint's bits
+    one = [torch.empty(specs[b].n_cols, device=dev) for b in range(B)]
+    p1 = dm.AdjointPlan([(mats[b], vs[0], one[b]) for b in range(B)], accumulate=True)
+    p1.launch()
+    torch.cuda.synchronize()
+    for b in range(B):
+        assert torch.equal(_bits(one[b]), _bits(mats[b].adjoint(vs[0]))), b
+    p1.close()
+    # refused: spot rows; outputs that overlap without being the same
+    R = dm.DoseMatrix(*host[0], specs[0].n_cols, fmt, transpose=True)
+    with pytest.raises(dm.DoseError) as e:
+        dm.AdjointPlan([(R, vs[0], one[0])], accumulate=True)
+    assert e.value.code == _lib.ERR_UNSUPPORTED
+    big = torch.zeros(specs[0].n_cols + 8, device=dev)
+    with pytest.raises(dm.DoseError) as e:
+        dm.AdjointPlan([(mats[0], vs[0], big[:specs[0].n_cols]), (mats[3], vs[1], big[8:])], accumulate=True)
+    assert e.value.code == _lib.ERR_INVALID_ARGUMENT
+    # without accumulate a shared output stays refused
+    with pytest.raises(dm.DoseError) as e:
+        dm.AdjointPlan([(mats[0], vs[0], one[0]), (mats[3], vs[1], one[0])])
+    assert e.value.code == _lib.ERR_INVALID_ARGUMENT
+    R.close()
+    for A in mats:
         A.close()
