@@ -3,9 +3,9 @@ makes the n-th device allocation after the variable takes that value fail
 with DOSE_ERR_OUT_OF_MEMORY.  For every n up to the first that lets the call
 succeed, the create call (a CSR matrix with its transpose in E4M3 with row
 scales, over spot rows or in voxel slabs, a SELL-C-sigma matrix with
-run-length indices, an autotuned batch plan) must fail with that status and
-leave the device's free memory where it was: whatever the call had allocated
-before the failure is freed."""
+run-length indices, an autotuned batch plan, an adjoint plan) must fail with
+that status and leave the device's free memory where it was: whatever the
+call had allocated before the failure is freed."""
 import numpy as np
 import pytest
 import torch
@@ -90,5 +90,19 @@ def test_batch_plan_create_cleans_up(dev, monkeypatch):
     n = _sweep(lambda: dm.BatchPlan([(A, x, y) for A, y in zip(mats, ys)], autotune=True), monkeypatch)
     print(f"batch plan create: {n - 1} allocations failed in turn", flush=True)
     assert n > 1
+    for A in mats:
+        A.close()
+
+
+def test_adjoint_plan_create_cleans_up(dev, monkeypatch):
+    # E4M3 over voxel slabs, accumulating: scratch, work list, re-made
+    # partitions, the seed-scaling and combine tables, each failing in turn
+    rp, cols, vals, n_cols = _matrix(n_rows=50_000)
+    mats = [dm.DoseMatrix(rp, cols, vals, n_cols, "fp8e4m3_rowscale", transpose="slabs") for _ in range(3)]
+    v = torch.rand(50_000, device=dev)
+    g = torch.empty(n_cols, device=dev)
+    n = _sweep(lambda: dm.AdjointPlan([(A, v, g) for A in mats], accumulate=True), monkeypatch)
+    print(f"adjoint plan create: {n - 1} allocations failed in turn", flush=True)
+    assert n > 4
     for A in mats:
         A.close()
