@@ -998,7 +998,8 @@ void check_adjoint_items(const dose_adjoint_item* items, int32_t n_items, bool a
 
 // The adjoints of all items: E4M3 seeds scaled into the plan's scratch, one
 // batched launch over the row groups of every item's transpose (writing g,
-// or the slab partials into the scratch), then the slab combines.  The row
+// or the slab partials into the scratch), then the slab combines (one output
+// group per g: with DOSE_ADJOINT_ACCUMULATE, every item writing it).  The row
 // groups are sized for the whole launch (a matrix's own are sized to fill the
 // chip alone): plan-owned partitions where the sizes differ, the results
 // not depending on the partition; with DOSE_PLAN_AUTOTUNE the launch is
