@@ -295,10 +295,12 @@ typedef struct {
  * hip_stream (asynchronous) and dose_batch_plan_destroy frees: E4M3 seeds
  * scaled by the row scales, one launch over the row groups of every item's
  * stored transpose, and (voxel slabs) each item's combine of its slab
- * partials.  Each g is bitwise what dose_spmv_adjoint writes for its item.
- * All items: the same value format, the same transpose layout (spot rows or
- * voxel slabs) and device; an item's v and g apart; no g overlapping another
- * item's v or g (items may share v).  The plan keeps the items' pointers
+ * partials.  Each g is bitwise what dose_spmv_adjoint writes for its item
+ * (unless accumulated, below).  All items: a stored transpose (else
+ * DOSE_ERR_NO_TRANSPOSE), the same value format and transpose layout (spot
+ * rows or voxel slabs; else DOSE_ERR_UNSUPPORTED) and the same device; an
+ * item's v and g apart; no g overlapping another item's v or g (items may
+ * share v; else DOSE_ERR_INVALID_ARGUMENT).  The plan keeps the items' pointers
  * (v, g and the matrices must stay valid while it is used; re-partitioning
  * a matrix does not affect it) and owns its scratch (n_rows
  * floats per E4M3 item, one per slab row per slab item): overlapping
