@@ -1,7 +1,9 @@
-"""The binding's ctypes structures against the C header: a small C program,
-compiled with gcc against include/dose.h, prints every structure's size and
-each field's offset; the ctypes declarations must agree field by field, so a
-reordered, resized or missing field in either is caught without a GPU."""
+"""The binding's ctypes structures and constants against the C header: small
+C programs, compiled with gcc against include/dose.h, print every
+structure's size and each field's offset, and every enumerator the binding
+mirrors; the ctypes declarations and constants must agree one by one, so a
+reordered, resized or missing field, or a flag renumbered on one side, is
+caught without a GPU."""
 import ctypes
 import os
 import subprocess
@@ -65,3 +67,31 @@ def test_header_compiles_as_c_and_cxx(tmp_path):
         subprocess.run([compiler, std, "-Wall", "-Werror", "-x", "c" if compiler == "gcc" else "c++",
                         "-I", os.path.join(ROOT, "include"), str(src), "-o", str(tmp_path / "h")],
                        check=True, capture_output=True, text=True)
+
+
+# every constant of the binding against the header's enumerator of that name
+# (the binding drops the DOSE_ prefix)
+CONSTANTS = ["OK", "ERR_INVALID_ARGUMENT", "ERR_BAD_CSR", "ERR_UNSUPPORTED", "ERR_NO_TRANSPOSE",
+             "ERR_OUT_OF_MEMORY", "ERR_HIP", "ERR_INTERNAL", "VAL_FP16", "VAL_BF16", "VAL_FP8E4M3_ROWSCALE",
+             "VAL_FP32", "IDX_I32", "IDX_U16", "IDX_RUNS", "CREATE_TRANSPOSE", "CREATE_AUTOTUNE",
+             "CREATE_TRANSPOSE_SLABS", "ADJOINT_ACCUMULATE", "PART_A", "PART_AT", "PLAN_AUTOTUNE",
+             "ROBUST_EXPECTED", "ROBUST_WORST"]
+
+
+def test_constants_match_header(tmp_path):
+    lines = ['#include <stdio.h>', '#include "dose.h"', "int main(void) {"]
+    lines += [f'  printf("{c} %lld\\n", (long long)DOSE_{c});' for c in CONSTANTS]
+    lines += ["  return 0;", "}"]
+    src, exe = tmp_path / "consts.c", tmp_path / "consts"
+    src.write_text("\n".join(lines) + "\n")
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src),
+                    "-o", str(exe)], check=True, capture_output=True, text=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    header = {name: int(value) for name, value in (line.split() for line in out.splitlines())}
+    for c in CONSTANTS:
+        assert getattr(_lib, c) == header[c], (c, getattr(_lib, c), header[c])
+    # create flags and plan flags are single bits, distinct within each family
+    create = [header[c] for c in ("CREATE_TRANSPOSE", "CREATE_AUTOTUNE", "CREATE_TRANSPOSE_SLABS")]
+    plan = [header[c] for c in ("PLAN_AUTOTUNE", "ADJOINT_ACCUMULATE")]
+    for family in (create, plan):
+        assert all(f > 0 and f & (f - 1) == 0 for f in family) and len(set(family)) == len(family)
