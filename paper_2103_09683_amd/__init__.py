@@ -575,6 +575,55 @@ class DoseObjective(torch.autograd.Function):
         return g.view(-1), None, None
 
 
+class RobustProblem:
+    """One robust plan-optimisation iteration in library calls (Sec. I, II-A):
+    the dose of every beam under every scenario (one batch plan), the robust
+    objective and the scenario seeds (FP64 reductions), the robust seeds, and
+    each beam's gradient summed over the scenarios (one accumulating adjoint
+    plan).  ``mats[s][b]`` is beam b's DoseMatrix under scenario s, all with
+    A^T in voxel slabs, one voxel grid; ``xs[b]`` beam b's FP32 spot weights
+    (read at every step: update them in place); ``p``, ``w`` the voxel
+    prescription and weights; ``mode`` "expected" (with ``prob``, or uniform)
+    or "worst".  :meth:`step` returns the n_scen + 3 FP64 values of
+    :func:`scenario_objective` and the list of beam gradients (FP32, each
+    ``(n_cols_b,)``), all on the device, asynchronously."""
+
+    def __init__(self, mats, xs, p: torch.Tensor, w: torch.Tensor, prob: torch.Tensor | None = None,
+                 mode: str = "expected"):
+        if mode not in ("expected", "worst"):
+            raise ValueError("mode is 'expected' or 'worst'")
+        n_scen, n_beams = len(mats), len(xs)
+        if n_scen == 0 or any(len(row) != n_beams for row in mats):
+            raise ValueError("mats must be n_scen lists of one matrix per beam")
+        n = mats[0][0].n_rows
+        if any(A.n_rows != n for row in mats for A in row):
+            raise ValueError("every matrix must have the voxel grid's rows")
+        for b in range(n_beams):
+            if any(mats[s][b].n_cols != xs[b].numel() for s in range(n_scen)):
+                raise ValueError(f"beam {b}: every scenario's matrix must have the beam's spots")
+        dev = xs[0].device
+        self.mats, self.xs, self.p, self.w, self.prob, self.mode = mats, xs, p, w, prob, mode
+        self.part = torch.empty(n_scen, n_beams, n, dtype=torch.float32, device=dev)
+        self.seed = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+        self.wseed = torch.empty(n_scen, n, dtype=torch.float32, device=dev)
+        self.out = torch.empty(n_scen + 3, dtype=torch.float64, device=dev)
+        self.grads = [torch.empty(x.numel(), dtype=torch.float32, device=dev) for x in xs]
+        self._doses = BatchPlan([(mats[s][b], xs[b], self.part[s, b]) for s in range(n_scen) for b in range(n_beams)])
+        self._adjoints = AdjointPlan([(mats[s][b], self.wseed[s], self.grads[b])
+                                      for s in range(n_scen) for b in range(n_beams)], accumulate=True)
+
+    def step(self, stream=None):
+        self._doses.launch(stream)
+        scenario_objective(self.part, self.p, self.w, prob=self.prob, seed=self.seed, out=self.out, stream=stream)
+        robust_seed(self.seed, self.mode, out=self.out, prob=self.prob, wseed=self.wseed, stream=stream)
+        self._adjoints.launch(stream)
+        return self.out, self.grads
+
+    def close(self) -> None:
+        self._doses.close()
+        self._adjoints.close()
+
+
 class ScenarioObjective(torch.autograd.Function):
     """Robust objective of the beam doses part (n_scen, n_beams, n): the
     expectation sum_s prob_s f_s (mode "expected"; the mean without prob) or

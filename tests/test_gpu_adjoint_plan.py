@@ -209,3 +209,47 @@ def test_adjoint_plan_accumulate(fmt, dev):
     R.close()
     for A in mats:
         A.close()
+
+
+@pytest.mark.parametrize("mode", ["expected", "worst"])
+def test_robust_problem_step(mode, dev):
+    """RobustProblem.step: the robust objective's values equal a direct
+    scenario_objective on the plan's beam doses (bitwise), and each beam's
+    gradient is the oracle's FP64 sum over the scenarios of A_sb^T of the
+    step's c_s-weighted seeds; updated spot weights are read at the next step."""
+    S, B = 2, 3
+    specs = dosegen.robust_scenarios(0.04, S, B)
+    host = [dosegen.csr(sp) for sp in specs]
+    mats = [[dm.DoseMatrix(*host[s * B + b], specs[s * B + b].n_cols, "fp16", transpose="slabs")
+             for b in range(B)] for s in range(S)]
+    n = mats[0][0].n_rows
+    rng = np.random.default_rng(90)
+    xs = [torch.from_numpy(dosegen.spot_weights(dosegen.SEED0, 90 + b, specs[b].n_cols) * np.float32(4)).cuda()
+          for b in range(B)]
+    p = torch.from_numpy(rng.choice([0.0, 20.0, 60.0], size=n).astype(np.float32)).cuda()
+    w = torch.from_numpy(rng.choice([1.0, 10.0], size=n).astype(np.float32)).cuda()
+    prob = torch.tensor([0.25, 0.75], dtype=torch.float64, device=dev) if mode == "expected" else None
+    R = dm.RobustProblem(mats, xs, p, w, prob=prob, mode=mode)
+    for rep in range(2):
+        out, grads = R.step()
+        torch.cuda.synchronize()
+        ref_out = dm.scenario_objective(R.part, p, w, prob=prob)
+        assert torch.equal(out.view(torch.int64), ref_out.view(torch.int64)), rep
+        ws = R.wseed.cpu().numpy()
+        for b in range(B):
+            g_ref = np.zeros(specs[b].n_cols)
+            scale = np.zeros(specs[b].n_cols)
+            for s in range(S):
+                rp, cols, vals = host[s * B + b]
+                dec, _ = oracle.decode_matrix("fp16", rp, vals)
+                g_ref += oracle.spmv_T(rp, cols, dec, ws[s], specs[b].n_cols)
+                scale += oracle.spmv_T(rp, cols, np.abs(dec), np.abs(ws[s]), specs[b].n_cols)
+            err = oracle.max_scaled_err(grads[b].cpu().numpy(), g_ref, scale)
+            _say(f"robust problem ({mode}) step {rep} beam {b}: max scaled err {err:.3e}")
+            assert err <= 1e-5, (rep, b, err)
+        for x in xs:
+            x.mul_(0.5)  # the next step reads the new weights
+    R.close()
+    for row in mats:
+        for A in row:
+            A.close()
