@@ -586,7 +586,8 @@ class RobustProblem:
     prescription and weights; ``mode`` "expected" (with ``prob``, or uniform)
     or "worst".  :meth:`step` returns the n_scen + 3 FP64 values of
     :func:`scenario_objective` and the list of beam gradients (FP32, each
-    ``(n_cols_b,)``), all on the device, asynchronously."""
+    ``(n_cols_b,)``), all on the device, asynchronously: they are the
+    problem's own tensors, overwritten by the next step (clone to keep)."""
 
     def __init__(self, mats, xs, p: torch.Tensor, w: torch.Tensor, prob: torch.Tensor | None = None,
                  mode: str = "expected"):
